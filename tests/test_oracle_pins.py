@@ -1,0 +1,406 @@
+"""Pins of the CPU oracle against the paper and against mathematics.
+
+Each test checks the oracle against something other than itself: closed
+forms (homogeneous media, 1D series resistances), invariants (partition of
+unity, conservation, symmetry), library routines (SciPy sparse LU, NumPy
+dense solves, SciPy triangular solves) and brute force on tiny grids.
+"""
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle
+from tests import helpers
+from workloads import Problem, config1, small_problem
+from workloads.configs import FE, FV
+
+
+def homogeneous(nx, ny, nz, r, k=2.5, dx=1.0, dy=1.0, dz=1.0, wells="corners", c=0.1):
+    pb = small_problem(nx, ny, nz, r, wells=wells, c=c)
+    pb.perm = np.full(pb.n, k)
+    pb.dx, pb.dy, pb.dz = dx, dy, dz
+    return pb
+
+
+# ---------------------------------------------------------------- TPFA ----
+
+def test_tpfa_homogeneous_closed_form():
+    pb = homogeneous(5, 4, 3, 2, k=3.0, dx=2.0, dy=0.5, dz=1.5)
+    T = oracle.transmissibility(pb)
+    Tx, Ty, Tz = (t.reshape(3, 4, 5) for t in T)
+    # interior faces: k * area / spacing; boundary faces: no flow
+    assert np.allclose(Tx[:, :, :-1], 3.0 * 0.5 * 1.5 / 2.0, rtol=1e-15)
+    assert np.allclose(Ty[:, :-1, :], 3.0 * 2.0 * 1.5 / 0.5, rtol=1e-15)
+    assert np.allclose(Tz[:-1, :, :], 3.0 * 2.0 * 0.5 / 1.5, rtol=1e-15)
+    assert np.all(Tx[:, :, -1] == 0) and np.all(Ty[:, -1, :] == 0) and np.all(Tz[-1] == 0)
+
+
+def test_tpfa_series_resistance_steady_1d():
+    """Steady incompressible flow through a 1D chain of cells: the pressure
+    at each cell centre falls in proportion to the accumulated half-cell
+    resistances h / (2 k A) (textbook layered-medium result)."""
+    n = 9
+    rng = np.random.default_rng(0)
+    k = np.exp(rng.normal(0, 1.5, n))
+    pb = Problem("chain", n, 2, 1, 3, 2, 1, np.repeat(k[None, :], 2, axis=0).ravel(),
+                 np.full(2 * n, 0.2), [(0, 1.0), (n, 1.0), (n - 1, 0.0), (2 * n - 1, 0.0)],
+                 dx=1.3, dy=0.7, c=0.0, dt=1.0)
+    T = oracle.transmissibility(pb)
+    p0 = pb.initial_pressure()
+    p, _ = helpers.direct_newton(pb, T, p0, p0)
+    area = pb.dy * pb.dz
+    half = (pb.dx / 2) / (k * area)          # half-cell resistance
+    # resistance from centre of cell 0 to centre of cell m
+    R = np.concatenate([[0.0], np.cumsum(half[:-1] + half[1:])])
+    expected = 1.0 - R / R[-1]
+    assert np.allclose(p[:n], expected, rtol=0, atol=1e-13)
+    assert np.allclose(p[n:], expected, rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------ assembly ----
+
+def test_jacobian_equals_finite_difference_at_uniform_state():
+    """At a uniform state p = p^n the paper's linearisation (Eqs. (3)-(6))
+    is the exact Jacobian of the residual of Eq. (2): the lagged face
+    densities multiply zero pressure differences and c^nu uses rho^n."""
+    pb = small_problem(6, 5, 4, 2, wells="none", c=0.3, dt=0.2)
+    T = oracle.transmissibility(pb)
+    p = np.full(pb.n, 0.37)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, p)
+    A = helpers.stencil_matrix(pb, W, diag).toarray()
+    h = 1e-6
+    J = np.zeros((pb.n, pb.n))
+    for j in range(pb.n):
+        e = np.zeros(pb.n); e[j] = h
+        Fp, _ = oracle.nonlinear_residual(pb, T, p + e, p)
+        Fm, _ = oracle.nonlinear_residual(pb, T, p - e, p)
+        J[:, j] = (Fp - Fm) / (2 * h)
+    assert np.max(np.abs(J - A)) <= 1e-7 * np.max(np.abs(A))
+    assert np.max(np.abs(r)) == 0.0
+
+
+def test_incompressible_residual_is_affine():
+    """c = 0: the residual is affine in p with the assembled matrix as its
+    exact Jacobian (no density lag), so F(p+x) - F(p) = A x."""
+    pb = small_problem(7, 6, 3, 3, c=0.0)
+    T = oracle.transmissibility(pb)
+    rng = np.random.default_rng(1)
+    p = pb.initial_pressure() + 0.0
+    p[pb.dirichlet_mask() == 0] = rng.uniform(0, 1, (pb.dirichlet_mask() == 0).sum())
+    x = rng.normal(size=pb.n)
+    x[pb.dirichlet_mask() == 1] = 0.0
+    W, diag, r, _ = oracle.linear_system(pb, T, p, p)
+    F1, _ = oracle.nonlinear_residual(pb, T, p, p)
+    F2, _ = oracle.nonlinear_residual(pb, T, p + x, p)
+    Ax = helpers.stencil_matrix(pb, W, diag) @ x
+    free = pb.dirichlet_mask() == 0
+    assert np.allclose((F2 - F1)[free], Ax[free], rtol=0, atol=1e-12 * np.abs(Ax).max())
+
+
+def test_fluxes_conserve_mass():
+    """Closed domain, no wells: summing Eq. (2) over all cells, inter-cell
+    fluxes cancel, so dt * sum_i F_i does not depend on dt."""
+    pb = small_problem(6, 6, 4, 2, wells="none", c=0.2)
+    T = oracle.transmissibility(pb)
+    rng = np.random.default_rng(2)
+    p = rng.uniform(0, 1, pb.n)
+    pn = rng.uniform(0, 1, pb.n)
+    s = []
+    for dt in (0.1, 0.7):
+        pb.dt = dt
+        F, _ = oracle.nonlinear_residual(pb, T, p, pn)
+        s.append(dt * F.sum())
+    assert abs(s[0] - s[1]) <= 1e-12 * abs(s[0])
+
+
+def test_matrix_is_symmetric_m_matrix():
+    pb = config1()
+    T = oracle.transmissibility(pb)
+    p = np.random.default_rng(3).uniform(0, 1, pb.n)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
+    A = helpers.stencil_matrix(pb, W, diag)
+    assert abs(A - A.T).max() == 0
+    off = A - sp.diags(A.diagonal())
+    assert off.max() <= 0
+    rowsum = np.asarray(A.sum(axis=1)).ravel()
+    assert np.all(rowsum > 0)          # accumulation makes rows strictly dominant
+    dm = pb.dirichlet_mask() == 1
+    assert np.all(r[dm] == 0) and np.all(diag[dm] == 1)
+
+
+def test_incompressible_newton_converges_in_one_iteration():
+    pb = small_problem(8, 8, 4, 4, c=0.0)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, rc, st = oracle.newton_step(pb, T, P, p0, p0, lin_rtol=1e-12, newton_tol=1e-10)
+    assert rc == 0 and st["newton_iters"] == 1
+
+
+def test_converged_state_balances_well_inflow():
+    """At convergence of a time step with no sources, the mass gained in the
+    free cells equals the net inflow through faces adjacent to the
+    Dirichlet cells (global balance of Eq. (1))."""
+    pb = small_problem(10, 8, 4, 4, c=0.1)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, rc, st = oracle.newton_step(pb, T, P, p0, p0, lin_rtol=1e-13, newton_tol=1e-13)
+    assert rc == 0
+    rho = pb.rho0 * np.exp(pb.c * (p - pb.p0))
+    rho_n = pb.rho0 * np.exp(pb.c * (p0 - pb.p0))
+    dm = pb.dirichlet_mask() == 1
+    gained = (pb.phi * (rho - rho_n) / pb.dt)[~dm].sum()
+    # inflow through faces between a Dirichlet and a free cell
+    nx, ny, nz = pb.nx, pb.ny, pb.nz
+    inflow = 0.0
+    for a in range(pb.n):
+        i, j, k = a % nx, (a // nx) % ny, a // (nx * ny)
+        for (di, dj, dk, Tf) in ((1, 0, 0, T[0]), (0, 1, 0, T[1]), (0, 0, 1, T[2])):
+            if i + di >= nx or j + dj >= ny or k + dk >= nz:
+                continue
+            b = a + di + nx * (dj + ny * dk)
+            if dm[a] == dm[b]:
+                continue
+            d, f = (a, b) if dm[a] else (b, a)
+            inflow += Tf[a] * 0.5 * (rho[a] + rho[b]) * (p[d] - p[f])
+    assert abs(gained - inflow) <= 1e-9 * abs(inflow)
+
+
+# -------------------------------------------------------- coarse grids ----
+
+def test_vertex_placement_and_levels_brute_force():
+    assert list(oracle.vertex_coords(20, 4)) == [2, 6, 10, 14, 18]
+    assert list(oracle.vertex_coords(64, 8)) == [4 + 8 * a for a in range(8)]
+    assert list(oracle.vertex_coords(10, 4)) == [2, 6, 9]        # last block has length 2
+    pb = small_problem(10, 9, 7, (4, 3, 3))
+    lv = oracle.cell_levels(pb).reshape(7, 9, 10)
+    vx, vy, vz = (set(oracle.vertex_coords(n, r)) for n, r in ((10, 4), (9, 3), (7, 3)))
+    for k in range(7):
+        for j in range(9):
+            for i in range(10):
+                assert lv[k, j, i] == (i in vx) + (j in vy) + (k in vz)
+    assert (lv == 3).sum() == len(vx) * len(vy) * len(vz)
+    assert oracle.num_coarse(pb) == 3 * 3 * 3
+
+
+# --------------------------------------------------------------- basis ----
+
+def _hat(n, r):
+    """Per-axis 1D hat weights (lower, upper) of the bracketing vertices."""
+    v = list(oracle.vertex_coords(n, r))
+    lo = np.zeros(n); hi = np.zeros(n)
+    for x in range(n):
+        a = max([b for b in range(len(v)) if v[b] <= x], default=0)
+        if x < v[0] or x >= v[-1] or x == v[a]:
+            lo[x], hi[x] = 1.0, 0.0
+        else:
+            t = (x - v[a]) / (v[a + 1] - v[a])
+            lo[x], hi[x] = 1.0 - t, t
+    return lo, hi
+
+
+@pytest.mark.parametrize("shape,r,sp_", [((12, 9, 1), (4, 3, 1), (1.0, 1.0, 1.0)),
+                                          ((10, 11, 9), (4, 4, 3), (1.0, 2.0, 0.5)),
+                                          ((16, 16, 16), (8, 8, 8), (1.0, 1.0, 1.0))])
+def test_basis_homogeneous_is_multilinear_hat(shape, r, sp_):
+    nx, ny, nz = shape
+    pb = homogeneous(nx, ny, nz, r, dx=sp_[0], dy=sp_[1], dz=sp_[2])
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    hx, hy, hz = _hat(nx, pb.rx), _hat(ny, pb.ry), _hat(nz, pb.rz) if nz > 1 else (np.ones(1), np.zeros(1))
+    for s in range(8):
+        bx, by, bz = s & 1, (s >> 1) & 1, (s >> 2) & 1
+        expect = (hz[bz][:, None, None] * hy[by][None, :, None] * hx[bx][None, None, :]).ravel()
+        assert np.allclose(P[s], expect, rtol=0, atol=1e-13), s
+
+
+def test_basis_edge_series_resistance():
+    """Along a dual edge the B4 basis is the 1D harmonic interpolant:
+    Phi_upper(m) = (sum of face resistances up to m) / (total resistance),
+    computed here in exact rational arithmetic."""
+    pb = small_problem(17, 9, 1, (8, 4, 1), sigma=2.0, seed=11)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    v = list(oracle.vertex_coords(17, 8))   # [4, 12, 16]
+    j = list(oracle.vertex_coords(9, 4))[0]
+    Tx = T[0].reshape(9, 17)[j]
+    res = [Fraction(1) / Fraction(float(t)) if t > 0 else None for t in Tx]
+    total = sum(res[v[0]:v[1]])
+    for m in range(v[0] + 1, v[1]):
+        up = sum(res[v[0]:m]) / total
+        cell = m + 17 * j
+        assert abs(P[1][cell] - float(up)) <= 1e-14
+        assert abs(P[0][cell] - float(1 - up)) <= 1e-14
+
+
+@pytest.mark.parametrize("shape,r", [((20, 20, 1), (4, 4, 1)), ((13, 11, 9), (4, 3, 3)),
+                                      ((24, 16, 16), (8, 8, 8))])
+def test_basis_partition_of_unity_and_bounds(shape, r):
+    pb = small_problem(*shape, r, sigma=2.5, seed=5)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    assert np.max(np.abs(P.sum(axis=0) - 1.0)) <= 1e-12
+    assert P.min() >= -1e-14 and P.max() <= 1 + 1e-12
+    nodes = oracle.slot_nodes(pb)
+    lv = oracle.cell_levels(pb)
+    dim = 3 if pb.nz > 1 else 2
+    vert = np.nonzero(lv == dim)[0]
+    assert np.all(P[0][vert] == 1.0) and np.all(P[1:, vert] == 0.0)
+    # weights only on existing nodes
+    assert np.all(P[nodes < 0] == 0.0)
+    # at most 2^dim nonzeros per row
+    assert np.max((P != 0).sum(axis=0)) <= 2 ** dim
+
+
+def test_basis_solves_the_local_problems():
+    """Interior rows of the B4 basis satisfy T Phi = 0 exactly (Eq. (11))."""
+    pb = small_problem(16, 16, 8, (8, 8, 4), sigma=2.0, seed=9)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    Nc = oracle.num_coarse(pb)
+    Pm = helpers.prolongation_matrix(pb.with_options(wells=[]), P, oracle.slot_nodes(pb), Nc)
+    Top = helpers.stencil_matrix(pb, T, np.zeros(pb.n))
+    Top = Top - sp.diags(np.asarray(Top.sum(axis=1)).ravel())   # zero row sums
+    res = (Top @ Pm).toarray()
+    lv = oracle.cell_levels(pb)
+    assert np.max(np.abs(res[lv == 0])) <= 1e-12 * np.abs(T).max()
+
+
+# -------------------------------------------------- coarse operator ----
+
+@pytest.mark.parametrize("restriction", [FV, FE])
+def test_coarse_operator_equals_sparse_triple_product(restriction):
+    pb = small_problem(16, 12, 8, (4, 4, 4), sigma=2.0)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p = np.random.default_rng(4).uniform(0, 1, pb.n)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
+    Ac = oracle.coarse_operator(pb, W, diag, P, restriction)
+    Nc = oracle.num_coarse(pb)
+    A = helpers.stencil_matrix(pb, W, diag)
+    Ph = helpers.prolongation_matrix(pb, P, oracle.slot_nodes(pb), Nc)
+    R = Ph.T if restriction == FE else helpers.fv_restriction_matrix(oracle.primal_block(pb), Nc)
+    ref = (R @ A @ Ph).toarray()
+    assert np.max(np.abs(Ac - ref)) <= 1e-13 * np.abs(ref).max()
+    if restriction == FE:
+        assert np.max(np.abs(Ac - Ac.T)) <= 1e-15 * np.abs(Ac).max() * 10
+        np.linalg.cholesky(Ac)      # SPD (Sec. 4.2: MSFE always converges)
+
+
+def test_lu_solve_matches_numpy():
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(40, 40)) + 3 * np.eye(40)
+    b = rng.normal(size=40)
+    LU, piv = oracle.lu_factor(A)
+    x = oracle.lu_solve(LU, piv, b)
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------- ILU(0) ----
+
+@pytest.mark.parametrize("ordering", ["natural", "redblack"])
+def test_ilu0_defining_property_and_apply(ordering):
+    """ILU(0): (L U)_ij = A_ij on the sparsity pattern of A (permuted), and
+    one application equals forward/backward substitution with L, U."""
+    pb = small_problem(7, 6, 5, 3, sigma=2.0)
+    T = oracle.transmissibility(pb)
+    p = np.random.default_rng(6).uniform(0, 1, pb.n)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
+    order = np.arange(pb.n) if ordering == "natural" else oracle.redblack_order(pb)
+    ilu = oracle.ILU0(pb, W, diag, order=order)
+    rp, col, val = ilu.export()
+    N = pb.n
+    F = sp.csr_matrix((val, col, rp), shape=(N, N)).toarray()
+    L = np.tril(F, -1) + np.eye(N)
+    U = np.triu(F)
+    A = helpers.stencil_matrix(pb, W, diag).toarray()[np.ix_(order, order)]
+    pattern = A != 0
+    assert np.max(np.abs((L @ U - A)[pattern])) <= 1e-13 * np.abs(A).max()
+    assert np.all(np.diag(U) > 0)            # M-matrix: positive pivots
+    z = np.random.default_rng(7).normal(size=N)
+    y = spla.spsolve_triangular(sp.csr_matrix(L), z[order], lower=True)
+    x = spla.spsolve_triangular(sp.csr_matrix(U), y, lower=False)
+    expect = np.zeros(N); expect[order] = x
+    assert np.allclose(ilu.apply(z), expect, rtol=1e-12, atol=1e-14)
+
+
+# -------------------------------------------------------------- C-AMS ----
+
+def _setup(pb, restriction):
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p = pb.initial_pressure()
+    W, diag, r, _ = oracle.linear_system(pb, T, p, p)
+    Ac = oracle.coarse_operator(pb, W, diag, P, restriction)
+    LU, piv = oracle.lu_factor(Ac)
+    return T, P, W, diag, r, LU, piv
+
+
+def test_msfv_stage_is_conservative():
+    """After the MSFV coarse stage the residual sums to zero over every
+    primal block (Sec. 4: a conservative velocity can be built)."""
+    pb = small_problem(16, 16, 8, (4, 4, 4), sigma=2.0)
+    T, P, W, diag, r, LU, piv = _setup(pb, FV)
+    dc = oracle.lu_solve(LU, piv, oracle.restrict(pb, P, FV, r))
+    d1 = oracle.prolong(pb, P, dc)
+    r1 = r - oracle.matvec(pb, W, diag, d1)
+    blk = oracle.primal_block(pb)
+    sums = np.bincount(blk, weights=r1)
+    assert np.max(np.abs(sums)) <= 1e-12 * np.abs(r).sum()
+
+
+def test_msfe_stage_is_galerkin_orthogonal():
+    pb = small_problem(16, 16, 8, (4, 4, 4), sigma=2.0)
+    T, P, W, diag, r, LU, piv = _setup(pb, FE)
+    dc = oracle.lu_solve(LU, piv, oracle.restrict(pb, P, FE, r))
+    d1 = oracle.prolong(pb, P, dc)
+    r1 = r - oracle.matvec(pb, W, diag, d1)
+    Nc = oracle.num_coarse(pb)
+    Ph = helpers.prolongation_matrix(pb, P, oracle.slot_nodes(pb), Nc)
+    assert np.max(np.abs(Ph.T @ r1)) <= 1e-12 * np.abs(r).sum()
+
+
+@pytest.mark.parametrize("restriction,n_pre", [(FV, 0), (FE, 0), (FV, 5)])
+def test_cams_converges_to_sparse_lu_solution(restriction, n_pre):
+    pb = small_problem(16, 16, 8, (4, 4, 4), sigma=2.0)
+    T, P, W, diag, r, LU, piv = _setup(pb, restriction)
+    ilu = oracle.ILU0(pb, W, diag)
+    d, its, hist = oracle.cams_solve(pb, W, diag, P, restriction, LU, piv, ilu, r,
+                                     n_pre=n_pre, n_post=5, rtol=1e-14, maxit=300)
+    assert its > 0
+    ref = spla.splu(helpers.stencil_matrix(pb, W, diag).tocsc()).solve(r)
+    assert np.max(np.abs(d - ref)) <= 1e-12 * np.abs(ref).max()
+    # deterministic iteration count and iterates
+    d2, its2, _ = oracle.cams_solve(pb, W, diag, P, restriction, LU, piv, ilu, r,
+                                    n_pre=n_pre, n_post=5, rtol=1e-14, maxit=300)
+    assert its2 == its and np.array_equal(d, d2)
+
+
+def test_config1_newton_matches_direct_newton():
+    """Converged C-AMS Newton (MSFV, 5 pre + 5 post ILU(0)) equals Newton
+    with sparse LU solves (C-AMS is an exact solver, Sec. 1)."""
+    pb = config1()
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, rc, st = oracle.newton_step(pb, T, P, p0, p0, lin_rtol=1e-13, newton_tol=1e-12)
+    assert rc == 0
+    ref, _ = helpers.direct_newton(pb, T, p0, p0, tol=1e-12)
+    assert np.max(np.abs(p - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.slow
+def test_3d_newton_matches_direct_newton_fe():
+    pb = small_problem(24, 24, 16, 8, sigma=3.0, c=0.05, dt=0.05)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, rc, st = oracle.newton_step(pb, T, P, p0, p0, restriction=FE, lin_rtol=1e-13, newton_tol=1e-12)
+    assert rc == 0
+    ref, _ = helpers.direct_newton(pb, T, p0, p0, tol=1e-12)
+    assert np.max(np.abs(p - ref)) <= 1e-10 * np.abs(ref).max()
