@@ -1,0 +1,218 @@
+/*
+ * cams.h — C ABI of the MI355X C-AMS pressure solver (libcams.so).
+ *
+ * Compressible algebraic multiscale solver (C-AMS) of Tene, Wang and
+ * Hajibeygi, "Adaptive Algebraic Multiscale Solver for Compressible Flow in
+ * Heterogeneous Porous Media" (arXiv 1705.05783).  Equations are numbered in
+ * order of appearance in the paper: (1) mass balance, (2) backward-Euler
+ * nonlinear pressure equation, (3)-(5) its linearisation, (6) the algebraic
+ * system, (7) finite-volume restriction, (8)-(11) basis types B1-B4, (12)
+ * superposition, (13) coarse system R A P, (14)-(15) multiscale solution and
+ * correction, (16) nonlinear error.  Table "cams" is the iteration procedure.
+ *
+ * Conventions shared by every entry point
+ *  - Cells are indexed n = i + nx*(j + ny*k), x fastest, zero based.  A grid
+ *    with nz == 1 is two-dimensional.
+ *  - Every array argument named *_dev is DEVICE memory on the context's
+ *    device, FP64 unless stated, borrowed for the duration of the call only
+ *    (the library keeps no pointer to it).  Arrays named *_host are host
+ *    memory, copied before the call returns.
+ *  - All device work is enqueued on the HIP stream given to cams_create.
+ *    Calls that return a host-visible number (eps_norm_out, cams_stats)
+ *    synchronise that stream; the others return after enqueueing.
+ *  - The library allocates no device memory of its own beyond one small
+ *    pinned host buffer: all device state lives in a caller-provided
+ *    workspace (cams_workspace_bytes / cams_set_workspace), typically a
+ *    torch.empty(..., dtype=torch.uint8) buffer.  The workspace must outlive
+ *    the context.
+ *  - Errors are returned as cams_status; nothing is thrown across the ABI.
+ *    cams_last_error gives a readable message for the last failure.
+ *  - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef CAMS_H
+#define CAMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cams_ctx cams_ctx;
+
+typedef enum {
+    CAMS_OK = 0,
+    CAMS_E_ARG = -1,           /* invalid argument (checked on the host before any device work) */
+    CAMS_E_STATE = -2,         /* call out of order (e.g. iterate before assemble) */
+    CAMS_E_DEVICE = -3,        /* a HIP runtime call failed */
+    CAMS_E_NOMEM = -4,         /* workspace missing or too small */
+    CAMS_E_NOT_CONVERGED = -5, /* iteration limit reached; last iterate is kept */
+    CAMS_E_BREAKDOWN = -6      /* NaN/Inf norm, zero pivot or non-positive local pivot */
+} cams_status;
+
+/* Restriction operator (Sec. 3): finite volume, Eq. (7), or finite element R = P^T. */
+enum { CAMS_R_FV = 0, CAMS_R_FE = 1 };
+
+/* Arithmetic of the solve.  FP64: everything in double.  MIXED_FP32: matrix
+ * copy, smoother, basis and prolongation in float with float accumulation;
+ * residual, Newton update, norms and the coarse solve in double (iterative
+ * refinement).  MIXED_BF16: as MIXED_FP32 but the basis stored in bfloat16. */
+enum { CAMS_FP64 = 0, CAMS_MIXED_FP32 = 1, CAMS_MIXED_BF16 = 2 };
+
+typedef struct {
+    int32_t nx, ny, nz;       /* fine cells per axis, >= 2 on active axes (nz == 1 for 2D) */
+    double dx, dy, dz;        /* cell sizes (> 0) */
+    int32_t rx, ry, rz;       /* coarsening ratio per axis, 2..8 (rz = 1 in 2D) */
+} cams_grid;
+
+/* Fluid and time step (Sec. 2, Eqs. (1)-(2)): rho(p) = rho0 exp(c (p - p0)),
+ * viscosity mu, backward-Euler step dt. */
+typedef struct {
+    double rho0, c, p0, mu, dt;
+} cams_fluid;
+
+typedef struct {
+    int32_t restriction;      /* CAMS_R_FV or CAMS_R_FE */
+    int32_t n_pre;            /* ILU(0) Richardson steps before the multiscale stage (0..64) */
+    int32_t n_post;           /* ILU(0) Richardson steps after it (Table "cams" step 6; 0..64) */
+    int32_t precision;        /* CAMS_FP64 / CAMS_MIXED_FP32 / CAMS_MIXED_BF16 */
+    double lin_rtol;          /* stop when ||r||_2 <= lin_rtol ||r0||_2 */
+    int32_t lin_maxit;        /* linear iteration limit */
+    double newton_tol;        /* stop Newton when ||eps||_2 <= newton_tol (Eq. (16)) */
+    int32_t newton_maxit;     /* Newton iteration limit per time step */
+} cams_options;
+
+typedef struct {
+    int32_t newton_iters;     /* linear solves performed in the last cams_newton_step */
+    int32_t lin_iters_total;  /* C-AMS iterations summed over those solves */
+    int32_t lin_iters_last;   /* C-AMS iterations of the last cams_iterate */
+    int32_t reserved;
+    double relres_last;       /* ||r||/||r0|| at the end of the last cams_iterate */
+    double eps_norm_last;     /* last ||eps||_2 from cams_assemble */
+    double t_assemble_ms;     /* device time of the last newton step's phases (hipEvent) */
+    double t_basis_ms;
+    double t_coarse_ms;
+    double t_iterate_ms;
+} cams_stats;
+
+/* Create a context for one grid.  Validates grid/fluid/options: active axes
+ * >= 2 cells, 2 <= r <= 8 and r <= n per axis, vertex spacing >= 2 cells,
+ * at most 32768 coarse nodes, dx,dy,dz,dt,mu,rho0 > 0, c >= 0, tolerances
+ * > 0, precision CAMS_FP64.  `hip_stream` is a hipStream_t (NULL = default
+ * stream).  Makes no HIP call (works without a GPU); on success *out owns
+ * no device memory.  Release with cams_destroy.  Errors: CAMS_E_ARG,
+ * CAMS_E_NOMEM (host allocation). */
+cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const cams_options *opt,
+                        void *hip_stream, cams_ctx **out);
+
+/* Bytes of device workspace the context needs (256-byte aligned). */
+size_t cams_workspace_bytes(const cams_ctx *ctx);
+
+/* Hand over the device workspace: `dev_ptr` must be 256-byte aligned and hold
+ * at least cams_workspace_bytes() bytes; its contents are overwritten and
+ * all rock, well and basis state is reset.  The first call also allocates a
+ * 4 KB pinned host buffer for scalar read-backs.
+ * Errors: CAMS_E_ARG (null, misaligned), CAMS_E_NOMEM (too small),
+ * CAMS_E_DEVICE. */
+cams_status cams_set_workspace(cams_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Rock properties (Sec. 2): isotropic permeability perm_dev[N] (> 0), porosity
+ * phi_dev[N] (0 < phi <= 1), optional source q_dev[N] per unit volume (NULL =
+ * none).  Copies them into the workspace and computes the two-point
+ * transmissibilities (harmonic average of the two half-cell conductances,
+ * Eq. (6)).  Invalidates any basis already built.
+ * Errors: CAMS_E_STATE (no workspace), CAMS_E_ARG (null pointers),
+ * CAMS_E_BREAKDOWN (a permeability or porosity value is out of range). */
+cams_status cams_set_rock(cams_ctx *ctx, const double *perm_dev, const double *phi_dev,
+                          const double *q_dev);
+
+/* Dirichlet (well) cells: cells_host[n] are cell indices, p_host[n] their fixed
+ * pressures (wells as fixed-pressure cells, Sec. 4.2 test case 2).
+ * Replaces any earlier set.  n = 0 removes all wells (then c > 0 is required
+ * for a non-singular system).  Errors: CAMS_E_ARG (index out of range,
+ * duplicate, non-finite pressure), CAMS_E_STATE (no workspace). */
+cams_status cams_set_wells(cams_ctx *ctx, const int64_t *cells_host, const double *p_host, int32_t n);
+
+/* Assemble the Newton linear system at pressure p_dev, old-time pressure
+ * pn_dev (Sec. 2, Eqs. (2)-(6), multiplied by rho_i dV_i):
+ *   A_ii = phi_i c rho(pn_i) dV/dt + sum_j W_ij,  A_ij = -W_ij,
+ *   W_ij = T_ij (rho(p_i) + rho(p_j))/2,  r = -F(p)
+ * with Dirichlet rows/columns set to identity and r = 0 there.  Writes the
+ * nonlinear error norm ||eps||_2 (Eq. (16), eps_i = F_i/(rho_i dV)) to
+ * *eps_norm_out (host pointer, may be NULL; non-NULL synchronises).
+ * Errors: CAMS_E_STATE (no rock), CAMS_E_ARG, CAMS_E_DEVICE. */
+cams_status cams_assemble(cams_ctx *ctx, const double *p_dev, const double *pn_dev,
+                          double *eps_norm_out);
+
+/* Build the prolongation from basis type B4 (Sec. 3, Eq. (11)) with
+ * reduced-problem boundary conditions: vertices, then dual edges (1D),
+ * faces (2D) and interiors (3D) by exact local solves, one workgroup per
+ * dual region.  Pressure independent: built once per rock.
+ * Errors: CAMS_E_STATE (no rock), CAMS_E_BREAKDOWN (non-positive pivot). */
+cams_status cams_build_basis(cams_ctx *ctx);
+
+/* Coarse operator A_c = R A P_hat (Eq. (13); P_hat = basis with Dirichlet rows
+ * zeroed, R = R^FV of Eq. (7) or P_hat^T) and its factorisation (LU with
+ * partial pivoting, then the explicit inverse used by every coarse solve).
+ * Errors: CAMS_E_STATE (no basis or no assembled system), CAMS_E_BREAKDOWN
+ * (singular coarse matrix). */
+cams_status cams_coarse_op(cams_ctx *ctx);
+
+/* Solve the assembled system for the Newton update by C-AMS iterations
+ * (Table "cams"; Eq. (15) multiscale stage, ILU(0) smoothing in red-black
+ * order) and add it to p_dev in place:  p <- p + d,  A d = r.  Stops when
+ * ||r||_2 <= lin_rtol ||r0||_2 or after lin_maxit iterations.  `stats` may be
+ * NULL.  Errors: CAMS_E_STATE (no coarse operator for the current system),
+ * CAMS_E_NOT_CONVERGED (limit reached; p holds the last iterate),
+ * CAMS_E_BREAKDOWN (non-finite residual norm). */
+cams_status cams_iterate(cams_ctx *ctx, double *p_dev, cams_stats *stats);
+
+/* One backward-Euler time step: Dirichlet values are imposed on p_dev, the
+ * basis is built if needed, then repeat assemble -> (stop if ||eps||_2 <=
+ * newton_tol) -> coarse_op -> iterate, at most newton_maxit solves.
+ * p_dev (in/out) starts as the initial guess (normally pn_dev).
+ * Errors: as the calls above; CAMS_E_NOT_CONVERGED if Newton does not reach
+ * newton_tol. */
+cams_status cams_newton_step(cams_ctx *ctx, const double *pn_dev, double *p_dev, cams_stats *stats);
+
+/* One application of the smoother, x = M^{-1} z, with M the ILU(0) factor of
+ * the assembled matrix in red-black order (Table "cams" step 6).  z_dev and
+ * x_dev have N entries.  Errors: CAMS_E_STATE (no coarse_op for the current
+ * system: the factor is computed there). */
+cams_status cams_smooth_apply(cams_ctx *ctx, const double *z_dev, double *x_dev);
+
+/* Copy an internal array to dst_dev (device, `bytes` >= cams_array_bytes).
+ * For inspection and parity tests.  Errors: CAMS_E_ARG, CAMS_E_STATE. */
+typedef enum {
+    CAMS_ARR_T = 0,        /* 3*N doubles: Tx, Ty, Tz (face on its lower cell) */
+    CAMS_ARR_W = 1,        /* 3*N doubles: masked off-diagonal magnitudes of A */
+    CAMS_ARR_DIAG = 2,     /* N doubles */
+    CAMS_ARR_R0 = 3,       /* N doubles: Newton residual r = -F */
+    CAMS_ARR_P = 4,        /* 8*N doubles: basis weights, slot-major */
+    CAMS_ARR_AC = 5,       /* Nc*Nc doubles: coarse operator, row-major (before factorisation) */
+    CAMS_ARR_AC_INV = 6,   /* Nc*Nc doubles: inverse of the coarse operator */
+    CAMS_ARR_INVD = 7      /* N doubles: inverse ILU(0) pivots (red-black order) */
+} cams_array;
+
+size_t cams_array_bytes(const cams_ctx *ctx, cams_array which);
+cams_status cams_export(cams_ctx *ctx, cams_array which, void *dst_dev, size_t bytes);
+
+/* Test hook of the coarse factorisation's FP64 matrix-core GEMM: C -= A B for
+ * dense row-major DEVICE matrices C (M x Nn), A (M x K), B (K x Nn), run on the
+ * context's stream and synchronised.  Used by the parity tests of the blocked
+ * LU (Sec. 3, coarse solve of Eq. (15)).  Errors: CAMS_E_ARG, CAMS_E_DEVICE. */
+cams_status cams_debug_gemm_sub(cams_ctx *ctx, double *C_dev, const double *A_dev, const double *B_dev,
+                                int M, int Nn, int K);
+
+/* Number of coarse nodes (product of ceil(n/r) per axis). */
+int64_t cams_num_coarse(const cams_ctx *ctx);
+
+cams_status cams_destroy(cams_ctx *ctx);
+const char *cams_status_string(cams_status s);
+const char *cams_last_error(const cams_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAMS_H */

@@ -1,0 +1,151 @@
+"""ctypes binding of libcams.so: the C ABI of include/cams.h, same names.
+
+Argument marshalling only; every step of the solve runs in the HIP library.
+Importing this module raises if the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcams.so")
+
+CAMS_OK = 0
+CAMS_E_ARG = -1
+CAMS_E_STATE = -2
+CAMS_E_DEVICE = -3
+CAMS_E_NOMEM = -4
+CAMS_E_NOT_CONVERGED = -5
+CAMS_E_BREAKDOWN = -6
+
+CAMS_R_FV = 0
+CAMS_R_FE = 1
+CAMS_FP64 = 0
+CAMS_MIXED_FP32 = 1
+CAMS_MIXED_BF16 = 2
+
+CAMS_ARR_T = 0
+CAMS_ARR_W = 1
+CAMS_ARR_DIAG = 2
+CAMS_ARR_R0 = 3
+CAMS_ARR_P = 4
+CAMS_ARR_AC = 5
+CAMS_ARR_AC_INV = 6
+CAMS_ARR_INVD = 7
+
+
+class cams_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("rx", ctypes.c_int32), ("ry", ctypes.c_int32), ("rz", ctypes.c_int32)]
+
+
+class cams_fluid(ctypes.Structure):
+    _fields_ = [("rho0", ctypes.c_double), ("c", ctypes.c_double), ("p0", ctypes.c_double),
+                ("mu", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+class cams_options(ctypes.Structure):
+    _fields_ = [("restriction", ctypes.c_int32), ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("lin_rtol", ctypes.c_double), ("lin_maxit", ctypes.c_int32),
+                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32)]
+
+
+class cams_stats(ctypes.Structure):
+    _fields_ = [("newton_iters", ctypes.c_int32), ("lin_iters_total", ctypes.c_int32),
+                ("lin_iters_last", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("relres_last", ctypes.c_double), ("eps_norm_last", ctypes.c_double),
+                ("t_assemble_ms", ctypes.c_double), ("t_basis_ms", ctypes.c_double),
+                ("t_coarse_ms", ctypes.c_double), ("t_iterate_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+# (name, restype, argtypes) for every entry point declared in include/cams.h
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = [
+    ("cams_create", _I, [ctypes.POINTER(cams_grid), ctypes.POINTER(cams_fluid), ctypes.POINTER(cams_options),
+                         _VP, ctypes.POINTER(_VP)]),
+    ("cams_workspace_bytes", ctypes.c_size_t, [_VP]),
+    ("cams_set_workspace", _I, [_VP, _VP, ctypes.c_size_t]),
+    ("cams_set_rock", _I, [_VP, _VP, _VP, _VP]),
+    ("cams_set_wells", _I, [_VP, _VP, _VP, ctypes.c_int32]),
+    ("cams_assemble", _I, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double)]),
+    ("cams_build_basis", _I, [_VP]),
+    ("cams_coarse_op", _I, [_VP]),
+    ("cams_iterate", _I, [_VP, _VP, ctypes.POINTER(cams_stats)]),
+    ("cams_newton_step", _I, [_VP, _VP, _VP, ctypes.POINTER(cams_stats)]),
+    ("cams_smooth_apply", _I, [_VP, _VP, _VP]),
+    ("cams_array_bytes", ctypes.c_size_t, [_VP, _I]),
+    ("cams_export", _I, [_VP, _I, _VP, ctypes.c_size_t]),
+    ("cams_num_coarse", ctypes.c_int64, [_VP]),
+    ("cams_debug_gemm_sub", _I, [_VP, _VP, _VP, _VP, _I, _I, _I]),
+    ("cams_destroy", _I, [_VP]),
+    ("cams_status_string", ctypes.c_char_p, [_I]),
+    ("cams_last_error", ctypes.c_char_p, [_VP]),
+]
+
+EXPORTED = [name for name, _, _ in _SIGS]
+
+_lib = None
+
+
+def load():
+    """Load libcams.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1705_05783_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class CamsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def check(status, ctx=None, what=""):
+    if status != CAMS_OK:
+        lib = load()
+        detail = lib.cams_last_error(ctx).decode() if ctx else lib.cams_status_string(status).decode()
+        raise CamsError(status, f"{what}: {detail}")
+    return status
+
+
+def _fwd(name):
+    def f(*args):
+        return getattr(load(), name)(*args)
+    f.__name__ = name
+    return f
+
+
+cams_create = _fwd("cams_create")
+cams_workspace_bytes = _fwd("cams_workspace_bytes")
+cams_set_workspace = _fwd("cams_set_workspace")
+cams_set_rock = _fwd("cams_set_rock")
+cams_set_wells = _fwd("cams_set_wells")
+cams_assemble = _fwd("cams_assemble")
+cams_build_basis = _fwd("cams_build_basis")
+cams_coarse_op = _fwd("cams_coarse_op")
+cams_iterate = _fwd("cams_iterate")
+cams_newton_step = _fwd("cams_newton_step")
+cams_smooth_apply = _fwd("cams_smooth_apply")
+cams_array_bytes = _fwd("cams_array_bytes")
+cams_export = _fwd("cams_export")
+cams_num_coarse = _fwd("cams_num_coarse")
+cams_debug_gemm_sub = _fwd("cams_debug_gemm_sub")
+cams_destroy = _fwd("cams_destroy")
+cams_status_string = _fwd("cams_status_string")
+cams_last_error = _fwd("cams_last_error")

@@ -1,0 +1,667 @@
+// C ABI of libcams: argument validation, workspace layout and the host-side
+// sequencing of the C-AMS kernels (Table "cams").  All device work goes to
+// the caller's stream; host reads happen only where a norm decides control
+// flow (Newton and linear stopping tests).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cams_internal.h"
+
+using namespace cams;
+
+namespace cams {
+void launch_gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, const double *B, int ldb, int M,
+                     int Nn, int K);
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+cams_status fail(cams_ctx *c, cams_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+int num_blocks(int n, int r) { return (n + r - 1) / r; }
+
+// Vertex coordinate of primal block a: start + floor(len/2).
+std::vector<int32_t> vertex_coords(int n, int r)
+{
+    const int nb = num_blocks(n, r);
+    std::vector<int32_t> v(nb);
+    for (int a = 0; a < nb; ++a) {
+        const int s = a * r, e = std::min((a + 1) * r, n);
+        v[a] = s + (e - s) / 2;
+    }
+    return v;
+}
+
+struct Segment {
+    int s, len;
+    bool free_axis;
+};
+
+// Per axis: vertex coordinates as fixed one-cell segments and the maximal
+// runs between them (including the stubs next to the domain boundary).
+std::vector<Segment> segments(int n, const std::vector<int32_t> &v, bool active)
+{
+    std::vector<Segment> out;
+    if (!active) {
+        out.push_back({0, 1, false});
+        return out;
+    }
+    int x = 0;
+    for (size_t a = 0; a <= v.size(); ++a) {
+        const int stop = a < v.size() ? v[a] : n;
+        if (stop > x) out.push_back({x, stop - x, true});
+        if (a < v.size()) out.push_back({v[a], 1, false});
+        x = stop + 1;
+    }
+    return out;
+}
+
+struct Layout {
+    size_t *off;
+    size_t total = 0;
+    size_t add(size_t bytes)
+    {
+        size_t o = total;
+        total = align_up(total + bytes);
+        return o;
+    }
+};
+
+void sync_status(cams_ctx *c, int32_t *flags)
+{
+    CAMS_HIP(hipMemcpyAsync(c->host, c->a.status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    CAMS_HIP(hipStreamSynchronize(c->stream));
+    memcpy(flags, c->host, sizeof(int32_t));
+}
+
+double read_scalar(cams_ctx *c, const double *dev)
+{
+    CAMS_HIP(hipMemcpyAsync(c->host, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    CAMS_HIP(hipStreamSynchronize(c->stream));
+    return c->host[0];
+}
+
+void clear_status(cams_ctx *c)
+{
+    // a one-word host-to-device copy keeps graph capture free of memset nodes
+    int32_t zero[4] = {0, 0, 0, 0};
+    memcpy(c->host + 8, zero, sizeof(zero));
+    CAMS_HIP(hipMemcpyAsync(c->a.status, c->host + 8, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+}
+
+float elapsed_ms(cams_ctx *c, int a, int b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.f;
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cams_status_string(cams_status s)
+{
+    switch (s) {
+    case CAMS_OK: return "ok";
+    case CAMS_E_ARG: return "invalid argument";
+    case CAMS_E_STATE: return "call out of order";
+    case CAMS_E_DEVICE: return "HIP runtime error";
+    case CAMS_E_NOMEM: return "workspace missing or too small";
+    case CAMS_E_NOT_CONVERGED: return "not converged";
+    case CAMS_E_BREAKDOWN: return "numerical breakdown";
+    }
+    return "unknown status";
+}
+
+const char *cams_last_error(const cams_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const cams_options *opt, void *hip_stream,
+                        cams_ctx **out)
+{
+    if (!out) return CAMS_E_ARG;
+    *out = nullptr;
+    if (!grid || !fluid || !opt) return CAMS_E_ARG;
+    const cams_grid &G = *grid;
+    const bool three_d = G.nz > 1;
+    const int n[3] = {G.nx, G.ny, G.nz};
+    int r[3] = {G.rx, G.ry, three_d ? G.rz : 1};
+    for (int a = 0; a < 3; ++a) {
+        const bool active = a < 2 || three_d;
+        if (!active) {
+            if (n[a] != 1) return CAMS_E_ARG;
+            continue;
+        }
+        if (n[a] < 2 || r[a] < 2 || r[a] > kMaxRatio || r[a] > n[a]) return CAMS_E_ARG;
+        std::vector<int32_t> v = vertex_coords(n[a], r[a]);
+        for (size_t b = 1; b < v.size(); ++b)
+            if (v[b] - v[b - 1] < 2) return CAMS_E_ARG;  // adjacent vertex lines are not supported
+    }
+    const double N = (double)G.nx * G.ny * G.nz;
+    if (N > 2.0e9) return CAMS_E_ARG;
+    if (!(G.dx > 0) || !(G.dy > 0) || !(G.dz > 0)) return CAMS_E_ARG;
+    const cams_fluid &F = *fluid;
+    if (!(F.rho0 > 0) || !(F.c >= 0) || !(F.mu > 0) || !(F.dt > 0) || !isfinite(F.p0) || !isfinite(F.c))
+        return CAMS_E_ARG;
+    const cams_options &O = *opt;
+    if (O.restriction != CAMS_R_FV && O.restriction != CAMS_R_FE) return CAMS_E_ARG;
+    if (O.n_pre < 0 || O.n_pre > 64 || O.n_post < 0 || O.n_post > 64) return CAMS_E_ARG;
+    if (O.precision != CAMS_FP64) return CAMS_E_ARG;  // mixed precision: not in this library build
+    if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
+    const int nb[3] = {num_blocks(n[0], r[0]), num_blocks(n[1], r[1]), num_blocks(n[2], r[2])};
+    const double Nc = (double)nb[0] * nb[1] * nb[2];
+    if (Nc > 32768) return CAMS_E_ARG;  // dense coarse operator limit
+
+    cams_ctx *c = new (std::nothrow) cams_ctx();
+    if (!c) return CAMS_E_NOMEM;
+    c->grid = G;
+    c->grid.rz = r[2];
+    c->fluid = F;
+    c->opt = O;
+    c->stream = (hipStream_t)hip_stream;
+    GridDev &g = c->g;
+    g.nx = G.nx; g.ny = G.ny; g.nz = G.nz;
+    g.N = G.nx * G.ny * G.nz;
+    g.sxy = G.nx * G.ny;
+    g.dx = G.dx; g.dy = G.dy; g.dz = G.dz;
+    g.dV = G.dx * G.dy * G.dz;
+    for (int a = 0; a < 3; ++a) { g.nb[a] = nb[a]; g.r[a] = r[a]; }
+    g.Nc = nb[0] * nb[1] * nb[2];
+    g.dim = three_d ? 3 : 2;
+    c->fl = {F.rho0, F.c, F.p0, F.mu, F.dt};
+
+    // per-axis tables: vc (nb), lo (n), isv (n, stored as int32)
+    cams_ctx &t = *c;
+    std::vector<Segment> seg[3];
+    for (int a = 0; a < 3; ++a) {
+        std::vector<int32_t> v = (a < 2 || three_d) ? vertex_coords(n[a], r[a]) : std::vector<int32_t>{0};
+        t.tab_off[a][0] = t.tab.size();
+        for (int32_t x : v) t.tab.push_back(x);
+        t.tab_off[a][1] = t.tab.size();
+        for (int x = 0; x < n[a]; ++x) {
+            int lo = 0;
+            for (size_t b = 0; b < v.size(); ++b)
+                if (v[b] <= x) lo = (int)b;
+            t.tab.push_back(lo);
+        }
+        t.tab_off[a][2] = t.tab.size();
+        // isv packed 4 per int32 word (uint8 view)
+        std::vector<uint8_t> isv(n[a], 0);
+        for (int32_t x : v) isv[x] = 1;
+        const size_t words = (n[a] + 3) / 4;
+        size_t base = t.tab.size();
+        t.tab.resize(base + words, 0);
+        memcpy(t.tab.data() + base, isv.data(), n[a]);
+        seg[a] = segments(n[a], v, a < 2 || three_d);
+    }
+    // dual regions by number of open axes
+    std::vector<Region> by[4];
+    for (const Segment &sz : seg[2])
+        for (const Segment &sy : seg[1])
+            for (const Segment &sx : seg[0]) {
+                int fm = (sx.free_axis ? 1 : 0) | (sy.free_axis ? 2 : 0) | (sz.free_axis ? 4 : 0);
+                int nf = __builtin_popcount(fm);
+                if (nf == 0) continue;
+                Region R;
+                R.s[0] = sx.s; R.s[1] = sy.s; R.s[2] = sz.s;
+                R.len[0] = sx.len; R.len[1] = sy.len; R.len[2] = sz.len;
+                R.freemask = fm;
+                R.pad = 0;
+                by[nf].push_back(R);
+            }
+    int off = 0;
+    for (int f = 0; f < 4; ++f) {
+        c->nreg[f] = (int)by[f].size();
+        c->regoff[f] = off;
+        off += c->nreg[f];
+        for (const Region &R : by[f]) t.regions.push_back(R);
+    }
+    c->region_total = off;
+
+    // workspace layout
+    Layout L;
+    L.off = c->off;
+    const size_t n8 = (size_t)g.N * 8;
+    const size_t nc = (size_t)g.Nc;
+    c->nparts = (g.N + kBlock - 1) / kBlock;
+    int k = 0;
+    L.off[k++] = L.add(3 * n8);        // 0 T
+    L.off[k++] = L.add(n8);            // 1 phi
+    L.off[k++] = L.add(n8);            // 2 q
+    L.off[k++] = L.add(3 * n8);        // 3 W
+    L.off[k++] = L.add(n8);            // 4 diag
+    L.off[k++] = L.add(n8);            // 5 r0
+    L.off[k++] = L.add(n8);            // 6 r
+    L.off[k++] = L.add(n8);            // 7 dp0
+    L.off[k++] = L.add(n8);            // 8 dp1
+    L.off[k++] = L.add(n8);            // 9 d0
+    L.off[k++] = L.add(n8);            // 10 d1
+    L.off[k++] = L.add(n8);            // 11 d2
+    L.off[k++] = L.add(n8);            // 12 z
+    L.off[k++] = L.add(n8);            // 13 x
+    L.off[k++] = L.add(n8);            // 14 invd
+    L.off[k++] = L.add(8 * n8);        // 15 P
+    L.off[k++] = L.add(nc * nc * 8);   // 16 Ac
+    L.off[k++] = L.add(nc * nc * 8);   // 17 Ainv
+    L.off[k++] = L.add(nc * nc * 8);   // 18 work
+    L.off[k++] = L.add(nc * 8);        // 19 rc
+    L.off[k++] = L.add(nc * 8);        // 20 xc
+    L.off[k++] = L.add((size_t)c->nparts * 8);  // 21 partial
+    L.off[k++] = L.add(64 * 8);        // 22 scal
+    L.off[k++] = L.add(nc * 2 * 4);    // 23 piv + perm
+    L.off[k++] = L.add(64 * 4);        // 24 status
+    L.off[k++] = L.add((size_t)g.N);   // 25 dmask
+    const size_t wcap = (size_t)g.N / 8 + 64;
+    L.off[k++] = L.add(wcap * 4);      // 26 wcell
+    L.off[k++] = L.add(wcap * 8);      // 27 wp
+    L.off[k++] = L.add(t.tab.size() * 4);            // 28 tables
+    L.off[k++] = L.add(t.regions.size() * sizeof(Region) + 16);  // 29 regions
+    c->need = L.total;
+
+    *out = c;
+    return CAMS_OK;
+}
+
+size_t cams_workspace_bytes(const cams_ctx *c) { return c ? c->need : 0; }
+
+int64_t cams_num_coarse(const cams_ctx *c) { return c ? c->g.Nc : 0; }
+
+cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
+{
+    if (!c || !dev_ptr) return CAMS_E_ARG;
+    if (((uintptr_t)dev_ptr) % kAlign) return fail(c, CAMS_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < c->need) return fail(c, CAMS_E_NOMEM, "workspace too small");
+    const size_t *off = c->off;
+    char *w = (char *)dev_ptr;
+    Arrays &a = c->a;
+    const int N = c->g.N;
+    a.T = (double *)(w + off[0]);
+    a.phi = (double *)(w + off[1]);
+    a.q = (double *)(w + off[2]);
+    a.W = (double *)(w + off[3]);
+    a.diag = (double *)(w + off[4]);
+    a.r0 = (double *)(w + off[5]);
+    a.r = (double *)(w + off[6]);
+    a.dp[0] = (double *)(w + off[7]);
+    a.dp[1] = (double *)(w + off[8]);
+    a.d0 = (double *)(w + off[9]);
+    a.d1 = (double *)(w + off[10]);
+    a.d2 = (double *)(w + off[11]);
+    a.z = (double *)(w + off[12]);
+    a.x = (double *)(w + off[13]);
+    a.invd = (double *)(w + off[14]);
+    a.P = (double *)(w + off[15]);
+    a.Ac = (double *)(w + off[16]);
+    a.Ainv = (double *)(w + off[17]);
+    a.work = (double *)(w + off[18]);
+    a.rc = (double *)(w + off[19]);
+    a.xc = (double *)(w + off[20]);
+    a.partial = (double *)(w + off[21]);
+    a.scal = (double *)(w + off[22]);
+    a.piv = (int32_t *)(w + off[23]);
+    a.status = (int32_t *)(w + off[24]);
+    a.dmask = (uint8_t *)(w + off[25]);
+    a.wcell = (int32_t *)(w + off[26]);
+    a.wp = (double *)(w + off[27]);
+    a.tab = (int32_t *)(w + off[28]);
+    a.regions = (Region *)(w + off[29]);
+    if (!c->host) {
+        // first device interaction of the context: pinned scalars and timers
+        if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
+            c->host = nullptr;
+            return fail(c, CAMS_E_DEVICE, "hipHostMalloc of the scalar buffer failed");
+        }
+        for (int e = 0; e < 8; ++e)
+            if (hipEventCreate(&c->ev[e]) != hipSuccess) c->ev[e] = nullptr;
+    }
+    const cams_ctx &t = *c;
+    for (int ax = 0; ax < 3; ++ax) {
+        c->g.vc[ax] = a.tab + t.tab_off[ax][0];
+        c->g.lo[ax] = a.tab + t.tab_off[ax][1];
+        c->g.isv[ax] = (const uint8_t *)(a.tab + t.tab_off[ax][2]);
+    }
+    try {
+        CAMS_HIP(hipMemcpyAsync(a.tab, t.tab.data(), t.tab.size() * 4, hipMemcpyHostToDevice, c->stream));
+        if (!t.regions.empty())
+            CAMS_HIP(hipMemcpyAsync(a.regions, t.regions.data(), t.regions.size() * sizeof(Region),
+                                    hipMemcpyHostToDevice, c->stream));
+        std::vector<uint8_t> zero((size_t)N, 0);
+        CAMS_HIP(hipMemcpyAsync(a.dmask, zero.data(), (size_t)N, hipMemcpyHostToDevice, c->stream));
+        clear_status(c);
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("set_workspace: ") + hipGetErrorString(e.code));
+    }
+    c->ws = w;
+    c->ws_bytes = bytes;
+    c->has_ws = true;
+    c->has_rock = c->has_basis = c->has_system = c->has_coarse = false;
+    c->nwells = 0;
+    return CAMS_OK;
+}
+
+cams_status cams_set_rock(cams_ctx *c, const double *perm_dev, const double *phi_dev, const double *q_dev)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!c->has_ws) return fail(c, CAMS_E_STATE, "set_rock before set_workspace");
+    if (!perm_dev || !phi_dev) return fail(c, CAMS_E_ARG, "perm and phi are required");
+    const size_t nb = (size_t)c->g.N * 8;
+    try {
+        clear_status(c);
+        launch_check_rock(c, perm_dev, phi_dev);
+        CAMS_HIP(hipMemcpyAsync(c->a.phi, phi_dev, nb, hipMemcpyDeviceToDevice, c->stream));
+        if (q_dev) CAMS_HIP(hipMemcpyAsync(c->a.q, q_dev, nb, hipMemcpyDeviceToDevice, c->stream));
+        launch_transmissibility(c, perm_dev);
+        CAMS_HIP(hipGetLastError());
+        int32_t flags = 0;
+        sync_status(c, &flags);
+        if (flags & F_BAD_INPUT) return fail(c, CAMS_E_BREAKDOWN, "permeability must be > 0, porosity in (0,1]");
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("set_rock: ") + hipGetErrorString(e.code));
+    }
+    c->has_q = q_dev != nullptr;
+    c->has_rock = true;
+    c->has_basis = c->has_system = c->has_coarse = false;
+    return CAMS_OK;
+}
+
+cams_status cams_set_wells(cams_ctx *c, const int64_t *cells, const double *p, int32_t n)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!c->has_ws) return fail(c, CAMS_E_STATE, "set_wells before set_workspace");
+    const size_t wcap = (size_t)c->g.N / 8 + 64;
+    if (n < 0 || (size_t)n > wcap || (n > 0 && (!cells || !p))) return fail(c, CAMS_E_ARG, "bad well list");
+    if (n == 0 && !(c->fl.c > 0)) return fail(c, CAMS_E_ARG, "no wells and c = 0: singular system");
+    std::vector<uint8_t> mask((size_t)c->g.N, 0);
+    std::vector<int32_t> ci(n);
+    std::vector<double> pv(n);
+    for (int t = 0; t < n; ++t) {
+        if (cells[t] < 0 || cells[t] >= c->g.N || !isfinite(p[t])) return fail(c, CAMS_E_ARG, "bad well cell");
+        if (mask[cells[t]]) return fail(c, CAMS_E_ARG, "duplicate well cell");
+        mask[cells[t]] = 1;
+        ci[t] = (int32_t)cells[t];
+        pv[t] = p[t];
+    }
+    try {
+        CAMS_HIP(hipMemcpyAsync(c->a.dmask, mask.data(), mask.size(), hipMemcpyHostToDevice, c->stream));
+        if (n > 0) {
+            CAMS_HIP(hipMemcpyAsync(c->a.wcell, ci.data(), (size_t)n * 4, hipMemcpyHostToDevice, c->stream));
+            CAMS_HIP(hipMemcpyAsync(c->a.wp, pv.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+        }
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("set_wells: ") + hipGetErrorString(e.code));
+    }
+    c->nwells = n;
+    c->has_system = c->has_coarse = false;
+    return CAMS_OK;
+}
+
+cams_status cams_assemble(cams_ctx *c, const double *p_dev, const double *pn_dev, double *eps_norm_out)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!c->has_rock) return fail(c, CAMS_E_STATE, "assemble before set_rock");
+    if (!p_dev || !pn_dev) return fail(c, CAMS_E_ARG, "null pressure");
+    try {
+        launch_assemble(c, p_dev, pn_dev);
+        launch_reduce(c, c->a.partial, c->nparts, c->a.scal + S_EPS2);
+        CAMS_HIP(hipGetLastError());
+        if (eps_norm_out) {
+            double e2 = read_scalar(c, c->a.scal + S_EPS2);
+            *eps_norm_out = sqrt(e2);
+            c->last.eps_norm_last = *eps_norm_out;
+        }
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("assemble: ") + hipGetErrorString(e.code));
+    }
+    c->has_system = true;
+    c->has_coarse = false;
+    return CAMS_OK;
+}
+
+cams_status cams_build_basis(cams_ctx *c)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!c->has_rock) return fail(c, CAMS_E_STATE, "build_basis before set_rock");
+    try {
+        clear_status(c);
+        launch_basis(c);
+        CAMS_HIP(hipGetLastError());
+        int32_t flags = 0;
+        sync_status(c, &flags);
+        if (flags) return fail(c, CAMS_E_BREAKDOWN, "basis: non-positive local pivot or inconsistent region");
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("build_basis: ") + hipGetErrorString(e.code));
+    }
+    c->has_basis = true;
+    c->has_coarse = false;
+    return CAMS_OK;
+}
+
+cams_status cams_coarse_op(cams_ctx *c)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!c->has_basis) return fail(c, CAMS_E_STATE, "coarse_op before build_basis");
+    if (!c->has_system) return fail(c, CAMS_E_STATE, "coarse_op before assemble");
+    try {
+        clear_status(c);
+        launch_coarse_operator(c);
+        launch_ilu_setup(c);
+        launch_coarse_factor(c);
+        CAMS_HIP(hipGetLastError());
+        int32_t flags = 0;
+        sync_status(c, &flags);
+        if (flags & F_SINGULAR_COARSE) return fail(c, CAMS_E_BREAKDOWN, "singular coarse operator");
+        if (flags & F_BAD_PIVOT) return fail(c, CAMS_E_BREAKDOWN, "non-positive ILU(0) pivot");
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("coarse_op: ") + hipGetErrorString(e.code));
+    }
+    c->has_coarse = true;
+    return CAMS_OK;
+}
+
+cams_status cams_smooth_apply(cams_ctx *c, const double *z, double *x)
+{
+    if (!c || !z || !x) return CAMS_E_ARG;
+    if (!c->has_coarse) return fail(c, CAMS_E_STATE, "smoother factor is built by coarse_op");
+    try {
+        launch_smooth(c, z, x, 1);
+        CAMS_HIP(hipGetLastError());
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("smooth_apply: ") + hipGetErrorString(e.code));
+    }
+    return CAMS_OK;
+}
+
+cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!p_dev) return fail(c, CAMS_E_ARG, "null pressure");
+    if (!c->has_coarse) return fail(c, CAMS_E_STATE, "iterate before coarse_op");
+    const cams_options &O = c->opt;
+    const int N = c->g.N;
+    Arrays &a = c->a;
+    cams_status rc = CAMS_OK;
+    int it = 0;
+    double nr0 = 0.0, nr = 0.0;
+    try {
+        launch_fill(c, a.dp[0], N, 0.0);
+        int cur = 0;
+        const double *adds[3] = {nullptr, nullptr, nullptr};
+        for (;; ++it) {
+            const bool pending = adds[0] || adds[1] || adds[2];
+            launch_residual(c, a.dp[cur], adds[0], adds[1], adds[2], pending ? a.dp[1 - cur] : nullptr, a.r);
+            if (pending) cur = 1 - cur;
+            launch_restrict(c, a.r, a.rc, true);
+            nr = sqrt(read_scalar(c, a.scal + S_RN2));
+            if (it == 0) nr0 = nr;
+            if (!isfinite(nr)) { rc = CAMS_E_BREAKDOWN; break; }
+            if (nr <= O.lin_rtol * nr0 || nr0 == 0.0) break;
+            if (it >= O.lin_maxit) { rc = CAMS_E_NOT_CONVERGED; break; }
+            adds[0] = adds[1] = adds[2] = nullptr;
+            if (O.n_pre > 0) {
+                launch_smooth(c, a.r, a.d0, O.n_pre);
+                launch_stencil_sub(c, a.r, a.d0, a.r);
+                launch_restrict(c, a.r, a.rc, false);
+                adds[0] = a.d0;
+            }
+            launch_gemv(c, a.rc, a.xc);                 // Eq. (15): coarse solve
+            launch_prolong(c, a.xc, a.d1);              // Eq. (12)
+            launch_stencil_sub(c, a.r, a.d1, a.r);      // r1 = r - A d1
+            adds[1] = a.d1;
+            if (O.n_post > 0) {
+                launch_smooth(c, a.r, a.d2, O.n_post);
+                adds[2] = a.d2;
+            }
+        }
+        launch_axpy(c, p_dev, a.dp[cur], N);
+        CAMS_HIP(hipGetLastError());
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("iterate: ") + hipGetErrorString(e.code));
+    }
+    c->last.lin_iters_last = it;
+    c->last.relres_last = nr0 > 0 ? nr / nr0 : 0.0;
+    if (stats) {
+        stats->lin_iters_last = it;
+        stats->relres_last = c->last.relres_last;
+    }
+    if (rc == CAMS_E_NOT_CONVERGED) return fail(c, rc, "linear iteration limit reached");
+    if (rc == CAMS_E_BREAKDOWN) return fail(c, rc, "non-finite residual norm");
+    return CAMS_OK;
+}
+
+cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, cams_stats *stats)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!pn_dev || !p_dev) return fail(c, CAMS_E_ARG, "null pressure");
+    if (!c->has_rock) return fail(c, CAMS_E_STATE, "newton_step before set_rock");
+    cams_stats st;
+    memset(&st, 0, sizeof(st));
+    cams_status s = CAMS_OK;
+    try {
+        launch_impose_wells(c, p_dev);
+        CAMS_HIP(hipGetLastError());
+        if (!c->has_basis) {
+            CAMS_HIP(hipEventRecord(c->ev[0], c->stream));
+            s = cams_build_basis(c);
+            if (s != CAMS_OK) return s;
+            CAMS_HIP(hipEventRecord(c->ev[1], c->stream));
+            CAMS_HIP(hipEventSynchronize(c->ev[1]));
+            st.t_basis_ms = elapsed_ms(c, 0, 1);
+        }
+        for (int nit = 0;; ++nit) {
+            double en = 0.0;
+            CAMS_HIP(hipEventRecord(c->ev[2], c->stream));
+            s = cams_assemble(c, p_dev, pn_dev, &en);
+            if (s != CAMS_OK) break;
+            CAMS_HIP(hipEventRecord(c->ev[3], c->stream));
+            CAMS_HIP(hipEventSynchronize(c->ev[3]));
+            st.t_assemble_ms += elapsed_ms(c, 2, 3);
+            st.eps_norm_last = en;
+            if (!isfinite(en)) { s = fail(c, CAMS_E_BREAKDOWN, "non-finite nonlinear error"); break; }
+            if (en <= c->opt.newton_tol) break;
+            if (nit >= c->opt.newton_maxit) { s = fail(c, CAMS_E_NOT_CONVERGED, "Newton iteration limit"); break; }
+            s = cams_coarse_op(c);
+            if (s != CAMS_OK) break;
+            CAMS_HIP(hipEventRecord(c->ev[4], c->stream));
+            cams_stats ls;
+            memset(&ls, 0, sizeof(ls));
+            s = cams_iterate(c, p_dev, &ls);
+            CAMS_HIP(hipEventRecord(c->ev[5], c->stream));
+            CAMS_HIP(hipEventSynchronize(c->ev[5]));
+            st.t_coarse_ms += elapsed_ms(c, 3, 4);
+            st.t_iterate_ms += elapsed_ms(c, 4, 5);
+            st.newton_iters += 1;
+            st.lin_iters_total += ls.lin_iters_last;
+            st.lin_iters_last = ls.lin_iters_last;
+            st.relres_last = ls.relres_last;
+            if (s != CAMS_OK) break;
+        }
+    } catch (const HipError &e) {
+        s = fail(c, CAMS_E_DEVICE, std::string("newton_step: ") + hipGetErrorString(e.code));
+    }
+    c->last = st;
+    if (stats) *stats = st;
+    return s;
+}
+
+size_t cams_array_bytes(const cams_ctx *c, cams_array which)
+{
+    if (!c) return 0;
+    const size_t N = c->g.N, Nc = c->g.Nc;
+    switch (which) {
+    case CAMS_ARR_T: case CAMS_ARR_W: return 3 * N * 8;
+    case CAMS_ARR_DIAG: case CAMS_ARR_R0: case CAMS_ARR_INVD: return N * 8;
+    case CAMS_ARR_P: return 8 * N * 8;
+    case CAMS_ARR_AC: case CAMS_ARR_AC_INV: return Nc * Nc * 8;
+    }
+    return 0;
+}
+
+cams_status cams_export(cams_ctx *c, cams_array which, void *dst, size_t bytes)
+{
+    if (!c || !dst) return CAMS_E_ARG;
+    if (!c->has_ws) return fail(c, CAMS_E_STATE, "no workspace");
+    const size_t need = cams_array_bytes(c, which);
+    if (need == 0 || bytes < need) return fail(c, CAMS_E_ARG, "bad array or size");
+    const void *src = nullptr;
+    switch (which) {
+    case CAMS_ARR_T: src = c->a.T; break;
+    case CAMS_ARR_W: src = c->a.W; break;
+    case CAMS_ARR_DIAG: src = c->a.diag; break;
+    case CAMS_ARR_R0: src = c->a.r0; break;
+    case CAMS_ARR_P: src = c->a.P; break;
+    case CAMS_ARR_AC: src = c->a.Ac; break;
+    case CAMS_ARR_AC_INV: src = c->a.Ainv; break;
+    case CAMS_ARR_INVD: src = c->a.invd; break;
+    }
+    try {
+        CAMS_HIP(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, c->stream));
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("export: ") + hipGetErrorString(e.code));
+    }
+    return CAMS_OK;
+}
+
+// Test hook of the coarse factorisation's matrix-core GEMM: C -= A B with
+// row-major device matrices (C: M x Nn, A: M x K, B: K x Nn, dense).
+cams_status cams_debug_gemm_sub(cams_ctx *c, double *C, const double *A, const double *B, int M, int Nn, int K)
+{
+    if (!c || !C || !A || !B || M <= 0 || Nn <= 0 || K <= 0) return CAMS_E_ARG;
+    try {
+        launch_gemm_sub(c, C, Nn, A, K, B, Nn, M, Nn, K);
+        CAMS_HIP(hipGetLastError());
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("gemm: ") + hipGetErrorString(e.code));
+    }
+    return CAMS_OK;
+}
+
+cams_status cams_destroy(cams_ctx *c)
+{
+    if (!c) return CAMS_E_ARG;
+    if (c->host) (void)hipHostFree(c->host);
+    for (int e = 0; e < 8; ++e)
+        if (c->ev[e]) (void)hipEventDestroy(c->ev[e]);
+    delete c;
+    return CAMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations of libcams: context, device grid descriptor and the
+// host-side launchers of every kernel.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "cams.h"
+
+namespace cams {
+
+constexpr int kMaxRatio = 8;      // largest coarsening ratio the LDS local solves support
+constexpr int kBlock = 256;       // threads per workgroup of the fine-grid kernels
+
+// Grid descriptor passed by value to kernels.  Per-axis tables live in the
+// workspace: vertex coordinates (nb entries), "is vertex coordinate" flags
+// and the lower bracketing vertex of every coordinate (n entries).
+struct GridDev {
+    int nx, ny, nz, N, sxy;
+    double dx, dy, dz, dV;
+    int nb[3];
+    int r[3];
+    int Nc;
+    int dim;
+    const int32_t *vc[3];
+    const int32_t *lo[3];
+    const uint8_t *isv[3];
+};
+
+struct Fluid {
+    double rho0, c, p0, mu, dt;
+};
+
+// One dual region (edge segment, face patch or interior box): per axis the
+// first cell and the number of cells; `nfree` axes are open intervals.
+struct Region {
+    int32_t s[3];
+    int32_t len[3];
+    int32_t freemask;   // bit a set: axis a is an open interval
+    int32_t pad;
+};
+
+// Pointers into the caller's workspace.
+struct Arrays {
+    double *T;        // 3N: Tx, Ty, Tz
+    double *phi, *q;  // N, N (q only when sources are given)
+    double *W;        // 3N: masked off-diagonal magnitudes of A
+    double *diag, *r0, *r;
+    double *dp[2];    // ping-pong accumulated update
+    double *d0, *d1, *d2, *z, *x, *invd;
+    double *P;        // 8N slot-major
+    double *Ac, *Ainv, *work; // Nc*Nc each
+    double *rc, *xc;  // Nc
+    double *partial;  // reduction partials
+    double *scal;     // device scalars
+    int32_t *piv;     // Nc
+    int32_t *status;  // device error flags
+    uint8_t *dmask;   // N
+    int32_t *wcell;   // wells
+    double *wp;
+    int32_t *tab;     // per-axis tables
+    Region *regions;  // dual regions of all stages
+    // mixed precision copies
+    float *W32, *diag32, *invd32, *P32;
+    uint16_t *Pbf;
+    float *r1f, *d1f, *d2f, *zf, *xf;
+};
+
+// Scalar slots in Arrays::scal.
+enum { S_EPS2 = 0, S_R0N2 = 1, S_RN2 = 2 };
+
+// Device status flags (bitwise OR).
+enum { F_BAD_PIVOT = 1, F_BAD_INPUT = 2, F_SINGULAR_COARSE = 4 };
+
+}  // namespace cams
+
+struct cams_ctx {
+    cams_grid grid;
+    cams_fluid fluid;
+    cams_options opt;
+    hipStream_t stream;
+    cams::GridDev g;
+    cams::Fluid fl;
+    int nreg[4];            // regions per stage (index = number of free axes)
+    int regoff[4];
+    int region_total;
+    int maxm[4], maxbw[4];  // largest local system per stage
+    size_t need;
+    char *ws;
+    size_t ws_bytes;
+    cams::Arrays a;
+    int nparts;             // reduction partial count
+    int nwells;
+    bool has_ws, has_rock, has_q, has_basis, has_system, has_coarse;
+    int cur_dp;
+    double *host;           // pinned host scalars
+    hipEvent_t ev[8];
+    cams_stats last;
+    std::string err;
+    // host copies of the per-axis tables and dual regions (uploaded by
+    // cams_set_workspace) and the workspace offsets
+    std::vector<int32_t> tab;
+    std::vector<cams::Region> regions;
+    size_t tab_off[3][3];
+    size_t off[32];
+};
+
+namespace cams {
+
+// ---- fine-grid kernels (k_fine.hip)
+void launch_fill(cams_ctx *c, double *x, int n, double v);
+void launch_transmissibility(cams_ctx *c, const double *perm);
+void launch_check_rock(cams_ctx *c, const double *perm, const double *phi);
+void launch_assemble(cams_ctx *c, const double *p, const double *pn);
+void launch_reduce(cams_ctx *c, const double *partial, int n, double *out);
+void launch_impose_wells(cams_ctx *c, double *p);
+void launch_residual(cams_ctx *c, const double *dp_in, const double *a0, const double *a1,
+                     const double *a2, double *dp_out, double *r);
+void launch_stencil_sub(cams_ctx *c, const double *b, const double *x, double *out);
+void launch_prolong(cams_ctx *c, const double *xc, double *out);
+void launch_ilu_setup(cams_ctx *c);
+void launch_smooth(cams_ctx *c, const double *rhs, double *e, int steps);
+void launch_axpy(cams_ctx *c, double *y, const double *x, int n);
+
+// ---- basis (k_basis.hip)
+void launch_basis(cams_ctx *c);
+
+// ---- coarse level (k_coarse.hip)
+void launch_coarse_operator(cams_ctx *c);
+void launch_restrict(cams_ctx *c, const double *r, double *rc, bool finalize_norm);
+void launch_coarse_factor(cams_ctx *c);   // LU + explicit inverse of Ac
+void launch_gemv(cams_ctx *c, const double *rc, double *xc);
+
+}  // namespace cams
+
+#define CAMS_HIP(call)                                                   \
+    do {                                                                 \
+        hipError_t e_ = (call);                                          \
+        if (e_ != hipSuccess) throw cams::HipError(e_, #call, __LINE__); \
+    } while (0)
+
+namespace cams {
+struct HipError {
+    hipError_t code;
+    const char *what;
+    int line;
+    HipError(hipError_t c, const char *w, int l) : code(c), what(w), line(l) {}
+};
+}  // namespace cams

@@ -1,0 +1,447 @@
+// Coarse level of the C-AMS solve (Sec. 3, Eqs. (7), (13)-(15)):
+//  - A_c = R A P_hat, one workgroup per coarse row (MSFV: the rows of the
+//    primal block; MSFE: the cells of the coarse node's basis support, each
+//    weighted by its basis value).  27 neighbouring coarse nodes per row are
+//    accumulated in LDS and reduced in a fixed order, so A_c is bitwise
+//    deterministic (no atomics).
+//  - restriction R r for the iteration (same ownership, one value per row);
+//  - LU with partial pivoting by column panels: panel factorisation in one
+//    workgroup, row interchanges, unit-lower triangular solve for the U row
+//    block, and the trailing update C -= A B on FP64 matrix cores
+//    (v_mfma_f64_16x16x4f64, 64x64 tiles per workgroup);
+//  - the explicit inverse from the LU factors with the same kernels, so that
+//    every coarse solve of the iteration is one fully parallel GEMV instead
+//    of two latency-bound triangular sweeps.
+#include "cams_internal.h"
+#include "dev_util.h"
+
+namespace cams {
+
+namespace {
+
+constexpr int kNB = 64;   // LU panel width
+
+// Cell range of coarse row k along one axis.
+__device__ __forceinline__ void row_range(const GridDev &g, int axis, int a, int fe, int &lo, int &hi)
+{
+    const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+    if (fe) {
+        const int32_t *v = g.vc[axis];
+        lo = a > 0 ? v[a - 1] + 1 : 0;
+        hi = a < g.nb[axis] - 1 ? v[a + 1] - 1 : n - 1;
+    } else {
+        lo = a * g.r[axis];
+        hi = min((a + 1) * g.r[axis], n) - 1;
+    }
+}
+
+// Row k of A_c: sum over the row's cells of w_i (A P_hat)_{i,l}, with w_i
+// the basis value of node k at cell i (MSFE) or 1 (MSFV).
+__global__ __launch_bounds__(kBlock) void k_coarse_row(GridDev g, const double *__restrict__ W,
+                                                        const double *__restrict__ diag,
+                                                        const uint8_t *__restrict__ dm, const double *__restrict__ P,
+                                                        int fe, double *__restrict__ Ac)
+{
+    __shared__ double acc[27][kBlock];
+    __shared__ double row[27];
+    const int k = blockIdx.x;
+    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
+    int lo[3], hi[3];
+    row_range(g, 0, ka, fe, lo[0], hi[0]);
+    row_range(g, 1, kb, fe, lo[1], hi[1]);
+    row_range(g, 2, kc, fe, lo[2], hi[2]);
+    for (int t = 0; t < 27; ++t) acc[t][threadIdx.x] = 0.0;
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    const int cnt = ex * ey * ez;
+    const double *Wa[3] = {W, W + g.N, W + 2 * g.N};
+    for (int t = threadIdx.x; t < cnt; t += kBlock) {
+        const int i = lo[0] + t % ex, j = lo[1] + (t / ex) % ey, kk = lo[2] + t / (ex * ey);
+        const int n = i + g.nx * (j + g.ny * kk);
+        if (dm[n]) continue;
+        double w = 1.0;
+        if (fe) {
+            const int sx = ka - g.lo[0][i], sy = kb - g.lo[1][j], sz = kc - g.lo[2][kk];
+            if (sx < 0 || sx > 1 || sy < 0 || sy > 1 || sz < 0 || sz > 1) continue;
+            w = P[(size_t)(sx + 2 * sy + 4 * sz) * g.N + n];
+            if (w == 0.0) continue;
+        }
+        // the seven points of row n of A
+        for (int pt = 0; pt < 7; ++pt) {
+            int m = n, mi = i, mj = j, mk = kk;
+            double coef;
+            if (pt == 0) {
+                coef = diag[n];
+            } else {
+                const int a = (pt - 1) >> 1, dir = ((pt - 1) & 1) ? 1 : -1;
+                if (a == 0) { mi += dir; if (mi < 0 || mi >= g.nx) continue; m += dir; }
+                if (a == 1) { mj += dir; if (mj < 0 || mj >= g.ny) continue; m += dir * g.nx; }
+                if (a == 2) { mk += dir; if (mk < 0 || mk >= g.nz) continue; m += dir * g.sxy; }
+                coef = -(dir > 0 ? Wa[a][n] : Wa[a][m]);
+            }
+            if (coef == 0.0 || dm[m]) continue;
+            const int la = g.lo[0][mi], lb = g.lo[1][mj], lc = g.lo[2][mk];
+            for (int s = 0; s < 8; ++s) {
+                const double pw = P[(size_t)s * g.N + m];
+                if (pw == 0.0) continue;
+                const int ox = la + (s & 1) - ka + 1, oy = lb + ((s >> 1) & 1) - kb + 1,
+                          oz = lc + ((s >> 2) & 1) - kc + 1;
+                if (ox < 0 || ox > 2 || oy < 0 || oy > 2 || oz < 0 || oz > 2) continue;  // cannot happen
+                acc[ox + 3 * oy + 9 * oz][threadIdx.x] += w * coef * pw;
+            }
+        }
+    }
+    __syncthreads();
+    // fixed-order (serial) reduction of each of the 27 entries over the threads
+    for (int e = threadIdx.x; e < 27; e += kBlock) {
+        double s = 0.0;
+        for (int t = 0; t < kBlock; ++t) s += acc[e][t];
+        row[e] = s;
+    }
+    __syncthreads();
+    const size_t base = (size_t)k * g.Nc;
+    for (int col = threadIdx.x; col < g.Nc; col += kBlock) {
+        const int ca = col % g.nb[0], cb = (col / g.nb[0]) % g.nb[1], cc = col / (g.nb[0] * g.nb[1]);
+        const int ox = ca - ka + 1, oy = cb - kb + 1, oz = cc - kc + 1;
+        double v = 0.0;
+        if (ox >= 0 && ox <= 2 && oy >= 0 && oy <= 2 && oz >= 0 && oz <= 2) v = row[ox + 3 * oy + 9 * oz];
+        Ac[base + col] = v;
+    }
+}
+
+// rc[k] = sum over the row's cells of w_i r_i; workgroup 0 also finishes the
+// norm ||r||^2 from the residual kernel's partials.
+__global__ __launch_bounds__(kBlock) void k_restrict(GridDev g, const uint8_t *__restrict__ dm,
+                                                      const double *__restrict__ P, int fe,
+                                                      const double *__restrict__ r, double *__restrict__ rc,
+                                                      const double *__restrict__ partial, int nparts,
+                                                      double *__restrict__ norm_out)
+{
+    __shared__ double sh[kBlock / 64];
+    const int k = blockIdx.x;
+    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
+    int lo[3], hi[3];
+    row_range(g, 0, ka, fe, lo[0], hi[0]);
+    row_range(g, 1, kb, fe, lo[1], hi[1]);
+    row_range(g, 2, kc, fe, lo[2], hi[2]);
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    const int cnt = ex * ey * ez;
+    double v = 0.0;
+    for (int t = threadIdx.x; t < cnt; t += kBlock) {
+        const int i = lo[0] + t % ex, j = lo[1] + (t / ex) % ey, kk = lo[2] + t / (ex * ey);
+        const int n = i + g.nx * (j + g.ny * kk);
+        if (fe) {
+            if (dm[n]) continue;
+            const int sx = ka - g.lo[0][i], sy = kb - g.lo[1][j], sz = kc - g.lo[2][kk];
+            if (sx < 0 || sx > 1 || sy < 0 || sy > 1 || sz < 0 || sz > 1) continue;
+            v += P[(size_t)(sx + 2 * sy + 4 * sz) * g.N + n] * r[n];
+        } else {
+            v += r[n];
+        }
+    }
+    double s = block_sum<kBlock>(v, sh);
+    if (threadIdx.x == 0) rc[k] = s;
+    if (norm_out && k == 0) {
+        double u = 0.0;
+        for (int t = threadIdx.x; t < nparts; t += kBlock) u += partial[t];
+        double su = block_sum<kBlock>(u, sh);
+        if (threadIdx.x == 0) *norm_out = su;
+    }
+}
+
+// ---------------------------------------------------------------- LU ----
+
+// Factor columns [j0, j0+nb) of the row-major n x n matrix A (rows j0..n-1):
+// partial pivoting inside the panel; interchanges recorded in piv.
+__global__ __launch_bounds__(kBlock) void k_lu_panel(double *__restrict__ A, int n, int j0, int nb,
+                                                      int32_t *__restrict__ piv, int32_t *status)
+{
+    __shared__ double sv[kBlock];
+    __shared__ int si[kBlock];
+    for (int c = j0; c < j0 + nb; ++c) {
+        double best = -1.0;
+        int bi = c;
+        for (int i = c + threadIdx.x; i < n; i += kBlock) {
+            const double v = fabs(A[(size_t)i * n + c]);
+            if (v > best) { best = v; bi = i; }
+        }
+        sv[threadIdx.x] = best;
+        si[threadIdx.x] = bi;
+        __syncthreads();
+        for (int off = kBlock / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) {
+                const double o = sv[threadIdx.x + off];
+                const int oi = si[threadIdx.x + off];
+                if (o > sv[threadIdx.x] || (o == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sv[threadIdx.x] = o;
+                    si[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int p = si[0];
+        if (threadIdx.x == 0) {
+            piv[c] = p;
+            if (!(sv[0] > 0.0)) atomicOr(status, F_SINGULAR_COARSE);
+        }
+        if (p != c) {
+            for (int col = j0 + threadIdx.x; col < j0 + nb; col += kBlock) {
+                const double t = A[(size_t)c * n + col];
+                A[(size_t)c * n + col] = A[(size_t)p * n + col];
+                A[(size_t)p * n + col] = t;
+            }
+        }
+        __syncthreads();
+        double pv = A[(size_t)c * n + c];
+        if (pv == 0.0) pv = 1.0;  // flagged above; keep the arithmetic finite
+        for (int i = c + 1 + threadIdx.x; i < n; i += kBlock) {
+            const double l = A[(size_t)i * n + c] / pv;
+            A[(size_t)i * n + c] = l;
+            if (l != 0.0)
+                for (int col = c + 1; col < j0 + nb; ++col) A[(size_t)i * n + col] -= l * A[(size_t)c * n + col];
+        }
+        __syncthreads();
+    }
+}
+
+// Apply the panel's interchanges to the columns outside [j0, j0+nb).
+__global__ __launch_bounds__(kBlock) void k_lu_swap(double *__restrict__ A, int n, int j0, int nb,
+                                                     const int32_t *__restrict__ piv)
+{
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n - nb) return;
+    const int col = t < j0 ? t : t + nb;
+    for (int c = j0; c < j0 + nb; ++c) {
+        const int p = piv[c];
+        if (p != c) {
+            const double v = A[(size_t)c * n + col];
+            A[(size_t)c * n + col] = A[(size_t)p * n + col];
+            A[(size_t)p * n + col] = v;
+        }
+    }
+}
+
+// Solve with the nb x nb diagonal block of the factor at (j0, j0) for the
+// rows j0..j0+nb-1 of B (ncols columns starting at col0, leading dim ldb):
+// upper = 0: unit lower triangle (forward); upper = 1: upper triangle
+// (backward).  A block shorter than kNB is padded with identity rows so the
+// loops are static and the column stays in registers.
+__global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, int n, int j0, int nb, double *B,
+                                                  int ldb, int col0, int ncols, int upper)
+{
+    __shared__ double Ls[kNB][kNB + 1];
+    for (int t = threadIdx.x; t < kNB * kNB; t += kBlock) {
+        const int r = t / kNB, c = t % kNB;
+        double v = (r == c) ? 1.0 : 0.0;
+        if (r < nb && c < nb) v = F[(size_t)(j0 + r) * n + j0 + c];
+        Ls[r][c] = v;
+    }
+    __syncthreads();
+    const int col = col0 + blockIdx.x * kBlock + threadIdx.x;
+    if (col >= col0 + ncols) return;
+    double x[kNB];
+#pragma unroll
+    for (int r = 0; r < kNB; ++r) x[r] = (r < nb) ? B[(size_t)(j0 + r) * ldb + col] : 0.0;
+    if (!upper) {
+#pragma unroll
+        for (int r = 1; r < kNB; ++r) {
+            double s = x[r];
+#pragma unroll
+            for (int t = 0; t < r; ++t) s -= Ls[r][t] * x[t];
+            x[r] = s;
+        }
+    } else {
+#pragma unroll
+        for (int r = kNB - 1; r >= 0; --r) {
+            double s = x[r];
+#pragma unroll
+            for (int t = r + 1; t < kNB; ++t) s -= Ls[r][t] * x[t];
+            x[r] = s / Ls[r][r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kNB; ++r)
+        if (r < nb) B[(size_t)(j0 + r) * ldb + col] = x[r];
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C (M x Nn, ldc) -= A (M x K, lda) * B (K x Nn, ldb); row-major.
+// 256 threads = 4 waves as 2 x 2; each wave owns a 32 x 32 block of the
+// 64 x 64 tile as 2 x 2 tiles of v_mfma_f64_16x16x4f64.  K is staged through
+// LDS 16 at a time.  Operand lanes: A row = lane%16, k = lane/16; B col =
+// lane%16, k = lane/16; result element v of a lane: row lane/16 + 4v,
+// col lane%16 (checked against a host GEMM by the parity tests).
+__global__ __launch_bounds__(kBlock) void k_gemm_sub(double *__restrict__ C, int ldc, const double *__restrict__ A,
+                                                      int lda, const double *__restrict__ B, int ldb, int M, int Nn,
+                                                      int K)
+{
+    __shared__ double As[64][17];
+    __shared__ double Bs[16][65];
+    const int tm = blockIdx.y * 64, tn = blockIdx.x * 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        for (int t = threadIdx.x; t < 64 * 16; t += kBlock) {
+            const int r = t / 16, c = t % 16;
+            const int gr = tm + r, gc = k0 + c;
+            As[r][c] = (gr < M && gc < K) ? A[(size_t)gr * lda + gc] : 0.0;
+        }
+        for (int t = threadIdx.x; t < 16 * 64; t += kBlock) {
+            const int r = t / 64, c = t % 64;
+            const int gr = k0 + r, gc = tn + c;
+            Bs[r][c] = (gr < K && gc < Nn) ? B[(size_t)gr * ldb + gc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const double av = As[wm + a * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double bv = Bs[kk + (lane >> 4)][wn + b * 16 + (lane & 15)];
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = tm + wm + a * 16 + (lane >> 4) + 4 * v;
+                const int c = tn + wn + b * 16 + (lane & 15);
+                if (r < M && c < Nn) C[(size_t)r * ldc + c] -= acc[a][b][v];
+            }
+}
+
+// B = P I for the row interchanges of the factorisation (one thread builds
+// the permutation, then every thread fills a row).
+__global__ __launch_bounds__(kBlock) void k_perm_identity(const int32_t *__restrict__ piv, int n,
+                                                           int32_t *__restrict__ perm, double *__restrict__ B)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int c = 0; c < n; ++c) {
+            const int p = piv[c];
+            const int t = perm[c];
+            perm[c] = perm[p];
+            perm[p] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_perm_fill(const int32_t *__restrict__ perm, int n, double *__restrict__ B)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (size_t)n * n) return;
+    const int i = (int)(t / n), j = (int)(t % n);
+    B[t] = (perm[i] == j) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const double *__restrict__ a, double *__restrict__ b, size_t n)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) b[t] = a[t];
+}
+
+// y = M x, one wave per row (fixed lane partition and shuffle tree).
+__global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, int n, const double *__restrict__ x,
+                                                  double *__restrict__ y)
+{
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double *mr = M + (size_t)row * n;
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    s = wave_sum(s);
+    if (lane == 0) y[row] = s;
+}
+
+inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+void gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, const double *B, int ldb, int M, int Nn,
+              int K)
+{
+    if (M <= 0 || Nn <= 0 || K <= 0) return;
+    dim3 grid(cdiv(Nn, 64), cdiv(M, 64));
+    k_gemm_sub<<<grid, kBlock, 0, c->stream>>>(C, ldc, A, lda, B, ldb, M, Nn, K);
+}
+
+}  // namespace
+
+void launch_coarse_operator(cams_ctx *c)
+{
+    k_coarse_row<<<c->g.Nc, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.dmask, c->a.P,
+                                                    c->opt.restriction == CAMS_R_FE, c->a.Ac);
+}
+
+void launch_restrict(cams_ctx *c, const double *r, double *rc, bool finalize_norm)
+{
+    k_restrict<<<c->g.Nc, kBlock, 0, c->stream>>>(c->g, c->a.dmask, c->a.P, c->opt.restriction == CAMS_R_FE, r, rc,
+                                                  c->a.partial, c->nparts,
+                                                  finalize_norm ? c->a.scal + S_RN2 : nullptr);
+}
+
+void launch_coarse_factor(cams_ctx *c)
+{
+    const int n = c->g.Nc;
+    double *F = c->a.work;
+    const size_t nn = (size_t)n * n;
+    k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
+    // LU with partial pivoting, right looking by panels
+    for (int j0 = 0; j0 < n; j0 += kNB) {
+        const int nb = n - j0 < kNB ? n - j0 : kNB;
+        k_lu_panel<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.piv, c->a.status);
+        if (n - nb > 0) k_lu_swap<<<cdiv(n - nb, kBlock), kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.piv);
+        const int rest = n - j0 - nb;
+        if (rest > 0) {
+            k_trsm<<<cdiv(rest, kBlock), kBlock, 0, c->stream>>>(F, n, j0, nb, F, n, j0 + nb, rest, 0);
+            gemm_sub(c, F + (size_t)(j0 + nb) * n + j0 + nb, n, F + (size_t)(j0 + nb) * n + j0, n,
+                     F + (size_t)j0 * n + j0 + nb, n, rest, rest, nb);
+        }
+    }
+    // inverse: X = U^{-1} L^{-1} (P I)
+    double *X = c->a.Ainv;
+    int32_t *perm = c->a.piv + n;
+    k_perm_identity<<<1, 1, 0, c->stream>>>(c->a.piv, n, perm, X);
+    k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(perm, n, X);
+    for (int j0 = 0; j0 < n; j0 += kNB) {
+        const int nb = n - j0 < kNB ? n - j0 : kNB;
+        k_trsm<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(F, n, j0, nb, X, n, 0, n, 0);
+        const int rest = n - j0 - nb;
+        if (rest > 0)
+            gemm_sub(c, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, X + (size_t)j0 * n, n, rest,
+                     n, nb);
+    }
+    const int last = ((n - 1) / kNB) * kNB;
+    for (int j0 = last; j0 >= 0; j0 -= kNB) {
+        const int nb = n - j0 < kNB ? n - j0 : kNB;
+        k_trsm<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(F, n, j0, nb, X, n, 0, n, 1);
+        if (j0 > 0) gemm_sub(c, X, n, F + j0, n, X + (size_t)j0 * n, n, j0, n, nb);
+    }
+}
+
+void launch_gemv(cams_ctx *c, const double *rc, double *xc)
+{
+    const int n = c->g.Nc;
+    k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, rc, xc);
+}
+
+// Test hook: C -= A B on the device, same kernel as the factorisation.
+void launch_gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, const double *B, int ldb, int M,
+                     int Nn, int K)
+{
+    gemm_sub(c, C, ldc, A, lda, B, ldb, M, Nn, K);
+}
+
+}  // namespace cams

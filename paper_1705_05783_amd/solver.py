@@ -1,0 +1,125 @@
+"""Convenience wrapper over the libcams C ABI for one problem on one GPU.
+
+Torch provides the device memory (the workspace and the pressure vectors)
+and the stream; every computation is a libcams call.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _cams as C
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Owns a libcams context, its workspace and the rock/well data of one
+    problem.  `problem` is any object with the attributes of
+    workloads.Problem (grid, fluid, rock, wells, options)."""
+
+    def __init__(self, problem, device="cuda:0", stream=None, **overrides):
+        self.pb = problem
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        g = C.cams_grid(problem.nx, problem.ny, problem.nz, problem.dx, problem.dy, problem.dz,
+                        problem.rx, problem.ry, problem.rz)
+        f = C.cams_fluid(problem.rho0, problem.c, problem.p0, problem.mu, problem.dt)
+        o = C.cams_options(overrides.get("restriction", problem.restriction),
+                           overrides.get("n_pre", problem.n_pre), overrides.get("n_post", problem.n_post),
+                           overrides.get("precision", problem.precision),
+                           overrides.get("lin_rtol", problem.lin_rtol),
+                           overrides.get("lin_maxit", problem.lin_maxit),
+                           overrides.get("newton_tol", problem.newton_tol),
+                           overrides.get("newton_maxit", problem.newton_maxit))
+        self.options = o
+        h = ctypes.c_void_p()
+        C.check(C.cams_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(o),
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None, "cams_create")
+        self.ctx = h
+        nbytes = C.cams_workspace_bytes(self.ctx)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        C.check(C.cams_set_workspace(self.ctx, ctypes.c_void_p(self._ws_ptr), nbytes), self.ctx,
+                "cams_set_workspace")
+        self.N = problem.n
+        self.Nc = int(C.cams_num_coarse(self.ctx))
+        perm = torch.as_tensor(np.ascontiguousarray(problem.perm, dtype=np.float64), device=self.device)
+        phi = torch.as_tensor(np.ascontiguousarray(problem.phi, dtype=np.float64), device=self.device)
+        q = None
+        if problem.q is not None:
+            q = torch.as_tensor(np.ascontiguousarray(problem.q, dtype=np.float64), device=self.device)
+        self._rock = (perm, phi, q)
+        self.reset_rock()
+        cells = np.array([w[0] for w in problem.wells], dtype=np.int64)
+        vals = np.array([w[1] for w in problem.wells], dtype=np.float64)
+        C.check(C.cams_set_wells(self.ctx, cells.ctypes.data_as(ctypes.c_void_p),
+                                 vals.ctypes.data_as(ctypes.c_void_p), len(problem.wells)),
+                self.ctx, "cams_set_wells")
+        self.last_stats = C.cams_stats()
+
+    def reset_rock(self):
+        """(Re)load permeability and porosity: recomputes the transmissibilities
+        and invalidates the basis, so the next step rebuilds it."""
+        perm, phi, q = self._rock
+        C.check(C.cams_set_rock(self.ctx, _ptr(perm), _ptr(phi), _ptr(q) if q is not None else None),
+                self.ctx, "cams_set_rock")
+
+    # ---- the five hot-path calls
+    def assemble(self, p: torch.Tensor, pn: torch.Tensor) -> float:
+        e = ctypes.c_double()
+        C.check(C.cams_assemble(self.ctx, _ptr(p), _ptr(pn), ctypes.byref(e)), self.ctx, "cams_assemble")
+        return e.value
+
+    def build_basis(self):
+        C.check(C.cams_build_basis(self.ctx), self.ctx, "cams_build_basis")
+
+    def coarse_op(self):
+        C.check(C.cams_coarse_op(self.ctx), self.ctx, "cams_coarse_op")
+
+    def iterate(self, p: torch.Tensor) -> dict:
+        st = C.cams_stats()
+        C.check(C.cams_iterate(self.ctx, _ptr(p), ctypes.byref(st)), self.ctx, "cams_iterate")
+        return st.as_dict()
+
+    def newton_step(self, pn: torch.Tensor, p: torch.Tensor, check=True) -> dict:
+        st = C.cams_stats()
+        status = C.cams_newton_step(self.ctx, _ptr(pn), _ptr(p), ctypes.byref(st))
+        self.last_stats = st
+        if check:
+            C.check(status, self.ctx, "cams_newton_step")
+        d = st.as_dict()
+        d["status"] = status
+        return d
+
+    def smooth_apply(self, z: torch.Tensor) -> torch.Tensor:
+        x = torch.empty_like(z)
+        C.check(C.cams_smooth_apply(self.ctx, _ptr(z), _ptr(x)), self.ctx, "cams_smooth_apply")
+        return x
+
+    # ---- inspection
+    def export(self, which: int) -> torch.Tensor:
+        nbytes = C.cams_array_bytes(self.ctx, which)
+        out = torch.empty(nbytes // 8, dtype=torch.float64, device=self.device)
+        C.check(C.cams_export(self.ctx, which, _ptr(out), nbytes), self.ctx, "cams_export")
+        return out
+
+    def new_pressure(self) -> torch.Tensor:
+        return torch.as_tensor(self.pb.initial_pressure(), dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if self.ctx:
+            C.cams_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

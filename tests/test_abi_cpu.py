@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function declared in include/cams.h,
+and reject invalid arguments in cams_create before any device work.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(cams_[a-z_0-9]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1705_05783_amd import _cams
+    if not os.path.exists(_cams.LIB_PATH):
+        pytest.fail("libcams.so is not built (run __graft_entry__.build())")
+    return _cams.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1705_05783_amd import _cams
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(_cams.EXPORTED)
+
+
+def _create(grid=None, fluid=None, opt=None):
+    from paper_1705_05783_amd import _cams as C
+    g = grid or C.cams_grid(16, 16, 8, 1.0, 1.0, 1.0, 4, 4, 4)
+    f = fluid or C.cams_fluid(1.0, 0.1, 0.0, 1.0, 0.1)
+    o = opt or C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 1e-8, 100, 1e-8, 20)
+    h = ctypes.c_void_p()
+    s = C.cams_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(o), None, ctypes.byref(h))
+    return s, h
+
+
+def test_create_valid_makes_no_device_call(lib):
+    from paper_1705_05783_amd import _cams as C
+    s, h = _create()
+    assert s == C.CAMS_OK
+    assert C.cams_num_coarse(h) == 4 * 4 * 2
+    nbytes = C.cams_workspace_bytes(h)
+    assert nbytes > 16 * 16 * 8 * 8 * 25 and nbytes % 256 == 0
+    # calls out of order are rejected on the host
+    e = ctypes.c_double()
+    assert C.cams_assemble(h, None, None, ctypes.byref(e)) == C.CAMS_E_STATE
+    assert C.cams_build_basis(h) == C.CAMS_E_STATE
+    assert C.cams_coarse_op(h) == C.CAMS_E_STATE
+    assert C.cams_destroy(h) == C.CAMS_OK
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=1), dict(rx=1), dict(rx=9), dict(rx=20), dict(nz=1, rz=2, bad2d=True),
+    dict(nx=9, rx=2),  # last vertex one cell from the previous one
+    dict(dx=0.0),
+])
+def test_create_rejects_bad_grids(lib, bad):
+    from paper_1705_05783_amd import _cams as C
+    kw = dict(nx=16, ny=16, nz=8, dx=1.0, dy=1.0, dz=1.0, rx=4, ry=4, rz=4)
+    kw.update({k: v for k, v in bad.items() if k != "bad2d"})
+    if bad.get("bad2d"):
+        kw.update(nx=1)
+    g = C.cams_grid(kw["nx"], kw["ny"], kw["nz"], kw["dx"], kw["dy"], kw["dz"], kw["rx"], kw["ry"], kw["rz"])
+    s, h = _create(grid=g)
+    assert s == C.CAMS_E_ARG and not h.value
+
+
+@pytest.mark.parametrize("field,value", [("dt", 0.0), ("c", -1.0), ("mu", 0.0), ("rho0", -1.0)])
+def test_create_rejects_bad_fluid(lib, field, value):
+    from paper_1705_05783_amd import _cams as C
+    f = C.cams_fluid(1.0, 0.1, 0.0, 1.0, 0.1)
+    setattr(f, field, value)
+    s, h = _create(fluid=f)
+    assert s == C.CAMS_E_ARG
+
+
+@pytest.mark.parametrize("field,value", [("restriction", 3), ("n_post", -1), ("n_pre", 65),
+                                         ("lin_rtol", 0.0), ("lin_maxit", 0), ("newton_maxit", 0),
+                                         ("precision", 7)])
+def test_create_rejects_bad_options(lib, field, value):
+    from paper_1705_05783_amd import _cams as C
+    o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 1e-8, 100, 1e-8, 20)
+    setattr(o, field, value)
+    s, h = _create(opt=o)
+    assert s == C.CAMS_E_ARG
+
+
+def test_two_dimensional_grid_accepted(lib):
+    from paper_1705_05783_amd import _cams as C
+    g = C.cams_grid(20, 20, 1, 1.0, 1.0, 1.0, 4, 4, 1)
+    s, h = _create(grid=g)
+    assert s == C.CAMS_OK
+    assert C.cams_num_coarse(h) == 25
+    C.cams_destroy(h)
+
+
+def test_null_arguments(lib):
+    from paper_1705_05783_amd import _cams as C
+    assert C.cams_create(None, None, None, None, None) == C.CAMS_E_ARG
+    assert C.cams_destroy(None) == C.CAMS_E_ARG
+    assert C.cams_workspace_bytes(None) == 0
