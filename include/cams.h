@@ -60,6 +60,13 @@ enum { CAMS_R_FV = 0, CAMS_R_FE = 1 };
  * refinement).  MIXED_BF16: as MIXED_FP32 but the basis stored in bfloat16. */
 enum { CAMS_FP64 = 0, CAMS_MIXED_FP32 = 1, CAMS_MIXED_BF16 = 2 };
 
+/* ILU(0) smoother of Table "cams" step 6.  BLOCK: block-Jacobi ILU(0) in
+ * natural order on 8x8x8 cell blocks aligned at the origin (8x8 in 2D; the
+ * last block of an axis may be shorter), couplings across block faces left
+ * out of the factor only.  RB: ILU(0) of the whole matrix in red-black
+ * order (even i+j+k first). */
+enum { CAMS_SMOOTH_BLOCK_ILU0 = 0, CAMS_SMOOTH_RB_ILU0 = 1 };
+
 typedef struct {
     int32_t nx, ny, nz;       /* fine cells per axis, >= 2 on active axes (nz == 1 for 2D) */
     double dx, dy, dz;        /* cell sizes (> 0) */
@@ -77,6 +84,7 @@ typedef struct {
     int32_t n_pre;            /* ILU(0) Richardson steps before the multiscale stage (0..64) */
     int32_t n_post;           /* ILU(0) Richardson steps after it (Table "cams" step 6; 0..64) */
     int32_t precision;        /* CAMS_FP64 / CAMS_MIXED_FP32 / CAMS_MIXED_BF16 */
+    int32_t smoother;         /* CAMS_SMOOTH_BLOCK_ILU0 or CAMS_SMOOTH_RB_ILU0 */
     double lin_rtol;          /* stop when ||r||_2 <= lin_rtol ||r0||_2 */
     int32_t lin_maxit;        /* linear iteration limit */
     double newton_tol;        /* stop Newton when ||eps||_2 <= newton_tol (Eq. (16)) */
@@ -160,8 +168,8 @@ cams_status cams_build_basis(cams_ctx *ctx);
 cams_status cams_coarse_op(cams_ctx *ctx);
 
 /* Solve the assembled system for the Newton update by C-AMS iterations
- * (Table "cams"; Eq. (15) multiscale stage, ILU(0) smoothing in red-black
- * order) and add it to p_dev in place:  p <- p + d,  A d = r.  Stops when
+ * (Table "cams"; Eq. (15) multiscale stage, ILU(0) smoothing) and add it to
+ * p_dev in place:  p <- p + d,  A d = r.  Stops when
  * ||r||_2 <= lin_rtol ||r0||_2 or after lin_maxit iterations.  `stats` may be
  * NULL.  Errors: CAMS_E_STATE (no coarse operator for the current system),
  * CAMS_E_NOT_CONVERGED (limit reached; p holds the last iterate),
@@ -177,7 +185,7 @@ cams_status cams_iterate(cams_ctx *ctx, double *p_dev, cams_stats *stats);
 cams_status cams_newton_step(cams_ctx *ctx, const double *pn_dev, double *p_dev, cams_stats *stats);
 
 /* One application of the smoother, x = M^{-1} z, with M the ILU(0) factor of
- * the assembled matrix in red-black order (Table "cams" step 6).  z_dev and
+ * the assembled matrix chosen by options.smoother (Table "cams" step 6).  z_dev and
  * x_dev have N entries.  Errors: CAMS_E_STATE (no coarse_op for the current
  * system: the factor is computed there). */
 cams_status cams_smooth_apply(cams_ctx *ctx, const double *z_dev, double *x_dev);
@@ -192,7 +200,7 @@ typedef enum {
     CAMS_ARR_P = 4,        /* 8*N doubles: basis weights, slot-major */
     CAMS_ARR_AC = 5,       /* Nc*Nc doubles: coarse operator, row-major (before factorisation) */
     CAMS_ARR_AC_INV = 6,   /* Nc*Nc doubles: inverse of the coarse operator */
-    CAMS_ARR_INVD = 7      /* N doubles: inverse ILU(0) pivots (red-black order) */
+    CAMS_ARR_INVD = 7      /* N doubles: inverse ILU(0) pivots of the smoother */
 } cams_array;
 
 size_t cams_array_bytes(const cams_ctx *ctx, cams_array which);

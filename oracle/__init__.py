@@ -64,6 +64,8 @@ def lib():
         L.or_lu_factor.restype = ctypes.c_int
         L.or_ilu0_create.restype = P
         L.or_ilu0_create.argtypes = [P, P, P, P, P, P]
+        L.or_ilu0_block_create.restype = P
+        L.or_ilu0_block_create.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_ilu0_free.argtypes = [P]
         L.or_ilu0_nnz.restype = ctypes.c_long
         L.or_ilu0_nnz.argtypes = [P]
@@ -233,15 +235,31 @@ def redblack_order(pb) -> np.ndarray:
     return o
 
 
-class ILU0:
-    """ILU(0) of the 7-point operator in a given ordering (default red-black)."""
+SMOOTH_BLOCK = 0       # block-Jacobi ILU(0), natural order inside 8x8x8 blocks
+SMOOTH_REDBLACK = 1    # ILU(0) in red-black order
 
-    def __init__(self, pb, W, diag, order=None):
+
+def smoother_block(pb):
+    """Smoother block extents: 8 cells per active axis."""
+    return (8, 8, 8 if pb.nz > 1 else 1)
+
+
+class ILU0:
+    """ILU(0) of the 7-point operator: in a given ordering (default
+    red-black), or block-Jacobi ILU(0) when `block` = (bx, by, bz)."""
+
+    def __init__(self, pb, W, diag, order=None, block=None):
         self.pb = pb
         g = grid_of(pb)
         W = _f64(W)
-        self.order = redblack_order(pb) if order is None else np.ascontiguousarray(order, dtype=np.int64)
         self._keep = (W, _f64(diag))
+        if block is not None:
+            self.order = np.arange(pb.n, dtype=np.int64)
+            self.h = lib().or_ilu0_block_create(ctypes.byref(g), _ptr(W[0]), _ptr(W[1]), _ptr(W[2]),
+                                                _ptr(self._keep[1]), int(block[0]), int(block[1]),
+                                                int(block[2]))
+            return
+        self.order = redblack_order(pb) if order is None else np.ascontiguousarray(order, dtype=np.int64)
         self.h = lib().or_ilu0_create(ctypes.byref(g), _ptr(W[0]), _ptr(W[1]), _ptr(W[2]),
                                       _ptr(self._keep[1]), _ptr(self.order))
 
@@ -284,14 +302,23 @@ def cams_solve(pb, W, diag, P, restriction, LU, piv, ilu, r0, n_pre=None, n_post
     return d, its, hist[:n_hist]
 
 
+def smoother_for(pb, W, diag, smoother=None):
+    """The ILU(0) smoother the problem asks for (default: block-Jacobi)."""
+    kind = getattr(pb, "smoother", SMOOTH_BLOCK) if smoother is None else smoother
+    if kind == SMOOTH_BLOCK:
+        return ILU0(pb, W, diag, block=smoother_block(pb))
+    return ILU0(pb, W, diag)
+
+
 def newton_step(pb, T, P, pn, p, restriction=None, n_pre=None, n_post=None, lin_rtol=None,
-                lin_maxit=None, newton_tol=None, newton_maxit=None):
+                lin_maxit=None, newton_tol=None, newton_maxit=None, smoother=None):
     """One time step.  Returns (p_new, status, stats dict)."""
     g, f = grid_of(pb), fluid_of(pb)
     T = _f64(T)
     p = np.array(p, dtype=np.float64, copy=True)
     q = None if pb.q is None else _f64(pb.q)
     st = np.zeros(3)
+    kind = getattr(pb, "smoother", SMOOTH_BLOCK) if smoother is None else smoother
     rc = lib().or_newton_step(
         ctypes.byref(g), ctypes.byref(f), _ptr(T[0]), _ptr(T[1]), _ptr(T[2]), _ptr(_f64(pb.phi)),
         None if q is None else _ptr(q), _ptr(pb.dirichlet_mask()), _ptr(_f64(P)),
@@ -301,5 +328,6 @@ def newton_step(pb, T, P, pn, p, restriction=None, n_pre=None, n_post=None, lin_
         int(pb.lin_maxit if lin_maxit is None else lin_maxit),
         ctypes.c_double(pb.newton_tol if newton_tol is None else newton_tol),
         int(pb.newton_maxit if newton_maxit is None else newton_maxit),
+        int(1 if kind == SMOOTH_BLOCK else 0), *smoother_block(pb),
         _ptr(_f64(pn)), _ptr(p), _ptr(st))
     return p, rc, {"newton_iters": int(st[0]), "lin_iters": int(st[1]), "eps_norm": float(st[2])}

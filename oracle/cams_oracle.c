@@ -721,6 +721,32 @@ void or_ilu0_apply(void *h, const double *z, double *x)
     free(y);
 }
 
+/* Block-Jacobi ILU(0): the couplings across the faces of bx x by x bz cell
+ * blocks (aligned at the origin, the last block of an axis possibly shorter)
+ * are removed, and ILU(0) in natural order is taken of what remains; the
+ * blocks are then independent of each other.  The smoothing residual still
+ * uses the full matrix. */
+void *or_ilu0_block_create(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
+                           const double *diag, int bx, int by, int bz)
+{
+    long N = ncells(g);
+    double *W = (double *)malloc(sizeof(double) * 3 * N);
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * N);
+    for (int k = 0; k < g->nz; k++)
+        for (int j = 0; j < g->ny; j++)
+            for (int i = 0; i < g->nx; i++) {
+                long n = cell_index(g, i, j, k);
+                W[n] = ((i + 1) % bx == 0) ? 0.0 : Wx[n];
+                W[N + n] = ((j + 1) % by == 0) ? 0.0 : Wy[n];
+                W[2 * N + n] = ((k + 1) % bz == 0) ? 0.0 : Wz[n];
+                order[n] = n;
+            }
+    void *h = or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
+    free(W);
+    free(order);
+    return h;
+}
+
 /* The red-black ordering used by the smoother. */
 void or_redblack_order(const og_grid *g, int64_t *order)
 {
@@ -806,7 +832,9 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
  * One backward-Euler time step by the paper's Newton-Raphson linearisation
  * (Sec. 2; Table "cams" outer loop; Sec. 4.1.1 for the error norm):
  *   repeat: assemble A, r at p; if ||eps||_2 <= newton_tol stop;
- *           coarse operator + LU; ILU(0) (red-black order); C-AMS solve; p += d.
+ *           coarse operator + LU; ILU(0) smoother (smoother 0: red-black
+ *           order; 1: block-Jacobi ILU(0) on bx x by x bz blocks); C-AMS
+ *           solve; p += d.
  * The basis P (type B4) is pressure independent and passed in.
  * stats[0] = Newton iterations, stats[1] = total linear iterations,
  * stats[2] = final ||eps||_2.  Returns 0, -1 (Newton not converged),
@@ -816,7 +844,7 @@ int or_newton_step(const og_grid *g, const og_fluid *f,
                    const double *Tx, const double *Ty, const double *Tz,
                    const double *phi, const double *q, const uint8_t *dmask, const double *P,
                    int restriction, int n_pre, int n_post, double lin_rtol, int lin_maxit,
-                   double newton_tol, int newton_maxit,
+                   double newton_tol, int newton_maxit, int smoother, int bx, int by, int bz,
                    const double *pn, double *p, double *stats)
 {
     long N = ncells(g);
@@ -837,7 +865,8 @@ int or_newton_step(const og_grid *g, const og_fluid *f,
         if (nit == newton_maxit || !isfinite(en)) break;
         or_coarse_operator(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac);
         if (or_lu_factor(Nc, Ac, piv) != 0) { rc = -3; break; }
-        void *ilu = or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
+        void *ilu = smoother == 1 ? or_ilu0_block_create(g, W, W + N, W + 2 * N, diag, bx, by, bz)
+                                  : or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
         int its = or_cams_solve(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac, piv, ilu,
                                 n_pre, n_post, lin_rtol, lin_maxit, r, d, NULL);
         or_ilu0_free(ilu);

@@ -25,6 +25,8 @@ CAMS_R_FE = 1
 CAMS_FP64 = 0
 CAMS_MIXED_FP32 = 1
 CAMS_MIXED_BF16 = 2
+CAMS_SMOOTH_BLOCK_ILU0 = 0
+CAMS_SMOOTH_RB_ILU0 = 1
 
 CAMS_ARR_T = 0
 CAMS_ARR_W = 1
@@ -49,7 +51,8 @@ class cams_fluid(ctypes.Structure):
 
 class cams_options(ctypes.Structure):
     _fields_ = [("restriction", ctypes.c_int32), ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("lin_rtol", ctypes.c_double), ("lin_maxit", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("lin_rtol", ctypes.c_double), ("lin_maxit", ctypes.c_int32),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32)]
 
 

@@ -161,6 +161,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     if (O.restriction != CAMS_R_FV && O.restriction != CAMS_R_FE) return CAMS_E_ARG;
     if (O.n_pre < 0 || O.n_pre > 64 || O.n_post < 0 || O.n_post > 64) return CAMS_E_ARG;
     if (O.precision != CAMS_FP64) return CAMS_E_ARG;  // mixed precision: not in this library build
+    if (O.smoother != CAMS_SMOOTH_BLOCK_ILU0 && O.smoother != CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
     if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
     const int nb[3] = {num_blocks(n[0], r[0]), num_blocks(n[1], r[1]), num_blocks(n[2], r[2])};
     const double Nc = (double)nb[0] * nb[1] * nb[2];
@@ -207,6 +208,16 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
         t.tab.resize(base + words, 0);
         memcpy(t.tab.data() + base, isv.data(), n[a]);
         seg[a] = segments(n[a], v, a < 2 || three_d);
+        // restriction-owner boxes: primal blocks (MSFV) or [v_a, v_{a+1}) with
+        // the first box starting at 0 and the last ending at n (MSFE)
+        t.tab_off[a][3] = t.tab.size();
+        const int nba = (int)v.size();
+        for (int b = 0; b <= nba; ++b) {
+            int x;
+            if (O.restriction == CAMS_R_FV) x = std::min(b * r[a], n[a]);
+            else x = b == 0 ? 0 : (b == nba ? n[a] : v[b]);
+            t.tab.push_back(x);
+        }
     }
     // dual regions by number of open axes
     std::vector<Region> by[4];
@@ -235,41 +246,70 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     // workspace layout
     Layout L;
     L.off = c->off;
+    constexpr int kMaxArrays = (int)(sizeof(c->off) / sizeof(c->off[0]));
+    int k = 0;
+    auto put = [&](size_t o) {
+        if (k < kMaxArrays) c->off[k] = o;
+        ++k;
+    };
     const size_t n8 = (size_t)g.N * 8;
     const size_t nc = (size_t)g.Nc;
-    c->nparts = (g.N + kBlock - 1) / kBlock;
-    int k = 0;
-    L.off[k++] = L.add(3 * n8);        // 0 T
-    L.off[k++] = L.add(n8);            // 1 phi
-    L.off[k++] = L.add(n8);            // 2 q
-    L.off[k++] = L.add(3 * n8);        // 3 W
-    L.off[k++] = L.add(n8);            // 4 diag
-    L.off[k++] = L.add(n8);            // 5 r0
-    L.off[k++] = L.add(n8);            // 6 r
-    L.off[k++] = L.add(n8);            // 7 dp0
-    L.off[k++] = L.add(n8);            // 8 dp1
-    L.off[k++] = L.add(n8);            // 9 d0
-    L.off[k++] = L.add(n8);            // 10 d1
-    L.off[k++] = L.add(n8);            // 11 d2
-    L.off[k++] = L.add(n8);            // 12 z
-    L.off[k++] = L.add(n8);            // 13 x
-    L.off[k++] = L.add(n8);            // 14 invd
-    L.off[k++] = L.add(8 * n8);        // 15 P
-    L.off[k++] = L.add(nc * nc * 8);   // 16 Ac
-    L.off[k++] = L.add(nc * nc * 8);   // 17 Ainv
-    L.off[k++] = L.add(nc * nc * 8);   // 18 work
-    L.off[k++] = L.add(nc * 8);        // 19 rc
-    L.off[k++] = L.add(nc * 8);        // 20 xc
-    L.off[k++] = L.add((size_t)c->nparts * 8);  // 21 partial
-    L.off[k++] = L.add(64 * 8);        // 22 scal
-    L.off[k++] = L.add(nc * 2 * 4);    // 23 piv + perm
-    L.off[k++] = L.add(64 * 4);        // 24 status
-    L.off[k++] = L.add((size_t)g.N);   // 25 dmask
+    c->nparts = std::max((g.N + kBlock - 1) / kBlock, g.Nc);
+    put(L.add(3 * n8));        // 0 T
+    put(L.add(n8));            // 1 phi
+    put(L.add(n8));            // 2 q
+    put(L.add(3 * n8));        // 3 W
+    put(L.add(n8));            // 4 diag
+    put(L.add(n8));            // 5 r0
+    put(L.add(n8));            // 6 r
+    put(L.add(n8));            // 7 dp0
+    put(L.add(n8));            // 8 dp1
+    put(L.add(n8));            // 9 d0
+    put(L.add(n8));            // 10 d1
+    put(L.add(n8));            // 11 d2
+    put(L.add(n8));            // 12 z
+    put(L.add(n8));            // 13 x
+    put(L.add(n8));            // 14 invd
+    put(L.add(8 * n8));        // 15 P
+    put(L.add(nc * nc * 8));   // 16 Ac
+    put(L.add(nc * nc * 8));   // 17 Ainv
+    put(L.add(nc * nc * 8));   // 18 work
+    put(L.add(nc * 8));        // 19 rc
+    put(L.add(nc * 8));        // 20 xc
+    put(L.add((size_t)c->nparts * 8));  // 21 partial
+    put(L.add(64 * 8));        // 22 scal
+    put(L.add(nc * 2 * 4));    // 23 piv + perm
+    put(L.add(64 * 4));        // 24 status
+    put(L.add((size_t)g.N));   // 25 dmask
     const size_t wcap = (size_t)g.N / 8 + 64;
-    L.off[k++] = L.add(wcap * 4);      // 26 wcell
-    L.off[k++] = L.add(wcap * 8);      // 27 wp
-    L.off[k++] = L.add(t.tab.size() * 4);            // 28 tables
-    L.off[k++] = L.add(t.regions.size() * sizeof(Region) + 16);  // 29 regions
+    put(L.add(wcap * 4));      // 26 wcell
+    put(L.add(wcap * 8));      // 27 wp
+    put(L.add(t.tab.size() * 4));            // 28 tables
+    put(L.add(t.regions.size() * sizeof(Region) + 16));  // 29 regions
+    put(L.add(nc * 8 * 8));    // 30 restriction slot sums
+    put(L.add((nc + 64) * 4));   // 31 iteration control
+    // restriction rows: largest number of z-planes
+    {
+        int mp = 1;
+        std::vector<int32_t> vz = three_d ? vertex_coords(n[2], r[2]) : std::vector<int32_t>{0};
+        for (int b = 0; b < nb[2]; ++b) {
+            int lo, hi;
+            if (O.restriction == CAMS_R_FE) {
+                lo = b > 0 ? vz[b - 1] + 1 : 0;
+                hi = b < nb[2] - 1 ? vz[b + 1] - 1 : n[2] - 1;
+            } else {
+                lo = b * r[2];
+                hi = std::min((b + 1) * r[2], n[2]) - 1;
+            }
+            mp = std::max(mp, hi - lo + 1);
+        }
+        c->max_planes = mp;
+    }
+    put(L.add(nc * (size_t)c->max_planes * 8));   // 32 restriction plane partials
+    if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
+        delete c;
+        return CAMS_E_NOMEM;
+    }
     c->need = L.total;
 
     *out = c;
@@ -319,6 +359,9 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.wp = (double *)(w + off[27]);
     a.tab = (int32_t *)(w + off[28]);
     a.regions = (Region *)(w + off[29]);
+    a.slots = (double *)(w + off[30]);
+    a.ictl = (int32_t *)(w + off[31]);
+    a.planes = (double *)(w + off[32]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -333,6 +376,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
         c->g.vc[ax] = a.tab + t.tab_off[ax][0];
         c->g.lo[ax] = a.tab + t.tab_off[ax][1];
         c->g.isv[ax] = (const uint8_t *)(a.tab + t.tab_off[ax][2]);
+        c->g.ob[ax] = a.tab + t.tab_off[ax][3];
     }
     try {
         CAMS_HIP(hipMemcpyAsync(a.tab, t.tab.data(), t.tab.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -341,6 +385,8 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
                                     hipMemcpyHostToDevice, c->stream));
         std::vector<uint8_t> zero((size_t)N, 0);
         CAMS_HIP(hipMemcpyAsync(a.dmask, zero.data(), (size_t)N, hipMemcpyHostToDevice, c->stream));
+        std::vector<int32_t> zctl((size_t)c->g.Nc + 64, 0);
+        CAMS_HIP(hipMemcpyAsync(a.ictl, zctl.data(), zctl.size() * 4, hipMemcpyHostToDevice, c->stream));
         clear_status(c);
         CAMS_HIP(hipStreamSynchronize(c->stream));
     } catch (const HipError &e) {
@@ -418,7 +464,7 @@ cams_status cams_assemble(cams_ctx *c, const double *p_dev, const double *pn_dev
     if (!p_dev || !pn_dev) return fail(c, CAMS_E_ARG, "null pressure");
     try {
         launch_assemble(c, p_dev, pn_dev);
-        launch_reduce(c, c->a.partial, c->nparts, c->a.scal + S_EPS2);
+        launch_reduce(c, c->a.partial, (c->g.N + kBlock - 1) / kBlock, c->a.scal + S_EPS2);
         CAMS_HIP(hipGetLastError());
         if (eps_norm_out) {
             double e2 = read_scalar(c, c->a.scal + S_EPS2);
@@ -479,12 +525,38 @@ cams_status cams_smooth_apply(cams_ctx *c, const double *z, double *x)
     if (!c || !z || !x) return CAMS_E_ARG;
     if (!c->has_coarse) return fail(c, CAMS_E_STATE, "smoother factor is built by coarse_op");
     try {
-        launch_smooth(c, z, x, 1);
+        launch_smooth(c, z, x, 1, nullptr);
         CAMS_HIP(hipGetLastError());
     } catch (const HipError &e) {
         return fail(c, CAMS_E_DEVICE, std::string("smooth_apply: ") + hipGetErrorString(e.code));
     }
     return CAMS_OK;
+}
+
+// Enqueue one C-AMS iteration (Table "cams" steps 2, 5-7).  The residual
+// kernel of iteration `it` reads dp[it % 2], folds in the corrections of the
+// previous iteration and writes dp[(it + 1) % 2]; it also decides on the
+// device whether to stop.  Every other kernel returns at once when the
+// stop flag is set, so iterations enqueued past convergence cost only their
+// launches.
+static void enqueue_iteration(cams_ctx *c, int it)
+{
+    const cams_options &O = c->opt;
+    Arrays &a = c->a;
+    const int32_t *done = a.ictl + 1;
+    const double *pend0 = O.n_pre > 0 ? a.d0 : nullptr;
+    const double *pend2 = O.n_post > 0 ? a.d2 : nullptr;
+    launch_residual_ctl(c, a.dp[it & 1], pend0, a.d1, pend2, a.dp[(it + 1) & 1]);
+    launch_finalize_ctl(c);
+    if (O.n_pre > 0) {
+        launch_smooth(c, a.r, a.d0, O.n_pre, done);
+        launch_stencil_sub(c, a.r, a.d0, a.r, done);
+    }
+    launch_restrict_planes(c, a.r, done);
+    launch_gemv(c, a.rc, a.xc, done);                  // Eq. (15): coarse solve
+    launch_prolong(c, a.xc, a.d1, done);               // Eq. (12)
+    launch_stencil_sub(c, a.r, a.d1, a.r, done);       // r1 = r - A d1
+    if (O.n_post > 0) launch_smooth(c, a.r, a.d2, O.n_post, done);
 }
 
 cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
@@ -495,40 +567,43 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
     const cams_options &O = c->opt;
     const int N = c->g.N;
     Arrays &a = c->a;
-    cams_status rc = CAMS_OK;
-    int it = 0;
+    int it = 0, outcome = 0;
     double nr0 = 0.0, nr = 0.0;
     try {
-        launch_fill(c, a.dp[0], N, 0.0);
-        int cur = 0;
-        const double *adds[3] = {nullptr, nullptr, nullptr};
-        for (;; ++it) {
-            const bool pending = adds[0] || adds[1] || adds[2];
-            launch_residual(c, a.dp[cur], adds[0], adds[1], adds[2], pending ? a.dp[1 - cur] : nullptr, a.r);
-            if (pending) cur = 1 - cur;
-            launch_restrict(c, a.r, a.rc, true);
-            nr = sqrt(read_scalar(c, a.scal + S_RN2));
-            if (it == 0) nr0 = nr;
-            if (!isfinite(nr)) { rc = CAMS_E_BREAKDOWN; break; }
-            if (nr <= O.lin_rtol * nr0 || nr0 == 0.0) break;
-            if (it >= O.lin_maxit) { rc = CAMS_E_NOT_CONVERGED; break; }
-            adds[0] = adds[1] = adds[2] = nullptr;
-            if (O.n_pre > 0) {
-                launch_smooth(c, a.r, a.d0, O.n_pre);
-                launch_stencil_sub(c, a.r, a.d0, a.r);
-                launch_restrict(c, a.r, a.rc, false);
-                adds[0] = a.d0;
+        launch_iter_reset(c);
+        int launched = 0, ahead = 4;
+        double prev_nr = -1.0;
+        // the red-black smoother kernels have no stop flag: check every iteration
+        const bool sync_each = O.smoother == CAMS_SMOOTH_RB_ILU0;
+        for (;;) {
+            const int batch = sync_each ? 1 : ahead;
+            for (int q = 0; q < batch && launched <= O.lin_maxit; ++q) enqueue_iteration(c, launched++);
+            int32_t ctl[3];
+            CAMS_HIP(hipMemcpyAsync(c->host + 16, a.ictl, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            CAMS_HIP(hipMemcpyAsync(c->host + 20, a.scal + S_R0N2, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                    c->stream));
+            CAMS_HIP(hipStreamSynchronize(c->stream));
+            memcpy(ctl, c->host + 16, sizeof(ctl));
+            nr0 = sqrt(c->host[20]);
+            nr = sqrt(c->host[21]);
+            it = ctl[0];
+            if (ctl[1]) {
+                outcome = ctl[2];
+                break;
             }
-            launch_gemv(c, a.rc, a.xc);                 // Eq. (15): coarse solve
-            launch_prolong(c, a.xc, a.d1);              // Eq. (12)
-            launch_stencil_sub(c, a.r, a.d1, a.r);      // r1 = r - A d1
-            adds[1] = a.d1;
-            if (O.n_post > 0) {
-                launch_smooth(c, a.r, a.d2, O.n_post);
-                adds[2] = a.d2;
+            if (launched > O.lin_maxit) {  // cannot happen: the device stops at lin_maxit
+                outcome = 1;
+                break;
             }
+            // enqueue about as many iterations as the observed rate needs
+            if (prev_nr > 0.0 && nr < prev_nr && nr0 > 0.0) {
+                const double rate = pow(nr / prev_nr, 1.0 / std::max(1, batch));
+                const double need = log(O.lin_rtol * nr0 / nr) / log(rate);
+                ahead = (int)std::min(32.0, std::max(2.0, ceil(need)));
+            }
+            prev_nr = nr;
         }
-        launch_axpy(c, p_dev, a.dp[cur], N);
+        launch_axpy(c, p_dev, a.dp[(it + 1) & 1], N);
         CAMS_HIP(hipGetLastError());
         CAMS_HIP(hipStreamSynchronize(c->stream));
     } catch (const HipError &e) {
@@ -540,8 +615,8 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
         stats->lin_iters_last = it;
         stats->relres_last = c->last.relres_last;
     }
-    if (rc == CAMS_E_NOT_CONVERGED) return fail(c, rc, "linear iteration limit reached");
-    if (rc == CAMS_E_BREAKDOWN) return fail(c, rc, "non-finite residual norm");
+    if (outcome == 1) return fail(c, CAMS_E_NOT_CONVERGED, "linear iteration limit reached");
+    if (outcome == 2) return fail(c, CAMS_E_BREAKDOWN, "non-finite residual norm");
     return CAMS_OK;
 }
 

@@ -27,6 +27,7 @@ struct GridDev {
     const int32_t *vc[3];
     const int32_t *lo[3];
     const uint8_t *isv[3];
+    const int32_t *ob[3];   // restriction-owner box starts per axis (nb + 1 entries)
 };
 
 struct Fluid {
@@ -54,9 +55,13 @@ struct Arrays {
     double *Ac, *Ainv, *work; // Nc*Nc each
     double *rc, *xc;  // Nc
     double *partial;  // reduction partials
+    double *slots;    // Nc*8 restriction slot sums
     double *scal;     // device scalars
     int32_t *piv;     // Nc
     int32_t *status;  // device error flags
+    int32_t *ictl;    // iteration control: [0] iteration, [1] done, [2] outcome, [3] arrival counter,
+                      // [4..4+Nc) per-node arrival counters of the restriction
+    double *planes;   // Nc * max_planes restriction partials
     uint8_t *dmask;   // N
     int32_t *wcell;   // wells
     double *wp;
@@ -92,6 +97,7 @@ struct cams_ctx {
     size_t ws_bytes;
     cams::Arrays a;
     int nparts;             // reduction partial count
+    int max_planes;         // largest number of z-planes in a restriction row
     int nwells;
     bool has_ws, has_rock, has_q, has_basis, has_system, has_coarse;
     int cur_dp;
@@ -103,8 +109,8 @@ struct cams_ctx {
     // cams_set_workspace) and the workspace offsets
     std::vector<int32_t> tab;
     std::vector<cams::Region> regions;
-    size_t tab_off[3][3];
-    size_t off[32];
+    size_t tab_off[3][4];
+    size_t off[48];         // workspace offsets (kMaxArrays entries)
 };
 
 namespace cams {
@@ -116,22 +122,35 @@ void launch_check_rock(cams_ctx *c, const double *perm, const double *phi);
 void launch_assemble(cams_ctx *c, const double *p, const double *pn);
 void launch_reduce(cams_ctx *c, const double *partial, int n, double *out);
 void launch_impose_wells(cams_ctx *c, double *p);
-void launch_residual(cams_ctx *c, const double *dp_in, const double *a0, const double *a1,
-                     const double *a2, double *dp_out, double *r);
-void launch_stencil_sub(cams_ctx *c, const double *b, const double *x, double *out);
-void launch_prolong(cams_ctx *c, const double *xc, double *out);
-void launch_ilu_setup(cams_ctx *c);
-void launch_smooth(cams_ctx *c, const double *rhs, double *e, int steps);
+void launch_stencil_sub(cams_ctx *c, const double *b, const double *x, double *out, const int32_t *done);
+void launch_prolong(cams_ctx *c, const double *xc, double *out, const int32_t *done);
+void launch_ilu_setup(cams_ctx *c);  // dispatches on opt.smoother
+void launch_rb_setup(cams_ctx *c);
+void launch_rb_smooth(cams_ctx *c, const double *rhs, double *e, int steps);
+// dispatches on opt.smoother; `done` (nullable) skips the work once the iteration has converged
+void launch_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done);
 void launch_axpy(cams_ctx *c, double *y, const double *x, int n);
+
+// ---- block ILU(0) smoother (k_smooth.hip)
+void launch_bilu_setup(cams_ctx *c);
+void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done);
+
+// ---- iteration control (k_iter.hip)
+void launch_iter_reset(cams_ctx *c);
+// r = r0 - A v with v = dp_in (+ the pending corrections after the first
+// iteration), dp_out = v, ||r|| and the stopping test on the device
+void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, const double *a1, const double *a2,
+                         double *dp_out);
+void launch_finalize_ctl(cams_ctx *c);   // ||r||, stopping test, iteration counter
+void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *done);
 
 // ---- basis (k_basis.hip)
 void launch_basis(cams_ctx *c);
 
 // ---- coarse level (k_coarse.hip)
 void launch_coarse_operator(cams_ctx *c);
-void launch_restrict(cams_ctx *c, const double *r, double *rc, bool finalize_norm);
 void launch_coarse_factor(cams_ctx *c);   // LU + explicit inverse of Ac
-void launch_gemv(cams_ctx *c, const double *rc, double *xc);
+void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done);
 
 }  // namespace cams
 

@@ -108,46 +108,6 @@ __global__ __launch_bounds__(kBlock) void k_coarse_row(GridDev g, const double *
     }
 }
 
-// rc[k] = sum over the row's cells of w_i r_i; workgroup 0 also finishes the
-// norm ||r||^2 from the residual kernel's partials.
-__global__ __launch_bounds__(kBlock) void k_restrict(GridDev g, const uint8_t *__restrict__ dm,
-                                                      const double *__restrict__ P, int fe,
-                                                      const double *__restrict__ r, double *__restrict__ rc,
-                                                      const double *__restrict__ partial, int nparts,
-                                                      double *__restrict__ norm_out)
-{
-    __shared__ double sh[kBlock / 64];
-    const int k = blockIdx.x;
-    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
-    int lo[3], hi[3];
-    row_range(g, 0, ka, fe, lo[0], hi[0]);
-    row_range(g, 1, kb, fe, lo[1], hi[1]);
-    row_range(g, 2, kc, fe, lo[2], hi[2]);
-    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-    const int cnt = ex * ey * ez;
-    double v = 0.0;
-    for (int t = threadIdx.x; t < cnt; t += kBlock) {
-        const int i = lo[0] + t % ex, j = lo[1] + (t / ex) % ey, kk = lo[2] + t / (ex * ey);
-        const int n = i + g.nx * (j + g.ny * kk);
-        if (fe) {
-            if (dm[n]) continue;
-            const int sx = ka - g.lo[0][i], sy = kb - g.lo[1][j], sz = kc - g.lo[2][kk];
-            if (sx < 0 || sx > 1 || sy < 0 || sy > 1 || sz < 0 || sz > 1) continue;
-            v += P[(size_t)(sx + 2 * sy + 4 * sz) * g.N + n] * r[n];
-        } else {
-            v += r[n];
-        }
-    }
-    double s = block_sum<kBlock>(v, sh);
-    if (threadIdx.x == 0) rc[k] = s;
-    if (norm_out && k == 0) {
-        double u = 0.0;
-        for (int t = threadIdx.x; t < nparts; t += kBlock) u += partial[t];
-        double su = block_sum<kBlock>(u, sh);
-        if (threadIdx.x == 0) *norm_out = su;
-    }
-}
-
 // ---------------------------------------------------------------- LU ----
 
 // Factor columns [j0, j0+nb) of the row-major n x n matrix A (rows j0..n-1):
@@ -203,6 +163,74 @@ __global__ __launch_bounds__(kBlock) void k_lu_panel(double *__restrict__ A, int
     }
 }
 
+// Same factorisation with the whole panel ((n - j0) x nb, row stride nb + 1
+// against bank conflicts, at most kPanelLds doubles) held in LDS: one global
+// read and write of the panel.
+constexpr int kPanelLds = 16640;   // 256 rows x 65
+
+__global__ __launch_bounds__(kBlock) void k_lu_panel_lds(double *__restrict__ A, int n, int j0, int nb,
+                                                          int32_t *__restrict__ piv, int32_t *status)
+{
+    __shared__ double Ps[kPanelLds];
+    __shared__ double wv[kBlock / 64];
+    __shared__ int wi[kBlock / 64];
+    const int m = n - j0;
+    const int ld = nb + 1;
+    for (int t = threadIdx.x; t < m * nb; t += kBlock) {
+        const int i = t / nb, c = t % nb;
+        Ps[i * ld + c] = A[(size_t)(j0 + i) * n + j0 + c];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int cc = 0; cc < nb; ++cc) {
+        // pivot: largest |entry| of column cc in rows cc..m-1 (lowest row on ties)
+        double best = -1.0;
+        int bi = cc;
+        for (int i = cc + threadIdx.x; i < m; i += kBlock) {
+            const double v = fabs(Ps[i * ld + cc]);
+            if (v > best) { best = v; bi = i; }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_down(best, off, 64);
+            const int oi = __shfl_down(bi, off, 64);
+            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        if (lane == 0) { wv[w] = best; wi[w] = bi; }
+        __syncthreads();
+        double pb = wv[0];
+        int p = wi[0];
+        for (int t = 1; t < kBlock / 64; ++t)
+            if (wv[t] > pb || (wv[t] == pb && wi[t] < p)) { pb = wv[t]; p = wi[t]; }
+        if (threadIdx.x == 0) {
+            piv[j0 + cc] = j0 + p;
+            if (!(pb > 0.0)) atomicOr(status, F_SINGULAR_COARSE);
+        }
+        if (p != cc)
+            for (int c = threadIdx.x; c < nb; c += kBlock) {
+                const double t = Ps[cc * ld + c];
+                Ps[cc * ld + c] = Ps[p * ld + c];
+                Ps[p * ld + c] = t;
+            }
+        __syncthreads();
+        double pv = Ps[cc * ld + cc];
+        if (pv == 0.0) pv = 1.0;  // flagged above; keep the arithmetic finite
+        for (int i = cc + 1 + threadIdx.x; i < m; i += kBlock) Ps[i * ld + cc] /= pv;
+        __syncthreads();
+        // rank-1 update: lane = column, waves stride over rows
+        const int c = cc + 1 + lane;
+        if (c < nb) {
+            const double u = Ps[cc * ld + c];
+            for (int i = cc + 1 + w; i < m; i += kBlock / 64) Ps[i * ld + c] -= Ps[i * ld + cc] * u;
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < m * nb; t += kBlock) {
+        const int i = t / nb, c = t % nb;
+        A[(size_t)(j0 + i) * n + j0 + c] = Ps[i * ld + c];
+    }
+}
+
 // Apply the panel's interchanges to the columns outside [j0, j0+nb).
 __global__ __launch_bounds__(kBlock) void k_lu_swap(double *__restrict__ A, int n, int j0, int nb,
                                                      const int32_t *__restrict__ piv)
@@ -224,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_lu_swap(double *__restrict__ A, int 
 // rows j0..j0+nb-1 of B (ncols columns starting at col0, leading dim ldb):
 // upper = 0: unit lower triangle (forward); upper = 1: upper triangle
 // (backward).  A block shorter than kNB is padded with identity rows so the
-// loops are static and the column stays in registers.
+// loops are static and the column stays in registers.  Column-oriented
+// updates keep up to 63 independent FMAs in flight per step.
 __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, int n, int j0, int nb, double *B,
                                                   int ldb, int col0, int ncols, int upper)
 {
@@ -243,19 +272,15 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
     for (int r = 0; r < kNB; ++r) x[r] = (r < nb) ? B[(size_t)(j0 + r) * ldb + col] : 0.0;
     if (!upper) {
 #pragma unroll
-        for (int r = 1; r < kNB; ++r) {
-            double s = x[r];
+        for (int t = 0; t < kNB - 1; ++t)
 #pragma unroll
-            for (int t = 0; t < r; ++t) s -= Ls[r][t] * x[t];
-            x[r] = s;
-        }
+            for (int r = t + 1; r < kNB; ++r) x[r] -= Ls[r][t] * x[t];
     } else {
 #pragma unroll
-        for (int r = kNB - 1; r >= 0; --r) {
-            double s = x[r];
+        for (int t = kNB - 1; t >= 0; --t) {
+            x[t] /= Ls[t][t];
 #pragma unroll
-            for (int t = r + 1; t < kNB; ++t) s -= Ls[r][t] * x[t];
-            x[r] = s / Ls[r][r];
+            for (int r = 0; r < t; ++r) x[r] -= Ls[r][t] * x[t];
         }
     }
 #pragma unroll
@@ -353,16 +378,45 @@ __global__ __launch_bounds__(kBlock) void k_copy(const double *__restrict__ a, d
     if (t < n) b[t] = a[t];
 }
 
-// y = M x, one wave per row (fixed lane partition and shuffle tree).
-__global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, int n, const double *__restrict__ x,
-                                                  double *__restrict__ y)
+// rc[k] = sum of the restriction plane partials of row k (in plane order).
+__global__ __launch_bounds__(kBlock) void k_sum_planes(const double *__restrict__ planes, int n, int np,
+                                                        double *__restrict__ rc, const int32_t *done)
 {
+    if (done && *done) return;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    double s = 0.0;
+    for (int q = 0; q < np; ++q) s += planes[(size_t)k * np + q];
+    rc[k] = s;
+}
+
+constexpr int kGemvLds = 4096;   // coarse sizes whose rhs fits in LDS
+
+// y = M x, one wave per row (fixed lane partition and shuffle tree).  With
+// `planes` set (n <= kGemvLds), x is first assembled in LDS from the
+// restriction plane partials (row k: planes[k*np .. k*np+np-1], in order).
+__global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, int n, const double *__restrict__ x,
+                                                  const double *__restrict__ planes, int np,
+                                                  double *__restrict__ y, const int32_t *done)
+{
+    __shared__ double xs[kGemvLds];
+    if (done && *done) return;
+    const double *xv = x;
+    if (planes) {
+        for (int k = threadIdx.x; k < n; k += kBlock) {
+            double s = 0.0;
+            for (int q = 0; q < np; ++q) s += planes[(size_t)k * np + q];
+            xs[k] = s;
+        }
+        __syncthreads();
+        xv = xs;
+    }
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
     const double *mr = M + (size_t)row * n;
     double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    for (int c = lane; c < n; c += 64) s += mr[c] * xv[c];
     s = wave_sum(s);
     if (lane == 0) y[row] = s;
 }
@@ -385,13 +439,6 @@ void launch_coarse_operator(cams_ctx *c)
                                                     c->opt.restriction == CAMS_R_FE, c->a.Ac);
 }
 
-void launch_restrict(cams_ctx *c, const double *r, double *rc, bool finalize_norm)
-{
-    k_restrict<<<c->g.Nc, kBlock, 0, c->stream>>>(c->g, c->a.dmask, c->a.P, c->opt.restriction == CAMS_R_FE, r, rc,
-                                                  c->a.partial, c->nparts,
-                                                  finalize_norm ? c->a.scal + S_RN2 : nullptr);
-}
-
 void launch_coarse_factor(cams_ctx *c)
 {
     const int n = c->g.Nc;
@@ -401,7 +448,10 @@ void launch_coarse_factor(cams_ctx *c)
     // LU with partial pivoting, right looking by panels
     for (int j0 = 0; j0 < n; j0 += kNB) {
         const int nb = n - j0 < kNB ? n - j0 : kNB;
-        k_lu_panel<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.piv, c->a.status);
+        if ((size_t)(n - j0) * (nb + 1) <= (size_t)kPanelLds)
+            k_lu_panel_lds<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.piv, c->a.status);
+        else
+            k_lu_panel<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.piv, c->a.status);
         if (n - nb > 0) k_lu_swap<<<cdiv(n - nb, kBlock), kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.piv);
         const int rest = n - j0 - nb;
         if (rest > 0) {
@@ -431,10 +481,17 @@ void launch_coarse_factor(cams_ctx *c)
     }
 }
 
-void launch_gemv(cams_ctx *c, const double *rc, double *xc)
+void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done)
 {
     const int n = c->g.Nc;
-    k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, rc, xc);
+    if (n <= kGemvLds) {
+        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, nullptr, c->a.planes, c->max_planes,
+                                                             xc, done);
+    } else {
+        k_sum_planes<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.planes, n, c->max_planes, c->a.rc, done);
+        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, nullptr, 0, xc, done);
+    }
+    (void)rc;
 }
 
 // Test hook: C -= A B on the device, same kernel as the factorisation.

@@ -157,36 +157,18 @@ __device__ __forceinline__ double apply_A(const GridDev &g, const double *__rest
     return s;
 }
 
-// r = r0 - A (dp + a0 + a1 + a2); dp_out = dp + a0 + a1 + a2; partial ||r||^2.
-__global__ __launch_bounds__(kBlock) void k_residual(GridDev g, const double *__restrict__ W,
-                                                      const double *__restrict__ diag, const double *__restrict__ r0,
-                                                      VecSum v, double *__restrict__ dp_out, double *__restrict__ r,
-                                                      double *__restrict__ partial)
-{
-    __shared__ double sh[kBlock / 64];
-    int n = blockIdx.x * kBlock + threadIdx.x;
-    double e2 = 0.0;
-    if (n < g.N) {
-        double vn = v(n);
-        double rr = r0[n] - apply_A(g, W, diag, v, n, vn);
-        r[n] = rr;
-        if (dp_out) dp_out[n] = vn;
-        e2 = rr * rr;
-    }
-    double s = block_sum<kBlock>(e2, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
 struct Vec1 {
     const double *v;
     __device__ __forceinline__ double operator()(int m) const { return v[m]; }
 };
 
-// out = b - A x   (out may alias b).
+// out = b - A x   (out may alias b).  Skipped once `done` (nullable) is set.
 __global__ __launch_bounds__(kBlock) void k_stencil_sub(GridDev g, const double *__restrict__ W,
                                                          const double *__restrict__ diag, const double *b,
-                                                         const double *__restrict__ x, double *out)
+                                                         const double *__restrict__ x, double *out,
+                                                         const int32_t *done)
 {
+    if (done && *done) return;
     int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
     Vec1 xv{x};
@@ -197,8 +179,9 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sub(GridDev g, const double 
 // out = P_hat xc: the (up to) eight bracketing coarse nodes of each cell.
 __global__ __launch_bounds__(kBlock) void k_prolong(GridDev g, const double *__restrict__ P,
                                                      const uint8_t *__restrict__ dm, const double *__restrict__ xc,
-                                                     double *__restrict__ out)
+                                                     double *__restrict__ out, const int32_t *done)
 {
+    if (done && *done) return;
     int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
     double s = 0.0;
@@ -330,38 +313,46 @@ void launch_impose_wells(cams_ctx *c, double *p)
     k_impose_wells<<<grid_blocks(c->nwells), kBlock, 0, c->stream>>>(p, c->a.wcell, c->a.wp, c->nwells);
 }
 
-void launch_residual(cams_ctx *c, const double *dp_in, const double *a0, const double *a1, const double *a2,
-                     double *dp_out, double *r)
+void launch_stencil_sub(cams_ctx *c, const double *b, const double *x, double *out, const int32_t *done)
 {
-    VecSum v{dp_in, a0, a1, a2};
-    k_residual<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, r,
-                                                              c->a.partial);
+    k_stencil_sub<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, b, x, out, done);
 }
 
-void launch_stencil_sub(cams_ctx *c, const double *b, const double *x, double *out)
+void launch_prolong(cams_ctx *c, const double *xc, double *out, const int32_t *done)
 {
-    k_stencil_sub<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, b, x, out);
+    k_prolong<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.P, c->a.dmask, xc, out, done);
 }
 
-void launch_prolong(cams_ctx *c, const double *xc, double *out)
-{
-    k_prolong<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.P, c->a.dmask, xc, out);
-}
-
-void launch_ilu_setup(cams_ctx *c)
+void launch_rb_setup(cams_ctx *c)
 {
     k_ilu_setup<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd, c->a.status);
 }
 
+void launch_ilu_setup(cams_ctx *c)
+{
+    if (c->opt.smoother == CAMS_SMOOTH_RB_ILU0)
+        launch_rb_setup(c);
+    else
+        launch_bilu_setup(c);
+}
+
+void launch_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done)
+{
+    if (c->opt.smoother == CAMS_SMOOTH_RB_ILU0)
+        launch_rb_smooth(c, rhs, e, steps);   // the red-black path is host-controlled only
+    else
+        launch_bilu_smooth(c, rhs, e, steps, done);
+}
+
 // e = sum of `steps` ILU(0)-preconditioned Richardson steps on A e = rhs,
 // starting from e = 0:  e += M^{-1}(rhs - A e).
-void launch_smooth(cams_ctx *c, const double *rhs, double *e, int steps)
+void launch_rb_smooth(cams_ctx *c, const double *rhs, double *e, int steps)
 {
     const int nb = grid_blocks(c->g.N);
     for (int s = 0; s < steps; ++s) {
         const double *z = rhs;
         if (s > 0) {
-            k_stencil_sub<<<nb, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, rhs, e, c->a.z);
+            k_stencil_sub<<<nb, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, rhs, e, c->a.z, nullptr);
             z = c->a.z;
         }
         k_rb_black<<<nb, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.invd, z, c->a.x);

@@ -1,0 +1,185 @@
+// Iteration control of the C-AMS solve (Table "cams" steps 2 and 5) kept on
+// the device: the residual kernel computes r = r0 - A d, its norm, and the
+// stopping test; every later kernel of the iteration reads the resulting
+// `done` flag and returns at once after convergence.  The host can therefore
+// enqueue several iterations ahead and look at the flag only now and then.
+//
+// Reductions are two-stage and deterministic: workgroups write partials, a
+// later launch (one workgroup, or the consumer kernel itself) adds them in
+// index order.  Kernel boundaries order the stages; no workgroup uses a
+// device-scope fence (on a multi-XCD part that writes back the whole L2).
+#include "cams_internal.h"
+#include "dev_util.h"
+
+namespace cams {
+
+namespace {
+
+enum { C_IT = 0, C_DONE = 1, C_OUTCOME = 2, C_ARRIVE = 3, C_NODE = 4 };
+
+__global__ __launch_bounds__(kBlock) void k_iter_reset(int32_t *__restrict__ ictl, double *__restrict__ dp, int N,
+                                                        int nctl)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < N) dp[t] = 0.0;
+    if (t < nctl) ictl[t] = 0;
+}
+
+struct Pending {
+    const double *v0, *v1, *v2, *v3;
+    bool fold;
+    __device__ __forceinline__ double operator()(int m) const
+    {
+        double s = v0[m];
+        if (fold) {
+            if (v1) s += v1[m];
+            if (v2) s += v2[m];
+            if (v3) s += v3[m];
+        }
+        return s;
+    }
+};
+
+__global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double *__restrict__ W,
+                                                          const double *__restrict__ diag,
+                                                          const double *__restrict__ r0, Pending v,
+                                                          double *__restrict__ dp_out, double *__restrict__ r,
+                                                          double *__restrict__ partial, const int32_t *ictl)
+{
+    __shared__ double sh[kBlock / 64];
+    if (ictl[C_DONE]) return;
+    v.fold = ictl[C_IT] > 0;
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    double e2 = 0.0;
+    if (n < g.N) {
+        const Cell c = cell_of(g, n);
+        const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+        const double vn = v(n);
+        double s = diag[n] * vn;
+        if (c.i > 0) s -= Wx[n - 1] * v(n - 1);
+        if (c.i + 1 < g.nx) s -= Wx[n] * v(n + 1);
+        if (c.j > 0) s -= Wy[n - g.nx] * v(n - g.nx);
+        if (c.j + 1 < g.ny) s -= Wy[n] * v(n + g.nx);
+        if (c.k > 0) s -= Wz[n - g.sxy] * v(n - g.sxy);
+        if (c.k + 1 < g.nz) s -= Wz[n] * v(n + g.sxy);
+        const double rr = r0[n] - s;
+        r[n] = rr;
+        dp_out[n] = vn;
+        e2 = rr * rr;
+    }
+    const double bs = block_sum<kBlock>(e2, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+}
+
+// ||r||^2 from the residual kernel's partials and the stopping test.
+__global__ __launch_bounds__(kBlock) void k_finalize_ctl(const double *__restrict__ partial, int nparts,
+                                                          int32_t *ictl, double *scal, double rtol2, int maxit)
+{
+    __shared__ double sh[kBlock / 64];
+    if (ictl[C_DONE]) return;
+    double u = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += kBlock) u += partial[t];
+    const double s = block_sum<kBlock>(u, sh);
+    if (threadIdx.x == 0) {
+        const int it = ictl[C_IT];
+        if (it == 0) scal[S_R0N2] = s;
+        const double r0n2 = it == 0 ? s : scal[S_R0N2];
+        scal[S_RN2] = s;
+        if (!(s < 1e300)) {                      // NaN or Inf
+            ictl[C_OUTCOME] = 2;
+            ictl[C_DONE] = 1;
+        } else if (s <= rtol2 * r0n2 || r0n2 == 0.0) {
+            ictl[C_OUTCOME] = 0;
+            ictl[C_DONE] = 1;
+        } else if (it >= maxit) {
+            ictl[C_OUTCOME] = 1;
+            ictl[C_DONE] = 1;
+        } else {
+            ictl[C_IT] = it + 1;
+        }
+    }
+}
+
+// Restriction R r (Eq. (13)/(15)): one workgroup per (coarse node, z-plane of
+// its row's cells); a row box is at most 15 x 15 cells per plane (MSFE
+// support at ratio 8), covered by a 16 x 16 thread tile.  MSFV rows are the
+// primal block (weights 1); MSFE rows are the basis support (weights P_hat).
+// The coarse solve adds the plane sums of each row in order.
+__global__ __launch_bounds__(kBlock) void k_restrict_planes(GridDev g, const uint8_t *__restrict__ dm,
+                                                             const double *__restrict__ P, int fe,
+                                                             const double *__restrict__ r,
+                                                             double *__restrict__ planes, int max_planes,
+                                                             const int32_t *ictl)
+{
+    __shared__ double sh[kBlock / 64];
+    if (ictl[C_DONE]) return;
+    const int k = blockIdx.x, pz = blockIdx.y;
+    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        const int idx = a == 0 ? ka : (a == 1 ? kb : kc);
+        const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+        if (fe) {
+            lo[a] = idx > 0 ? g.vc[a][idx - 1] + 1 : 0;
+            hi[a] = idx < g.nb[a] - 1 ? g.vc[a][idx + 1] - 1 : n - 1;
+        } else {
+            lo[a] = idx * g.r[a];
+            hi[a] = min((idx + 1) * g.r[a], n) - 1;
+        }
+    }
+    const int nplanes = hi[2] - lo[2] + 1;
+    if (pz >= nplanes) {   // rows with fewer planes: the unused partials are zero
+        if (threadIdx.x == 0) planes[(size_t)k * max_planes + pz] = 0.0;
+        return;
+    }
+    const int x = lo[0] + (threadIdx.x & 15), y = lo[1] + (threadIdx.x >> 4), z = lo[2] + pz;
+    double v = 0.0;
+    if (x <= hi[0] && y <= hi[1]) {
+        const int n = x + g.nx * (y + g.ny * z);
+        if (fe) {
+            if (!dm[n]) {
+                const int sx = ka - g.lo[0][x], sy = kb - g.lo[1][y], sz = kc - g.lo[2][z];
+                if (sx >= 0 && sx <= 1 && sy >= 0 && sy <= 1 && sz >= 0 && sz <= 1)
+                    v = P[(size_t)(sx + 2 * sy + 4 * sz) * g.N + n] * r[n];
+            }
+        } else {
+            v = r[n];
+        }
+    }
+    const double s = block_sum<kBlock>(v, sh);
+    if (threadIdx.x == 0) planes[(size_t)k * max_planes + pz] = s;
+}
+
+}  // namespace
+
+void launch_iter_reset(cams_ctx *c)
+{
+    const int nctl = C_NODE + c->g.Nc;
+    const int n = c->g.N > nctl ? c->g.N : nctl;
+    k_iter_reset<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->a.ictl, c->a.dp[0], c->g.N, nctl);
+}
+
+void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, const double *a1, const double *a2,
+                         double *dp_out)
+{
+    Pending v{dp_in, a0, a1, a2, false};
+    k_residual_ctl<<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.r0, v,
+                                                                             dp_out, c->a.r, c->a.partial,
+                                                                             c->a.ictl);
+}
+
+void launch_finalize_ctl(cams_ctx *c)
+{
+    const double rt = c->opt.lin_rtol;
+    k_finalize_ctl<<<1, kBlock, 0, c->stream>>>(c->a.partial, (c->g.N + kBlock - 1) / kBlock, c->a.ictl, c->a.scal,
+                                                rt * rt, c->opt.lin_maxit);
+}
+
+void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *)
+{
+    dim3 grid(c->g.Nc, c->max_planes);
+    k_restrict_planes<<<grid, kBlock, 0, c->stream>>>(c->g, c->a.dmask, c->a.P, c->opt.restriction == CAMS_R_FE, r,
+                                                      c->a.planes, c->max_planes, c->a.ictl);
+}
+
+}  // namespace cams

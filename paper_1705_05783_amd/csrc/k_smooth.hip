@@ -1,0 +1,223 @@
+// Block-Jacobi ILU(0) smoother (Table "cams" step 6: n_s ILU(0) smoothing
+// steps).  The grid is cut into 8x8x8 cell blocks (8x8 in 2D; the last block
+// of an axis may be shorter).  Couplings across block faces are left out of
+// the factorisation, so every block is an independent ILU(0) in natural
+// order that one workgroup solves in LDS by hyperplane wavefronts
+// (i+j+k = const, 22 levels for a full block); the Richardson residual of
+// each step still uses the full matrix.
+//
+// For the 7-point matrix in natural order ILU(0) keeps the off-diagonals of
+// A and only modifies the diagonal: d_i = a_ii - sum_{j<i} W_ij^2 / d_j.
+// One application of M^{-1} z is then
+//   forward   y_i = (z_i + sum_{j<i} W_ij y_j) / d_i,
+//   backward  x_i = y_i + (sum_{j>i} W_ij x_j) / d_i.
+//
+// Workgroups are mapped XCD-aware: consecutive logical blocks (neighbours
+// along x, which share 128-byte lines of every array) are given to
+// workgroup ids that the dispatcher sends to the same XCD, so the shared
+// lines are fetched into one L2 instead of two.
+#include "cams_internal.h"
+#include "dev_util.h"
+
+namespace cams {
+
+namespace {
+
+constexpr int SB = 8;                 // block extent per active axis
+constexpr int ST = SB * SB * SB;      // one thread per cell
+
+// Bijection from the dispatch id to a logical block id such that each of the
+// 8 XCDs (which receive dispatch ids round-robin) works on one contiguous
+// range of logical blocks.
+__device__ __forceinline__ int xcd_swizzle(int wg, int n)
+{
+    const int q = n / 8, rem = n % 8;
+    const int xcd = wg % 8, slot = wg / 8;
+    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
+}
+
+struct BlockCell {
+    int n;          // global cell index
+    int t;          // local slot li + 8 lj + 64 lk
+    int li, lj, lk;
+    int ex, ey, ez; // block extents
+    int i, j, k;
+    bool active;
+};
+
+__device__ __forceinline__ BlockCell block_cell(const GridDev &g)
+{
+    BlockCell b;
+    const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
+    const int id = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
+    const int i0 = bx * SB, j0 = by * SB, k0 = bz * SB;
+    b.ex = min(SB, g.nx - i0);
+    b.ey = min(SB, g.ny - j0);
+    b.ez = min(SB, g.nz - k0);
+    b.t = threadIdx.x;
+    b.li = b.t & (SB - 1);
+    b.lj = (b.t >> 3) & (SB - 1);
+    b.lk = b.t >> 6;
+    b.active = b.li < b.ex && b.lj < b.ey && b.lk < b.ez;
+    b.i = i0 + b.li;
+    b.j = j0 + b.lj;
+    b.k = k0 + b.lk;
+    b.n = b.active ? b.i + g.nx * (b.j + g.ny * b.k) : 0;
+    return b;
+}
+
+// Pivots of the block ILU(0), once per assembled matrix.
+__global__ __launch_bounds__(ST) void k_bilu_setup(GridDev g, const double *__restrict__ W,
+                                                    const double *__restrict__ diag, double *__restrict__ invd,
+                                                    int32_t *status)
+{
+    __shared__ double d[ST];
+    const BlockCell b = block_cell(g);
+    const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    double dg = 1.0, wxm = 0.0, wym = 0.0, wzm = 0.0;
+    if (b.active) {
+        dg = diag[b.n];
+        if (b.li > 0) wxm = Wx[b.n - 1];
+        if (b.lj > 0) wym = Wy[b.n - g.nx];
+        if (b.lk > 0) wzm = Wz[b.n - g.sxy];
+    }
+    d[b.t] = 1.0;
+    __syncthreads();
+    const int lev = b.li + b.lj + b.lk;
+    const int nlev = b.ex + b.ey + b.ez - 2;
+    for (int l = 0; l < nlev; ++l) {
+        if (b.active && lev == l) {
+            double v = dg;
+            if (b.li > 0) v -= wxm * wxm / d[b.t - 1];
+            if (b.lj > 0) v -= wym * wym / d[b.t - SB];
+            if (b.lk > 0) v -= wzm * wzm / d[b.t - SB * SB];
+            if (!(v > 0.0)) {
+                atomicOr(status, F_BAD_PIVOT);
+                v = 1.0;
+            }
+            d[b.t] = v;
+        }
+        __syncthreads();
+    }
+    if (b.active) invd[b.n] = 1.0 / d[b.t];
+}
+
+// One Richardson step  e_new = e_old + M^{-1}(rhs - A e_old)  (e_old = 0 when
+// null) for one block.  All 512 threads stage the block in one memory round
+// trip (residual with the full matrix, pivots, in-block couplings) into LDS;
+// then the first wave alone sweeps the hyperplanes forward and backward,
+// one lane per x-pencil (so the sweeps need only wave-level ordering, no
+// workgroup barrier); finally all threads write the block back.  e_old and e_new must be different arrays: neighbouring blocks
+// read e_old across block faces.  Skipped once `done` (nullable) is set.
+__global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const double *__restrict__ W,
+                                                   const double *__restrict__ diag, const double *__restrict__ invd,
+                                                   const double *__restrict__ rhs, const double *__restrict__ eold,
+                                                   double *__restrict__ enew, const int32_t *done)
+{
+    // y and the +x/+y/+z couplings carry SB*SB zero entries on both sides, so
+    // the sweeps read neighbours without bounds tests: a coupling that leaves
+    // the block (or the grid) is zero, and its partner value is finite.
+    constexpr int PAD = SB * SB;
+    __shared__ double y[ST + 2 * PAD], wx[ST + 2 * PAD], wy[ST + 2 * PAD], wz[ST + 2 * PAD], dinv[ST];
+    if (done && *done) return;
+    const BlockCell b = block_cell(g);
+    const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    double z = 0.0, e0 = 0.0, id = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    if (b.active) {
+        const int n = b.n;
+        const double fxm = b.i > 0 ? Wx[n - 1] : 0.0, fxp = b.i + 1 < g.nx ? Wx[n] : 0.0;
+        const double fym = b.j > 0 ? Wy[n - g.nx] : 0.0, fyp = b.j + 1 < g.ny ? Wy[n] : 0.0;
+        const double fzm = b.k > 0 ? Wz[n - g.sxy] : 0.0, fzp = b.k + 1 < g.nz ? Wz[n] : 0.0;
+        z = rhs[n];
+        if (eold) {
+            e0 = eold[n];
+            double ae = diag[n] * e0;
+            if (b.i > 0) ae -= fxm * eold[n - 1];
+            if (b.i + 1 < g.nx) ae -= fxp * eold[n + 1];
+            if (b.j > 0) ae -= fym * eold[n - g.nx];
+            if (b.j + 1 < g.ny) ae -= fyp * eold[n + g.nx];
+            if (b.k > 0) ae -= fzm * eold[n - g.sxy];
+            if (b.k + 1 < g.nz) ae -= fzp * eold[n + g.sxy];
+            z -= ae;
+        }
+        id = invd[n];
+        // coupling to the +x/+y/+z neighbour when it lies in the block
+        fx = b.li + 1 < b.ex ? fxp : 0.0;
+        fy = b.lj + 1 < b.ey ? fyp : 0.0;
+        fz = b.lk + 1 < b.ez ? fzp : 0.0;
+    }
+    y[PAD + b.t] = z;
+    dinv[b.t] = id;
+    wx[PAD + b.t] = fx;
+    wy[PAD + b.t] = fy;
+    wz[PAD + b.t] = fz;
+    if (threadIdx.x < 2 * PAD) {
+        const int q = threadIdx.x < PAD ? threadIdx.x : ST + threadIdx.x;
+        y[q] = 0.0;
+        wx[q] = 0.0;
+        wy[q] = 0.0;
+        wz[q] = 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // lane owns the x-pencil (lj, lk) = (lane % 8, lane / 8); at time step
+        // tau it handles the cell li = tau - lj - lk of hyperplane tau
+        const int pj = threadIdx.x & (SB - 1), pk = threadIdx.x >> 3;
+        const bool pencil = pj < b.ey && pk < b.ez;
+        const int nlev = b.ex + b.ey + b.ez - 2;
+        const int base = PAD + SB * pj + SB * SB * pk;
+        for (int tau = 0; tau < nlev; ++tau) {
+            const int a = tau - pj - pk;
+            const bool act = pencil && a >= 0 && a < b.ex;
+            const int t = base + min(max(a, 0), SB - 1);
+            const double s = y[t] + wx[t - 1] * y[t - 1] + wy[t - SB] * y[t - SB] + wz[t - SB * SB] * y[t - SB * SB];
+            if (act) y[t] = s * dinv[t - PAD];
+            // LDS operations of one wave execute in order; keep the compiler
+            // from moving the next step's reads above this step's writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        for (int tau = nlev - 1; tau >= 0; --tau) {
+            const int a = tau - pj - pk;
+            const bool act = pencil && a >= 0 && a < b.ex;
+            const int t = base + min(max(a, 0), SB - 1);
+            const double s = wx[t] * y[t + 1] + wy[t] * y[t + SB] + wz[t] * y[t + SB * SB];
+            if (act) y[t] += s * dinv[t - PAD];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+    if (b.active) enew[b.n] = e0 + y[PAD + b.t];
+}
+
+inline int num_sblocks(const GridDev &g)
+{
+    return ((g.nx + SB - 1) / SB) * ((g.ny + SB - 1) / SB) * ((g.nz + SB - 1) / SB);
+}
+
+}  // namespace
+
+void launch_bilu_setup(cams_ctx *c)
+{
+    k_bilu_setup<<<num_sblocks(c->g), ST, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd, c->a.status);
+}
+
+// e = result of `steps` block-ILU(0) Richardson steps on A e = rhs from e = 0.
+// Ping-pong between e and the scratch vector so the last step writes e.
+void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done)
+{
+    const int nb = num_sblocks(c->g);
+    double *buf[2] = {e, c->a.z};
+    const double *prev = nullptr;
+    for (int s = 0; s < steps; ++s) {
+        double *out = buf[(steps - 1 - s) & 1];
+        k_bilu_step<<<nb, ST, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd, rhs, prev, out, done);
+        prev = out;
+    }
+}
+
+}  // namespace cams

@@ -33,6 +33,7 @@ class Solver:
         o = C.cams_options(overrides.get("restriction", problem.restriction),
                            overrides.get("n_pre", problem.n_pre), overrides.get("n_post", problem.n_post),
                            overrides.get("precision", problem.precision),
+                           overrides.get("smoother", getattr(problem, "smoother", C.CAMS_SMOOTH_BLOCK_ILU0)),
                            overrides.get("lin_rtol", problem.lin_rtol),
                            overrides.get("lin_maxit", problem.lin_maxit),
                            overrides.get("newton_tol", problem.newton_tol),

@@ -46,7 +46,7 @@ def _create(grid=None, fluid=None, opt=None):
     from paper_1705_05783_amd import _cams as C
     g = grid or C.cams_grid(16, 16, 8, 1.0, 1.0, 1.0, 4, 4, 4)
     f = fluid or C.cams_fluid(1.0, 0.1, 0.0, 1.0, 0.1)
-    o = opt or C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 1e-8, 100, 1e-8, 20)
+    o = opt or C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 0, 1e-8, 100, 1e-8, 20)
     h = ctypes.c_void_p()
     s = C.cams_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(o), None, ctypes.byref(h))
     return s, h
@@ -94,10 +94,10 @@ def test_create_rejects_bad_fluid(lib, field, value):
 
 @pytest.mark.parametrize("field,value", [("restriction", 3), ("n_post", -1), ("n_pre", 65),
                                          ("lin_rtol", 0.0), ("lin_maxit", 0), ("newton_maxit", 0),
-                                         ("precision", 7)])
+                                         ("precision", 7), ("smoother", 2)])
 def test_create_rejects_bad_options(lib, field, value):
     from paper_1705_05783_amd import _cams as C
-    o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 1e-8, 100, 1e-8, 20)
+    o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 0, 1e-8, 100, 1e-8, 20)
     setattr(o, field, value)
     s, h = _create(opt=o)
     assert s == C.CAMS_E_ARG

@@ -15,7 +15,7 @@ import pytest
 import oracle
 from tests.gpu_util import log, rel_err, require_gpu, solver_for, to_np
 from workloads import config1, config2, small_problem
-from workloads.configs import FE, FV
+from workloads.configs import FE, FV, SMOOTH_BLOCK, SMOOTH_REDBLACK
 
 pytestmark = pytest.mark.gpu
 
@@ -126,11 +126,13 @@ def test_matrix_core_gemm(_gpu, M, N, K):
     assert np.max(np.abs(to_np(Ct) - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()) * K
 
 
-@pytest.mark.parametrize("shape,r", SHAPES[:5])
-def test_smoother_apply(_gpu, shape, r):
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK])
+@pytest.mark.parametrize("shape,r", SHAPES[:5] + [((37, 29, 19), 4)])
+def test_smoother_apply(_gpu, shape, r, smoother):
     torch = _gpu
     pb = _pb(shape, r, sigma=2.0, seed=6)
-    log("case", pb.name)
+    pb.smoother = smoother
+    log("case", pb.name, "smoother", smoother)
     s = solver_for(pb)
     s.build_basis()
     rng = np.random.default_rng(12)
@@ -142,18 +144,20 @@ def test_smoother_apply(_gpu, shape, r):
     s.coarse_op()
     T = oracle.transmissibility(pb)
     W, diag, _, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
-    ilu = oracle.ILU0(pb, W, diag)          # red-black order
+    ilu = oracle.smoother_for(pb, W, diag)
     z = rng.normal(size=pb.n)
     z[~free] = 0.0
     x = to_np(s.smooth_apply(torch.as_tensor(z, device="cuda")))
     assert rel_err(x, ilu.apply(z)) <= 1e-12
 
 
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK])
 @pytest.mark.parametrize("restriction,n_pre", [(FE, 0), (FV, 0), (FV, 5)])
 @pytest.mark.parametrize("shape,r", [((16, 12, 8), 4), ((24, 24, 16), 8), ((20, 20, 1), 4)])
-def test_linear_solve(_gpu, shape, r, restriction, n_pre):
+def test_linear_solve(_gpu, shape, r, restriction, n_pre, smoother):
     torch = _gpu
     pb = _pb(shape, r, sigma=2.0, seed=7, restriction=restriction, n_pre=n_pre)
+    pb.smoother = smoother
     pb.lin_rtol = 1e-12
     log("case", pb.name, restriction, n_pre)
     s = solver_for(pb)
@@ -168,8 +172,8 @@ def test_linear_solve(_gpu, shape, r, restriction, n_pre):
     W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
     P = oracle.basis_b4(pb, T)
     LU, piv = oracle.lu_factor(oracle.coarse_operator(pb, W, diag, P, restriction))
-    d_ref, its, _ = oracle.cams_solve(pb, W, diag, P, restriction, LU, piv, oracle.ILU0(pb, W, diag), r0,
-                                      rtol=1e-12, maxit=500)
+    d_ref, its, _ = oracle.cams_solve(pb, W, diag, P, restriction, LU, piv, oracle.smoother_for(pb, W, diag),
+                                      r0, rtol=1e-12, maxit=500)
     log("iters gpu", st["lin_iters_last"], "oracle", its)
     assert its >= 0
     assert abs(st["lin_iters_last"] - its) <= 1
@@ -202,10 +206,14 @@ def test_newton_config1_2d_msfv(_gpu):
     _newton_parity(_gpu, config1())
 
 
-@pytest.mark.parametrize("shape,r,restriction", [((19, 17, 11), (4, 3, 5), FE), ((24, 24, 16), 8, FE),
-                                                  ((24, 24, 16), 8, FV), ((13, 11, 1), (3, 4, 1), FE)])
-def test_newton_3d(_gpu, shape, r, restriction):
+@pytest.mark.parametrize("shape,r,restriction,smoother", [((19, 17, 11), (4, 3, 5), FE, SMOOTH_BLOCK),
+                                                           ((24, 24, 16), 8, FE, SMOOTH_BLOCK),
+                                                           ((24, 24, 16), 8, FV, SMOOTH_BLOCK),
+                                                           ((24, 24, 16), 8, FE, SMOOTH_REDBLACK),
+                                                           ((13, 11, 1), (3, 4, 1), FE, SMOOTH_BLOCK)])
+def test_newton_3d(_gpu, shape, r, restriction, smoother):
     pb = _pb(shape, r, sigma=2.5, seed=8, restriction=restriction, c=0.08, dt=0.05)
+    pb.smoother = smoother
     _newton_parity(_gpu, pb)
 
 

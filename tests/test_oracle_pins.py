@@ -404,3 +404,31 @@ def test_3d_newton_matches_direct_newton_fe():
     assert rc == 0
     ref, _ = helpers.direct_newton(pb, T, p0, p0, tol=1e-12)
     assert np.max(np.abs(p - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+def test_block_ilu0_is_ilu0_of_the_block_diagonal_part():
+    """Block-Jacobi ILU(0): the factor reproduces, on its sparsity pattern,
+    the matrix with couplings across 8x8x8 block faces removed (built here
+    from geometry), and has no entry coupling two blocks."""
+    pb = small_problem(19, 17, 11, 4, sigma=2.0)
+    T = oracle.transmissibility(pb)
+    p = np.random.default_rng(8).uniform(0, 1, pb.n)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
+    ilu = oracle.ILU0(pb, W, diag, block=(8, 8, 8))
+    rp, col, val = ilu.export()
+    N = pb.n
+    F = sp.csr_matrix((val, col, rp), shape=(N, N)).toarray()
+    L = np.tril(F, -1) + np.eye(N)
+    U = np.triu(F)
+    A = helpers.stencil_matrix(pb, W, diag).toarray()
+    idx = np.arange(N)
+    i, j, k = idx % pb.nx, (idx // pb.nx) % pb.ny, idx // (pb.nx * pb.ny)
+    blk = (i // 8) + 100 * (j // 8) + 10000 * (k // 8)
+    same = blk[:, None] == blk[None, :]
+    Ab = np.where(same, A, 0.0)
+    pattern = Ab != 0
+    assert np.max(np.abs((L @ U - Ab)[pattern])) <= 1e-13 * np.abs(A).max()
+    assert np.all(F[~same] == 0)
+    z = np.random.default_rng(9).normal(size=N)
+    x = np.linalg.solve(U, np.linalg.solve(L, z))
+    assert np.allclose(ilu.apply(z), x, rtol=1e-11, atol=1e-13)

@@ -31,6 +31,9 @@ FP64 = 0
 MIXED_FP32 = 1
 MIXED_BF16 = 2
 
+SMOOTH_BLOCK = 0      # block-Jacobi ILU(0) on 8x8x8 blocks
+SMOOTH_REDBLACK = 1   # ILU(0) in red-black order
+
 
 @dataclasses.dataclass
 class Problem:
@@ -62,6 +65,7 @@ class Problem:
     newton_tol: float = 1e-8
     newton_maxit: int = 30
     precision: int = FP64
+    smoother: int = SMOOTH_BLOCK
 
     @property
     def n(self) -> int:
