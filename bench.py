@@ -7,7 +7,10 @@ dt = 0.05, each Newton iteration solving its linear system by C-AMS to a
 1e-8 relative residual (Newton to ||eps||_2 <= 1e-8).
 
 Metric: seconds per Newton linear solve = (timed wall time of K steps) /
-(number of Newton linear solves in them), inputs resident in HBM.
+(number of Newton linear solves in them), inputs resident in HBM.  The
+headline value is the mixed-precision solve (FP32 smoother, basis storage
+and prolongation; FP64 residual, update and coarse solve); the plain FP64
+solve of the same workload is timed beside it.
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -38,8 +41,6 @@ def _cpu_model():
 
 def run_workload(solver, pb, torch):
     """One pass of the whole hot path over the workload; returns stats."""
-    from paper_1705_05783_amd import _cams as C
-    import ctypes
     # new rock => transmissibilities and basis are rebuilt inside the step
     solver.reset_rock()
     pn = solver.new_pressure()
@@ -75,12 +76,49 @@ def cpu_baseline(pb):
                       f"{len(os.sched_getaffinity(0))} host cores available, oracle is single-threaded"}
 
 
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E
+
+
+def timed_run(pb, steps, warmup, torch):
+    """Warm up, then time `steps` whole-workload passes; the smoothing-step
+    kernel is timed by the library with HIP events on its stream."""
+    from paper_1705_05783_amd.solver import Solver
+    solver = Solver(pb, device=torch.device("cuda:0"))
+    for _ in range(warmup):
+        run_workload(solver, pb, torch)
+    torch.cuda.synchronize()
+    solver.profile()
+    t0 = time.perf_counter()
+    solves = iters = 0
+    for _ in range(steps):
+        s, i, _ = run_workload(solver, pb, torch)
+        solves += s
+        iters += i
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = solver.profile_read()
+    return {"elapsed": elapsed, "solves": solves, "iters": iters, "prof": prof, "Nc": solver.Nc}
+
+
+def roofline(prof):
+    if prof["launches"] == 0 or prof["total_ms"] <= 0:
+        return None
+    per_launch_bytes = prof["bytes"] / prof["launches"]
+    avg_s = prof["total_ms"] * 1e-3 / prof["launches"]
+    achieved = per_launch_bytes / avg_s / 1e9
+    return {"kernel": "k_bilu_step (block-ILU(0) Richardson step)", "bound": "hbm",
+            "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None, "avg_launch_us": avg_s * 1e6, "bytes_per_launch": per_launch_bytes,
+            "launches": prof["launches"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "plain", "both"], default="both")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -89,43 +127,51 @@ def main():
 
     import torch
     from workloads import config2
-    from paper_1705_05783_amd.solver import Solver
+    from workloads.configs import FP64, MIXED_FP32
 
+    runs = {}
+    if args.only in ("mixed", "both"):
+        runs["mixed"] = timed_run(config2(precision=MIXED_FP32), args.steps, args.warmup, torch)
+    if args.only in ("plain", "both"):
+        runs["plain"] = timed_run(config2(precision=FP64), args.steps, args.warmup, torch)
+    head = runs.get("mixed") or runs["plain"]
     pb = config2()
-    dev = torch.device("cuda:0")
-    solver = Solver(pb, device=dev)
-    for _ in range(args.warmup):
-        run_workload(solver, pb, torch)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solves = iters = 0
-    for _ in range(args.steps):
-        s, i, _ = run_workload(solver, pb, torch)
-        solves += s
-        iters += i
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = elapsed / max(solves, 1)
+
+    def summary(r):
+        return {"s_per_solve": r["elapsed"] / max(r["solves"], 1),
+                "ms_per_step": r["elapsed"] * 1e3 / args.steps,
+                "newton_solves_per_step": r["solves"] / args.steps,
+                "cams_iterations_per_solve": r["iters"] / max(r["solves"], 1),
+                "roofline_smoother": roofline(r["prof"])}
+
     out = {
         "metric": "s per Newton linear solve to 1e-8 rel. residual",
-        "value": value,
+        "value": head["elapsed"] / max(head["solves"], 1),
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["elapsed"] * 1e3 / args.steps,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if "mixed" in runs else "f64",
         "data": "synthetic",
-        "config": {"workload": "64x64x32 lognormal (sigma 3), coarsening 8^3, MSFE, 5 block-ILU(0) "
-                               "post-smoothing steps, 10 backward-Euler steps dt=0.05, FP64",
-                   "cells": pb.n, "coarse_nodes": solver.Nc,
-                   "newton_solves_per_step": solves / args.steps,
-                   "cams_iterations_per_solve": iters / max(solves, 1)},
+        "config": {"workload": "64x64x32 lognormal (sigma 3, corr. 8x8x2), coarsening 8^3 (256 coarse nodes), "
+                               "MSFE, 5 block-ILU(0) post-smoothing steps, 10 backward-Euler steps dt=0.05, "
+                               "Newton and linear solves to 1e-8; value = mixed precision (FP32 smoother, "
+                               "basis and prolongation, FP64 residual/update/coarse solve)" if "mixed" in runs
+                               else "64x64x32 workload, plain FP64",
+                   "cells": pb.n, "coarse_nodes": head["Nc"],
+                   "newton_solves_per_step": head["solves"] / args.steps,
+                   "cams_iterations_per_solve": head["iters"] / max(head["solves"], 1)},
+        "roofline": roofline(head["prof"]),
     }
+    for k, r in runs.items():
+        out[k] = summary(r)
+    if "mixed" in runs and "plain" in runs:
+        out["speedup_mixed_vs_plain_per_solve"] = (runs["plain"]["elapsed"] / runs["plain"]["solves"]) / \
+            (runs["mixed"]["elapsed"] / runs["mixed"]["solves"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
     print(json.dumps(out), flush=True)

@@ -54,10 +54,13 @@ typedef enum {
 /* Restriction operator (Sec. 3): finite volume, Eq. (7), or finite element R = P^T. */
 enum { CAMS_R_FV = 0, CAMS_R_FE = 1 };
 
-/* Arithmetic of the solve.  FP64: everything in double.  MIXED_FP32: matrix
- * copy, smoother, basis and prolongation in float with float accumulation;
- * residual, Newton update, norms and the coarse solve in double (iterative
- * refinement).  MIXED_BF16: as MIXED_FP32 but the basis stored in bfloat16. */
+/* Arithmetic of the solve.  FP64: everything in double.  MIXED_FP32: a float
+ * copy of the matrix and smoother pivots, the smoother, the basis storage and
+ * the prolongation in float with float accumulation; residual, Newton
+ * update, norms, coarse operator and coarse solve in double (iterative
+ * refinement on the FP64 residual).  The basis is computed in double and
+ * rounded once; the coarse operator and the restriction use the rounded
+ * basis.  MIXED_BF16: as MIXED_FP32 but the basis stored in bfloat16. */
 enum { CAMS_FP64 = 0, CAMS_MIXED_FP32 = 1, CAMS_MIXED_BF16 = 2 };
 
 /* ILU(0) smoother of Table "cams" step 6.  BLOCK: block-Jacobi ILU(0) in
@@ -107,7 +110,8 @@ typedef struct {
 /* Create a context for one grid.  Validates grid/fluid/options: active axes
  * >= 2 cells, 2 <= r <= 8 and r <= n per axis, vertex spacing >= 2 cells,
  * at most 32768 coarse nodes, dx,dy,dz,dt,mu,rho0 > 0, c >= 0, tolerances
- * > 0, precision CAMS_FP64.  `hip_stream` is a hipStream_t (NULL = default
+ * > 0; the mixed precisions need the block smoother.  `hip_stream` is a
+ * hipStream_t (NULL = default
  * stream).  Makes no HIP call (works without a GPU); on success *out owns
  * no device memory.  Release with cams_destroy.  Errors: CAMS_E_ARG,
  * CAMS_E_NOMEM (host allocation). */
@@ -212,6 +216,19 @@ cams_status cams_export(cams_ctx *ctx, cams_array which, void *dst_dev, size_t b
  * LU (Sec. 3, coarse solve of Eq. (15)).  Errors: CAMS_E_ARG, CAMS_E_DEVICE. */
 cams_status cams_debug_gemm_sub(cams_ctx *ctx, double *C_dev, const double *A_dev, const double *B_dev,
                                 int M, int Nn, int K);
+
+/* Measurement hook: time every launch of one kernel class with HIP events on
+ * the context's stream (kernel = CAMS_PROF_SMOOTH_STEP, the block-ILU(0)
+ * Richardson step of Table "cams" step 6; CAMS_PROF_NONE switches timing off
+ * and clears the totals).  To keep the event overhead out of the run, only
+ * the launches of every 16th C-AMS iteration are timed; launches that return
+ * early because the iteration had already converged are not counted.  cams_profile_read returns the
+ * summed device time in ms, the number of counted launches and their summed
+ * algorithmic bytes (each array read or written once per launch).
+ * Errors: CAMS_E_ARG, CAMS_E_DEVICE. */
+enum { CAMS_PROF_NONE = 0, CAMS_PROF_SMOOTH_STEP = 1 };
+cams_status cams_profile(cams_ctx *ctx, int kernel);
+cams_status cams_profile_read(cams_ctx *ctx, double *total_ms, int64_t *launches, double *bytes);
 
 /* Number of coarse nodes (product of ceil(n/r) per axis). */
 int64_t cams_num_coarse(const cams_ctx *ctx);

@@ -37,6 +37,9 @@ CAMS_ARR_AC = 5
 CAMS_ARR_AC_INV = 6
 CAMS_ARR_INVD = 7
 
+CAMS_PROF_NONE = 0
+CAMS_PROF_SMOOTH_STEP = 1
+
 
 class cams_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
@@ -87,6 +90,9 @@ _SIGS = [
     ("cams_export", _I, [_VP, _I, _VP, ctypes.c_size_t]),
     ("cams_num_coarse", ctypes.c_int64, [_VP]),
     ("cams_debug_gemm_sub", _I, [_VP, _VP, _VP, _VP, _I, _I, _I]),
+    ("cams_profile", _I, [_VP, _I]),
+    ("cams_profile_read", _I, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_double)]),
     ("cams_destroy", _I, [_VP]),
     ("cams_status_string", ctypes.c_char_p, [_I]),
     ("cams_last_error", ctypes.c_char_p, [_VP]),
@@ -149,6 +155,8 @@ cams_array_bytes = _fwd("cams_array_bytes")
 cams_export = _fwd("cams_export")
 cams_num_coarse = _fwd("cams_num_coarse")
 cams_debug_gemm_sub = _fwd("cams_debug_gemm_sub")
+cams_profile = _fwd("cams_profile")
+cams_profile_read = _fwd("cams_profile_read")
 cams_destroy = _fwd("cams_destroy")
 cams_status_string = _fwd("cams_status_string")
 cams_last_error = _fwd("cams_last_error")

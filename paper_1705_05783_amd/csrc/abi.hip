@@ -112,6 +112,53 @@ float elapsed_ms(cams_ctx *c, int a, int b)
 
 }  // namespace
 
+namespace cams {
+
+constexpr int kProfPairs = 4096;
+
+void prof_begin(cams_ctx *c, double bytes)
+{
+    if (c->prof_used >= kProfPairs) return;   // pool full until the next collection
+    if ((int)c->prof_ev.size() < 2 * (c->prof_used + 1)) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return;
+        if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return; }
+        c->prof_ev.push_back(e0);
+        c->prof_ev.push_back(e1);
+    }
+    if ((int)c->prof_tag.size() <= c->prof_used) {
+        c->prof_tag.push_back(0);
+        c->prof_bytes_pair.push_back(0.0);
+    }
+    c->prof_tag[c->prof_used] = c->prof_iter;
+    c->prof_bytes_pair[c->prof_used] = bytes;
+    (void)hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream);
+}
+
+void prof_end(cams_ctx *c)
+{
+    if (c->prof_used >= kProfPairs) return;
+    (void)hipEventRecord(c->prof_ev[2 * c->prof_used + 1], c->stream);
+    ++c->prof_used;
+}
+
+// After a stream synchronisation: add up the recorded pairs whose iteration
+// index is below `valid_below` (later ones returned early after convergence).
+static void prof_collect(cams_ctx *c, int valid_below)
+{
+    for (int q = 0; q < c->prof_used; ++q) {
+        if (c->prof_tag[q] >= valid_below) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->prof_ev[2 * q], c->prof_ev[2 * q + 1]) != hipSuccess) continue;
+        c->prof_ms += ms;
+        c->prof_bytes += c->prof_bytes_pair[q];
+        ++c->prof_launches;
+    }
+    c->prof_used = 0;
+}
+
+}  // namespace cams
+
 extern "C" {
 
 const char *cams_status_string(cams_status s)
@@ -160,8 +207,10 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     const cams_options &O = *opt;
     if (O.restriction != CAMS_R_FV && O.restriction != CAMS_R_FE) return CAMS_E_ARG;
     if (O.n_pre < 0 || O.n_pre > 64 || O.n_post < 0 || O.n_post > 64) return CAMS_E_ARG;
-    if (O.precision != CAMS_FP64) return CAMS_E_ARG;  // mixed precision: not in this library build
+    if (O.precision != CAMS_FP64 && O.precision != CAMS_MIXED_FP32 && O.precision != CAMS_MIXED_BF16)
+        return CAMS_E_ARG;
     if (O.smoother != CAMS_SMOOTH_BLOCK_ILU0 && O.smoother != CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
+    if (O.precision != CAMS_FP64 && O.smoother != CAMS_SMOOTH_BLOCK_ILU0) return CAMS_E_ARG;
     if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
     const int nb[3] = {num_blocks(n[0], r[0]), num_blocks(n[1], r[1]), num_blocks(n[2], r[2])};
     const double Nc = (double)nb[0] * nb[1] * nb[2];
@@ -306,6 +355,18 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
         c->max_planes = mp;
     }
     put(L.add(nc * (size_t)c->max_planes * 8));   // 32 restriction plane partials
+    const bool mixed = O.precision != CAMS_FP64;
+    const size_t n4 = mixed ? (size_t)g.N * 4 : 0;
+    put(L.add(3 * n4));        // 33 W32
+    put(L.add(n4));            // 34 diag32
+    put(L.add(n4));            // 35 invd32
+    put(L.add(O.precision == CAMS_MIXED_FP32 ? 8 * n4 : 0));   // 36 P32
+    put(L.add(O.precision == CAMS_MIXED_BF16 ? 4 * n4 : 0));   // 37 Pbf (8 x 2 bytes per cell)
+    put(L.add(n4));            // 38 r1f
+    put(L.add(n4));            // 39 d0f
+    put(L.add(n4));            // 40 d1f
+    put(L.add(n4));            // 41 d2f
+    put(L.add(n4));            // 42 zf
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
         return CAMS_E_NOMEM;
@@ -362,6 +423,16 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.slots = (double *)(w + off[30]);
     a.ictl = (int32_t *)(w + off[31]);
     a.planes = (double *)(w + off[32]);
+    a.W32 = (float *)(w + off[33]);
+    a.diag32 = (float *)(w + off[34]);
+    a.invd32 = (float *)(w + off[35]);
+    a.P32 = (float *)(w + off[36]);
+    a.Pbf = (uint16_t *)(w + off[37]);
+    a.r1f = (float *)(w + off[38]);
+    a.d0f = (float *)(w + off[39]);
+    a.d1f = (float *)(w + off[40]);
+    a.d2f = (float *)(w + off[41]);
+    a.zf = (float *)(w + off[42]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -486,6 +557,7 @@ cams_status cams_build_basis(cams_ctx *c)
     try {
         clear_status(c);
         launch_basis(c);
+        if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
         CAMS_HIP(hipGetLastError());
         int32_t flags = 0;
         sync_status(c, &flags);
@@ -507,6 +579,7 @@ cams_status cams_coarse_op(cams_ctx *c)
         clear_status(c);
         launch_coarse_operator(c);
         launch_ilu_setup(c);
+        if (c->opt.precision != CAMS_FP64) launch_convert_matrix32(c);
         launch_coarse_factor(c);
         CAMS_HIP(hipGetLastError());
         int32_t flags = 0;
@@ -541,9 +614,27 @@ cams_status cams_smooth_apply(cams_ctx *c, const double *z, double *x)
 // launches.
 static void enqueue_iteration(cams_ctx *c, int it)
 {
+    c->prof_iter = it;
     const cams_options &O = c->opt;
     Arrays &a = c->a;
     const int32_t *done = a.ictl + 1;
+    if (O.precision != CAMS_FP64) {
+        // FP64 residual and update; FP32 corrections (iterative refinement)
+        const float *pend0 = O.n_pre > 0 ? a.d0f : nullptr;
+        const float *pend2 = O.n_post > 0 ? a.d2f : nullptr;
+        launch_residual_ctl32(c, a.dp[it & 1], pend0, a.d1f, pend2, a.dp[(it + 1) & 1]);
+        launch_finalize_ctl(c);
+        if (O.n_pre > 0) {
+            launch_bilu_smooth32(c, (const double *)a.r, a.d0f, O.n_pre, done);
+            launch_sub64_lo(c, a.d0f, a.r, done);
+        }
+        launch_restrict_planes(c, a.r, done);
+        launch_gemv(c, a.rc, a.xc, done);
+        launch_prolong32(c, a.xc, a.d1f, done);
+        launch_r1_32(c, a.r, a.d1f, a.r1f, done);
+        if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done);
+        return;
+    }
     const double *pend0 = O.n_pre > 0 ? a.d0 : nullptr;
     const double *pend2 = O.n_post > 0 ? a.d2 : nullptr;
     launch_residual_ctl(c, a.dp[it & 1], pend0, a.d1, pend2, a.dp[(it + 1) & 1]);
@@ -606,6 +697,7 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
         launch_axpy(c, p_dev, a.dp[(it + 1) & 1], N);
         CAMS_HIP(hipGetLastError());
         CAMS_HIP(hipStreamSynchronize(c->stream));
+        if (c->prof_kernel) prof_collect(c, it);
     } catch (const HipError &e) {
         return fail(c, CAMS_E_DEVICE, std::string("iterate: ") + hipGetErrorString(e.code));
     }
@@ -729,10 +821,30 @@ cams_status cams_debug_gemm_sub(cams_ctx *c, double *C, const double *A, const d
     return CAMS_OK;
 }
 
+cams_status cams_profile(cams_ctx *c, int kernel)
+{
+    if (!c || (kernel != CAMS_PROF_NONE && kernel != CAMS_PROF_SMOOTH_STEP)) return CAMS_E_ARG;
+    c->prof_kernel = kernel;
+    c->prof_used = 0;
+    c->prof_ms = c->prof_bytes = 0.0;
+    c->prof_launches = 0;
+    return CAMS_OK;
+}
+
+cams_status cams_profile_read(cams_ctx *c, double *total_ms, int64_t *launches, double *bytes)
+{
+    if (!c || !total_ms || !launches || !bytes) return CAMS_E_ARG;
+    *total_ms = c->prof_ms;
+    *launches = c->prof_launches;
+    *bytes = c->prof_bytes;
+    return CAMS_OK;
+}
+
 cams_status cams_destroy(cams_ctx *c)
 {
     if (!c) return CAMS_E_ARG;
     if (c->host) (void)hipHostFree(c->host);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     for (int e = 0; e < 8; ++e)
         if (c->ev[e]) (void)hipEventDestroy(c->ev[e]);
     delete c;

@@ -70,7 +70,7 @@ struct Arrays {
     // mixed precision copies
     float *W32, *diag32, *invd32, *P32;
     uint16_t *Pbf;
-    float *r1f, *d1f, *d2f, *zf, *xf;
+    float *r1f, *d0f, *d1f, *d2f, *zf;
 };
 
 // Scalar slots in Arrays::scal.
@@ -110,6 +110,15 @@ struct cams_ctx {
     std::vector<int32_t> tab;
     std::vector<cams::Region> regions;
     size_t tab_off[3][4];
+    // timing of one kernel class for measurement (cams_profile)
+    int prof_kernel;
+    std::vector<hipEvent_t> prof_ev;        // pool: pairs (start, stop)
+    std::vector<int> prof_tag;              // iteration index of each pair
+    std::vector<double> prof_bytes_pair;    // algorithmic bytes of each pair
+    int prof_used;
+    int prof_iter;                          // iteration index being enqueued
+    double prof_ms, prof_bytes;
+    long long prof_launches;
     size_t off[48];         // workspace offsets (kMaxArrays entries)
 };
 
@@ -135,12 +144,31 @@ void launch_axpy(cams_ctx *c, double *y, const double *x, int n);
 void launch_bilu_setup(cams_ctx *c);
 void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done);
 
+void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done);
+void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done);
+
+// measurement hooks around the smoothing-step launches (abi.hip); only the
+// launches of every kProfEvery-th iteration are bracketed by events, which
+// keeps the event overhead out of the rest of the timed run
+constexpr int kProfEvery = 16;
+void prof_begin(cams_ctx *c, double bytes);
+void prof_end(cams_ctx *c);
+
+// ---- mixed precision (k_mixed.hip)
+void launch_convert_matrix32(cams_ctx *c);   // W, diag, invd -> FP32 copies
+void launch_round_basis(cams_ctx *c);        // P -> FP32 / BF16, P := the rounded values
+void launch_prolong32(cams_ctx *c, const double *xc, float *out, const int32_t *done);
+void launch_r1_32(cams_ctx *c, const double *r, const float *x, float *out, const int32_t *done);
+void launch_sub64_lo(cams_ctx *c, const float *x, double *r, const int32_t *done);
+
 // ---- iteration control (k_iter.hip)
 void launch_iter_reset(cams_ctx *c);
 // r = r0 - A v with v = dp_in (+ the pending corrections after the first
 // iteration), dp_out = v, ||r|| and the stopping test on the device
 void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, const double *a1, const double *a2,
                          double *dp_out);
+void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
+                           double *dp_out);
 void launch_finalize_ctl(cams_ctx *c);   // ||r||, stopping test, iteration counter
 void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *done);
 

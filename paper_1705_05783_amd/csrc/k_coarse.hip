@@ -217,11 +217,26 @@ __global__ __launch_bounds__(kBlock) void k_lu_panel_lds(double *__restrict__ A,
         if (pv == 0.0) pv = 1.0;  // flagged above; keep the arithmetic finite
         for (int i = cc + 1 + threadIdx.x; i < m; i += kBlock) Ps[i * ld + cc] /= pv;
         __syncthreads();
-        // rank-1 update: lane = column, waves stride over rows
+        // rank-1 update: lane = column, waves stride over rows; each chunk of
+        // eight rows is read before it is written so the LDS reads overlap
         const int c = cc + 1 + lane;
         if (c < nb) {
             const double u = Ps[cc * ld + c];
-            for (int i = cc + 1 + w; i < m; i += kBlock / 64) Ps[i * ld + c] -= Ps[i * ld + cc] * u;
+            constexpr int RS = kBlock / 64, CH = 8;
+            for (int i0 = cc + 1 + w; i0 < m; i0 += RS * CH) {
+                double l[CH], v[CH];
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    const int i = i0 + q * RS;
+                    l[q] = i < m ? Ps[i * ld + cc] : 0.0;
+                    v[q] = i < m ? Ps[i * ld + c] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    const int i = i0 + q * RS;
+                    if (i < m) Ps[i * ld + c] = v[q] - l[q] * u;
+                }
+            }
         }
         __syncthreads();
     }

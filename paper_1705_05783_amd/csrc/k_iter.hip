@@ -25,24 +25,29 @@ __global__ __launch_bounds__(kBlock) void k_iter_reset(int32_t *__restrict__ ict
     if (t < nctl) ictl[t] = 0;
 }
 
+// v0 + (v1 + v2 + v3 once `fold` is set); the pending corrections are FP64
+// or, in the mixed-precision solve, FP32.
+template <class TA>
 struct Pending {
-    const double *v0, *v1, *v2, *v3;
+    const double *v0;
+    const TA *v1, *v2, *v3;
     bool fold;
     __device__ __forceinline__ double operator()(int m) const
     {
         double s = v0[m];
         if (fold) {
-            if (v1) s += v1[m];
-            if (v2) s += v2[m];
-            if (v3) s += v3[m];
+            if (v1) s += (double)v1[m];
+            if (v2) s += (double)v2[m];
+            if (v3) s += (double)v3[m];
         }
         return s;
     }
 };
 
+template <class TA>
 __global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double *__restrict__ W,
                                                           const double *__restrict__ diag,
-                                                          const double *__restrict__ r0, Pending v,
+                                                          const double *__restrict__ r0, Pending<TA> v,
                                                           double *__restrict__ dp_out, double *__restrict__ r,
                                                           double *__restrict__ partial, const int32_t *ictl)
 {
@@ -162,10 +167,17 @@ void launch_iter_reset(cams_ctx *c)
 void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, const double *a1, const double *a2,
                          double *dp_out)
 {
-    Pending v{dp_in, a0, a1, a2, false};
-    k_residual_ctl<<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.r0, v,
-                                                                             dp_out, c->a.r, c->a.partial,
-                                                                             c->a.ictl);
+    Pending<double> v{dp_in, a0, a1, a2, false};
+    k_residual_ctl<double><<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, c->a.partial, c->a.ictl);
+}
+
+void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
+                           double *dp_out)
+{
+    Pending<float> v{dp_in, a0, a1, a2, false};
+    k_residual_ctl<float><<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, c->a.partial, c->a.ictl);
 }
 
 void launch_finalize_ctl(cams_ctx *c)

@@ -1,0 +1,153 @@
+// Mixed-precision pieces of the C-AMS solve: the smoother, the basis
+// storage and the prolongation run in FP32 (basis optionally in bfloat16)
+// with FP32 accumulation, while the residual r = r0 - A d, the update d, the
+// norms and the coarse solve stay in FP64.  The outer C-AMS iteration on the
+// FP64 residual is then an iterative refinement: it converges to the FP64
+// solution whenever the low-precision correction contracts the error.
+//
+// The rounded basis replaces the FP64 one everywhere (the coarse operator and
+// the restriction use exactly the prolongation that is applied), so the
+// multiscale stage stays a consistent Galerkin / finite-volume projection.
+#include "cams_internal.h"
+#include "dev_util.h"
+
+namespace cams {
+
+namespace {
+
+inline int blocks_of(size_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// float -> bfloat16, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, size_t n)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) dst[t] = (float)src[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_basis(double *__restrict__ P, float *__restrict__ P32,
+                                                         uint16_t *__restrict__ Pbf, size_t n, int bf16)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n) return;
+    const float f = (float)P[t];
+    if (bf16) {
+        const uint16_t b = to_bf16(f);
+        Pbf[t] = b;
+        P[t] = (double)from_bf16(b);
+    } else {
+        P32[t] = f;
+        P[t] = (double)f;
+    }
+}
+
+// out = P_hat xc in FP32 (basis stored as float or bfloat16).
+template <int BF>
+__global__ __launch_bounds__(kBlock) void k_prolong_lo(GridDev g, const float *__restrict__ P32,
+                                                        const uint16_t *__restrict__ Pbf,
+                                                        const uint8_t *__restrict__ dm, const double *__restrict__ xc,
+                                                        float *__restrict__ out, const int32_t *done)
+{
+    if (done && *done) return;
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    float s = 0.f;
+    if (!dm[n]) {
+        const Cell c = cell_of(g, n);
+        const int a = g.lo[0][c.i], b = g.lo[1][c.j], cc = g.lo[2][c.k];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const float w = BF ? from_bf16(Pbf[(size_t)t * g.N + n]) : P32[(size_t)t * g.N + n];
+            const int na = a + (t & 1), nb = b + ((t >> 1) & 1), nc = cc + ((t >> 2) & 1);
+            if (w != 0.f && na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2]) s += w * (float)xc[node_index(g, na, nb, nc)];
+        }
+    }
+    out[n] = s;
+}
+
+// out = r - A32 x in FP32 (r given in FP64).
+__global__ __launch_bounds__(kBlock) void k_r1_lo(GridDev g, const float *__restrict__ W, const float *__restrict__ diag,
+                                                   const double *__restrict__ r, const float *__restrict__ x,
+                                                   float *__restrict__ out, const int32_t *done)
+{
+    if (done && *done) return;
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const Cell c = cell_of(g, n);
+    const float *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    float s = diag[n] * x[n];
+    if (c.i > 0) s -= Wx[n - 1] * x[n - 1];
+    if (c.i + 1 < g.nx) s -= Wx[n] * x[n + 1];
+    if (c.j > 0) s -= Wy[n - g.nx] * x[n - g.nx];
+    if (c.j + 1 < g.ny) s -= Wy[n] * x[n + g.nx];
+    if (c.k > 0) s -= Wz[n - g.sxy] * x[n - g.sxy];
+    if (c.k + 1 < g.nz) s -= Wz[n] * x[n + g.sxy];
+    out[n] = (float)r[n] - s;
+}
+
+// r -= A x in FP64 with an FP32 correction x (pre-smoothing update).
+__global__ __launch_bounds__(kBlock) void k_sub64_lo(GridDev g, const double *__restrict__ W,
+                                                      const double *__restrict__ diag, const float *__restrict__ x,
+                                                      double *__restrict__ r, const int32_t *done)
+{
+    if (done && *done) return;
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    const Cell c = cell_of(g, n);
+    const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    double s = diag[n] * (double)x[n];
+    if (c.i > 0) s -= Wx[n - 1] * (double)x[n - 1];
+    if (c.i + 1 < g.nx) s -= Wx[n] * (double)x[n + 1];
+    if (c.j > 0) s -= Wy[n - g.nx] * (double)x[n - g.nx];
+    if (c.j + 1 < g.ny) s -= Wy[n] * (double)x[n + g.nx];
+    if (c.k > 0) s -= Wz[n - g.sxy] * (double)x[n - g.sxy];
+    if (c.k + 1 < g.nz) s -= Wz[n] * (double)x[n + g.sxy];
+    r[n] -= s;
+}
+
+}  // namespace
+
+void launch_convert_matrix32(cams_ctx *c)
+{
+    const size_t n = (size_t)c->g.N;
+    k_to_f32<<<blocks_of(3 * n), kBlock, 0, c->stream>>>(c->a.W, c->a.W32, 3 * n);
+    k_to_f32<<<blocks_of(n), kBlock, 0, c->stream>>>(c->a.diag, c->a.diag32, n);
+    k_to_f32<<<blocks_of(n), kBlock, 0, c->stream>>>(c->a.invd, c->a.invd32, n);
+}
+
+void launch_round_basis(cams_ctx *c)
+{
+    const size_t n = (size_t)c->g.N * 8;
+    k_round_basis<<<blocks_of(n), kBlock, 0, c->stream>>>(c->a.P, c->a.P32, c->a.Pbf, n,
+                                                          c->opt.precision == CAMS_MIXED_BF16);
+}
+
+void launch_prolong32(cams_ctx *c, const double *xc, float *out, const int32_t *done)
+{
+    if (c->opt.precision == CAMS_MIXED_BF16)
+        k_prolong_lo<1><<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.P32, c->a.Pbf, c->a.dmask, xc, out,
+                                                                      done);
+    else
+        k_prolong_lo<0><<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.P32, c->a.Pbf, c->a.dmask, xc, out,
+                                                                      done);
+}
+
+void launch_r1_32(cams_ctx *c, const double *r, const float *x, float *out, const int32_t *done)
+{
+    k_r1_lo<<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W32, c->a.diag32, r, x, out, done);
+}
+
+void launch_sub64_lo(cams_ctx *c, const float *x, double *r, const int32_t *done)
+{
+    k_sub64_lo<<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, x, r, done);
+}
+
+}  // namespace cams

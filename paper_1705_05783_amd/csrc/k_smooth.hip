@@ -110,29 +110,32 @@ __global__ __launch_bounds__(ST) void k_bilu_setup(GridDev g, const double *__re
 // one lane per x-pencil (so the sweeps need only wave-level ordering, no
 // workgroup barrier); finally all threads write the block back.  e_old and e_new must be different arrays: neighbouring blocks
 // read e_old across block faces.  Skipped once `done` (nullable) is set.
-__global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const double *__restrict__ W,
-                                                   const double *__restrict__ diag, const double *__restrict__ invd,
-                                                   const double *__restrict__ rhs, const double *__restrict__ eold,
-                                                   double *__restrict__ enew, const int32_t *done)
+// T: arithmetic and storage of the smoother (double, or float in the mixed
+// precision solve); TR: type of the right-hand side.
+template <class T, class TR>
+__global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
+                                                   const T *__restrict__ invd, const TR *__restrict__ rhs,
+                                                   const T *__restrict__ eold, T *__restrict__ enew,
+                                                   const int32_t *done)
 {
     // y and the +x/+y/+z couplings carry SB*SB zero entries on both sides, so
     // the sweeps read neighbours without bounds tests: a coupling that leaves
     // the block (or the grid) is zero, and its partner value is finite.
     constexpr int PAD = SB * SB;
-    __shared__ double y[ST + 2 * PAD], wx[ST + 2 * PAD], wy[ST + 2 * PAD], wz[ST + 2 * PAD], dinv[ST];
+    __shared__ T y[ST + 2 * PAD], wx[ST + 2 * PAD], wy[ST + 2 * PAD], wz[ST + 2 * PAD], dinv[ST];
     if (done && *done) return;
     const BlockCell b = block_cell(g);
-    const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
-    double z = 0.0, e0 = 0.0, id = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    const T *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    T z = 0, e0 = 0, id = 0, fx = 0, fy = 0, fz = 0;
     if (b.active) {
         const int n = b.n;
-        const double fxm = b.i > 0 ? Wx[n - 1] : 0.0, fxp = b.i + 1 < g.nx ? Wx[n] : 0.0;
-        const double fym = b.j > 0 ? Wy[n - g.nx] : 0.0, fyp = b.j + 1 < g.ny ? Wy[n] : 0.0;
-        const double fzm = b.k > 0 ? Wz[n - g.sxy] : 0.0, fzp = b.k + 1 < g.nz ? Wz[n] : 0.0;
-        z = rhs[n];
+        const T fxm = b.i > 0 ? Wx[n - 1] : T(0), fxp = b.i + 1 < g.nx ? Wx[n] : T(0);
+        const T fym = b.j > 0 ? Wy[n - g.nx] : T(0), fyp = b.j + 1 < g.ny ? Wy[n] : T(0);
+        const T fzm = b.k > 0 ? Wz[n - g.sxy] : T(0), fzp = b.k + 1 < g.nz ? Wz[n] : T(0);
+        z = (T)rhs[n];
         if (eold) {
             e0 = eold[n];
-            double ae = diag[n] * e0;
+            T ae = diag[n] * e0;
             if (b.i > 0) ae -= fxm * eold[n - 1];
             if (b.i + 1 < g.nx) ae -= fxp * eold[n + 1];
             if (b.j > 0) ae -= fym * eold[n - g.nx];
@@ -143,9 +146,9 @@ __global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const double *__res
         }
         id = invd[n];
         // coupling to the +x/+y/+z neighbour when it lies in the block
-        fx = b.li + 1 < b.ex ? fxp : 0.0;
-        fy = b.lj + 1 < b.ey ? fyp : 0.0;
-        fz = b.lk + 1 < b.ez ? fzp : 0.0;
+        fx = b.li + 1 < b.ex ? fxp : T(0);
+        fy = b.lj + 1 < b.ey ? fyp : T(0);
+        fz = b.lk + 1 < b.ez ? fzp : T(0);
     }
     y[PAD + b.t] = z;
     dinv[b.t] = id;
@@ -154,10 +157,10 @@ __global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const double *__res
     wz[PAD + b.t] = fz;
     if (threadIdx.x < 2 * PAD) {
         const int q = threadIdx.x < PAD ? threadIdx.x : ST + threadIdx.x;
-        y[q] = 0.0;
-        wx[q] = 0.0;
-        wy[q] = 0.0;
-        wz[q] = 0.0;
+        y[q] = 0;
+        wx[q] = 0;
+        wy[q] = 0;
+        wz[q] = 0;
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const double *__res
             const int a = tau - pj - pk;
             const bool act = pencil && a >= 0 && a < b.ex;
             const int t = base + min(max(a, 0), SB - 1);
-            const double s = y[t] + wx[t - 1] * y[t - 1] + wy[t - SB] * y[t - SB] + wz[t - SB * SB] * y[t - SB * SB];
+            const T s = y[t] + wx[t - 1] * y[t - 1] + wy[t - SB] * y[t - SB] + wz[t - SB * SB] * y[t - SB * SB];
             if (act) y[t] = s * dinv[t - PAD];
             // LDS operations of one wave execute in order; keep the compiler
             // from moving the next step's reads above this step's writes
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const double *__res
             const int a = tau - pj - pk;
             const bool act = pencil && a >= 0 && a < b.ex;
             const int t = base + min(max(a, 0), SB - 1);
-            const double s = wx[t] * y[t + 1] + wy[t] * y[t + SB] + wz[t] * y[t + SB * SB];
+            const T s = wx[t] * y[t + 1] + wy[t] * y[t + SB] + wz[t] * y[t + SB * SB];
             if (act) y[t] += s * dinv[t - PAD];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -206,18 +209,42 @@ void launch_bilu_setup(cams_ctx *c)
     k_bilu_setup<<<num_sblocks(c->g), ST, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd, c->a.status);
 }
 
-// e = result of `steps` block-ILU(0) Richardson steps on A e = rhs from e = 0.
-// Ping-pong between e and the scratch vector so the last step writes e.
-void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done)
+template <class T, class TR>
+void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR *rhs, T *e, T *scratch, int steps,
+                 const int32_t *done)
 {
     const int nb = num_sblocks(c->g);
-    double *buf[2] = {e, c->a.z};
-    const double *prev = nullptr;
+    T *buf[2] = {e, scratch};
+    const T *prev = nullptr;
+    // algorithmic bytes of a step: rhs, W (3), invd, e_new; plus diag and e_old after the first
+    const double n = (double)c->g.N;
     for (int s = 0; s < steps; ++s) {
-        double *out = buf[(steps - 1 - s) & 1];
-        k_bilu_step<<<nb, ST, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd, rhs, prev, out, done);
+        T *out = buf[(steps - 1 - s) & 1];
+        const double bytes = n * ((double)sizeof(TR) + 5.0 * sizeof(T) + (s > 0 ? 2.0 * sizeof(T) : 0.0));
+        const bool timed = c->prof_kernel == CAMS_PROF_SMOOTH_STEP && c->prof_iter % kProfEvery == 0;
+        if (timed) prof_begin(c, bytes);
+        k_bilu_step<T, TR><<<nb, ST, 0, c->stream>>>(c->g, W, diag, invd, rhs, prev, out, done);
+        if (timed) prof_end(c);
         prev = out;
     }
+}
+
+// e = result of `steps` block-ILU(0) Richardson steps on A e = rhs from e = 0.
+// Ping-pong between e and a scratch vector so the last step writes e.
+void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done)
+{
+    bilu_smooth<double, double>(c, c->a.W, c->a.diag, c->a.invd, rhs, e, c->a.z, steps, done);
+}
+
+// The same in FP32 (mixed precision), on the rounded matrix and pivots.
+void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done)
+{
+    bilu_smooth<float, float>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done);
+}
+
+void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done)
+{
+    bilu_smooth<float, double>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done);
 }
 
 }  // namespace cams

@@ -104,6 +104,16 @@ class Solver:
         C.check(C.cams_smooth_apply(self.ctx, _ptr(z), _ptr(x)), self.ctx, "cams_smooth_apply")
         return x
 
+    # ---- measurement
+    def profile(self, kernel=C.CAMS_PROF_SMOOTH_STEP):
+        C.check(C.cams_profile(self.ctx, kernel), self.ctx, "cams_profile")
+
+    def profile_read(self) -> dict:
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        C.check(C.cams_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)), self.ctx,
+                "cams_profile_read")
+        return {"total_ms": ms.value, "launches": n.value, "bytes": b.value}
+
     # ---- inspection
     def export(self, which: int) -> torch.Tensor:
         nbytes = C.cams_array_bytes(self.ctx, which)

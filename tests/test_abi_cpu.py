@@ -117,3 +117,20 @@ def test_null_arguments(lib):
     assert C.cams_create(None, None, None, None, None) == C.CAMS_E_ARG
     assert C.cams_destroy(None) == C.CAMS_E_ARG
     assert C.cams_workspace_bytes(None) == 0
+
+
+def test_mixed_precision_needs_block_smoother(lib):
+    from paper_1705_05783_amd import _cams as C
+    for prec in (C.CAMS_MIXED_FP32, C.CAMS_MIXED_BF16):
+        o = C.cams_options(C.CAMS_R_FE, 0, 5, prec, C.CAMS_SMOOTH_BLOCK_ILU0, 1e-8, 100, 1e-8, 20)
+        s, h = _create(opt=o)
+        assert s == C.CAMS_OK
+        n_mixed = C.cams_workspace_bytes(h)
+        C.cams_destroy(h)
+        o.smoother = C.CAMS_SMOOTH_RB_ILU0
+        s, h = _create(opt=o)
+        assert s == C.CAMS_E_ARG
+    o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 0, 1e-8, 100, 1e-8, 20)
+    s, h = _create(opt=o)
+    assert C.cams_workspace_bytes(h) < n_mixed
+    C.cams_destroy(h)

@@ -288,3 +288,55 @@ def test_determinism_bitwise(_gpu):
         s.newton_step(p.clone(), p)
         out.append(to_np(p))
     assert np.array_equal(out[0], out[1])
+
+
+# ---------------------------------------------------------------- mixed precision ----
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("shape,r,restriction", [((24, 24, 16), 8, FE), ((19, 17, 11), (4, 3, 5), FV),
+                                                  ((20, 20, 1), 4, FE)])
+def test_mixed_linear_solve_meets_fp64_residual(_gpu, shape, r, restriction, precision):
+    """Mixed FP32/BF16 smoother + prolongation with FP64 refinement: the
+    update satisfies the FP64 linear system to the requested 1e-8 relative
+    residual, recomputed independently by the oracle."""
+    torch = _gpu
+    pb = _pb(shape, r, sigma=2.5, seed=9, restriction=restriction)
+    pb.precision = precision
+    s = solver_for(pb)
+    s.build_basis()
+    p = pb.initial_pressure()
+    pt = torch.as_tensor(p, device="cuda")
+    s.assemble(pt, pt)
+    s.coarse_op()
+    st = s.iterate(pt)
+    T = oracle.transmissibility(pb)
+    W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
+    res = r0 - oracle.matvec(pb, W, diag, to_np(pt) - p)
+    rel = np.linalg.norm(res) / np.linalg.norm(r0)
+    log(pb.name, "precision", precision, "iters", st["lin_iters_last"], "relres", rel)
+    assert rel <= 1.05e-8
+    # the prolongation in use is the rounded basis (FP32 / BF16)
+    P = to_np(s.export(C.CAMS_ARR_P)).reshape(8, -1)
+    P_ref = oracle.basis_b4(pb, T)
+    tol = 2.0 ** -24 if precision == 1 else 2.0 ** -8
+    assert np.max(np.abs(P - P_ref)) <= tol
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_newton_matches_fp64_oracle(_gpu, precision):
+    """One time step of the 64x64x32 workload in mixed precision: the
+    oracle recomputes the nonlinear error of the GPU pressure (<= 1e-8) and
+    the pressure agrees with the FP64 oracle's."""
+    torch = _gpu
+    pb = config2(precision=precision)
+    s = solver_for(pb)
+    pn = pb.initial_pressure()
+    p_gpu = torch.as_tensor(pn, device="cuda")
+    st = s.newton_step(p_gpu.clone(), p_gpu)
+    log("config2 precision", precision, st)
+    T = oracle.transmissibility(pb)
+    _, e = oracle.nonlinear_residual(pb, T, to_np(p_gpu), pn)
+    assert e <= pb.newton_tol
+    p_ref, rc, ost = oracle.newton_step(pb, T, oracle.basis_b4(pb, T), pn, pn)
+    assert rc == 0
+    assert rel_err(to_np(p_gpu), p_ref) <= 1e-7
