@@ -221,14 +221,67 @@ cams_status cams_debug_gemm_sub(cams_ctx *ctx, double *C_dev, const double *A_de
  * the context's stream (kernel = CAMS_PROF_SMOOTH_STEP, the block-ILU(0)
  * Richardson step of Table "cams" step 6; CAMS_PROF_NONE switches timing off
  * and clears the totals).  To keep the event overhead out of the run, only
- * the launches of every 16th C-AMS iteration are timed; launches that return
- * early because the iteration had already converged are not counted.  cams_profile_read returns the
+ * the smoothing sequences of every 16th C-AMS iteration are timed, each as
+ * one bracket around its back-to-back launches (so the time includes the
+ * short gaps between them); iterations past convergence are not counted.  cams_profile_read returns the
  * summed device time in ms, the number of counted launches and their summed
  * algorithmic bytes (each array read or written once per launch).
  * Errors: CAMS_E_ARG, CAMS_E_DEVICE. */
 enum { CAMS_PROF_NONE = 0, CAMS_PROF_SMOOTH_STEP = 1 };
 cams_status cams_profile(cams_ctx *ctx, int kernel);
 cams_status cams_profile_read(cams_ctx *ctx, double *total_ms, int64_t *launches, double *bytes);
+
+/* ---- Learned basis (extension of the basis construction of Sec. 3) ------
+ * A 3D CNN maps the log-transmissibility patch of a full dual block (the
+ * 9x9x9 cells between and on its bounding vertex planes; ratio 8, 3D only)
+ * to the 8 basis values of its 7x7x7 interior cells; a softmax over the 8
+ * vertex channels makes the prediction a partition of unity.  Features:
+ * channel 0/1/2 = ln T on each patch cell's +x/+y/+z face (0 on the patch's
+ * last face of that axis), layout feat[b][c][x + 9(y + 9z)] float.  Network:
+ * conv3d 3->32, ReLU, 32->32, ReLU, 32->32, ReLU, 32->8, 3x3x3 kernels, zero
+ * padding; parameters one float vector, per layer W[tap][ci][co] (tap =
+ * 9(dz+1) + 3(dy+1) + (dx+1)) followed by the bias[co].  Outputs phi[b][s][p]
+ * (s = corner bx + 2by + 4bz of the block), targets tgt[b][s][x + 7(y + 7z)]
+ * over the interior cells.  All arrays are device memory, FP32. */
+
+/* Number of network parameters (64904). */
+int64_t cams_cnn_num_params(void);
+/* Scratch bytes the network calls below need for a batch of `batch` patches. */
+size_t cams_cnn_workspace_bytes(int32_t batch);
+/* phi = network(feat) for `batch` patches, on `stream` (hipStream_t).
+ * Errors: CAMS_E_ARG (null pointer, batch <= 0), CAMS_E_DEVICE. */
+cams_status cams_cnn_forward(void *stream, const float *params_dev, const float *feat_dev, int32_t batch,
+                             void *ws_dev, float *phi_dev);
+/* Mean-squared error of phi against tgt over the interior cells and 8 channels
+ * (written to *loss_dev, a device double) and its gradient wrt the
+ * parameters (grad_dev, cams_cnn_num_params floats); the project's own
+ * backward kernels.  Errors: CAMS_E_ARG, CAMS_E_DEVICE. */
+cams_status cams_cnn_loss_grad(void *stream, const float *params_dev, const float *feat_dev, const float *tgt_dev,
+                               int32_t batch, void *ws_dev, float *grad_dev, double *loss_dev);
+/* One bias-corrected Adam update of n parameters at step `step` (>= 1).
+ * Errors: CAMS_E_ARG, CAMS_E_DEVICE. */
+cams_status cams_cnn_adam(void *stream, float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                          int32_t n, int32_t step, float lr, float beta1, float beta2, float eps);
+/* Number of full dual blocks of the context (those the network handles). */
+int32_t cams_cnn_num_blocks(const cams_ctx *ctx);
+/* Training patches of the context: features of every full dual block, and
+ * (tgt_dev non-NULL, basis built) the exact basis values of its interior.
+ * Synchronises.  Errors: CAMS_E_ARG, CAMS_E_STATE (no rock / no basis). */
+cams_status cams_cnn_patches(cams_ctx *ctx, float *feat_dev, float *tgt_dev);
+/* Scratch bytes cams_set_learned needs for this context. */
+size_t cams_learned_scratch_bytes(const cams_ctx *ctx);
+/* Switch cams_build_basis to the learned interiors (params_dev non-NULL) or
+ * back to exact local solves (NULL).  Edges, faces and stub interiors stay
+ * exact; each predicted interior is checked with the local equation, and a
+ * block with ||(T Phi)_I|| / ||T_IF Phi_F|| > fallback_tol is re-solved
+ * exactly.  params_dev and scratch_dev (256-byte aligned) are borrowed until
+ * switched off.  Invalidates the basis.  Errors: CAMS_E_ARG (not 3D with
+ * ratio 8, scratch too small, fallback_tol <= 0). */
+cams_status cams_set_learned(cams_ctx *ctx, const float *params_dev, void *scratch_dev, size_t scratch_bytes,
+                             double fallback_tol);
+/* Blocks taken from the network and blocks re-solved by the fallback in the
+ * last cams_build_basis.  Errors: CAMS_E_ARG. */
+cams_status cams_basis_stats(const cams_ctx *ctx, int32_t *learned_blocks, int32_t *fallback_blocks);
 
 /* Number of coarse nodes (product of ceil(n/r) per axis). */
 int64_t cams_num_coarse(const cams_ctx *ctx);

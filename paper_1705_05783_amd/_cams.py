@@ -90,6 +90,17 @@ _SIGS = [
     ("cams_export", _I, [_VP, _I, _VP, ctypes.c_size_t]),
     ("cams_num_coarse", ctypes.c_int64, [_VP]),
     ("cams_debug_gemm_sub", _I, [_VP, _VP, _VP, _VP, _I, _I, _I]),
+    ("cams_cnn_num_params", ctypes.c_int64, []),
+    ("cams_cnn_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32]),
+    ("cams_cnn_forward", _I, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
+    ("cams_cnn_loss_grad", _I, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
+    ("cams_cnn_adam", _I, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                           ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    ("cams_cnn_num_blocks", ctypes.c_int32, [_VP]),
+    ("cams_cnn_patches", _I, [_VP, _VP, _VP]),
+    ("cams_learned_scratch_bytes", ctypes.c_size_t, [_VP]),
+    ("cams_set_learned", _I, [_VP, _VP, _VP, ctypes.c_size_t, ctypes.c_double]),
+    ("cams_basis_stats", _I, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     ("cams_profile", _I, [_VP, _I]),
     ("cams_profile_read", _I, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_double)]),
@@ -155,6 +166,16 @@ cams_array_bytes = _fwd("cams_array_bytes")
 cams_export = _fwd("cams_export")
 cams_num_coarse = _fwd("cams_num_coarse")
 cams_debug_gemm_sub = _fwd("cams_debug_gemm_sub")
+cams_cnn_num_params = _fwd("cams_cnn_num_params")
+cams_cnn_workspace_bytes = _fwd("cams_cnn_workspace_bytes")
+cams_cnn_forward = _fwd("cams_cnn_forward")
+cams_cnn_loss_grad = _fwd("cams_cnn_loss_grad")
+cams_cnn_adam = _fwd("cams_cnn_adam")
+cams_cnn_num_blocks = _fwd("cams_cnn_num_blocks")
+cams_cnn_patches = _fwd("cams_cnn_patches")
+cams_learned_scratch_bytes = _fwd("cams_learned_scratch_bytes")
+cams_set_learned = _fwd("cams_set_learned")
+cams_basis_stats = _fwd("cams_basis_stats")
 cams_profile = _fwd("cams_profile")
 cams_profile_read = _fwd("cams_profile_read")
 cams_destroy = _fwd("cams_destroy")

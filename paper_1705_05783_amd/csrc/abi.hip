@@ -116,7 +116,7 @@ namespace cams {
 
 constexpr int kProfPairs = 4096;
 
-void prof_begin(cams_ctx *c, double bytes)
+void prof_begin(cams_ctx *c, double bytes, int launches)
 {
     if (c->prof_used >= kProfPairs) return;   // pool full until the next collection
     if ((int)c->prof_ev.size() < 2 * (c->prof_used + 1)) {
@@ -129,9 +129,11 @@ void prof_begin(cams_ctx *c, double bytes)
     if ((int)c->prof_tag.size() <= c->prof_used) {
         c->prof_tag.push_back(0);
         c->prof_bytes_pair.push_back(0.0);
+        c->prof_count_pair.push_back(0);
     }
     c->prof_tag[c->prof_used] = c->prof_iter;
     c->prof_bytes_pair[c->prof_used] = bytes;
+    c->prof_count_pair[c->prof_used] = launches;
     (void)hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream);
 }
 
@@ -152,9 +154,66 @@ static void prof_collect(cams_ctx *c, int valid_below)
         if (hipEventElapsedTime(&ms, c->prof_ev[2 * q], c->prof_ev[2 * q + 1]) != hipSuccess) continue;
         c->prof_ms += ms;
         c->prof_bytes += c->prof_bytes_pair[q];
-        ++c->prof_launches;
+        c->prof_launches += c->prof_count_pair[q];
     }
     c->prof_used = 0;
+}
+
+// Learned scratch layout: [feat | phi | ratio | fallback regions | network workspace (chunk)].
+static int learned_chunk(const cams_ctx *c) { return std::min(c->nfull, 1024); }
+
+static size_t learned_scratch_need(const cams_ctx *c)
+{
+    const size_t nf = (size_t)c->nfull, ch = (size_t)learned_chunk(c);
+    return align_up(nf * 3 * 729 * 4) + align_up(nf * 8 * 729 * 4) + align_up(nf * 8) +
+           align_up(nf * sizeof(Region)) + align_up(cnn_workspace_floats((int)std::max<size_t>(ch, 1)) * 4);
+}
+
+// Basis with the network predicting the interiors of full dual blocks:
+// vertices, edges and faces exact; stub interiors exact; full interiors from
+// the network, then the local-equation check and exact re-solves of the
+// blocks whose ratio exceeds fallback_tol.
+static void build_basis_learned(cams_ctx *c)
+{
+    char *s = c->learned_scratch;
+    const size_t nf = (size_t)c->nfull;
+    float *feat = (float *)s;
+    s += align_up(nf * 3 * 729 * 4);
+    float *phi = (float *)s;
+    s += align_up(nf * 8 * 729 * 4);
+    double *ratio = (double *)s;
+    s += align_up(nf * 8);
+    Region *fb = (Region *)s;
+    s += align_up(nf * sizeof(Region));
+    float *ws = (float *)s;
+    launch_basis_vertices(c);
+    for (int nfree = 1; nfree <= 2; ++nfree)
+        launch_basis_regions(c, nfree, c->a.regions + c->regoff[nfree], c->nreg[nfree]);
+    const Region *full = c->a.regions + c->regoff[3];
+    launch_basis_regions(c, 3, full + c->nfull, c->nreg[3] - c->nfull);   // stubs
+    cnn_features(c, full, c->nfull, feat);
+    const int ch = learned_chunk(c);
+    for (int b0 = 0; b0 < c->nfull; b0 += ch) {
+        const int nb = std::min(ch, c->nfull - b0);
+        cnn_forward(c->stream, c->learned_params, feat + (size_t)b0 * 3 * 729, nb, ws, phi + (size_t)b0 * 8 * 729);
+    }
+    cnn_scatter(c, full, c->nfull, phi);
+    cnn_block_residual(c, full, c->nfull, ratio);
+    std::vector<double> r(nf);
+    CAMS_HIP(hipMemcpyAsync(r.data(), ratio, nf * 8, hipMemcpyDeviceToHost, c->stream));
+    CAMS_HIP(hipStreamSynchronize(c->stream));
+    std::vector<Region> host_full(c->regions.begin() + c->regoff[3], c->regions.begin() + c->regoff[3] + c->nfull);
+    c->fallback_list.clear();
+    for (size_t b = 0; b < nf; ++b)
+        if (!(r[b] <= c->fallback_tol)) c->fallback_list.push_back(host_full[b]);
+    c->learned_blocks = c->nfull - (int)c->fallback_list.size();
+    c->fallback_blocks = (int)c->fallback_list.size();
+    if (!c->fallback_list.empty()) {
+        CAMS_HIP(hipMemcpyAsync(fb, c->fallback_list.data(), c->fallback_list.size() * sizeof(Region),
+                                hipMemcpyHostToDevice, c->stream));
+        launch_basis_regions(c, 3, fb, (int)c->fallback_list.size());
+        CAMS_HIP(hipStreamSynchronize(c->stream));   // the host list must outlive the copy
+    }
 }
 
 }  // namespace cams
@@ -283,6 +342,13 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
                 R.pad = 0;
                 by[nf].push_back(R);
             }
+    // interiors that are full dual blocks (7x7x7 at ratio 8) first: the
+    // learned basis predicts exactly those
+    std::stable_partition(by[3].begin(), by[3].end(),
+                          [](const Region &R) { return R.len[0] == 7 && R.len[1] == 7 && R.len[2] == 7; });
+    c->nfull = 0;
+    for (const Region &R : by[3])
+        if (R.len[0] == 7 && R.len[1] == 7 && R.len[2] == 7) ++c->nfull;
     int off = 0;
     for (int f = 0; f < 4; ++f) {
         c->nreg[f] = (int)by[f].size();
@@ -367,6 +433,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     put(L.add(n4));            // 40 d1f
     put(L.add(n4));            // 41 d2f
     put(L.add(n4));            // 42 zf
+    put(L.add((size_t)2 * ((nc + 63) / 64) * 64 * 64 * 8));   // 43 coarse LU block inverses
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
         return CAMS_E_NOMEM;
@@ -433,6 +500,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.d1f = (float *)(w + off[40]);
     a.d2f = (float *)(w + off[41]);
     a.zf = (float *)(w + off[42]);
+    a.tri = (double *)(w + off[43]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -556,7 +624,12 @@ cams_status cams_build_basis(cams_ctx *c)
     if (!c->has_rock) return fail(c, CAMS_E_STATE, "build_basis before set_rock");
     try {
         clear_status(c);
-        launch_basis(c);
+        c->learned_blocks = c->fallback_blocks = 0;
+        if (c->learned_params && c->nfull > 0) {
+            build_basis_learned(c);
+        } else {
+            launch_basis(c);
+        }
         if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
         CAMS_HIP(hipGetLastError());
         int32_t flags = 0;
@@ -818,6 +891,83 @@ cams_status cams_debug_gemm_sub(cams_ctx *c, double *C, const double *A, const d
     } catch (const HipError &e) {
         return fail(c, CAMS_E_DEVICE, std::string("gemm: ") + hipGetErrorString(e.code));
     }
+    return CAMS_OK;
+}
+
+int64_t cams_cnn_num_params(void) { return (int64_t)cnn_num_params(); }
+
+size_t cams_cnn_workspace_bytes(int32_t batch) { return batch > 0 ? cnn_workspace_floats(batch) * 4 : 0; }
+
+cams_status cams_cnn_forward(void *stream, const float *params, const float *feat, int32_t batch, void *ws,
+                             float *phi)
+{
+    if (!params || !feat || !ws || !phi || batch <= 0) return CAMS_E_ARG;
+    cnn_forward((hipStream_t)stream, params, feat, batch, (float *)ws, phi);
+    return hipGetLastError() == hipSuccess ? CAMS_OK : CAMS_E_DEVICE;
+}
+
+cams_status cams_cnn_loss_grad(void *stream, const float *params, const float *feat, const float *target,
+                               int32_t batch, void *ws, float *grad, double *loss)
+{
+    if (!params || !feat || !target || !ws || !grad || !loss || batch <= 0) return CAMS_E_ARG;
+    cnn_loss_grad((hipStream_t)stream, params, feat, target, batch, (float *)ws, grad, loss);
+    return hipGetLastError() == hipSuccess ? CAMS_OK : CAMS_E_DEVICE;
+}
+
+cams_status cams_cnn_adam(void *stream, float *params, const float *grad, float *m, float *v, int32_t n,
+                          int32_t step, float lr, float beta1, float beta2, float eps)
+{
+    if (!params || !grad || !m || !v || n <= 0 || step < 1) return CAMS_E_ARG;
+    cnn_adam((hipStream_t)stream, params, grad, m, v, n, step, lr, beta1, beta2, eps);
+    return hipGetLastError() == hipSuccess ? CAMS_OK : CAMS_E_DEVICE;
+}
+
+int32_t cams_cnn_num_blocks(const cams_ctx *c) { return c ? c->nfull : 0; }
+
+cams_status cams_cnn_patches(cams_ctx *c, float *feat, float *target)
+{
+    if (!c || !feat) return CAMS_E_ARG;
+    if (!c->has_rock) return fail(c, CAMS_E_STATE, "patches before set_rock");
+    if (target && !c->has_basis) return fail(c, CAMS_E_STATE, "targets need a built basis");
+    try {
+        const Region *full = c->a.regions + c->regoff[3];
+        cnn_features(c, full, c->nfull, feat);
+        if (target) cnn_targets(c, full, c->nfull, target);
+        CAMS_HIP(hipGetLastError());
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("cnn_patches: ") + hipGetErrorString(e.code));
+    }
+    return CAMS_OK;
+}
+
+size_t cams_learned_scratch_bytes(const cams_ctx *c) { return c ? learned_scratch_need(c) : 0; }
+
+cams_status cams_set_learned(cams_ctx *c, const float *params, void *scratch, size_t bytes, double fallback_tol)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!params) {
+        c->learned_params = nullptr;
+        c->has_basis = c->has_coarse = false;
+        return CAMS_OK;
+    }
+    if (c->g.dim != 3 || c->g.r[0] != 8 || c->g.r[1] != 8 || c->g.r[2] != 8)
+        return fail(c, CAMS_E_ARG, "the learned basis needs coarsening ratio 8 on a 3D grid");
+    if (!scratch || ((uintptr_t)scratch) % kAlign || bytes < learned_scratch_need(c) || !(fallback_tol > 0))
+        return fail(c, CAMS_E_ARG, "learned basis: scratch missing, misaligned or too small, or bad tolerance");
+    c->learned_params = params;
+    c->learned_scratch = (char *)scratch;
+    c->learned_scratch_bytes = bytes;
+    c->fallback_tol = fallback_tol;
+    c->has_basis = c->has_coarse = false;
+    return CAMS_OK;
+}
+
+cams_status cams_basis_stats(const cams_ctx *c, int32_t *learned_blocks, int32_t *fallback_blocks)
+{
+    if (!c || !learned_blocks || !fallback_blocks) return CAMS_E_ARG;
+    *learned_blocks = c->learned_blocks;
+    *fallback_blocks = c->fallback_blocks;
     return CAMS_OK;
 }
 

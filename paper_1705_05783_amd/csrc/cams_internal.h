@@ -53,6 +53,7 @@ struct Arrays {
     double *d0, *d1, *d2, *z, *x, *invd;
     double *P;        // 8N slot-major
     double *Ac, *Ainv, *work; // Nc*Nc each
+    double *tri;      // inverses of the 64x64 diagonal blocks of the coarse LU (2 per panel)
     double *rc, *xc;  // Nc
     double *partial;  // reduction partials
     double *slots;    // Nc*8 restriction slot sums
@@ -92,6 +93,14 @@ struct cams_ctx {
     int regoff[4];
     int region_total;
     int maxm[4], maxbw[4];  // largest local system per stage
+    int nfull;              // interior regions that are full 7x7x7 dual blocks (listed first)
+    // learned basis: network parameters and scratch (caller-owned), settings, counters
+    const float *learned_params;
+    char *learned_scratch;
+    size_t learned_scratch_bytes;
+    double fallback_tol;
+    int learned_blocks, fallback_blocks;
+    std::vector<cams::Region> fallback_list;
     size_t need;
     char *ws;
     size_t ws_bytes;
@@ -115,6 +124,7 @@ struct cams_ctx {
     std::vector<hipEvent_t> prof_ev;        // pool: pairs (start, stop)
     std::vector<int> prof_tag;              // iteration index of each pair
     std::vector<double> prof_bytes_pair;    // algorithmic bytes of each pair
+    std::vector<int> prof_count_pair;       // kernel launches inside each pair
     int prof_used;
     int prof_iter;                          // iteration index being enqueued
     double prof_ms, prof_bytes;
@@ -151,7 +161,7 @@ void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, c
 // launches of every kProfEvery-th iteration are bracketed by events, which
 // keeps the event overhead out of the rest of the timed run
 constexpr int kProfEvery = 16;
-void prof_begin(cams_ctx *c, double bytes);
+void prof_begin(cams_ctx *c, double bytes, int launches);
 void prof_end(cams_ctx *c);
 
 // ---- mixed precision (k_mixed.hip)
@@ -174,6 +184,21 @@ void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *done);
 
 // ---- basis (k_basis.hip)
 void launch_basis(cams_ctx *c);
+void launch_basis_vertices(cams_ctx *c);
+void launch_basis_regions(cams_ctx *c, int nfree, const Region *regs, int count);
+
+// ---- learned basis network (k_cnn.hip)
+size_t cnn_num_params();
+size_t cnn_workspace_floats(int B);
+void cnn_forward(hipStream_t st, const float *params, const float *feat, int B, float *ws, float *phi_out);
+void cnn_loss_grad(hipStream_t st, const float *params, const float *feat, const float *target, int B, float *ws,
+                   float *grad, double *loss_out);
+void cnn_adam(hipStream_t st, float *p, const float *g, float *m, float *v, int n, int t, float lr, float b1,
+              float b2, float eps);
+void cnn_features(cams_ctx *c, const Region *regs, int nblk, float *feat);
+void cnn_targets(cams_ctx *c, const Region *regs, int nblk, float *tgt);
+void cnn_scatter(cams_ctx *c, const Region *regs, int nblk, const float *phi);
+void cnn_block_residual(cams_ctx *c, const Region *regs, int nblk, double *ratio);
 
 // ---- coarse level (k_coarse.hip)
 void launch_coarse_operator(cams_ctx *c);

@@ -152,23 +152,32 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
 
 }  // namespace
 
-void launch_basis(cams_ctx *c)
+void launch_basis_vertices(cams_ctx *c)
 {
     const GridDev &g = c->g;
     k_basis_vertices<<<(g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(g, c->a.P);
+}
+
+// Exact local solves of `count` regions with `nfree` open axes.
+void launch_basis_regions(cams_ctx *c, int nfree, const Region *regs, int count)
+{
+    if (count <= 0) return;
+    const GridDev &g = c->g;
     constexpr int E = kMaxRatio - 1;
-    for (int nfree = 1; nfree <= g.dim; ++nfree) {
-        const int nr = c->nreg[nfree];
-        if (nr == 0) continue;
-        const Region *regs = c->a.regions + c->regoff[nfree];
-        if (nfree == 1)
-            k_basis_region<64, E, 1><<<nr, 64, 0, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status);
-        else if (nfree == 2)
-            k_basis_region<kBlock, E * E, E><<<nr, kBlock, 0, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status);
-        else
-            k_basis_region<kBlock, E * E * E, E * E><<<nr, kBlock, 0, c->stream>>>(g, c->a.T, regs, c->a.P,
-                                                                                c->a.status);
-    }
+    if (nfree == 1)
+        k_basis_region<64, E, 1><<<count, 64, 0, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status);
+    else if (nfree == 2)
+        k_basis_region<kBlock, E * E, E><<<count, kBlock, 0, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status);
+    else
+        k_basis_region<kBlock, E * E * E, E * E><<<count, kBlock, 0, c->stream>>>(g, c->a.T, regs, c->a.P,
+                                                                            c->a.status);
+}
+
+void launch_basis(cams_ctx *c)
+{
+    launch_basis_vertices(c);
+    for (int nfree = 1; nfree <= c->g.dim; ++nfree)
+        launch_basis_regions(c, nfree, c->a.regions + c->regoff[nfree], c->nreg[nfree]);
 }
 
 }  // namespace cams

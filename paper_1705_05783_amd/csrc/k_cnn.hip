@@ -1,0 +1,480 @@
+// Learned basis (extension of the B4 basis construction, Sec. 3): a 3D CNN
+// maps the log-transmissibility patch of a full dual block (9x9x9 cells, the
+// block and its bounding vertex planes) to the 8 basis values of its 7x7x7
+// interior cells; a softmax over the 8 vertex channels gives a partition of
+// unity by construction.  Edges and faces stay exact (cheap 1D/2D solves),
+// so neighbouring blocks agree on shared entities; interiors whose
+// local-equation residual is too large fall back to the exact solve.
+//
+// Layout: activations channel-major per patch x[b][c][p], p = x + 9(y + 9z);
+// weights W[tap][ci][co], tap = 9(dz+1) + 3(dy+1) + (dx+1); the convolution is
+// out[b][co][p] = bias[co] + sum_{tap,ci} W[tap][ci][co] x[b][ci][p + d(tap)]
+// with zero padding.  Network: conv 3->32, ReLU, 32->32, ReLU, 32->32, ReLU,
+// 32->8, softmax.  FP32 storage and accumulation.
+#include "cams_internal.h"
+#include "dev_util.h"
+
+namespace cams {
+
+namespace {
+
+constexpr int PD = 9;                 // patch extent
+constexpr int PP = PD * PD * PD;      // 729 positions
+constexpr int CT = 256;               // threads per workgroup
+constexpr int COG = 8;                // output channels per workgroup
+constexpr int MAXC = 32;
+
+__device__ __forceinline__ int nb_pos(int p, int tap)
+{
+    const int x = p % PD, y = (p / PD) % PD, z = p / (PD * PD);
+    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+    const int X = x + dx, Y = y + dy, Z = z + dz;
+    if (X < 0 || X >= PD || Y < 0 || Y >= PD || Z < 0 || Z >= PD) return -1;
+    return X + PD * (Y + PD * Z);
+}
+
+// out[b][co][p] (8 channels co0..co0+7 per workgroup) = bias + conv(x), then
+// optional ReLU, optional multiplication by (mask[b][co][p] > 0).
+__global__ __launch_bounds__(CT) void k_conv_fwd(const float *__restrict__ x, int Ci, const float *__restrict__ W,
+                                                  const float *__restrict__ bias, int Co, float *__restrict__ out,
+                                                  int relu, const float *__restrict__ mask)
+{
+    __shared__ float xs[MAXC * PP];
+    __shared__ float ws[27 * MAXC * COG];
+    const int b = blockIdx.x, co0 = blockIdx.y * COG;
+    const int nco = min(COG, Co - co0);
+    const float *xb = x + (size_t)b * Ci * PP;
+    for (int t = threadIdx.x; t < Ci * PP; t += CT) xs[t] = xb[t];
+    for (int t = threadIdx.x; t < 27 * Ci * COG; t += CT) {
+        const int j = t % COG, ci = (t / COG) % Ci, tap = t / (COG * Ci);
+        ws[t] = j < nco ? W[((size_t)tap * Ci + ci) * Co + co0 + j] : 0.f;
+    }
+    __syncthreads();
+    float acc[3][COG];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int j = 0; j < COG; ++j) acc[q][j] = 0.f;
+    for (int tap = 0; tap < 27; ++tap) {
+        int nbq[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int p = threadIdx.x + q * CT;
+            nbq[q] = p < PP ? nb_pos(p, tap) : -1;
+        }
+        const float *wt = ws + tap * Ci * COG;
+        for (int ci = 0; ci < Ci; ++ci) {
+            float w[COG];
+#pragma unroll
+            for (int j = 0; j < COG; ++j) w[j] = wt[ci * COG + j];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const float a = nbq[q] >= 0 ? xs[ci * PP + nbq[q]] : 0.f;
+#pragma unroll
+                for (int j = 0; j < COG; ++j) acc[q][j] += a * w[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int p = threadIdx.x + q * CT;
+        if (p >= PP) continue;
+#pragma unroll
+        for (int j = 0; j < COG; ++j) {
+            if (j >= nco) continue;
+            const int co = co0 + j;
+            float v = acc[q][j] + (bias ? bias[co] : 0.f);
+            if (relu) v = fmaxf(v, 0.f);
+            const size_t o = ((size_t)b * Co + co) * PP + p;
+            if (mask && !(mask[o] > 0.f)) v = 0.f;
+            out[o] = v;
+        }
+    }
+}
+
+// Weights for the input gradient: Wt[26 - tap][co][ci] = W[tap][ci][co].
+__global__ __launch_bounds__(CT) void k_flip_weights(const float *__restrict__ W, int Ci, int Co,
+                                                      float *__restrict__ Wt)
+{
+    const int t = blockIdx.x * CT + threadIdx.x;
+    if (t >= 27 * Ci * Co) return;
+    const int co = t % Co, ci = (t / Co) % Ci, tap = t / (Co * Ci);
+    Wt[((size_t)(26 - tap) * Co + co) * Ci + ci] = W[t];
+}
+
+// Partial weight gradient of one tap over a group of patches:
+// part[grp][tap][ci][co] = sum_{b in grp} sum_p x[b][ci][p + d(tap)] g[b][co][p].
+__global__ __launch_bounds__(CT) void k_conv_wgrad(const float *__restrict__ x, int Ci, const float *__restrict__ g,
+                                                    int Co, int B, int per_group, float *__restrict__ part)
+{
+    constexpr int CH = 64;
+    __shared__ float xs[MAXC][CH + 1];
+    __shared__ float gs[MAXC][CH + 1];
+    const int tap = blockIdx.x, grp = blockIdx.y;
+    const int b0 = grp * per_group, b1 = min(B, b0 + per_group);
+    const int ne = Ci * Co;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int b = b0; b < b1; ++b) {
+        for (int p0 = 0; p0 < PP; p0 += CH) {
+            for (int t = threadIdx.x; t < Ci * CH; t += CT) {
+                const int ci = t / CH, pp = t % CH, p = p0 + pp;
+                float v = 0.f;
+                if (p < PP) {
+                    const int q = nb_pos(p, tap);
+                    if (q >= 0) v = x[((size_t)b * Ci + ci) * PP + q];
+                }
+                xs[ci][pp] = v;
+            }
+            for (int t = threadIdx.x; t < Co * CH; t += CT) {
+                const int co = t / CH, pp = t % CH, p = p0 + pp;
+                gs[co][pp] = p < PP ? g[((size_t)b * Co + co) * PP + p] : 0.f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = threadIdx.x + j * CT;
+                if (e >= ne) continue;
+                const int ci = e / Co, co = e % Co;
+                float s = 0.f;
+                for (int pp = 0; pp < CH; ++pp) s += xs[ci][pp] * gs[co][pp];
+                acc[j] += s;
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = threadIdx.x + j * CT;
+        if (e < ne) part[((size_t)grp * 27 + tap) * ne + e] = acc[j];
+    }
+}
+
+// grad[i] = sum over groups of part[grp][i] (fixed order).
+__global__ __launch_bounds__(CT) void k_sum_groups(const float *__restrict__ part, int groups, int n,
+                                                    float *__restrict__ grad)
+{
+    const int i = blockIdx.x * CT + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int q = 0; q < groups; ++q) s += part[(size_t)q * n + i];
+    grad[i] = s;
+}
+
+// Bias gradient: sum over patches and positions, one workgroup per channel.
+__global__ __launch_bounds__(CT) void k_bias_grad(const float *__restrict__ g, int Co, int B, float *__restrict__ gb)
+{
+    __shared__ double sh[CT / 64];
+    const int co = blockIdx.x;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < B * PP; t += CT) {
+        const int b = t / PP, p = t % PP;
+        s += g[((size_t)b * Co + co) * PP + p];
+    }
+    const double tot = block_sum<CT>(s, sh);
+    if (threadIdx.x == 0) gb[co] = (float)tot;
+}
+
+__device__ __forceinline__ bool interior_pos(int p, int &ip)
+{
+    const int x = p % PD, y = (p / PD) % PD, z = p / (PD * PD);
+    if (x < 1 || x > PD - 2 || y < 1 || y > PD - 2 || z < 1 || z > PD - 2) return false;
+    ip = (x - 1) + 7 * ((y - 1) + 7 * (z - 1));
+    return true;
+}
+
+// Softmax over the 8 channels; with a target: MSE over the interior cells,
+// its gradient wrt the logits, and per-workgroup loss partials.
+__global__ __launch_bounds__(CT) void k_softmax_mse(const float *__restrict__ logits, const float *__restrict__ target,
+                                                     int B, float inv_nterm, float *__restrict__ phi,
+                                                     float *__restrict__ glog, double *__restrict__ loss_part)
+{
+    __shared__ double sh[CT / 64];
+    const int t = blockIdx.x * CT + threadIdx.x;
+    double l2 = 0.0;
+    if (t < B * PP) {
+        const int b = t / PP, p = t % PP;
+        float z[8], m = -3.0e38f;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            z[s] = logits[((size_t)b * 8 + s) * PP + p];
+            m = fmaxf(m, z[s]);
+        }
+        float e[8], se = 0.f;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            e[s] = expf(z[s] - m);
+            se += e[s];
+        }
+        float ph[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            ph[s] = e[s] / se;
+            if (phi) phi[((size_t)b * 8 + s) * PP + p] = ph[s];
+        }
+        if (target && glog) {
+            int ip;
+            float gz[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (interior_pos(p, ip)) {
+                float gp[8], dot = 0.f;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const float d = ph[s] - target[((size_t)b * 8 + s) * 343 + ip];
+                    l2 += (double)d * d;
+                    gp[s] = 2.f * d * inv_nterm;
+                    dot += ph[s] * gp[s];
+                }
+#pragma unroll
+                for (int s = 0; s < 8; ++s) gz[s] = ph[s] * (gp[s] - dot);
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s) glog[((size_t)b * 8 + s) * PP + p] = gz[s];
+        }
+    }
+    const double tot = block_sum<CT>(l2, sh);
+    if (threadIdx.x == 0 && loss_part) loss_part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(CT) void k_loss_final(const double *__restrict__ part, int n, double scale,
+                                                    double *__restrict__ loss)
+{
+    __shared__ double sh[CT / 64];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < n; t += CT) s += part[t];
+    const double tot = block_sum<CT>(s, sh);
+    if (threadIdx.x == 0) *loss = tot * scale;
+}
+
+__global__ __launch_bounds__(CT) void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                                              float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2)
+{
+    const int i = blockIdx.x * CT + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Features of full dual blocks: ln T on the +x/+y/+z face of every patch cell
+// (0 on the patch's last face along that axis).  Region list entries are
+// interior boxes of 7x7x7 cells; the patch starts one cell before them.
+__global__ __launch_bounds__(CT) void k_cnn_features(GridDev g, const double *__restrict__ T,
+                                                      const Region *__restrict__ regs, float *__restrict__ feat)
+{
+    const int blk = blockIdx.x;
+    const Region R = regs[blk];
+    const int i0 = R.s[0] - 1, j0 = R.s[1] - 1, k0 = R.s[2] - 1;
+    for (int p = threadIdx.x; p < PP; p += CT) {
+        const int x = p % PD, y = (p / PD) % PD, z = p / (PD * PD);
+        const int n = (i0 + x) + g.nx * ((j0 + y) + g.ny * (k0 + z));
+        const double tx = x < PD - 1 ? T[n] : 0.0;
+        const double ty = y < PD - 1 ? T[g.N + n] : 0.0;
+        const double tz = z < PD - 1 ? T[2 * (size_t)g.N + n] : 0.0;
+        float *f = feat + (size_t)blk * 3 * PP;
+        f[p] = tx > 0.0 ? (float)log(tx) : 0.f;
+        f[PP + p] = ty > 0.0 ? (float)log(ty) : 0.f;
+        f[2 * PP + p] = tz > 0.0 ? (float)log(tz) : 0.f;
+    }
+}
+
+// Targets: the exact basis values of the interior cells (slot s = corner s).
+__global__ __launch_bounds__(CT) void k_cnn_targets(GridDev g, const double *__restrict__ P,
+                                                     const Region *__restrict__ regs, float *__restrict__ tgt)
+{
+    const int blk = blockIdx.x;
+    const Region R = regs[blk];
+    for (int t = threadIdx.x; t < 8 * 343; t += CT) {
+        const int s = t / 343, ip = t % 343;
+        const int x = ip % 7, y = (ip / 7) % 7, z = ip / 49;
+        const int n = (R.s[0] + x) + g.nx * ((R.s[1] + y) + g.ny * (R.s[2] + z));
+        tgt[(size_t)blk * 8 * 343 + t] = (float)P[(size_t)s * g.N + n];
+    }
+}
+
+// Write the predicted interior values into the basis.
+__global__ __launch_bounds__(CT) void k_cnn_scatter(GridDev g, const float *__restrict__ phi,
+                                                     const Region *__restrict__ regs, double *__restrict__ P)
+{
+    const int blk = blockIdx.x;
+    const Region R = regs[blk];
+    for (int t = threadIdx.x; t < 8 * 343; t += CT) {
+        const int s = t / 343, ip = t % 343;
+        const int x = ip % 7, y = (ip / 7) % 7, z = ip / 49;
+        const int p = (x + 1) + PD * ((y + 1) + PD * (z + 1));
+        const int n = (R.s[0] + x) + g.nx * ((R.s[1] + y) + g.ny * (R.s[2] + z));
+        P[(size_t)s * g.N + n] = (double)phi[((size_t)blk * 8 + s) * PP + p];
+    }
+}
+
+// Local-equation check of a predicted interior: ||(T Phi)_I|| / ||T_IF Phi_F||
+// over the 8 basis functions (T the incompressible two-point operator).
+__global__ __launch_bounds__(CT) void k_block_residual(GridDev g, const double *__restrict__ T,
+                                                        const double *__restrict__ P,
+                                                        const Region *__restrict__ regs, double *__restrict__ ratio)
+{
+    __shared__ double sh[CT / 64];
+    const int blk = blockIdx.x;
+    const Region R = regs[blk];
+    const double *Tx = T, *Ty = T + g.N, *Tz = T + 2 * (size_t)g.N;
+    double num = 0.0, den = 0.0;
+    for (int t = threadIdx.x; t < 8 * 343; t += CT) {
+        const int s = t / 343, ip = t % 343;
+        const int x = ip % 7, y = (ip / 7) % 7, z = ip / 49;
+        const int i = R.s[0] + x, j = R.s[1] + y, k = R.s[2] + z;
+        const int n = i + g.nx * (j + g.ny * k);
+        const double *Ps = P + (size_t)s * g.N;
+        const double pn = Ps[n];
+        double res = 0.0, bnd = 0.0;
+        const int nbr[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - g.sxy, n + g.sxy};
+        const double tf[6] = {Tx[n - 1], Tx[n], Ty[n - g.nx], Ty[n], Tz[n - g.sxy], Tz[n]};
+        const bool onb[6] = {x == 0, x == 6, y == 0, y == 6, z == 0, z == 6};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const double pj = Ps[nbr[f]];
+            res += tf[f] * (pn - pj);
+            if (onb[f]) bnd += tf[f] * pj;
+        }
+        num += res * res;
+        den += bnd * bnd;
+    }
+    const double sn = block_sum<CT>(num, sh);
+    const double sd = block_sum<CT>(den, sh);
+    if (threadIdx.x == 0) ratio[blk] = sd > 0.0 ? sqrt(sn / sd) : 0.0;
+}
+
+inline unsigned cdiv_u(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- host ----
+
+size_t cnn_num_params()
+{
+    return 27 * 3 * 32 + 32 + 2 * (27 * 32 * 32 + 32) + 27 * 32 * 8 + 8;
+}
+
+static const int kLayers[4][2] = {{3, 32}, {32, 32}, {32, 32}, {32, 8}};
+
+static size_t layer_offset(int l)
+{
+    size_t o = 0;
+    for (int q = 0; q < l; ++q) o += 27 * kLayers[q][0] * kLayers[q][1] + kLayers[q][1];
+    return o;
+}
+
+static int wgrad_groups(int B) { return B < 8 ? B : 8; }
+
+// Workspace (floats) for a batch of B patches: three hidden activations,
+// logits, softmax output, two gradient buffers, flipped weights, partial
+// weight gradients, loss partials.
+size_t cnn_workspace_floats(int B)
+{
+    const size_t act = (size_t)B * 32 * PP;
+    return 3 * act + 2 * (size_t)B * 8 * PP + 2 * act + 27 * 32 * 32 + (size_t)wgrad_groups(B) * 27 * 32 * 32 +
+           2 * (size_t)cdiv_u((size_t)B * PP, CT) + 64;
+}
+
+struct CnnWs {
+    float *a[3], *logits, *phi, *g0, *g1, *wflip, *part;
+    double *loss_part;
+};
+
+static CnnWs carve(float *ws, int B)
+{
+    CnnWs w;
+    const size_t act = (size_t)B * 32 * PP;
+    float *q = ws;
+    for (int l = 0; l < 3; ++l) { w.a[l] = q; q += act; }
+    w.logits = q; q += (size_t)B * 8 * PP;
+    w.phi = q; q += (size_t)B * 8 * PP;
+    w.g0 = q; q += act;
+    w.g1 = q; q += act;
+    w.wflip = q; q += 27 * 32 * 32;
+    w.part = q; q += (size_t)wgrad_groups(B) * 27 * 32 * 32;
+    w.loss_part = (double *)q;
+    return w;
+}
+
+void cnn_forward(hipStream_t st, const float *params, const float *feat, int B, float *ws_f, float *phi_out)
+{
+    CnnWs w = carve(ws_f, B);
+    const float *in = feat;
+    for (int l = 0; l < 4; ++l) {
+        const int Ci = kLayers[l][0], Co = kLayers[l][1];
+        const float *W = params + layer_offset(l);
+        const float *bias = W + 27 * Ci * Co;
+        float *out = l < 3 ? w.a[l] : w.logits;
+        dim3 grid(B, cdiv_u(Co, COG));
+        k_conv_fwd<<<grid, CT, 0, st>>>(in, Ci, W, bias, Co, out, l < 3, nullptr);
+        in = out;
+    }
+    k_softmax_mse<<<cdiv_u((size_t)B * PP, CT), CT, 0, st>>>(w.logits, nullptr, B, 0.f, phi_out ? phi_out : w.phi,
+                                                             nullptr, nullptr);
+}
+
+void cnn_loss_grad(hipStream_t st, const float *params, const float *feat, const float *target, int B,
+                   float *ws_f, float *grad, double *loss_out)
+{
+    CnnWs w = carve(ws_f, B);
+    cnn_forward(st, params, feat, B, ws_f, w.phi);
+    const float inv = 1.f / (float)((size_t)B * 8 * 343);
+    const unsigned nb = cdiv_u((size_t)B * PP, CT);
+    // g0 = d loss / d logits (stored in the logits-sized prefix of g0)
+    k_softmax_mse<<<nb, CT, 0, st>>>(w.logits, target, B, inv, w.phi, w.g0, w.loss_part);
+    k_loss_final<<<1, CT, 0, st>>>(w.loss_part, (int)nb, (double)inv, loss_out);
+    float *gcur = w.g0, *gnext = w.g1;
+    const int groups = wgrad_groups(B);
+    const int per = (B + groups - 1) / groups;
+    for (int l = 3; l >= 0; --l) {
+        const int Ci = kLayers[l][0], Co = kLayers[l][1];
+        const float *W = params + layer_offset(l);
+        const float *xin = l > 0 ? w.a[l - 1] : feat;
+        float *gW = grad + layer_offset(l);
+        float *gb = gW + 27 * Ci * Co;
+        dim3 gw(27, groups);
+        k_conv_wgrad<<<gw, CT, 0, st>>>(xin, Ci, gcur, Co, B, per, w.part);
+        k_sum_groups<<<cdiv_u(27 * Ci * Co, CT), CT, 0, st>>>(w.part, groups, 27 * Ci * Co, gW);
+        k_bias_grad<<<Co, CT, 0, st>>>(gcur, Co, B, gb);
+        if (l > 0) {
+            // input gradient through the flipped kernel, masked by ReLU'(a)
+            k_flip_weights<<<cdiv_u(27 * Ci * Co, CT), CT, 0, st>>>(W, Ci, Co, w.wflip);
+            dim3 grid(B, cdiv_u(Ci, COG));
+            k_conv_fwd<<<grid, CT, 0, st>>>(gcur, Co, w.wflip, nullptr, Ci, gnext, 0, w.a[l - 1]);
+            float *t = gcur;
+            gcur = gnext;
+            gnext = t;
+        }
+    }
+}
+
+void cnn_adam(hipStream_t st, float *p, const float *g, float *m, float *v, int n, int t, float lr, float b1,
+              float b2, float eps)
+{
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    k_adam<<<cdiv_u(n, CT), CT, 0, st>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+void cnn_features(cams_ctx *c, const Region *regs, int nblk, float *feat)
+{
+    if (nblk > 0) k_cnn_features<<<nblk, CT, 0, c->stream>>>(c->g, c->a.T, regs, feat);
+}
+
+void cnn_targets(cams_ctx *c, const Region *regs, int nblk, float *tgt)
+{
+    if (nblk > 0) k_cnn_targets<<<nblk, CT, 0, c->stream>>>(c->g, c->a.P, regs, tgt);
+}
+
+void cnn_scatter(cams_ctx *c, const Region *regs, int nblk, const float *phi)
+{
+    if (nblk > 0) k_cnn_scatter<<<nblk, CT, 0, c->stream>>>(c->g, phi, regs, c->a.P);
+}
+
+void cnn_block_residual(cams_ctx *c, const Region *regs, int nblk, double *ratio)
+{
+    if (nblk > 0) k_block_residual<<<nblk, CT, 0, c->stream>>>(c->g, c->a.T, c->a.P, regs, ratio);
+}
+
+}  // namespace cams

@@ -5,10 +5,12 @@
 //    accumulated in LDS and reduced in a fixed order, so A_c is bitwise
 //    deterministic (no atomics).
 //  - restriction R r for the iteration (same ownership, one value per row);
-//  - LU with partial pivoting by column panels: panel factorisation in one
-//    workgroup, row interchanges, unit-lower triangular solve for the U row
-//    block, and the trailing update C -= A B on FP64 matrix cores
-//    (v_mfma_f64_16x16x4f64, 64x64 tiles per workgroup);
+//  - LU by 64-column panels with the trailing update C -= A B on FP64
+//    matrix cores (v_mfma_f64_16x16x4f64, 64x64 tiles per workgroup):
+//    MSFV: partial pivoting, panel factorised by one workgroup;
+//    MSFE (symmetric positive definite): no interchanges, only the 64x64
+//    diagonal block is sequential, the row and column triangular solves of
+//    the panel are fully parallel;
 //  - the explicit inverse from the LU factors with the same kernels, so that
 //    every coarse solve of the iteration is one fully parallel GEMV instead
 //    of two latency-bound triangular sweeps.
@@ -246,6 +248,34 @@ __global__ __launch_bounds__(kBlock) void k_lu_panel_lds(double *__restrict__ A,
     }
 }
 
+// Unpivoted LU of the nb x nb diagonal block at (j0, j0), in LDS (MSFE:
+// the coarse operator is symmetric positive definite, so no pivoting is
+// needed).  A non-positive pivot is flagged.
+__global__ __launch_bounds__(kBlock) void k_lu_diag_nopiv(double *__restrict__ A, int n, int j0, int nb,
+                                                           int32_t *status)
+{
+    __shared__ double D[kNB][kNB + 1];
+    for (int t = threadIdx.x; t < nb * nb; t += kBlock) D[t / nb][t % nb] = A[(size_t)(j0 + t / nb) * n + j0 + t % nb];
+    __syncthreads();
+    for (int c = 0; c < nb; ++c) {
+        double pv = D[c][c];
+        if (!(pv > 0.0)) {
+            if (threadIdx.x == 0) atomicOr(status, F_SINGULAR_COARSE);
+            pv = 1.0;
+        }
+        __syncthreads();
+        for (int i = c + 1 + threadIdx.x; i < nb; i += kBlock) D[i][c] /= pv;
+        __syncthreads();
+        const int w = nb - c - 1;
+        for (int t = threadIdx.x; t < w * w; t += kBlock) {
+            const int i = c + 1 + t / w, j = c + 1 + t % w;
+            D[i][j] -= D[i][c] * D[c][j];
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < nb * nb; t += kBlock) A[(size_t)(j0 + t / nb) * n + j0 + t % nb] = D[t / nb][t % nb];
+}
+
 // Apply the panel's interchanges to the columns outside [j0, j0+nb).
 __global__ __launch_bounds__(kBlock) void k_lu_swap(double *__restrict__ A, int n, int j0, int nb,
                                                      const int32_t *__restrict__ piv)
@@ -305,15 +335,16 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// C (M x Nn, ldc) -= A (M x K, lda) * B (K x Nn, ldb); row-major.
+// C (M x Nn, ldc) = alpha A (M x K, lda) B (K x Nn, ldb) + beta C; row-major.
+// C may alias A when Nn <= 64 (each workgroup then owns whole rows of C and
+// reads its rows of A before writing), or B when M <= 64 (whole columns).
 // 256 threads = 4 waves as 2 x 2; each wave owns a 32 x 32 block of the
 // 64 x 64 tile as 2 x 2 tiles of v_mfma_f64_16x16x4f64.  K is staged through
 // LDS 16 at a time.  Operand lanes: A row = lane%16, k = lane/16; B col =
 // lane%16, k = lane/16; result element v of a lane: row lane/16 + 4v,
 // col lane%16 (checked against a host GEMM by the parity tests).
-__global__ __launch_bounds__(kBlock) void k_gemm_sub(double *__restrict__ C, int ldc, const double *__restrict__ A,
-                                                      int lda, const double *__restrict__ B, int ldb, int M, int Nn,
-                                                      int K)
+__global__ __launch_bounds__(kBlock) void k_gemm(double *C, int ldc, const double *A, int lda, const double *B,
+                                                  int ldb, int M, int Nn, int K, double alpha, double beta)
 {
     __shared__ double As[64][17];
     __shared__ double Bs[16][65];
@@ -359,8 +390,17 @@ __global__ __launch_bounds__(kBlock) void k_gemm_sub(double *__restrict__ C, int
             for (int v = 0; v < 4; ++v) {
                 const int r = tm + wm + a * 16 + (lane >> 4) + 4 * v;
                 const int c = tn + wn + b * 16 + (lane & 15);
-                if (r < M && c < Nn) C[(size_t)r * ldc + c] -= acc[a][b][v];
+                if (r < M && c < Nn) {
+                    const double prod = alpha * acc[a][b][v];
+                    C[(size_t)r * ldc + c] = beta == 0.0 ? prod : beta * C[(size_t)r * ldc + c] + prod;
+                }
             }
+}
+
+__global__ __launch_bounds__(kBlock) void k_identity_piv(int32_t *__restrict__ piv, int n)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) piv[t] = t;
 }
 
 // B = P I for the row interchanges of the factorisation (one thread builds
@@ -438,12 +478,27 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
 
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
-void gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, const double *B, int ldb, int M, int Nn,
-              int K)
+void gemm(cams_ctx *c, double *C, int ldc, const double *A, int lda, const double *B, int ldb, int M, int Nn, int K,
+          double alpha, double beta)
 {
     if (M <= 0 || Nn <= 0 || K <= 0) return;
     dim3 grid(cdiv(Nn, 64), cdiv(M, 64));
-    k_gemm_sub<<<grid, kBlock, 0, c->stream>>>(C, ldc, A, lda, B, ldb, M, Nn, K);
+    k_gemm<<<grid, kBlock, 0, c->stream>>>(C, ldc, A, lda, B, ldb, M, Nn, K, alpha, beta);
+}
+
+// C -= A B
+void gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, const double *B, int ldb, int M, int Nn,
+              int K)
+{
+    gemm(c, C, ldc, A, lda, B, ldb, M, Nn, K, -1.0, 1.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_identity64(double *__restrict__ X, int blocks)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= blocks * kNB * kNB) return;
+    const int e = t % (kNB * kNB);
+    X[t] = (e / kNB == e % kNB) ? 1.0 : 0.0;
 }
 
 }  // namespace
@@ -460,8 +515,57 @@ void launch_coarse_factor(cams_ctx *c)
     double *F = c->a.work;
     const size_t nn = (size_t)n * n;
     k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
+    const bool pivoting = c->opt.restriction != CAMS_R_FE;
+    double *X = c->a.Ainv;
+    if (!pivoting) {
+        // MSFE (SPD): blocked LU without interchanges.  Per 64-column panel:
+        // the diagonal block is factorised in LDS and its two triangles are
+        // inverted (stored in `tri`); then L21 = A21 U11^-1 and
+        // U12 = L11^-1 A12 are in-place MFMA products and A22 -= L21 U12.
+        double *tri = c->a.tri;
+        const int npan = (n + kNB - 1) / kNB;
+        k_identity64<<<cdiv((size_t)2 * npan * kNB * kNB, kBlock), kBlock, 0, c->stream>>>(tri, 2 * npan);
+        for (int b = 0; b < npan; ++b) {
+            const int j0 = b * kNB;
+            const int nb = n - j0 < kNB ? n - j0 : kNB;
+            const int rest = n - j0 - nb;
+            double *Linv = tri + (size_t)(2 * b) * kNB * kNB, *Uinv = Linv + kNB * kNB;
+            k_lu_diag_nopiv<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.status);
+            k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Linv - (size_t)j0 * kNB, kNB, 0, kNB, 0);
+            k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Uinv - (size_t)j0 * kNB, kNB, 0, kNB, 1);
+            if (rest > 0) {
+                double *A21 = F + (size_t)(j0 + nb) * n + j0, *A12 = F + (size_t)j0 * n + j0 + nb;
+                gemm(c, A21, n, A21, n, Uinv, kNB, rest, nb, nb, 1.0, 0.0);
+                gemm(c, A12, n, Linv, kNB, A12, n, nb, rest, nb, 1.0, 0.0);
+                gemm_sub(c, F + (size_t)(j0 + nb) * n + j0 + nb, n, A21, n, A12, n, rest, rest, nb);
+            }
+        }
+        // inverse: X = U^-1 L^-1 by block substitutions with the stored
+        // diagonal-block inverses (all MFMA products)
+        k_identity_piv<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n);
+        k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, X);
+        for (int b = 0; b < npan; ++b) {
+            const int j0 = b * kNB;
+            const int nb = n - j0 < kNB ? n - j0 : kNB;
+            const int rest = n - j0 - nb;
+            const double *Linv = tri + (size_t)(2 * b) * kNB * kNB;
+            double *Xb = X + (size_t)j0 * n;
+            gemm(c, Xb, n, Linv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
+            if (rest > 0) gemm_sub(c, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, Xb, n, rest,
+                                   n, nb);
+        }
+        for (int b = npan - 1; b >= 0; --b) {
+            const int j0 = b * kNB;
+            const int nb = n - j0 < kNB ? n - j0 : kNB;
+            const double *Uinv = tri + (size_t)(2 * b + 1) * kNB * kNB;
+            double *Xb = X + (size_t)j0 * n;
+            gemm(c, Xb, n, Uinv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
+            if (j0 > 0) gemm_sub(c, X, n, F + j0, n, Xb, n, j0, n, nb);
+        }
+        return;
+    }
     // LU with partial pivoting, right looking by panels
-    for (int j0 = 0; j0 < n; j0 += kNB) {
+    for (int j0 = 0; pivoting && j0 < n; j0 += kNB) {
         const int nb = n - j0 < kNB ? n - j0 : kNB;
         if ((size_t)(n - j0) * (nb + 1) <= (size_t)kPanelLds)
             k_lu_panel_lds<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.piv, c->a.status);
@@ -476,7 +580,6 @@ void launch_coarse_factor(cams_ctx *c)
         }
     }
     // inverse: X = U^{-1} L^{-1} (P I)
-    double *X = c->a.Ainv;
     int32_t *perm = c->a.piv + n;
     k_perm_identity<<<1, 1, 0, c->stream>>>(c->a.piv, n, perm, X);
     k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(perm, n, X);

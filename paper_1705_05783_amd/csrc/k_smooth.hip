@@ -218,15 +218,19 @@ void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR
     const T *prev = nullptr;
     // algorithmic bytes of a step: rhs, W (3), invd, e_new; plus diag and e_old after the first
     const double n = (double)c->g.N;
+    double bytes = 0.0;
+    for (int s = 0; s < steps; ++s)
+        bytes += n * ((double)sizeof(TR) + 5.0 * sizeof(T) + (s > 0 ? 2.0 * sizeof(T) : 0.0));
+    // the whole back-to-back sequence is bracketed, which keeps the event
+    // overhead per launch small
+    const bool timed = c->prof_kernel == CAMS_PROF_SMOOTH_STEP && c->prof_iter % kProfEvery == 0 && steps > 0;
+    if (timed) prof_begin(c, bytes, steps);
     for (int s = 0; s < steps; ++s) {
         T *out = buf[(steps - 1 - s) & 1];
-        const double bytes = n * ((double)sizeof(TR) + 5.0 * sizeof(T) + (s > 0 ? 2.0 * sizeof(T) : 0.0));
-        const bool timed = c->prof_kernel == CAMS_PROF_SMOOTH_STEP && c->prof_iter % kProfEvery == 0;
-        if (timed) prof_begin(c, bytes);
         k_bilu_step<T, TR><<<nb, ST, 0, c->stream>>>(c->g, W, diag, invd, rhs, prev, out, done);
-        if (timed) prof_end(c);
         prev = out;
     }
+    if (timed) prof_end(c);
 }
 
 // e = result of `steps` block-ILU(0) Richardson steps on A e = rhs from e = 0.

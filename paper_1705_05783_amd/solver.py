@@ -104,6 +104,39 @@ class Solver:
         C.check(C.cams_smooth_apply(self.ctx, _ptr(z), _ptr(x)), self.ctx, "cams_smooth_apply")
         return x
 
+    # ---- learned basis
+    def num_full_blocks(self) -> int:
+        return int(C.cams_cnn_num_blocks(self.ctx))
+
+    def cnn_patches(self, with_targets=True):
+        """(features (B,3,729), targets (B,8,343) or None) of the full dual blocks;
+        targets need a built (exact) basis."""
+        nb = self.num_full_blocks()
+        feat = torch.empty((nb, 3, 729), dtype=torch.float32, device=self.device)
+        tgt = torch.empty((nb, 8, 343), dtype=torch.float32, device=self.device) if with_targets else None
+        C.check(C.cams_cnn_patches(self.ctx, _ptr(feat), _ptr(tgt) if tgt is not None else None), self.ctx,
+                "cams_cnn_patches")
+        return feat, tgt
+
+    def set_learned(self, params, fallback_tol=1e-2):
+        """Use the network for full-block interiors (params: float32 device
+        tensor), or exact local solves again (params None)."""
+        if params is None:
+            C.check(C.cams_set_learned(self.ctx, None, None, 0, 0.0), self.ctx, "cams_set_learned")
+            self._learned = None
+            return
+        nbytes = C.cams_learned_scratch_bytes(self.ctx)
+        scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (scratch.data_ptr() + 255) // 256 * 256
+        C.check(C.cams_set_learned(self.ctx, _ptr(params), ctypes.c_void_p(ptr), nbytes, float(fallback_tol)),
+                self.ctx, "cams_set_learned")
+        self._learned = (params, scratch)
+
+    def basis_stats(self) -> dict:
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        C.check(C.cams_basis_stats(self.ctx, ctypes.byref(a), ctypes.byref(b)), self.ctx, "cams_basis_stats")
+        return {"learned_blocks": a.value, "fallback_blocks": b.value}
+
     # ---- measurement
     def profile(self, kernel=C.CAMS_PROF_SMOOTH_STEP):
         C.check(C.cams_profile(self.ctx, kernel), self.ctx, "cams_profile")

@@ -1,0 +1,170 @@
+"""Learned basis on the GPU: the network's forward, loss gradient and Adam
+kernels against the FP64 oracle (FP32 kernels: 1e-5 relative), patch
+extraction against the oracle basis, and the learned build with fallback."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn as ocnn
+from tests.gpu_util import log, rel_err, require_gpu, solver_for, to_np
+from workloads import small_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _rand_params(seed):
+    p = ocnn.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    # non-zero biases so their gradients are exercised
+    o = 0
+    for ci, co in ocnn.LAYERS:
+        o += 27 * ci * co
+        p[o:o + co] = rng.normal(0, 0.1, co)
+        o += co
+    return p
+
+
+def test_forward_matches_oracle(torch):
+    from paper_1705_05783_amd import learned
+    rng = np.random.default_rng(0)
+    params = _rand_params(1)
+    feat = rng.normal(size=(3, 3, 9, 9, 9))
+    phi_ref, _ = ocnn.forward(params, feat)
+    pt = torch.tensor(params, dtype=torch.float32, device="cuda")
+    ft = torch.tensor(feat.reshape(3, 3, 729), dtype=torch.float32, device="cuda")
+    phi = to_np(learned.forward(pt, ft)).reshape(3, 8, 9, 9, 9)
+    assert rel_err(phi, phi_ref) <= 2e-5
+
+
+def test_loss_gradient_matches_oracle(torch):
+    from paper_1705_05783_amd import learned
+    rng = np.random.default_rng(2)
+    params = _rand_params(3)
+    feat = rng.normal(size=(5, 3, 9, 9, 9))
+    tgt = rng.dirichlet(np.ones(8), size=(5, 7, 7, 7)).transpose(0, 4, 1, 2, 3)
+    loss_ref, g_ref = ocnn.loss_and_grad(params, feat, tgt)
+    pt = torch.tensor(params, dtype=torch.float32, device="cuda")
+    tr = learned.Trainer(pt, batch=5)
+    loss, g = tr.loss_grad(torch.tensor(feat.reshape(5, 3, 729), dtype=torch.float32, device="cuda"),
+                           torch.tensor(tgt.reshape(5, 8, 343), dtype=torch.float32, device="cuda"))
+    log("loss", float(loss), loss_ref)
+    assert abs(float(loss) - loss_ref) <= 1e-5 * loss_ref
+    g = to_np(g).astype(np.float64)
+    o = 0
+    for ci, co in ocnn.LAYERS:
+        n = 27 * ci * co + co
+        assert rel_err(g[o:o + n], g_ref[o:o + n]) <= 1e-4, (ci, co)
+        o += n
+
+
+def test_adam_matches_oracle(torch):
+    from paper_1705_05783_amd import learned
+    rng = np.random.default_rng(4)
+    n = learned.num_params()
+    p0 = rng.normal(size=n)
+    pt = torch.tensor(p0, dtype=torch.float32, device="cuda")
+    tr = learned.Trainer(pt, batch=1, lr=1e-2)
+    p, m, v = p0.astype(np.float32).astype(np.float64), np.zeros(n), np.zeros(n)
+    import ctypes
+    from paper_1705_05783_amd import _cams as C
+    for t in range(1, 4):
+        g = rng.normal(size=n)
+        tr.grad.copy_(torch.tensor(g, dtype=torch.float32))
+        C.cams_cnn_adam(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.c_void_p(pt.data_ptr()),
+                        ctypes.c_void_p(tr.grad.data_ptr()), ctypes.c_void_p(tr.m.data_ptr()),
+                        ctypes.c_void_p(tr.v.data_ptr()), n, t, 1e-2, 0.9, 0.999, 1e-8)
+        p, m, v = ocnn.adam_step(p, g.astype(np.float32).astype(np.float64), m, v, t, lr=1e-2)
+    torch.cuda.synchronize()
+    assert rel_err(to_np(pt), p) <= 1e-5
+
+
+def _learned_problem():
+    return small_problem(26, 24, 20, 8, sigma=2.0, seed=21)
+
+
+def test_patches_match_oracle_basis(torch):
+    pb = _learned_problem()
+    s = solver_for(pb)
+    s.build_basis()
+    feat, tgt = s.cnn_patches()
+    nb = feat.shape[0]
+    assert nb == s.num_full_blocks() and nb > 0
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    v = [list(oracle.vertex_coords(n, 8)) for n in (pb.nx, pb.ny, pb.nz)]
+    blocks = [(a, b, c) for c in range(len(v[2]) - 1) for b in range(len(v[1]) - 1) for a in range(len(v[0]) - 1)
+              if v[0][a + 1] - v[0][a] == 8 and v[1][b + 1] - v[1][b] == 8 and v[2][c + 1] - v[2][c] == 8]
+    assert len(blocks) == nb
+    F = to_np(feat).reshape(nb, 3, 9, 9, 9)
+    G = to_np(tgt).reshape(nb, 8, 7, 7, 7)
+    Tg = T.reshape(3, pb.nz, pb.ny, pb.nx)
+    Pg = P.reshape(8, pb.nz, pb.ny, pb.nx)
+    found = 0
+    for (a, b, c) in blocks:
+        x0, y0, z0 = v[0][a], v[1][b], v[2][c]
+        ref_t = Pg[:, z0 + 1:z0 + 8, y0 + 1:y0 + 8, x0 + 1:x0 + 8]
+        # locate this block among the GPU patches by its targets
+        k = int(np.argmin([np.abs(G[q] - ref_t).max() for q in range(nb)]))
+        assert np.abs(G[k] - ref_t).max() <= 1e-6
+        lnT = np.log(np.where(Tg > 0, Tg, 1.0))[:, z0:z0 + 9, y0:y0 + 9, x0:x0 + 9].copy()
+        lnT[0, :, :, 8] = 0
+        lnT[1, :, 8, :] = 0
+        lnT[2, 8, :, :] = 0
+        assert np.abs(F[k] - lnT).max() <= 1e-5 * max(1.0, np.abs(lnT).max())
+        found += 1
+    assert found == nb
+
+
+def test_learned_build_fallback_and_prediction(torch):
+    """Tiny tolerance: every predicted block falls back, the basis is exact.
+    Huge tolerance: interiors are the network's softmax output (partition of
+    unity), and the Newton step still converges to the oracle pressure."""
+    from paper_1705_05783_amd import learned
+    pb = _learned_problem()
+    params = torch.tensor(_rand_params(7), dtype=torch.float32, device="cuda")
+    T = oracle.transmissibility(pb)
+    P_ref = oracle.basis_b4(pb, T)
+    s = solver_for(pb)
+    s.set_learned(params, fallback_tol=1e-12)
+    s.build_basis()
+    st = s.basis_stats()
+    assert st["fallback_blocks"] == s.num_full_blocks() and st["learned_blocks"] == 0
+    assert np.max(np.abs(to_np(s.export(4)).reshape(8, -1) - P_ref)) <= 1e-12
+
+    s2 = solver_for(pb)
+    s2.set_learned(params, fallback_tol=1e30)
+    s2.build_basis()
+    st2 = s2.basis_stats()
+    assert st2["learned_blocks"] == s2.num_full_blocks() and st2["fallback_blocks"] == 0
+    P = to_np(s2.export(4)).reshape(8, -1)
+    assert np.max(np.abs(P.sum(axis=0) - 1.0)) <= 1e-5
+    feat, _ = s2.cnn_patches(with_targets=False)
+    phi = to_np(learned.forward(params, feat)).reshape(-1, 8, 9, 9, 9)
+    # every predicted interior appears in the basis
+    Pg = P.reshape(8, pb.nz, pb.ny, pb.nx)
+    v = [list(oracle.vertex_coords(n, 8)) for n in (pb.nx, pb.ny, pb.nz)]
+    x0, y0, z0 = v[0][0], v[1][0], v[2][0]
+    block = Pg[:, z0 + 1:z0 + 8, y0 + 1:y0 + 8, x0 + 1:x0 + 8]
+    assert min(np.abs(phi[q][:, 1:8, 1:8, 1:8] - block).max() for q in range(phi.shape[0])) <= 1e-6
+    pn = pb.initial_pressure()
+    p = torch.as_tensor(pn, device="cuda")
+    s2.newton_step(p.clone(), p)
+    _, e = oracle.nonlinear_residual(pb, T, to_np(p), pn)
+    assert e <= pb.newton_tol
+    p_ref, rc, _ = oracle.newton_step(pb, T, P_ref, pn, pn)
+    assert rel_err(to_np(p), p_ref) <= 1e-6
+
+
+def test_short_training_reduces_loss(torch):
+    from paper_1705_05783_amd import learned
+    feat, tgt = learned.generate(2, seed0=4000)
+    assert feat.shape == (2 * 343, 3, 729)
+    params, hist = learned.train(feat, tgt, epochs=3, batch=64, lr=2e-3, seed=1)
+    log("loss history", hist)
+    assert hist[-1] < hist[0]

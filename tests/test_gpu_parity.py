@@ -340,3 +340,22 @@ def test_mixed_newton_matches_fp64_oracle(_gpu, precision):
     p_ref, rc, ost = oracle.newton_step(pb, T, oracle.basis_b4(pb, T), pn, pn)
     assert rc == 0
     assert rel_err(to_np(p_gpu), p_ref) <= 1e-7
+
+
+@pytest.mark.parametrize("shape,r,restriction", [((48, 48, 40), 4, FE), ((40, 32, 16), 4, FV)])
+def test_coarse_inverse_multi_panel(_gpu, shape, r, restriction):
+    """Coarse sizes beyond one LDS panel: MSFE 1440 nodes (unpivoted blocked
+    LU, 23 panels), MSFV 320 nodes (pivoted panels in global memory)."""
+    torch = _gpu
+    pb = _pb(shape, r, sigma=1.5, seed=12, restriction=restriction)
+    s = solver_for(pb)
+    s.build_basis()
+    p = pb.initial_pressure()
+    pt = torch.as_tensor(p, device="cuda")
+    s.assemble(pt, pt)
+    s.coarse_op()
+    Nc = s.Nc
+    Ac = to_np(s.export(C.CAMS_ARR_AC)).reshape(Nc, Nc)
+    Ainv = to_np(s.export(C.CAMS_ARR_AC_INV)).reshape(Nc, Nc)
+    log(pb.name, "Nc", Nc, "cond", np.linalg.cond(Ac))
+    assert np.max(np.abs(Ainv @ Ac - np.eye(Nc))) <= 1e-15 * np.linalg.cond(Ac) * 100
