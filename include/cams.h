@@ -139,6 +139,11 @@ cams_status cams_set_workspace(cams_ctx *ctx, void *dev_ptr, size_t bytes);
 cams_status cams_set_rock(cams_ctx *ctx, const double *perm_dev, const double *phi_dev,
                           const double *q_dev);
 
+/* Mark the basis (and the coarse operator) stale, so that the next
+ * cams_newton_step or batched iteration rebuilds it from the current
+ * transmissibilities.  Host only; no device call. */
+cams_status cams_invalidate_basis(cams_ctx *ctx);
+
 /* Dirichlet (well) cells: cells_host[n] are cell indices, p_host[n] their fixed
  * pressures (wells as fixed-pressure cells, Sec. 4.2 test case 2).
  * Replaces any earlier set.  n = 0 removes all wells (then c > 0 is required
@@ -289,6 +294,57 @@ int64_t cams_num_coarse(const cams_ctx *ctx);
 cams_status cams_destroy(cams_ctx *ctx);
 const char *cams_status_string(cams_status s);
 const char *cams_last_error(const cams_ctx *ctx);
+
+/* ---- Batched solve of many independent problems.
+ *
+ * One Newton iteration of Sec. 2 (assembly of Eqs. (3)-(6), basis of
+ * Eq. (11) if not built yet, coarse system of Eq. (13), C-AMS iterations of
+ * Table "cams" to lin_rtol, update p += delta) for every context of the
+ * batch at once.  Each C-AMS iteration is one launch per kernel over the
+ * cells of ALL instances; instances that have met their stopping test stop
+ * taking part.  The iterations run from HIP graphs captured at the first
+ * call; the number of iterations per graph is tuned on that call by timing
+ * (cams_batch_tuning reports the choice).
+ *
+ * The contexts must have been created on the same stream (the one given
+ * here), have their workspace and rock set, share precision and n_pre /
+ * n_post, use the block ILU(0) smoother and the local basis (no learned
+ * basis).  The batch keeps pointers to the contexts: destroy it before them.
+ * Each instance computes exactly what cams_newton_step with newton_maxit = 1
+ * computes for its first linear solve (same kernels, same order of
+ * floating-point operations within an instance).
+ */
+typedef struct cams_batch cams_batch;
+
+/* Group `count` contexts; builds the host work lists.  No HIP call.
+ * Errors: CAMS_E_ARG (null/duplicate context, different stream, precision
+ * or smoothing counts, red-black smoother), CAMS_E_NOMEM. */
+cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_stream, cams_batch **out);
+/* Device workspace of the batch (instance table, work lists, counters). */
+size_t cams_batch_workspace_bytes(const cams_batch *b);
+/* Attach the batch workspace (device memory, 256-byte aligned, caller
+ * owned, must outlive the batch) and upload the tables; call again after a
+ * context's workspace changes.  Creates the batch's own streams, events and
+ * a small pinned host buffer at the first call.  Synchronises. */
+cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes);
+/* One Newton iteration for every instance.  pn_dev[i], p_dev[i]: device
+ * pressures of instance i (p_dev[i] is updated in place).  status_out[i]
+ * (nullable): CAMS_OK, CAMS_E_NOT_CONVERGED (lin_maxit reached) or
+ * CAMS_E_BREAKDOWN.  stats[i] (nullable): newton_iters = 1, C-AMS
+ * iterations, relative residual, ||eps|| of the assembled iterate,
+ * t_coarse_ms = wall time of the overlapped setup phases of the batch,
+ * t_iterate_ms = wall time of the batched iterations.  Returns CAMS_OK when
+ * every instance succeeded, else the first failing instance's status.
+ * Synchronises. */
+cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_dev, double *const *p_dev,
+                                        int32_t *status_out, cams_stats *stats);
+/* Tuning outcome: iterations per graph replay (0 before the first call) and
+ * the measured ms per batched iteration of each of the `ncand` candidates
+ * (2, 4 and 8 iterations per graph; -1 where not measurable). */
+cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, double *ms_per_iter_candidates,
+                              int32_t ncand);
+const char *cams_batch_last_error(const cams_batch *b);
+void cams_batch_destroy(cams_batch *b);
 
 #ifdef __cplusplus
 }

@@ -107,6 +107,16 @@ _SIGS = [
     ("cams_destroy", _I, [_VP]),
     ("cams_status_string", ctypes.c_char_p, [_I]),
     ("cams_last_error", ctypes.c_char_p, [_VP]),
+    ("cams_invalidate_basis", _I, [_VP]),
+    ("cams_batch_create", _I, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
+    ("cams_batch_workspace_bytes", ctypes.c_size_t, [_VP]),
+    ("cams_batch_set_workspace", _I, [_VP, _VP, ctypes.c_size_t]),
+    ("cams_batch_newton_iteration", _I, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(cams_stats)]),
+    ("cams_batch_tuning", _I, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                               ctypes.c_int32]),
+    ("cams_batch_last_error", ctypes.c_char_p, [_VP]),
+    ("cams_batch_destroy", None, [_VP]),
 ]
 
 EXPORTED = [name for name, _, _ in _SIGS]
@@ -181,3 +191,11 @@ cams_profile_read = _fwd("cams_profile_read")
 cams_destroy = _fwd("cams_destroy")
 cams_status_string = _fwd("cams_status_string")
 cams_last_error = _fwd("cams_last_error")
+cams_batch_create = _fwd("cams_batch_create")
+cams_batch_workspace_bytes = _fwd("cams_batch_workspace_bytes")
+cams_batch_set_workspace = _fwd("cams_batch_set_workspace")
+cams_batch_newton_iteration = _fwd("cams_batch_newton_iteration")
+cams_batch_tuning = _fwd("cams_batch_tuning")
+cams_batch_last_error = _fwd("cams_batch_last_error")
+cams_batch_destroy = _fwd("cams_batch_destroy")
+cams_invalidate_basis = _fwd("cams_invalidate_basis")

@@ -564,6 +564,13 @@ cams_status cams_set_rock(cams_ctx *c, const double *perm_dev, const double *phi
     return CAMS_OK;
 }
 
+cams_status cams_invalidate_basis(cams_ctx *c)
+{
+    if (!c) return CAMS_E_ARG;
+    c->has_basis = c->has_coarse = false;
+    return CAMS_OK;
+}
+
 cams_status cams_set_wells(cams_ctx *c, const int64_t *cells, const double *p, int32_t n)
 {
     if (!c) return CAMS_E_ARG;
@@ -596,14 +603,45 @@ cams_status cams_set_wells(cams_ctx *c, const int64_t *cells, const double *p, i
     return CAMS_OK;
 }
 
+}  // extern "C"
+
+namespace cams {
+
+// Device work of the setup phases, enqueued without host synchronisation;
+// shared by the single-problem entry points and the batched solve.
+void enqueue_assemble(cams_ctx *c, const double *p, const double *pn)
+{
+    launch_assemble(c, p, pn);
+    launch_reduce(c, c->a.partial, (c->g.N + kBlock - 1) / kBlock, c->a.scal + S_EPS2);
+}
+
+void enqueue_basis_local(cams_ctx *c)
+{
+    launch_basis(c);
+    if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
+}
+
+void enqueue_coarse(cams_ctx *c)
+{
+    launch_coarse_operator(c);
+    launch_ilu_setup(c);
+    if (c->opt.precision != CAMS_FP64) launch_convert_matrix32(c);
+    launch_coarse_factor(c);
+}
+
+void enqueue_clear_status(cams_ctx *c) { clear_status(c); }
+
+}  // namespace cams
+
+extern "C" {
+
 cams_status cams_assemble(cams_ctx *c, const double *p_dev, const double *pn_dev, double *eps_norm_out)
 {
     if (!c) return CAMS_E_ARG;
     if (!c->has_rock) return fail(c, CAMS_E_STATE, "assemble before set_rock");
     if (!p_dev || !pn_dev) return fail(c, CAMS_E_ARG, "null pressure");
     try {
-        launch_assemble(c, p_dev, pn_dev);
-        launch_reduce(c, c->a.partial, (c->g.N + kBlock - 1) / kBlock, c->a.scal + S_EPS2);
+        enqueue_assemble(c, p_dev, pn_dev);
         CAMS_HIP(hipGetLastError());
         if (eps_norm_out) {
             double e2 = read_scalar(c, c->a.scal + S_EPS2);
@@ -627,10 +665,10 @@ cams_status cams_build_basis(cams_ctx *c)
         c->learned_blocks = c->fallback_blocks = 0;
         if (c->learned_params && c->nfull > 0) {
             build_basis_learned(c);
+            if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
         } else {
-            launch_basis(c);
+            enqueue_basis_local(c);
         }
-        if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
         CAMS_HIP(hipGetLastError());
         int32_t flags = 0;
         sync_status(c, &flags);
@@ -650,10 +688,7 @@ cams_status cams_coarse_op(cams_ctx *c)
     if (!c->has_system) return fail(c, CAMS_E_STATE, "coarse_op before assemble");
     try {
         clear_status(c);
-        launch_coarse_operator(c);
-        launch_ilu_setup(c);
-        if (c->opt.precision != CAMS_FP64) launch_convert_matrix32(c);
-        launch_coarse_factor(c);
+        enqueue_coarse(c);
         CAMS_HIP(hipGetLastError());
         int32_t flags = 0;
         sync_status(c, &flags);

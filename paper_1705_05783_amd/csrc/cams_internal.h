@@ -74,6 +74,43 @@ struct Arrays {
     float *r1f, *d0f, *d1f, *d2f, *zf;
 };
 
+// One instance of a batched solve as the batched kernels see it (a copy of
+// its context's grid descriptor and workspace pointers).
+struct InstDev {
+    GridDev g;
+    Arrays a;
+    int fe;           // MSFE restriction
+    int bf16;         // mixed precision with a bfloat16 basis
+    int n_pre, n_post;
+    int max_planes;   // restriction partials per coarse node
+    int nparts;       // residual partials, ceil(N / kBlock)
+    int maxit;
+    double rtol2;
+};
+
+// The share of a batched launch given to one workgroup.
+struct WorkItem {
+    int32_t inst;     // instance
+    int32_t blk;      // block of that instance (meaning set by the kernel)
+};
+
+// A batched launch: instance table, one work item per workgroup, stream.
+struct BatchLaunch {
+    const InstDev *inst;
+    const WorkItem *work;
+    int count;
+    hipStream_t stream;
+};
+
+// Per-instance results copied to the host after a batched solve.
+struct BatchResult {
+    int32_t it, done, outcome, status;
+    double eps2, r0n2, rn2;
+};
+
+// Slots of Arrays::ictl (iteration control).
+enum { C_IT = 0, C_DONE = 1, C_OUTCOME = 2, C_ARRIVE = 3, C_NODE = 4 };
+
 // Scalar slots in Arrays::scal.
 enum { S_EPS2 = 0, S_R0N2 = 1, S_RN2 = 2 };
 
@@ -181,6 +218,29 @@ void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, co
                            double *dp_out);
 void launch_finalize_ctl(cams_ctx *c);   // ||r||, stopping test, iteration counter
 void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *done);
+
+// ---- setup phases without host synchronisation (abi.hip)
+void enqueue_clear_status(cams_ctx *c);
+void enqueue_assemble(cams_ctx *c, const double *p, const double *pn);
+void enqueue_basis_local(cams_ctx *c);
+void enqueue_coarse(cams_ctx *c);
+
+// ---- batched iteration (one launch per kernel for all instances)
+void launch_batch_residual(const BatchLaunch &L, int par, bool mixed);
+void launch_batch_finalize(const InstDev *inst, int count, int32_t *ndone, hipStream_t st);
+void launch_batch_restrict(const BatchLaunch &L);
+void launch_batch_gather(const InstDev *inst, int count, BatchResult *out, hipStream_t st);
+void launch_batch_reset(const BatchLaunch &L);   // iteration state of every instance to its start
+void launch_batch_sum_planes(const BatchLaunch &L);
+void launch_batch_gemv(const BatchLaunch &L);
+void launch_batch_prolong(const BatchLaunch &L, bool mixed, bool bf16);
+void launch_batch_r1(const BatchLaunch &L, bool mixed);
+void launch_batch_sub_pre(const BatchLaunch &L, bool mixed);
+void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed);
+void launch_batch_update(const BatchLaunch &L, double *const *p);
+void launch_batch_prolong64(const BatchLaunch &L);
+void launch_batch_r1_64(const BatchLaunch &L);
+void launch_batch_sub_pre64(const BatchLaunch &L);
 
 // ---- basis (k_basis.hip)
 void launch_basis(cams_ctx *c);

@@ -53,4 +53,16 @@ __device__ __forceinline__ int node_index(const GridDev &g, int a, int b, int c)
     return a + g.nb[0] * (b + g.nb[1] * c);
 }
 
+// Cell of this thread in a flat batched launch, or -1; also returns the
+// instance descriptor and skips instances that have converged.
+__device__ __forceinline__ int flat_cell(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                         const InstDev *&d)
+{
+    const WorkItem w = work[blockIdx.x];
+    d = &inst[w.inst];
+    if (d->a.ictl[C_DONE]) return -1;
+    const int n = w.blk * kBlock + threadIdx.x;
+    return n < d->g.N ? n : -1;
+}
+
 }  // namespace cams

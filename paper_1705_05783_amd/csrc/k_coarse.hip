@@ -476,6 +476,39 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
     if (lane == 0) y[row] = s;
 }
 
+// Batched coarse solve: rc = sum of the plane partials (work item = block of
+// kBlock coarse nodes), then xc = Ainv rc (work item = kBlock/64 rows).
+__global__ __launch_bounds__(kBlock) void kb_sum_planes(const InstDev *__restrict__ inst,
+                                                         const WorkItem *__restrict__ work)
+{
+    const WorkItem w = work[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    if (d.a.ictl[C_DONE]) return;
+    const int k = w.blk * kBlock + threadIdx.x;
+    if (k >= d.g.Nc) return;
+    const double *pl = d.a.planes + (size_t)k * d.max_planes;
+    double s = 0.0;
+    for (int q = 0; q < d.max_planes; ++q) s += pl[q];
+    d.a.rc[k] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void kb_gemv(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+{
+    const WorkItem w = work[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    if (d.a.ictl[C_DONE]) return;
+    const int n = d.g.Nc;
+    const int row = w.blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double *mr = d.a.Ainv + (size_t)row * n;
+    const double *x = d.a.rc;
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    s = wave_sum(s);
+    if (lane == 0) d.a.xc[row] = s;
+}
+
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 void gemm(cams_ctx *c, double *C, int ldc, const double *A, int lda, const double *B, int ldb, int M, int Nn, int K,
@@ -617,6 +650,16 @@ void launch_gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, 
                      int Nn, int K)
 {
     gemm_sub(c, C, ldc, A, lda, B, ldb, M, Nn, K);
+}
+
+void launch_batch_sum_planes(const BatchLaunch &L)
+{
+    if (L.count > 0) kb_sum_planes<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+}
+
+void launch_batch_gemv(const BatchLaunch &L)
+{
+    if (L.count > 0) kb_gemv<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
 }
 
 }  // namespace cams

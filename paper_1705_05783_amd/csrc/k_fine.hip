@@ -176,14 +176,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil_sub(GridDev g, const double 
     out[n] = s;
 }
 
-// out = P_hat xc: the (up to) eight bracketing coarse nodes of each cell.
-__global__ __launch_bounds__(kBlock) void k_prolong(GridDev g, const double *__restrict__ P,
-                                                     const uint8_t *__restrict__ dm, const double *__restrict__ xc,
-                                                     double *__restrict__ out, const int32_t *done)
+// out[n] = (P_hat xc)[n]: the (up to) eight bracketing coarse nodes of cell n.
+__device__ __forceinline__ void prolong_body(const GridDev &g, const double *__restrict__ P,
+                                             const uint8_t *__restrict__ dm, const double *__restrict__ xc,
+                                             double *__restrict__ out, int n)
 {
-    if (done && *done) return;
-    int n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.N) return;
     double s = 0.0;
     if (!dm[n]) {
         Cell c = cell_of(g, n);
@@ -196,6 +193,16 @@ __global__ __launch_bounds__(kBlock) void k_prolong(GridDev g, const double *__r
         }
     }
     out[n] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_prolong(GridDev g, const double *__restrict__ P,
+                                                     const uint8_t *__restrict__ dm, const double *__restrict__ xc,
+                                                     double *__restrict__ out, const int32_t *done)
+{
+    if (done && *done) return;
+    int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    prolong_body(g, P, dm, xc, out, n);
 }
 
 // ILU(0) of A in red-black order (red = even i+j+k first).  Red rows keep
@@ -276,6 +283,51 @@ __global__ __launch_bounds__(kBlock) void k_axpy(double *__restrict__ y, const d
 {
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t < n) y[t] += x[t];
+}
+
+// ---- batched forms (FP64 solve): work item = (instance, block of kBlock cells)
+
+__global__ __launch_bounds__(kBlock) void kb_prolong(const InstDev *__restrict__ inst,
+                                                      const WorkItem *__restrict__ work)
+{
+    const InstDev *d;
+    const int n = flat_cell(inst, work, d);
+    if (n < 0) return;
+    prolong_body(d->g, d->a.P, d->a.dmask, d->a.xc, d->a.d1, n);
+}
+
+// r := r - A d1 (r1 of the FP64 solve, in place)
+__global__ __launch_bounds__(kBlock) void kb_r1(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+{
+    const InstDev *d;
+    const int n = flat_cell(inst, work, d);
+    if (n < 0) return;
+    Vec1 xv{d->a.d1};
+    d->a.r[n] -= apply_A(d->g, d->a.W, d->a.diag, xv, n, d->a.d1[n]);
+}
+
+// r := r - A d0 after pre-smoothing
+__global__ __launch_bounds__(kBlock) void kb_sub_pre(const InstDev *__restrict__ inst,
+                                                      const WorkItem *__restrict__ work)
+{
+    const InstDev *d;
+    const int n = flat_cell(inst, work, d);
+    if (n < 0) return;
+    Vec1 xv{d->a.d0};
+    d->a.r[n] -= apply_A(d->g, d->a.W, d->a.diag, xv, n, d->a.d0[n]);
+}
+
+// p += dp of the instance's last iteration (read from its own counter); runs
+// after the iteration has stopped, so the done flag is not consulted.
+__global__ __launch_bounds__(kBlock) void kb_update(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                                     double *const *__restrict__ p)
+{
+    const WorkItem w = work[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    const int n = w.blk * kBlock + threadIdx.x;
+    if (n >= d.g.N) return;
+    const int it = d.a.ictl[C_IT];
+    p[w.inst][n] += d.a.dp[(it + 1) & 1][n];
 }
 
 }  // namespace
@@ -363,6 +415,26 @@ void launch_rb_smooth(cams_ctx *c, const double *rhs, double *e, int steps)
 void launch_axpy(cams_ctx *c, double *y, const double *x, int n)
 {
     k_axpy<<<grid_blocks(n), kBlock, 0, c->stream>>>(y, x, n);
+}
+
+void launch_batch_update(const BatchLaunch &L, double *const *p)
+{
+    if (L.count > 0) kb_update<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work, p);
+}
+
+void launch_batch_prolong64(const BatchLaunch &L)
+{
+    if (L.count > 0) kb_prolong<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+}
+
+void launch_batch_r1_64(const BatchLaunch &L)
+{
+    if (L.count > 0) kb_r1<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+}
+
+void launch_batch_sub_pre64(const BatchLaunch &L)
+{
+    if (L.count > 0) kb_sub_pre<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
 }
 
 }  // namespace cams

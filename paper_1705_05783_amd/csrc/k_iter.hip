@@ -15,8 +15,6 @@ namespace cams {
 
 namespace {
 
-enum { C_IT = 0, C_DONE = 1, C_OUTCOME = 2, C_ARRIVE = 3, C_NODE = 4 };
-
 __global__ __launch_bounds__(kBlock) void k_iter_reset(int32_t *__restrict__ ictl, double *__restrict__ dp, int N,
                                                         int nctl)
 {
@@ -44,17 +42,16 @@ struct Pending {
     }
 };
 
+// r = r0 - A v over the cells of workgroup `blk`, dp_out = v, and the
+// workgroup's partial of ||r||^2.
 template <class TA>
-__global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double *__restrict__ W,
-                                                          const double *__restrict__ diag,
-                                                          const double *__restrict__ r0, Pending<TA> v,
-                                                          double *__restrict__ dp_out, double *__restrict__ r,
-                                                          double *__restrict__ partial, const int32_t *ictl)
+__device__ __forceinline__ void residual_body(const GridDev &g, const double *__restrict__ W,
+                                              const double *__restrict__ diag, const double *__restrict__ r0,
+                                              const Pending<TA> &v, double *__restrict__ dp_out,
+                                              double *__restrict__ r, double *__restrict__ partial, int blk,
+                                              double *sh)
 {
-    __shared__ double sh[kBlock / 64];
-    if (ictl[C_DONE]) return;
-    v.fold = ictl[C_IT] > 0;
-    const int n = blockIdx.x * kBlock + threadIdx.x;
+    const int n = blk * kBlock + threadIdx.x;
     double e2 = 0.0;
     if (n < g.N) {
         const Cell c = cell_of(g, n);
@@ -73,36 +70,57 @@ __global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double
         e2 = rr * rr;
     }
     const double bs = block_sum<kBlock>(e2, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+    if (threadIdx.x == 0) partial[blk] = bs;
+}
+
+template <class TA>
+__global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double *__restrict__ W,
+                                                          const double *__restrict__ diag,
+                                                          const double *__restrict__ r0, Pending<TA> v,
+                                                          double *__restrict__ dp_out, double *__restrict__ r,
+                                                          double *__restrict__ partial, const int32_t *ictl)
+{
+    __shared__ double sh[kBlock / 64];
+    if (ictl[C_DONE]) return;
+    v.fold = ictl[C_IT] > 0;
+    residual_body(g, W, diag, r0, v, dp_out, r, partial, blockIdx.x, sh);
 }
 
 // ||r||^2 from the residual kernel's partials and the stopping test.
+// Returns true (in thread 0) when this call ended the iteration.
+__device__ __forceinline__ bool finalize_body(const double *__restrict__ partial, int nparts, int32_t *ictl,
+                                              double *scal, double rtol2, int maxit, double *sh)
+{
+    double u = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += kBlock) u += partial[t];
+    const double s = block_sum<kBlock>(u, sh);
+    if (threadIdx.x != 0) return false;
+    const int it = ictl[C_IT];
+    if (it == 0) scal[S_R0N2] = s;
+    const double r0n2 = it == 0 ? s : scal[S_R0N2];
+    scal[S_RN2] = s;
+    int outcome = -1;
+    if (!(s < 1e300))                          // NaN or Inf
+        outcome = 2;
+    else if (s <= rtol2 * r0n2 || r0n2 == 0.0)
+        outcome = 0;
+    else if (it >= maxit)
+        outcome = 1;
+    if (outcome < 0) {
+        ictl[C_IT] = it + 1;
+        return false;
+    }
+    ictl[C_OUTCOME] = outcome;
+    ictl[C_DONE] = 1;
+    return true;
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize_ctl(const double *__restrict__ partial, int nparts,
                                                           int32_t *ictl, double *scal, double rtol2, int maxit)
 {
     __shared__ double sh[kBlock / 64];
     if (ictl[C_DONE]) return;
-    double u = 0.0;
-    for (int t = threadIdx.x; t < nparts; t += kBlock) u += partial[t];
-    const double s = block_sum<kBlock>(u, sh);
-    if (threadIdx.x == 0) {
-        const int it = ictl[C_IT];
-        if (it == 0) scal[S_R0N2] = s;
-        const double r0n2 = it == 0 ? s : scal[S_R0N2];
-        scal[S_RN2] = s;
-        if (!(s < 1e300)) {                      // NaN or Inf
-            ictl[C_OUTCOME] = 2;
-            ictl[C_DONE] = 1;
-        } else if (s <= rtol2 * r0n2 || r0n2 == 0.0) {
-            ictl[C_OUTCOME] = 0;
-            ictl[C_DONE] = 1;
-        } else if (it >= maxit) {
-            ictl[C_OUTCOME] = 1;
-            ictl[C_DONE] = 1;
-        } else {
-            ictl[C_IT] = it + 1;
-        }
-    }
+    finalize_body(partial, nparts, ictl, scal, rtol2, maxit, sh);
 }
 
 // Restriction R r (Eq. (13)/(15)): one workgroup per (coarse node, z-plane of
@@ -110,15 +128,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize_ctl(const double *__restric
 // support at ratio 8), covered by a 16 x 16 thread tile.  MSFV rows are the
 // primal block (weights 1); MSFE rows are the basis support (weights P_hat).
 // The coarse solve adds the plane sums of each row in order.
-__global__ __launch_bounds__(kBlock) void k_restrict_planes(GridDev g, const uint8_t *__restrict__ dm,
-                                                             const double *__restrict__ P, int fe,
-                                                             const double *__restrict__ r,
-                                                             double *__restrict__ planes, int max_planes,
-                                                             const int32_t *ictl)
+__device__ __forceinline__ void restrict_body(const GridDev &g, const uint8_t *__restrict__ dm,
+                                              const double *__restrict__ P, int fe, const double *__restrict__ r,
+                                              double *__restrict__ planes, int max_planes, int k, int pz,
+                                              double *sh)
 {
-    __shared__ double sh[kBlock / 64];
-    if (ictl[C_DONE]) return;
-    const int k = blockIdx.x, pz = blockIdx.y;
     const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
@@ -153,6 +167,100 @@ __global__ __launch_bounds__(kBlock) void k_restrict_planes(GridDev g, const uin
     }
     const double s = block_sum<kBlock>(v, sh);
     if (threadIdx.x == 0) planes[(size_t)k * max_planes + pz] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_restrict_planes(GridDev g, const uint8_t *__restrict__ dm,
+                                                             const double *__restrict__ P, int fe,
+                                                             const double *__restrict__ r,
+                                                             double *__restrict__ planes, int max_planes,
+                                                             const int32_t *ictl)
+{
+    __shared__ double sh[kBlock / 64];
+    if (ictl[C_DONE]) return;
+    restrict_body(g, dm, P, fe, r, planes, max_planes, blockIdx.x, blockIdx.y, sh);
+}
+
+// ---- batched forms: one launch covers every instance of a batch; the work
+// item of a workgroup names the instance and the block within it, and
+// workgroups of instances that have converged return at once.
+
+template <class TA>
+__device__ __forceinline__ Pending<TA> pending_of(const InstDev &d, int par, bool fold);
+
+template <>
+__device__ __forceinline__ Pending<double> pending_of<double>(const InstDev &d, int par, bool fold)
+{
+    return Pending<double>{d.a.dp[par], d.n_pre > 0 ? d.a.d0 : nullptr, d.a.d1, d.n_post > 0 ? d.a.d2 : nullptr,
+                           fold};
+}
+
+template <>
+__device__ __forceinline__ Pending<float> pending_of<float>(const InstDev &d, int par, bool fold)
+{
+    return Pending<float>{d.a.dp[par], d.n_pre > 0 ? d.a.d0f : nullptr, d.a.d1f, d.n_post > 0 ? d.a.d2f : nullptr,
+                          fold};
+}
+
+template <class TA>
+__global__ __launch_bounds__(kBlock) void kb_residual(const InstDev *__restrict__ inst,
+                                                       const WorkItem *__restrict__ work, int par)
+{
+    __shared__ double sh[kBlock / 64];
+    const WorkItem w = work[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    if (d.a.ictl[C_DONE]) return;
+    const Pending<TA> v = pending_of<TA>(d, par, d.a.ictl[C_IT] > 0);
+    residual_body(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, d.a.partial, w.blk, sh);
+}
+
+// One workgroup per instance; `ndone` counts the instances that have stopped.
+__global__ __launch_bounds__(kBlock) void kb_finalize(const InstDev *__restrict__ inst, int32_t *ndone)
+{
+    __shared__ double sh[kBlock / 64];
+    const InstDev &d = inst[blockIdx.x];
+    if (d.a.ictl[C_DONE]) return;
+    if (finalize_body(d.a.partial, d.nparts, d.a.ictl, d.a.scal, d.rtol2, d.maxit, sh)) atomicAdd(ndone, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_restrict(const InstDev *__restrict__ inst,
+                                                       const WorkItem *__restrict__ work)
+{
+    __shared__ double sh[kBlock / 64];
+    const WorkItem w = work[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    if (d.a.ictl[C_DONE]) return;
+    restrict_body(d.g, d.a.dmask, d.a.P, d.fe, d.a.r, d.a.planes, d.max_planes, w.blk / d.max_planes,
+                  w.blk % d.max_planes, sh);
+}
+
+// Iteration state of every instance back to its start (dp = 0, counters 0);
+// work item = (instance, block of kBlock cells).
+__global__ __launch_bounds__(kBlock) void kb_reset(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+{
+    const WorkItem w = work[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    const int n = w.blk * kBlock + threadIdx.x;
+    if (n < d.g.N) d.a.dp[0][n] = 0.0;
+    if (w.blk == 0)
+        for (int t = threadIdx.x; t < C_NODE + d.g.Nc; t += kBlock) d.a.ictl[t] = 0;
+}
+
+// Iteration counters, outcomes and norms of every instance, for one copy to the host.
+__global__ __launch_bounds__(kBlock) void kb_gather(const InstDev *__restrict__ inst, int count,
+                                                     BatchResult *__restrict__ out)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= count) return;
+    const InstDev &d = inst[t];
+    BatchResult r;
+    r.it = d.a.ictl[C_IT];
+    r.done = d.a.ictl[C_DONE];
+    r.outcome = d.a.ictl[C_OUTCOME];
+    r.status = d.a.status[0];
+    r.eps2 = d.a.scal[S_EPS2];
+    r.r0n2 = d.a.scal[S_R0N2];
+    r.rn2 = d.a.scal[S_RN2];
+    out[t] = r;
 }
 
 }  // namespace
@@ -192,6 +300,35 @@ void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *)
     dim3 grid(c->g.Nc, c->max_planes);
     k_restrict_planes<<<grid, kBlock, 0, c->stream>>>(c->g, c->a.dmask, c->a.P, c->opt.restriction == CAMS_R_FE, r,
                                                       c->a.planes, c->max_planes, c->a.ictl);
+}
+
+void launch_batch_residual(const BatchLaunch &L, int par, bool mixed)
+{
+    if (L.count <= 0) return;
+    if (mixed)
+        kb_residual<float><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work, par);
+    else
+        kb_residual<double><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work, par);
+}
+
+void launch_batch_finalize(const InstDev *inst, int count, int32_t *ndone, hipStream_t st)
+{
+    kb_finalize<<<count, kBlock, 0, st>>>(inst, ndone);
+}
+
+void launch_batch_restrict(const BatchLaunch &L)
+{
+    if (L.count > 0) kb_restrict<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+}
+
+void launch_batch_reset(const BatchLaunch &L)
+{
+    if (L.count > 0) kb_reset<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+}
+
+void launch_batch_gather(const InstDev *inst, int count, BatchResult *out, hipStream_t st)
+{
+    kb_gather<<<(count + kBlock - 1) / kBlock, kBlock, 0, st>>>(inst, count, out);
 }
 
 }  // namespace cams

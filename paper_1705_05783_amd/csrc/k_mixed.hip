@@ -51,14 +51,10 @@ __global__ __launch_bounds__(kBlock) void k_round_basis(double *__restrict__ P, 
 
 // out = P_hat xc in FP32 (basis stored as float or bfloat16).
 template <int BF>
-__global__ __launch_bounds__(kBlock) void k_prolong_lo(GridDev g, const float *__restrict__ P32,
-                                                        const uint16_t *__restrict__ Pbf,
-                                                        const uint8_t *__restrict__ dm, const double *__restrict__ xc,
-                                                        float *__restrict__ out, const int32_t *done)
+__device__ __forceinline__ void prolong_lo_body(const GridDev &g, const float *__restrict__ P32,
+                                                const uint16_t *__restrict__ Pbf, const uint8_t *__restrict__ dm,
+                                                const double *__restrict__ xc, float *__restrict__ out, int n)
 {
-    if (done && *done) return;
-    const int n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.N) return;
     float s = 0.f;
     if (!dm[n]) {
         const Cell c = cell_of(g, n);
@@ -73,14 +69,23 @@ __global__ __launch_bounds__(kBlock) void k_prolong_lo(GridDev g, const float *_
     out[n] = s;
 }
 
-// out = r - A32 x in FP32 (r given in FP64).
-__global__ __launch_bounds__(kBlock) void k_r1_lo(GridDev g, const float *__restrict__ W, const float *__restrict__ diag,
-                                                   const double *__restrict__ r, const float *__restrict__ x,
-                                                   float *__restrict__ out, const int32_t *done)
+template <int BF>
+__global__ __launch_bounds__(kBlock) void k_prolong_lo(GridDev g, const float *__restrict__ P32,
+                                                        const uint16_t *__restrict__ Pbf,
+                                                        const uint8_t *__restrict__ dm, const double *__restrict__ xc,
+                                                        float *__restrict__ out, const int32_t *done)
 {
     if (done && *done) return;
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
+    prolong_lo_body<BF>(g, P32, Pbf, dm, xc, out, n);
+}
+
+// out = r - A32 x in FP32 (r given in FP64).
+__device__ __forceinline__ void r1_lo_body(const GridDev &g, const float *__restrict__ W,
+                                           const float *__restrict__ diag, const double *__restrict__ r,
+                                           const float *__restrict__ x, float *__restrict__ out, int n)
+{
     const Cell c = cell_of(g, n);
     const float *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
     float s = diag[n] * x[n];
@@ -93,14 +98,21 @@ __global__ __launch_bounds__(kBlock) void k_r1_lo(GridDev g, const float *__rest
     out[n] = (float)r[n] - s;
 }
 
-// r -= A x in FP64 with an FP32 correction x (pre-smoothing update).
-__global__ __launch_bounds__(kBlock) void k_sub64_lo(GridDev g, const double *__restrict__ W,
-                                                      const double *__restrict__ diag, const float *__restrict__ x,
-                                                      double *__restrict__ r, const int32_t *done)
+__global__ __launch_bounds__(kBlock) void k_r1_lo(GridDev g, const float *__restrict__ W, const float *__restrict__ diag,
+                                                   const double *__restrict__ r, const float *__restrict__ x,
+                                                   float *__restrict__ out, const int32_t *done)
 {
     if (done && *done) return;
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
+    r1_lo_body(g, W, diag, r, x, out, n);
+}
+
+// r -= A x in FP64 with an FP32 correction x (pre-smoothing update).
+__device__ __forceinline__ void sub64_lo_body(const GridDev &g, const double *__restrict__ W,
+                                              const double *__restrict__ diag, const float *__restrict__ x,
+                                              double *__restrict__ r, int n)
+{
     const Cell c = cell_of(g, n);
     const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
     double s = diag[n] * (double)x[n];
@@ -111,6 +123,45 @@ __global__ __launch_bounds__(kBlock) void k_sub64_lo(GridDev g, const double *__
     if (c.k > 0) s -= Wz[n - g.sxy] * (double)x[n - g.sxy];
     if (c.k + 1 < g.nz) s -= Wz[n] * (double)x[n + g.sxy];
     r[n] -= s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub64_lo(GridDev g, const double *__restrict__ W,
+                                                      const double *__restrict__ diag, const float *__restrict__ x,
+                                                      double *__restrict__ r, const int32_t *done)
+{
+    if (done && *done) return;
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    sub64_lo_body(g, W, diag, x, r, n);
+}
+
+// ---- batched forms: work item = (instance, block of kBlock cells)
+
+template <int BF>
+__global__ __launch_bounds__(kBlock) void kb_prolong_lo(const InstDev *__restrict__ inst,
+                                                         const WorkItem *__restrict__ work)
+{
+    const InstDev *d;
+    const int n = flat_cell(inst, work, d);
+    if (n < 0) return;
+    prolong_lo_body<BF>(d->g, d->a.P32, d->a.Pbf, d->a.dmask, d->a.xc, d->a.d1f, n);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_r1_lo(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+{
+    const InstDev *d;
+    const int n = flat_cell(inst, work, d);
+    if (n < 0) return;
+    r1_lo_body(d->g, d->a.W32, d->a.diag32, d->a.r, d->a.d1f, d->a.r1f, n);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_sub64_lo(const InstDev *__restrict__ inst,
+                                                       const WorkItem *__restrict__ work)
+{
+    const InstDev *d;
+    const int n = flat_cell(inst, work, d);
+    if (n < 0) return;
+    sub64_lo_body(d->g, d->a.W, d->a.diag, d->a.d0f, d->a.r, n);
 }
 
 }  // namespace
@@ -148,6 +199,35 @@ void launch_r1_32(cams_ctx *c, const double *r, const float *x, float *out, cons
 void launch_sub64_lo(cams_ctx *c, const float *x, double *r, const int32_t *done)
 {
     k_sub64_lo<<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, x, r, done);
+}
+
+void launch_batch_prolong(const BatchLaunch &L, bool mixed, bool bf16)
+{
+    if (L.count <= 0) return;
+    if (!mixed)
+        launch_batch_prolong64(L);
+    else if (bf16)
+        kb_prolong_lo<1><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    else
+        kb_prolong_lo<0><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+}
+
+void launch_batch_r1(const BatchLaunch &L, bool mixed)
+{
+    if (L.count <= 0) return;
+    if (mixed)
+        kb_r1_lo<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    else
+        launch_batch_r1_64(L);
+}
+
+void launch_batch_sub_pre(const BatchLaunch &L, bool mixed)
+{
+    if (L.count <= 0) return;
+    if (mixed)
+        kb_sub64_lo<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    else
+        launch_batch_sub_pre64(L);
 }
 
 }  // namespace cams

@@ -45,11 +45,11 @@ struct BlockCell {
     bool active;
 };
 
-__device__ __forceinline__ BlockCell block_cell(const GridDev &g)
+// Cell of this thread in logical block `id` (x fastest, then y, then z).
+__device__ __forceinline__ BlockCell block_cell(const GridDev &g, int id)
 {
     BlockCell b;
     const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
-    const int id = xcd_swizzle(blockIdx.x, gridDim.x);
     const int bx = id % nbx, by = (id / nbx) % nby, bz = id / (nbx * nby);
     const int i0 = bx * SB, j0 = by * SB, k0 = bz * SB;
     b.ex = min(SB, g.nx - i0);
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(ST) void k_bilu_setup(GridDev g, const double *__re
                                                     int32_t *status)
 {
     __shared__ double d[ST];
-    const BlockCell b = block_cell(g);
+    const BlockCell b = block_cell(g, xcd_swizzle(blockIdx.x, gridDim.x));
     const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
     double dg = 1.0, wxm = 0.0, wym = 0.0, wzm = 0.0;
     if (b.active) {
@@ -113,18 +113,16 @@ __global__ __launch_bounds__(ST) void k_bilu_setup(GridDev g, const double *__re
 // T: arithmetic and storage of the smoother (double, or float in the mixed
 // precision solve); TR: type of the right-hand side.
 template <class T, class TR>
-__global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
-                                                   const T *__restrict__ invd, const TR *__restrict__ rhs,
-                                                   const T *__restrict__ eold, T *__restrict__ enew,
-                                                   const int32_t *done)
+__device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
+                                               const T *__restrict__ invd, const TR *__restrict__ rhs,
+                                               const T *__restrict__ eold, T *__restrict__ enew, int blk)
 {
     // y and the +x/+y/+z couplings carry SB*SB zero entries on both sides, so
     // the sweeps read neighbours without bounds tests: a coupling that leaves
     // the block (or the grid) is zero, and its partner value is finite.
     constexpr int PAD = SB * SB;
     __shared__ T y[ST + 2 * PAD], wx[ST + 2 * PAD], wy[ST + 2 * PAD], wz[ST + 2 * PAD], dinv[ST];
-    if (done && *done) return;
-    const BlockCell b = block_cell(g);
+    const BlockCell b = block_cell(g, blk);
     const T *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
     T z = 0, e0 = 0, id = 0, fx = 0, fy = 0, fz = 0;
     if (b.active) {
@@ -197,6 +195,47 @@ __global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const T *__restrict
     if (b.active) enew[b.n] = e0 + y[PAD + b.t];
 }
 
+template <class T, class TR>
+__global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
+                                                   const T *__restrict__ invd, const TR *__restrict__ rhs,
+                                                   const T *__restrict__ eold, T *__restrict__ enew,
+                                                   const int32_t *done)
+{
+    if (done && *done) return;
+    bilu_step_body<T, TR>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x));
+}
+
+// Batched step `s` of `steps` for every instance.  `post` selects the
+// correction (post-smoothing d2, else pre-smoothing d0); the right-hand side
+// is r, or in the mixed-precision post-smoothing the FP32 r1.  The work list
+// is ordered host-side so that each XCD receives a contiguous range of
+// logical blocks.
+template <class T, class TR>
+__global__ __launch_bounds__(ST) void kb_bilu_step(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                                    int post, int s, int steps)
+{
+    const WorkItem w = work[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    if (d.a.ictl[C_DONE]) return;
+    const Arrays &a = d.a;
+    const T *W, *diag, *invd;
+    T *e, *scratch;
+    if constexpr (sizeof(T) == 4) {
+        W = a.W32; diag = a.diag32; invd = a.invd32; e = post ? a.d2f : a.d0f; scratch = a.zf;
+    } else {
+        W = a.W; diag = a.diag; invd = a.invd; e = post ? a.d2 : a.d0; scratch = a.z;
+    }
+    const TR *rhs;
+    if constexpr (sizeof(TR) == 4)
+        rhs = a.r1f;
+    else
+        rhs = a.r;
+    T *buf[2] = {e, scratch};
+    T *out = buf[(steps - 1 - s) & 1];
+    const T *prev = s > 0 ? buf[(steps - s) & 1] : nullptr;
+    bilu_step_body<T, TR>(d.g, W, diag, invd, rhs, prev, out, w.blk);
+}
+
 inline int num_sblocks(const GridDev &g)
 {
     return ((g.nx + SB - 1) / SB) * ((g.ny + SB - 1) / SB) * ((g.nz + SB - 1) / SB);
@@ -249,6 +288,22 @@ void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, co
 void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done)
 {
     bilu_smooth<float, double>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done);
+}
+
+// Batched smoothing: `steps` Richardson steps from zero for every instance.
+// rhs_kind 0: pre-smoothing on r; 1: post-smoothing (on r1 in FP32 when mixed,
+// else on r, which then holds r1).
+void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed)
+{
+    if (L.count <= 0) return;
+    for (int s = 0; s < steps; ++s) {
+        if (!mixed)
+            kb_bilu_step<double, double><<<L.count, ST, 0, L.stream>>>(L.inst, L.work, rhs_kind, s, steps);
+        else if (rhs_kind == 1)
+            kb_bilu_step<float, float><<<L.count, ST, 0, L.stream>>>(L.inst, L.work, rhs_kind, s, steps);
+        else
+            kb_bilu_step<float, double><<<L.count, ST, 0, L.stream>>>(L.inst, L.work, rhs_kind, s, steps);
+    }
 }
 
 }  // namespace cams

@@ -139,3 +139,15 @@ def train(feat, tgt, epochs=3, batch=256, lr=1e-3, seed=0, log=None, time_limit=
         if time_limit and time.time() - t0 > time_limit:
             break
     return params, hist
+
+
+def evaluate(params, feat, tgt, batch=256):
+    """Mean loss of `params` over all patches (no update)."""
+    tr = Trainer(params, batch)
+    tot, n = 0.0, feat.shape[0]
+    for b0 in range(0, n, batch):
+        b = min(batch, n - b0)
+        loss, _ = tr.loss_grad(feat[b0:b0 + b], tgt[b0:b0 + b])
+        tot += float(loss) * b
+    return tot / max(1, n)
+

@@ -72,6 +72,10 @@ class Solver:
         C.check(C.cams_set_rock(self.ctx, _ptr(perm), _ptr(phi), _ptr(q) if q is not None else None),
                 self.ctx, "cams_set_rock")
 
+    def invalidate_basis(self):
+        """The next step rebuilds the basis from the current transmissibilities."""
+        C.check(C.cams_invalidate_basis(self.ctx), self.ctx, "cams_invalidate_basis")
+
     # ---- the five hot-path calls
     def assemble(self, p: torch.Tensor, pn: torch.Tensor) -> float:
         e = ctypes.c_double()

@@ -134,3 +134,49 @@ def test_mixed_precision_needs_block_smoother(lib):
     s, h = _create(opt=o)
     assert C.cams_workspace_bytes(h) < n_mixed
     C.cams_destroy(h)
+
+
+def test_batch_create_validation(lib):
+    """cams_batch_create checks its contexts on the host (no HIP call)."""
+    from paper_1705_05783_amd import _cams as C
+
+    def opts(**kw):
+        o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_MIXED_FP32, 0, 1e-8, 100, 1e-8, 1)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    ctxs = []
+    for g in (C.cams_grid(16, 16, 8, 1.0, 1.0, 1.0, 4, 4, 4), C.cams_grid(20, 12, 9, 1.0, 1.0, 1.0, 5, 4, 3)):
+        s, h = _create(grid=g, opt=opts())
+        assert s == C.CAMS_OK
+        ctxs.append(h)
+
+    def create(hs):
+        arr = (ctypes.c_void_p * len(hs))(*[h.value for h in hs])
+        b = ctypes.c_void_p()
+        return C.cams_batch_create(arr, len(hs), None, ctypes.byref(b)), b
+
+    s, b = create(ctxs)
+    assert s == C.CAMS_OK
+    assert C.cams_batch_workspace_bytes(b) % 256 == 0 and C.cams_batch_workspace_bytes(b) > 0
+    # before a workspace is attached, a solve is refused on the host
+    assert C.cams_batch_newton_iteration(b, None, None, None, None) == C.CAMS_E_ARG
+    C.cams_batch_destroy(b)
+    s, b = create([ctxs[0], ctxs[0]])              # the same context twice
+    assert s == C.CAMS_E_ARG
+    s, h = _create(opt=opts(precision=C.CAMS_FP64))  # different precision
+    s2, b = create([ctxs[0], h])
+    assert s2 == C.CAMS_E_ARG
+    C.cams_destroy(h)
+    s, h = _create(opt=opts(n_post=3))             # different smoothing count
+    s2, b = create([ctxs[0], h])
+    assert s2 == C.CAMS_E_ARG
+    C.cams_destroy(h)
+    s, h = _create(opt=opts(precision=C.CAMS_FP64, smoother=C.CAMS_SMOOTH_RB_ILU0))
+    s2, b = create([h])                              # red-black smoother is not batched
+    assert s2 == C.CAMS_E_ARG
+    C.cams_destroy(h)
+    assert C.cams_batch_create(None, 0, None, ctypes.byref(ctypes.c_void_p())) == C.CAMS_E_ARG
+    for h in ctxs:
+        C.cams_destroy(h)

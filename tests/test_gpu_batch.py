@@ -1,0 +1,179 @@
+"""Batched solve (cams_batch_*) against the oracle and the single-problem path.
+
+Every instance of a batch must compute what one Newton iteration of its own
+problem computes: the oracle's Newton update (one iteration, linear solves
+to 1e-12 on both sides: relative error of the update <= 1e-9), and the
+single-problem path's result (same kernels and the same order of operations
+per instance: relative difference <= 1e-12, equal iteration counts).  At
+the full 256-instance size every instance's residual is recomputed by the
+oracle (||r0 - A delta|| <= lin_rtol ||r0|| up to rounding) and sampled
+instances are compared with the single-problem path.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import log, rel_err, require_gpu, to_np
+from workloads import small_problem
+from workloads.configs import FE, FP64, FV, MIXED_BF16, MIXED_FP32, batch_problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _instances(precision, n_pre=0, rtol=1e-12):
+    """Uneven shapes, ratios and restrictions, one instance at rest."""
+    specs = [
+        ((16, 12, 8), 4, FE, dict(sigma=2.0, seed=3, c=0.1)),
+        ((19, 17, 11), (4, 3, 5), FE, dict(sigma=2.5, seed=4, c=0.05)),
+        ((24, 24, 16), 8, FE, dict(sigma=3.0, seed=5, c=0.2)),
+        ((10, 9, 12), (2, 3, 2), FV, dict(sigma=1.5, seed=6, c=0.01)),
+        ((8, 8, 8), 8, FE, dict(sigma=1.0, seed=7, c=0.1)),
+        ((33, 21, 17), (5, 4, 6), FV, dict(sigma=2.0, seed=8, c=0.1)),
+        ((20, 20, 1), 4, FE, dict(sigma=2.0, seed=9, c=0.1)),
+        ((16, 12, 8), 4, FE, dict(sigma=2.0, seed=10, c=0.1, wells="none")),   # at rest: r0 = 0
+    ]
+    out = []
+    for shape, r, restr, kw in specs:
+        pb = small_problem(*shape, r, restriction=restr, n_pre=n_pre, **kw)
+        out.append(pb.with_options(precision=precision, lin_rtol=rtol, newton_maxit=1))
+    return out
+
+
+def _start(pb):
+    p = pb.initial_pressure()
+    if not pb.wells:
+        p = np.full(pb.n, 0.3)
+    return p
+
+
+def _run_batch(torch, pbs):
+    from paper_1705_05783_amd.batch import Batch
+    b = Batch.from_problems(pbs)
+    pn = [torch.as_tensor(_start(pb), device="cuda") for pb in pbs]
+    p = [t.clone() for t in pn]
+    status, stats = b.newton_iteration(pn, p)
+    return b, status, stats, [to_np(t) for t in p]
+
+
+def _oracle_update(pb, lin_rtol):
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = _start(pb)
+    p, rc, st = oracle.newton_step(pb, T, P, p0, p0, lin_rtol=lin_rtol, newton_maxit=1)
+    return p - p0, st
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED_FP32, MIXED_BF16])
+def test_batch_matches_oracle(torch, precision):
+    pbs = _instances(precision)
+    b, status, stats, p = _run_batch(torch, pbs)
+    log("batch", precision, status, [s["lin_iters_last"] for s in stats], b.tuning())
+    for pb, s, st, pg in zip(pbs, status, stats, p):
+        assert s == 0, (pb.name, s)
+        d_gpu = pg - _start(pb)
+        if not pb.wells:
+            assert st["lin_iters_last"] == 0 and np.max(np.abs(d_gpu)) == 0.0
+            continue
+        d_ref, ost = _oracle_update(pb, 1e-12)
+        err = rel_err(d_gpu, d_ref)
+        log(pb.name, "iters", st["lin_iters_last"], "oracle", ost["lin_iters"], "err", err)
+        assert err <= 1e-9, pb.name
+        assert st["relres_last"] <= 1e-12
+    b.close()
+
+
+@pytest.mark.parametrize("precision,n_pre", [(FP64, 0), (FP64, 2), (MIXED_FP32, 1), (MIXED_BF16, 0)])
+def test_batch_matches_single_path(torch, precision, n_pre):
+    from paper_1705_05783_amd.solver import Solver
+    pbs = _instances(precision, n_pre=n_pre, rtol=1e-8)
+    b, status, stats, p = _run_batch(torch, pbs)
+    for pb, s, st, pg in zip(pbs, status, stats, p):
+        assert s == 0, (pb.name, s)
+        sv = Solver(pb)
+        pn = torch.as_tensor(_start(pb), device="cuda")
+        ps = pn.clone()
+        single = sv.newton_step(pn, ps, check=False)
+        first = single["lin_iters_total"] if single["newton_iters"] else 0
+        diff = rel_err(pg, to_np(ps))
+        log(pb.name, "batch iters", st["lin_iters_last"], "single", first, "diff", diff)
+        assert st["lin_iters_last"] == first, pb.name
+        assert diff <= 1e-12, pb.name
+        sv.close()
+    b.close()
+
+
+def test_batch_second_call_replays_the_tuned_graph(torch):
+    """The second call runs the chosen graph only; it must reproduce the first
+    call's result bit for bit from the same starting state."""
+    from paper_1705_05783_amd.batch import Batch
+    pbs = _instances(MIXED_FP32, rtol=1e-8)
+    b = Batch.from_problems(pbs)
+    pn = [torch.as_tensor(_start(pb), device="cuda") for pb in pbs]
+    runs = []
+    for rep in range(2):
+        p = [t.clone() for t in pn]
+        status, stats = b.newton_iteration(pn, p)
+        assert all(s == 0 for s in status)
+        runs.append(([to_np(t) for t in p], [s["lin_iters_last"] for s in stats]))
+    t = b.tuning()
+    log("tuning", t)
+    assert t["iters_per_graph"] in (2, 4, 8)
+    assert runs[0][1] == runs[1][1]
+    for a, c in zip(runs[0][0], runs[1][0]):
+        assert np.array_equal(a, c)
+    b.close()
+
+
+def test_batch_of_one_and_iteration_limit(torch):
+    """A batch of one instance; an instance that reaches lin_maxit reports
+    CAMS_E_NOT_CONVERGED while the others finish."""
+    from paper_1705_05783_amd import _cams as C
+    pbs = _instances(FP64, rtol=1e-8)[:3]
+    b, status, stats, _ = _run_batch(torch, pbs[:1])
+    assert status == [0]
+    b.close()
+    pbs[1] = pbs[1].with_options(lin_maxit=2)
+    b, status, stats, _ = _run_batch(torch, pbs)
+    log("limit", status, [s["lin_iters_last"] for s in stats])
+    assert status[0] == 0 and status[2] == 0
+    assert status[1] == C.CAMS_E_NOT_CONVERGED and stats[1]["lin_iters_last"] == 2
+    b.close()
+
+
+def test_batch_full_size_256_instances(torch):
+    """The 256-instance uneven batch (mixed precision, one Newton iteration):
+    every instance's update meets the linear tolerance on the oracle's own
+    FP64 matrix, and sampled instances match the single-problem path."""
+    from paper_1705_05783_amd.solver import Solver
+    pbs = batch_problems()
+    log("cells", sum(pb.n for pb in pbs))
+    b, status, stats, p = _run_batch(torch, pbs)
+    its = [s["lin_iters_last"] for s in stats]
+    log("status", set(status), "iters min/max", min(its), max(its), "tuning", b.tuning(),
+        "setup ms", stats[0]["t_coarse_ms"], "iterate ms", stats[0]["t_iterate_ms"])
+    assert all(s == 0 for s in status)
+    for i, pb in enumerate(pbs):
+        T = oracle.transmissibility(pb)
+        p0 = _start(pb)
+        W, diag, r0, _ = oracle.linear_system(pb, T, p0, p0)
+        r = r0 - oracle.matvec(pb, W, diag, p[i] - p0)
+        rel = np.linalg.norm(r) / np.linalg.norm(r0)
+        assert rel <= 1e-8 * 1.01 + 1e-12, (pb.name, rel)
+    order = np.argsort([pb.n for pb in pbs])
+    for i in (order[0], order[len(order) // 2], order[-1]):
+        pb = pbs[i]
+        sv = Solver(pb)
+        pn = torch.as_tensor(_start(pb), device="cuda")
+        ps = pn.clone()
+        single = sv.newton_step(pn, ps, check=False)
+        diff = rel_err(p[i], to_np(ps))
+        log(pb.name, "diff vs single", diff)
+        assert diff <= 1e-12 and single["lin_iters_total"] == its[i]
+        sv.close()
+    b.close()
