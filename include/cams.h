@@ -303,8 +303,8 @@ const char *cams_last_error(const cams_ctx *ctx);
  * batch at once.  Each C-AMS iteration is one launch per kernel over the
  * cells of ALL instances; instances that have met their stopping test stop
  * taking part.  The iterations run from HIP graphs captured at the first
- * call; the number of iterations per graph is tuned on that call by timing
- * (cams_batch_tuning reports the choice).
+ * call; the smoother's workgroup size and the number of iterations per
+ * graph are tuned on that call by timing (cams_batch_tuning reports them).
  *
  * The contexts must have been created on the same stream (the one given
  * here), have their workspace and rock set, share precision and n_pre /
@@ -338,10 +338,13 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes);
  * Synchronises. */
 cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_dev, double *const *p_dev,
                                         int32_t *status_out, cams_stats *stats);
-/* Tuning outcome: iterations per graph replay (0 before the first call) and
- * the measured ms per batched iteration of each of the `ncand` candidates
- * (2, 4 and 8 iterations per graph; -1 where not measurable). */
-cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, double *ms_per_iter_candidates,
+/* Tuning outcome (0 / unset before the first call): iterations per graph
+ * replay and the smoother's threads per 8x8x8 block, with the measured ms
+ * per batched iteration of the graph candidates (2, 4, 8 iterations per
+ * graph) and ms per smoothing step of the workgroup candidates (128, 256,
+ * 512 threads); `ncand` entries of each array are written (arrays nullable). */
+cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, int32_t *smoother_threads,
+                              double *ms_per_iter_candidates, double *ms_per_smooth_step_candidates,
                               int32_t ncand);
 const char *cams_batch_last_error(const cams_batch *b);
 void cams_batch_destroy(cams_batch *b);

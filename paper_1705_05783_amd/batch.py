@@ -62,10 +62,12 @@ class Batch:
         return list(st), [s.as_dict() for s in stats]
 
     def tuning(self):
-        k = ctypes.c_int32()
-        ms = (ctypes.c_double * 3)()
-        _check(C.cams_batch_tuning(self.handle, ctypes.byref(k), ms, 3), self.handle, "cams_batch_tuning")
-        return {"iters_per_graph": k.value, "ms_per_iter": list(ms)}
+        k, nt = ctypes.c_int32(), ctypes.c_int32()
+        ms, sm = (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+        _check(C.cams_batch_tuning(self.handle, ctypes.byref(k), ctypes.byref(nt), ms, sm, 3), self.handle,
+               "cams_batch_tuning")
+        return {"iters_per_graph": k.value, "smoother_threads": nt.value, "ms_per_iter": list(ms),
+                "ms_per_smooth_step": list(sm)}
 
     def close(self):
         if self.handle:

@@ -403,24 +403,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     put(L.add(t.regions.size() * sizeof(Region) + 16));  // 29 regions
     put(L.add(nc * 8 * 8));    // 30 restriction slot sums
     put(L.add((nc + 64) * 4));   // 31 iteration control
-    // restriction rows: largest number of z-planes
-    {
-        int mp = 1;
-        std::vector<int32_t> vz = three_d ? vertex_coords(n[2], r[2]) : std::vector<int32_t>{0};
-        for (int b = 0; b < nb[2]; ++b) {
-            int lo, hi;
-            if (O.restriction == CAMS_R_FE) {
-                lo = b > 0 ? vz[b - 1] + 1 : 0;
-                hi = b < nb[2] - 1 ? vz[b + 1] - 1 : n[2] - 1;
-            } else {
-                lo = b * r[2];
-                hi = std::min((b + 1) * r[2], n[2]) - 1;
-            }
-            mp = std::max(mp, hi - lo + 1);
-        }
-        c->max_planes = mp;
-    }
-    put(L.add(nc * (size_t)c->max_planes * 8));   // 32 restriction plane partials
+    put(L.add(0));             // 32 (unused)
     const bool mixed = O.precision != CAMS_FP64;
     const size_t n4 = mixed ? (size_t)g.N * 4 : 0;
     put(L.add(3 * n4));        // 33 W32
@@ -489,7 +472,6 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.regions = (Region *)(w + off[29]);
     a.slots = (double *)(w + off[30]);
     a.ictl = (int32_t *)(w + off[31]);
-    a.planes = (double *)(w + off[32]);
     a.W32 = (float *)(w + off[33]);
     a.diag32 = (float *)(w + off[34]);
     a.invd32 = (float *)(w + off[35]);
@@ -736,7 +718,7 @@ static void enqueue_iteration(cams_ctx *c, int it)
             launch_bilu_smooth32(c, (const double *)a.r, a.d0f, O.n_pre, done);
             launch_sub64_lo(c, a.d0f, a.r, done);
         }
-        launch_restrict_planes(c, a.r, done);
+        launch_restrict(c, a.r);
         launch_gemv(c, a.rc, a.xc, done);
         launch_prolong32(c, a.xc, a.d1f, done);
         launch_r1_32(c, a.r, a.d1f, a.r1f, done);
@@ -751,7 +733,7 @@ static void enqueue_iteration(cams_ctx *c, int it)
         launch_smooth(c, a.r, a.d0, O.n_pre, done);
         launch_stencil_sub(c, a.r, a.d0, a.r, done);
     }
-    launch_restrict_planes(c, a.r, done);
+    launch_restrict(c, a.r);
     launch_gemv(c, a.rc, a.xc, done);                  // Eq. (15): coarse solve
     launch_prolong(c, a.xc, a.d1, done);               // Eq. (12)
     launch_stencil_sub(c, a.r, a.d1, a.r, done);       // r1 = r - A d1

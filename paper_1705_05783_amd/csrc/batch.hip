@@ -2,20 +2,27 @@
 // one Newton iteration together.  The setup of each instance (basis,
 // assembly, coarse operator and its inverse, smoother pivots) is enqueued on
 // a few side streams so that the instances' small kernels overlap; the
-// C-AMS iterations then run as ONE launch per kernel for all instances: a
-// work list names (instance, block) for every workgroup, so each launch
-// covers the concatenated cells of the whole batch, and instances that have
-// converged drop out (their workgroups return at once).  A fixed number of
-// iterations is captured once into a HIP graph and replayed until every
-// instance has stopped; the host reads one counter between replays.
+// C-AMS iterations then run as ONE launch per kernel for all instances.
+// Each batched kernel is persistent: as many workgroups as the device holds
+// at once walk a work list of (instance, block) items in device memory.
+// A fixed number of iterations is captured once into a HIP graph and
+// replayed until every instance has stopped; between replays the host reads
+// the per-instance results and, once the instances still running hold
+// clearly fewer cells than the lists cover, uploads lists compacted to them
+// (the graph reads the list lengths from device memory, so it stays valid).
 //
-// The graph is tuned per batch: on the first call every candidate number of
-// iterations per graph runs the same first iterations from the same state,
-// timed with events, and the state is reset before the real solve.
+// Tuning, on the first call of a batch: the smoother's workgroup size (128,
+// 256 or 512 threads per 8x8x8 block: fewer threads keep more of the
+// latency-bound sweeps in flight per compute unit) is chosen by timing the
+// batch's own smoothing steps; then every candidate number of iterations per
+// graph runs the same first iterations from the same state, timed with
+// events, and the state is reset before the real solve.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +35,8 @@ namespace {
 constexpr int kSide = 4;                     // setup streams (the device has 4 hardware queues per process)
 constexpr int kGraphIters[] = {2, 4, 8};     // candidates of the tuner (even: the ping-pong parity repeats)
 constexpr int kNumCand = 3;
+constexpr int kSmoothNT[] = {128, 256, 512};   // smoother workgroup sizes the tuner compares
+constexpr int kNumSmooth = 3;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -45,6 +54,26 @@ enum { L_FLAT = 0, L_SBLOCK, L_RESTRICT, L_NODES, L_ROWS, L_NUM };
 
 }  // namespace
 
+namespace cams {
+
+int resident_workgroups(const void *kernel, int threads)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({kernel, threads});
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per_cu = 0;
+    CAMS_HIP(hipGetDevice(&dev));
+    CAMS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CAMS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+    const int n = std::max(1, per_cu) * std::max(1, cus);
+    cache[{kernel, threads}] = n;
+    return n;
+}
+
+}  // namespace cams
+
 struct cams_batch {
     std::vector<cams_ctx *> ctx;
     hipStream_t user = nullptr;      // the contexts' stream: ordered before and after each call
@@ -52,25 +81,34 @@ struct cams_batch {
     hipStream_t side[kSide] = {};
     hipEvent_t fork = nullptr, join[kSide] = {}, ev[4] = {};
     bool mixed = false, bf16 = false;
+    int precision = CAMS_FP64;
     int n_pre = 0, n_post = 0, maxit = 0;
-    // work lists (host copies, uploaded by cams_batch_set_workspace)
+    // full work lists per kind, instance-major (host); the device holds the
+    // lists of the instances still running (XCD order) and their lengths
     std::vector<WorkItem> lists[L_NUM];
     std::vector<InstDev> h_inst;
-    size_t off_inst = 0, off_list[L_NUM] = {}, off_ndone = 0, off_res = 0, off_pptr = 0, need = 0;
+    std::vector<double> cells;       // cells per instance
+    std::vector<char> listed;        // instance in the device lists
+    double listed_cells = 0.0;
+    size_t off_inst = 0, off_list[L_NUM + 1] = {}, off_nwork = 0, off_res = 0, off_pptr = 0,
+           need = 0;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     InstDev *inst = nullptr;
-    WorkItem *work[L_NUM] = {};
-    int32_t *ndone = nullptr;
+    WorkItem *work[L_NUM + 1] = {};  // [L_NUM]: the full flat list (update, reset)
+    int32_t *nwork = nullptr;        // list lengths, L_NUM + 1 entries
     BatchResult *res = nullptr;
     double **pptr = nullptr;
-    // pinned host staging
+    // pinned host staging: counters, results, pressure table, lists
     char *host = nullptr;
-    size_t host_bytes = 0;
+    size_t host_bytes = 0, host_lists = 0;
+    int compactions = 0;
     // captured iterations
     hipGraphExec_t exec[kNumCand] = {};
     int chosen = -1;                 // index into kGraphIters once tuned
     double tune_ms[kNumCand] = {};   // ms per iteration of each candidate (first call)
+    int smooth_nt = 512;             // threads per smoother block (tuned on the first call)
+    double smooth_ms[kNumSmooth] = {};
     std::string err;
     float t_setup_ms = 0.f, t_iter_ms = 0.f;
     int iters_launched = 0;
@@ -84,26 +122,57 @@ cams_status bfail(cams_batch *b, cams_status s, const std::string &m)
     return s;
 }
 
-BatchLaunch L(const cams_batch *b, int which)
+// A batched launch over list `which` (L_NUM: the full flat list); `prime`
+// launches nothing (occupancy queries only).
+BatchLaunch L(const cams_batch *b, int which, bool prime = false)
 {
-    return BatchLaunch{b->inst, b->work[which], (int)b->lists[which].size(), b->stream};
+    const size_t n = b->lists[which == L_NUM ? L_FLAT : which].size();
+    return BatchLaunch{b->inst, b->work[which], b->nwork + which, prime ? 0 : (int)n, b->stream};
 }
 
-void enqueue_batch_iteration(cams_batch *b, int par)
+void enqueue_batch_iteration(cams_batch *b, int par, bool prime = false)
 {
     const int count = (int)b->ctx.size();
-    launch_batch_residual(L(b, L_FLAT), par, b->mixed);
-    launch_batch_finalize(b->inst, count, b->ndone, b->stream);
+    launch_batch_residual(L(b, L_FLAT, prime), par, b->mixed);
+    if (!prime) launch_batch_finalize(b->inst, count, b->stream);
     if (b->n_pre > 0) {
-        launch_batch_smooth(L(b, L_SBLOCK), b->n_pre, 0, b->mixed);
-        launch_batch_sub_pre(L(b, L_FLAT), b->mixed);
+        launch_batch_smooth(L(b, L_SBLOCK, prime), b->n_pre, 0, b->mixed, b->smooth_nt);
+        launch_batch_sub_pre(L(b, L_FLAT, prime), b->mixed);
     }
-    launch_batch_restrict(L(b, L_RESTRICT));
-    launch_batch_sum_planes(L(b, L_NODES));
-    launch_batch_gemv(L(b, L_ROWS));
-    launch_batch_prolong(L(b, L_FLAT), b->mixed, b->bf16);
-    launch_batch_r1(L(b, L_FLAT), b->mixed);
-    if (b->n_post > 0) launch_batch_smooth(L(b, L_SBLOCK), b->n_post, 1, b->mixed);
+    launch_batch_restrict(L(b, L_RESTRICT, prime), b->precision);
+    launch_batch_node_sum(L(b, L_NODES, prime));
+    launch_batch_gemv(L(b, L_ROWS, prime));
+    launch_batch_prolong(L(b, L_FLAT, prime), b->mixed, b->bf16);
+    launch_batch_r1(L(b, L_FLAT, prime), b->mixed);
+    if (b->n_post > 0) launch_batch_smooth(L(b, L_SBLOCK, prime), b->n_post, 1, b->mixed, b->smooth_nt);
+}
+
+WorkItem *host_list(cams_batch *b, int l);
+
+// Upload the lists restricted to the instances with keep[i] set, each list
+// in XCD order; the lengths go to nwork.  Only called when no launch that
+// reads the lists can be pending (after a stream synchronisation).
+void upload_lists(cams_batch *b, const std::vector<char> &keep)
+{
+    int32_t *counts = (int32_t *)b->host;
+    std::vector<WorkItem> v;
+    for (int l = 0; l < L_NUM; ++l) {
+        v.clear();
+        for (const WorkItem &w : b->lists[l])
+            if (keep[w.inst]) v.push_back(w);
+        WorkItem *dst = host_list(b, l);
+        const int n = (int)v.size();
+        for (int t = 0; t < n; ++t) dst[t] = v[xcd_swizzle_host(t, n)];
+        counts[l] = n;
+        if (n > 0)
+            CAMS_HIP(hipMemcpyAsync(b->work[l], dst, n * sizeof(WorkItem), hipMemcpyHostToDevice, b->stream));
+    }
+    counts[L_NUM] = (int)b->lists[L_FLAT].size();
+    CAMS_HIP(hipMemcpyAsync(b->nwork, counts, (L_NUM + 1) * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    b->listed = keep;
+    b->listed_cells = 0.0;
+    for (size_t i = 0; i < keep.size(); ++i)
+        if (keep[i]) b->listed_cells += b->cells[i];
 }
 
 // Capture `iters` iterations (iters even) into an executable graph.
@@ -121,22 +190,50 @@ hipGraphExec_t capture(cams_batch *b, int iters)
     return ex;
 }
 
-int32_t *host_ndone(cams_batch *b) { return (int32_t *)b->host; }
+// Pinned host layout: [0, 256) list lengths, results, pressure table, then
+// the list staging area.
 BatchResult *host_res(cams_batch *b) { return (BatchResult *)(b->host + 256); }
 double **host_pptr(cams_batch *b) { return (double **)(b->host + 256 + align_up(b->ctx.size() * sizeof(BatchResult))); }
-
-int read_ndone(cams_batch *b)
+WorkItem *host_list(cams_batch *b, int l)
 {
-    CAMS_HIP(hipMemcpyAsync(host_ndone(b), b->ndone, sizeof(int32_t), hipMemcpyDeviceToHost, b->stream));
-    CAMS_HIP(hipStreamSynchronize(b->stream));
-    return *host_ndone(b);
+    size_t o = b->host_lists;
+    for (int k = 0; k < l; ++k) o += align_up(b->lists[k].size() * sizeof(WorkItem));
+    return (WorkItem *)(b->host + o);
+}
+
+void read_results(cams_batch *b)
+{
+    const int count = (int)b->ctx.size();
+    launch_batch_gather(b->inst, count, b->res, b->stream);
+    CAMS_HIP(hipMemcpyAsync(host_res(b), b->res, count * sizeof(BatchResult), hipMemcpyDeviceToHost, b->stream));
 }
 
 void reset_iteration(cams_batch *b)
 {
-    launch_batch_reset(L(b, L_FLAT));
-    *host_ndone(b) = 0;
-    CAMS_HIP(hipMemcpyAsync(b->ndone, host_ndone(b), sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    launch_batch_reset(L(b, L_NUM));
+}
+
+// Choose the smoother's workgroup size: each candidate runs the same
+// smoothing steps over the whole batch (eager launches, timed with events).
+// The steps only write the smoother's own output vectors, which every
+// iteration rewrites before reading them.
+void tune_smoother(cams_batch *b)
+{
+    const int steps = std::max(1, b->n_post > 0 ? b->n_post : b->n_pre);
+    const int kind = b->n_post > 0 ? 1 : 0;
+    int best = kNumSmooth - 1;
+    for (int k = 0; k < kNumSmooth; ++k) {
+        launch_batch_smooth(L(b, L_SBLOCK), steps, kind, b->mixed, kSmoothNT[k]);   // warm
+        CAMS_HIP(hipEventRecord(b->ev[2], b->stream));
+        launch_batch_smooth(L(b, L_SBLOCK), steps, kind, b->mixed, kSmoothNT[k]);
+        CAMS_HIP(hipEventRecord(b->ev[3], b->stream));
+        CAMS_HIP(hipEventSynchronize(b->ev[3]));
+        float ms = 0.f;
+        CAMS_HIP(hipEventElapsedTime(&ms, b->ev[2], b->ev[3]));
+        b->smooth_ms[k] = ms / steps;
+        if (b->smooth_ms[k] < b->smooth_ms[best]) best = k;
+    }
+    b->smooth_nt = kSmoothNT[best];
 }
 
 // Choose the iterations per graph: every candidate runs the same
@@ -194,6 +291,7 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
     if (!b) return CAMS_E_NOMEM;
     b->ctx.assign(ctxs, ctxs + count);
     b->user = st;
+    b->precision = O.precision;
     b->mixed = O.precision != CAMS_FP64;
     b->bf16 = O.precision == CAMS_MIXED_BF16;
     b->n_pre = O.n_pre;
@@ -208,29 +306,25 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         for (int k = 0; k < nflat; ++k) b->lists[L_FLAT].push_back({i, k});
         const int nsb = ((g.nx + 7) / 8) * ((g.ny + 7) / 8) * ((g.nz + 7) / 8);
         for (int k = 0; k < nsb; ++k) b->lists[L_SBLOCK].push_back({i, k});
-        for (int k = 0; k < g.Nc * c->max_planes; ++k) b->lists[L_RESTRICT].push_back({i, k});
+        for (int k = 0; k < (g.Nc + kBlock / 64 - 1) / (kBlock / 64); ++k) b->lists[L_RESTRICT].push_back({i, k});
         for (int k = 0; k < (g.Nc + kBlock - 1) / kBlock; ++k) b->lists[L_NODES].push_back({i, k});
         for (int k = 0; k < (g.Nc + kBlock / 64 - 1) / (kBlock / 64); ++k) b->lists[L_ROWS].push_back({i, k});
     }
-    for (int l = 0; l < L_NUM; ++l) {
-        std::vector<WorkItem> &v = b->lists[l];
-        std::vector<WorkItem> w(v.size());
-        for (size_t t = 0; t < v.size(); ++t) w[t] = v[xcd_swizzle_host((int)t, (int)v.size())];
-        v.swap(w);
-    }
-    if (b->lists[L_RESTRICT].size() > 0x7fffffffu || b->lists[L_FLAT].size() > 0x7fffffffu) {
-        delete b;
-        return CAMS_E_ARG;
-    }
+    for (int i = 0; i < count; ++i) b->cells.push_back((double)ctxs[i]->g.N);
+    for (int l = 0; l < L_NUM; ++l)
+        if (b->lists[l].size() > 0x7fffffffu) {
+            delete b;
+            return CAMS_E_ARG;
+        }
     size_t o = 0;
     b->off_inst = o;
     o = align_up(o + count * sizeof(InstDev));
-    for (int l = 0; l < L_NUM; ++l) {
+    for (int l = 0; l <= L_NUM; ++l) {
         b->off_list[l] = o;
-        o = align_up(o + b->lists[l].size() * sizeof(WorkItem));
+        o = align_up(o + b->lists[l == L_NUM ? L_FLAT : l].size() * sizeof(WorkItem));
     }
-    b->off_ndone = o;
-    o = align_up(o + sizeof(int32_t));
+    b->off_nwork = o;
+    o = align_up(o + (L_NUM + 1) * sizeof(int32_t));
     b->off_res = o;
     o = align_up(o + count * sizeof(BatchResult));
     b->off_pptr = o;
@@ -252,7 +346,9 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
     try {
         const int count = (int)b->ctx.size();
         if (!b->host) {
-            b->host_bytes = 256 + align_up(count * sizeof(BatchResult)) + align_up(count * sizeof(double *));
+            b->host_lists = 256 + align_up(count * sizeof(BatchResult)) + align_up(count * sizeof(double *));
+            b->host_bytes = b->host_lists;
+            for (int l = 0; l < L_NUM; ++l) b->host_bytes += align_up(b->lists[l].size() * sizeof(WorkItem));
             CAMS_HIP(hipHostMalloc((void **)&b->host, b->host_bytes, hipHostMallocDefault));
             CAMS_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
             for (int s = 0; s < kSide; ++s) {
@@ -271,8 +367,8 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
         b->ws = w;
         b->ws_bytes = bytes;
         b->inst = (InstDev *)(w + b->off_inst);
-        for (int l = 0; l < L_NUM; ++l) b->work[l] = (WorkItem *)(w + b->off_list[l]);
-        b->ndone = (int32_t *)(w + b->off_ndone);
+        for (int l = 0; l <= L_NUM; ++l) b->work[l] = (WorkItem *)(w + b->off_list[l]);
+        b->nwork = (int32_t *)(w + b->off_nwork);
         b->res = (BatchResult *)(w + b->off_res);
         b->pptr = (double **)(w + b->off_pptr);
         b->h_inst.resize(count);
@@ -286,18 +382,27 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
             d.bf16 = b->bf16;
             d.n_pre = c->opt.n_pre;
             d.n_post = c->opt.n_post;
-            d.max_planes = c->max_planes;
             d.nparts = (c->g.N + kBlock - 1) / kBlock;
             d.maxit = c->opt.lin_maxit;
             d.rtol2 = c->opt.lin_rtol * c->opt.lin_rtol;
         }
         CAMS_HIP(hipMemcpyAsync(b->inst, b->h_inst.data(), count * sizeof(InstDev), hipMemcpyHostToDevice,
                                 b->stream));
-        for (int l = 0; l < L_NUM; ++l)
-            if (!b->lists[l].empty())
-                CAMS_HIP(hipMemcpyAsync(b->work[l], b->lists[l].data(), b->lists[l].size() * sizeof(WorkItem),
-                                        hipMemcpyHostToDevice, b->stream));
-        CAMS_HIP(hipStreamSynchronize(b->stream));   // the host vectors must outlive the copies
+        // the full flat list (XCD order) for the update and the reset
+        {
+            const std::vector<WorkItem> &v = b->lists[L_FLAT];
+            std::vector<WorkItem> full(v.size());
+            for (size_t t = 0; t < v.size(); ++t) full[t] = v[xcd_swizzle_host((int)t, (int)v.size())];
+            CAMS_HIP(hipMemcpyAsync(b->work[L_NUM], full.data(), full.size() * sizeof(WorkItem),
+                                    hipMemcpyHostToDevice, b->stream));
+            CAMS_HIP(hipStreamSynchronize(b->stream));   // `full` must outlive the copy
+        }
+        upload_lists(b, std::vector<char>(count, 1));
+        // occupancy of every batched kernel, before any capture
+        enqueue_batch_iteration(b, 0, true);
+        launch_batch_reset(L(b, L_NUM, true));
+        launch_batch_update(L(b, L_NUM, true), nullptr);
+        CAMS_HIP(hipStreamSynchronize(b->stream));
     } catch (const HipError &e) {
         return bfail(b, CAMS_E_DEVICE, std::string("batch_set_workspace: ") + hipGetErrorString(e.code));
     }
@@ -324,8 +429,6 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
         CAMS_HIP(hipStreamWaitEvent(b->stream, b->fork, 0));
         memcpy(host_pptr(b), p_dev, count * sizeof(double *));
         CAMS_HIP(hipMemcpyAsync(b->pptr, host_pptr(b), count * sizeof(double *), hipMemcpyHostToDevice, b->stream));
-        *host_ndone(b) = 0;
-        CAMS_HIP(hipMemcpyAsync(b->ndone, host_ndone(b), sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
         CAMS_HIP(hipEventRecord(b->ev[0], b->stream));
 
         // setup of every instance, spread over the side streams
@@ -356,8 +459,13 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
         CAMS_HIP(hipEventRecord(b->ev[1], b->stream));
 
         // batched iterations: replay captured graphs until every instance stopped
-        if (!b->exec[0])
+        bool all_listed = true;
+        for (char k : b->listed) all_listed = all_listed && k;
+        if (!all_listed) upload_lists(b, std::vector<char>(count, 1));
+        if (!b->exec[0]) {
+            tune_smoother(b);
             for (int k = 0; k < kNumCand; ++k) b->exec[k] = capture(b, kGraphIters[k]);
+        }
         if (b->chosen < 0) tune(b);
         const int k = b->chosen;
         int launched = 0, done = 0;
@@ -367,15 +475,30 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
             const int reps = std::max(1, ahead / kGraphIters[k]);
             for (int q = 0; q < reps; ++q) CAMS_HIP(hipGraphLaunch(b->exec[k], b->stream));
             launched += reps * kGraphIters[k];
-            done = read_ndone(b);
+            read_results(b);
+            CAMS_HIP(hipStreamSynchronize(b->stream));
+            std::vector<char> running(count, 0);
+            double running_cells = 0.0;
+            done = 0;
+            for (int i = 0; i < count; ++i) {
+                if (host_res(b)[i].done) {
+                    ++done;
+                } else {
+                    running[i] = 1;
+                    running_cells += b->cells[i];
+                }
+            }
             if (done >= count) break;
+            // compact once the running instances cover well under the listed cells
+            if (running_cells < 0.7 * b->listed_cells) {
+                upload_lists(b, running);
+                ++b->compactions;
+            }
             ahead = std::min(32, ahead * 2);
         }
         b->iters_launched = launched;
-        launch_batch_update(BatchLaunch{b->inst, b->work[L_FLAT], (int)b->lists[L_FLAT].size(), b->stream},
-                            b->pptr);
-        launch_batch_gather(b->inst, count, b->res, b->stream);
-        CAMS_HIP(hipMemcpyAsync(host_res(b), b->res, count * sizeof(BatchResult), hipMemcpyDeviceToHost, b->stream));
+        launch_batch_update(L(b, L_NUM), b->pptr);
+        read_results(b);
         CAMS_HIP(hipEventRecord(b->ev[2], b->stream));
         CAMS_HIP(hipStreamWaitEvent(b->user, b->ev[2], 0));
         CAMS_HIP(hipStreamSynchronize(b->stream));
@@ -415,13 +538,16 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
     return CAMS_OK;
 }
 
-cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, double *ms_per_iter_candidates,
-                              int32_t ncand)
+cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, int32_t *smoother_threads,
+                              double *ms_per_iter_candidates, double *ms_per_smooth_step_candidates, int32_t ncand)
 {
     if (!b) return CAMS_E_ARG;
     if (iters_per_graph) *iters_per_graph = b->chosen >= 0 ? kGraphIters[b->chosen] : 0;
-    if (ms_per_iter_candidates)
-        for (int k = 0; k < std::min<int>(ncand, kNumCand); ++k) ms_per_iter_candidates[k] = b->tune_ms[k];
+    if (smoother_threads) *smoother_threads = b->exec[0] ? b->smooth_nt : 0;
+    for (int k = 0; k < std::min<int>(ncand, kNumCand); ++k) {
+        if (ms_per_iter_candidates) ms_per_iter_candidates[k] = b->tune_ms[k];
+        if (ms_per_smooth_step_candidates) ms_per_smooth_step_candidates[k] = b->smooth_ms[k];
+    }
     return CAMS_OK;
 }
 

@@ -56,13 +56,12 @@ struct Arrays {
     double *tri;      // inverses of the 64x64 diagonal blocks of the coarse LU (2 per panel)
     double *rc, *xc;  // Nc
     double *partial;  // reduction partials
-    double *slots;    // Nc*8 restriction slot sums
+    double *slots;    // Nc*8 restriction partials: slot s of owner box k
     double *scal;     // device scalars
     int32_t *piv;     // Nc
     int32_t *status;  // device error flags
     int32_t *ictl;    // iteration control: [0] iteration, [1] done, [2] outcome, [3] arrival counter,
                       // [4..4+Nc) per-node arrival counters of the restriction
-    double *planes;   // Nc * max_planes restriction partials
     uint8_t *dmask;   // N
     int32_t *wcell;   // wells
     double *wp;
@@ -82,7 +81,6 @@ struct InstDev {
     int fe;           // MSFE restriction
     int bf16;         // mixed precision with a bfloat16 basis
     int n_pre, n_post;
-    int max_planes;   // restriction partials per coarse node
     int nparts;       // residual partials, ceil(N / kBlock)
     int maxit;
     double rtol2;
@@ -94,13 +92,33 @@ struct WorkItem {
     int32_t blk;      // block of that instance (meaning set by the kernel)
 };
 
-// A batched launch: instance table, one work item per workgroup, stream.
+// A batched launch: `grid` persistent workgroups take the work items
+// blockIdx.x, blockIdx.x + grid, ... below the device-side count *nwork (the
+// list shrinks between launches as instances stop).
 struct BatchLaunch {
     const InstDev *inst;
     const WorkItem *work;
-    int count;
+    const int32_t *nwork;
+    int grid;
     hipStream_t stream;
 };
+
+// Workgroups of `kernel` (with `threads` per workgroup) that the device
+// holds at once: occupancy per CU x number of CUs, queried once per kernel.
+int resident_workgroups(const void *kernel, int threads);
+
+// Launch a persistent batched kernel with as many workgroups as are resident
+// at once, at most L.grid (the list's full length).  With L.grid == 0 it
+// launches nothing but still caches the occupancy (done before any graph
+// capture, so that capture records launches only).
+template <class K, class... Args>
+inline void launch_persistent(K kernel, int threads, const BatchLaunch &L, Args... args)
+{
+    const int res = resident_workgroups((const void *)kernel, threads);
+    if (L.grid <= 0) return;
+    const int grid = L.grid < res ? L.grid : res;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, L.stream, args...);
+}
 
 // Per-instance results copied to the host after a batched solve.
 struct BatchResult {
@@ -143,7 +161,6 @@ struct cams_ctx {
     size_t ws_bytes;
     cams::Arrays a;
     int nparts;             // reduction partial count
-    int max_planes;         // largest number of z-planes in a restriction row
     int nwells;
     bool has_ws, has_rock, has_q, has_basis, has_system, has_coarse;
     int cur_dp;
@@ -217,7 +234,7 @@ void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, con
 void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
                            double *dp_out);
 void launch_finalize_ctl(cams_ctx *c);   // ||r||, stopping test, iteration counter
-void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *done);
+void launch_restrict(cams_ctx *c, const double *r);   // slot partials of R r (stage 1)
 
 // ---- setup phases without host synchronisation (abi.hip)
 void enqueue_clear_status(cams_ctx *c);
@@ -227,16 +244,16 @@ void enqueue_coarse(cams_ctx *c);
 
 // ---- batched iteration (one launch per kernel for all instances)
 void launch_batch_residual(const BatchLaunch &L, int par, bool mixed);
-void launch_batch_finalize(const InstDev *inst, int count, int32_t *ndone, hipStream_t st);
-void launch_batch_restrict(const BatchLaunch &L);
+void launch_batch_finalize(const InstDev *inst, int count, hipStream_t st);
+void launch_batch_restrict(const BatchLaunch &L, int precision);
 void launch_batch_gather(const InstDev *inst, int count, BatchResult *out, hipStream_t st);
 void launch_batch_reset(const BatchLaunch &L);   // iteration state of every instance to its start
-void launch_batch_sum_planes(const BatchLaunch &L);
+void launch_batch_node_sum(const BatchLaunch &L);
 void launch_batch_gemv(const BatchLaunch &L);
 void launch_batch_prolong(const BatchLaunch &L, bool mixed, bool bf16);
 void launch_batch_r1(const BatchLaunch &L, bool mixed);
 void launch_batch_sub_pre(const BatchLaunch &L, bool mixed);
-void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed);
+void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed, int nt);
 void launch_batch_update(const BatchLaunch &L, double *const *p);
 void launch_batch_prolong64(const BatchLaunch &L);
 void launch_batch_r1_64(const BatchLaunch &L);

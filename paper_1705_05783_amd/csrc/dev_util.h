@@ -53,12 +53,16 @@ __device__ __forceinline__ int node_index(const GridDev &g, int a, int b, int c)
     return a + g.nb[0] * (b + g.nb[1] * c);
 }
 
-// Cell of this thread in a flat batched launch, or -1; also returns the
-// instance descriptor and skips instances that have converged.
-__device__ __forceinline__ int flat_cell(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
-                                         const InstDev *&d)
+// Loop of a persistent batched kernel over its work items: blockIdx.x,
+// blockIdx.x + gridDim.x, ... below the device-side count *nwork (uniform
+// over the workgroup).
+#define CAMS_FOR_ITEMS(t, nwork) for (int t = blockIdx.x, t##_end = *(nwork); t < t##_end; t += gridDim.x)
+
+// Cell of this thread for work item w of a flat batched launch (w.blk =
+// block of kBlock cells), or -1 past the instance's cells or once the
+// instance has stopped; also returns the instance descriptor.
+__device__ __forceinline__ int flat_cell(const InstDev *__restrict__ inst, const WorkItem w, const InstDev *&d)
 {
-    const WorkItem w = work[blockIdx.x];
     d = &inst[w.inst];
     if (d->a.ictl[C_DONE]) return -1;
     const int n = w.blk * kBlock + threadIdx.x;

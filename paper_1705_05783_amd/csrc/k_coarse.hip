@@ -433,36 +433,45 @@ __global__ __launch_bounds__(kBlock) void k_copy(const double *__restrict__ a, d
     if (t < n) b[t] = a[t];
 }
 
-// rc[k] = sum of the restriction plane partials of row k (in plane order).
-__global__ __launch_bounds__(kBlock) void k_sum_planes(const double *__restrict__ planes, int n, int np,
-                                                        double *__restrict__ rc, const int32_t *done)
+// (R r)_k from the owner-box slot partials of the restriction: MSFE adds,
+// in a fixed order, slot (dx + 2 dy + 4 dz) of the box k - (dx, dy, dz) for
+// the boxes that exist; MSFV takes slot 0 of box k.
+__device__ __forceinline__ double node_sum(const GridDev &g, const double *__restrict__ slots, int fe, int k)
+{
+    if (!fe) return slots[(size_t)k * 8];
+    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = ka - (q & 1), b = kb - ((q >> 1) & 1), c = kc - (q >> 2);
+        if (a >= 0 && b >= 0 && c >= 0) s += slots[(size_t)node_index(g, a, b, c) * 8 + q];
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_node_sum(GridDev g, const double *__restrict__ slots, int fe,
+                                                      double *__restrict__ rc, const int32_t *done)
 {
     if (done && *done) return;
     const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= n) return;
-    double s = 0.0;
-    for (int q = 0; q < np; ++q) s += planes[(size_t)k * np + q];
-    rc[k] = s;
+    if (k >= g.Nc) return;
+    rc[k] = node_sum(g, slots, fe, k);
 }
 
-constexpr int kGemvLds = 4096;   // coarse sizes whose rhs fits in LDS
+constexpr int kGemvLds = 1024;   // coarse sizes for which every GEMV workgroup forms R r itself
 
 // y = M x, one wave per row (fixed lane partition and shuffle tree).  With
-// `planes` set (n <= kGemvLds), x is first assembled in LDS from the
-// restriction plane partials (row k: planes[k*np .. k*np+np-1], in order).
+// `slots` set (n <= kGemvLds), x = R r is first assembled in LDS from the
+// restriction's slot partials.
 __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, int n, const double *__restrict__ x,
-                                                  const double *__restrict__ planes, int np,
+                                                  GridDev g, const double *__restrict__ slots, int fe,
                                                   double *__restrict__ y, const int32_t *done)
 {
     __shared__ double xs[kGemvLds];
     if (done && *done) return;
     const double *xv = x;
-    if (planes) {
-        for (int k = threadIdx.x; k < n; k += kBlock) {
-            double s = 0.0;
-            for (int q = 0; q < np; ++q) s += planes[(size_t)k * np + q];
-            xs[k] = s;
-        }
+    if (slots) {
+        for (int k = threadIdx.x; k < n; k += kBlock) xs[k] = node_sum(g, slots, fe, k);
         __syncthreads();
         xv = xs;
     }
@@ -476,37 +485,40 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
     if (lane == 0) y[row] = s;
 }
 
-// Batched coarse solve: rc = sum of the plane partials (work item = block of
-// kBlock coarse nodes), then xc = Ainv rc (work item = kBlock/64 rows).
-__global__ __launch_bounds__(kBlock) void kb_sum_planes(const InstDev *__restrict__ inst,
-                                                         const WorkItem *__restrict__ work)
+// Batched coarse solve: rc = R r from the slot partials (work item = block
+// of kBlock coarse nodes), then xc = Ainv rc (work item = kBlock/64 rows).
+__global__ __launch_bounds__(kBlock) void kb_node_sum(const InstDev *__restrict__ inst,
+                                                       const WorkItem *__restrict__ work, const int32_t *nwork)
 {
-    const WorkItem w = work[blockIdx.x];
-    const InstDev &d = inst[w.inst];
-    if (d.a.ictl[C_DONE]) return;
-    const int k = w.blk * kBlock + threadIdx.x;
-    if (k >= d.g.Nc) return;
-    const double *pl = d.a.planes + (size_t)k * d.max_planes;
-    double s = 0.0;
-    for (int q = 0; q < d.max_planes; ++q) s += pl[q];
-    d.a.rc[k] = s;
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        if (d.a.ictl[C_DONE]) continue;
+        const int k = w.blk * kBlock + threadIdx.x;
+        if (k < d.g.Nc) d.a.rc[k] = node_sum(d.g, d.a.slots, d.fe, k);
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void kb_gemv(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+__global__ __launch_bounds__(kBlock) void kb_gemv(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                                   const int32_t *nwork)
 {
-    const WorkItem w = work[blockIdx.x];
-    const InstDev &d = inst[w.inst];
-    if (d.a.ictl[C_DONE]) return;
-    const int n = d.g.Nc;
-    const int row = w.blk * (kBlock / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= n) return;
-    const double *mr = d.a.Ainv + (size_t)row * n;
-    const double *x = d.a.rc;
-    double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
-    s = wave_sum(s);
-    if (lane == 0) d.a.xc[row] = s;
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        if (d.a.ictl[C_DONE]) continue;
+        const int n = d.g.Nc;
+        const int row = w.blk * (kBlock / 64) + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (row >= n) continue;   // whole waves: no workgroup barrier follows
+        const double *mr = d.a.Ainv + (size_t)row * n;
+        const double *x = d.a.rc;
+        double s = 0.0;
+        for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+        s = wave_sum(s);
+        if (lane == 0) d.a.xc[row] = s;
+    }
 }
 
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
@@ -635,12 +647,13 @@ void launch_coarse_factor(cams_ctx *c)
 void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done)
 {
     const int n = c->g.Nc;
+    const int fe = c->opt.restriction == CAMS_R_FE;
     if (n <= kGemvLds) {
-        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, nullptr, c->a.planes, c->max_planes,
-                                                             xc, done);
+        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, nullptr, c->g, c->a.slots, fe, xc,
+                                                             done);
     } else {
-        k_sum_planes<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.planes, n, c->max_planes, c->a.rc, done);
-        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, nullptr, 0, xc, done);
+        k_node_sum<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.slots, fe, c->a.rc, done);
+        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, c->g, nullptr, fe, xc, done);
     }
     (void)rc;
 }
@@ -652,14 +665,14 @@ void launch_gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, 
     gemm_sub(c, C, ldc, A, lda, B, ldb, M, Nn, K);
 }
 
-void launch_batch_sum_planes(const BatchLaunch &L)
+void launch_batch_node_sum(const BatchLaunch &L)
 {
-    if (L.count > 0) kb_sum_planes<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    launch_persistent(kb_node_sum, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 void launch_batch_gemv(const BatchLaunch &L)
 {
-    if (L.count > 0) kb_gemv<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    launch_persistent(kb_gemv, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 }  // namespace cams

@@ -288,46 +288,58 @@ __global__ __launch_bounds__(kBlock) void k_axpy(double *__restrict__ y, const d
 // ---- batched forms (FP64 solve): work item = (instance, block of kBlock cells)
 
 __global__ __launch_bounds__(kBlock) void kb_prolong(const InstDev *__restrict__ inst,
-                                                      const WorkItem *__restrict__ work)
+                                                      const WorkItem *__restrict__ work, const int32_t *nwork)
 {
-    const InstDev *d;
-    const int n = flat_cell(inst, work, d);
-    if (n < 0) return;
-    prolong_body(d->g, d->a.P, d->a.dmask, d->a.xc, d->a.d1, n);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const InstDev *d;
+        const int n = flat_cell(inst, work[t], d);
+        if (n >= 0) prolong_body(d->g, d->a.P, d->a.dmask, d->a.xc, d->a.d1, n);
+    }
 }
 
 // r := r - A d1 (r1 of the FP64 solve, in place)
-__global__ __launch_bounds__(kBlock) void kb_r1(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+__global__ __launch_bounds__(kBlock) void kb_r1(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                                 const int32_t *nwork)
 {
-    const InstDev *d;
-    const int n = flat_cell(inst, work, d);
-    if (n < 0) return;
-    Vec1 xv{d->a.d1};
-    d->a.r[n] -= apply_A(d->g, d->a.W, d->a.diag, xv, n, d->a.d1[n]);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const InstDev *d;
+        const int n = flat_cell(inst, work[t], d);
+        if (n < 0) continue;
+        Vec1 xv{d->a.d1};
+        d->a.r[n] -= apply_A(d->g, d->a.W, d->a.diag, xv, n, d->a.d1[n]);
+    }
 }
 
 // r := r - A d0 after pre-smoothing
 __global__ __launch_bounds__(kBlock) void kb_sub_pre(const InstDev *__restrict__ inst,
-                                                      const WorkItem *__restrict__ work)
+                                                      const WorkItem *__restrict__ work, const int32_t *nwork)
 {
-    const InstDev *d;
-    const int n = flat_cell(inst, work, d);
-    if (n < 0) return;
-    Vec1 xv{d->a.d0};
-    d->a.r[n] -= apply_A(d->g, d->a.W, d->a.diag, xv, n, d->a.d0[n]);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const InstDev *d;
+        const int n = flat_cell(inst, work[t], d);
+        if (n < 0) continue;
+        Vec1 xv{d->a.d0};
+        d->a.r[n] -= apply_A(d->g, d->a.W, d->a.diag, xv, n, d->a.d0[n]);
+    }
 }
 
 // p += dp of the instance's last iteration (read from its own counter); runs
 // after the iteration has stopped, so the done flag is not consulted.
 __global__ __launch_bounds__(kBlock) void kb_update(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
-                                                     double *const *__restrict__ p)
+                                                     const int32_t *nwork, double *const *__restrict__ p)
 {
-    const WorkItem w = work[blockIdx.x];
-    const InstDev &d = inst[w.inst];
-    const int n = w.blk * kBlock + threadIdx.x;
-    if (n >= d.g.N) return;
-    const int it = d.a.ictl[C_IT];
-    p[w.inst][n] += d.a.dp[(it + 1) & 1][n];
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        const int n = w.blk * kBlock + threadIdx.x;
+        if (n >= d.g.N) continue;
+        const int it = d.a.ictl[C_IT];
+        p[w.inst][n] += d.a.dp[(it + 1) & 1][n];
+    }
 }
 
 }  // namespace
@@ -419,22 +431,22 @@ void launch_axpy(cams_ctx *c, double *y, const double *x, int n)
 
 void launch_batch_update(const BatchLaunch &L, double *const *p)
 {
-    if (L.count > 0) kb_update<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work, p);
+    launch_persistent(kb_update, kBlock, L, L.inst, L.work, L.nwork, p);
 }
 
 void launch_batch_prolong64(const BatchLaunch &L)
 {
-    if (L.count > 0) kb_prolong<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    launch_persistent(kb_prolong, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 void launch_batch_r1_64(const BatchLaunch &L)
 {
-    if (L.count > 0) kb_r1<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    launch_persistent(kb_r1, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 void launch_batch_sub_pre64(const BatchLaunch &L)
 {
-    if (L.count > 0) kb_sub_pre<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    launch_persistent(kb_sub_pre, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 }  // namespace cams

@@ -87,14 +87,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double
 }
 
 // ||r||^2 from the residual kernel's partials and the stopping test.
-// Returns true (in thread 0) when this call ended the iteration.
-__device__ __forceinline__ bool finalize_body(const double *__restrict__ partial, int nparts, int32_t *ictl,
+__device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int nparts, int32_t *ictl,
                                               double *scal, double rtol2, int maxit, double *sh)
 {
     double u = 0.0;
     for (int t = threadIdx.x; t < nparts; t += kBlock) u += partial[t];
     const double s = block_sum<kBlock>(u, sh);
-    if (threadIdx.x != 0) return false;
+    if (threadIdx.x != 0) return;
     const int it = ictl[C_IT];
     if (it == 0) scal[S_R0N2] = s;
     const double r0n2 = it == 0 ? s : scal[S_R0N2];
@@ -108,11 +107,10 @@ __device__ __forceinline__ bool finalize_body(const double *__restrict__ partial
         outcome = 1;
     if (outcome < 0) {
         ictl[C_IT] = it + 1;
-        return false;
+        return;
     }
     ictl[C_OUTCOME] = outcome;
     ictl[C_DONE] = 1;
-    return true;
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize_ctl(const double *__restrict__ partial, int nparts,
@@ -123,61 +121,72 @@ __global__ __launch_bounds__(kBlock) void k_finalize_ctl(const double *__restric
     finalize_body(partial, nparts, ictl, scal, rtol2, maxit, sh);
 }
 
-// Restriction R r (Eq. (13)/(15)): one workgroup per (coarse node, z-plane of
-// its row's cells); a row box is at most 15 x 15 cells per plane (MSFE
-// support at ratio 8), covered by a 16 x 16 thread tile.  MSFV rows are the
-// primal block (weights 1); MSFE rows are the basis support (weights P_hat).
-// The coarse solve adds the plane sums of each row in order.
-__device__ __forceinline__ void restrict_body(const GridDev &g, const uint8_t *__restrict__ dm,
-                                              const double *__restrict__ P, int fe, const double *__restrict__ r,
-                                              double *__restrict__ planes, int max_planes, int k, int pz,
-                                              double *sh)
+// Restriction R r (Eqs. (7), (13), (15)) in two deterministic stages.
+// Stage 1, one workgroup per owner box k = (a, b, c): MSFE: the box holds
+// the cells whose lower bracketing coarse node is k, so all of them share
+// the same 8 bracketing nodes; the workgroup sums P_s[n] r[n] over its
+// non-Dirichlet cells for the 8 slots s (slot s = the node k + (s&1,
+// (s>>1)&1, s>>2)).  MSFV: the box is the primal block of node k, summed
+// with weight 1 into slot 0.  Every cell is read once.
+// Stage 2 (node_sum, in the coarse solve): (R r)_k adds, in a fixed order,
+// the slot partials that the (up to) 8 boxes around node k hold for it.
+// TP: storage type of the basis (double, float, or bfloat16 bits).
+template <class TP>
+__device__ __forceinline__ double basis_value(const TP *P, size_t i);
+template <>
+__device__ __forceinline__ double basis_value<double>(const double *P, size_t i) { return P[i]; }
+template <>
+__device__ __forceinline__ double basis_value<float>(const float *P, size_t i) { return (double)P[i]; }
+template <>
+__device__ __forceinline__ double basis_value<uint16_t>(const uint16_t *P, size_t i)
 {
-    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-        const int idx = a == 0 ? ka : (a == 1 ? kb : kc);
-        const int n = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
-        if (fe) {
-            lo[a] = idx > 0 ? g.vc[a][idx - 1] + 1 : 0;
-            hi[a] = idx < g.nb[a] - 1 ? g.vc[a][idx + 1] - 1 : n - 1;
-        } else {
-            lo[a] = idx * g.r[a];
-            hi[a] = min((idx + 1) * g.r[a], n) - 1;
-        }
-    }
-    const int nplanes = hi[2] - lo[2] + 1;
-    if (pz >= nplanes) {   // rows with fewer planes: the unused partials are zero
-        if (threadIdx.x == 0) planes[(size_t)k * max_planes + pz] = 0.0;
-        return;
-    }
-    const int x = lo[0] + (threadIdx.x & 15), y = lo[1] + (threadIdx.x >> 4), z = lo[2] + pz;
-    double v = 0.0;
-    if (x <= hi[0] && y <= hi[1]) {
-        const int n = x + g.nx * (y + g.ny * z);
-        if (fe) {
-            if (!dm[n]) {
-                const int sx = ka - g.lo[0][x], sy = kb - g.lo[1][y], sz = kc - g.lo[2][z];
-                if (sx >= 0 && sx <= 1 && sy >= 0 && sy <= 1 && sz >= 0 && sz <= 1)
-                    v = P[(size_t)(sx + 2 * sy + 4 * sz) * g.N + n] * r[n];
-            }
-        } else {
-            v = r[n];
-        }
-    }
-    const double s = block_sum<kBlock>(v, sh);
-    if (threadIdx.x == 0) planes[(size_t)k * max_planes + pz] = s;
+    return (double)__uint_as_float((uint32_t)P[i] << 16);
 }
 
-__global__ __launch_bounds__(kBlock) void k_restrict_planes(GridDev g, const uint8_t *__restrict__ dm,
-                                                             const double *__restrict__ P, int fe,
-                                                             const double *__restrict__ r,
-                                                             double *__restrict__ planes, int max_planes,
-                                                             const int32_t *ictl)
+// One wave sums owner box k (cells in x-fastest order, lane-strided, then a
+// fixed shuffle tree per slot); lane 0 writes the 8 slot partials.
+template <class TP>
+__device__ __forceinline__ void restrict_box(const GridDev &g, const uint8_t *__restrict__ dm,
+                                             const TP *__restrict__ P, int fe, const double *__restrict__ r,
+                                             double *__restrict__ slots, int k)
 {
-    __shared__ double sh[kBlock / 64];
+    const int lane = threadIdx.x & 63;
+    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
+    const int x0 = g.ob[0][ka], y0 = g.ob[1][kb], z0 = g.ob[2][kc];
+    const int ex = g.ob[0][ka + 1] - x0, ey = g.ob[1][kb + 1] - y0, ez = g.ob[2][kc + 1] - z0;
+    const int m = ex * ey * ez;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int t = lane; t < m; t += 64) {
+        const int x = x0 + t % ex, y = y0 + (t / ex) % ey, z = z0 + t / (ex * ey);
+        const int n = x + g.nx * (y + g.ny * z);
+        const double rn = r[n];
+        if (fe) {
+            if (!dm[n]) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += basis_value(P, (size_t)q * g.N + n) * rn;
+            }
+        } else {
+            acc[0] += rn;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) slots[(size_t)k * 8 + q] = acc[q];
+    }
+}
+
+// One wave per owner box, four boxes per workgroup.
+template <class TP>
+__global__ __launch_bounds__(kBlock) void k_restrict(GridDev g, const uint8_t *__restrict__ dm,
+                                                      const TP *__restrict__ P, int fe, const double *__restrict__ r,
+                                                      double *__restrict__ slots, const int32_t *ictl)
+{
     if (ictl[C_DONE]) return;
-    restrict_body(g, dm, P, fe, r, planes, max_planes, blockIdx.x, blockIdx.y, sh);
+    const int k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (k < g.Nc) restrict_box<TP>(g, dm, P, fe, r, slots, k);
 }
 
 // ---- batched forms: one launch covers every instance of a batch; the work
@@ -203,46 +212,65 @@ __device__ __forceinline__ Pending<float> pending_of<float>(const InstDev &d, in
 
 template <class TA>
 __global__ __launch_bounds__(kBlock) void kb_residual(const InstDev *__restrict__ inst,
-                                                       const WorkItem *__restrict__ work, int par)
+                                                       const WorkItem *__restrict__ work, const int32_t *nwork, int par)
 {
     __shared__ double sh[kBlock / 64];
-    const WorkItem w = work[blockIdx.x];
-    const InstDev &d = inst[w.inst];
-    if (d.a.ictl[C_DONE]) return;
-    const Pending<TA> v = pending_of<TA>(d, par, d.a.ictl[C_IT] > 0);
-    residual_body(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, d.a.partial, w.blk, sh);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        if (d.a.ictl[C_DONE]) continue;
+        const Pending<TA> v = pending_of<TA>(d, par, d.a.ictl[C_IT] > 0);
+        residual_body(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, d.a.partial, w.blk, sh);
+    }
 }
 
-// One workgroup per instance; `ndone` counts the instances that have stopped.
-__global__ __launch_bounds__(kBlock) void kb_finalize(const InstDev *__restrict__ inst, int32_t *ndone)
+// One workgroup per instance.
+__global__ __launch_bounds__(kBlock) void kb_finalize(const InstDev *__restrict__ inst)
 {
     __shared__ double sh[kBlock / 64];
     const InstDev &d = inst[blockIdx.x];
     if (d.a.ictl[C_DONE]) return;
-    if (finalize_body(d.a.partial, d.nparts, d.a.ictl, d.a.scal, d.rtol2, d.maxit, sh)) atomicAdd(ndone, 1);
+    finalize_body(d.a.partial, d.nparts, d.a.ictl, d.a.scal, d.rtol2, d.maxit, sh);
 }
 
+// Work item = (instance, group of kBlock/64 owner boxes), one wave per box.
+template <class TP>
 __global__ __launch_bounds__(kBlock) void kb_restrict(const InstDev *__restrict__ inst,
-                                                       const WorkItem *__restrict__ work)
+                                                       const WorkItem *__restrict__ work, const int32_t *nwork)
 {
-    __shared__ double sh[kBlock / 64];
-    const WorkItem w = work[blockIdx.x];
-    const InstDev &d = inst[w.inst];
-    if (d.a.ictl[C_DONE]) return;
-    restrict_body(d.g, d.a.dmask, d.a.P, d.fe, d.a.r, d.a.planes, d.max_planes, w.blk / d.max_planes,
-                  w.blk % d.max_planes, sh);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        if (d.a.ictl[C_DONE]) continue;
+        const int k = w.blk * (kBlock / 64) + (threadIdx.x >> 6);
+        if (k >= d.g.Nc) continue;   // whole waves; no workgroup barrier follows
+        const TP *P;
+        if constexpr (sizeof(TP) == 8)
+            P = d.a.P;
+        else if constexpr (sizeof(TP) == 4)
+            P = d.a.P32;
+        else
+            P = d.a.Pbf;
+        restrict_box<TP>(d.g, d.a.dmask, P, d.fe, d.a.r, d.a.slots, k);
+    }
 }
 
 // Iteration state of every instance back to its start (dp = 0, counters 0);
 // work item = (instance, block of kBlock cells).
-__global__ __launch_bounds__(kBlock) void kb_reset(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+__global__ __launch_bounds__(kBlock) void kb_reset(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                                    const int32_t *nwork)
 {
-    const WorkItem w = work[blockIdx.x];
-    const InstDev &d = inst[w.inst];
-    const int n = w.blk * kBlock + threadIdx.x;
-    if (n < d.g.N) d.a.dp[0][n] = 0.0;
-    if (w.blk == 0)
-        for (int t = threadIdx.x; t < C_NODE + d.g.Nc; t += kBlock) d.a.ictl[t] = 0;
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        const int n = w.blk * kBlock + threadIdx.x;
+        if (n < d.g.N) d.a.dp[0][n] = 0.0;
+        if (w.blk == 0)
+            for (int q = threadIdx.x; q < C_NODE + d.g.Nc; q += kBlock) d.a.ictl[q] = 0;
+    }
 }
 
 // Iteration counters, outcomes and norms of every instance, for one copy to the host.
@@ -295,35 +323,46 @@ void launch_finalize_ctl(cams_ctx *c)
                                                 rt * rt, c->opt.lin_maxit);
 }
 
-void launch_restrict_planes(cams_ctx *c, const double *r, const int32_t *)
+void launch_restrict(cams_ctx *c, const double *r)
 {
-    dim3 grid(c->g.Nc, c->max_planes);
-    k_restrict_planes<<<grid, kBlock, 0, c->stream>>>(c->g, c->a.dmask, c->a.P, c->opt.restriction == CAMS_R_FE, r,
-                                                      c->a.planes, c->max_planes, c->a.ictl);
+    const int fe = c->opt.restriction == CAMS_R_FE;
+    const GridDev &g = c->g;
+    const Arrays &a = c->a;
+    const int grid = (g.Nc + kBlock / 64 - 1) / (kBlock / 64);
+    if (c->opt.precision == CAMS_MIXED_BF16)
+        k_restrict<uint16_t><<<grid, kBlock, 0, c->stream>>>(g, a.dmask, a.Pbf, fe, r, a.slots, a.ictl);
+    else if (c->opt.precision == CAMS_MIXED_FP32)
+        k_restrict<float><<<grid, kBlock, 0, c->stream>>>(g, a.dmask, a.P32, fe, r, a.slots, a.ictl);
+    else
+        k_restrict<double><<<grid, kBlock, 0, c->stream>>>(g, a.dmask, a.P, fe, r, a.slots, a.ictl);
 }
 
 void launch_batch_residual(const BatchLaunch &L, int par, bool mixed)
 {
-    if (L.count <= 0) return;
     if (mixed)
-        kb_residual<float><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work, par);
+        launch_persistent(kb_residual<float>, kBlock, L, L.inst, L.work, L.nwork, par);
     else
-        kb_residual<double><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work, par);
+        launch_persistent(kb_residual<double>, kBlock, L, L.inst, L.work, L.nwork, par);
 }
 
-void launch_batch_finalize(const InstDev *inst, int count, int32_t *ndone, hipStream_t st)
+void launch_batch_finalize(const InstDev *inst, int count, hipStream_t st)
 {
-    kb_finalize<<<count, kBlock, 0, st>>>(inst, ndone);
+    kb_finalize<<<count, kBlock, 0, st>>>(inst);
 }
 
-void launch_batch_restrict(const BatchLaunch &L)
+void launch_batch_restrict(const BatchLaunch &L, int precision)
 {
-    if (L.count > 0) kb_restrict<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    if (precision == CAMS_MIXED_BF16)
+        launch_persistent(kb_restrict<uint16_t>, kBlock, L, L.inst, L.work, L.nwork);
+    else if (precision == CAMS_MIXED_FP32)
+        launch_persistent(kb_restrict<float>, kBlock, L, L.inst, L.work, L.nwork);
+    else
+        launch_persistent(kb_restrict<double>, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 void launch_batch_reset(const BatchLaunch &L)
 {
-    if (L.count > 0) kb_reset<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+    launch_persistent(kb_reset, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 void launch_batch_gather(const InstDev *inst, int count, BatchResult *out, hipStream_t st)

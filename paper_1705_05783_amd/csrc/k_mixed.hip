@@ -139,29 +139,36 @@ __global__ __launch_bounds__(kBlock) void k_sub64_lo(GridDev g, const double *__
 
 template <int BF>
 __global__ __launch_bounds__(kBlock) void kb_prolong_lo(const InstDev *__restrict__ inst,
-                                                         const WorkItem *__restrict__ work)
+                                                         const WorkItem *__restrict__ work, const int32_t *nwork)
 {
-    const InstDev *d;
-    const int n = flat_cell(inst, work, d);
-    if (n < 0) return;
-    prolong_lo_body<BF>(d->g, d->a.P32, d->a.Pbf, d->a.dmask, d->a.xc, d->a.d1f, n);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const InstDev *d;
+        const int n = flat_cell(inst, work[t], d);
+        if (n >= 0) prolong_lo_body<BF>(d->g, d->a.P32, d->a.Pbf, d->a.dmask, d->a.xc, d->a.d1f, n);
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void kb_r1_lo(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work)
+__global__ __launch_bounds__(kBlock) void kb_r1_lo(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                                    const int32_t *nwork)
 {
-    const InstDev *d;
-    const int n = flat_cell(inst, work, d);
-    if (n < 0) return;
-    r1_lo_body(d->g, d->a.W32, d->a.diag32, d->a.r, d->a.d1f, d->a.r1f, n);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const InstDev *d;
+        const int n = flat_cell(inst, work[t], d);
+        if (n >= 0) r1_lo_body(d->g, d->a.W32, d->a.diag32, d->a.r, d->a.d1f, d->a.r1f, n);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void kb_sub64_lo(const InstDev *__restrict__ inst,
-                                                       const WorkItem *__restrict__ work)
+                                                       const WorkItem *__restrict__ work, const int32_t *nwork)
 {
-    const InstDev *d;
-    const int n = flat_cell(inst, work, d);
-    if (n < 0) return;
-    sub64_lo_body(d->g, d->a.W, d->a.diag, d->a.d0f, d->a.r, n);
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const InstDev *d;
+        const int n = flat_cell(inst, work[t], d);
+        if (n >= 0) sub64_lo_body(d->g, d->a.W, d->a.diag, d->a.d0f, d->a.r, n);
+    }
 }
 
 }  // namespace
@@ -203,29 +210,26 @@ void launch_sub64_lo(cams_ctx *c, const float *x, double *r, const int32_t *done
 
 void launch_batch_prolong(const BatchLaunch &L, bool mixed, bool bf16)
 {
-    if (L.count <= 0) return;
     if (!mixed)
         launch_batch_prolong64(L);
     else if (bf16)
-        kb_prolong_lo<1><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+        launch_persistent(kb_prolong_lo<1>, kBlock, L, L.inst, L.work, L.nwork);
     else
-        kb_prolong_lo<0><<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+        launch_persistent(kb_prolong_lo<0>, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 void launch_batch_r1(const BatchLaunch &L, bool mixed)
 {
-    if (L.count <= 0) return;
     if (mixed)
-        kb_r1_lo<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+        launch_persistent(kb_r1_lo, kBlock, L, L.inst, L.work, L.nwork);
     else
         launch_batch_r1_64(L);
 }
 
 void launch_batch_sub_pre(const BatchLaunch &L, bool mixed)
 {
-    if (L.count <= 0) return;
     if (mixed)
-        kb_sub64_lo<<<L.count, kBlock, 0, L.stream>>>(L.inst, L.work);
+        launch_persistent(kb_sub64_lo, kBlock, L, L.inst, L.work, L.nwork);
     else
         launch_batch_sub_pre64(L);
 }

@@ -2,9 +2,9 @@
 // steps).  The grid is cut into 8x8x8 cell blocks (8x8 in 2D; the last block
 // of an axis may be shorter).  Couplings across block faces are left out of
 // the factorisation, so every block is an independent ILU(0) in natural
-// order that one workgroup solves in LDS by hyperplane wavefronts
-// (i+j+k = const, 22 levels for a full block); the Richardson residual of
-// each step still uses the full matrix.
+// order that one wave solves in LDS by hyperplane wavefronts (i+j+k =
+// const, 22 levels for a full block); the Richardson residual of each step
+// still uses the full matrix.
 //
 // For the 7-point matrix in natural order ILU(0) keeps the off-diagonals of
 // A and only modifies the diagonal: d_i = a_ii - sum_{j<i} W_ij^2 / d_j.
@@ -103,106 +103,140 @@ __global__ __launch_bounds__(ST) void k_bilu_setup(GridDev g, const double *__re
     if (b.active) invd[b.n] = 1.0 / d[b.t];
 }
 
+constexpr int PAD = SB * SB;
+
 // One Richardson step  e_new = e_old + M^{-1}(rhs - A e_old)  (e_old = 0 when
-// null) for one block.  All 512 threads stage the block in one memory round
-// trip (residual with the full matrix, pivots, in-block couplings) into LDS;
-// then the first wave alone sweeps the hyperplanes forward and backward,
-// one lane per x-pencil (so the sweeps need only wave-level ordering, no
-// workgroup barrier); finally all threads write the block back.  e_old and e_new must be different arrays: neighbouring blocks
-// read e_old across block faces.  Skipped once `done` (nullable) is set.
-// T: arithmetic and storage of the smoother (double, or float in the mixed
-// precision solve); TR: type of the right-hand side.
-template <class T, class TR>
+// null) for logical block `blk` by a workgroup of NT threads (NT = 64..512,
+// ST / NT cells per thread): all threads stage the block (residual with the
+// full matrix, pivots, in-block couplings) into LDS; the first wave alone
+// sweeps the hyperplanes forward and backward, one lane per x-pencil (only
+// wave-level ordering inside the sweeps); then all threads write the block
+// back.  Fewer threads per block let a compute unit keep more blocks, and so
+// more of the latency-bound sweeps, in flight; the batched solve tunes NT.
+// e_old and e_new must be different arrays: neighbouring blocks read e_old
+// across block faces.  T: arithmetic and storage of the smoother (double, or
+// float in the mixed precision solve); TR: type of the right-hand side.
+//
+// y and the +x/+y/+z couplings carry SB*SB zero entries on both sides, so
+// the sweeps read neighbours without bounds tests: a coupling that leaves
+// the block (or the grid) is zero, and its partner value is finite.
+template <class T>
+struct SmoothLds {
+    T y[ST + 2 * PAD], wx[ST + 2 * PAD], wy[ST + 2 * PAD], wz[ST + 2 * PAD], dinv[ST];
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    // LDS operations of one wave execute in order; keep the compiler from
+    // moving the next step's reads above this step's writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T, class TR, int NT>
 __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
                                                const T *__restrict__ invd, const TR *__restrict__ rhs,
-                                               const T *__restrict__ eold, T *__restrict__ enew, int blk)
+                                               const T *__restrict__ eold, T *__restrict__ enew, int blk,
+                                               SmoothLds<T> &L)
 {
-    // y and the +x/+y/+z couplings carry SB*SB zero entries on both sides, so
-    // the sweeps read neighbours without bounds tests: a coupling that leaves
-    // the block (or the grid) is zero, and its partner value is finite.
-    constexpr int PAD = SB * SB;
-    __shared__ T y[ST + 2 * PAD], wx[ST + 2 * PAD], wy[ST + 2 * PAD], wz[ST + 2 * PAD], dinv[ST];
-    const BlockCell b = block_cell(g, blk);
+    constexpr int CPT = ST / NT;   // cells per thread
+    const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
+    const int i0 = (blk % nbx) * SB, j0 = ((blk / nbx) % nby) * SB, k0 = (blk / (nbx * nby)) * SB;
+    const int ex = min(SB, g.nx - i0), ey = min(SB, g.ny - j0), ez = min(SB, g.nz - k0);
     const T *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
-    T z = 0, e0 = 0, id = 0, fx = 0, fy = 0, fz = 0;
-    if (b.active) {
-        const int n = b.n;
-        const T fxm = b.i > 0 ? Wx[n - 1] : T(0), fxp = b.i + 1 < g.nx ? Wx[n] : T(0);
-        const T fym = b.j > 0 ? Wy[n - g.nx] : T(0), fyp = b.j + 1 < g.ny ? Wy[n] : T(0);
-        const T fzm = b.k > 0 ? Wz[n - g.sxy] : T(0), fzp = b.k + 1 < g.nz ? Wz[n] : T(0);
-        z = (T)rhs[n];
-        if (eold) {
-            e0 = eold[n];
-            T ae = diag[n] * e0;
-            if (b.i > 0) ae -= fxm * eold[n - 1];
-            if (b.i + 1 < g.nx) ae -= fxp * eold[n + 1];
-            if (b.j > 0) ae -= fym * eold[n - g.nx];
-            if (b.j + 1 < g.ny) ae -= fyp * eold[n + g.nx];
-            if (b.k > 0) ae -= fzm * eold[n - g.sxy];
-            if (b.k + 1 < g.nz) ae -= fzp * eold[n + g.sxy];
-            z -= ae;
-        }
-        id = invd[n];
-        // coupling to the +x/+y/+z neighbour when it lies in the block
-        fx = b.li + 1 < b.ex ? fxp : T(0);
-        fy = b.lj + 1 < b.ey ? fyp : T(0);
-        fz = b.lk + 1 < b.ez ? fzp : T(0);
+    for (int q = threadIdx.x; q < 2 * PAD; q += NT) {
+        const int idx = q < PAD ? q : ST + q;
+        L.y[idx] = 0;
+        L.wx[idx] = 0;
+        L.wy[idx] = 0;
+        L.wz[idx] = 0;
     }
-    y[PAD + b.t] = z;
-    dinv[b.t] = id;
-    wx[PAD + b.t] = fx;
-    wy[PAD + b.t] = fy;
-    wz[PAD + b.t] = fz;
-    if (threadIdx.x < 2 * PAD) {
-        const int q = threadIdx.x < PAD ? threadIdx.x : ST + threadIdx.x;
-        y[q] = 0;
-        wx[q] = 0;
-        wy[q] = 0;
-        wz[q] = 0;
+    T e0[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int t = threadIdx.x + NT * c;
+        const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
+        T z = 0, ev = 0, id = 0, fx = 0, fy = 0, fz = 0;
+        if (li < ex && lj < ey && lk < ez) {
+            const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+            const int n = i + g.nx * (j + g.ny * k);
+            const T fxm = i > 0 ? Wx[n - 1] : T(0), fxp = i + 1 < g.nx ? Wx[n] : T(0);
+            const T fym = j > 0 ? Wy[n - g.nx] : T(0), fyp = j + 1 < g.ny ? Wy[n] : T(0);
+            const T fzm = k > 0 ? Wz[n - g.sxy] : T(0), fzp = k + 1 < g.nz ? Wz[n] : T(0);
+            z = (T)rhs[n];
+            if (eold) {
+                ev = eold[n];
+                T ae = diag[n] * ev;
+                if (i > 0) ae -= fxm * eold[n - 1];
+                if (i + 1 < g.nx) ae -= fxp * eold[n + 1];
+                if (j > 0) ae -= fym * eold[n - g.nx];
+                if (j + 1 < g.ny) ae -= fyp * eold[n + g.nx];
+                if (k > 0) ae -= fzm * eold[n - g.sxy];
+                if (k + 1 < g.nz) ae -= fzp * eold[n + g.sxy];
+                z -= ae;
+            }
+            id = invd[n];
+            // coupling to the +x/+y/+z neighbour when it lies in the block
+            fx = li + 1 < ex ? fxp : T(0);
+            fy = lj + 1 < ey ? fyp : T(0);
+            fz = lk + 1 < ez ? fzp : T(0);
+        }
+        e0[c] = ev;
+        L.y[PAD + t] = z;
+        L.dinv[t] = id;
+        L.wx[PAD + t] = fx;
+        L.wy[PAD + t] = fy;
+        L.wz[PAD + t] = fz;
     }
     __syncthreads();
     if (threadIdx.x < 64) {
-        // lane owns the x-pencil (lj, lk) = (lane % 8, lane / 8); at time step
-        // tau it handles the cell li = tau - lj - lk of hyperplane tau
+        // lane owns the x-pencil (pj, pk) = (lane % 8, lane / 8); at time step
+        // tau it handles the cell li = tau - pj - pk of hyperplane tau
+        T *y = L.y, *wx = L.wx, *wy = L.wy, *wz = L.wz, *dinv = L.dinv;
         const int pj = threadIdx.x & (SB - 1), pk = threadIdx.x >> 3;
-        const bool pencil = pj < b.ey && pk < b.ez;
-        const int nlev = b.ex + b.ey + b.ez - 2;
+        const bool pencil = pj < ey && pk < ez;
+        const int nlev = ex + ey + ez - 2;
         const int base = PAD + SB * pj + SB * SB * pk;
         for (int tau = 0; tau < nlev; ++tau) {
             const int a = tau - pj - pk;
-            const bool act = pencil && a >= 0 && a < b.ex;
+            const bool act = pencil && a >= 0 && a < ex;
             const int t = base + min(max(a, 0), SB - 1);
             const T s = y[t] + wx[t - 1] * y[t - 1] + wy[t - SB] * y[t - SB] + wz[t - SB * SB] * y[t - SB * SB];
             if (act) y[t] = s * dinv[t - PAD];
-            // LDS operations of one wave execute in order; keep the compiler
-            // from moving the next step's reads above this step's writes
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync();
         }
         for (int tau = nlev - 1; tau >= 0; --tau) {
             const int a = tau - pj - pk;
-            const bool act = pencil && a >= 0 && a < b.ex;
+            const bool act = pencil && a >= 0 && a < ex;
             const int t = base + min(max(a, 0), SB - 1);
             const T s = wx[t] * y[t + 1] + wy[t] * y[t + SB] + wz[t] * y[t + SB * SB];
             if (act) y[t] += s * dinv[t - PAD];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync();
         }
     }
     __syncthreads();
-    if (b.active) enew[b.n] = e0 + y[PAD + b.t];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int t = threadIdx.x + NT * c;
+        const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
+        if (li < ex && lj < ey && lk < ez)
+            enew[(i0 + li) + g.nx * ((j0 + lj) + g.ny * (k0 + lk))] = e0[c] + L.y[PAD + t];
+    }
 }
 
-template <class T, class TR>
-__global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
+// Threads per block of the single-problem smoother.
+constexpr int kSmoothThreads = ST;
+
+template <class T, class TR, int NT>
+__global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
                                                    const T *__restrict__ invd, const TR *__restrict__ rhs,
                                                    const T *__restrict__ eold, T *__restrict__ enew,
                                                    const int32_t *done)
 {
+    __shared__ SmoothLds<T> lds;
     if (done && *done) return;
-    bilu_step_body<T, TR>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x));
+    bilu_step_body<T, TR, NT>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds);
 }
 
 // Batched step `s` of `steps` for every instance.  `post` selects the
@@ -210,30 +244,34 @@ __global__ __launch_bounds__(ST) void k_bilu_step(GridDev g, const T *__restrict
 // is r, or in the mixed-precision post-smoothing the FP32 r1.  The work list
 // is ordered host-side so that each XCD receives a contiguous range of
 // logical blocks.
-template <class T, class TR>
-__global__ __launch_bounds__(ST) void kb_bilu_step(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
-                                                    int post, int s, int steps)
+template <class T, class TR, int NT>
+__global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
+                                                    const int32_t *nwork, int post, int s, int steps)
 {
-    const WorkItem w = work[blockIdx.x];
-    const InstDev &d = inst[w.inst];
-    if (d.a.ictl[C_DONE]) return;
-    const Arrays &a = d.a;
-    const T *W, *diag, *invd;
-    T *e, *scratch;
-    if constexpr (sizeof(T) == 4) {
-        W = a.W32; diag = a.diag32; invd = a.invd32; e = post ? a.d2f : a.d0f; scratch = a.zf;
-    } else {
-        W = a.W; diag = a.diag; invd = a.invd; e = post ? a.d2 : a.d0; scratch = a.z;
+    __shared__ SmoothLds<T> lds;
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        if (d.a.ictl[C_DONE]) continue;
+        const Arrays &a = d.a;
+        const T *W, *diag, *invd;
+        T *e, *scratch;
+        if constexpr (sizeof(T) == 4) {
+            W = a.W32; diag = a.diag32; invd = a.invd32; e = post ? a.d2f : a.d0f; scratch = a.zf;
+        } else {
+            W = a.W; diag = a.diag; invd = a.invd; e = post ? a.d2 : a.d0; scratch = a.z;
+        }
+        const TR *rhs;
+        if constexpr (sizeof(TR) == 4)
+            rhs = a.r1f;
+        else
+            rhs = a.r;
+        T *buf[2] = {e, scratch};
+        T *out = buf[(steps - 1 - s) & 1];
+        const T *prev = s > 0 ? buf[(steps - s) & 1] : nullptr;
+        bilu_step_body<T, TR, NT>(d.g, W, diag, invd, rhs, prev, out, w.blk, lds);
     }
-    const TR *rhs;
-    if constexpr (sizeof(TR) == 4)
-        rhs = a.r1f;
-    else
-        rhs = a.r;
-    T *buf[2] = {e, scratch};
-    T *out = buf[(steps - 1 - s) & 1];
-    const T *prev = s > 0 ? buf[(steps - s) & 1] : nullptr;
-    bilu_step_body<T, TR>(d.g, W, diag, invd, rhs, prev, out, w.blk);
 }
 
 inline int num_sblocks(const GridDev &g)
@@ -266,7 +304,8 @@ void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR
     if (timed) prof_begin(c, bytes, steps);
     for (int s = 0; s < steps; ++s) {
         T *out = buf[(steps - 1 - s) & 1];
-        k_bilu_step<T, TR><<<nb, ST, 0, c->stream>>>(c->g, W, diag, invd, rhs, prev, out, done);
+        k_bilu_step<T, TR, kSmoothThreads><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, invd, rhs, prev,
+                                                                                 out, done);
         prev = out;
     }
     if (timed) prof_end(c);
@@ -290,20 +329,30 @@ void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, c
     bilu_smooth<float, double>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done);
 }
 
-// Batched smoothing: `steps` Richardson steps from zero for every instance.
-// rhs_kind 0: pre-smoothing on r; 1: post-smoothing (on r1 in FP32 when mixed,
-// else on r, which then holds r1).
-void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed)
+template <class T, class TR>
+void batch_smooth_nt(const BatchLaunch &L, int steps, int rhs_kind, int nt)
 {
-    if (L.count <= 0) return;
     for (int s = 0; s < steps; ++s) {
-        if (!mixed)
-            kb_bilu_step<double, double><<<L.count, ST, 0, L.stream>>>(L.inst, L.work, rhs_kind, s, steps);
-        else if (rhs_kind == 1)
-            kb_bilu_step<float, float><<<L.count, ST, 0, L.stream>>>(L.inst, L.work, rhs_kind, s, steps);
-        else
-            kb_bilu_step<float, double><<<L.count, ST, 0, L.stream>>>(L.inst, L.work, rhs_kind, s, steps);
+        switch (nt) {
+        case 128: launch_persistent(kb_bilu_step<T, TR, 128>, 128, L, L.inst, L.work, L.nwork, rhs_kind, s, steps); break;
+        case 256: launch_persistent(kb_bilu_step<T, TR, 256>, 256, L, L.inst, L.work, L.nwork, rhs_kind, s, steps); break;
+        default: launch_persistent(kb_bilu_step<T, TR, ST>, ST, L, L.inst, L.work, L.nwork, rhs_kind, s, steps); break;
+        }
     }
+}
+
+// Batched smoothing: `steps` Richardson steps from zero for every instance,
+// with `nt` threads per block (128, 256 or 512).  rhs_kind 0: pre-smoothing
+// on r; 1: post-smoothing (on r1 in FP32 when mixed, else on r, which then
+// holds r1).
+void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed, int nt)
+{
+    if (!mixed)
+        batch_smooth_nt<double, double>(L, steps, rhs_kind, nt);
+    else if (rhs_kind == 1)
+        batch_smooth_nt<float, float>(L, steps, rhs_kind, nt);
+    else
+        batch_smooth_nt<float, double>(L, steps, rhs_kind, nt);
 }
 
 }  // namespace cams
