@@ -291,6 +291,19 @@ cams_status cams_basis_stats(const cams_ctx *ctx, int32_t *learned_blocks, int32
 /* Number of coarse nodes (product of ceil(n/r) per axis). */
 int64_t cams_num_coarse(const cams_ctx *ctx);
 
+/* Coarse factorisation layout.  The MSFE coarse operator couples only nodes
+ * of adjacent z-planes of the coarse grid (a basis function of Eq. (11)
+ * vanishes on the vertex planes beside its own), so for 3D grids with more
+ * than 4096 coarse nodes and at least 3 planes it is factorised by block
+ * elimination over the planes (Schur complements S_k = D_k - L_k S_{k-1}^-1
+ * U_{k-1}, each inverted densely) instead of one dense inversion.  Returns
+ * the number of planes in that case, 0 for the dense explicit inverse. */
+int32_t cams_coarse_planes(const cams_ctx *ctx);
+
+/* Test hook: xc_dev = A_c^-1 rc_dev (Nc device doubles each) with the
+ * factorisation of the last cams_coarse_op.  Synchronises. */
+cams_status cams_debug_coarse_solve(cams_ctx *ctx, const double *rc_dev, double *xc_dev);
+
 cams_status cams_destroy(cams_ctx *ctx);
 const char *cams_status_string(cams_status s);
 const char *cams_last_error(const cams_ctx *ctx);

@@ -108,6 +108,8 @@ _SIGS = [
     ("cams_status_string", ctypes.c_char_p, [_I]),
     ("cams_last_error", ctypes.c_char_p, [_VP]),
     ("cams_invalidate_basis", _I, [_VP]),
+    ("cams_coarse_planes", ctypes.c_int32, [_VP]),
+    ("cams_debug_coarse_solve", _I, [_VP, _VP, _VP]),
     ("cams_batch_create", _I, [ctypes.POINTER(_VP), ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
     ("cams_batch_workspace_bytes", ctypes.c_size_t, [_VP]),
     ("cams_batch_set_workspace", _I, [_VP, _VP, ctypes.c_size_t]),
@@ -199,3 +201,5 @@ cams_batch_tuning = _fwd("cams_batch_tuning")
 cams_batch_last_error = _fwd("cams_batch_last_error")
 cams_batch_destroy = _fwd("cams_batch_destroy")
 cams_invalidate_basis = _fwd("cams_invalidate_basis")
+cams_coarse_planes = _fwd("cams_coarse_planes")
+cams_debug_coarse_solve = _fwd("cams_debug_coarse_solve")

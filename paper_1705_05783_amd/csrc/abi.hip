@@ -291,6 +291,8 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     for (int a = 0; a < 3; ++a) { g.nb[a] = nb[a]; g.r[a] = r[a]; }
     g.Nc = nb[0] * nb[1] * nb[2];
     g.dim = three_d ? 3 : 2;
+    // large MSFE coarse grids: block-tridiagonal elimination over z-planes
+    c->blocktri = O.restriction == CAMS_R_FE && three_d && g.Nc > kBlockTriMin && nb[2] >= 3;
     c->fl = {F.rho0, F.c, F.p0, F.mu, F.dt};
 
     // per-axis tables: vc (nb), lo (n), isv (n, stored as int32)
@@ -430,6 +432,8 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
 size_t cams_workspace_bytes(const cams_ctx *c) { return c ? c->need : 0; }
 
 int64_t cams_num_coarse(const cams_ctx *c) { return c ? c->g.Nc : 0; }
+
+int32_t cams_coarse_planes(const cams_ctx *c) { return c && c->blocktri ? c->g.nb[2] : 0; }
 
 cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
 {
@@ -603,11 +607,16 @@ void enqueue_basis_local(cams_ctx *c)
     if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
 }
 
-void enqueue_coarse(cams_ctx *c)
+void enqueue_coarse_operator(cams_ctx *c)
 {
     launch_coarse_operator(c);
     launch_ilu_setup(c);
     if (c->opt.precision != CAMS_FP64) launch_convert_matrix32(c);
+}
+
+void enqueue_coarse(cams_ctx *c)
+{
+    enqueue_coarse_operator(c);
     launch_coarse_factor(c);
 }
 
@@ -907,6 +916,20 @@ cams_status cams_debug_gemm_sub(cams_ctx *c, double *C, const double *A, const d
         CAMS_HIP(hipStreamSynchronize(c->stream));
     } catch (const HipError &e) {
         return fail(c, CAMS_E_DEVICE, std::string("gemm: ") + hipGetErrorString(e.code));
+    }
+    return CAMS_OK;
+}
+
+cams_status cams_debug_coarse_solve(cams_ctx *c, const double *rc, double *xc)
+{
+    if (!c || !rc || !xc) return CAMS_E_ARG;
+    if (!c->has_coarse) return fail(c, CAMS_E_STATE, "coarse solve before coarse_op");
+    try {
+        launch_coarse_solve(c, rc, xc);
+        CAMS_HIP(hipGetLastError());
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("coarse solve: ") + hipGetErrorString(e.code));
     }
     return CAMS_OK;
 }

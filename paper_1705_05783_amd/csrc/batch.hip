@@ -1,8 +1,10 @@
 // Batched C-AMS: many independent problems of different sizes advanced by
 // one Newton iteration together.  The setup of each instance (basis,
-// assembly, coarse operator and its inverse, smoother pivots) is enqueued on
-// a few side streams so that the instances' small kernels overlap; the
-// C-AMS iterations then run as ONE launch per kernel for all instances.
+// assembly, coarse operator, smoother pivots) is enqueued on a few side
+// streams so that the instances' small kernels overlap; the factorisation
+// and inverse of the MSFE coarse operators then run batched (one launch per
+// panel step for all instances, their GEMM tiles in one grid), and the
+// C-AMS iterations as ONE launch per kernel for all instances.
 // Each batched kernel is persistent: as many workgroups as the device holds
 // at once walk a work list of (instance, block) items in device memory.
 // A fixed number of iterations is captured once into a HIP graph and
@@ -90,8 +92,14 @@ struct cams_batch {
     std::vector<double> cells;       // cells per instance
     std::vector<char> listed;        // instance in the device lists
     double listed_cells = 0.0;
-    size_t off_inst = 0, off_list[L_NUM + 1] = {}, off_nwork = 0, off_res = 0, off_pptr = 0,
-           need = 0;
+    size_t off_inst = 0, off_list[L_NUM + 1] = {}, off_nwork = 0, off_res = 0, off_pptr = 0, off_lu_steps = 0,
+           off_lu_gemms = 0, need = 0;
+    // batched factorisation of the MSFE instances (plan built with the workspace)
+    std::vector<cams_ctx *> fe;
+    size_t lu_steps_cap = 0, lu_gemms_cap = 0;
+    BatchLuPlan lu;
+    LuStep *d_steps = nullptr;
+    GemmDesc *d_gemms = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     InstDev *inst = nullptr;
@@ -306,7 +314,7 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         for (int k = 0; k < nflat; ++k) b->lists[L_FLAT].push_back({i, k});
         const int nsb = ((g.nx + 7) / 8) * ((g.ny + 7) / 8) * ((g.nz + 7) / 8);
         for (int k = 0; k < nsb; ++k) b->lists[L_SBLOCK].push_back({i, k});
-        for (int k = 0; k < (g.Nc + kBlock / 64 - 1) / (kBlock / 64); ++k) b->lists[L_RESTRICT].push_back({i, k});
+        for (int k = 0; k < g.Nc; ++k) b->lists[L_RESTRICT].push_back({i, k});
         for (int k = 0; k < (g.Nc + kBlock - 1) / kBlock; ++k) b->lists[L_NODES].push_back({i, k});
         for (int k = 0; k < (g.Nc + kBlock / 64 - 1) / (kBlock / 64); ++k) b->lists[L_ROWS].push_back({i, k});
     }
@@ -329,6 +337,17 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
     o = align_up(o + count * sizeof(BatchResult));
     b->off_pptr = o;
     o = align_up(o + count * sizeof(double *));
+    for (int i = 0; i < count; ++i)
+        if (ctxs[i]->opt.restriction == CAMS_R_FE) {
+            const size_t T = (ctxs[i]->g.Nc + 63) / 64;
+            b->fe.push_back(ctxs[i]);
+            b->lu_steps_cap += T;
+            b->lu_gemms_cap += 7 * T;   // per panel at most: L21, U12, trailing, two forward, two backward
+        }
+    b->off_lu_steps = o;
+    o = align_up(o + b->lu_steps_cap * sizeof(LuStep));
+    b->off_lu_gemms = o;
+    o = align_up(o + b->lu_gemms_cap * sizeof(GemmDesc));
     b->need = o;
     *out = b;
     return CAMS_OK;
@@ -370,6 +389,8 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
         for (int l = 0; l <= L_NUM; ++l) b->work[l] = (WorkItem *)(w + b->off_list[l]);
         b->nwork = (int32_t *)(w + b->off_nwork);
         b->res = (BatchResult *)(w + b->off_res);
+        b->d_steps = (LuStep *)(w + b->off_lu_steps);
+        b->d_gemms = (GemmDesc *)(w + b->off_lu_gemms);
         b->pptr = (double **)(w + b->off_pptr);
         b->h_inst.resize(count);
         for (int i = 0; i < count; ++i) {
@@ -397,6 +418,15 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
                                     hipMemcpyHostToDevice, b->stream));
             CAMS_HIP(hipStreamSynchronize(b->stream));   // `full` must outlive the copy
         }
+        plan_batch_lu(b->fe, b->lu);
+        if (b->lu.steps.size() > b->lu_steps_cap || b->lu.gemms.size() > b->lu_gemms_cap)
+            return bfail(b, CAMS_E_STATE, "factorisation plan exceeds its capacity");
+        if (!b->lu.steps.empty())
+            CAMS_HIP(hipMemcpyAsync(b->d_steps, b->lu.steps.data(), b->lu.steps.size() * sizeof(LuStep),
+                                    hipMemcpyHostToDevice, b->stream));
+        if (!b->lu.gemms.empty())
+            CAMS_HIP(hipMemcpyAsync(b->d_gemms, b->lu.gemms.data(), b->lu.gemms.size() * sizeof(GemmDesc),
+                                    hipMemcpyHostToDevice, b->stream));
         upload_lists(b, std::vector<char>(count, 1));
         // occupancy of every batched kernel, before any capture
         enqueue_batch_iteration(b, 0, true);
@@ -443,7 +473,11 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
                 launch_impose_wells(c, p_dev[i]);
                 if (!c->has_basis) enqueue_basis_local(c);
                 enqueue_assemble(c, p_dev[i], pn_dev[i]);
-                enqueue_coarse(c);
+                enqueue_coarse_operator(c);
+                if (c->opt.restriction == CAMS_R_FE)
+                    launch_coarse_factor_prepare(c);   // factorised below, batched
+                else
+                    launch_coarse_factor(c);
                 launch_iter_reset(c);
             } catch (...) {
                 c->stream = own;
@@ -455,6 +489,7 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
             CAMS_HIP(hipEventRecord(b->join[s], b->side[s]));
             CAMS_HIP(hipStreamWaitEvent(b->stream, b->join[s], 0));
         }
+        launch_batch_lu(b->lu, b->d_steps, b->d_gemms, b->stream);
         CAMS_HIP(hipGetLastError());
         CAMS_HIP(hipEventRecord(b->ev[1], b->stream));
 

@@ -13,6 +13,7 @@ namespace cams {
 
 constexpr int kMaxRatio = 8;      // largest coarsening ratio the LDS local solves support
 constexpr int kBlock = 256;       // threads per workgroup of the fine-grid kernels
+constexpr int kBlockTriMin = 4096; // MSFE coarse grids above this many nodes use block-tridiagonal elimination
 
 // Grid descriptor passed by value to kernels.  Per-axis tables live in the
 // workspace: vertex coordinates (nb entries), "is vertex coordinate" flags
@@ -149,6 +150,7 @@ struct cams_ctx {
     int region_total;
     int maxm[4], maxbw[4];  // largest local system per stage
     int nfull;              // interior regions that are full 7x7x7 dual blocks (listed first)
+    bool blocktri;          // coarse operator factorised by block-tridiagonal elimination over z-planes
     // learned basis: network parameters and scratch (caller-owned), settings, counters
     const float *learned_params;
     char *learned_scratch;
@@ -240,6 +242,7 @@ void launch_restrict(cams_ctx *c, const double *r);   // slot partials of R r (s
 void enqueue_clear_status(cams_ctx *c);
 void enqueue_assemble(cams_ctx *c, const double *p, const double *pn);
 void enqueue_basis_local(cams_ctx *c);
+void enqueue_coarse_operator(cams_ctx *c);   // A_c, smoother pivots, FP32 copies (no factorisation)
 void enqueue_coarse(cams_ctx *c);
 
 // ---- batched iteration (one launch per kernel for all instances)
@@ -277,10 +280,45 @@ void cnn_targets(cams_ctx *c, const Region *regs, int nblk, float *tgt);
 void cnn_scatter(cams_ctx *c, const Region *regs, int nblk, const float *phi);
 void cnn_block_residual(cams_ctx *c, const Region *regs, int nblk, double *ratio);
 
+// ---- batched coarse factorisation (k_coarse.hip)
+// Diagonal-block step of one instance: factor F (n x n) at (j0, j0), nb
+// columns, and the inverses of its two triangles (Linv, Uinv: 64 x 64).
+struct LuStep {
+    double *F;
+    int n, j0, nb;
+    int32_t *status;
+    double *Linv, *Uinv;
+};
+// C = alpha A B + beta C for one instance; its tiles are tile0 .. tile0 +
+// tiles_n * ceil(M / 64) - 1 of the launch.
+struct GemmDesc {
+    double *C;
+    const double *A, *B;
+    int ldc, lda, ldb, M, N, K;
+    double alpha, beta;
+    int tiles_n, tile0;
+};
+struct BatchLuPlan {
+    enum Kind { DIAG = 0, TRI = 1, GEMM = 2 };
+    struct Launch {
+        int kind;
+        size_t off;     // into steps (DIAG, TRI) or gemms (GEMM)
+        int count;      // descriptors
+        int tiles;      // GEMM: workgroups
+    };
+    std::vector<LuStep> steps;
+    std::vector<GemmDesc> gemms;
+    std::vector<Launch> launches;
+};
+void launch_coarse_factor_prepare(cams_ctx *c);
+void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan);
+void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDesc *gemms, hipStream_t st);
+
 // ---- coarse level (k_coarse.hip)
 void launch_coarse_operator(cams_ctx *c);
 void launch_coarse_factor(cams_ctx *c);   // LU + explicit inverse of Ac
 void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done);
+void launch_coarse_solve(cams_ctx *c, const double *rc, double *xc);   // xc = A_c^-1 rc
 
 }  // namespace cams
 

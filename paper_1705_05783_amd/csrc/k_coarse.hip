@@ -17,6 +17,8 @@
 #include "cams_internal.h"
 #include "dev_util.h"
 
+#include <algorithm>
+
 namespace cams {
 
 namespace {
@@ -251,8 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_lu_panel_lds(double *__restrict__ A,
 // Unpivoted LU of the nb x nb diagonal block at (j0, j0), in LDS (MSFE:
 // the coarse operator is symmetric positive definite, so no pivoting is
 // needed).  A non-positive pivot is flagged.
-__global__ __launch_bounds__(kBlock) void k_lu_diag_nopiv(double *__restrict__ A, int n, int j0, int nb,
-                                                           int32_t *status)
+__device__ __forceinline__ void lu_diag_body(double *__restrict__ A, int n, int j0, int nb, int32_t *status)
 {
     __shared__ double D[kNB][kNB + 1];
     for (int t = threadIdx.x; t < nb * nb; t += kBlock) D[t / nb][t % nb] = A[(size_t)(j0 + t / nb) * n + j0 + t % nb];
@@ -274,6 +275,12 @@ __global__ __launch_bounds__(kBlock) void k_lu_diag_nopiv(double *__restrict__ A
         __syncthreads();
     }
     for (int t = threadIdx.x; t < nb * nb; t += kBlock) A[(size_t)(j0 + t / nb) * n + j0 + t % nb] = D[t / nb][t % nb];
+}
+
+__global__ __launch_bounds__(kBlock) void k_lu_diag_nopiv(double *__restrict__ A, int n, int j0, int nb,
+                                                           int32_t *status)
+{
+    lu_diag_body(A, n, j0, nb, status);
 }
 
 // Apply the panel's interchanges to the columns outside [j0, j0+nb).
@@ -299,8 +306,8 @@ __global__ __launch_bounds__(kBlock) void k_lu_swap(double *__restrict__ A, int 
 // (backward).  A block shorter than kNB is padded with identity rows so the
 // loops are static and the column stays in registers.  Column-oriented
 // updates keep up to 63 independent FMAs in flight per step.
-__global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, int n, int j0, int nb, double *B,
-                                                  int ldb, int col0, int ncols, int upper)
+__device__ __forceinline__ void trsm_body(const double *__restrict__ F, int n, int j0, int nb, double *B, int ldb,
+                                          int col0, int ncols, int upper, int colblock)
 {
     __shared__ double Ls[kNB][kNB + 1];
     for (int t = threadIdx.x; t < kNB * kNB; t += kBlock) {
@@ -310,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
         Ls[r][c] = v;
     }
     __syncthreads();
-    const int col = col0 + blockIdx.x * kBlock + threadIdx.x;
+    const int col = col0 + colblock * kBlock + threadIdx.x;
     if (col >= col0 + ncols) return;
     double x[kNB];
 #pragma unroll
@@ -333,6 +340,12 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
         if (r < nb) B[(size_t)(j0 + r) * ldb + col] = x[r];
 }
 
+__global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, int n, int j0, int nb, double *B,
+                                                  int ldb, int col0, int ncols, int upper)
+{
+    trsm_body(F, n, j0, nb, B, ldb, col0, ncols, upper, blockIdx.x);
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // C (M x Nn, ldc) = alpha A (M x K, lda) B (K x Nn, ldb) + beta C; row-major.
@@ -343,12 +356,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // LDS 16 at a time.  Operand lanes: A row = lane%16, k = lane/16; B col =
 // lane%16, k = lane/16; result element v of a lane: row lane/16 + 4v,
 // col lane%16 (checked against a host GEMM by the parity tests).
-__global__ __launch_bounds__(kBlock) void k_gemm(double *C, int ldc, const double *A, int lda, const double *B,
-                                                  int ldb, int M, int Nn, int K, double alpha, double beta)
+__device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, int lda, const double *B, int ldb,
+                                          int M, int Nn, int K, double alpha, double beta, int tm, int tn)
 {
     __shared__ double As[64][17];
     __shared__ double Bs[16][65];
-    const int tm = blockIdx.y * 64, tn = blockIdx.x * 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     v4d acc[2][2];
@@ -395,6 +407,46 @@ __global__ __launch_bounds__(kBlock) void k_gemm(double *C, int ldc, const doubl
                     C[(size_t)r * ldc + c] = beta == 0.0 ? prod : beta * C[(size_t)r * ldc + c] + prod;
                 }
             }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemm(double *C, int ldc, const double *A, int lda, const double *B,
+                                                  int ldb, int M, int Nn, int K, double alpha, double beta)
+{
+    gemm_tile(C, ldc, A, lda, B, ldb, M, Nn, K, alpha, beta, blockIdx.y * 64, blockIdx.x * 64);
+}
+
+// ---- batched unpivoted factorisation and inverse (MSFE instances of a
+// batch): every launch carries one descriptor per participating instance;
+// a GEMM launch covers all tiles of all its descriptors.
+
+__global__ __launch_bounds__(kBlock) void kb_lu_diag(const LuStep *__restrict__ st)
+{
+    const LuStep s = st[blockIdx.x];
+    lu_diag_body(s.F, s.n, s.j0, s.nb, s.status);
+}
+
+// Workgroup 2 i: L^-1 of descriptor i's diagonal block, 2 i + 1: U^-1.
+__global__ __launch_bounds__(kBlock) void kb_tri_inv(const LuStep *__restrict__ st)
+{
+    const LuStep s = st[blockIdx.x >> 1];
+    const int upper = blockIdx.x & 1;
+    double *out = upper ? s.Uinv : s.Linv;
+    trsm_body(s.F, s.n, s.j0, s.nb, out - (size_t)s.j0 * kNB, kNB, 0, kNB, upper, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_gemm(const GemmDesc *__restrict__ d, int nd)
+{
+    // the descriptor whose tile range holds this workgroup (binary search on tile0)
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc g = d[lo];
+    const int t = blockIdx.x - g.tile0;
+    gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
+              (t % g.tiles_n) * 64);
 }
 
 __global__ __launch_bounds__(kBlock) void k_identity_piv(int32_t *__restrict__ piv, int n)
@@ -485,6 +537,33 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
     if (lane == 0) y[row] = s;
 }
 
+// y = alpha M x + beta y for an m-row block M (leading dimension ldm, ncol
+// columns), one wave per row; used by the block-tridiagonal coarse solve.
+__global__ __launch_bounds__(kBlock) void k_gemv_ab(const double *__restrict__ M, int ldm, int m, int ncol,
+                                                     const double *__restrict__ x, double *y, double alpha,
+                                                     double beta, const int32_t *done)
+{
+    if (done && *done) return;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= m) return;
+    const double *mr = M + (size_t)row * ldm;
+    double s = 0.0;
+    for (int c = lane; c < ncol; c += 64) s += mr[c] * x[c];
+    s = wave_sum(s);
+    if (lane == 0) y[row] = beta == 0.0 ? alpha * s : beta * y[row] + alpha * s;
+}
+
+// dst (rows x cols, ldd) = src (lds)
+__global__ __launch_bounds__(kBlock) void k_copy2d(const double *__restrict__ src, int lds, double *__restrict__ dst,
+                                                    int ldd, int rows, int cols)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (size_t)rows * cols) return;
+    const int r = (int)(t / cols), c = (int)(t % cols);
+    dst[(size_t)r * ldd + c] = src[(size_t)r * lds + c];
+}
+
 // Batched coarse solve: rc = R r from the slot partials (work item = block
 // of kBlock coarse nodes), then xc = Ainv rc (work item = kBlock/64 rows).
 __global__ __launch_bounds__(kBlock) void kb_node_sum(const InstDev *__restrict__ inst,
@@ -554,61 +633,265 @@ void launch_coarse_operator(cams_ctx *c)
                                                     c->opt.restriction == CAMS_R_FE, c->a.Ac);
 }
 
+// The per-instance part of the batched MSFE factorisation: working copy of
+// A_c, identity triangle blocks and X = I.
+void launch_coarse_factor_prepare(cams_ctx *c)
+{
+    const int n = c->g.Nc;
+    const size_t nn = (size_t)n * n;
+    const int npan = (n + kNB - 1) / kNB;
+    k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, c->a.work, nn);
+    k_identity64<<<cdiv((size_t)2 * npan * kNB * kNB, kBlock), kBlock, 0, c->stream>>>(c->a.tri, 2 * npan);
+    k_identity_piv<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n);
+    k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, c->a.Ainv);
+}
+
+// The launches of the batched factorisation and inverse; each step mirrors
+// the single-instance MSFE sequence of launch_coarse_factor, so every
+// instance gets the same operations in the same order.
+void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan)
+{
+    plan = BatchLuPlan();
+    int maxT = 0;
+    for (const cams_ctx *c : fe) maxT = std::max(maxT, (c->g.Nc + kNB - 1) / kNB);
+    auto add_gemm = [&](std::vector<GemmDesc> &v, double *C, int ldc, const double *A, int lda, const double *B,
+                        int ldb, int M, int Nn, int K, double alpha, double beta) {
+        if (M <= 0 || Nn <= 0 || K <= 0) return;
+        GemmDesc g{C, A, B, ldc, lda, ldb, M, Nn, K, alpha, beta, (int)cdiv(Nn, 64), 0};
+        v.push_back(g);
+    };
+    auto flush_gemms = [&](std::vector<GemmDesc> &v) {
+        if (v.empty()) return;
+        int tiles = 0;
+        for (GemmDesc &g : v) {
+            g.tile0 = tiles;
+            tiles += g.tiles_n * (int)cdiv(g.M, 64);
+        }
+        plan.launches.push_back({BatchLuPlan::GEMM, plan.gemms.size(), (int)v.size(), tiles});
+        plan.gemms.insert(plan.gemms.end(), v.begin(), v.end());
+        v.clear();
+    };
+    std::vector<GemmDesc> v;
+    for (int b = 0; b < maxT; ++b) {
+        std::vector<LuStep> steps;
+        for (const cams_ctx *c : fe) {
+            const int n = c->g.Nc, j0 = b * kNB;
+            if (j0 >= n) continue;
+            const int nb = std::min(kNB, n - j0);
+            double *Linv = c->a.tri + (size_t)(2 * b) * kNB * kNB;
+            steps.push_back({c->a.work, n, j0, nb, c->a.status, Linv, Linv + kNB * kNB});
+        }
+        plan.launches.push_back({BatchLuPlan::DIAG, plan.steps.size(), (int)steps.size(), 0});
+        plan.launches.push_back({BatchLuPlan::TRI, plan.steps.size(), (int)steps.size(), 0});
+        plan.steps.insert(plan.steps.end(), steps.begin(), steps.end());
+        for (const cams_ctx *c : fe) {   // L21 = A21 U^-1 and U12 = L^-1 A12 (independent)
+            const int n = c->g.Nc, j0 = b * kNB;
+            if (j0 >= n) continue;
+            const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
+            if (rest <= 0) continue;
+            double *F = c->a.work, *Linv = c->a.tri + (size_t)(2 * b) * kNB * kNB, *Uinv = Linv + kNB * kNB;
+            double *A21 = F + (size_t)(j0 + nb) * n + j0, *A12 = F + (size_t)j0 * n + j0 + nb;
+            add_gemm(v, A21, n, A21, n, Uinv, kNB, rest, nb, nb, 1.0, 0.0);
+            add_gemm(v, A12, n, Linv, kNB, A12, n, nb, rest, nb, 1.0, 0.0);
+        }
+        flush_gemms(v);
+        for (const cams_ctx *c : fe) {   // A22 -= L21 U12
+            const int n = c->g.Nc, j0 = b * kNB;
+            if (j0 >= n) continue;
+            const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
+            if (rest <= 0) continue;
+            double *F = c->a.work;
+            add_gemm(v, F + (size_t)(j0 + nb) * n + j0 + nb, n, F + (size_t)(j0 + nb) * n + j0, n,
+                     F + (size_t)j0 * n + j0 + nb, n, rest, rest, nb, -1.0, 1.0);
+        }
+        flush_gemms(v);
+    }
+    for (int b = 0; b < maxT; ++b) {   // X = L^-1 X
+        for (const cams_ctx *c : fe) {
+            const int n = c->g.Nc, j0 = b * kNB;
+            if (j0 >= n) continue;
+            const int nb = std::min(kNB, n - j0);
+            double *Xb = c->a.Ainv + (size_t)j0 * n;
+            add_gemm(v, Xb, n, c->a.tri + (size_t)(2 * b) * kNB * kNB, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
+        }
+        flush_gemms(v);
+        for (const cams_ctx *c : fe) {
+            const int n = c->g.Nc, j0 = b * kNB;
+            if (j0 >= n) continue;
+            const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
+            double *X = c->a.Ainv, *F = c->a.work;
+            add_gemm(v, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, X + (size_t)j0 * n, n,
+                     rest, n, nb, -1.0, 1.0);
+        }
+        flush_gemms(v);
+    }
+    for (int b = maxT - 1; b >= 0; --b) {   // X = U^-1 X
+        for (const cams_ctx *c : fe) {
+            const int n = c->g.Nc, j0 = b * kNB;
+            if (j0 >= n) continue;
+            const int nb = std::min(kNB, n - j0);
+            double *Xb = c->a.Ainv + (size_t)j0 * n;
+            add_gemm(v, Xb, n, c->a.tri + (size_t)(2 * b + 1) * kNB * kNB, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
+        }
+        flush_gemms(v);
+        for (const cams_ctx *c : fe) {
+            const int n = c->g.Nc, j0 = b * kNB;
+            if (j0 >= n || j0 == 0) continue;
+            const int nb = std::min(kNB, n - j0);
+            double *X = c->a.Ainv, *F = c->a.work;
+            add_gemm(v, X, n, F + j0, n, X + (size_t)j0 * n, n, j0, n, nb, -1.0, 1.0);
+        }
+        flush_gemms(v);
+    }
+}
+
+void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDesc *gemms, hipStream_t st)
+{
+    for (const BatchLuPlan::Launch &L : plan.launches) {
+        if (L.count <= 0) continue;
+        if (L.kind == BatchLuPlan::DIAG)
+            kb_lu_diag<<<L.count, kBlock, 0, st>>>(steps + L.off);
+        else if (L.kind == BatchLuPlan::TRI)
+            kb_tri_inv<<<2 * L.count, kBlock, 0, st>>>(steps + L.off);
+        else
+            kb_gemm<<<L.tiles, kBlock, 0, st>>>(gemms + L.off, L.count);
+    }
+}
+
+// In-place unpivoted blocked LU of the n x n matrix F (leading dimension n;
+// MSFE: symmetric positive definite) and X = F^-1 (leading dimension n).
+// Per 64-column panel the diagonal block is factorised in LDS and its two
+// triangles are inverted (stored in `tri`); L21 = A21 U11^-1 and U12 =
+// L11^-1 A12 are in-place MFMA products and A22 -= L21 U12.  The inverse
+// follows by block substitutions with the stored triangle inverses.
+static void inverse_nopiv(cams_ctx *c, double *F, double *X, int n)
+{
+    const size_t nn = (size_t)n * n;
+    double *tri = c->a.tri;
+    const int npan = (n + kNB - 1) / kNB;
+    k_identity64<<<cdiv((size_t)2 * npan * kNB * kNB, kBlock), kBlock, 0, c->stream>>>(tri, 2 * npan);
+    for (int b = 0; b < npan; ++b) {
+        const int j0 = b * kNB;
+        const int nb = n - j0 < kNB ? n - j0 : kNB;
+        const int rest = n - j0 - nb;
+        double *Linv = tri + (size_t)(2 * b) * kNB * kNB, *Uinv = Linv + kNB * kNB;
+        k_lu_diag_nopiv<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.status);
+        k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Linv - (size_t)j0 * kNB, kNB, 0, kNB, 0);
+        k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Uinv - (size_t)j0 * kNB, kNB, 0, kNB, 1);
+        if (rest > 0) {
+            double *A21 = F + (size_t)(j0 + nb) * n + j0, *A12 = F + (size_t)j0 * n + j0 + nb;
+            gemm(c, A21, n, A21, n, Uinv, kNB, rest, nb, nb, 1.0, 0.0);
+            gemm(c, A12, n, Linv, kNB, A12, n, nb, rest, nb, 1.0, 0.0);
+            gemm_sub(c, F + (size_t)(j0 + nb) * n + j0 + nb, n, A21, n, A12, n, rest, rest, nb);
+        }
+    }
+    // X = U^-1 L^-1 by block substitutions (all MFMA products)
+    k_identity_piv<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n);
+    k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, X);
+    for (int b = 0; b < npan; ++b) {
+        const int j0 = b * kNB;
+        const int nb = n - j0 < kNB ? n - j0 : kNB;
+        const int rest = n - j0 - nb;
+        const double *Linv = tri + (size_t)(2 * b) * kNB * kNB;
+        double *Xb = X + (size_t)j0 * n;
+        gemm(c, Xb, n, Linv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
+        if (rest > 0) gemm_sub(c, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, Xb, n, rest, n,
+                               nb);
+    }
+    for (int b = npan - 1; b >= 0; --b) {
+        const int j0 = b * kNB;
+        const int nb = n - j0 < kNB ? n - j0 : kNB;
+        const double *Uinv = tri + (size_t)(2 * b + 1) * kNB * kNB;
+        double *Xb = X + (size_t)j0 * n;
+        gemm(c, Xb, n, Uinv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
+        if (j0 > 0) gemm_sub(c, X, n, F + j0, n, Xb, n, j0, n, nb);
+    }
+}
+
+// Blocks of the block-tridiagonal form (coarse nodes ordered plane by plane
+// in z, m = nb_x nb_y nodes per plane, Z planes): E_k = S_k^-1 with the
+// Schur complements S_0 = D_0, S_k = D_k - L_k E_{k-1} U_{k-1}; F_k = L_k
+// E_{k-1} and G_k = E_k U_k.  Stored in Ainv as E (Z m^2), F, G.
+static void blocktri_parts(const cams_ctx *c, double *&E, double *&Fk, double *&G, int &m, int &Z)
+{
+    m = c->g.nb[0] * c->g.nb[1];
+    Z = c->g.nb[2];
+    const size_t mm = (size_t)m * m;
+    E = c->a.Ainv;
+    Fk = E + Z * mm;
+    G = Fk + Z * mm;
+}
+
+// A_c of an MSFE problem couples only nodes of adjacent z-planes (a basis
+// function vanishes on the vertex planes next to its own), so the coarse
+// operator is block tridiagonal by planes.  Factorisation by block
+// elimination: 2 Z dense m x m inversions and products on matrix cores
+// instead of one Nc x Nc inversion (Nc = Z m).
+static void factor_blocktri(cams_ctx *c)
+{
+    double *E, *Fk, *G;
+    int m, Z;
+    blocktri_parts(c, E, Fk, G, m, Z);
+    const int n = c->g.Nc;
+    const size_t mm = (size_t)m * m;
+    const double *Ac = c->a.Ac;
+    double *S = c->a.work;
+    auto D = [&](int k) { return Ac + (size_t)k * m * n + (size_t)k * m; };
+    auto Lo = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k - 1) * m; };
+    auto Up = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k + 1) * m; };
+    for (int k = 0; k < Z; ++k) {
+        k_copy2d<<<cdiv(mm, kBlock), kBlock, 0, c->stream>>>(D(k), n, S, m, m, m);
+        if (k > 0) {
+            gemm(c, Fk + k * mm, m, Lo(k), n, E + (k - 1) * mm, m, m, m, m, 1.0, 0.0);   // F_k = L_k E_{k-1}
+            gemm_sub(c, S, m, Fk + k * mm, m, Up(k - 1), n, m, m, m);                    // S_k -= F_k U_{k-1}
+        }
+        inverse_nopiv(c, S, E + k * mm, m);
+        if (k > 0) {
+            // G_{k-1} = E_{k-1} U_{k-1} (E_{k-1} is final once S_k is formed)
+            gemm(c, G + (k - 1) * mm, m, E + (k - 1) * mm, m, Up(k - 1), n, m, m, m, 1.0, 0.0);
+        }
+    }
+}
+
+// xc = A_c^-1 rc by block forward and backward substitution:
+// g_0 = rc_0, g_k = rc_k - F_k g_{k-1};  x_{Z-1} = E_{Z-1} g_{Z-1},
+// x_k = E_k g_k - G_k x_{k+1}.  rc is overwritten by g.
+static void solve_blocktri(cams_ctx *c, double *rc, double *xc, const int32_t *done)
+{
+    double *E, *Fk, *G;
+    int m, Z;
+    blocktri_parts(c, E, Fk, G, m, Z);
+    const size_t mm = (size_t)m * m;
+    const unsigned grid = cdiv(m, kBlock / 64);
+    for (int k = 1; k < Z; ++k)
+        k_gemv_ab<<<grid, kBlock, 0, c->stream>>>(Fk + k * mm, m, m, m, rc + (size_t)(k - 1) * m,
+                                                  rc + (size_t)k * m, -1.0, 1.0, done);
+    for (int k = Z - 1; k >= 0; --k) {
+        k_gemv_ab<<<grid, kBlock, 0, c->stream>>>(E + k * mm, m, m, m, rc + (size_t)k * m, xc + (size_t)k * m, 1.0,
+                                                  0.0, done);
+        if (k < Z - 1)
+            k_gemv_ab<<<grid, kBlock, 0, c->stream>>>(G + k * mm, m, m, m, xc + (size_t)(k + 1) * m,
+                                                      xc + (size_t)k * m, -1.0, 1.0, done);
+    }
+}
+
 void launch_coarse_factor(cams_ctx *c)
 {
     const int n = c->g.Nc;
     double *F = c->a.work;
     const size_t nn = (size_t)n * n;
-    k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
     const bool pivoting = c->opt.restriction != CAMS_R_FE;
     double *X = c->a.Ainv;
-    if (!pivoting) {
-        // MSFE (SPD): blocked LU without interchanges.  Per 64-column panel:
-        // the diagonal block is factorised in LDS and its two triangles are
-        // inverted (stored in `tri`); then L21 = A21 U11^-1 and
-        // U12 = L11^-1 A12 are in-place MFMA products and A22 -= L21 U12.
-        double *tri = c->a.tri;
-        const int npan = (n + kNB - 1) / kNB;
-        k_identity64<<<cdiv((size_t)2 * npan * kNB * kNB, kBlock), kBlock, 0, c->stream>>>(tri, 2 * npan);
-        for (int b = 0; b < npan; ++b) {
-            const int j0 = b * kNB;
-            const int nb = n - j0 < kNB ? n - j0 : kNB;
-            const int rest = n - j0 - nb;
-            double *Linv = tri + (size_t)(2 * b) * kNB * kNB, *Uinv = Linv + kNB * kNB;
-            k_lu_diag_nopiv<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.status);
-            k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Linv - (size_t)j0 * kNB, kNB, 0, kNB, 0);
-            k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Uinv - (size_t)j0 * kNB, kNB, 0, kNB, 1);
-            if (rest > 0) {
-                double *A21 = F + (size_t)(j0 + nb) * n + j0, *A12 = F + (size_t)j0 * n + j0 + nb;
-                gemm(c, A21, n, A21, n, Uinv, kNB, rest, nb, nb, 1.0, 0.0);
-                gemm(c, A12, n, Linv, kNB, A12, n, nb, rest, nb, 1.0, 0.0);
-                gemm_sub(c, F + (size_t)(j0 + nb) * n + j0 + nb, n, A21, n, A12, n, rest, rest, nb);
-            }
-        }
-        // inverse: X = U^-1 L^-1 by block substitutions with the stored
-        // diagonal-block inverses (all MFMA products)
-        k_identity_piv<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n);
-        k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, X);
-        for (int b = 0; b < npan; ++b) {
-            const int j0 = b * kNB;
-            const int nb = n - j0 < kNB ? n - j0 : kNB;
-            const int rest = n - j0 - nb;
-            const double *Linv = tri + (size_t)(2 * b) * kNB * kNB;
-            double *Xb = X + (size_t)j0 * n;
-            gemm(c, Xb, n, Linv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
-            if (rest > 0) gemm_sub(c, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, Xb, n, rest,
-                                   n, nb);
-        }
-        for (int b = npan - 1; b >= 0; --b) {
-            const int j0 = b * kNB;
-            const int nb = n - j0 < kNB ? n - j0 : kNB;
-            const double *Uinv = tri + (size_t)(2 * b + 1) * kNB * kNB;
-            double *Xb = X + (size_t)j0 * n;
-            gemm(c, Xb, n, Uinv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
-            if (j0 > 0) gemm_sub(c, X, n, F + j0, n, Xb, n, j0, n, nb);
-        }
+    if (c->blocktri) {
+        factor_blocktri(c);
         return;
     }
+    if (!pivoting) {
+        k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
+        inverse_nopiv(c, F, X, n);
+        return;
+    }
+    k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
     // LU with partial pivoting, right looking by panels
     for (int j0 = 0; pivoting && j0 < n; j0 += kNB) {
         const int nb = n - j0 < kNB ? n - j0 : kNB;
@@ -648,7 +931,10 @@ void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done)
 {
     const int n = c->g.Nc;
     const int fe = c->opt.restriction == CAMS_R_FE;
-    if (n <= kGemvLds) {
+    if (c->blocktri) {
+        k_node_sum<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.slots, fe, c->a.rc, done);
+        solve_blocktri(c, c->a.rc, xc, done);
+    } else if (n <= kGemvLds) {
         k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, nullptr, c->g, c->a.slots, fe, xc,
                                                              done);
     } else {
@@ -656,6 +942,17 @@ void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done)
         k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, c->g, nullptr, fe, xc, done);
     }
     (void)rc;
+}
+
+// xc = A_c^-1 rc for a given rc (test hook; rc is copied first).
+void launch_coarse_solve(cams_ctx *c, const double *rc, double *xc)
+{
+    const int n = c->g.Nc;
+    k_copy<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(rc, c->a.rc, (size_t)n);
+    if (c->blocktri)
+        solve_blocktri(c, c->a.rc, xc, nullptr);
+    else
+        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, c->g, nullptr, 0, xc, nullptr);
 }
 
 // Test hook: C -= A B on the device, same kernel as the factorisation.

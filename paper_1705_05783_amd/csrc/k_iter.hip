@@ -143,21 +143,19 @@ __device__ __forceinline__ double basis_value<uint16_t>(const uint16_t *P, size_
     return (double)__uint_as_float((uint32_t)P[i] << 16);
 }
 
-// One wave sums owner box k (cells in x-fastest order, lane-strided, then a
-// fixed shuffle tree per slot); lane 0 writes the 8 slot partials.
+// One workgroup sums owner box k: cells in x-fastest order, thread-strided;
+// per slot a fixed shuffle tree in each wave, then the waves in order.
 template <class TP>
 __device__ __forceinline__ void restrict_box(const GridDev &g, const uint8_t *__restrict__ dm,
                                              const TP *__restrict__ P, int fe, const double *__restrict__ r,
-                                             double *__restrict__ slots, int k)
+                                             double *__restrict__ slots, int k, double *sh)
 {
-    const int lane = threadIdx.x & 63;
     const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
     const int x0 = g.ob[0][ka], y0 = g.ob[1][kb], z0 = g.ob[2][kc];
     const int ex = g.ob[0][ka + 1] - x0, ey = g.ob[1][kb + 1] - y0, ez = g.ob[2][kc + 1] - z0;
     const int m = ex * ey * ez;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
-    for (int t = lane; t < m; t += 64) {
+    for (int t = threadIdx.x; t < m; t += kBlock) {
         const int x = x0 + t % ex, y = y0 + (t / ex) % ey, z = z0 + t / (ex * ey);
         const int n = x + g.nx * (y + g.ny * z);
         const double rn = r[n];
@@ -170,23 +168,29 @@ __device__ __forceinline__ void restrict_box(const GridDev &g, const uint8_t *__
             acc[0] += rn;
         }
     }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = wave_sum(acc[q]);
-    if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) slots[(size_t)k * 8 + q] = acc[q];
+    for (int q = 0; q < 8; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) sh[q * (kBlock / 64) + w] = v;
     }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        double s = 0.0;
+        for (int u = 0; u < kBlock / 64; ++u) s += sh[threadIdx.x * (kBlock / 64) + u];
+        slots[(size_t)k * 8 + threadIdx.x] = s;
+    }
+    __syncthreads();   // sh is reused by the caller's next box
 }
 
-// One wave per owner box, four boxes per workgroup.
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_restrict(GridDev g, const uint8_t *__restrict__ dm,
                                                       const TP *__restrict__ P, int fe, const double *__restrict__ r,
                                                       double *__restrict__ slots, const int32_t *ictl)
 {
+    __shared__ double sh[8 * (kBlock / 64)];
     if (ictl[C_DONE]) return;
-    const int k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (k < g.Nc) restrict_box<TP>(g, dm, P, fe, r, slots, k);
+    restrict_box<TP>(g, dm, P, fe, r, slots, blockIdx.x, sh);
 }
 
 // ---- batched forms: one launch covers every instance of a batch; the work
@@ -234,18 +238,17 @@ __global__ __launch_bounds__(kBlock) void kb_finalize(const InstDev *__restrict_
     finalize_body(d.a.partial, d.nparts, d.a.ictl, d.a.scal, d.rtol2, d.maxit, sh);
 }
 
-// Work item = (instance, group of kBlock/64 owner boxes), one wave per box.
+// Work item = (instance, owner box).
 template <class TP>
 __global__ __launch_bounds__(kBlock) void kb_restrict(const InstDev *__restrict__ inst,
                                                        const WorkItem *__restrict__ work, const int32_t *nwork)
 {
+    __shared__ double sh[8 * (kBlock / 64)];
     CAMS_FOR_ITEMS(t, nwork)
     {
         const WorkItem w = work[t];
         const InstDev &d = inst[w.inst];
         if (d.a.ictl[C_DONE]) continue;
-        const int k = w.blk * (kBlock / 64) + (threadIdx.x >> 6);
-        if (k >= d.g.Nc) continue;   // whole waves; no workgroup barrier follows
         const TP *P;
         if constexpr (sizeof(TP) == 8)
             P = d.a.P;
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const InstDev *__restrict_
             P = d.a.P32;
         else
             P = d.a.Pbf;
-        restrict_box<TP>(d.g, d.a.dmask, P, d.fe, d.a.r, d.a.slots, k);
+        restrict_box<TP>(d.g, d.a.dmask, P, d.fe, d.a.r, d.a.slots, w.blk, sh);
     }
 }
 
@@ -328,7 +331,7 @@ void launch_restrict(cams_ctx *c, const double *r)
     const int fe = c->opt.restriction == CAMS_R_FE;
     const GridDev &g = c->g;
     const Arrays &a = c->a;
-    const int grid = (g.Nc + kBlock / 64 - 1) / (kBlock / 64);
+    const int grid = g.Nc;
     if (c->opt.precision == CAMS_MIXED_BF16)
         k_restrict<uint16_t><<<grid, kBlock, 0, c->stream>>>(g, a.dmask, a.Pbf, fe, r, a.slots, a.ictl);
     else if (c->opt.precision == CAMS_MIXED_FP32)

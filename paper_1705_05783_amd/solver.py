@@ -72,6 +72,12 @@ class Solver:
         C.check(C.cams_set_rock(self.ctx, _ptr(perm), _ptr(phi), _ptr(q) if q is not None else None),
                 self.ctx, "cams_set_rock")
 
+    def coarse_solve(self, rc: torch.Tensor) -> torch.Tensor:
+        """A_c^-1 rc with the current coarse factorisation (test hook)."""
+        xc = torch.empty_like(rc)
+        C.check(C.cams_debug_coarse_solve(self.ctx, _ptr(rc), _ptr(xc)), self.ctx, "cams_debug_coarse_solve")
+        return xc
+
     def invalidate_basis(self):
         """The next step rebuilds the basis from the current transmissibilities."""
         C.check(C.cams_invalidate_basis(self.ctx), self.ctx, "cams_invalidate_basis")

@@ -180,3 +180,20 @@ def test_batch_create_validation(lib):
     assert C.cams_batch_create(None, 0, None, ctypes.byref(ctypes.c_void_p())) == C.CAMS_E_ARG
     for h in ctxs:
         C.cams_destroy(h)
+
+
+def test_coarse_layout_choice(lib):
+    """Block-tridiagonal coarse factorisation exactly for 3D MSFE grids with
+    more than 4096 coarse nodes and at least 3 coarse z-planes."""
+    from paper_1705_05783_amd import _cams as C
+    cases = [((256, 256, 128), C.CAMS_R_FE, 16), ((256, 256, 128), C.CAMS_R_FV, 0),
+             ((128, 128, 128), C.CAMS_R_FE, 0),      # 4096 nodes: dense
+             ((96, 96, 40), C.CAMS_R_FE, 10), ((200, 200, 16), C.CAMS_R_FE, 0)]   # 2 planes: dense
+    for (nx, ny, nz), restr, planes in cases:
+        r = 4 if (nx, ny, nz) == (96, 96, 40) else 8
+        g = C.cams_grid(nx, ny, nz, 1.0, 1.0, 1.0, r, r, r)
+        o = C.cams_options(restr, 0, 5, C.CAMS_FP64, 0, 1e-8, 100, 1e-8, 20)
+        s, h = _create(grid=g, opt=o)
+        assert s == C.CAMS_OK, (nx, ny, nz)
+        assert C.cams_coarse_planes(h) == planes, ((nx, ny, nz), restr, C.cams_num_coarse(h))
+        C.cams_destroy(h)
