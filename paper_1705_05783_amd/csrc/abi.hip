@@ -717,11 +717,15 @@ static void enqueue_iteration(cams_ctx *c, int it)
     const cams_options &O = c->opt;
     Arrays &a = c->a;
     const int32_t *done = a.ictl + 1;
+    // The block smoother's post-smoothing runs on A e = r from e = d1 (the
+    // prolongated coarse correction) instead of on A d2 = r - A d1 from zero:
+    // the same iterates, e = d1 + d2, without forming r1.  The correction
+    // folded into the next residual is then d0 + e.
     if (O.precision != CAMS_FP64) {
         // FP64 residual and update; FP32 corrections (iterative refinement)
         const float *pend0 = O.n_pre > 0 ? a.d0f : nullptr;
-        const float *pend2 = O.n_post > 0 ? a.d2f : nullptr;
-        launch_residual_ctl32(c, a.dp[it & 1], pend0, a.d1f, pend2, a.dp[(it + 1) & 1]);
+        const float *pend1 = O.n_post > 0 ? a.d2f : a.d1f;
+        launch_residual_ctl32(c, a.dp[it & 1], pend0, pend1, nullptr, a.dp[(it + 1) & 1], a.r1f);
         launch_finalize_ctl(c);
         if (O.n_pre > 0) {
             launch_bilu_smooth32(c, (const double *)a.r, a.d0f, O.n_pre, done);
@@ -730,13 +734,14 @@ static void enqueue_iteration(cams_ctx *c, int it)
         launch_restrict(c, a.r);
         launch_gemv(c, a.rc, a.xc, done);
         launch_prolong32(c, a.xc, a.d1f, done);
-        launch_r1_32(c, a.r, a.d1f, a.r1f, done);
-        if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done);
+        if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done, a.d1f);
         return;
     }
+    const bool block = O.smoother == CAMS_SMOOTH_BLOCK_ILU0;
     const double *pend0 = O.n_pre > 0 ? a.d0 : nullptr;
-    const double *pend2 = O.n_post > 0 ? a.d2 : nullptr;
-    launch_residual_ctl(c, a.dp[it & 1], pend0, a.d1, pend2, a.dp[(it + 1) & 1]);
+    const double *pend1 = O.n_post > 0 && block ? a.d2 : a.d1;
+    const double *pend2 = O.n_post > 0 && !block ? a.d2 : nullptr;
+    launch_residual_ctl(c, a.dp[it & 1], pend0, pend1, pend2, a.dp[(it + 1) & 1]);
     launch_finalize_ctl(c);
     if (O.n_pre > 0) {
         launch_smooth(c, a.r, a.d0, O.n_pre, done);
@@ -745,8 +750,14 @@ static void enqueue_iteration(cams_ctx *c, int it)
     launch_restrict(c, a.r);
     launch_gemv(c, a.rc, a.xc, done);                  // Eq. (15): coarse solve
     launch_prolong(c, a.xc, a.d1, done);               // Eq. (12)
-    launch_stencil_sub(c, a.r, a.d1, a.r, done);       // r1 = r - A d1
-    if (O.n_post > 0) launch_smooth(c, a.r, a.d2, O.n_post, done);
+    if (O.n_post > 0) {
+        if (block) {
+            launch_bilu_smooth(c, a.r, a.d2, O.n_post, done, a.d1);
+        } else {
+            launch_stencil_sub(c, a.r, a.d1, a.r, done);   // r1 = r - A d1
+            launch_smooth(c, a.r, a.d2, O.n_post, done);
+        }
+    }
 }
 
 cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)

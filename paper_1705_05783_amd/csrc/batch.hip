@@ -151,7 +151,6 @@ void enqueue_batch_iteration(cams_batch *b, int par, bool prime = false)
     launch_batch_node_sum(L(b, L_NODES, prime));
     launch_batch_gemv(L(b, L_ROWS, prime));
     launch_batch_prolong(L(b, L_FLAT, prime), b->mixed, b->bf16);
-    launch_batch_r1(L(b, L_FLAT, prime), b->mixed);
     if (b->n_post > 0) launch_batch_smooth(L(b, L_SBLOCK, prime), b->n_post, 1, b->mixed, b->smooth_nt);
 }
 

@@ -208,10 +208,13 @@ void launch_axpy(cams_ctx *c, double *y, const double *x, int n);
 
 // ---- block ILU(0) smoother (k_smooth.hip)
 void launch_bilu_setup(cams_ctx *c);
-void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done);
+void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done,
+                        const double *e_init = nullptr);
 
-void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done);
-void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done);
+void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done,
+                          const float *e_init = nullptr);
+void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done,
+                          const float *e_init = nullptr);
 
 // measurement hooks around the smoothing-step launches (abi.hip); only the
 // launches of every kProfEvery-th iteration are bracketed by events, which
@@ -224,8 +227,7 @@ void prof_end(cams_ctx *c);
 void launch_convert_matrix32(cams_ctx *c);   // W, diag, invd -> FP32 copies
 void launch_round_basis(cams_ctx *c);        // P -> FP32 / BF16, P := the rounded values
 void launch_prolong32(cams_ctx *c, const double *xc, float *out, const int32_t *done);
-void launch_r1_32(cams_ctx *c, const double *r, const float *x, float *out, const int32_t *done);
-void launch_sub64_lo(cams_ctx *c, const float *x, double *r, const int32_t *done);
+void launch_sub64_lo(cams_ctx *c, const float *x, double *r, const int32_t *done);   // and r1f = (float) r
 
 // ---- iteration control (k_iter.hip)
 void launch_iter_reset(cams_ctx *c);
@@ -234,7 +236,7 @@ void launch_iter_reset(cams_ctx *c);
 void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, const double *a1, const double *a2,
                          double *dp_out);
 void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
-                           double *dp_out);
+                           double *dp_out, float *rf);   // also rf = (float) r
 void launch_finalize_ctl(cams_ctx *c);   // ||r||, stopping test, iteration counter
 void launch_restrict(cams_ctx *c, const double *r);   // slot partials of R r (stage 1)
 
@@ -254,12 +256,10 @@ void launch_batch_reset(const BatchLaunch &L);   // iteration state of every ins
 void launch_batch_node_sum(const BatchLaunch &L);
 void launch_batch_gemv(const BatchLaunch &L);
 void launch_batch_prolong(const BatchLaunch &L, bool mixed, bool bf16);
-void launch_batch_r1(const BatchLaunch &L, bool mixed);
 void launch_batch_sub_pre(const BatchLaunch &L, bool mixed);
 void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed, int nt);
 void launch_batch_update(const BatchLaunch &L, double *const *p);
 void launch_batch_prolong64(const BatchLaunch &L);
-void launch_batch_r1_64(const BatchLaunch &L);
 void launch_batch_sub_pre64(const BatchLaunch &L);
 
 // ---- basis (k_basis.hip)

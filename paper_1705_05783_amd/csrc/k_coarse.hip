@@ -538,20 +538,21 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
 }
 
 // y = alpha M x + beta y for an m-row block M (leading dimension ldm, ncol
-// columns), one wave per row; used by the block-tridiagonal coarse solve.
+// columns), one workgroup per row (the blocks have ~1000 rows, so a whole
+// workgroup per row keeps enough loads in flight); used by the
+// block-tridiagonal coarse solve.
 __global__ __launch_bounds__(kBlock) void k_gemv_ab(const double *__restrict__ M, int ldm, int m, int ncol,
                                                      const double *__restrict__ x, double *y, double alpha,
                                                      double beta, const int32_t *done)
 {
+    __shared__ double sh[kBlock / 64];
     if (done && *done) return;
-    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= m) return;
+    const int row = blockIdx.x;
     const double *mr = M + (size_t)row * ldm;
     double s = 0.0;
-    for (int c = lane; c < ncol; c += 64) s += mr[c] * x[c];
-    s = wave_sum(s);
-    if (lane == 0) y[row] = beta == 0.0 ? alpha * s : beta * y[row] + alpha * s;
+    for (int c = threadIdx.x; c < ncol; c += kBlock) s += mr[c] * x[c];
+    s = block_sum<kBlock>(s, sh);
+    if (threadIdx.x == 0) y[row] = beta == 0.0 ? alpha * s : beta * y[row] + alpha * s;
 }
 
 // dst (rows x cols, ldd) = src (lds)
@@ -862,7 +863,7 @@ static void solve_blocktri(cams_ctx *c, double *rc, double *xc, const int32_t *d
     int m, Z;
     blocktri_parts(c, E, Fk, G, m, Z);
     const size_t mm = (size_t)m * m;
-    const unsigned grid = cdiv(m, kBlock / 64);
+    const unsigned grid = m;
     for (int k = 1; k < Z; ++k)
         k_gemv_ab<<<grid, kBlock, 0, c->stream>>>(Fk + k * mm, m, m, m, rc + (size_t)(k - 1) * m,
                                                   rc + (size_t)k * m, -1.0, 1.0, done);

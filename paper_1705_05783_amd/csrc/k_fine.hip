@@ -298,20 +298,6 @@ __global__ __launch_bounds__(kBlock) void kb_prolong(const InstDev *__restrict__
     }
 }
 
-// r := r - A d1 (r1 of the FP64 solve, in place)
-__global__ __launch_bounds__(kBlock) void kb_r1(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
-                                                 const int32_t *nwork)
-{
-    CAMS_FOR_ITEMS(t, nwork)
-    {
-        const InstDev *d;
-        const int n = flat_cell(inst, work[t], d);
-        if (n < 0) continue;
-        Vec1 xv{d->a.d1};
-        d->a.r[n] -= apply_A(d->g, d->a.W, d->a.diag, xv, n, d->a.d1[n]);
-    }
-}
-
 // r := r - A d0 after pre-smoothing
 __global__ __launch_bounds__(kBlock) void kb_sub_pre(const InstDev *__restrict__ inst,
                                                       const WorkItem *__restrict__ work, const int32_t *nwork)
@@ -437,11 +423,6 @@ void launch_batch_update(const BatchLaunch &L, double *const *p)
 void launch_batch_prolong64(const BatchLaunch &L)
 {
     launch_persistent(kb_prolong, kBlock, L, L.inst, L.work, L.nwork);
-}
-
-void launch_batch_r1_64(const BatchLaunch &L)
-{
-    launch_persistent(kb_r1, kBlock, L, L.inst, L.work, L.nwork);
 }
 
 void launch_batch_sub_pre64(const BatchLaunch &L)

@@ -42,14 +42,14 @@ struct Pending {
     }
 };
 
-// r = r0 - A v over the cells of workgroup `blk`, dp_out = v, and the
-// workgroup's partial of ||r||^2.
+// r = r0 - A v over the cells of workgroup `blk` (and its FP32 copy rf when
+// given), dp_out = v, and the workgroup's partial of ||r||^2.
 template <class TA>
 __device__ __forceinline__ void residual_body(const GridDev &g, const double *__restrict__ W,
                                               const double *__restrict__ diag, const double *__restrict__ r0,
                                               const Pending<TA> &v, double *__restrict__ dp_out,
-                                              double *__restrict__ r, double *__restrict__ partial, int blk,
-                                              double *sh)
+                                              double *__restrict__ r, float *__restrict__ rf,
+                                              double *__restrict__ partial, int blk, double *sh)
 {
     const int n = blk * kBlock + threadIdx.x;
     double e2 = 0.0;
@@ -66,6 +66,7 @@ __device__ __forceinline__ void residual_body(const GridDev &g, const double *__
         if (c.k + 1 < g.nz) s -= Wz[n] * v(n + g.sxy);
         const double rr = r0[n] - s;
         r[n] = rr;
+        if (rf) rf[n] = (float)rr;
         dp_out[n] = vn;
         e2 = rr * rr;
     }
@@ -78,21 +79,25 @@ __global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double
                                                           const double *__restrict__ diag,
                                                           const double *__restrict__ r0, Pending<TA> v,
                                                           double *__restrict__ dp_out, double *__restrict__ r,
-                                                          double *__restrict__ partial, const int32_t *ictl)
+                                                          float *__restrict__ rf, double *__restrict__ partial,
+                                                          const int32_t *ictl)
 {
     __shared__ double sh[kBlock / 64];
     if (ictl[C_DONE]) return;
     v.fold = ictl[C_IT] > 0;
-    residual_body(g, W, diag, r0, v, dp_out, r, partial, blockIdx.x, sh);
+    residual_body(g, W, diag, r0, v, dp_out, r, rf, partial, blockIdx.x, sh);
 }
 
-// ||r||^2 from the residual kernel's partials and the stopping test.
+// ||r||^2 from the residual kernel's partials and the stopping test, by one
+// workgroup of kFinal threads.
+constexpr int kFinal = 1024;
+
 __device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int nparts, int32_t *ictl,
                                               double *scal, double rtol2, int maxit, double *sh)
 {
     double u = 0.0;
-    for (int t = threadIdx.x; t < nparts; t += kBlock) u += partial[t];
-    const double s = block_sum<kBlock>(u, sh);
+    for (int t = threadIdx.x; t < nparts; t += kFinal) u += partial[t];
+    const double s = block_sum<kFinal>(u, sh);
     if (threadIdx.x != 0) return;
     const int it = ictl[C_IT];
     if (it == 0) scal[S_R0N2] = s;
@@ -113,10 +118,10 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     ictl[C_DONE] = 1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize_ctl(const double *__restrict__ partial, int nparts,
+__global__ __launch_bounds__(kFinal) void k_finalize_ctl(const double *__restrict__ partial, int nparts,
                                                           int32_t *ictl, double *scal, double rtol2, int maxit)
 {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[kFinal / 64];
     if (ictl[C_DONE]) return;
     finalize_body(partial, nparts, ictl, scal, rtol2, maxit, sh);
 }
@@ -200,17 +205,20 @@ __global__ __launch_bounds__(kBlock) void k_restrict(GridDev g, const uint8_t *_
 template <class TA>
 __device__ __forceinline__ Pending<TA> pending_of(const InstDev &d, int par, bool fold);
 
+// Corrections of the previous iteration: d0 (pre-smoothing), then d2, which
+// the post-smoothing started from d1 and so holds d1 + d2, or d1 alone
+// without post-smoothing.
 template <>
 __device__ __forceinline__ Pending<double> pending_of<double>(const InstDev &d, int par, bool fold)
 {
-    return Pending<double>{d.a.dp[par], d.n_pre > 0 ? d.a.d0 : nullptr, d.a.d1, d.n_post > 0 ? d.a.d2 : nullptr,
+    return Pending<double>{d.a.dp[par], d.n_pre > 0 ? d.a.d0 : nullptr, d.n_post > 0 ? d.a.d2 : d.a.d1, nullptr,
                            fold};
 }
 
 template <>
 __device__ __forceinline__ Pending<float> pending_of<float>(const InstDev &d, int par, bool fold)
 {
-    return Pending<float>{d.a.dp[par], d.n_pre > 0 ? d.a.d0f : nullptr, d.a.d1f, d.n_post > 0 ? d.a.d2f : nullptr,
+    return Pending<float>{d.a.dp[par], d.n_pre > 0 ? d.a.d0f : nullptr, d.n_post > 0 ? d.a.d2f : d.a.d1f, nullptr,
                           fold};
 }
 
@@ -225,14 +233,15 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const InstDev *__restrict_
         const InstDev &d = inst[w.inst];
         if (d.a.ictl[C_DONE]) continue;
         const Pending<TA> v = pending_of<TA>(d, par, d.a.ictl[C_IT] > 0);
-        residual_body(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, d.a.partial, w.blk, sh);
+        float *rf = sizeof(TA) == 4 ? d.a.r1f : nullptr;
+        residual_body(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, rf, d.a.partial, w.blk, sh);
     }
 }
 
 // One workgroup per instance.
-__global__ __launch_bounds__(kBlock) void kb_finalize(const InstDev *__restrict__ inst)
+__global__ __launch_bounds__(kFinal) void kb_finalize(const InstDev *__restrict__ inst)
 {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[kFinal / 64];
     const InstDev &d = inst[blockIdx.x];
     if (d.a.ictl[C_DONE]) return;
     finalize_body(d.a.partial, d.nparts, d.a.ictl, d.a.scal, d.rtol2, d.maxit, sh);
@@ -308,21 +317,21 @@ void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, con
 {
     Pending<double> v{dp_in, a0, a1, a2, false};
     k_residual_ctl<double><<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
-        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, c->a.partial, c->a.ictl);
+        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, nullptr, c->a.partial, c->a.ictl);
 }
 
 void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
-                           double *dp_out)
+                           double *dp_out, float *rf)
 {
     Pending<float> v{dp_in, a0, a1, a2, false};
     k_residual_ctl<float><<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
-        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, c->a.partial, c->a.ictl);
+        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, rf, c->a.partial, c->a.ictl);
 }
 
 void launch_finalize_ctl(cams_ctx *c)
 {
     const double rt = c->opt.lin_rtol;
-    k_finalize_ctl<<<1, kBlock, 0, c->stream>>>(c->a.partial, (c->g.N + kBlock - 1) / kBlock, c->a.ictl, c->a.scal,
+    k_finalize_ctl<<<1, kFinal, 0, c->stream>>>(c->a.partial, (c->g.N + kBlock - 1) / kBlock, c->a.ictl, c->a.scal,
                                                 rt * rt, c->opt.lin_maxit);
 }
 
@@ -350,7 +359,7 @@ void launch_batch_residual(const BatchLaunch &L, int par, bool mixed)
 
 void launch_batch_finalize(const InstDev *inst, int count, hipStream_t st)
 {
-    kb_finalize<<<count, kBlock, 0, st>>>(inst);
+    kb_finalize<<<count, kFinal, 0, st>>>(inst);
 }
 
 void launch_batch_restrict(const BatchLaunch &L, int precision)

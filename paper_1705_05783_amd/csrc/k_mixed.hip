@@ -81,37 +81,11 @@ __global__ __launch_bounds__(kBlock) void k_prolong_lo(GridDev g, const float *_
     prolong_lo_body<BF>(g, P32, Pbf, dm, xc, out, n);
 }
 
-// out = r - A32 x in FP32 (r given in FP64).
-__device__ __forceinline__ void r1_lo_body(const GridDev &g, const float *__restrict__ W,
-                                           const float *__restrict__ diag, const double *__restrict__ r,
-                                           const float *__restrict__ x, float *__restrict__ out, int n)
-{
-    const Cell c = cell_of(g, n);
-    const float *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
-    float s = diag[n] * x[n];
-    if (c.i > 0) s -= Wx[n - 1] * x[n - 1];
-    if (c.i + 1 < g.nx) s -= Wx[n] * x[n + 1];
-    if (c.j > 0) s -= Wy[n - g.nx] * x[n - g.nx];
-    if (c.j + 1 < g.ny) s -= Wy[n] * x[n + g.nx];
-    if (c.k > 0) s -= Wz[n - g.sxy] * x[n - g.sxy];
-    if (c.k + 1 < g.nz) s -= Wz[n] * x[n + g.sxy];
-    out[n] = (float)r[n] - s;
-}
-
-__global__ __launch_bounds__(kBlock) void k_r1_lo(GridDev g, const float *__restrict__ W, const float *__restrict__ diag,
-                                                   const double *__restrict__ r, const float *__restrict__ x,
-                                                   float *__restrict__ out, const int32_t *done)
-{
-    if (done && *done) return;
-    const int n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= g.N) return;
-    r1_lo_body(g, W, diag, r, x, out, n);
-}
-
-// r -= A x in FP64 with an FP32 correction x (pre-smoothing update).
+// r -= A x in FP64 with an FP32 correction x (pre-smoothing update), and the
+// FP32 copy rf of the new r.
 __device__ __forceinline__ void sub64_lo_body(const GridDev &g, const double *__restrict__ W,
                                               const double *__restrict__ diag, const float *__restrict__ x,
-                                              double *__restrict__ r, int n)
+                                              double *__restrict__ r, float *__restrict__ rf, int n)
 {
     const Cell c = cell_of(g, n);
     const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
@@ -122,17 +96,20 @@ __device__ __forceinline__ void sub64_lo_body(const GridDev &g, const double *__
     if (c.j + 1 < g.ny) s -= Wy[n] * (double)x[n + g.nx];
     if (c.k > 0) s -= Wz[n - g.sxy] * (double)x[n - g.sxy];
     if (c.k + 1 < g.nz) s -= Wz[n] * (double)x[n + g.sxy];
-    r[n] -= s;
+    const double rn = r[n] - s;
+    r[n] = rn;
+    rf[n] = (float)rn;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sub64_lo(GridDev g, const double *__restrict__ W,
                                                       const double *__restrict__ diag, const float *__restrict__ x,
-                                                      double *__restrict__ r, const int32_t *done)
+                                                      double *__restrict__ r, float *__restrict__ rf,
+                                                      const int32_t *done)
 {
     if (done && *done) return;
     const int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
-    sub64_lo_body(g, W, diag, x, r, n);
+    sub64_lo_body(g, W, diag, x, r, rf, n);
 }
 
 // ---- batched forms: work item = (instance, block of kBlock cells)
@@ -149,17 +126,6 @@ __global__ __launch_bounds__(kBlock) void kb_prolong_lo(const InstDev *__restric
     }
 }
 
-__global__ __launch_bounds__(kBlock) void kb_r1_lo(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
-                                                    const int32_t *nwork)
-{
-    CAMS_FOR_ITEMS(t, nwork)
-    {
-        const InstDev *d;
-        const int n = flat_cell(inst, work[t], d);
-        if (n >= 0) r1_lo_body(d->g, d->a.W32, d->a.diag32, d->a.r, d->a.d1f, d->a.r1f, n);
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void kb_sub64_lo(const InstDev *__restrict__ inst,
                                                        const WorkItem *__restrict__ work, const int32_t *nwork)
 {
@@ -167,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void kb_sub64_lo(const InstDev *__restrict_
     {
         const InstDev *d;
         const int n = flat_cell(inst, work[t], d);
-        if (n >= 0) sub64_lo_body(d->g, d->a.W, d->a.diag, d->a.d0f, d->a.r, n);
+        if (n >= 0) sub64_lo_body(d->g, d->a.W, d->a.diag, d->a.d0f, d->a.r, d->a.r1f, n);
     }
 }
 
@@ -198,14 +164,9 @@ void launch_prolong32(cams_ctx *c, const double *xc, float *out, const int32_t *
                                                                       done);
 }
 
-void launch_r1_32(cams_ctx *c, const double *r, const float *x, float *out, const int32_t *done)
-{
-    k_r1_lo<<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W32, c->a.diag32, r, x, out, done);
-}
-
 void launch_sub64_lo(cams_ctx *c, const float *x, double *r, const int32_t *done)
 {
-    k_sub64_lo<<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, x, r, done);
+    k_sub64_lo<<<blocks_of(c->g.N), kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, x, r, c->a.r1f, done);
 }
 
 void launch_batch_prolong(const BatchLaunch &L, bool mixed, bool bf16)
@@ -216,14 +177,6 @@ void launch_batch_prolong(const BatchLaunch &L, bool mixed, bool bf16)
         launch_persistent(kb_prolong_lo<1>, kBlock, L, L.inst, L.work, L.nwork);
     else
         launch_persistent(kb_prolong_lo<0>, kBlock, L, L.inst, L.work, L.nwork);
-}
-
-void launch_batch_r1(const BatchLaunch &L, bool mixed)
-{
-    if (mixed)
-        launch_persistent(kb_r1_lo, kBlock, L, L.inst, L.work, L.nwork);
-    else
-        launch_batch_r1_64(L);
 }
 
 void launch_batch_sub_pre(const BatchLaunch &L, bool mixed)

@@ -240,10 +240,11 @@ __global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict
 }
 
 // Batched step `s` of `steps` for every instance.  `post` selects the
-// correction (post-smoothing d2, else pre-smoothing d0); the right-hand side
-// is r, or in the mixed-precision post-smoothing the FP32 r1.  The work list
-// is ordered host-side so that each XCD receives a contiguous range of
-// logical blocks.
+// correction: post-smoothing writes d2 starting from d1 (so d2 ends as
+// d1 + the smoothing correction), pre-smoothing writes d0 from zero.  The
+// right-hand side is r, in the mixed-precision post-smoothing its FP32 copy.
+// The work list is ordered host-side so that each XCD receives a contiguous
+// range of logical blocks.
 template <class T, class TR, int NT>
 __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ inst, const WorkItem *__restrict__ work,
                                                     const int32_t *nwork, int post, int s, int steps)
@@ -267,9 +268,14 @@ __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ i
             rhs = a.r1f;
         else
             rhs = a.r;
+        const T *init;   // post-smoothing starts from the prolongated coarse correction
+        if constexpr (sizeof(T) == 4)
+            init = post ? a.d1f : nullptr;
+        else
+            init = post ? a.d1 : nullptr;
         T *buf[2] = {e, scratch};
         T *out = buf[(steps - 1 - s) & 1];
-        const T *prev = s > 0 ? buf[(steps - s) & 1] : nullptr;
+        const T *prev = s > 0 ? buf[(steps - s) & 1] : init;
         bilu_step_body<T, TR, NT>(d.g, W, diag, invd, rhs, prev, out, w.blk, lds);
     }
 }
@@ -288,16 +294,16 @@ void launch_bilu_setup(cams_ctx *c)
 
 template <class T, class TR>
 void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR *rhs, T *e, T *scratch, int steps,
-                 const int32_t *done)
+                 const int32_t *done, const T *e_init)
 {
     const int nb = num_sblocks(c->g);
     T *buf[2] = {e, scratch};
-    const T *prev = nullptr;
+    const T *prev = e_init;
     // algorithmic bytes of a step: rhs, W (3), invd, e_new; plus diag and e_old after the first
     const double n = (double)c->g.N;
     double bytes = 0.0;
     for (int s = 0; s < steps; ++s)
-        bytes += n * ((double)sizeof(TR) + 5.0 * sizeof(T) + (s > 0 ? 2.0 * sizeof(T) : 0.0));
+        bytes += n * ((double)sizeof(TR) + 5.0 * sizeof(T) + (s > 0 || e_init ? 2.0 * sizeof(T) : 0.0));
     // the whole back-to-back sequence is bracketed, which keeps the event
     // overhead per launch small
     const bool timed = c->prof_kernel == CAMS_PROF_SMOOTH_STEP && c->prof_iter % kProfEvery == 0 && steps > 0;
@@ -311,22 +317,26 @@ void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR
     if (timed) prof_end(c);
 }
 
-// e = result of `steps` block-ILU(0) Richardson steps on A e = rhs from e = 0.
-// Ping-pong between e and a scratch vector so the last step writes e.
-void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done)
+// e = result of `steps` block-ILU(0) Richardson steps on A e = rhs from e =
+// e_init (0 when null).  Ping-pong between e and a scratch vector so the
+// last step writes e; e_init must be neither.
+void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done,
+                        const double *e_init)
 {
-    bilu_smooth<double, double>(c, c->a.W, c->a.diag, c->a.invd, rhs, e, c->a.z, steps, done);
+    bilu_smooth<double, double>(c, c->a.W, c->a.diag, c->a.invd, rhs, e, c->a.z, steps, done, e_init);
 }
 
 // The same in FP32 (mixed precision), on the rounded matrix and pivots.
-void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done)
+void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done,
+                          const float *e_init)
 {
-    bilu_smooth<float, float>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done);
+    bilu_smooth<float, float>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done, e_init);
 }
 
-void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done)
+void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done,
+                          const float *e_init)
 {
-    bilu_smooth<float, double>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done);
+    bilu_smooth<float, double>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps, done, e_init);
 }
 
 template <class T, class TR>
@@ -341,10 +351,9 @@ void batch_smooth_nt(const BatchLaunch &L, int steps, int rhs_kind, int nt)
     }
 }
 
-// Batched smoothing: `steps` Richardson steps from zero for every instance,
-// with `nt` threads per block (128, 256 or 512).  rhs_kind 0: pre-smoothing
-// on r; 1: post-smoothing (on r1 in FP32 when mixed, else on r, which then
-// holds r1).
+// Batched smoothing for every instance, `steps` Richardson steps with `nt`
+// threads per block (128, 256 or 512).  rhs_kind 0: pre-smoothing on r from
+// zero; 1: post-smoothing on r (its FP32 copy when mixed) from d1.
 void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed, int nt)
 {
     if (!mixed)
