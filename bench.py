@@ -79,6 +79,7 @@ def cpu_baseline(pb):
 
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E
+LEARNED_FALLBACK_TOL = 10.0   # a network block is re-solved when its basis residual exceeds 10x its boundary flux
 
 
 def timed_run(pb, steps, warmup, torch):
@@ -159,7 +160,98 @@ def batch_run(steps, warmup, torch, sequential=True):
     return out
 
 
-def roofline(prof):
+def large_run(torch):
+    """The 256x256x128 channelised workload (8.4M cells, 16384 coarse nodes,
+    block-tridiagonal coarse factorisation), BF16 basis and prolongation,
+    FP32 smoother, FP64 residual and coarse solve: one pass of its 5 time
+    steps, smoother kernel timed live."""
+    from paper_1705_05783_amd.solver import Solver
+    from workloads.configs import config4
+    pb = config4()
+    solver = Solver(pb, device=torch.device("cuda:0"))
+    solver.profile()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solves, iters, _ = run_workload(solver, pb, torch)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = {"workload": "256x256x128 channelised (k 1 / 1e-4, 30% channels), coarsening 8^3, 16384 coarse nodes, "
+                       "BF16 basis, 5 time steps dt=0.05 to 1e-8",
+           "cells": pb.n, "coarse_nodes": solver.Nc, "s_per_solve": elapsed / max(solves, 1),
+           "ms_per_pass": elapsed * 1e3, "newton_solves": solves,
+           "cams_iterations_per_solve": iters / max(solves, 1),
+           "roofline_smoother": roofline(solver.profile_read(), "256x256x128 channelised BF16")}
+    solver.close()
+    return out
+
+
+def learned_run(torch):
+    """The 128^3 evaluation workload (sigma 3, correlation 8, c = 0.1, one
+    time step): time to solution per Newton linear solve for plain FP64
+    C-AMS, mixed precision, and mixed precision with the trained network for
+    the full dual-block interiors (local-solve fallback for blocks whose
+    basis residual exceeds LEARNED_FALLBACK_TOL times their boundary flux).
+    The basis is rebuilt in every pass, so its cost is in the per-solve
+    time."""
+    import torch as _t
+    from paper_1705_05783_amd import _cams as C
+    from paper_1705_05783_amd.solver import Solver
+    from paper_1705_05783_amd.train_basis import load_weights
+    from workloads.configs import FP64, MIXED_FP32, config5_eval
+    params = load_weights()
+    out = {"workload": "128^3 lognormal (sigma 3, corr. 8), coarsening 8^3, c=0.1, one time step, Newton and "
+                       "linear solves to 1e-8"}
+    for label, prec, learned in (("plain_fp64", FP64, False), ("mixed", MIXED_FP32, False),
+                                 ("learned_mixed", MIXED_FP32, True)):
+        pb = config5_eval(precision=prec)
+        solver = Solver(pb, device=_t.device("cuda:0"))
+        if learned:
+            solver.set_learned(params, fallback_tol=LEARNED_FALLBACK_TOL)
+        run_workload(solver, pb, torch)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solves, iters, _ = run_workload(solver, pb, torch)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        r = {"s_per_solve": elapsed / max(solves, 1), "newton_solves": solves,
+             "cams_iterations_per_solve": iters / max(solves, 1)}
+        if learned:
+            r.update(solver.basis_stats())
+        out[label] = r
+        solver.close()
+    out["speedup_learned_mixed_vs_plain"] = out["plain_fp64"]["s_per_solve"] / out["learned_mixed"]["s_per_solve"]
+    out["speedup_mixed_vs_plain"] = out["plain_fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
+    # basis error of the network against the exact local solves (FP64 storage)
+    pb = config5_eval(precision=FP64)
+    solver = Solver(pb, device=_t.device("cuda:0"))
+    solver.build_basis()
+    P_exact = solver.export(C.CAMS_ARR_P)
+    solver.set_learned(params, fallback_tol=1e30)
+    solver.build_basis()
+    P_net = solver.export(C.CAMS_ARR_P)
+    out["basis_rel_l2_error_no_fallback"] = float((P_net - P_exact).norm() / P_exact.norm())
+    solver.close()
+    return out
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the smoother kernel from the committed memory
+    counter record (FETCH_SIZE + WRITE_SIZE, scaled by a device copy), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_bilu_step.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    w = rec["workloads"].get(workload)
+    return None if w is None else w["traffic_bytes_per_launch"]
+
+
+def roofline(prof, workload=None):
     if prof["launches"] == 0 or prof["total_ms"] <= 0:
         return None
     per_launch_bytes = prof["bytes"] / prof["launches"]
@@ -167,8 +259,8 @@ def roofline(prof):
     achieved = per_launch_bytes / avg_s / 1e9
     return {"kernel": "k_bilu_step (block-ILU(0) Richardson step)", "bound": "hbm",
             "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None, "avg_launch_us": avg_s * 1e6, "bytes_per_launch": per_launch_bytes,
-            "launches": prof["launches"]}
+            "traffic": measured_traffic(workload) if workload else None, "avg_launch_us": avg_s * 1e6,
+            "bytes_per_launch": per_launch_bytes, "launches": prof["launches"]}
 
 
 def main():
@@ -177,8 +269,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["mixed", "plain", "both"], default="both")
+    ap.add_argument("--only", choices=["mixed", "plain", "both", "batch", "large", "learned", "copy"],
+                    default="both",
+                    help="mixed/plain/both: the headline workload; batch/large/learned: that workload alone "
+                         "(one JSON object, for profiling); copy: a 256 MiB device copy, the reference kernel "
+                         "for scaling memory counters")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batched solve")
+    ap.add_argument("--no-extra", action="store_true", help="skip the large and learned-basis workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -188,6 +285,20 @@ def main():
     import torch
     from workloads import config2
     from workloads.configs import FP64, MIXED_FP32
+
+    if args.only == "copy":
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copies": 3}), flush=True)
+        return
+    if args.only in ("batch", "large", "learned"):
+        fn = {"batch": lambda: batch_run(args.steps, args.warmup, torch, sequential=False),
+              "large": lambda: large_run(torch), "learned": lambda: learned_run(torch)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
+        return
 
     runs = {}
     if args.only in ("mixed", "both"):
@@ -225,7 +336,7 @@ def main():
                    "cells": pb.n, "coarse_nodes": head["Nc"],
                    "newton_solves_per_step": head["solves"] / args.steps,
                    "cams_iterations_per_solve": head["iters"] / max(head["solves"], 1)},
-        "roofline": roofline(head["prof"]),
+        "roofline": roofline(head["prof"], "64x64x32 mixed" if "mixed" in runs else None),
     }
     for k, r in runs.items():
         out[k] = summary(r)
@@ -234,6 +345,9 @@ def main():
             (runs["mixed"]["elapsed"] / runs["mixed"]["solves"])
     if not args.no_batch:
         out["batch"] = batch_run(args.steps, args.warmup, torch)
+    if not args.no_extra:
+        out["large"] = large_run(torch)
+        out["learned"] = learned_run(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
     print(json.dumps(out), flush=True)
