@@ -257,6 +257,15 @@ size_t cams_cnn_workspace_bytes(int32_t batch);
  * Errors: CAMS_E_ARG (null pointer, batch <= 0), CAMS_E_DEVICE. */
 cams_status cams_cnn_forward(void *stream, const float *params_dev, const float *feat_dev, int32_t batch,
                              void *ws_dev, float *phi_dev);
+/* The same network on matrix cores: the parameters are converted to
+ * bfloat16 (weights; biases stay FP32) into ws_dev (at least
+ * cams_cnn_bf16_workspace_bytes(), 16-byte aligned), activations are
+ * bfloat16 between layers, every product accumulates in FP32 (one workgroup
+ * per patch, v_mfma_f32_16x16x32_bf16).  This is what cams_build_basis uses
+ * for the learned interiors.  Errors: CAMS_E_ARG, CAMS_E_DEVICE. */
+size_t cams_cnn_bf16_workspace_bytes(void);
+cams_status cams_cnn_forward_bf16(void *stream, const float *params_dev, const float *feat_dev, int32_t batch,
+                                  void *ws_dev, float *phi_dev);
 /* Mean-squared error of phi against tgt over the interior cells and 8 channels
  * (written to *loss_dev, a device double) and its gradient wrt the
  * parameters (grad_dev, cams_cnn_num_params floats); the project's own

@@ -93,6 +93,8 @@ _SIGS = [
     ("cams_cnn_num_params", ctypes.c_int64, []),
     ("cams_cnn_workspace_bytes", ctypes.c_size_t, [ctypes.c_int32]),
     ("cams_cnn_forward", _I, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
+    ("cams_cnn_bf16_workspace_bytes", ctypes.c_size_t, []),
+    ("cams_cnn_forward_bf16", _I, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
     ("cams_cnn_loss_grad", _I, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("cams_cnn_adam", _I, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                            ctypes.c_float, ctypes.c_float, ctypes.c_float]),
@@ -203,3 +205,5 @@ cams_batch_destroy = _fwd("cams_batch_destroy")
 cams_invalidate_basis = _fwd("cams_invalidate_basis")
 cams_coarse_planes = _fwd("cams_coarse_planes")
 cams_debug_coarse_solve = _fwd("cams_debug_coarse_solve")
+cams_cnn_bf16_workspace_bytes = _fwd("cams_cnn_bf16_workspace_bytes")
+cams_cnn_forward_bf16 = _fwd("cams_cnn_forward_bf16")

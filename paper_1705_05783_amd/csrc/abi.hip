@@ -160,13 +160,11 @@ static void prof_collect(cams_ctx *c, int valid_below)
 }
 
 // Learned scratch layout: [feat | phi | ratio | fallback regions | network workspace (chunk)].
-static int learned_chunk(const cams_ctx *c) { return std::min(c->nfull, 1024); }
-
 static size_t learned_scratch_need(const cams_ctx *c)
 {
-    const size_t nf = (size_t)c->nfull, ch = (size_t)learned_chunk(c);
+    const size_t nf = (size_t)c->nfull;
     return align_up(nf * 3 * 729 * 4) + align_up(nf * 8 * 729 * 4) + align_up(nf * 8) +
-           align_up(nf * sizeof(Region)) + align_up(cnn_workspace_floats((int)std::max<size_t>(ch, 1)) * 4);
+           align_up(nf * sizeof(Region)) + align_up(cnn_bf16_bytes());
 }
 
 // Basis with the network predicting the interiors of full dual blocks:
@@ -192,11 +190,8 @@ static void build_basis_learned(cams_ctx *c)
     const Region *full = c->a.regions + c->regoff[3];
     launch_basis_regions(c, 3, full + c->nfull, c->nreg[3] - c->nfull);   // stubs
     cnn_features(c, full, c->nfull, feat);
-    const int ch = learned_chunk(c);
-    for (int b0 = 0; b0 < c->nfull; b0 += ch) {
-        const int nb = std::min(ch, c->nfull - b0);
-        cnn_forward(c->stream, c->learned_params, feat + (size_t)b0 * 3 * 729, nb, ws, phi + (size_t)b0 * 8 * 729);
-    }
+    // inference on matrix cores (BF16 weights and activations, FP32 accumulation)
+    cnn_forward_bf16(c->stream, c->learned_params, feat, c->nfull, ws, phi);
     cnn_scatter(c, full, c->nfull, phi);
     cnn_block_residual(c, full, c->nfull, ratio);
     std::vector<double> r(nf);
@@ -954,6 +949,16 @@ cams_status cams_cnn_forward(void *stream, const float *params, const float *fea
 {
     if (!params || !feat || !ws || !phi || batch <= 0) return CAMS_E_ARG;
     cnn_forward((hipStream_t)stream, params, feat, batch, (float *)ws, phi);
+    return hipGetLastError() == hipSuccess ? CAMS_OK : CAMS_E_DEVICE;
+}
+
+size_t cams_cnn_bf16_workspace_bytes(void) { return cnn_bf16_bytes(); }
+
+cams_status cams_cnn_forward_bf16(void *stream, const float *params, const float *feat, int32_t batch, void *ws,
+                                  float *phi)
+{
+    if (!params || !feat || !ws || !phi || batch <= 0 || ((uintptr_t)ws & 15)) return CAMS_E_ARG;
+    cnn_forward_bf16((hipStream_t)stream, params, feat, batch, ws, phi);
     return hipGetLastError() == hipSuccess ? CAMS_OK : CAMS_E_DEVICE;
 }
 

@@ -275,6 +275,8 @@ void cnn_loss_grad(hipStream_t st, const float *params, const float *feat, const
                    float *grad, double *loss_out);
 void cnn_adam(hipStream_t st, float *p, const float *g, float *m, float *v, int n, int t, float lr, float b1,
               float b2, float eps);
+size_t cnn_bf16_bytes();
+void cnn_forward_bf16(hipStream_t st, const float *params, const float *feat, int B, void *wb, float *phi_out);
 void cnn_features(cams_ctx *c, const Region *regs, int nblk, float *feat);
 void cnn_targets(cams_ctx *c, const Region *regs, int nblk, float *tgt);
 void cnn_scatter(cams_ctx *c, const Region *regs, int nblk, const float *phi);
@@ -299,10 +301,10 @@ struct GemmDesc {
     int tiles_n, tile0;
 };
 struct BatchLuPlan {
-    enum Kind { DIAG = 0, TRI = 1, GEMM = 2 };
+    enum Kind { DIAG = 0, GEMM = 2 };
     struct Launch {
         int kind;
-        size_t off;     // into steps (DIAG, TRI) or gemms (GEMM)
+        size_t off;     // into steps (DIAG) or gemms (GEMM)
         int count;      // descriptors
         int tiles;      // GEMM: workgroups
     };

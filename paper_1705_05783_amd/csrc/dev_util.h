@@ -48,6 +48,16 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return s;
 }
 
+// Bijection from the dispatch id to a logical block id such that each of the
+// 8 XCDs (which receive dispatch ids round-robin) works on one contiguous
+// range of logical blocks, so neighbouring blocks share one L2.
+__device__ __forceinline__ int xcd_swizzle(int wg, int n)
+{
+    const int q = n / 8, rem = n % 8;
+    const int xcd = wg % 8, slot = wg / 8;
+    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
+}
+
 __device__ __forceinline__ int node_index(const GridDev &g, int a, int b, int c)
 {
     return a + g.nb[0] * (b + g.nb[1] * c);

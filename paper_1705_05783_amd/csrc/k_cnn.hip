@@ -23,6 +23,7 @@ constexpr int PP = PD * PD * PD;      // 729 positions
 constexpr int CT = 256;               // threads per workgroup
 constexpr int COG = 8;                // output channels per workgroup
 constexpr int MAXC = 32;
+__constant__ int kLayersDev[4][2] = {{3, 32}, {32, 32}, {32, 32}, {32, 8}};
 
 __device__ __forceinline__ int nb_pos(int p, int tap)
 {
@@ -398,6 +399,128 @@ static CnnWs carve(float *ws, int B)
     return w;
 }
 
+// ---- inference on matrix cores (BF16 weights and activations, FP32
+// accumulation): one workgroup runs the whole network for one patch with
+// both activation buffers in LDS.  Each layer is an implicit GEMM:
+// out[p][co] = sum over 27 taps of X[p + d(tap)][0..31] . W[tap][0..31][co],
+// one v_mfma_f32_16x16x32_bf16 per (16 positions, 16 channels, tap).
+// Activations are position-major with 32 channels (zero padded), so an A
+// fragment (8 consecutive channels of one position) is one 16-byte LDS read;
+// each wave keeps the B fragments of all 27 taps of its 16 output channels
+// in registers and walks its share of the 46 position tiles.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int KC = 32;             // channels per position in the inference buffers
+constexpr int NPT = 46;            // 16-position tiles per patch (736 >= 729)
+constexpr int IT = 512;            // threads of the inference workgroup (8 waves)
+constexpr int kWbLayer = 27 * KC * KC;   // bf16 weights per layer
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// wb[l][tap][co][ci] (co, ci padded to 32, zeros outside) from the FP32
+// parameters W[tap][ci][co]; bb[l][co] FP32 biases (zero padded).
+__global__ __launch_bounds__(CT) void k_prepare_bf16(const float *__restrict__ params, uint16_t *__restrict__ wb,
+                                                      float *__restrict__ bb)
+{
+    const int t = blockIdx.x * CT + threadIdx.x;
+    if (t >= 4 * kWbLayer + 4 * KC) return;
+    if (t >= 4 * kWbLayer) {
+        const int l = (t - 4 * kWbLayer) / KC, co = (t - 4 * kWbLayer) % KC;
+        size_t off = 0;
+        for (int q = 0; q < l; ++q) off += 27 * kLayersDev[q][0] * kLayersDev[q][1] + kLayersDev[q][1];
+        const int Ci = kLayersDev[l][0], Co = kLayersDev[l][1];
+        bb[l * KC + co] = co < Co ? params[off + 27 * Ci * Co + co] : 0.f;
+        return;
+    }
+    const int l = t / kWbLayer, e = t % kWbLayer;
+    const int tap = e / (KC * KC), co = (e / KC) % KC, ci = e % KC;
+    const int Ci = kLayersDev[l][0], Co = kLayersDev[l][1];
+    size_t off = 0;
+    for (int q = 0; q < l; ++q) off += 27 * kLayersDev[q][0] * kLayersDev[q][1] + kLayersDev[q][1];
+    const float w = (ci < Ci && co < Co) ? params[off + ((size_t)tap * Ci + ci) * Co + co] : 0.f;
+    wb[t] = bf16_bits(w);
+}
+
+__global__ __launch_bounds__(IT) void k_cnn_infer(const float *__restrict__ feat, const uint16_t *__restrict__ wb,
+                                                   const float *__restrict__ bb, float *__restrict__ phi)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t bufA[NPT * 16 * KC];
+    __shared__ __attribute__((aligned(16))) uint16_t bufB[NPT * 16 * KC];
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // input: 3 channels of ln T, zero elsewhere (padding channels and rows)
+    for (int t = threadIdx.x; t < NPT * 16 * KC; t += IT) {
+        const int p = t / KC, c = t % KC;
+        bufA[t] = (c < 3 && p < PP) ? bf16_bits(feat[((size_t)b * 3 + c) * PP + p]) : (uint16_t)0;
+    }
+    __syncthreads();
+    const int row = lane & 15, kq = lane >> 4;   // A row / B column, 8-wide k slice
+    for (int l = 0; l < 4; ++l) {
+        const uint16_t *in = (l & 1) ? bufB : bufA;
+        uint16_t *out = (l & 1) ? bufA : bufB;
+        const int Co = kLayersDev[l][1];
+        const int ntile_c = (Co + 15) / 16;                 // 2 (32 channels) or 1 (8)
+        const int cot = wave % ntile_c, pstart = wave / ntile_c, pstep = 8 / ntile_c;
+        const int co = cot * 16 + row;
+        bf16x8 bw[27];
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap)
+            bw[tap] = *(const bf16x8 *)(wb + (size_t)l * kWbLayer + ((size_t)tap * KC + co) * KC + 8 * kq);
+        const float bias = bb[l * KC + co];
+        for (int pt = pstart; pt < NPT; pt += pstep) {
+            const int p = pt * 16 + row;
+            const int x = p % PD, y = (p / PD) % PD, z = p / (PD * PD);
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int tap = 0; tap < 27; ++tap) {
+                const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+                const int X = x + dx, Y = y + dy, Z = z + dz;
+                const bool ok = p < PP && X >= 0 && X < PD && Y >= 0 && Y < PD && Z >= 0 && Z < PD;
+                const int q = ok ? X + PD * (Y + PD * Z) : 0;
+                bf16x8 a = *(const bf16x8 *)(in + q * KC + 8 * kq);
+                if (!ok) a = bf16x8{};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[tap], acc, 0, 0, 0);
+            }
+            // D element v of this lane: position pt*16 + 4 kq + v, channel co
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int pr = pt * 16 + 4 * kq + v;
+                float val = acc[v] + bias;
+                if (l < 3) {
+                    out[pr * KC + co] = bf16_bits(fmaxf(val, 0.f));
+                } else if (co < 8) {
+                    ((float *)out)[pr * 8 + co] = val;   // logits, FP32
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // softmax over the 8 channels (the last layer wrote FP32 logits [p][8] to bufA)
+    const float *lg = (const float *)bufA;
+    for (int p = threadIdx.x; p < PP; p += IT) {
+        float m = lg[p * 8];
+#pragma unroll
+        for (int s = 1; s < 8; ++s) m = fmaxf(m, lg[p * 8 + s]);
+        float e[8], sum = 0.f;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            e[s] = __expf(lg[p * 8 + s] - m);
+            sum += e[s];
+        }
+        const float inv = 1.f / sum;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) phi[((size_t)b * 8 + s) * PP + p] = e[s] * inv;
+    }
+}
+
 void cnn_forward(hipStream_t st, const float *params, const float *feat, int B, float *ws_f, float *phi_out)
 {
     CnnWs w = carve(ws_f, B);
@@ -475,6 +598,19 @@ void cnn_scatter(cams_ctx *c, const Region *regs, int nblk, const float *phi)
 void cnn_block_residual(cams_ctx *c, const Region *regs, int nblk, double *ratio)
 {
     if (nblk > 0) k_block_residual<<<nblk, CT, 0, c->stream>>>(c->g, c->a.T, c->a.P, regs, ratio);
+}
+
+// Bytes of the inference weights (bf16) and biases prepared by cnn_forward_bf16.
+size_t cnn_bf16_bytes() { return 4 * kWbLayer * 2 + 4 * KC * 4; }
+
+// phi_out[b][8][729] from the BF16 matrix-core path; `wb` (cnn_bf16_bytes,
+// 16-byte aligned) receives the converted weights first.
+void cnn_forward_bf16(hipStream_t st, const float *params, const float *feat, int B, void *wb, float *phi_out)
+{
+    uint16_t *w16 = (uint16_t *)wb;
+    float *bias = (float *)(w16 + 4 * kWbLayer);
+    k_prepare_bf16<<<cdiv_u(4 * kWbLayer + 4 * KC, CT), CT, 0, st>>>(params, w16, bias);
+    if (B > 0) k_cnn_infer<<<B, IT, 0, st>>>(feat, w16, bias, phi_out);
 }
 
 }  // namespace cams

@@ -258,19 +258,22 @@ __device__ __forceinline__ void lu_diag_body(double *__restrict__ A, int n, int 
     __shared__ double D[kNB][kNB + 1];
     for (int t = threadIdx.x; t < nb * nb; t += kBlock) D[t / nb][t % nb] = A[(size_t)(j0 + t / nb) * n + j0 + t % nb];
     __syncthreads();
+    // the trailing update of column c: thread (ty, tx) of a 16 x 16 grid takes
+    // rows c+1+ty+16u and columns c+1+tx+16v (no index division)
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     for (int c = 0; c < nb; ++c) {
         double pv = D[c][c];
         if (!(pv > 0.0)) {
             if (threadIdx.x == 0) atomicOr(status, F_SINGULAR_COARSE);
             pv = 1.0;
         }
+        const double rp = 1.0 / pv;
         __syncthreads();
-        for (int i = c + 1 + threadIdx.x; i < nb; i += kBlock) D[i][c] /= pv;
+        for (int i = c + 1 + threadIdx.x; i < nb; i += kBlock) D[i][c] *= rp;
         __syncthreads();
-        const int w = nb - c - 1;
-        for (int t = threadIdx.x; t < w * w; t += kBlock) {
-            const int i = c + 1 + t / w, j = c + 1 + t % w;
-            D[i][j] -= D[i][c] * D[c][j];
+        for (int i = c + 1 + ty; i < nb; i += 16) {
+            const double l = D[i][c];
+            for (int j = c + 1 + tx; j < nb; j += 16) D[i][j] -= l * D[c][j];
         }
         __syncthreads();
     }
@@ -281,6 +284,89 @@ __global__ __launch_bounds__(kBlock) void k_lu_diag_nopiv(double *__restrict__ A
                                                            int32_t *status)
 {
     lu_diag_body(A, n, j0, nb, status);
+}
+
+// Unpivoted LU of the diagonal block at (j0, j0) together with the inverses
+// of its two triangles (unit lower L, upper U; both padded with identity
+// beyond nb), in one workgroup.  Wave 0 factorises with one row per lane in
+// registers: at step c, lane c's row is final and is broadcast with
+// readlane, and every lower lane eliminates with it (no workgroup barrier
+// inside the 64 steps).  Then wave 0 inverts L and wave 1 inverts U, one
+// column per lane, reading the factor from LDS (all lanes read the same
+// element: broadcast).  Linv and Uinv are 64 x 64, leading dimension 64.
+__device__ __forceinline__ double bcast(double v, int lane)
+{
+    const unsigned long long u = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void lu_diag_inv_body(double *__restrict__ A, int n, int j0, int nb, int32_t *status,
+                                                 double *__restrict__ Linv, double *__restrict__ Uinv)
+{
+    __shared__ double D[kNB][kNB + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        double r[kNB];
+#pragma unroll
+        for (int j = 0; j < kNB; ++j)
+            r[j] = (lane < nb && j < nb) ? A[(size_t)(j0 + lane) * n + j0 + j] : (lane == j ? 1.0 : 0.0);
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) {
+            double pv = bcast(r[c], c);
+            if (!(pv > 0.0)) {
+                bad = true;
+                pv = 1.0;
+            }
+            const double rp = 1.0 / pv;
+            const double l = r[c] * rp;
+            if (lane > c) r[c] = l;
+#pragma unroll
+            for (int j = c + 1; j < kNB; ++j) {
+                const double u = bcast(r[j], c);
+                if (lane > c) r[j] -= l * u;
+            }
+        }
+        if (bad && lane == 0) atomicOr(status, F_SINGULAR_COARSE);
+#pragma unroll
+        for (int j = 0; j < kNB; ++j) D[lane][j] = r[j];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nb * nb; t += kBlock) A[(size_t)(j0 + t / nb) * n + j0 + t % nb] = D[t / nb][t % nb];
+    if (wave == 0) {
+        // column `lane` of L^-1: x_r = -sum_{k<r} L[r][k] x_k, x_lane = 1
+        double x[kNB];
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) {
+            double v = r == lane ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < r; ++k) v -= D[r][k] * x[k];
+            x[r] = r < lane ? 0.0 : v;
+        }
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) Linv[r * kNB + lane] = x[r];
+    } else if (wave == 1) {
+        // column `lane` of U^-1: x_r = (e_r - sum_{k>r} U[r][k] x_k) / U[r][r]
+        double x[kNB];
+#pragma unroll
+        for (int r = kNB - 1; r >= 0; --r) {
+            double v = r == lane ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = r + 1; k < kNB; ++k) v -= D[r][k] * x[k];
+            x[r] = r > lane ? 0.0 : v / D[r][r];
+        }
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) Uinv[r * kNB + lane] = x[r];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_lu_diag_inv(double *__restrict__ A, int n, int j0, int nb,
+                                                         int32_t *status, double *__restrict__ Linv,
+                                                         double *__restrict__ Uinv)
+{
+    lu_diag_inv_body(A, n, j0, nb, status, Linv, Uinv);
 }
 
 // Apply the panel's interchanges to the columns outside [j0, j0+nb).
@@ -422,16 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm(double *C, int ldc, const doubl
 __global__ __launch_bounds__(kBlock) void kb_lu_diag(const LuStep *__restrict__ st)
 {
     const LuStep s = st[blockIdx.x];
-    lu_diag_body(s.F, s.n, s.j0, s.nb, s.status);
-}
-
-// Workgroup 2 i: L^-1 of descriptor i's diagonal block, 2 i + 1: U^-1.
-__global__ __launch_bounds__(kBlock) void kb_tri_inv(const LuStep *__restrict__ st)
-{
-    const LuStep s = st[blockIdx.x >> 1];
-    const int upper = blockIdx.x & 1;
-    double *out = upper ? s.Uinv : s.Linv;
-    trsm_body(s.F, s.n, s.j0, s.nb, out - (size_t)s.j0 * kNB, kNB, 0, kNB, upper, 0);
+    lu_diag_inv_body(s.F, s.n, s.j0, s.nb, s.status, s.Linv, s.Uinv);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_gemm(const GemmDesc *__restrict__ d, int nd)
@@ -683,7 +760,6 @@ void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan)
             steps.push_back({c->a.work, n, j0, nb, c->a.status, Linv, Linv + kNB * kNB});
         }
         plan.launches.push_back({BatchLuPlan::DIAG, plan.steps.size(), (int)steps.size(), 0});
-        plan.launches.push_back({BatchLuPlan::TRI, plan.steps.size(), (int)steps.size(), 0});
         plan.steps.insert(plan.steps.end(), steps.begin(), steps.end());
         for (const cams_ctx *c : fe) {   // L21 = A21 U^-1 and U12 = L^-1 A12 (independent)
             const int n = c->g.Nc, j0 = b * kNB;
@@ -713,7 +789,7 @@ void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan)
             if (j0 >= n) continue;
             const int nb = std::min(kNB, n - j0);
             double *Xb = c->a.Ainv + (size_t)j0 * n;
-            add_gemm(v, Xb, n, c->a.tri + (size_t)(2 * b) * kNB * kNB, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
+            add_gemm(v, Xb, n, c->a.tri + (size_t)(2 * b) * kNB * kNB, kNB, Xb, n, nb, j0 + nb, nb, 1.0, 0.0);
         }
         flush_gemms(v);
         for (const cams_ctx *c : fe) {
@@ -722,7 +798,7 @@ void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan)
             const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
             double *X = c->a.Ainv, *F = c->a.work;
             add_gemm(v, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, X + (size_t)j0 * n, n,
-                     rest, n, nb, -1.0, 1.0);
+                     rest, j0 + nb, nb, -1.0, 1.0);
         }
         flush_gemms(v);
     }
@@ -752,8 +828,6 @@ void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDes
         if (L.count <= 0) continue;
         if (L.kind == BatchLuPlan::DIAG)
             kb_lu_diag<<<L.count, kBlock, 0, st>>>(steps + L.off);
-        else if (L.kind == BatchLuPlan::TRI)
-            kb_tri_inv<<<2 * L.count, kBlock, 0, st>>>(steps + L.off);
         else
             kb_gemm<<<L.tiles, kBlock, 0, st>>>(gemms + L.off, L.count);
     }
@@ -776,9 +850,7 @@ static void inverse_nopiv(cams_ctx *c, double *F, double *X, int n)
         const int nb = n - j0 < kNB ? n - j0 : kNB;
         const int rest = n - j0 - nb;
         double *Linv = tri + (size_t)(2 * b) * kNB * kNB, *Uinv = Linv + kNB * kNB;
-        k_lu_diag_nopiv<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.status);
-        k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Linv - (size_t)j0 * kNB, kNB, 0, kNB, 0);
-        k_trsm<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, Uinv - (size_t)j0 * kNB, kNB, 0, kNB, 1);
+        k_lu_diag_inv<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.status, Linv, Uinv);
         if (rest > 0) {
             double *A21 = F + (size_t)(j0 + nb) * n + j0, *A12 = F + (size_t)j0 * n + j0 + nb;
             gemm(c, A21, n, A21, n, Uinv, kNB, rest, nb, nb, 1.0, 0.0);
@@ -789,15 +861,17 @@ static void inverse_nopiv(cams_ctx *c, double *F, double *X, int n)
     // X = U^-1 L^-1 by block substitutions (all MFMA products)
     k_identity_piv<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n);
     k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, X);
+    // (X = L^-1 is lower triangular: at panel b only its first j0 + nb
+    // columns are nonzero, so the products stop there)
     for (int b = 0; b < npan; ++b) {
         const int j0 = b * kNB;
         const int nb = n - j0 < kNB ? n - j0 : kNB;
         const int rest = n - j0 - nb;
         const double *Linv = tri + (size_t)(2 * b) * kNB * kNB;
         double *Xb = X + (size_t)j0 * n;
-        gemm(c, Xb, n, Linv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
-        if (rest > 0) gemm_sub(c, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, Xb, n, rest, n,
-                               nb);
+        gemm(c, Xb, n, Linv, kNB, Xb, n, nb, j0 + nb, nb, 1.0, 0.0);
+        if (rest > 0) gemm_sub(c, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, Xb, n, rest,
+                               j0 + nb, nb);
     }
     for (int b = npan - 1; b >= 0; --b) {
         const int j0 = b * kNB;

@@ -85,7 +85,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double
     __shared__ double sh[kBlock / 64];
     if (ictl[C_DONE]) return;
     v.fold = ictl[C_IT] > 0;
-    residual_body(g, W, diag, r0, v, dp_out, r, rf, partial, blockIdx.x, sh);
+    // XCD-aware order: the rows above and below a workgroup's rows are read
+    // by workgroups of the same XCD, so their lines are found in its L2
+    residual_body(g, W, diag, r0, v, dp_out, r, rf, partial, xcd_swizzle(blockIdx.x, gridDim.x), sh);
 }
 
 // ||r||^2 from the residual kernel's partials and the stopping test, by one

@@ -26,16 +26,6 @@ namespace {
 constexpr int SB = 8;                 // block extent per active axis
 constexpr int ST = SB * SB * SB;      // one thread per cell
 
-// Bijection from the dispatch id to a logical block id such that each of the
-// 8 XCDs (which receive dispatch ids round-robin) works on one contiguous
-// range of logical blocks.
-__device__ __forceinline__ int xcd_swizzle(int wg, int n)
-{
-    const int q = n / 8, rem = n % 8;
-    const int xcd = wg % 8, slot = wg / 8;
-    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
-}
-
 struct BlockCell {
     int n;          // global cell index
     int t;          // local slot li + 8 lj + 64 lk

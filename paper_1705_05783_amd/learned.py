@@ -74,12 +74,22 @@ class Trainer:
         return self.loss
 
 
-def forward(params, feat, ws=None):
+def forward(params, feat, ws=None, bf16=False):
+    """phi (B, 8, 729) of the network; bf16=True: the matrix-core inference
+    path the basis construction uses."""
     b = feat.shape[0]
-    if ws is None:
-        ws = torch.empty(int(C.cams_cnn_workspace_bytes(b)) // 4 + 64, dtype=torch.float32, device=feat.device)
+    feat = feat.contiguous()
     phi = torch.empty((b, 8, 729), dtype=torch.float32, device=feat.device)
     stream = torch.cuda.current_stream(feat.device).cuda_stream
+    if bf16:
+        if ws is None:
+            ws = torch.empty(int(C.cams_cnn_bf16_workspace_bytes()) // 4 + 64, dtype=torch.float32,
+                             device=feat.device)
+        C.check(C.cams_cnn_forward_bf16(ctypes.c_void_p(stream), _p(params), _p(feat), b, _p(ws), _p(phi)), None,
+                "cams_cnn_forward_bf16")
+        return phi
+    if ws is None:
+        ws = torch.empty(int(C.cams_cnn_workspace_bytes(b)) // 4 + 64, dtype=torch.float32, device=feat.device)
     C.check(C.cams_cnn_forward(ctypes.c_void_p(stream), _p(params), _p(feat), b, _p(ws), _p(phi)), None,
             "cams_cnn_forward")
     return phi

@@ -42,6 +42,24 @@ def test_forward_matches_oracle(torch):
     assert rel_err(phi, phi_ref) <= 2e-5
 
 
+def test_forward_bf16_matches_oracle(torch):
+    """Matrix-core inference (BF16 weights and activations, FP32 accumulation)
+    against the FP64 oracle: bfloat16 keeps 8 significant bits, so the basis
+    values (in [0, 1]) agree to 0.03 in the worst cell and 3e-3 on average."""
+    from paper_1705_05783_amd import learned
+    rng = np.random.default_rng(10)
+    params = _rand_params(11)
+    feat = rng.normal(size=(5, 3, 9, 9, 9))
+    phi_ref, _ = ocnn.forward(params, feat)
+    pt = torch.tensor(params, dtype=torch.float32, device="cuda")
+    ft = torch.tensor(feat.reshape(5, 3, 729), dtype=torch.float32, device="cuda")
+    phi = to_np(learned.forward(pt, ft, bf16=True)).reshape(5, 8, 9, 9, 9)
+    d = np.abs(phi - phi_ref)
+    log("bf16 inference: max", d.max(), "mean", d.mean())
+    assert d.max() <= 0.03 and d.mean() <= 3e-3
+    assert np.allclose(phi.sum(axis=1), 1.0, atol=1e-5)
+
+
 def test_loss_gradient_matches_oracle(torch):
     from paper_1705_05783_amd import learned
     rng = np.random.default_rng(2)
@@ -145,7 +163,7 @@ def test_learned_build_fallback_and_prediction(torch):
     P = to_np(s2.export(4)).reshape(8, -1)
     assert np.max(np.abs(P.sum(axis=0) - 1.0)) <= 1e-5
     feat, _ = s2.cnn_patches(with_targets=False)
-    phi = to_np(learned.forward(params, feat)).reshape(-1, 8, 9, 9, 9)
+    phi = to_np(learned.forward(params, feat, bf16=True)).reshape(-1, 8, 9, 9, 9)
     # every predicted interior appears in the basis
     Pg = P.reshape(8, pb.nz, pb.ny, pb.nx)
     v = [list(oracle.vertex_coords(n, 8)) for n in (pb.nx, pb.ny, pb.nz)]
