@@ -438,15 +438,20 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // C may alias A when Nn <= 64 (each workgroup then owns whole rows of C and
 // reads its rows of A before writing), or B when M <= 64 (whole columns).
 // 256 threads = 4 waves as 2 x 2; each wave owns a 32 x 32 block of the
-// 64 x 64 tile as 2 x 2 tiles of v_mfma_f64_16x16x4f64.  K is staged through
-// LDS 16 at a time.  Operand lanes: A row = lane%16, k = lane/16; B col =
+// 64 x 64 tile as 2 x 2 tiles of v_mfma_f64_16x16x4f64.  Operand lanes: A row = lane%16, k = lane/16; B col =
 // lane%16, k = lane/16; result element v of a lane: row lane/16 + 4v,
 // col lane%16 (checked against a host GEMM by the parity tests).
+// K is staged through LDS KS = 32 columns at a time; the next stage's
+// operands are loaded into registers while the matrix cores work on the
+// current one (one LDS buffer, one register buffer).
+constexpr int KS = 32;
+
 __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, int lda, const double *B, int ldb,
                                           int M, int Nn, int K, double alpha, double beta, int tm, int tn)
 {
-    __shared__ double As[64][17];
-    __shared__ double Bs[16][65];
+    __shared__ double As[64][KS + 1];
+    __shared__ double Bs[KS][64 + 1];
+    constexpr int PER = 64 * KS / kBlock;   // operand elements per thread and stage (8)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     v4d acc[2][2];
@@ -454,20 +459,31 @@ __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, i
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        for (int t = threadIdx.x; t < 64 * 16; t += kBlock) {
-            const int r = t / 16, c = t % 16;
-            const int gr = tm + r, gc = k0 + c;
-            As[r][c] = (gr < M && gc < K) ? A[(size_t)gr * lda + gc] : 0.0;
+    double ra[PER], rb[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int t = threadIdx.x + kBlock * i;
+            const int ar = t / KS, ac = t % KS;          // A: 64 rows x KS
+            const int gr = tm + ar, gc = k0 + ac;
+            ra[i] = (gr < M && gc < K) ? A[(size_t)gr * lda + gc] : 0.0;
+            const int br = t / 64, bc = t % 64;          // B: KS rows x 64
+            const int hr = k0 + br, hc = tn + bc;
+            rb[i] = (hr < K && hc < Nn) ? B[(size_t)hr * ldb + hc] : 0.0;
         }
-        for (int t = threadIdx.x; t < 16 * 64; t += kBlock) {
-            const int r = t / 64, c = t % 64;
-            const int gr = k0 + r, gc = tn + c;
-            Bs[r][c] = (gr < K && gc < Nn) ? B[(size_t)gr * ldb + gc] : 0.0;
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += KS) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int t = threadIdx.x + kBlock * i;
+            As[t / KS][t % KS] = ra[i];
+            Bs[t / 64][t % 64] = rb[i];
         }
         __syncthreads();
+        if (k0 + KS < K) fetch(k0 + KS);
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
+        for (int kk = 0; kk < KS; kk += 4) {
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const double av = As[wm + a * 16 + (lane & 15)][kk + (lane >> 4)];
