@@ -103,6 +103,21 @@ constexpr int PAD = SB * SB;
 // wave-level ordering inside the sweeps); then all threads write the block
 // back.  Fewer threads per block let a compute unit keep more blocks, and so
 // more of the latency-bound sweeps, in flight; the batched solve tunes NT.
+//
+// Two sweep forms, equal bit for bit:
+//  SW = 0  the running values live in LDS: every level reads its
+//          neighbours' results of the previous level back from LDS (little
+//          register use, so many blocks per compute unit: grids with many
+//          more blocks than compute units);
+//  SW = 1  the running values live in registers: each lane loads the
+//          coefficients of all levels of its pencil before the sweep (the
+//          loads do not depend on the recurrence, so all are in flight
+//          together) and takes the previous level's values of its -y/+y and
+//          -z/+z neighbour pencils (lanes -/+1 and -/+8) by ds_bpermute; a
+//          level is then two lane exchanges and four arithmetic operations
+//          on the critical path instead of an LDS write and read.  It needs
+//          about 230 registers per lane, so it pays when every block of the
+//          grid is resident at once (one block per compute unit).
 // e_old and e_new must be different arrays: neighbouring blocks read e_old
 // across block faces.  T: arithmetic and storage of the smoother (double, or
 // float in the mixed precision solve); TR: type of the right-hand side.
@@ -124,7 +139,90 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class T, class TR, int NT>
+// Value of v in lane `src` of the wave.
+template <class T>
+__device__ __forceinline__ T lane_value(T v, int src)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_ds_bpermute(4 * src, __float_as_int(v)));
+    } else {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(4 * src, (int)(unsigned)b);
+        const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(4 * src, (int)(unsigned)(b >> 32));
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+}
+
+// Forward and backward sweeps of the staged block by the first wave with the
+// running values in registers (SW = 1 above).  Lane (pj, pk) = (lane % 8,
+// lane / 8) owns the x-pencil; at level tau it handles li = tau - pj - pk.
+// Coefficients are loaded in batches of CH levels (all 22 in FP32, 11 in
+// FP64 to bound the register count); inactive lanes keep their running value
+// and store into the upper zero pad, which nothing reads here.
+template <class T>
+__device__ __forceinline__ void sweep_registers(SmoothLds<T> &L, int ex, int ey, int ez)
+{
+    constexpr int NL = 3 * SB - 2;
+    constexpr int CH = sizeof(T) == 4 ? NL : NL / 2;
+    const int lane = threadIdx.x;
+    const int pj = lane & (SB - 1), pk = lane >> 3;
+    const bool pencil = pj < ey && pk < ez;
+    const int base = PAD + SB * pj + SB * SB * pk, s0 = pj + pk;
+    const int junk = PAD + ST + lane;
+    const int ym = lane > 0 ? lane - 1 : 0, zm = lane >= SB ? lane - SB : 0;
+    const int yp = lane < 63 ? lane + 1 : 63, zp = lane < 64 - SB ? lane + SB : 63;
+    T yv[NL];
+    T run = 0;
+#pragma unroll
+    for (int c0 = 0; c0 < NL; c0 += CH) {
+        T z[CH], cx[CH], cy[CH], cz[CH], di[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int t = base + min(max(c0 + q - s0, 0), SB - 1);
+            z[q] = L.y[t];
+            cx[q] = L.wx[t - 1];
+            cy[q] = L.wy[t - SB];
+            cz[q] = L.wz[t - SB * SB];
+            di[q] = L.dinv[t - PAD];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the batch of loads ahead of the recurrence
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int a = c0 + q - s0;
+            const bool act = pencil && a >= 0 && a < ex;
+            const T s = z[q] + cx[q] * run + cy[q] * lane_value(run, ym) + cz[q] * lane_value(run, zm);
+            const T v = s * di[q];
+            run = act ? v : run;
+            yv[c0 + q] = v;
+        }
+    }
+    run = 0;
+#pragma unroll
+    for (int c0 = NL - CH; c0 >= 0; c0 -= CH) {
+        T cx[CH], cy[CH], cz[CH], di[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int t = base + min(max(c0 + q - s0, 0), SB - 1);
+            cx[q] = L.wx[t];
+            cy[q] = L.wy[t];
+            cz[q] = L.wz[t];
+            di[q] = L.dinv[t - PAD];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = CH - 1; q >= 0; --q) {
+            const int a = c0 + q - s0;
+            const bool act = pencil && a >= 0 && a < ex;
+            const int t = base + min(max(a, 0), SB - 1);
+            const T s = cx[q] * run + cy[q] * lane_value(run, yp) + cz[q] * lane_value(run, zp);
+            const T v = yv[c0 + q] + s * di[q];
+            run = act ? v : run;
+            L.y[act ? t : junk] = v;
+        }
+    }
+}
+
+template <class T, class TR, int NT, int SW = 0>
 __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
                                                const T *__restrict__ invd, const TR *__restrict__ rhs,
                                                const T *__restrict__ eold, T *__restrict__ enew, int blk,
@@ -180,7 +278,9 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         L.wz[PAD + t] = fz;
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
+    if (SW == 1 && threadIdx.x < 64) {
+        sweep_registers<T>(L, ex, ey, ez);
+    } else if (SW == 0 && threadIdx.x < 64) {
         // lane owns the x-pencil (pj, pk) = (lane % 8, lane / 8); at time step
         // tau it handles the cell li = tau - pj - pk of hyperplane tau
         T *y = L.y, *wx = L.wx, *wy = L.wy, *wz = L.wz, *dinv = L.dinv;
@@ -215,10 +315,13 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
     }
 }
 
-// Threads per block of the single-problem smoother.
+// Single-problem smoother: register sweeps with one 512-thread workgroup per
+// block when all blocks are resident at once, else LDS sweeps with 256
+// threads per block (several blocks per compute unit).
 constexpr int kSmoothThreads = ST;
+constexpr int kSmoothThreadsMany = 256;
 
-template <class T, class TR, int NT>
+template <class T, class TR, int NT, int SW>
 __global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
                                                    const T *__restrict__ invd, const TR *__restrict__ rhs,
                                                    const T *__restrict__ eold, T *__restrict__ enew,
@@ -226,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict
 {
     __shared__ SmoothLds<T> lds;
     if (done && *done) return;
-    bilu_step_body<T, TR, NT>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds);
+    bilu_step_body<T, TR, NT, SW>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds);
 }
 
 // Batched step `s` of `steps` for every instance.  `post` selects the
@@ -298,10 +401,15 @@ void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR
     // overhead per launch small
     const bool timed = c->prof_kernel == CAMS_PROF_SMOOTH_STEP && c->prof_iter % kProfEvery == 0 && steps > 0;
     if (timed) prof_begin(c, bytes, steps);
+    const bool in_regs = nb <= resident_workgroups((const void *)k_bilu_step<T, TR, kSmoothThreads, 1>, kSmoothThreads);
     for (int s = 0; s < steps; ++s) {
         T *out = buf[(steps - 1 - s) & 1];
-        k_bilu_step<T, TR, kSmoothThreads><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, invd, rhs, prev,
-                                                                                 out, done);
+        if (in_regs)
+            k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, invd, rhs,
+                                                                                        prev, out, done);
+        else
+            k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(
+                c->g, W, diag, invd, rhs, prev, out, done);
         prev = out;
     }
     if (timed) prof_end(c);

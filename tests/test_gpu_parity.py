@@ -127,8 +127,11 @@ def test_matrix_core_gemm(_gpu, M, N, K):
 
 
 @pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK])
-@pytest.mark.parametrize("shape,r", SHAPES[:5] + [((37, 29, 19), 4)])
+@pytest.mark.parametrize("shape,r", SHAPES[:5] + [((37, 29, 19), 4), ((75, 70, 45), 8)])
 def test_smoother_apply(_gpu, shape, r, smoother):
+    """One smoother application against the oracle's.  The small grids have
+    fewer 8^3 blocks than the device has compute units (register sweeps); the
+    75x70x45 grid (540 blocks, ragged on every axis) takes the LDS sweeps."""
     torch = _gpu
     pb = _pb(shape, r, sigma=2.0, seed=6)
     pb.smoother = smoother
