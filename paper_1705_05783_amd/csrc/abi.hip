@@ -716,17 +716,23 @@ static void enqueue_iteration(cams_ctx *c, int it)
     // prolongated coarse correction) instead of on A d2 = r - A d1 from zero:
     // the same iterates, e = d1 + d2, without forming r1.  The correction
     // folded into the next residual is then d0 + e.
+    // Without pre-smoothing the restriction acts on the new residual and is
+    // computed by the residual kernel itself (partials per owner box).
+    const int flat_parts = (c->g.N + kBlock - 1) / kBlock;
     if (O.precision != CAMS_FP64) {
         // FP64 residual and update; FP32 corrections (iterative refinement)
         const float *pend0 = O.n_pre > 0 ? a.d0f : nullptr;
         const float *pend1 = O.n_post > 0 ? a.d2f : a.d1f;
-        launch_residual_ctl32(c, a.dp[it & 1], pend0, pend1, nullptr, a.dp[(it + 1) & 1], a.r1f);
-        launch_finalize_ctl(c);
         if (O.n_pre > 0) {
+            launch_residual_ctl32(c, a.dp[it & 1], pend0, pend1, nullptr, a.dp[(it + 1) & 1], a.r1f);
+            launch_finalize_ctl(c, flat_parts);
             launch_bilu_smooth32(c, (const double *)a.r, a.d0f, O.n_pre, done);
             launch_sub64_lo(c, a.d0f, a.r, done);
+            launch_restrict(c, a.r);
+        } else {
+            launch_residual_restrict32(c, a.dp[it & 1], pend0, pend1, nullptr, a.dp[(it + 1) & 1], a.r1f);
+            launch_finalize_ctl(c, c->g.Nc);
         }
-        launch_restrict(c, a.r);
         launch_gemv(c, a.rc, a.xc, done);
         launch_prolong32(c, a.xc, a.d1f, done);
         if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done, a.d1f);
@@ -736,13 +742,16 @@ static void enqueue_iteration(cams_ctx *c, int it)
     const double *pend0 = O.n_pre > 0 ? a.d0 : nullptr;
     const double *pend1 = O.n_post > 0 && block ? a.d2 : a.d1;
     const double *pend2 = O.n_post > 0 && !block ? a.d2 : nullptr;
-    launch_residual_ctl(c, a.dp[it & 1], pend0, pend1, pend2, a.dp[(it + 1) & 1]);
-    launch_finalize_ctl(c);
     if (O.n_pre > 0) {
+        launch_residual_ctl(c, a.dp[it & 1], pend0, pend1, pend2, a.dp[(it + 1) & 1]);
+        launch_finalize_ctl(c, flat_parts);
         launch_smooth(c, a.r, a.d0, O.n_pre, done);
         launch_stencil_sub(c, a.r, a.d0, a.r, done);
+        launch_restrict(c, a.r);
+    } else {
+        launch_residual_restrict(c, a.dp[it & 1], pend0, pend1, pend2, a.dp[(it + 1) & 1]);
+        launch_finalize_ctl(c, c->g.Nc);
     }
-    launch_restrict(c, a.r);
     launch_gemv(c, a.rc, a.xc, done);                  // Eq. (15): coarse solve
     launch_prolong(c, a.xc, a.d1, done);               // Eq. (12)
     if (O.n_post > 0) {

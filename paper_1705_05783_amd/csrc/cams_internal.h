@@ -82,7 +82,7 @@ struct InstDev {
     int fe;           // MSFE restriction
     int bf16;         // mixed precision with a bfloat16 basis
     int n_pre, n_post;
-    int nparts;       // residual partials, ceil(N / kBlock)
+    int nparts;       // residual partials: Nc (fused residual-restriction) or ceil(N / kBlock)
     int maxit;
     double rtol2;
 };
@@ -237,7 +237,12 @@ void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, con
                          double *dp_out);
 void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
                            double *dp_out, float *rf);   // also rf = (float) r
-void launch_finalize_ctl(cams_ctx *c);   // ||r||, stopping test, iteration counter
+// residual and restriction slots in one pass (no pre-smoothing); partial[k] per owner box
+void launch_residual_restrict(cams_ctx *c, const double *dp_in, const double *a0, const double *a1,
+                              const double *a2, double *dp_out);
+void launch_residual_restrict32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
+                                double *dp_out, float *rf);
+void launch_finalize_ctl(cams_ctx *c, int nparts);   // ||r|| from nparts partials, stopping test, counter
 void launch_restrict(cams_ctx *c, const double *r);   // slot partials of R r (stage 1)
 
 // ---- setup phases without host synchronisation (abi.hip)
@@ -251,6 +256,7 @@ void enqueue_coarse(cams_ctx *c);
 void launch_batch_residual(const BatchLaunch &L, int par, bool mixed);
 void launch_batch_finalize(const InstDev *inst, int count, hipStream_t st);
 void launch_batch_restrict(const BatchLaunch &L, int precision);
+void launch_batch_residual_restrict(const BatchLaunch &L, int par, bool mixed, int precision);
 void launch_batch_gather(const InstDev *inst, int count, BatchResult *out, hipStream_t st);
 void launch_batch_reset(const BatchLaunch &L);   // iteration state of every instance to its start
 void launch_batch_node_sum(const BatchLaunch &L);

@@ -23,31 +23,76 @@ __global__ __launch_bounds__(kBlock) void k_iter_reset(int32_t *__restrict__ ict
     if (t < nctl) ictl[t] = 0;
 }
 
-// v0 + (v1 + v2 + v3 once `fold` is set); the pending corrections are FP64
-// or, in the mixed-precision solve, FP32.
-template <class TA>
+// v0 + (v[0] + ... + v[NV-1] once `fold` is set), added in that order; the
+// pending corrections are FP64 or, in the mixed-precision solve, FP32.  The
+// NV pointers are valid whether or not `fold` is set, so all NV + 1 loads
+// are issued together and none waits on a branch.
+template <class TA, int NV>
 struct Pending {
     const double *v0;
-    const TA *v1, *v2, *v3;
+    const TA *v[3];
     bool fold;
     __device__ __forceinline__ double operator()(int m) const
     {
         double s = v0[m];
-        if (fold) {
-            if (v1) s += (double)v1[m];
-            if (v2) s += (double)v2[m];
-            if (v3) s += (double)v3[m];
-        }
+        TA a[NV > 0 ? NV : 1];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) a[q] = v[q][m];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) s = fold ? s + (double)a[q] : s;
         return s;
     }
 };
 
+// The non-null pointers of (a0, a1, a2) in order; returns their count.
+template <class TA>
+int compact_pending(const TA *a0, const TA *a1, const TA *a2, const TA *out[3])
+{
+    int nv = 0;
+    for (const TA *p : {a0, a1, a2})
+        if (p) out[nv++] = p;
+    for (int q = nv; q < 3; ++q) out[q] = nv ? out[0] : nullptr;
+    return nv;
+}
+
+// r = r0 - A v at cell n = (i, j, k); writes r (and its FP32 copy rf when
+// given) and dp_out = v there, and returns r_n.  A neighbour outside the
+// grid is replaced by the cell itself with coupling 0 (s - 0 * v = s), so
+// every load is issued at once, without branches.
+template <class TA, int NV>
+__device__ __forceinline__ double residual_cell(const GridDev &g, const double *__restrict__ W,
+                                                const double *__restrict__ diag, const double *__restrict__ r0,
+                                                const Pending<TA, NV> &v, double *__restrict__ dp_out,
+                                                double *__restrict__ r, float *__restrict__ rf, int n, int i, int j,
+                                                int k)
+{
+    const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    const bool xm = i > 0, xp = i + 1 < g.nx, ym = j > 0, yp = j + 1 < g.ny, zm = k > 0, zp = k + 1 < g.nz;
+    const int nxm = xm ? n - 1 : n, nxp = xp ? n + 1 : n;
+    const int nym = ym ? n - g.nx : n, nyp = yp ? n + g.nx : n;
+    const int nzm = zm ? n - g.sxy : n, nzp = zp ? n + g.sxy : n;
+    const double wxm = Wx[nxm], wxp = Wx[n], wym = Wy[nym], wyp = Wy[n], wzm = Wz[nzm], wzp = Wz[n];
+    const double vn = v(n);
+    double s = diag[n] * vn;
+    s -= (xm ? wxm : 0.0) * v(nxm);
+    s -= (xp ? wxp : 0.0) * v(nxp);
+    s -= (ym ? wym : 0.0) * v(nym);
+    s -= (yp ? wyp : 0.0) * v(nyp);
+    s -= (zm ? wzm : 0.0) * v(nzm);
+    s -= (zp ? wzp : 0.0) * v(nzp);
+    const double rr = r0[n] - s;
+    r[n] = rr;
+    if (rf) rf[n] = (float)rr;
+    dp_out[n] = vn;
+    return rr;
+}
+
 // r = r0 - A v over the cells of workgroup `blk` (and its FP32 copy rf when
 // given), dp_out = v, and the workgroup's partial of ||r||^2.
-template <class TA>
+template <class TA, int NV>
 __device__ __forceinline__ void residual_body(const GridDev &g, const double *__restrict__ W,
                                               const double *__restrict__ diag, const double *__restrict__ r0,
-                                              const Pending<TA> &v, double *__restrict__ dp_out,
+                                              const Pending<TA, NV> &v, double *__restrict__ dp_out,
                                               double *__restrict__ r, float *__restrict__ rf,
                                               double *__restrict__ partial, int blk, double *sh)
 {
@@ -55,29 +100,17 @@ __device__ __forceinline__ void residual_body(const GridDev &g, const double *__
     double e2 = 0.0;
     if (n < g.N) {
         const Cell c = cell_of(g, n);
-        const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
-        const double vn = v(n);
-        double s = diag[n] * vn;
-        if (c.i > 0) s -= Wx[n - 1] * v(n - 1);
-        if (c.i + 1 < g.nx) s -= Wx[n] * v(n + 1);
-        if (c.j > 0) s -= Wy[n - g.nx] * v(n - g.nx);
-        if (c.j + 1 < g.ny) s -= Wy[n] * v(n + g.nx);
-        if (c.k > 0) s -= Wz[n - g.sxy] * v(n - g.sxy);
-        if (c.k + 1 < g.nz) s -= Wz[n] * v(n + g.sxy);
-        const double rr = r0[n] - s;
-        r[n] = rr;
-        if (rf) rf[n] = (float)rr;
-        dp_out[n] = vn;
+        const double rr = residual_cell(g, W, diag, r0, v, dp_out, r, rf, n, c.i, c.j, c.k);
         e2 = rr * rr;
     }
     const double bs = block_sum<kBlock>(e2, sh);
     if (threadIdx.x == 0) partial[blk] = bs;
 }
 
-template <class TA>
+template <class TA, int NV>
 __global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double *__restrict__ W,
                                                           const double *__restrict__ diag,
-                                                          const double *__restrict__ r0, Pending<TA> v,
+                                                          const double *__restrict__ r0, Pending<TA, NV> v,
                                                           double *__restrict__ dp_out, double *__restrict__ r,
                                                           float *__restrict__ rf, double *__restrict__ partial,
                                                           const int32_t *ictl)
@@ -167,10 +200,10 @@ __device__ __forceinline__ void restrict_box(const GridDev &g, const uint8_t *__
         const int n = x + g.nx * (y + g.ny * z);
         const double rn = r[n];
         if (fe) {
-            if (!dm[n]) {
+            // the basis loads do not wait for the mask: masked cells add 0
+            const double wn = dm[n] ? 0.0 : rn;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) acc[q] += basis_value(P, (size_t)q * g.N + n) * rn;
-            }
+            for (int q = 0; q < 8; ++q) acc[q] += basis_value(P, (size_t)q * g.N + n) * wn;
         } else {
             acc[0] += rn;
         }
@@ -200,28 +233,112 @@ __global__ __launch_bounds__(kBlock) void k_restrict(GridDev g, const uint8_t *_
     restrict_box<TP>(g, dm, P, fe, r, slots, blockIdx.x, sh);
 }
 
+// Residual and restriction in one pass, for iterations without
+// pre-smoothing (the restriction then acts on the new residual itself): one
+// workgroup per owner box k computes, over the box's cells in the order of
+// restrict_box, r = r0 - A v as residual_body does, the box's partial of
+// ||r||^2 (partial[k]) and its 8 restriction slots from the values just
+// computed, so r is not read back and the restriction needs no launch of its
+// own.  The slots equal restrict_box's (a masked cell adds P * 0 = +-0).
+template <class TA, int NV, class TP, int NT>
+__device__ __forceinline__ void residual_restrict_box(const GridDev &g, const double *__restrict__ W,
+                                                      const double *__restrict__ diag,
+                                                      const double *__restrict__ r0, const Pending<TA, NV> &v,
+                                                      double *__restrict__ dp_out, double *__restrict__ r,
+                                                      float *__restrict__ rf, double *__restrict__ partial,
+                                                      const uint8_t *__restrict__ dm, const TP *__restrict__ P,
+                                                      int fe, double *__restrict__ slots, int k, double *sh)
+{
+    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
+    const int x0 = g.ob[0][ka], y0 = g.ob[1][kb], z0 = g.ob[2][kc];
+    const int ex = g.ob[0][ka + 1] - x0, ey = g.ob[1][kb + 1] - y0, ez = g.ob[2][kc + 1] - z0;
+    const int m = ex * ey * ez;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double e2 = 0.0;
+    for (int t = threadIdx.x; t < m; t += NT) {
+        const int x = x0 + t % ex, y = y0 + (t / ex) % ey, z = z0 + t / (ex * ey);
+        const int n = x + g.nx * (y + g.ny * z);
+        // issued with the residual's loads, outside any branch, so that no
+        // load waits for another (MSFV reads the basis without using it)
+        TP pv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[q] = P[(size_t)q * g.N + n];
+        const bool keep = !dm[n];
+        const double rn = residual_cell(g, W, diag, r0, v, dp_out, r, rf, n, x, y, z);
+        e2 += rn * rn;
+        if (fe) {
+            const double wn = keep ? rn : 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += basis_value(pv + q, 0) * wn;
+        } else {
+            acc[0] += rn;
+        }
+    }
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double u = wave_sum(acc[q]);
+        if (lane == 0) sh[q * NW + w] = u;
+    }
+    {
+        const double u = wave_sum(e2);
+        if (lane == 0) sh[8 * NW + w] = u;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double s = 0.0;
+        for (int u = 0; u < NW; ++u) s += sh[threadIdx.x * NW + u];
+        if (threadIdx.x < 8)
+            slots[(size_t)k * 8 + threadIdx.x] = s;
+        else
+            partial[k] = s;
+    }
+    __syncthreads();   // sh is reused by the caller's next box
+}
+
+// Threads per box of the single-problem form: one cell per thread in full
+// 8x8x8 boxes.
+constexpr int kBoxThreads = 512;
+
+template <class TA, int NV, class TP>
+__global__ __launch_bounds__(kBoxThreads) void k_residual_restrict(GridDev g, const double *__restrict__ W,
+                                                               const double *__restrict__ diag,
+                                                               const double *__restrict__ r0, Pending<TA, NV> v,
+                                                               double *__restrict__ dp_out, double *__restrict__ r,
+                                                               float *__restrict__ rf, double *__restrict__ partial,
+                                                               const uint8_t *__restrict__ dm,
+                                                               const TP *__restrict__ P, int fe,
+                                                               double *__restrict__ slots, const int32_t *ictl)
+{
+    __shared__ double sh[9 * (kBoxThreads / 64)];
+    if (ictl[C_DONE]) return;
+    v.fold = ictl[C_IT] > 0;
+    residual_restrict_box<TA, NV, TP, kBoxThreads>(g, W, diag, r0, v, dp_out, r, rf, partial, dm, P, fe, slots,
+                                               xcd_swizzle(blockIdx.x, gridDim.x), sh);
+}
+
 // ---- batched forms: one launch covers every instance of a batch; the work
 // item of a workgroup names the instance and the block within it, and
 // workgroups of instances that have converged return at once.
 
-template <class TA>
-__device__ __forceinline__ Pending<TA> pending_of(const InstDev &d, int par, bool fold);
-
-// Corrections of the previous iteration: d0 (pre-smoothing), then d2, which
-// the post-smoothing started from d1 and so holds d1 + d2, or d1 alone
-// without post-smoothing.
-template <>
-__device__ __forceinline__ Pending<double> pending_of<double>(const InstDev &d, int par, bool fold)
+// Corrections of the previous iteration: d0 (pre-smoothing; NV = 2), then
+// d2, which the post-smoothing started from d1 and so holds d1 + d2, or d1
+// alone without post-smoothing.  The batch shares n_pre and n_post.
+template <class TA, int NV>
+__device__ __forceinline__ Pending<TA, NV> pending_of(const InstDev &d, int par, bool fold)
 {
-    return Pending<double>{d.a.dp[par], d.n_pre > 0 ? d.a.d0 : nullptr, d.n_post > 0 ? d.a.d2 : d.a.d1, nullptr,
-                           fold};
-}
-
-template <>
-__device__ __forceinline__ Pending<float> pending_of<float>(const InstDev &d, int par, bool fold)
-{
-    return Pending<float>{d.a.dp[par], d.n_pre > 0 ? d.a.d0f : nullptr, d.n_post > 0 ? d.a.d2f : d.a.d1f, nullptr,
-                          fold};
+    const TA *d0, *d1, *d2;
+    if constexpr (sizeof(TA) == 4) {
+        d0 = d.a.d0f; d1 = d.a.d1f; d2 = d.a.d2f;
+    } else {
+        d0 = d.a.d0; d1 = d.a.d1; d2 = d.a.d2;
+    }
+    const TA *post = d.n_post > 0 ? d2 : d1;
+    if constexpr (NV == 2)
+        return Pending<TA, NV>{d.a.dp[par], {d0, post, post}, fold};
+    else
+        return Pending<TA, NV>{d.a.dp[par], {post, post, post}, fold};
 }
 
 template <class TA>
@@ -234,7 +351,8 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const InstDev *__restrict_
         const WorkItem w = work[t];
         const InstDev &d = inst[w.inst];
         if (d.a.ictl[C_DONE]) continue;
-        const Pending<TA> v = pending_of<TA>(d, par, d.a.ictl[C_IT] > 0);
+        // the flat residual serves the batches with pre-smoothing: d0 and the post correction
+        const Pending<TA, 2> v = pending_of<TA, 2>(d, par, d.a.ictl[C_IT] > 0);
         float *rf = sizeof(TA) == 4 ? d.a.r1f : nullptr;
         residual_body(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, rf, d.a.partial, w.blk, sh);
     }
@@ -268,6 +386,32 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const InstDev *__restrict_
         else
             P = d.a.Pbf;
         restrict_box<TP>(d.g, d.a.dmask, P, d.fe, d.a.r, d.a.slots, w.blk, sh);
+    }
+}
+
+// Work item = (instance, owner box); batches without pre-smoothing.
+template <class TA, class TP>
+__global__ __launch_bounds__(kBlock) void kb_residual_restrict(const InstDev *__restrict__ inst,
+                                                                const WorkItem *__restrict__ work,
+                                                                const int32_t *nwork, int par)
+{
+    __shared__ double sh[9 * (kBlock / 64)];
+    CAMS_FOR_ITEMS(t, nwork)
+    {
+        const WorkItem w = work[t];
+        const InstDev &d = inst[w.inst];
+        if (d.a.ictl[C_DONE]) continue;
+        const TP *P;
+        if constexpr (sizeof(TP) == 8)
+            P = d.a.P;
+        else if constexpr (sizeof(TP) == 4)
+            P = d.a.P32;
+        else
+            P = d.a.Pbf;
+        const Pending<TA, 1> v = pending_of<TA, 1>(d, par, d.a.ictl[C_IT] > 0);
+        float *rf = sizeof(TA) == 4 ? d.a.r1f : nullptr;
+        residual_restrict_box<TA, 1, TP, kBlock>(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, rf,
+                                              d.a.partial, d.a.dmask, P, d.fe, d.a.slots, w.blk, sh);
     }
 }
 
@@ -314,27 +458,90 @@ void launch_iter_reset(cams_ctx *c)
     k_iter_reset<<<(n + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(c->a.ictl, c->a.dp[0], c->g.N, nctl);
 }
 
+template <class TA, int NV>
+void residual_flat(cams_ctx *c, const double *dp_in, const TA *const pv[3], double *dp_out, float *rf)
+{
+    const Pending<TA, NV> v{dp_in, {pv[0], pv[1], pv[2]}, false};
+    k_residual_ctl<TA, NV><<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, rf, c->a.partial, c->a.ictl);
+}
+
+template <class TA>
+void residual_flat(cams_ctx *c, const double *dp_in, const TA *a0, const TA *a1, const TA *a2, double *dp_out,
+                   float *rf)
+{
+    const TA *pv[3];
+    switch (compact_pending(a0, a1, a2, pv)) {
+    case 1: residual_flat<TA, 1>(c, dp_in, pv, dp_out, rf); break;
+    case 2: residual_flat<TA, 2>(c, dp_in, pv, dp_out, rf); break;
+    case 3: residual_flat<TA, 3>(c, dp_in, pv, dp_out, rf); break;
+    default: throw HipError(hipErrorInvalidValue, "pending corrections", __LINE__);   // none: not a C-AMS iteration
+    }
+}
+
 void launch_residual_ctl(cams_ctx *c, const double *dp_in, const double *a0, const double *a1, const double *a2,
                          double *dp_out)
 {
-    Pending<double> v{dp_in, a0, a1, a2, false};
-    k_residual_ctl<double><<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
-        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, nullptr, c->a.partial, c->a.ictl);
+    residual_flat<double>(c, dp_in, a0, a1, a2, dp_out, nullptr);
 }
 
 void launch_residual_ctl32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
                            double *dp_out, float *rf)
 {
-    Pending<float> v{dp_in, a0, a1, a2, false};
-    k_residual_ctl<float><<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
-        c->g, c->a.W, c->a.diag, c->a.r0, v, dp_out, c->a.r, rf, c->a.partial, c->a.ictl);
+    residual_flat<float>(c, dp_in, a0, a1, a2, dp_out, rf);
 }
 
-void launch_finalize_ctl(cams_ctx *c)
+template <class TA, int NV>
+void residual_restrict(cams_ctx *c, const Pending<TA, NV> &v, double *dp_out, float *rf)
+{
+    const GridDev &g = c->g;
+    const Arrays &a = c->a;
+    const int fe = c->opt.restriction == CAMS_R_FE;
+    if (c->opt.precision == CAMS_MIXED_BF16)
+        k_residual_restrict<TA, NV, uint16_t><<<g.Nc, kBoxThreads, 0, c->stream>>>(g, a.W, a.diag, a.r0, v, dp_out, a.r, rf,
+                                                                           a.partial, a.dmask, a.Pbf, fe, a.slots,
+                                                                           a.ictl);
+    else if (c->opt.precision == CAMS_MIXED_FP32)
+        k_residual_restrict<TA, NV, float><<<g.Nc, kBoxThreads, 0, c->stream>>>(g, a.W, a.diag, a.r0, v, dp_out, a.r, rf,
+                                                                        a.partial, a.dmask, a.P32, fe, a.slots,
+                                                                        a.ictl);
+    else
+        k_residual_restrict<TA, NV, double><<<g.Nc, kBoxThreads, 0, c->stream>>>(g, a.W, a.diag, a.r0, v, dp_out, a.r, rf,
+                                                                         a.partial, a.dmask, a.P, fe, a.slots,
+                                                                         a.ictl);
+}
+
+// Without pre-smoothing at most two corrections are pending (d1 and d2 of
+// the red-black smoother's post-smoothing).
+template <class TA>
+void residual_restrict(cams_ctx *c, const double *dp_in, const TA *a0, const TA *a1, const TA *a2, double *dp_out,
+                       float *rf)
+{
+    const TA *pv[3];
+    switch (compact_pending(a0, a1, a2, pv)) {
+    case 1: residual_restrict<TA, 1>(c, Pending<TA, 1>{dp_in, {pv[0], pv[1], pv[2]}, false}, dp_out, rf); break;
+    case 2: residual_restrict<TA, 2>(c, Pending<TA, 2>{dp_in, {pv[0], pv[1], pv[2]}, false}, dp_out, rf); break;
+    default: throw HipError(hipErrorInvalidValue, "pending corrections", __LINE__);
+    }
+}
+
+void launch_residual_restrict(cams_ctx *c, const double *dp_in, const double *a0, const double *a1,
+                              const double *a2, double *dp_out)
+{
+    residual_restrict<double>(c, dp_in, a0, a1, a2, dp_out, nullptr);
+}
+
+void launch_residual_restrict32(cams_ctx *c, const double *dp_in, const float *a0, const float *a1, const float *a2,
+                                double *dp_out, float *rf)
+{
+    residual_restrict<float>(c, dp_in, a0, a1, a2, dp_out, rf);
+}
+
+void launch_finalize_ctl(cams_ctx *c, int nparts)
 {
     const double rt = c->opt.lin_rtol;
-    k_finalize_ctl<<<1, kFinal, 0, c->stream>>>(c->a.partial, (c->g.N + kBlock - 1) / kBlock, c->a.ictl, c->a.scal,
-                                                rt * rt, c->opt.lin_maxit);
+    k_finalize_ctl<<<1, kFinal, 0, c->stream>>>(c->a.partial, nparts, c->a.ictl, c->a.scal, rt * rt,
+                                                c->opt.lin_maxit);
 }
 
 void launch_restrict(cams_ctx *c, const double *r)
@@ -362,6 +569,16 @@ void launch_batch_residual(const BatchLaunch &L, int par, bool mixed)
 void launch_batch_finalize(const InstDev *inst, int count, hipStream_t st)
 {
     kb_finalize<<<count, kFinal, 0, st>>>(inst);
+}
+
+void launch_batch_residual_restrict(const BatchLaunch &L, int par, bool mixed, int precision)
+{
+    if (!mixed)
+        launch_persistent(kb_residual_restrict<double, double>, kBlock, L, L.inst, L.work, L.nwork, par);
+    else if (precision == CAMS_MIXED_BF16)
+        launch_persistent(kb_residual_restrict<float, uint16_t>, kBlock, L, L.inst, L.work, L.nwork, par);
+    else
+        launch_persistent(kb_residual_restrict<float, float>, kBlock, L, L.inst, L.work, L.nwork, par);
 }
 
 void launch_batch_restrict(const BatchLaunch &L, int precision)
