@@ -55,18 +55,27 @@ __device__ __forceinline__ void prolong_lo_body(const GridDev &g, const float *_
                                                 const uint16_t *__restrict__ Pbf, const uint8_t *__restrict__ dm,
                                                 const double *__restrict__ xc, float *__restrict__ out, int n)
 {
-    float s = 0.f;
-    if (!dm[n]) {
-        const Cell c = cell_of(g, n);
-        const int a = g.lo[0][c.i], b = g.lo[1][c.j], cc = g.lo[2][c.k];
+    // branch-free as prolong_body: mask, node-table and basis loads together,
+    // then the coarse values
+    const Cell c = cell_of(g, n);
+    const bool keep = !dm[n];
+    const int a = g.lo[0][c.i], b = g.lo[1][c.j], cc = g.lo[2][c.k];
+    float w[8];
+    double xv[8];
+    bool use[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const float w = BF ? from_bf16(Pbf[(size_t)t * g.N + n]) : P32[(size_t)t * g.N + n];
-            const int na = a + (t & 1), nb = b + ((t >> 1) & 1), nc = cc + ((t >> 2) & 1);
-            if (w != 0.f && na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2]) s += w * (float)xc[node_index(g, na, nb, nc)];
-        }
+    for (int t = 0; t < 8; ++t) w[t] = BF ? from_bf16(Pbf[(size_t)t * g.N + n]) : P32[(size_t)t * g.N + n];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int na = a + (t & 1), nb = b + ((t >> 1) & 1), nc = cc + ((t >> 2) & 1);
+        const bool in = na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2];
+        xv[t] = xc[in ? node_index(g, na, nb, nc) : 0];
+        use[t] = in;
     }
-    out[n] = s;
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s = (use[t] && w[t] != 0.f) ? s + w[t] * (float)xv[t] : s;
+    out[n] = keep ? s : 0.f;
 }
 
 template <int BF>
@@ -87,15 +96,20 @@ __device__ __forceinline__ void sub64_lo_body(const GridDev &g, const double *__
                                               const double *__restrict__ diag, const float *__restrict__ x,
                                               double *__restrict__ r, float *__restrict__ rf, int n)
 {
+    // neighbours outside the grid: the cell itself with coupling 0 (no branches)
     const Cell c = cell_of(g, n);
     const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    const bool xm = c.i > 0, xp = c.i + 1 < g.nx, ym = c.j > 0, yp = c.j + 1 < g.ny, zm = c.k > 0, zp = c.k + 1 < g.nz;
+    const int nxm = xm ? n - 1 : n, nxp = xp ? n + 1 : n, nym = ym ? n - g.nx : n, nyp = yp ? n + g.nx : n;
+    const int nzm = zm ? n - g.sxy : n, nzp = zp ? n + g.sxy : n;
+    const double wxm = Wx[nxm], wxp = Wx[n], wym = Wy[nym], wyp = Wy[n], wzm = Wz[nzm], wzp = Wz[n];
     double s = diag[n] * (double)x[n];
-    if (c.i > 0) s -= Wx[n - 1] * (double)x[n - 1];
-    if (c.i + 1 < g.nx) s -= Wx[n] * (double)x[n + 1];
-    if (c.j > 0) s -= Wy[n - g.nx] * (double)x[n - g.nx];
-    if (c.j + 1 < g.ny) s -= Wy[n] * (double)x[n + g.nx];
-    if (c.k > 0) s -= Wz[n - g.sxy] * (double)x[n - g.sxy];
-    if (c.k + 1 < g.nz) s -= Wz[n] * (double)x[n + g.sxy];
+    s -= (xm ? wxm : 0.0) * (double)x[nxm];
+    s -= (xp ? wxp : 0.0) * (double)x[nxp];
+    s -= (ym ? wym : 0.0) * (double)x[nym];
+    s -= (yp ? wyp : 0.0) * (double)x[nyp];
+    s -= (zm ? wzm : 0.0) * (double)x[nzm];
+    s -= (zp ? wzp : 0.0) * (double)x[nzp];
     const double rn = r[n] - s;
     r[n] = rn;
     rf[n] = (float)rn;

@@ -240,42 +240,49 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         L.wy[idx] = 0;
         L.wz[idx] = 0;
     }
+    // Branch-free staging, so that all loads of a thread go out together:
+    // slots outside a ragged block read the block's first cell and store
+    // zeros; a neighbour outside the grid is the cell itself with coupling 0
+    // (ae - 0 * e = ae).
     T e0[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int t = threadIdx.x + NT * c;
         const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
-        T z = 0, ev = 0, id = 0, fx = 0, fy = 0, fz = 0;
-        if (li < ex && lj < ey && lk < ez) {
-            const int i = i0 + li, j = j0 + lj, k = k0 + lk;
-            const int n = i + g.nx * (j + g.ny * k);
-            const T fxm = i > 0 ? Wx[n - 1] : T(0), fxp = i + 1 < g.nx ? Wx[n] : T(0);
-            const T fym = j > 0 ? Wy[n - g.nx] : T(0), fyp = j + 1 < g.ny ? Wy[n] : T(0);
-            const T fzm = k > 0 ? Wz[n - g.sxy] : T(0), fzp = k + 1 < g.nz ? Wz[n] : T(0);
-            z = (T)rhs[n];
-            if (eold) {
-                ev = eold[n];
-                T ae = diag[n] * ev;
-                if (i > 0) ae -= fxm * eold[n - 1];
-                if (i + 1 < g.nx) ae -= fxp * eold[n + 1];
-                if (j > 0) ae -= fym * eold[n - g.nx];
-                if (j + 1 < g.ny) ae -= fyp * eold[n + g.nx];
-                if (k > 0) ae -= fzm * eold[n - g.sxy];
-                if (k + 1 < g.nz) ae -= fzp * eold[n + g.sxy];
-                z -= ae;
-            }
-            id = invd[n];
-            // coupling to the +x/+y/+z neighbour when it lies in the block
-            fx = li + 1 < ex ? fxp : T(0);
-            fy = lj + 1 < ey ? fyp : T(0);
-            fz = lk + 1 < ez ? fzp : T(0);
-        }
-        e0[c] = ev;
-        L.y[PAD + t] = z;
-        L.dinv[t] = id;
-        L.wx[PAD + t] = fx;
-        L.wy[PAD + t] = fy;
-        L.wz[PAD + t] = fz;
+        const bool act = li < ex && lj < ey && lk < ez;
+        const int i = i0 + (act ? li : 0), j = j0 + (act ? lj : 0), k = k0 + (act ? lk : 0);
+        const int n = i + g.nx * (j + g.ny * k);
+        const bool xm = i > 0, xp = i + 1 < g.nx, ym = j > 0, yp = j + 1 < g.ny, zm = k > 0, zp = k + 1 < g.nz;
+        const int nxm = xm ? n - 1 : n, nxp = xp ? n + 1 : n, nym = ym ? n - g.nx : n, nyp = yp ? n + g.nx : n;
+        const int nzm = zm ? n - g.sxy : n, nzp = zp ? n + g.sxy : n;
+        const T wxm = Wx[nxm], wxp = Wx[n], wym = Wy[nym], wyp = Wy[n], wzm = Wz[nzm], wzp = Wz[n];
+        const T fxm = xm ? wxm : T(0), fxp = xp ? wxp : T(0);
+        const T fym = ym ? wym : T(0), fyp = yp ? wyp : T(0);
+        const T fzm = zm ? wzm : T(0), fzp = zp ? wzp : T(0);
+        // without e_old (a step from zero) the loads read W and the result is unused
+        const T *eo = eold ? eold : W;
+        const T ec = eo[n], exm = eo[nxm], exp = eo[nxp], eym = eo[nym], eyp = eo[nyp];
+        const T ezm = eo[nzm], ezp = eo[nzp];
+        T ae = diag[n] * ec;
+        ae -= fxm * exm;
+        ae -= fxp * exp;
+        ae -= fym * eym;
+        ae -= fyp * eyp;
+        ae -= fzm * ezm;
+        ae -= fzp * ezp;
+        // weights instead of selects keep the compiler from splitting the code
+        // on e_old (rhs - 1 * ae rounds as rhs - ae; rhs - 0 * ae = rhs)
+        const T on = eold ? T(1) : T(0);
+        const T z = (T)rhs[n] - on * ae;
+        const T ev = on * ec;
+        const T id = invd[n];
+        e0[c] = act ? ev : T(0);
+        L.y[PAD + t] = act ? z : T(0);
+        L.dinv[t] = act ? id : T(0);
+        // coupling to the +x/+y/+z neighbour when it lies in the block
+        L.wx[PAD + t] = act && li + 1 < ex ? fxp : T(0);
+        L.wy[PAD + t] = act && lj + 1 < ey ? fyp : T(0);
+        L.wz[PAD + t] = act && lk + 1 < ez ? fzp : T(0);
     }
     __syncthreads();
     if (SW == 1 && threadIdx.x < 64) {
