@@ -729,11 +729,12 @@ static void enqueue_iteration(cams_ctx *c, int it)
             launch_bilu_smooth32(c, (const double *)a.r, a.d0f, O.n_pre, done);
             launch_sub64_lo(c, a.d0f, a.r, done);
             launch_restrict(c, a.r);
+            launch_gemv(c, a.rc, a.xc, done);
         } else {
+            // the stopping test runs with the coarse solve
             launch_residual_restrict32(c, a.dp[it & 1], pend0, pend1, nullptr, a.dp[(it + 1) & 1], a.r1f);
-            launch_finalize_ctl(c, c->g.Nc);
+            launch_gemv(c, a.rc, a.xc, done, c->g.Nc);
         }
-        launch_gemv(c, a.rc, a.xc, done);
         launch_prolong32(c, a.xc, a.d1f, done);
         if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done, a.d1f);
         return;
@@ -748,11 +749,11 @@ static void enqueue_iteration(cams_ctx *c, int it)
         launch_smooth(c, a.r, a.d0, O.n_pre, done);
         launch_stencil_sub(c, a.r, a.d0, a.r, done);
         launch_restrict(c, a.r);
+        launch_gemv(c, a.rc, a.xc, done);              // Eq. (15): coarse solve
     } else {
         launch_residual_restrict(c, a.dp[it & 1], pend0, pend1, pend2, a.dp[(it + 1) & 1]);
-        launch_finalize_ctl(c, c->g.Nc);
+        launch_gemv(c, a.rc, a.xc, done, c->g.Nc);     // Eq. (15), with the stopping test
     }
-    launch_gemv(c, a.rc, a.xc, done);                  // Eq. (15): coarse solve
     launch_prolong(c, a.xc, a.d1, done);               // Eq. (12)
     if (O.n_post > 0) {
         if (block) {

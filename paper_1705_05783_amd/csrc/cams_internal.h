@@ -325,7 +325,7 @@ void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDes
 // ---- coarse level (k_coarse.hip)
 void launch_coarse_operator(cams_ctx *c);
 void launch_coarse_factor(cams_ctx *c);   // LU + explicit inverse of Ac
-void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done);
+void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done, int stop_parts = 0);
 void launch_coarse_solve(cams_ctx *c, const double *rc, double *xc);   // xc = A_c^-1 rc
 
 }  // namespace cams

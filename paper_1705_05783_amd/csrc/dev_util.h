@@ -79,4 +79,38 @@ __device__ __forceinline__ int flat_cell(const InstDev *__restrict__ inst, const
     return n < d->g.N ? n : -1;
 }
 
+// ||r||^2 from the residual kernel's nparts partials (in index order, then
+// a fixed tree) and the stopping test of the C-AMS iteration, by one
+// workgroup of kStopThreads threads: outcome 0 converged (||r||^2 <= rtol2
+// ||r0||^2, or r0 = 0), 1 iteration limit, 2 non-finite norm; otherwise the
+// iteration counter advances.  Every caller uses the same thread count, so
+// the norm is the same bit for bit wherever the test runs.
+constexpr int kStopThreads = 256;
+
+__device__ __forceinline__ void stop_test(const double *__restrict__ partial, int nparts, int32_t *ictl,
+                                          double *scal, double rtol2, int maxit, double *sh)
+{
+    double u = 0.0;
+    for (int t = threadIdx.x; t < nparts; t += kStopThreads) u += partial[t];
+    const double s = block_sum<kStopThreads>(u, sh);
+    if (threadIdx.x != 0) return;
+    const int it = ictl[C_IT];
+    if (it == 0) scal[S_R0N2] = s;
+    const double r0n2 = it == 0 ? s : scal[S_R0N2];
+    scal[S_RN2] = s;
+    int outcome = -1;
+    if (!(s < 1e300))                          // NaN or Inf
+        outcome = 2;
+    else if (s <= rtol2 * r0n2 || r0n2 == 0.0)
+        outcome = 0;
+    else if (it >= maxit)
+        outcome = 1;
+    if (outcome < 0) {
+        ictl[C_IT] = it + 1;
+        return;
+    }
+    ictl[C_OUTCOME] = outcome;
+    ictl[C_DONE] = 1;
+}
+
 }  // namespace cams

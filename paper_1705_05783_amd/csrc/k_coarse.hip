@@ -608,12 +608,24 @@ constexpr int kGemvLds = 1024;   // coarse sizes for which every GEMV workgroup 
 // y = M x, one wave per row (fixed lane partition and shuffle tree).  With
 // `slots` set (n <= kGemvLds), x = R r is first assembled in LDS from the
 // restriction's slot partials.
+//
+// With `partial` set, one extra workgroup (the last) runs the stopping test
+// of the iteration on the residual partials instead (stop_test), in parallel
+// with the rows.  The test may set the done flag while the row workgroups
+// start: a row workgroup that sees it skips its row, which is then unused.
 __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, int n, const double *__restrict__ x,
                                                   GridDev g, const double *__restrict__ slots, int fe,
-                                                  double *__restrict__ y, const int32_t *done)
+                                                  double *__restrict__ y, const int32_t *done,
+                                                  const double *__restrict__ partial, int nparts, int32_t *ictl,
+                                                  double *scal, double rtol2, int maxit)
 {
+    static_assert(kBlock == kStopThreads, "one workgroup shape for the rows and the stopping test");
     __shared__ double xs[kGemvLds];
     if (done && *done) return;
+    if (partial && blockIdx.x == gridDim.x - 1) {
+        stop_test(partial, nparts, ictl, scal, rtol2, maxit, xs);
+        return;
+    }
     const double *xv = x;
     if (slots) {
         for (int k = threadIdx.x; k < n; k += kBlock) xs[k] = node_sum(g, slots, fe, k);
@@ -1018,19 +1030,30 @@ void launch_coarse_factor(cams_ctx *c)
     }
 }
 
-void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done)
+// xc = A_c^-1 (R r) from the restriction slots.  With stop_parts > 0 the
+// stopping test on that many residual partials runs first: inside the GEMV
+// launch when the coarse system is small enough for the LDS form, else as a
+// launch of its own.
+void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done, int stop_parts)
 {
     const int n = c->g.Nc;
     const int fe = c->opt.restriction == CAMS_R_FE;
+    const double rt = c->opt.lin_rtol;
+    if (!c->blocktri && n <= kGemvLds) {
+        const bool stop = stop_parts > 0;
+        k_gemv<<<cdiv(n, kBlock / 64) + (stop ? 1 : 0), kBlock, 0, c->stream>>>(
+            c->a.Ainv, n, nullptr, c->g, c->a.slots, fe, xc, done, stop ? c->a.partial : nullptr, stop_parts,
+            c->a.ictl, c->a.scal, rt * rt, c->opt.lin_maxit);
+        return;
+    }
+    if (stop_parts > 0) launch_finalize_ctl(c, stop_parts);
     if (c->blocktri) {
         k_node_sum<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.slots, fe, c->a.rc, done);
         solve_blocktri(c, c->a.rc, xc, done);
-    } else if (n <= kGemvLds) {
-        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, nullptr, c->g, c->a.slots, fe, xc,
-                                                             done);
     } else {
         k_node_sum<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.slots, fe, c->a.rc, done);
-        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, c->g, nullptr, fe, xc, done);
+        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, c->g, nullptr, fe, xc, done,
+                                                             nullptr, 0, nullptr, nullptr, 0.0, 0);
     }
     (void)rc;
 }
@@ -1043,7 +1066,8 @@ void launch_coarse_solve(cams_ctx *c, const double *rc, double *xc)
     if (c->blocktri)
         solve_blocktri(c, c->a.rc, xc, nullptr);
     else
-        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, c->g, nullptr, 0, xc, nullptr);
+        k_gemv<<<cdiv(n, kBlock / 64), kBlock, 0, c->stream>>>(c->a.Ainv, n, c->a.rc, c->g, nullptr, 0, xc, nullptr,
+                                                             nullptr, 0, nullptr, nullptr, 0.0, 0);
 }
 
 // Test hook: C -= A B on the device, same kernel as the factorisation.

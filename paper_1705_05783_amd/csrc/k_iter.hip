@@ -123,42 +123,15 @@ __global__ __launch_bounds__(kBlock) void k_residual_ctl(GridDev g, const double
     residual_body(g, W, diag, r0, v, dp_out, r, rf, partial, xcd_swizzle(blockIdx.x, gridDim.x), sh);
 }
 
-// ||r||^2 from the residual kernel's partials and the stopping test, by one
-// workgroup of kFinal threads.
-constexpr int kFinal = 1024;
-
-__device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int nparts, int32_t *ictl,
-                                              double *scal, double rtol2, int maxit, double *sh)
-{
-    double u = 0.0;
-    for (int t = threadIdx.x; t < nparts; t += kFinal) u += partial[t];
-    const double s = block_sum<kFinal>(u, sh);
-    if (threadIdx.x != 0) return;
-    const int it = ictl[C_IT];
-    if (it == 0) scal[S_R0N2] = s;
-    const double r0n2 = it == 0 ? s : scal[S_R0N2];
-    scal[S_RN2] = s;
-    int outcome = -1;
-    if (!(s < 1e300))                          // NaN or Inf
-        outcome = 2;
-    else if (s <= rtol2 * r0n2 || r0n2 == 0.0)
-        outcome = 0;
-    else if (it >= maxit)
-        outcome = 1;
-    if (outcome < 0) {
-        ictl[C_IT] = it + 1;
-        return;
-    }
-    ictl[C_OUTCOME] = outcome;
-    ictl[C_DONE] = 1;
-}
+// ||r||^2 from the residual kernel's partials and the stopping test.
+constexpr int kFinal = kStopThreads;
 
 __global__ __launch_bounds__(kFinal) void k_finalize_ctl(const double *__restrict__ partial, int nparts,
                                                           int32_t *ictl, double *scal, double rtol2, int maxit)
 {
     __shared__ double sh[kFinal / 64];
     if (ictl[C_DONE]) return;
-    finalize_body(partial, nparts, ictl, scal, rtol2, maxit, sh);
+    stop_test(partial, nparts, ictl, scal, rtol2, maxit, sh);
 }
 
 // Restriction R r (Eqs. (7), (13), (15)) in two deterministic stages.
@@ -364,7 +337,7 @@ __global__ __launch_bounds__(kFinal) void kb_finalize(const InstDev *__restrict_
     __shared__ double sh[kFinal / 64];
     const InstDev &d = inst[blockIdx.x];
     if (d.a.ictl[C_DONE]) return;
-    finalize_body(d.a.partial, d.nparts, d.a.ictl, d.a.scal, d.rtol2, d.maxit, sh);
+    stop_test(d.a.partial, d.nparts, d.a.ictl, d.a.scal, d.rtol2, d.maxit, sh);
 }
 
 // Work item = (instance, owner box).
