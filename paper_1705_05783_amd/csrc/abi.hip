@@ -735,6 +735,10 @@ static void enqueue_iteration(cams_ctx *c, int it)
             launch_residual_restrict32(c, a.dp[it & 1], pend0, pend1, nullptr, a.dp[(it + 1) & 1], a.r1f);
             launch_gemv(c, a.rc, a.xc, done, c->g.Nc);
         }
+        if (O.n_post > 0 && bilu_first_fused(c)) {   // Eq. (12) inside the first smoothing step
+            launch_bilu_smooth32_from_coarse(c, (const float *)a.r1f, a.d2f, O.n_post, done);
+            return;
+        }
         launch_prolong32(c, a.xc, a.d1f, done);
         if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done, a.d1f);
         return;
@@ -753,6 +757,10 @@ static void enqueue_iteration(cams_ctx *c, int it)
     } else {
         launch_residual_restrict(c, a.dp[it & 1], pend0, pend1, pend2, a.dp[(it + 1) & 1]);
         launch_gemv(c, a.rc, a.xc, done, c->g.Nc);     // Eq. (15), with the stopping test
+    }
+    if (O.n_post > 0 && block && bilu_first_fused(c)) {
+        launch_bilu_smooth_from_coarse(c, a.r, a.d2, O.n_post, done);   // Eq. (12) inside the first step
+        return;
     }
     launch_prolong(c, a.xc, a.d1, done);               // Eq. (12)
     if (O.n_post > 0) {

@@ -211,6 +211,11 @@ void launch_bilu_setup(cams_ctx *c);
 void launch_bilu_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done,
                         const double *e_init = nullptr);
 
+// post-smoothing from e = P xc, the prolongation fused into the first step
+// (when bilu_first_fused: grids whose blocks are all resident at once)
+bool bilu_first_fused(cams_ctx *c);
+void launch_bilu_smooth_from_coarse(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done);
+void launch_bilu_smooth32_from_coarse(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done);
 void launch_bilu_smooth32(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done,
                           const float *e_init = nullptr);
 void launch_bilu_smooth32(cams_ctx *c, const double *rhs, float *e, int steps, const int32_t *done,

@@ -63,6 +63,55 @@ __device__ __forceinline__ int node_index(const GridDev &g, int a, int b, int c)
     return a + g.nb[0] * (b + g.nb[1] * c);
 }
 
+// Prolongation (Eq. (12)) at one cell: sum over the 8 coarse nodes that
+// bracket cell n = (i, j, k) of P_t[n] xc[node t], skipping zero weights and
+// nodes past the last; 0 at Dirichlet cells.  The basis is FP64 (summed in
+// FP64) or FP32 / bfloat16 bits (summed in FP32).  Branch-free: the mask,
+// node-table and basis loads go out together, then the coarse values.  Every
+// prolongation of the solve (standalone or inside the first smoothing step)
+// goes through here, so all agree bit for bit.
+template <class TP>
+struct BasisAcc {
+    using T = float;
+};
+template <>
+struct BasisAcc<double> {
+    using T = double;
+};
+__device__ __forceinline__ double basis_load(const double *P, size_t i) { return P[i]; }
+__device__ __forceinline__ float basis_load(const float *P, size_t i) { return P[i]; }
+__device__ __forceinline__ float basis_load(const uint16_t *P, size_t i)
+{
+    return __uint_as_float((uint32_t)P[i] << 16);
+}
+
+template <class TP>
+__device__ __forceinline__ typename BasisAcc<TP>::T prolong_at(const GridDev &g, const TP *__restrict__ P,
+                                                               const uint8_t *__restrict__ dm,
+                                                               const double *__restrict__ xc, int n, int i, int j,
+                                                               int k)
+{
+    using A = typename BasisAcc<TP>::T;
+    const bool keep = !dm[n];
+    const int a = g.lo[0][i], b = g.lo[1][j], cc = g.lo[2][k];
+    A w[8];
+    double xv[8];
+    bool use[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) w[t] = basis_load(P, (size_t)t * g.N + n);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int na = a + (t & 1), nb = b + ((t >> 1) & 1), nc = cc + ((t >> 2) & 1);
+        const bool in = na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2];
+        xv[t] = xc[in ? node_index(g, na, nb, nc) : 0];
+        use[t] = in;
+    }
+    A s = A(0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s = (use[t] && w[t] != A(0)) ? s + w[t] * (A)xv[t] : s;
+    return keep ? s : A(0);
+}
+
 // Loop of a persistent batched kernel over its work items: blockIdx.x,
 // blockIdx.x + gridDim.x, ... below the device-side count *nwork (uniform
 // over the workgroup).

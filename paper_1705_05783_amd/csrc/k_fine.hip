@@ -181,26 +181,8 @@ __device__ __forceinline__ void prolong_body(const GridDev &g, const double *__r
                                              const uint8_t *__restrict__ dm, const double *__restrict__ xc,
                                              double *__restrict__ out, int n)
 {
-    // branch-free: the mask, node-table and basis loads go out together, then
-    // the coarse values (the terms with w = 0 or no node are skipped by select)
     const Cell c = cell_of(g, n);
-    const bool keep = !dm[n];
-    const int a = g.lo[0][c.i], b = g.lo[1][c.j], cc = g.lo[2][c.k];
-    double w[8], xv[8];
-    bool use[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) w[t] = P[(size_t)t * g.N + n];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int na = a + (t & 1), nb = b + ((t >> 1) & 1), nc = cc + ((t >> 2) & 1);
-        const bool in = na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2];
-        xv[t] = xc[in ? node_index(g, na, nb, nc) : 0];
-        use[t] = in;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) s = (use[t] && w[t] != 0.0) ? s + w[t] * xv[t] : s;
-    out[n] = keep ? s : 0.0;
+    out[n] = prolong_at(g, P, dm, xc, n, c.i, c.j, c.k);
 }
 
 __global__ __launch_bounds__(kBlock) void k_prolong(GridDev g, const double *__restrict__ P,

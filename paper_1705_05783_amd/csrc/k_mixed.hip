@@ -55,27 +55,11 @@ __device__ __forceinline__ void prolong_lo_body(const GridDev &g, const float *_
                                                 const uint16_t *__restrict__ Pbf, const uint8_t *__restrict__ dm,
                                                 const double *__restrict__ xc, float *__restrict__ out, int n)
 {
-    // branch-free as prolong_body: mask, node-table and basis loads together,
-    // then the coarse values
     const Cell c = cell_of(g, n);
-    const bool keep = !dm[n];
-    const int a = g.lo[0][c.i], b = g.lo[1][c.j], cc = g.lo[2][c.k];
-    float w[8];
-    double xv[8];
-    bool use[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) w[t] = BF ? from_bf16(Pbf[(size_t)t * g.N + n]) : P32[(size_t)t * g.N + n];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int na = a + (t & 1), nb = b + ((t >> 1) & 1), nc = cc + ((t >> 2) & 1);
-        const bool in = na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2];
-        xv[t] = xc[in ? node_index(g, na, nb, nc) : 0];
-        use[t] = in;
-    }
-    float s = 0.f;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) s = (use[t] && w[t] != 0.f) ? s + w[t] * (float)xv[t] : s;
-    out[n] = keep ? s : 0.f;
+    if constexpr (BF)
+        out[n] = prolong_at(g, Pbf, dm, xc, n, c.i, c.j, c.k);
+    else
+        out[n] = prolong_at(g, P32, dm, xc, n, c.i, c.j, c.k);
 }
 
 template <int BF>

@@ -16,6 +16,8 @@
 // along x, which share 128-byte lines of every array) are given to
 // workgroup ids that the dispatcher sends to the same XCD, so the shared
 // lines are fetched into one L2 instead of two.
+#include <type_traits>
+
 #include "cams_internal.h"
 #include "dev_util.h"
 
@@ -222,11 +224,59 @@ __device__ __forceinline__ void sweep_registers(SmoothLds<T> &L, int ex, int ey,
     }
 }
 
-template <class T, class TR, int NT, int SW = 0>
+// Prolongated coarse correction as e_old (the first post-smoothing step):
+// basis P (TP = double, float or bfloat16 bits), Dirichlet mask, coarse
+// solution, and an LDS cube of (SB + 2)^3 values for the block and its face
+// neighbours.
+template <class T, class TP>
+struct FromCoarse {
+    const TP *P;
+    const uint8_t *dm;
+    const double *xc;
+    T *cube;
+};
+
+constexpr int CB = SB + 2;    // cube edge: the block with one layer around it
+
+// e_old = P xc on the block's cells and on the cells across its six faces
+// (those outside the grid get 0), into the LDS cube at (li+1, lj+1, lk+1).
+template <class T, class TP, int NT>
+__device__ __forceinline__ void prolong_cube(const GridDev &g, const FromCoarse<T, TP> &fc, int i0, int j0, int k0,
+                                             int ex, int ey, int ez)
+{
+    for (int q = threadIdx.x; q < ST + 6 * PAD; q += NT) {
+        int ci, cj, ck;
+        bool need;
+        if (q < ST) {
+            ci = q & (SB - 1);
+            cj = (q >> 3) & (SB - 1);
+            ck = q >> 6;
+            need = ci < ex && cj < ey && ck < ez;
+        } else {
+            const int f = (q - ST) >> 6, u = (q - ST) & (SB - 1), v = ((q - ST) >> 3) & (SB - 1);
+            switch (f) {
+            case 0: ci = -1; cj = u; ck = v; need = u < ey && v < ez; break;
+            case 1: ci = ex; cj = u; ck = v; need = u < ey && v < ez; break;
+            case 2: ci = u; cj = -1; ck = v; need = u < ex && v < ez; break;
+            case 3: ci = u; cj = ey; ck = v; need = u < ex && v < ez; break;
+            case 4: ci = u; cj = v; ck = -1; need = u < ex && v < ey; break;
+            default: ci = u; cj = v; ck = ez; need = u < ex && v < ey; break;
+            }
+        }
+        if (!need) continue;
+        const int i = i0 + ci, j = j0 + cj, k = k0 + ck;
+        const bool in = i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
+        const int ii = in ? i : i0, jj = in ? j : j0, kk = in ? k : k0;
+        const T v = (T)prolong_at(g, fc.P, fc.dm, fc.xc, ii + g.nx * (jj + g.ny * kk), ii, jj, kk);
+        fc.cube[(ci + 1) + CB * (cj + 1) + CB * CB * (ck + 1)] = in ? v : T(0);
+    }
+}
+
+template <class T, class TR, int NT, int SW = 0, class TP = void>
 __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
                                                const T *__restrict__ invd, const TR *__restrict__ rhs,
                                                const T *__restrict__ eold, T *__restrict__ enew, int blk,
-                                               SmoothLds<T> &L)
+                                               SmoothLds<T> &L, FromCoarse<T, TP> fc = {})
 {
     constexpr int CPT = ST / NT;   // cells per thread
     const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
@@ -245,6 +295,59 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
     // zeros; a neighbour outside the grid is the cell itself with coupling 0
     // (ae - 0 * e = ae).
     T e0[CPT];
+    if constexpr (!std::is_void_v<TP>) {
+        // e_old = P xc: the coefficient loads go out first, then the
+        // prolongation fills the cube, then the residual reads e_old there
+        T f6[CPT][6], dg[CPT], rh[CPT], idv[CPT];
+        int qc[CPT];
+        bool av[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int t = threadIdx.x + NT * c;
+            const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
+            const bool act = li < ex && lj < ey && lk < ez;
+            const int ai = act ? li : 0, aj = act ? lj : 0, ak = act ? lk : 0;
+            const int i = i0 + ai, j = j0 + aj, k = k0 + ak;
+            const int n = i + g.nx * (j + g.ny * k);
+            const bool xm = i > 0, xp = i + 1 < g.nx, ym = j > 0, yp = j + 1 < g.ny, zm = k > 0, zp = k + 1 < g.nz;
+            const int nxm = xm ? n - 1 : n, nym = ym ? n - g.nx : n, nzm = zm ? n - g.sxy : n;
+            const T wxm = Wx[nxm], wxp = Wx[n], wym = Wy[nym], wyp = Wy[n], wzm = Wz[nzm], wzp = Wz[n];
+            f6[c][0] = xm ? wxm : T(0);
+            f6[c][1] = xp ? wxp : T(0);
+            f6[c][2] = ym ? wym : T(0);
+            f6[c][3] = yp ? wyp : T(0);
+            f6[c][4] = zm ? wzm : T(0);
+            f6[c][5] = zp ? wzp : T(0);
+            dg[c] = diag[n];
+            rh[c] = (T)rhs[n];
+            idv[c] = invd[n];
+            qc[c] = (ai + 1) + CB * (aj + 1) + CB * CB * (ak + 1);
+            av[c] = act;
+        }
+        prolong_cube<T, TP, NT>(g, fc, i0, j0, k0, ex, ey, ez);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int t = threadIdx.x + NT * c;
+            const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
+            const T *cb = fc.cube + qc[c];
+            const T ec = cb[0];
+            T ae = dg[c] * ec;
+            ae -= f6[c][0] * cb[-1];
+            ae -= f6[c][1] * cb[1];
+            ae -= f6[c][2] * cb[-CB];
+            ae -= f6[c][3] * cb[CB];
+            ae -= f6[c][4] * cb[-CB * CB];
+            ae -= f6[c][5] * cb[CB * CB];
+            const bool act = av[c];
+            e0[c] = act ? ec : T(0);
+            L.y[PAD + t] = act ? rh[c] - ae : T(0);
+            L.dinv[t] = act ? idv[c] : T(0);
+            L.wx[PAD + t] = act && li + 1 < ex ? f6[c][1] : T(0);
+            L.wy[PAD + t] = act && lj + 1 < ey ? f6[c][3] : T(0);
+            L.wz[PAD + t] = act && lk + 1 < ez ? f6[c][5] : T(0);
+        }
+    } else {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int t = threadIdx.x + NT * c;
@@ -283,6 +386,7 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         L.wx[PAD + t] = act && li + 1 < ex ? fxp : T(0);
         L.wy[PAD + t] = act && lj + 1 < ey ? fyp : T(0);
         L.wz[PAD + t] = act && lk + 1 < ez ? fzp : T(0);
+    }
     }
     __syncthreads();
     if (SW == 1 && threadIdx.x < 64) {
@@ -337,6 +441,25 @@ __global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict
     __shared__ SmoothLds<T> lds;
     if (done && *done) return;
     bilu_step_body<T, TR, NT, SW>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds);
+}
+
+// The first post-smoothing step, whose e_old is the prolongated coarse
+// correction P xc (Eq. (12)): the prolongation runs inside the step (on the
+// block and its face neighbours), so it needs no launch of its own and the
+// correction d1 is never stored; the result equals prolongation followed by
+// k_bilu_step bit for bit.
+template <class T, class TR, int NT, int SW, class TP>
+__global__ __launch_bounds__(NT) void k_bilu_first(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
+                                                    const T *__restrict__ invd, const TR *__restrict__ rhs,
+                                                    const TP *__restrict__ P, const uint8_t *__restrict__ dm,
+                                                    const double *__restrict__ xc, T *__restrict__ enew,
+                                                    const int32_t *done)
+{
+    __shared__ SmoothLds<T> lds;
+    __shared__ T cube[CB * CB * CB];
+    if (done && *done) return;
+    bilu_step_body<T, TR, NT, SW, TP>(g, W, diag, invd, rhs, nullptr, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds,
+                                      FromCoarse<T, TP>{P, dm, xc, cube});
 }
 
 // Batched step `s` of `steps` for every instance.  `post` selects the
@@ -420,6 +543,79 @@ void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR
         prev = out;
     }
     if (timed) prof_end(c);
+}
+
+// `steps` block-ILU(0) Richardson steps on A e = rhs from e = P xc (the
+// prolongated coarse correction, Eq. (12)), the first with the prolongation
+// inside it.  Timing (cams_profile) brackets the later steps, which are
+// k_bilu_step launches.
+template <class T, class TR, class TP>
+void bilu_smooth_from_coarse(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR *rhs, T *e, T *scratch,
+                             int steps, const int32_t *done, const TP *P)
+{
+    if (steps <= 0) return;
+    const int nb = num_sblocks(c->g);
+    T *buf[2] = {e, scratch};
+    const bool in_regs = nb <= resident_workgroups((const void *)k_bilu_first<T, TR, kSmoothThreads, 1, TP>,
+                                                   kSmoothThreads);
+    const double n = (double)c->g.N;
+    const double bytes = (steps - 1) * n * ((double)sizeof(TR) + 7.0 * sizeof(T));
+    const bool timed = c->prof_kernel == CAMS_PROF_SMOOTH_STEP && c->prof_iter % kProfEvery == 0 && steps > 1;
+    T *out = buf[(steps - 1) & 1];
+    if (in_regs)
+        k_bilu_first<T, TR, kSmoothThreads, 1, TP><<<nb, kSmoothThreads, 0, c->stream>>>(
+            c->g, W, diag, invd, rhs, P, c->a.dmask, c->a.xc, out, done);
+    else
+        k_bilu_first<T, TR, kSmoothThreadsMany, 0, TP><<<nb, kSmoothThreadsMany, 0, c->stream>>>(
+            c->g, W, diag, invd, rhs, P, c->a.dmask, c->a.xc, out, done);
+    const T *prev = out;
+    if (timed) prof_begin(c, bytes, steps - 1);
+    const bool regs_step = nb <= resident_workgroups((const void *)k_bilu_step<T, TR, kSmoothThreads, 1>,
+                                                     kSmoothThreads);
+    for (int s = 1; s < steps; ++s) {
+        out = buf[(steps - 1 - s) & 1];
+        if (regs_step)
+            k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, invd, rhs,
+                                                                                        prev, out, done);
+        else
+            k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(
+                c->g, W, diag, invd, rhs, prev, out, done);
+        prev = out;
+    }
+    if (timed) prof_end(c);
+}
+
+// Whether the first post-smoothing step takes the prolongation: when every
+// block of the grid is resident at once (the launch is latency-bound and one
+// launch less pays); on larger grids a separate prolongation is cheaper than
+// prolongating each block's face neighbours again.
+bool bilu_first_fused(cams_ctx *c)
+{
+    const int nb = num_sblocks(c->g);
+    const void *k;
+    if (c->opt.precision == CAMS_FP64)
+        k = (const void *)k_bilu_first<double, double, kSmoothThreads, 1, double>;
+    else if (c->opt.precision == CAMS_MIXED_BF16)
+        k = (const void *)k_bilu_first<float, float, kSmoothThreads, 1, uint16_t>;
+    else
+        k = (const void *)k_bilu_first<float, float, kSmoothThreads, 1, float>;
+    return nb <= resident_workgroups(k, kSmoothThreads);
+}
+
+void launch_bilu_smooth_from_coarse(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done)
+{
+    bilu_smooth_from_coarse<double, double, double>(c, c->a.W, c->a.diag, c->a.invd, rhs, e, c->a.z, steps, done,
+                                                    c->a.P);
+}
+
+void launch_bilu_smooth32_from_coarse(cams_ctx *c, const float *rhs, float *e, int steps, const int32_t *done)
+{
+    if (c->opt.precision == CAMS_MIXED_BF16)
+        bilu_smooth_from_coarse<float, float, uint16_t>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf,
+                                                        steps, done, c->a.Pbf);
+    else
+        bilu_smooth_from_coarse<float, float, float>(c, c->a.W32, c->a.diag32, c->a.invd32, rhs, e, c->a.zf, steps,
+                                                     done, c->a.P32);
 }
 
 // e = result of `steps` block-ILU(0) Richardson steps on A e = rhs from e =
