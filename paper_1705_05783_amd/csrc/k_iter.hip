@@ -362,7 +362,10 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const InstDev *__restrict_
     }
 }
 
-// Work item = (instance, owner box); batches without pre-smoothing.
+// Work item = (instance, owner box); batches without pre-smoothing.  The
+// batch's boxes are as small as 4^3 cells, so 256 threads per box (the sums
+// then group the cells differently from the single-problem form: the two
+// agree to rounding).
 template <class TA, class TP>
 __global__ __launch_bounds__(kBlock) void kb_residual_restrict(const InstDev *__restrict__ inst,
                                                                 const WorkItem *__restrict__ work,
