@@ -443,7 +443,10 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // col lane%16 (checked against a host GEMM by the parity tests).
 // K is staged through LDS KS = 32 columns at a time; the next stage's
 // operands are loaded into registers while the matrix cores work on the
-// current one (one LDS buffer, one register buffer).
+// current one (one LDS buffer, one register buffer).  With beta != 0 the
+// thread's 16 elements of C are loaded with the first stage, so their
+// latency hides behind the products (C is only written at the end, so an
+// aliased A or B is still read before it is overwritten).
 constexpr int KS = 32;
 
 __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, int lda, const double *B, int ldb,
@@ -473,6 +476,17 @@ __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, i
         }
     };
     fetch(0);
+    double cv[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = tm + wm + a * 16 + (lane >> 4) + 4 * v;
+                const int c = tn + wn + b * 16 + (lane & 15);
+                cv[a][b][v] = (beta != 0.0 && r < M && c < Nn) ? C[(size_t)r * ldc + c] : 0.0;
+            }
     for (int k0 = 0; k0 < K; k0 += KS) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
@@ -506,7 +520,7 @@ __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, i
                 const int c = tn + wn + b * 16 + (lane & 15);
                 if (r < M && c < Nn) {
                     const double prod = alpha * acc[a][b][v];
-                    C[(size_t)r * ldc + c] = beta == 0.0 ? prod : beta * C[(size_t)r * ldc + c] + prod;
+                    C[(size_t)r * ldc + c] = beta == 0.0 ? prod : beta * cv[a][b][v] + prod;
                 }
             }
 }
@@ -668,6 +682,68 @@ __global__ __launch_bounds__(kBlock) void k_copy2d(const double *__restrict__ sr
     if (t >= (size_t)rows * cols) return;
     const int r = (int)(t / cols), c = (int)(t % cols);
     dst[(size_t)r * ldd + c] = src[(size_t)r * lds + c];
+}
+
+// ---- products with the off-diagonal plane blocks of the block-tridiagonal
+// coarse operator.  Node (a, b) of one coarse z-plane couples only with the
+// nodes (a + da, b + db), |da|, |db| <= 1, of the adjacent planes (the
+// 27-point coarse stencil; every other entry of A_c is exactly zero), so a
+// product with such a block sums 9 terms, in the fixed order q = 3 (db + 1)
+// + (da + 1), instead of m.
+
+// Plane-neighbour q of node r (nbx nodes per row of the plane), or -1.
+__device__ __forceinline__ int plane_nb(int r, int q, int nbx, int nby)
+{
+    const int a = r % nbx + (q % 3) - 1, b = r / nbx + (q / 3) - 1;
+    return (a >= 0 && a < nbx && b >= 0 && b < nby) ? a + nbx * b : -1;
+}
+
+// F (m x m) = L E: L = the block of A_c at (plane k, plane k - 1) (leading
+// dimension ldl), E (m x m).  One workgroup per (row r, 256 columns).
+__global__ __launch_bounds__(kBlock) void k_plane_left(double *__restrict__ F, const double *__restrict__ L, int ldl,
+                                                        const double *__restrict__ E, int m, int nbx, int nby)
+{
+    const int r = blockIdx.y;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int c = plane_nb(r, q, nbx, nby);
+        if (c >= 0) s += L[(size_t)r * ldl + c] * E[(size_t)c * m + j];
+    }
+    F[(size_t)r * m + j] = s;
+}
+
+// Uc (m x 9): the nonzeros of each column j of U (the block of A_c at
+// (plane k - 1, plane k), leading dimension ldu), Uc[j][q] = U[c_q(j)][j].
+__global__ __launch_bounds__(kBlock) void k_plane_cols(double *__restrict__ Uc, const double *__restrict__ U, int ldu,
+                                                        int m, int nbx, int nby)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 9 * m) return;
+    const int j = t / 9, q = t % 9;
+    const int c = plane_nb(j, q, nbx, nby);
+    Uc[t] = c >= 0 ? U[(size_t)c * ldu + j] : 0.0;
+}
+
+// Out (m x m) = X U (sub = 0) or Out -= X U (sub = 1), X (m x m), U given
+// by its column nonzeros Uc.  One thread per element.
+__global__ __launch_bounds__(kBlock) void k_plane_right(double *__restrict__ Out, const double *__restrict__ X,
+                                                         const double *__restrict__ Uc, int m, int nbx, int nby,
+                                                         int sub)
+{
+    const int r = blockIdx.y;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= m) return;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int c = plane_nb(j, q, nbx, nby);
+        if (c >= 0) s += X[(size_t)r * m + c] * Uc[(size_t)j * 9 + q];
+    }
+    double *o = Out + (size_t)r * m + j;
+    *o = sub ? *o - s : s;
 }
 
 // Batched coarse solve: rc = R r from the slot partials (work item = block
@@ -928,8 +1004,9 @@ static void blocktri_parts(const cams_ctx *c, double *&E, double *&Fk, double *&
 // A_c of an MSFE problem couples only nodes of adjacent z-planes (a basis
 // function vanishes on the vertex planes next to its own), so the coarse
 // operator is block tridiagonal by planes.  Factorisation by block
-// elimination: 2 Z dense m x m inversions and products on matrix cores
-// instead of one Nc x Nc inversion (Nc = Z m).
+// elimination: Z dense m x m inversions on matrix cores instead of one
+// Nc x Nc inversion (Nc = Z m); the products with the off-diagonal plane
+// blocks L_k, U_k use their 9-point sparsity.
 static void factor_blocktri(cams_ctx *c)
 {
     double *E, *Fk, *G;
@@ -942,17 +1019,20 @@ static void factor_blocktri(cams_ctx *c)
     auto D = [&](int k) { return Ac + (size_t)k * m * n + (size_t)k * m; };
     auto Lo = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k - 1) * m; };
     auto Up = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k + 1) * m; };
+    double *Uc = S + mm;   // column nonzeros of U_{k-1}, m x 9
+    const int nbx = c->g.nb[0], nby = c->g.nb[1];
+    const dim3 rows(cdiv(m, kBlock), m);
     for (int k = 0; k < Z; ++k) {
         k_copy2d<<<cdiv(mm, kBlock), kBlock, 0, c->stream>>>(D(k), n, S, m, m, m);
         if (k > 0) {
-            gemm(c, Fk + k * mm, m, Lo(k), n, E + (k - 1) * mm, m, m, m, m, 1.0, 0.0);   // F_k = L_k E_{k-1}
-            gemm_sub(c, S, m, Fk + k * mm, m, Up(k - 1), n, m, m, m);                    // S_k -= F_k U_{k-1}
+            // F_k = L_k E_{k-1}; S_k -= F_k U_{k-1}
+            k_plane_left<<<rows, kBlock, 0, c->stream>>>(Fk + k * mm, Lo(k), n, E + (k - 1) * mm, m, nbx, nby);
+            k_plane_cols<<<cdiv((size_t)9 * m, kBlock), kBlock, 0, c->stream>>>(Uc, Up(k - 1), n, m, nbx, nby);
+            k_plane_right<<<rows, kBlock, 0, c->stream>>>(S, Fk + k * mm, Uc, m, nbx, nby, 1);
         }
         inverse_nopiv(c, S, E + k * mm, m);
-        if (k > 0) {
-            // G_{k-1} = E_{k-1} U_{k-1} (E_{k-1} is final once S_k is formed)
-            gemm(c, G + (k - 1) * mm, m, E + (k - 1) * mm, m, Up(k - 1), n, m, m, m, 1.0, 0.0);
-        }
+        if (k > 0)   // G_{k-1} = E_{k-1} U_{k-1} (E_{k-1} is final once S_k is formed)
+            k_plane_right<<<rows, kBlock, 0, c->stream>>>(G + (k - 1) * mm, E + (k - 1) * mm, Uc, m, nbx, nby, 0);
     }
 }
 

@@ -44,6 +44,11 @@ def test_blocktri_coarse_operator_and_solve(torch):
     plane = np.arange(s.Nc) // m
     far = np.abs(plane[:, None] - plane[None, :]) > 1
     assert np.count_nonzero(Ac[far]) == 0   # block tridiagonal over coarse z-planes
+    # and within the coupling of adjacent planes, 9-point: the plane products use it
+    node = np.arange(s.Nc) % m
+    ax, by = node % 24, node // 24
+    spread = (np.abs(ax[:, None] - ax[None, :]) > 1) | (np.abs(by[:, None] - by[None, :]) > 1)
+    assert np.count_nonzero(Ac[~far & spread]) == 0
     Ac_gpu = to_np(s.export(C.CAMS_ARR_AC)).reshape(s.Nc, s.Nc)
     assert rel_err(Ac_gpu, Ac) <= 1e-12
     rng = np.random.default_rng(5)
