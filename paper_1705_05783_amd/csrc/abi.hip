@@ -400,7 +400,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     put(L.add(t.regions.size() * sizeof(Region) + 16));  // 29 regions
     put(L.add(nc * 8 * 8));    // 30 restriction slot sums
     put(L.add((nc + 64) * 4));   // 31 iteration control
-    put(L.add(0));             // 32 (unused)
+    put(L.add(O.restriction == CAMS_R_FE ? nc * 216 * 8 : 0));   // 32 coarse-operator box partials
     const bool mixed = O.precision != CAMS_FP64;
     const size_t n4 = mixed ? (size_t)g.N * 4 : 0;
     put(L.add(3 * n4));        // 33 W32
@@ -470,6 +470,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.tab = (int32_t *)(w + off[28]);
     a.regions = (Region *)(w + off[29]);
     a.slots = (double *)(w + off[30]);
+    a.boxp = (double *)(w + off[32]);
     a.ictl = (int32_t *)(w + off[31]);
     a.W32 = (float *)(w + off[33]);
     a.diag32 = (float *)(w + off[34]);
@@ -516,6 +517,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     c->ws_bytes = bytes;
     c->has_ws = true;
     c->has_rock = c->has_basis = c->has_system = c->has_coarse = false;
+    c->ac_zeroed = false;
     c->nwells = 0;
     return CAMS_OK;
 }

@@ -58,6 +58,7 @@ struct Arrays {
     double *rc, *xc;  // Nc
     double *partial;  // reduction partials
     double *slots;    // Nc*8 restriction partials: slot s of owner box k
+    double *boxp;     // Nc*216 coarse-operator partials of the owner boxes (MSFE)
     double *scal;     // device scalars
     int32_t *piv;     // Nc
     int32_t *status;  // device error flags
@@ -165,6 +166,7 @@ struct cams_ctx {
     int nparts;             // reduction partial count
     int nwells;
     bool has_ws, has_rock, has_q, has_basis, has_system, has_coarse;
+    bool ac_zeroed;         // A_c outside the 27-point pattern zeroed in this workspace
     int cur_dp;
     double *host;           // pinned host scalars
     hipEvent_t ev[8];

@@ -25,6 +25,166 @@ namespace {
 
 constexpr int kNB = 64;   // LU panel width
 
+// ---- MSFE coarse operator A_c = P^T A P by owner boxes (Eq. (13)).  The
+// cells of owner box L (the cells whose lower bracketing node is L) share
+// their 8 bracketing nodes I = L + s, s in {0,1}^3.  For such a cell i,
+// (A P_J)(i) = sum over the stencil points m of A_im P_J(m) is nonzero only
+// for J = L + u with u in {0,1}^3 or one coordinate of u in {-1, 2} (the
+// nodes of i and of its six neighbours; 32 values), and P_I(i) (A P_J)(i)
+// contributes to A_c[I][J] with J - I = d in {-1,0,1}^3.  Stage 1: one
+// workgroup per box forms the 160 reachable (s, d) sums over the box's cells
+// in a fixed order, boxp[L][27 s + d]; stage 2 adds the
+// 8 boxes around each node in a fixed order.  Deterministic; each cell and
+// its stencil are read once instead of once per node whose support holds it.
+constexpr int kOpThreads = 512;
+
+__device__ __forceinline__ constexpr int u_index(int ux, int uy, int uz) { return (ux + 1) + 4 * (uy + 1) + 16 * (uz + 1); }
+
+__device__ __forceinline__ constexpr bool u_reach(int ux, int uy, int uz)
+{
+    // at most one coordinate outside {0, 1}, and that one in {-1, 2}
+    const int out = (ux < 0 || ux > 1) + (uy < 0 || uy > 1) + (uz < 0 || uz > 1);
+    return out <= 1 && ux >= -1 && ux <= 2 && uy >= -1 && uy <= 2 && uz >= -1 && uz <= 2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(double *__restrict__ a, size_t n)
+{
+    const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) a[t] = 0.0;
+}
+
+__global__ __launch_bounds__(kOpThreads) void k_coarse_box(GridDev g, const double *__restrict__ W,
+                                                            const double *__restrict__ diag,
+                                                            const uint8_t *__restrict__ dm,
+                                                            const double *__restrict__ P, double *__restrict__ boxp)
+{
+    // The 160 reachable (s, d) pairs are reduced over the box's cells 16 at
+    // a time: every thread writes its cell's 16 products to LDS, then 32
+    // threads per pair add 16 cells each in order and combine their partial
+    // sums by DPP exchanges within rows of 16 and two lane reads.
+    constexpr int CH = 16, NPAIR = 160;
+    __shared__ double buf[CH][kOpThreads];
+    __shared__ double part[216];
+    __shared__ short pair_sd[NPAIR];
+    const int L = blockIdx.x;
+    const int la = L % g.nb[0], lb = (L / g.nb[0]) % g.nb[1], lc = L / (g.nb[0] * g.nb[1]);
+    const int x0 = g.ob[0][la], y0 = g.ob[1][lb], z0 = g.ob[2][lc];
+    const int ex = g.ob[0][la + 1] - x0, ey = g.ob[1][lb + 1] - y0, ez = g.ob[2][lc + 1] - z0;
+    const int m = ex * ey * ez;
+    for (int q = threadIdx.x; q < 216; q += kOpThreads) part[q] = 0.0;
+    if (threadIdx.x == 0) {
+        int p = 0;
+        for (int s = 0; s < 8; ++s)
+            for (int d = 0; d < 27; ++d) {
+                const int ux = (s & 1) + d % 3 - 1, uy = ((s >> 1) & 1) + (d / 3) % 3 - 1, uz = (s >> 2) + d / 9 - 1;
+                if (u_reach(ux, uy, uz)) pair_sd[p++] = (short)(s * 27 + d);
+            }
+    }
+    const double *Wa[3] = {W, W + g.N, W + 2 * g.N};
+    const int Lv[3] = {la, lb, lc};
+    for (int t0 = 0; t0 < m; t0 += kOpThreads) {   // uniform trip count: every thread takes part in the sums
+        const int t = t0 + threadIdx.x;
+        const bool act = t < m;
+        const int tt = act ? t : 0;
+        const int ci[3] = {x0 + tt % ex, y0 + (tt / ex) % ey, z0 + tt / (ex * ey)};
+        const int n = ci[0] + g.nx * (ci[1] + g.ny * ci[2]);
+        const bool keep = act && !dm[n];
+        double w[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const bool in = la + (s & 1) < g.nb[0] && lb + ((s >> 1) & 1) < g.nb[1] && lc + (s >> 2) < g.nb[2];
+            const double pv = P[(size_t)s * g.N + n];
+            w[s] = keep && in ? pv : 0.0;
+        }
+        double v[64];
+#pragma unroll
+        for (int q = 0; q < 64; ++q) v[q] = 0.0;
+        {
+            const double dg = diag[n];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) v[u_index(s & 1, (s >> 1) & 1, s >> 2)] += dg * P[(size_t)s * g.N + n];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int ext = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+            const int stride = a == 0 ? 1 : (a == 1 ? g.nx : g.sxy);
+#pragma unroll
+            for (int dir = -1; dir <= 1; dir += 2) {
+                const bool inside = dir < 0 ? ci[a] > 0 : ci[a] + 1 < ext;
+                const int nm = inside ? n + dir * stride : n;
+                const int cm = inside ? ci[a] + dir : ci[a];
+                const double coef = -(dir > 0 ? Wa[a][n] : Wa[a][nm]);
+                const bool ok = inside && !dm[nm];
+                const bool moved = g.lo[a][cm] != Lv[a];   // the neighbour's lower node is L + dir e_a
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int t3[3] = {s & 1, (s >> 1) & 1, s >> 2};
+                    const double val = ok ? coef * P[(size_t)s * g.N + nm] : 0.0;
+                    int us[3] = {t3[0], t3[1], t3[2]};
+                    v[u_index(us[0], us[1], us[2])] += moved ? 0.0 : val;
+                    us[a] += dir;
+                    v[u_index(us[0], us[1], us[2])] += moved ? val : 0.0;
+                }
+            }
+        }
+#pragma unroll
+        for (int chunk = 0; chunk < NPAIR / CH; ++chunk) {
+            int p = 0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+#pragma unroll
+                for (int d = 0; d < 27; ++d) {
+                    const int ux = (s & 1) + d % 3 - 1, uy = ((s >> 1) & 1) + (d / 3) % 3 - 1,
+                              uz = (s >> 2) + d / 9 - 1;
+                    if (!u_reach(ux, uy, uz)) continue;   // resolved at compile time
+                    if (p / CH == chunk) buf[p % CH][threadIdx.x] = w[s] * v[u_index(ux, uy, uz)];
+                    ++p;
+                }
+            __syncthreads();
+            {
+                const int j = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < kOpThreads / 32; ++k) acc += buf[j][l32 + 32 * k];
+                acc += dpp_f64<0xB1>(acc);    // quad_perm [1,0,3,2]
+                acc += dpp_f64<0x4E>(acc);    // quad_perm [2,3,0,1]
+                acc += dpp_f64<0x141>(acc);   // row_half_mirror
+                acc += dpp_f64<0x140>(acc);   // row_mirror
+                const double lo = read_lane_f64(acc, 0) + read_lane_f64(acc, 16);
+                const double hi = read_lane_f64(acc, 32) + read_lane_f64(acc, 48);
+                if (l32 == 0) {
+                    const int q = pair_sd[chunk * CH + j];
+                    part[q] += (threadIdx.x & 32) ? hi : lo;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = threadIdx.x; q < 216; q += kOpThreads) boxp[(size_t)L * 216 + q] = part[q];
+}
+
+// A_c[I][I + d] = sum over s of boxp[I - s][27 s + d] (boxes inside the
+// grid), s in increasing order; entries outside the 27-point pattern are
+// left as they are (zero).
+__global__ __launch_bounds__(kBlock) void k_coarse_nodes(GridDev g, const double *__restrict__ boxp,
+                                                          double *__restrict__ Ac)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= 27 * g.Nc) return;
+    const int I = t / 27, d = t % 27;
+    const int ia = I % g.nb[0], ib = (I / g.nb[0]) % g.nb[1], ic = I / (g.nb[0] * g.nb[1]);
+    const int ja = ia + d % 3 - 1, jb = ib + (d / 3) % 3 - 1, jc = ic + d / 9 - 1;
+    if (ja < 0 || ja >= g.nb[0] || jb < 0 || jb >= g.nb[1] || jc < 0 || jc >= g.nb[2]) return;
+    double sum = 0.0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int la = ia - (s & 1), lb = ib - ((s >> 1) & 1), lc = ic - (s >> 2);
+        if (la < 0 || lb < 0 || lc < 0) continue;
+        sum += boxp[(size_t)(la + g.nb[0] * (lb + g.nb[1] * lc)) * 216 + s * 27 + d];
+    }
+    Ac[(size_t)I * g.Nc + (ja + g.nb[0] * (jb + g.nb[1] * jc))] = sum;
+}
+
 // Cell range of coarse row k along one axis.
 __device__ __forceinline__ void row_range(const GridDev &g, int axis, int a, int fe, int &lo, int &hi)
 {
@@ -811,8 +971,17 @@ __global__ __launch_bounds__(kBlock) void k_identity64(double *__restrict__ X, i
 
 void launch_coarse_operator(cams_ctx *c)
 {
-    k_coarse_row<<<c->g.Nc, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.dmask, c->a.P,
-                                                    c->opt.restriction == CAMS_R_FE, c->a.Ac);
+    const int n = c->g.Nc;
+    if (c->opt.restriction != CAMS_R_FE) {
+        k_coarse_row<<<n, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.dmask, c->a.P, 0, c->a.Ac);
+        return;
+    }
+    if (!c->ac_zeroed) {   // entries outside the 27-point pattern stay zero from now on
+        k_zero<<<cdiv((size_t)n * n, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, (size_t)n * n);
+        c->ac_zeroed = true;
+    }
+    k_coarse_box<<<n, kOpThreads, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.dmask, c->a.P, c->a.boxp);
+    k_coarse_nodes<<<cdiv((size_t)27 * n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.boxp, c->a.Ac);
 }
 
 // The per-instance part of the batched MSFE factorisation: working copy of
