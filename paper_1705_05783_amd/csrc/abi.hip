@@ -414,6 +414,10 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     put(L.add(n4));            // 41 d2f
     put(L.add(n4));            // 42 zf
     put(L.add((size_t)2 * ((nc + 63) / 64) * 64 * 64 * 8));   // 43 coarse LU block inverses
+    {   // 44 Gauss-Jordan GEMM descriptors (MSFE): 8 per 64-column panel of each inverted matrix
+        const size_t mats = c->blocktri ? (size_t)nb[2] : 1, dim = c->blocktri ? (size_t)nb[0] * nb[1] : nc;
+        put(L.add(O.restriction == CAMS_R_FE ? mats * ((dim + 63) / 64) * 8 * sizeof(GemmDesc) : 0));
+    }
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
         return CAMS_E_NOMEM;
@@ -483,6 +487,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.d2f = (float *)(w + off[41]);
     a.zf = (float *)(w + off[42]);
     a.tri = (double *)(w + off[43]);
+    a.gjd = (void *)(w + off[44]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -518,6 +523,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     c->has_ws = true;
     c->has_rock = c->has_basis = c->has_system = c->has_coarse = false;
     c->ac_zeroed = false;
+    c->gj_ready = false;
     c->nwells = 0;
     return CAMS_OK;
 }

@@ -59,6 +59,7 @@ struct Arrays {
     double *partial;  // reduction partials
     double *slots;    // Nc*8 restriction partials: slot s of owner box k
     double *boxp;     // Nc*216 coarse-operator partials of the owner boxes (MSFE)
+    void *gjd;        // GEMM descriptors of the Gauss-Jordan inverse (MSFE)
     double *scal;     // device scalars
     int32_t *piv;     // Nc
     int32_t *status;  // device error flags
@@ -167,6 +168,8 @@ struct cams_ctx {
     int nwells;
     bool has_ws, has_rock, has_q, has_basis, has_system, has_coarse;
     bool ac_zeroed;         // A_c outside the 27-point pattern zeroed in this workspace
+    bool gj_ready;          // Gauss-Jordan descriptors uploaded for this workspace
+    std::vector<int> gj_launch;   // per GEMM launch of the inverse: offset, count, tiles
     int cur_dp;
     double *host;           // pinned host scalars
     hipEvent_t ev[8];

@@ -592,6 +592,81 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
     trsm_body(F, n, j0, nb, B, ldb, col0, ncols, upper, blockIdx.x);
 }
 
+// ---- Gauss-Jordan inverse of an MSFE coarse matrix (symmetric positive
+// definite, so the pivots are those of an unpivoted LU and stay positive):
+// sweeps over 64-column panels J with D = A[J,J]:
+//   A[J,J] <- D^-1,  A[J,~J] <- D^-1 A[J,~J],  A[~J,J] <- -A[~J,J] D^-1,
+//   A[~J,~J] <- A[~J,~J] - A[~J,J]_old D^-1 A[J,~J]_old;
+// after the last panel A holds its inverse (2 n^3 flop, as LU plus inverse).
+// Three launches per panel: the pivot block inverse (with the copy of the
+// old column block), the two panel products (one launch), the update.
+
+// Workgroup 0: D^-1 of the nb x nb pivot block (padded to 64 x 64 with the
+// identity) by the same sweep on single entries, 4 x 4 entries per thread,
+// pivot row and column through LDS (two buffers, one barrier per pivot);
+// writes it into A[J,J].  Workgroups 1..: Cb[i][c] = A[i][j0 + c] for the
+// rows i outside J.
+__global__ __launch_bounds__(kBlock) void k_gj_pivot(double *__restrict__ A, int n, int j0, int nb,
+                                                      double *__restrict__ Cb, int32_t *status)
+{
+    if (blockIdx.x > 0) {
+        const size_t t = (size_t)(blockIdx.x - 1) * kBlock + threadIdx.x;
+        if (t >= (size_t)(n - nb) * nb) return;
+        const int rr = (int)(t / nb), cc = (int)(t % nb);
+        const int i = rr < j0 ? rr : rr + nb;
+        Cb[(size_t)i * nb + cc] = A[(size_t)i * n + j0 + cc];
+        return;
+    }
+    __shared__ double colk[2][kNB], rowk[2][kNB];
+    const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+    double a[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = 4 * ti + r, j = 4 * tj + c;
+            a[r][c] = (i < nb && j < nb) ? A[(size_t)(j0 + i) * n + j0 + j] : (i == j ? 1.0 : 0.0);
+        }
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) {
+        const int kg = k >> 2, kr = k & 3, b = k & 1;
+        if (tj == kg)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) colk[b][4 * ti + r] = a[r][kr];
+        if (ti == kg)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rowk[b][4 * tj + c] = a[kr][c];
+        __syncthreads();
+        double p = rowk[b][k];
+        if (!(p > 0.0 && p < 1e300)) {   // not positive definite (or not finite)
+            bad = true;
+            p = 1.0;
+        }
+        const double ip = 1.0 / p;
+        double ck[4], rk[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ck[r] = colk[b][4 * ti + r] * ip;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rk[c] = rowk[b][4 * tj + c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const bool onrow = ti == kg && r == kr, oncol = tj == kg && c == kr;
+                a[r][c] = onrow ? (oncol ? ip : a[r][c] * ip) : (oncol ? -a[r][c] * ip : a[r][c] - ck[r] * rk[c]);
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = 4 * ti + r, j = 4 * tj + c;
+            if (i < nb && j < nb) A[(size_t)(j0 + i) * n + j0 + j] = a[r][c];
+        }
+    if (bad && threadIdx.x == 0) atomicOr(status, F_SINGULAR_COARSE);
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // C (M x Nn, ldc) = alpha A (M x K, lda) B (K x Nn, ldb) + beta C; row-major.
@@ -997,9 +1072,13 @@ void launch_coarse_factor_prepare(cams_ctx *c)
     k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, c->a.Ainv);
 }
 
-// The launches of the batched factorisation and inverse; each step mirrors
-// the single-instance MSFE sequence of launch_coarse_factor, so every
-// instance gets the same operations in the same order.
+// The launches of the batched MSFE factorisation and inverse: unpivoted
+// blocked LU by 64-column panels (diagonal block factorised and its two
+// triangles inverted by one workgroup; L21 = A21 U11^-1, U12 = L11^-1 A12
+// and A22 -= L21 U12 as MFMA products), then X = U^-1 L^-1 by block
+// substitutions; every launch covers the same step of all instances.  (The
+// single-instance path inverts by Gauss-Jordan sweeps instead; the two agree
+// to rounding.)
 void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan)
 {
     plan = BatchLuPlan();
@@ -1106,53 +1185,77 @@ void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDes
     }
 }
 
-// In-place unpivoted blocked LU of the n x n matrix F (leading dimension n;
-// MSFE: symmetric positive definite) and X = F^-1 (leading dimension n).
-// Per 64-column panel the diagonal block is factorised in LDS and its two
-// triangles are inverted (stored in `tri`); L21 = A21 U11^-1 and U12 =
-// L11^-1 A12 are in-place MFMA products and A22 -= L21 U12.  The inverse
-// follows by block substitutions with the stored triangle inverses.
-static void inverse_nopiv(cams_ctx *c, double *F, double *X, int n)
+// Descriptors of the two GEMM launches of every panel of the Gauss-Jordan
+// sweep of A (n x n, leading dimension n); Cb holds the old column block
+// (row stride nb).  Each launch entry of L is (offset, count, tiles).
+static void gj_plan(double *A, int n, double *Cb, std::vector<GemmDesc> &d, std::vector<int> &L)
 {
-    const size_t nn = (size_t)n * n;
-    double *tri = c->a.tri;
-    const int npan = (n + kNB - 1) / kNB;
-    k_identity64<<<cdiv((size_t)2 * npan * kNB * kNB, kBlock), kBlock, 0, c->stream>>>(tri, 2 * npan);
-    for (int b = 0; b < npan; ++b) {
-        const int j0 = b * kNB;
-        const int nb = n - j0 < kNB ? n - j0 : kNB;
-        const int rest = n - j0 - nb;
-        double *Linv = tri + (size_t)(2 * b) * kNB * kNB, *Uinv = Linv + kNB * kNB;
-        k_lu_diag_inv<<<1, kBlock, 0, c->stream>>>(F, n, j0, nb, c->a.status, Linv, Uinv);
-        if (rest > 0) {
-            double *A21 = F + (size_t)(j0 + nb) * n + j0, *A12 = F + (size_t)j0 * n + j0 + nb;
-            gemm(c, A21, n, A21, n, Uinv, kNB, rest, nb, nb, 1.0, 0.0);
-            gemm(c, A12, n, Linv, kNB, A12, n, nb, rest, nb, 1.0, 0.0);
-            gemm_sub(c, F + (size_t)(j0 + nb) * n + j0 + nb, n, A21, n, A12, n, rest, rest, nb);
+    std::vector<GemmDesc> v;
+    auto add = [&](double *C, const double *Aop, int lda, const double *B, int M, int N, int K, double al,
+                   double be) {
+        if (M <= 0 || N <= 0 || K <= 0) return;
+        v.push_back(GemmDesc{C, Aop, B, n, lda, n, M, N, K, al, be, (int)cdiv(N, 64), 0});
+    };
+    auto flush = [&]() {
+        int tiles = 0;
+        for (GemmDesc &g : v) {
+            g.tile0 = tiles;
+            tiles += g.tiles_n * (int)cdiv(g.M, 64);
         }
+        L.push_back((int)d.size());
+        L.push_back((int)v.size());
+        L.push_back(tiles);
+        d.insert(d.end(), v.begin(), v.end());
+        v.clear();
+    };
+    for (int j0 = 0; j0 < n; j0 += kNB) {
+        const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
+        const double *Dq = A + (size_t)j0 * n + j0;
+        double *rowJ = A + (size_t)j0 * n;
+        // A[J,~J] <- D^-1 A[J,~J] (in place: a workgroup owns whole columns);
+        // A[~J,J] <- -A[~J,J] D^-1 (in place: a workgroup owns whole rows)
+        add(rowJ, Dq, n, rowJ, nb, j0, nb, 1.0, 0.0);
+        add(rowJ + j0 + nb, Dq, n, rowJ + j0 + nb, nb, rest, nb, 1.0, 0.0);
+        add(A + j0, A + j0, n, Dq, j0, nb, nb, -1.0, 0.0);
+        add(A + (size_t)(j0 + nb) * n + j0, A + (size_t)(j0 + nb) * n + j0, n, Dq, rest, nb, nb, -1.0, 0.0);
+        flush();
+        // A[~J,~J] -= Cb[~J] A[J,~J]
+        const int r0[2] = {0, j0 + nb}, rn[2] = {j0, rest};
+        for (int u = 0; u < 2; ++u)
+            for (int w = 0; w < 2; ++w)
+                add(A + (size_t)r0[u] * n + r0[w], Cb + (size_t)r0[u] * nb, nb, rowJ + r0[w], rn[u], rn[w], nb, -1.0,
+                    1.0);
+        flush();
     }
-    // X = U^-1 L^-1 by block substitutions (all MFMA products)
-    k_identity_piv<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n);
-    k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, X);
-    // (X = L^-1 is lower triangular: at panel b only its first j0 + nb
-    // columns are nonzero, so the products stop there)
-    for (int b = 0; b < npan; ++b) {
-        const int j0 = b * kNB;
-        const int nb = n - j0 < kNB ? n - j0 : kNB;
-        const int rest = n - j0 - nb;
-        const double *Linv = tri + (size_t)(2 * b) * kNB * kNB;
-        double *Xb = X + (size_t)j0 * n;
-        gemm(c, Xb, n, Linv, kNB, Xb, n, nb, j0 + nb, nb, 1.0, 0.0);
-        if (rest > 0) gemm_sub(c, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, Xb, n, rest,
-                               j0 + nb, nb);
-    }
-    for (int b = npan - 1; b >= 0; --b) {
-        const int j0 = b * kNB;
-        const int nb = n - j0 < kNB ? n - j0 : kNB;
-        const double *Uinv = tri + (size_t)(2 * b + 1) * kNB * kNB;
-        double *Xb = X + (size_t)j0 * n;
-        gemm(c, Xb, n, Uinv, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
-        if (j0 > 0) gemm_sub(c, X, n, F + j0, n, Xb, n, j0, n, nb);
+}
+
+// The descriptors of every matrix the factorisation inverts, uploaded once
+// per workspace (the matrices live at fixed places in it).
+static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m, double *Cb)
+{
+    if (c->gj_ready) return;
+    std::vector<GemmDesc> d;
+    c->gj_launch.clear();
+    for (double *A : mats) gj_plan(A, m, Cb, d, c->gj_launch);
+    if (!d.empty())
+        CAMS_HIP(hipMemcpyAsync(c->a.gjd, d.data(), d.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, c->stream));
+    CAMS_HIP(hipStreamSynchronize(c->stream));   // d is a local buffer
+    c->gj_ready = true;
+}
+
+// In-place inverse of matrix `mat` (the mat-th of gj_prepare's list), m x m.
+static void inverse_gj(cams_ctx *c, double *A, int m, int mat, double *Cb)
+{
+    const int panels = (m + kNB - 1) / kNB;
+    const GemmDesc *dd = (const GemmDesc *)c->a.gjd;
+    for (int p = 0; p < panels; ++p) {
+        const int j0 = p * kNB, nb = std::min(kNB, m - j0);
+        k_gj_pivot<<<1 + cdiv((size_t)(m - nb) * nb, kBlock), kBlock, 0, c->stream>>>(A, m, j0, nb, Cb,
+                                                                                       c->a.status);
+        for (int h = 0; h < 2; ++h) {
+            const int *e = &c->gj_launch[3 * (2 * (mat * panels + p) + h)];
+            if (e[1] > 0) kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+        }
     }
 }
 
@@ -1184,14 +1287,18 @@ static void factor_blocktri(cams_ctx *c)
     const int n = c->g.Nc;
     const size_t mm = (size_t)m * m;
     const double *Ac = c->a.Ac;
-    double *S = c->a.work;
     auto D = [&](int k) { return Ac + (size_t)k * m * n + (size_t)k * m; };
     auto Lo = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k - 1) * m; };
     auto Up = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k + 1) * m; };
-    double *Uc = S + mm;   // column nonzeros of U_{k-1}, m x 9
+    double *Uc = c->a.work;         // column nonzeros of U_{k-1}, m x 9
+    double *Cb = Uc + 9 * (size_t)m;   // old column block of the inverse's panel
     const int nbx = c->g.nb[0], nby = c->g.nb[1];
     const dim3 rows(cdiv(m, kBlock), m);
+    std::vector<double *> mats;
+    for (int k = 0; k < Z; ++k) mats.push_back(E + k * mm);
+    gj_prepare(c, mats, m, Cb);
     for (int k = 0; k < Z; ++k) {
+        double *S = E + k * mm;   // S_k, inverted in place into E_k
         k_copy2d<<<cdiv(mm, kBlock), kBlock, 0, c->stream>>>(D(k), n, S, m, m, m);
         if (k > 0) {
             // F_k = L_k E_{k-1}; S_k -= F_k U_{k-1}
@@ -1199,7 +1306,7 @@ static void factor_blocktri(cams_ctx *c)
             k_plane_cols<<<cdiv((size_t)9 * m, kBlock), kBlock, 0, c->stream>>>(Uc, Up(k - 1), n, m, nbx, nby);
             k_plane_right<<<rows, kBlock, 0, c->stream>>>(S, Fk + k * mm, Uc, m, nbx, nby, 1);
         }
-        inverse_nopiv(c, S, E + k * mm, m);
+        inverse_gj(c, S, m, k, Cb);
         if (k > 0)   // G_{k-1} = E_{k-1} U_{k-1} (E_{k-1} is final once S_k is formed)
             k_plane_right<<<rows, kBlock, 0, c->stream>>>(G + (k - 1) * mm, E + (k - 1) * mm, Uc, m, nbx, nby, 0);
     }
@@ -1238,9 +1345,10 @@ void launch_coarse_factor(cams_ctx *c)
         factor_blocktri(c);
         return;
     }
-    if (!pivoting) {
-        k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
-        inverse_nopiv(c, F, X, n);
+    if (!pivoting) {   // Gauss-Jordan in place in X, the old column blocks in F
+        gj_prepare(c, {X}, n, F);
+        k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, X, nn);
+        inverse_gj(c, X, n, 0, F);
         return;
     }
     k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
