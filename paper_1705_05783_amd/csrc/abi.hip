@@ -725,7 +725,8 @@ static void enqueue_iteration(cams_ctx *c, int it)
     // the same iterates, e = d1 + d2, without forming r1.  The correction
     // folded into the next residual is then d0 + e.
     // Without pre-smoothing the restriction acts on the new residual and is
-    // computed by the residual kernel itself (partials per owner box).
+    // computed by the residual kernel itself (partials per owner box); the
+    // stopping test runs with the coarse solve.
     const int flat_parts = (c->g.N + kBlock - 1) / kBlock;
     if (O.precision != CAMS_FP64) {
         // FP64 residual and update; FP32 corrections (iterative refinement)

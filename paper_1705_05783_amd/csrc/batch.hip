@@ -141,17 +141,13 @@ BatchLaunch L(const cams_batch *b, int which, bool prime = false)
 void enqueue_batch_iteration(cams_batch *b, int par, bool prime = false)
 {
     const int count = (int)b->ctx.size();
+    launch_batch_residual(L(b, L_FLAT, prime), par, b->mixed, b->n_pre > 0);
+    if (!prime) launch_batch_finalize(b->inst, count, b->stream);
     if (b->n_pre > 0) {
-        launch_batch_residual(L(b, L_FLAT, prime), par, b->mixed);
-        if (!prime) launch_batch_finalize(b->inst, count, b->stream);
         launch_batch_smooth(L(b, L_SBLOCK, prime), b->n_pre, 0, b->mixed, b->smooth_nt);
         launch_batch_sub_pre(L(b, L_FLAT, prime), b->mixed);
-        launch_batch_restrict(L(b, L_RESTRICT, prime), b->precision);
-    } else {
-        // residual and restriction in one pass (partials per owner box)
-        launch_batch_residual_restrict(L(b, L_RESTRICT, prime), par, b->mixed, b->precision);
-        if (!prime) launch_batch_finalize(b->inst, count, b->stream);
     }
+    launch_batch_restrict(L(b, L_RESTRICT, prime), b->precision);
     launch_batch_node_sum(L(b, L_NODES, prime));
     launch_batch_gemv(L(b, L_ROWS, prime));
     launch_batch_prolong(L(b, L_FLAT, prime), b->mixed, b->bf16);
@@ -406,7 +402,7 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
             d.bf16 = b->bf16;
             d.n_pre = c->opt.n_pre;
             d.n_post = c->opt.n_post;
-            d.nparts = c->opt.n_pre > 0 ? (c->g.N + kBlock - 1) / kBlock : c->g.Nc;
+            d.nparts = (c->g.N + kBlock - 1) / kBlock;
             d.maxit = c->opt.lin_maxit;
             d.rtol2 = c->opt.lin_rtol * c->opt.lin_rtol;
         }

@@ -263,10 +263,9 @@ void enqueue_coarse_operator(cams_ctx *c);   // A_c, smoother pivots, FP32 copie
 void enqueue_coarse(cams_ctx *c);
 
 // ---- batched iteration (one launch per kernel for all instances)
-void launch_batch_residual(const BatchLaunch &L, int par, bool mixed);
+void launch_batch_residual(const BatchLaunch &L, int par, bool mixed, bool pre);
 void launch_batch_finalize(const InstDev *inst, int count, hipStream_t st);
 void launch_batch_restrict(const BatchLaunch &L, int precision);
-void launch_batch_residual_restrict(const BatchLaunch &L, int par, bool mixed, int precision);
 void launch_batch_gather(const InstDev *inst, int count, BatchResult *out, hipStream_t st);
 void launch_batch_reset(const BatchLaunch &L);   // iteration state of every instance to its start
 void launch_batch_node_sum(const BatchLaunch &L);

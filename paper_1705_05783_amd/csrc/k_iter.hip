@@ -314,7 +314,8 @@ __device__ __forceinline__ Pending<TA, NV> pending_of(const InstDev &d, int par,
         return Pending<TA, NV>{d.a.dp[par], {post, post, post}, fold};
 }
 
-template <class TA>
+// NV = 2 with pre-smoothing (d0 and the post correction), else 1.
+template <class TA, int NV>
 __global__ __launch_bounds__(kBlock) void kb_residual(const InstDev *__restrict__ inst,
                                                        const WorkItem *__restrict__ work, const int32_t *nwork, int par)
 {
@@ -324,8 +325,7 @@ __global__ __launch_bounds__(kBlock) void kb_residual(const InstDev *__restrict_
         const WorkItem w = work[t];
         const InstDev &d = inst[w.inst];
         if (d.a.ictl[C_DONE]) continue;
-        // the flat residual serves the batches with pre-smoothing: d0 and the post correction
-        const Pending<TA, 2> v = pending_of<TA, 2>(d, par, d.a.ictl[C_IT] > 0);
+        const Pending<TA, NV> v = pending_of<TA, NV>(d, par, d.a.ictl[C_IT] > 0);
         float *rf = sizeof(TA) == 4 ? d.a.r1f : nullptr;
         residual_body(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, rf, d.a.partial, w.blk, sh);
     }
@@ -359,35 +359,6 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const InstDev *__restrict_
         else
             P = d.a.Pbf;
         restrict_box<TP>(d.g, d.a.dmask, P, d.fe, d.a.r, d.a.slots, w.blk, sh);
-    }
-}
-
-// Work item = (instance, owner box); batches without pre-smoothing.  The
-// batch's boxes are as small as 4^3 cells, so 256 threads per box (the sums
-// then group the cells differently from the single-problem form: the two
-// agree to rounding).
-template <class TA, class TP>
-__global__ __launch_bounds__(kBlock) void kb_residual_restrict(const InstDev *__restrict__ inst,
-                                                                const WorkItem *__restrict__ work,
-                                                                const int32_t *nwork, int par)
-{
-    __shared__ double sh[9 * (kBlock / 64)];
-    CAMS_FOR_ITEMS(t, nwork)
-    {
-        const WorkItem w = work[t];
-        const InstDev &d = inst[w.inst];
-        if (d.a.ictl[C_DONE]) continue;
-        const TP *P;
-        if constexpr (sizeof(TP) == 8)
-            P = d.a.P;
-        else if constexpr (sizeof(TP) == 4)
-            P = d.a.P32;
-        else
-            P = d.a.Pbf;
-        const Pending<TA, 1> v = pending_of<TA, 1>(d, par, d.a.ictl[C_IT] > 0);
-        float *rf = sizeof(TA) == 4 ? d.a.r1f : nullptr;
-        residual_restrict_box<TA, 1, TP, kBlock>(d.g, d.a.W, d.a.diag, d.a.r0, v, d.a.dp[par ^ 1], d.a.r, rf,
-                                              d.a.partial, d.a.dmask, P, d.fe, d.a.slots, w.blk, sh);
     }
 }
 
@@ -534,27 +505,21 @@ void launch_restrict(cams_ctx *c, const double *r)
         k_restrict<double><<<grid, kBlock, 0, c->stream>>>(g, a.dmask, a.P, fe, r, a.slots, a.ictl);
 }
 
-void launch_batch_residual(const BatchLaunch &L, int par, bool mixed)
+void launch_batch_residual(const BatchLaunch &L, int par, bool mixed, bool pre)
 {
-    if (mixed)
-        launch_persistent(kb_residual<float>, kBlock, L, L.inst, L.work, L.nwork, par);
+    if (mixed && pre)
+        launch_persistent(kb_residual<float, 2>, kBlock, L, L.inst, L.work, L.nwork, par);
+    else if (mixed)
+        launch_persistent(kb_residual<float, 1>, kBlock, L, L.inst, L.work, L.nwork, par);
+    else if (pre)
+        launch_persistent(kb_residual<double, 2>, kBlock, L, L.inst, L.work, L.nwork, par);
     else
-        launch_persistent(kb_residual<double>, kBlock, L, L.inst, L.work, L.nwork, par);
+        launch_persistent(kb_residual<double, 1>, kBlock, L, L.inst, L.work, L.nwork, par);
 }
 
 void launch_batch_finalize(const InstDev *inst, int count, hipStream_t st)
 {
     kb_finalize<<<count, kFinal, 0, st>>>(inst);
-}
-
-void launch_batch_residual_restrict(const BatchLaunch &L, int par, bool mixed, int precision)
-{
-    if (!mixed)
-        launch_persistent(kb_residual_restrict<double, double>, kBlock, L, L.inst, L.work, L.nwork, par);
-    else if (precision == CAMS_MIXED_BF16)
-        launch_persistent(kb_residual_restrict<float, uint16_t>, kBlock, L, L.inst, L.work, L.nwork, par);
-    else
-        launch_persistent(kb_residual_restrict<float, float>, kBlock, L, L.inst, L.work, L.nwork, par);
 }
 
 void launch_batch_restrict(const BatchLaunch &L, int precision)
