@@ -108,31 +108,57 @@ __device__ __forceinline__ float basis_load(const uint16_t *P, size_t i)
     return __uint_as_float((uint32_t)P[i] << 16);
 }
 
+// The loads of one cell's prolongation that do not depend on the coarse
+// vector (mask, node tables, basis), and the combination with the coarse
+// values (from device memory or a copy in LDS).
+template <class TP>
+struct ProlongIn {
+    typename BasisAcc<TP>::T w[8];
+    int a, b, c;
+    bool keep;
+};
+
+template <class TP>
+__device__ __forceinline__ ProlongIn<TP> prolong_load(const GridDev &g, const TP *__restrict__ P,
+                                                     const uint8_t *__restrict__ dm, int n, int i, int j, int k)
+{
+    ProlongIn<TP> in;
+    in.keep = !dm[n];
+    in.a = g.lo[0][i];
+    in.b = g.lo[1][j];
+    in.c = g.lo[2][k];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) in.w[t] = basis_load(P, (size_t)t * g.N + n);
+    return in;
+}
+
+template <class TP>
+__device__ __forceinline__ typename BasisAcc<TP>::T prolong_combine(const GridDev &g, const ProlongIn<TP> &in,
+                                                                    const double *xc)
+{
+    using A = typename BasisAcc<TP>::T;
+    double xv[8];
+    bool use[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int na = in.a + (t & 1), nb = in.b + ((t >> 1) & 1), nc = in.c + ((t >> 2) & 1);
+        const bool inn = na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2];
+        xv[t] = xc[inn ? node_index(g, na, nb, nc) : 0];
+        use[t] = inn;
+    }
+    A s = A(0);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) s = (use[t] && in.w[t] != A(0)) ? s + in.w[t] * (A)xv[t] : s;
+    return in.keep ? s : A(0);
+}
+
 template <class TP>
 __device__ __forceinline__ typename BasisAcc<TP>::T prolong_at(const GridDev &g, const TP *__restrict__ P,
                                                                const uint8_t *__restrict__ dm,
                                                                const double *__restrict__ xc, int n, int i, int j,
                                                                int k)
 {
-    using A = typename BasisAcc<TP>::T;
-    const bool keep = !dm[n];
-    const int a = g.lo[0][i], b = g.lo[1][j], cc = g.lo[2][k];
-    A w[8];
-    double xv[8];
-    bool use[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) w[t] = basis_load(P, (size_t)t * g.N + n);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const int na = a + (t & 1), nb = b + ((t >> 1) & 1), nc = cc + ((t >> 2) & 1);
-        const bool in = na < g.nb[0] && nb < g.nb[1] && nc < g.nb[2];
-        xv[t] = xc[in ? node_index(g, na, nb, nc) : 0];
-        use[t] = in;
-    }
-    A s = A(0);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) s = (use[t] && w[t] != A(0)) ? s + w[t] * (A)xv[t] : s;
-    return keep ? s : A(0);
+    return prolong_combine(g, prolong_load(g, P, dm, n, i, j, k), xc);
 }
 
 // Loop of a persistent batched kernel over its work items: blockIdx.x,

@@ -234,41 +234,78 @@ struct FromCoarse {
     const uint8_t *dm;
     const double *xc;
     T *cube;
+    double *xs;   // LDS room for kXcLds coarse values
 };
 
 constexpr int CB = SB + 2;    // cube edge: the block with one layer around it
+constexpr int kXcLds = 2048;  // coarse vectors up to this size are copied into LDS by the first step
 
 // e_old = P xc on the block's cells and on the cells across its six faces
 // (those outside the grid get 0), into the LDS cube at (li+1, lj+1, lk+1).
-template <class T, class TP, int NT>
-__device__ __forceinline__ void prolong_cube(const GridDev &g, const FromCoarse<T, TP> &fc, int i0, int j0, int k0,
-                                             int ex, int ey, int ez)
+// Split in two so that the caller can issue every load of the step before
+// the first wait: cube_load gathers each slot's mask, node tables and basis
+// values; cube_fill combines them with the coarse values (read from `xcs`,
+// an LDS copy of xc when it fits) and stores the cube.
+constexpr int kCubeSlots = ST + 6 * PAD;
+
+template <int NT>
+__device__ __forceinline__ void cube_slot(int q, int ex, int ey, int ez, int &ci, int &cj, int &ck, bool &need)
 {
-    for (int q = threadIdx.x; q < ST + 6 * PAD; q += NT) {
+    ci = cj = ck = 0;
+    need = false;
+    if (q < ST) {
+        ci = q & (SB - 1);
+        cj = (q >> 3) & (SB - 1);
+        ck = q >> 6;
+        need = ci < ex && cj < ey && ck < ez;
+    } else if (q < kCubeSlots) {
+        const int f = (q - ST) >> 6, u = (q - ST) & (SB - 1), v = ((q - ST) >> 3) & (SB - 1);
+        switch (f) {
+        case 0: ci = -1; cj = u; ck = v; need = u < ey && v < ez; break;
+        case 1: ci = ex; cj = u; ck = v; need = u < ey && v < ez; break;
+        case 2: ci = u; cj = -1; ck = v; need = u < ex && v < ez; break;
+        case 3: ci = u; cj = ey; ck = v; need = u < ex && v < ez; break;
+        case 4: ci = u; cj = v; ck = -1; need = u < ex && v < ey; break;
+        default: ci = u; cj = v; ck = ez; need = u < ex && v < ey; break;
+        }
+    }
+}
+
+template <class TP, int NT>
+struct CubeLoads {
+    static constexpr int R = (kCubeSlots + NT - 1) / NT;
+    ProlongIn<TP> in[R];
+    int idx[R];
+    bool need[R], inside[R];
+};
+
+template <class T, class TP, int NT>
+__device__ __forceinline__ void cube_load(const GridDev &g, const FromCoarse<T, TP> &fc, int i0, int j0, int k0,
+                                          int ex, int ey, int ez, CubeLoads<TP, NT> &cl)
+{
+#pragma unroll
+    for (int h = 0; h < CubeLoads<TP, NT>::R; ++h) {
         int ci, cj, ck;
         bool need;
-        if (q < ST) {
-            ci = q & (SB - 1);
-            cj = (q >> 3) & (SB - 1);
-            ck = q >> 6;
-            need = ci < ex && cj < ey && ck < ez;
-        } else {
-            const int f = (q - ST) >> 6, u = (q - ST) & (SB - 1), v = ((q - ST) >> 3) & (SB - 1);
-            switch (f) {
-            case 0: ci = -1; cj = u; ck = v; need = u < ey && v < ez; break;
-            case 1: ci = ex; cj = u; ck = v; need = u < ey && v < ez; break;
-            case 2: ci = u; cj = -1; ck = v; need = u < ex && v < ez; break;
-            case 3: ci = u; cj = ey; ck = v; need = u < ex && v < ez; break;
-            case 4: ci = u; cj = v; ck = -1; need = u < ex && v < ey; break;
-            default: ci = u; cj = v; ck = ez; need = u < ex && v < ey; break;
-            }
-        }
-        if (!need) continue;
+        cube_slot<NT>(threadIdx.x + h * NT, ex, ey, ez, ci, cj, ck, need);
         const int i = i0 + ci, j = j0 + cj, k = k0 + ck;
-        const bool in = i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
+        const bool in = need && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
         const int ii = in ? i : i0, jj = in ? j : j0, kk = in ? k : k0;
-        const T v = (T)prolong_at(g, fc.P, fc.dm, fc.xc, ii + g.nx * (jj + g.ny * kk), ii, jj, kk);
-        fc.cube[(ci + 1) + CB * (cj + 1) + CB * CB * (ck + 1)] = in ? v : T(0);
+        cl.in[h] = prolong_load(g, fc.P, fc.dm, ii + g.nx * (jj + g.ny * kk), ii, jj, kk);
+        cl.idx[h] = (ci + 1) + CB * (cj + 1) + CB * CB * (ck + 1);
+        cl.need[h] = need;
+        cl.inside[h] = in;
+    }
+}
+
+template <class T, class TP, int NT>
+__device__ __forceinline__ void cube_fill(const GridDev &g, const FromCoarse<T, TP> &fc,
+                                          const CubeLoads<TP, NT> &cl, const double *xcs)
+{
+#pragma unroll
+    for (int h = 0; h < CubeLoads<TP, NT>::R; ++h) {
+        const T v = (T)prolong_combine(g, cl.in[h], xcs);
+        if (cl.need[h]) fc.cube[cl.idx[h]] = cl.inside[h] ? v : T(0);
     }
 }
 
@@ -324,7 +361,27 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
             qc[c] = (ai + 1) + CB * (aj + 1) + CB * CB * (ak + 1);
             av[c] = act;
         }
-        prolong_cube<T, TP, NT>(g, fc, i0, j0, k0, ex, ey, ez);
+        // every global load of the step goes out here: the prolongation's
+        // tables and basis values, and the coarse vector (into LDS when it fits)
+        CubeLoads<TP, NT> cl;
+        cube_load<T, TP, NT>(g, fc, i0, j0, k0, ex, ey, ez, cl);
+        const bool xlds = g.Nc <= kXcLds;
+        if (xlds) {
+            constexpr int XR = (kXcLds + NT - 1) / NT;
+            double xv[XR];
+#pragma unroll
+            for (int h = 0; h < XR; ++h) {
+                const int q = threadIdx.x + h * NT;
+                xv[h] = q < g.Nc ? fc.xc[q] : 0.0;
+            }
+#pragma unroll
+            for (int h = 0; h < XR; ++h) {
+                const int q = threadIdx.x + h * NT;
+                if (q < g.Nc) fc.xs[q] = xv[h];
+            }
+            __syncthreads();
+        }
+        cube_fill<T, TP, NT>(g, fc, cl, xlds ? fc.xs : fc.xc);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -457,9 +514,10 @@ __global__ __launch_bounds__(NT) void k_bilu_first(GridDev g, const T *__restric
 {
     __shared__ SmoothLds<T> lds;
     __shared__ T cube[CB * CB * CB];
+    __shared__ double xs[kXcLds];
     if (done && *done) return;
     bilu_step_body<T, TR, NT, SW, TP>(g, W, diag, invd, rhs, nullptr, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds,
-                                      FromCoarse<T, TP>{P, dm, xc, cube});
+                                      FromCoarse<T, TP>{P, dm, xc, cube, xs});
 }
 
 // Batched step `s` of `steps` for every instance.  `post` selects the
