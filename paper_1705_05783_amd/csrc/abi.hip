@@ -416,7 +416,8 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     put(L.add((size_t)2 * ((nc + 63) / 64) * 64 * 64 * 8));   // 43 coarse LU block inverses
     {   // 44 Gauss-Jordan GEMM descriptors (MSFE): 8 per 64-column panel of each inverted matrix
         const size_t mats = c->blocktri ? (size_t)nb[2] : 1, dim = c->blocktri ? (size_t)nb[0] * nb[1] : nc;
-        put(L.add(O.restriction == CAMS_R_FE ? mats * ((dim + 63) / 64) * 8 * sizeof(GemmDesc) : 0));
+        put(L.add(O.restriction == CAMS_R_FE ? mats * ((dim + 63) / 64) * 12 * sizeof(GemmDesc) : 0));
+        put(L.add(O.restriction == CAMS_R_FE ? 2 * dim * 64 * 8 : 0));   // 45 saved column blocks
     }
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
@@ -488,6 +489,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.zf = (float *)(w + off[42]);
     a.tri = (double *)(w + off[43]);
     a.gjd = (void *)(w + off[44]);
+    a.gjcb = (double *)(w + off[45]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {

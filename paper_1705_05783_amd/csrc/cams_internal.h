@@ -60,6 +60,7 @@ struct Arrays {
     double *slots;    // Nc*8 restriction partials: slot s of owner box k
     double *boxp;     // Nc*216 coarse-operator partials of the owner boxes (MSFE)
     void *gjd;        // GEMM descriptors of the Gauss-Jordan inverse (MSFE)
+    double *gjcb;     // two saved column blocks of the Gauss-Jordan sweep (2 x 64 x matrix order)
     double *scal;     // device scalars
     int32_t *piv;     // Nc
     int32_t *status;  // device error flags

@@ -598,19 +598,21 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
 //   A[J,J] <- D^-1,  A[J,~J] <- D^-1 A[J,~J],  A[~J,J] <- -A[~J,J] D^-1,
 //   A[~J,~J] <- A[~J,~J] - A[~J,J]_old D^-1 A[J,~J]_old;
 // after the last panel A holds its inverse (2 n^3 flop, as LU plus inverse).
-// Three launches per panel: the pivot block inverse (with the copy of the
-// old column block), the two panel products (one launch), the update.
+// Three launches per panel: the panel products (one launch), the update of
+// the next panel's columns, and the rest of the update together with the
+// next panel's pivot-block inverse (and the copy of its old column block),
+// so that the sequential pivot inverse overlaps the matrix-core update.
 
 // Workgroup 0: D^-1 of the nb x nb pivot block (padded to 64 x 64 with the
 // identity) by the same sweep on single entries, 4 x 4 entries per thread,
 // pivot row and column through LDS (two buffers, one barrier per pivot);
 // writes it into A[J,J].  Workgroups 1..: Cb[i][c] = A[i][j0 + c] for the
 // rows i outside J.
-__global__ __launch_bounds__(kBlock) void k_gj_pivot(double *__restrict__ A, int n, int j0, int nb,
-                                                      double *__restrict__ Cb, int32_t *status)
+__device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j0, int nb, double *__restrict__ Cb,
+                                            int32_t *status, int blk)
 {
-    if (blockIdx.x > 0) {
-        const size_t t = (size_t)(blockIdx.x - 1) * kBlock + threadIdx.x;
+    if (blk > 0) {
+        const size_t t = (size_t)(blk - 1) * kBlock + threadIdx.x;
         if (t >= (size_t)(n - nb) * nb) return;
         const int rr = (int)(t / nb), cc = (int)(t % nb);
         const int i = rr < j0 ? rr : rr + nb;
@@ -671,6 +673,15 @@ __global__ __launch_bounds__(kBlock) void k_gj_pivot(double *__restrict__ A, int
         }
     if (bad && threadIdx.x == 0) atomicOr(status, F_SINGULAR_COARSE);
 }
+
+__global__ __launch_bounds__(kBlock) void k_gj_pivot(double *__restrict__ A, int n, int j0, int nb,
+                                                      double *__restrict__ Cb, int32_t *status)
+{
+    gj_pivot_wg(A, n, j0, nb, Cb, status, blockIdx.x);
+}
+
+// Number of workgroups of a pivot step: the inverse and the column copy.
+inline unsigned gj_pivot_wgs(int n, int nb) { return 1 + (unsigned)(((size_t)(n - nb) * nb + kBlock - 1) / kBlock); }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -792,6 +803,33 @@ __global__ __launch_bounds__(kBlock) void kb_gemm(const GemmDesc *__restrict__ d
     }
     const GemmDesc g = d[lo];
     const int t = blockIdx.x - g.tile0;
+    gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
+              (t % g.tiles_n) * 64);
+}
+
+// The update of one Gauss-Jordan panel (outside the next panel's columns)
+// and the next panel's pivot step in one launch: workgroup 0 inverts the
+// next pivot block, the next `pw - 1` copy its old column block, the others
+// are GEMM tiles of the update.  The next pivot block and its column block
+// are final before the launch (their part of the update ran just before), so
+// the sequential pivot inverse runs while the matrix cores update the rest.
+__global__ __launch_bounds__(kBlock) void k_gj_update_pivot(const GemmDesc *__restrict__ d, int nd, int pw,
+                                                             double *A, int n, int j0, int nb, double *Cb,
+                                                             int32_t *status)
+{
+    if ((int)blockIdx.x < pw) {
+        gj_pivot_wg(A, n, j0, nb, Cb, status, blockIdx.x);
+        return;
+    }
+    const int tile = blockIdx.x - pw;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc g = d[lo];
+    const int t = tile - g.tile0;
     gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
               (t % g.tiles_n) * 64);
 }
@@ -1190,10 +1228,14 @@ void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDes
     }
 }
 
-// Descriptors of the two GEMM launches of every panel of the Gauss-Jordan
-// sweep of A (n x n, leading dimension n); Cb holds the old column block
-// (row stride nb).  Each launch entry of L is (offset, count, tiles).
-static void gj_plan(double *A, int n, double *Cb, std::vector<GemmDesc> &d, std::vector<int> &L)
+// Descriptors of the three GEMM launches of every panel of the Gauss-Jordan
+// sweep of A (n x n, leading dimension n): the panel products; the update of
+// the next panel's columns; the rest of the update (which runs together with
+// the next pivot step).  Panel p saves its old column block in Cb[p & 1]
+// (row stride nb), so the next pivot step can fill the other buffer while
+// the update still reads this one.  Each launch entry of L is (offset,
+// count, tiles).
+static void gj_plan(double *A, int n, double *const Cb[2], std::vector<GemmDesc> &d, std::vector<int> &L)
 {
     std::vector<GemmDesc> v;
     auto add = [&](double *C, const double *Aop, int lda, const double *B, int M, int N, int K, double al,
@@ -1213,10 +1255,12 @@ static void gj_plan(double *A, int n, double *Cb, std::vector<GemmDesc> &d, std:
         d.insert(d.end(), v.begin(), v.end());
         v.clear();
     };
-    for (int j0 = 0; j0 < n; j0 += kNB) {
+    for (int p = 0, j0 = 0; j0 < n; ++p, j0 += kNB) {
         const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
+        const int nb2 = std::min(kNB, rest);   // next panel's width (0 after the last)
         const double *Dq = A + (size_t)j0 * n + j0;
         double *rowJ = A + (size_t)j0 * n;
+        const double *Cbp = Cb[p & 1];
         // A[J,~J] <- D^-1 A[J,~J] (in place: a workgroup owns whole columns);
         // A[~J,J] <- -A[~J,J] D^-1 (in place: a workgroup owns whole rows)
         add(rowJ, Dq, n, rowJ, nb, j0, nb, 1.0, 0.0);
@@ -1224,11 +1268,16 @@ static void gj_plan(double *A, int n, double *Cb, std::vector<GemmDesc> &d, std:
         add(A + j0, A + j0, n, Dq, j0, nb, nb, -1.0, 0.0);
         add(A + (size_t)(j0 + nb) * n + j0, A + (size_t)(j0 + nb) * n + j0, n, Dq, rest, nb, nb, -1.0, 0.0);
         flush();
-        // A[~J,~J] -= Cb[~J] A[J,~J]
+        // A[~J,~J] -= Cb[~J] A[J,~J]: first the next panel's columns, then the rest
         const int r0[2] = {0, j0 + nb}, rn[2] = {j0, rest};
         for (int u = 0; u < 2; ++u)
+            add(A + (size_t)r0[u] * n + j0 + nb, Cbp + (size_t)r0[u] * nb, nb, rowJ + j0 + nb, rn[u], nb2, nb, -1.0,
+                1.0);
+        flush();
+        const int c0[2] = {0, j0 + nb + nb2}, cn[2] = {j0, rest - nb2};
+        for (int u = 0; u < 2; ++u)
             for (int w = 0; w < 2; ++w)
-                add(A + (size_t)r0[u] * n + r0[w], Cb + (size_t)r0[u] * nb, nb, rowJ + r0[w], rn[u], rn[w], nb, -1.0,
+                add(A + (size_t)r0[u] * n + c0[w], Cbp + (size_t)r0[u] * nb, nb, rowJ + c0[w], rn[u], cn[w], nb, -1.0,
                     1.0);
         flush();
     }
@@ -1236,11 +1285,12 @@ static void gj_plan(double *A, int n, double *Cb, std::vector<GemmDesc> &d, std:
 
 // The descriptors of every matrix the factorisation inverts, uploaded once
 // per workspace (the matrices live at fixed places in it).
-static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m, double *Cb)
+static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m)
 {
     if (c->gj_ready) return;
     std::vector<GemmDesc> d;
     c->gj_launch.clear();
+    double *const Cb[2] = {c->a.gjcb, c->a.gjcb + (size_t)m * kNB};
     for (double *A : mats) gj_plan(A, m, Cb, d, c->gj_launch);
     if (!d.empty())
         CAMS_HIP(hipMemcpyAsync(c->a.gjd, d.data(), d.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, c->stream));
@@ -1249,17 +1299,27 @@ static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m, do
 }
 
 // In-place inverse of matrix `mat` (the mat-th of gj_prepare's list), m x m.
-static void inverse_gj(cams_ctx *c, double *A, int m, int mat, double *Cb)
+// Per panel: the panel products, the update of the next panel's columns,
+// then the rest of the update together with the next pivot step.
+static void inverse_gj(cams_ctx *c, double *A, int m, int mat)
 {
     const int panels = (m + kNB - 1) / kNB;
     const GemmDesc *dd = (const GemmDesc *)c->a.gjd;
+    double *const Cb[2] = {c->a.gjcb, c->a.gjcb + (size_t)m * kNB};
+    k_gj_pivot<<<gj_pivot_wgs(m, std::min(kNB, m)), kBlock, 0, c->stream>>>(A, m, 0, std::min(kNB, m), Cb[0],
+                                                                           c->a.status);
     for (int p = 0; p < panels; ++p) {
-        const int j0 = p * kNB, nb = std::min(kNB, m - j0);
-        k_gj_pivot<<<1 + cdiv((size_t)(m - nb) * nb, kBlock), kBlock, 0, c->stream>>>(A, m, j0, nb, Cb,
-                                                                                       c->a.status);
-        for (int h = 0; h < 2; ++h) {
-            const int *e = &c->gj_launch[3 * (2 * (mat * panels + p) + h)];
+        const int *e = &c->gj_launch[3 * 3 * (mat * panels + p)];
+        for (int h = 0; h < 2; ++h, e += 3)
             if (e[1] > 0) kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+        const int j1 = (p + 1) * kNB;
+        if (j1 < m) {
+            const int nb1 = std::min(kNB, m - j1);
+            const unsigned pw = gj_pivot_wgs(m, nb1);
+            k_gj_update_pivot<<<pw + e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1], (int)pw, A, m, j1, nb1,
+                                                                   Cb[(p + 1) & 1], c->a.status);
+        } else if (e[1] > 0) {
+            kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
         }
     }
 }
@@ -1295,13 +1355,12 @@ static void factor_blocktri(cams_ctx *c)
     auto D = [&](int k) { return Ac + (size_t)k * m * n + (size_t)k * m; };
     auto Lo = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k - 1) * m; };
     auto Up = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k + 1) * m; };
-    double *Uc = c->a.work;         // column nonzeros of U_{k-1}, m x 9
-    double *Cb = Uc + 9 * (size_t)m;   // old column block of the inverse's panel
+    double *Uc = c->a.work;   // column nonzeros of U_{k-1}, m x 9
     const int nbx = c->g.nb[0], nby = c->g.nb[1];
     const dim3 rows(cdiv(m, kBlock), m);
     std::vector<double *> mats;
     for (int k = 0; k < Z; ++k) mats.push_back(E + k * mm);
-    gj_prepare(c, mats, m, Cb);
+    gj_prepare(c, mats, m);
     for (int k = 0; k < Z; ++k) {
         double *S = E + k * mm;   // S_k, inverted in place into E_k
         k_copy2d<<<cdiv(mm, kBlock), kBlock, 0, c->stream>>>(D(k), n, S, m, m, m);
@@ -1311,7 +1370,7 @@ static void factor_blocktri(cams_ctx *c)
             k_plane_cols<<<cdiv((size_t)9 * m, kBlock), kBlock, 0, c->stream>>>(Uc, Up(k - 1), n, m, nbx, nby);
             k_plane_right<<<rows, kBlock, 0, c->stream>>>(S, Fk + k * mm, Uc, m, nbx, nby, 1);
         }
-        inverse_gj(c, S, m, k, Cb);
+        inverse_gj(c, S, m, k);
         if (k > 0)   // G_{k-1} = E_{k-1} U_{k-1} (E_{k-1} is final once S_k is formed)
             k_plane_right<<<rows, kBlock, 0, c->stream>>>(G + (k - 1) * mm, E + (k - 1) * mm, Uc, m, nbx, nby, 0);
     }
@@ -1350,10 +1409,10 @@ void launch_coarse_factor(cams_ctx *c)
         factor_blocktri(c);
         return;
     }
-    if (!pivoting) {   // Gauss-Jordan in place in X, the old column blocks in F
-        gj_prepare(c, {X}, n, F);
+    if (!pivoting) {   // Gauss-Jordan in place in X
+        gj_prepare(c, {X}, n);
         k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, X, nn);
-        inverse_gj(c, X, n, 0, F);
+        inverse_gj(c, X, n, 0);
         return;
     }
     k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
