@@ -1,19 +1,18 @@
 // Coarse level of the C-AMS solve (Sec. 3, Eqs. (7), (13)-(15)):
-//  - A_c = R A P_hat, one workgroup per coarse row (MSFV: the rows of the
-//    primal block; MSFE: the cells of the coarse node's basis support, each
-//    weighted by its basis value).  27 neighbouring coarse nodes per row are
-//    accumulated in LDS and reduced in a fixed order, so A_c is bitwise
-//    deterministic (no atomics).
-//  - restriction R r for the iteration (same ownership, one value per row);
-//  - LU by 64-column panels with the trailing update C -= A B on FP64
-//    matrix cores (v_mfma_f64_16x16x4f64, 64x64 tiles per workgroup):
-//    MSFV: partial pivoting, panel factorised by one workgroup;
-//    MSFE (symmetric positive definite): no interchanges, only the 64x64
-//    diagonal block is sequential, the row and column triangular solves of
-//    the panel are fully parallel;
-//  - the explicit inverse from the LU factors with the same kernels, so that
-//    every coarse solve of the iteration is one fully parallel GEMV instead
-//    of two latency-bound triangular sweeps.
+//  - A_c = R A P_hat: MSFE by owner boxes (each cell's stencil and basis
+//    read once, 160 sums per box, then the 8 boxes around each node); MSFV
+//    one workgroup per coarse row (the rows of the primal block).  Fixed
+//    reduction orders, no atomics: A_c is bitwise deterministic.
+//  - the explicit inverse, so that every coarse solve of the iteration is one
+//    fully parallel GEMV instead of two latency-bound triangular sweeps:
+//    MSFE (symmetric positive definite): Gauss-Jordan sweeps over 64-column
+//    panels, the products on FP64 matrix cores (v_mfma_f64_16x16x4f64,
+//    64x64 tiles per workgroup), the 64x64 pivot-block inverse overlapping
+//    the next update; MSFV: LU with partial pivoting by panels, then the
+//    inverse from the factors with the same kernels.  Large MSFE coarse grids
+//    are eliminated plane by plane (block tridiagonal).
+//  - the batched MSFE factorisation of many instances (blocked LU, every
+//    instance's step in one launch).
 #include "cams_internal.h"
 #include "dev_util.h"
 
@@ -410,42 +409,6 @@ __global__ __launch_bounds__(kBlock) void k_lu_panel_lds(double *__restrict__ A,
     }
 }
 
-// Unpivoted LU of the nb x nb diagonal block at (j0, j0), in LDS (MSFE:
-// the coarse operator is symmetric positive definite, so no pivoting is
-// needed).  A non-positive pivot is flagged.
-__device__ __forceinline__ void lu_diag_body(double *__restrict__ A, int n, int j0, int nb, int32_t *status)
-{
-    __shared__ double D[kNB][kNB + 1];
-    for (int t = threadIdx.x; t < nb * nb; t += kBlock) D[t / nb][t % nb] = A[(size_t)(j0 + t / nb) * n + j0 + t % nb];
-    __syncthreads();
-    // the trailing update of column c: thread (ty, tx) of a 16 x 16 grid takes
-    // rows c+1+ty+16u and columns c+1+tx+16v (no index division)
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    for (int c = 0; c < nb; ++c) {
-        double pv = D[c][c];
-        if (!(pv > 0.0)) {
-            if (threadIdx.x == 0) atomicOr(status, F_SINGULAR_COARSE);
-            pv = 1.0;
-        }
-        const double rp = 1.0 / pv;
-        __syncthreads();
-        for (int i = c + 1 + threadIdx.x; i < nb; i += kBlock) D[i][c] *= rp;
-        __syncthreads();
-        for (int i = c + 1 + ty; i < nb; i += 16) {
-            const double l = D[i][c];
-            for (int j = c + 1 + tx; j < nb; j += 16) D[i][j] -= l * D[c][j];
-        }
-        __syncthreads();
-    }
-    for (int t = threadIdx.x; t < nb * nb; t += kBlock) A[(size_t)(j0 + t / nb) * n + j0 + t % nb] = D[t / nb][t % nb];
-}
-
-__global__ __launch_bounds__(kBlock) void k_lu_diag_nopiv(double *__restrict__ A, int n, int j0, int nb,
-                                                           int32_t *status)
-{
-    lu_diag_body(A, n, j0, nb, status);
-}
-
 // Unpivoted LU of the diagonal block at (j0, j0) together with the inverses
 // of its two triangles (unit lower L, upper U; both padded with identity
 // beyond nb), in one workgroup.  Wave 0 factorises with one row per lane in
@@ -520,13 +483,6 @@ __device__ __forceinline__ void lu_diag_inv_body(double *__restrict__ A, int n, 
 #pragma unroll
         for (int r = 0; r < kNB; ++r) Uinv[r * kNB + lane] = x[r];
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_lu_diag_inv(double *__restrict__ A, int n, int j0, int nb,
-                                                         int32_t *status, double *__restrict__ Linv,
-                                                         double *__restrict__ Uinv)
-{
-    lu_diag_inv_body(A, n, j0, nb, status, Linv, Uinv);
 }
 
 // Apply the panel's interchanges to the columns outside [j0, j0+nb).
