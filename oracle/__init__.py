@@ -66,6 +66,8 @@ def lib():
         L.or_ilu0_create.argtypes = [P, P, P, P, P, P]
         L.or_ilu0_block_create.restype = P
         L.or_ilu0_block_create.argtypes = [P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_ilu0_block_create_shifted.restype = P
+        L.or_ilu0_block_create_shifted.argtypes = [P, P, P, P, P] + [ctypes.c_int] * 6
         L.or_ilu0_free.argtypes = [P]
         L.or_ilu0_nnz.restype = ctypes.c_long
         L.or_ilu0_nnz.argtypes = [P]
@@ -237,6 +239,7 @@ def redblack_order(pb) -> np.ndarray:
 
 SMOOTH_BLOCK = 0       # block-Jacobi ILU(0), natural order inside 8x8x8 blocks
 SMOOTH_REDBLACK = 1    # ILU(0) in red-black order
+SMOOTH_BLOCK_ALT = 2   # block ILU(0), every other step on the half-block-shifted block grid
 
 
 def smoother_block(pb):
@@ -244,20 +247,27 @@ def smoother_block(pb):
     return (8, 8, 8 if pb.nz > 1 else 1)
 
 
+def smoother_shift(pb):
+    """Offsets of the shifted block grid: half a block per active axis."""
+    return tuple(b // 2 for b in smoother_block(pb))
+
+
 class ILU0:
     """ILU(0) of the 7-point operator: in a given ordering (default
-    red-black), or block-Jacobi ILU(0) when `block` = (bx, by, bz)."""
+    red-black), or block-Jacobi ILU(0) when `block` = (bx, by, bz), on the
+    block grid shifted cyclically by `shift` = (ox, oy, oz) cells."""
 
-    def __init__(self, pb, W, diag, order=None, block=None):
+    def __init__(self, pb, W, diag, order=None, block=None, shift=(0, 0, 0)):
         self.pb = pb
         g = grid_of(pb)
         W = _f64(W)
         self._keep = (W, _f64(diag))
         if block is not None:
             self.order = np.arange(pb.n, dtype=np.int64)
-            self.h = lib().or_ilu0_block_create(ctypes.byref(g), _ptr(W[0]), _ptr(W[1]), _ptr(W[2]),
-                                                _ptr(self._keep[1]), int(block[0]), int(block[1]),
-                                                int(block[2]))
+            self.h = lib().or_ilu0_block_create_shifted(ctypes.byref(g), _ptr(W[0]), _ptr(W[1]), _ptr(W[2]),
+                                                        _ptr(self._keep[1]), int(block[0]), int(block[1]),
+                                                        int(block[2]), int(shift[0]), int(shift[1]),
+                                                        int(shift[2]))
             return
         self.order = redblack_order(pb) if order is None else np.ascontiguousarray(order, dtype=np.int64)
         self.h = lib().or_ilu0_create(ctypes.byref(g), _ptr(W[0]), _ptr(W[1]), _ptr(W[2]),
@@ -285,28 +295,37 @@ class ILU0:
 
 def cams_solve(pb, W, diag, P, restriction, LU, piv, ilu, r0, n_pre=None, n_post=None,
                rtol=None, maxit=None):
-    """(d, iterations, history): C-AMS iteration on A d = r0."""
+    """(d, iterations, history): C-AMS iteration on A d = r0.  `ilu` is one
+    smoother, or a pair whose members the Richardson steps of each smoothing
+    stage take in turn (first, second, first, ...)."""
     g = grid_of(pb)
     W = _f64(W)
     n_pre = pb.n_pre if n_pre is None else n_pre
     n_post = pb.n_post if n_post is None else n_post
     rtol = pb.lin_rtol if rtol is None else rtol
     maxit = pb.lin_maxit if maxit is None else maxit
+    first, alt = (ilu[0], ilu[1]) if isinstance(ilu, (tuple, list)) else (ilu, None)
     d = np.zeros(pb.n)
     hist = np.zeros(maxit + 1)
     its = lib().or_cams_solve(ctypes.byref(g), _ptr(W[0]), _ptr(W[1]), _ptr(W[2]), _ptr(_f64(diag)),
                               _ptr(pb.dirichlet_mask()), _ptr(_f64(P)), int(restriction),
-                              _ptr(LU), _ptr(piv), ctypes.c_void_p(ilu.h), int(n_pre), int(n_post),
+                              _ptr(LU), _ptr(piv), ctypes.c_void_p(first.h),
+                              ctypes.c_void_p(alt.h if alt is not None else None), int(n_pre), int(n_post),
                               ctypes.c_double(rtol), int(maxit), _ptr(_f64(r0)), _ptr(d), _ptr(hist))
     n_hist = (its + 1) if its >= 0 else (maxit + 1)
     return d, its, hist[:n_hist]
 
 
 def smoother_for(pb, W, diag, smoother=None):
-    """The ILU(0) smoother the problem asks for (default: block-Jacobi)."""
+    """The ILU(0) smoother the problem asks for (default: block-Jacobi): one
+    ILU0, or for SMOOTH_BLOCK_ALT the pair (blocks at the origin, shifted
+    blocks)."""
     kind = getattr(pb, "smoother", SMOOTH_BLOCK) if smoother is None else smoother
     if kind == SMOOTH_BLOCK:
         return ILU0(pb, W, diag, block=smoother_block(pb))
+    if kind == SMOOTH_BLOCK_ALT:
+        return (ILU0(pb, W, diag, block=smoother_block(pb)),
+                ILU0(pb, W, diag, block=smoother_block(pb), shift=smoother_shift(pb)))
     return ILU0(pb, W, diag)
 
 
@@ -328,6 +347,6 @@ def newton_step(pb, T, P, pn, p, restriction=None, n_pre=None, n_post=None, lin_
         int(pb.lin_maxit if lin_maxit is None else lin_maxit),
         ctypes.c_double(pb.newton_tol if newton_tol is None else newton_tol),
         int(pb.newton_maxit if newton_maxit is None else newton_maxit),
-        int(1 if kind == SMOOTH_BLOCK else 0), *smoother_block(pb),
+        int({SMOOTH_BLOCK: 1, SMOOTH_BLOCK_ALT: 2}.get(kind, 0)), *smoother_block(pb),
         _ptr(_f64(pn)), _ptr(p), _ptr(st))
     return p, rc, {"newton_iters": int(st[0]), "lin_iters": int(st[1]), "eps_norm": float(st[2])}

@@ -722,12 +722,23 @@ void or_ilu0_apply(void *h, const double *z, double *x)
 }
 
 /* Block-Jacobi ILU(0): the couplings across the faces of bx x by x bz cell
- * blocks (aligned at the origin, the last block of an axis possibly shorter)
- * are removed, and ILU(0) in natural order is taken of what remains; the
- * blocks are then independent of each other.  The smoothing residual still
- * uses the full matrix. */
-void *or_ilu0_block_create(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
-                           const double *diag, int bx, int by, int bz)
+ * blocks are removed, and ILU(0) in natural order is taken of what remains;
+ * the blocks are then independent of each other.  The smoothing residual
+ * still uses the full matrix.  Blocks are aligned at the origin (the last
+ * block of an axis possibly shorter), or, with offsets (ox, oy, oz), laid on
+ * the axis shifted cyclically: along x, cell i sits at position
+ * (i + ox) mod nx and the block holds 8 consecutive positions, so the first
+ * block may consist of a piece at the far end of the axis and a piece at
+ * its start (the two pieces share no coupling, so their ILU(0) factors are
+ * independent).  Two cells of a row are coupled in the factor iff their
+ * positions fall in the same block. */
+static int same_block(int i, int n, int b, int o)
+{
+    return ((i + o) % n) / b == ((i + 1 + o) % n) / b;
+}
+
+void *or_ilu0_block_create_shifted(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
+                                   const double *diag, int bx, int by, int bz, int ox, int oy, int oz)
 {
     long N = ncells(g);
     double *W = (double *)malloc(sizeof(double) * 3 * N);
@@ -736,15 +747,21 @@ void *or_ilu0_block_create(const og_grid *g, const double *Wx, const double *Wy,
         for (int j = 0; j < g->ny; j++)
             for (int i = 0; i < g->nx; i++) {
                 long n = cell_index(g, i, j, k);
-                W[n] = ((i + 1) % bx == 0) ? 0.0 : Wx[n];
-                W[N + n] = ((j + 1) % by == 0) ? 0.0 : Wy[n];
-                W[2 * N + n] = ((k + 1) % bz == 0) ? 0.0 : Wz[n];
+                W[n] = same_block(i, g->nx, bx, ox) ? Wx[n] : 0.0;
+                W[N + n] = same_block(j, g->ny, by, oy) ? Wy[n] : 0.0;
+                W[2 * N + n] = same_block(k, g->nz, bz, oz) ? Wz[n] : 0.0;
                 order[n] = n;
             }
     void *h = or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
     free(W);
     free(order);
     return h;
+}
+
+void *or_ilu0_block_create(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
+                           const double *diag, int bx, int by, int bz)
+{
+    return or_ilu0_block_create_shifted(g, Wx, Wy, Wz, diag, bx, by, bz, 0, 0, 0);
 }
 
 /* The red-black ordering used by the smoother. */
@@ -765,6 +782,9 @@ void or_redblack_order(const og_grid *g, int64_t *order)
  *            n_pre ILU(0) Richardson steps on A e = r  (d += e, r -= A e);
  *            d1 = P_hat A_c^{-1} R r;  d += d1;  r1 = r - A d1;
  *            d2 = 0; n_post times: d2 += M^{-1}(r1 - A d2);  d += d2.
+ * With a second smoother `ilu_alt` (nullable) the Richardson steps of each
+ * smoothing stage take M = ilu, ilu_alt, ilu, ... (the first step of the
+ * stage takes ilu).
  * Returns the number of iterations (>= 0), or -1 if maxit was reached;
  * hist (length maxit+1, nullable) receives ||r||/||r0|| per iteration.
  * Pinned: MSFV zero block residual / MSFE Galerkin orthogonality after the
@@ -772,7 +792,7 @@ void or_redblack_order(const og_grid *g, int64_t *order)
  * ---------------------------------------------------------------------- */
 int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
                   const double *diag, const uint8_t *dmask, const double *P, int restriction,
-                  const double *LU, const int32_t *piv, void *ilu,
+                  const double *LU, const int32_t *piv, void *ilu, void *ilu_alt,
                   int n_pre, int n_post, double rtol, int maxit,
                   const double *r0, double *dsol, double *hist)
 {
@@ -802,7 +822,7 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
             for (int s = 0; s < n_pre; s++) {
                 or_matvec(g, Wx, Wy, Wz, diag, e, t);
                 for (long n = 0; n < N; n++) t[n] = r[n] - t[n];
-                or_ilu0_apply(ilu, t, x);
+                or_ilu0_apply((s & 1) && ilu_alt ? ilu_alt : ilu, t, x);
                 for (long n = 0; n < N; n++) e[n] += x[n];
             }
             or_matvec(g, Wx, Wy, Wz, diag, e, t);
@@ -819,7 +839,7 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
         for (int s = 0; s < n_post; s++) {
             or_matvec(g, Wx, Wy, Wz, diag, e, t);
             for (long n = 0; n < N; n++) t[n] = r[n] - t[n];
-            or_ilu0_apply(ilu, t, x);
+            or_ilu0_apply((s & 1) && ilu_alt ? ilu_alt : ilu, t, x);
             for (long n = 0; n < N; n++) e[n] += x[n];
         }
         for (long n = 0; n < N; n++) dsol[n] += e[n];
@@ -833,7 +853,9 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
  * (Sec. 2; Table "cams" outer loop; Sec. 4.1.1 for the error norm):
  *   repeat: assemble A, r at p; if ||eps||_2 <= newton_tol stop;
  *           coarse operator + LU; ILU(0) smoother (smoother 0: red-black
- *           order; 1: block-Jacobi ILU(0) on bx x by x bz blocks); C-AMS
+ *           order; 1: block-Jacobi ILU(0) on bx x by x bz blocks; 2: the
+ *           same blocks alternating, step by step, with the block grid
+ *           shifted cyclically by half a block, (bx/2, by/2, bz/2)); C-AMS
  *           solve; p += d.
  * The basis P (type B4) is pressure independent and passed in.
  * stats[0] = Newton iterations, stats[1] = total linear iterations,
@@ -865,11 +887,15 @@ int or_newton_step(const og_grid *g, const og_fluid *f,
         if (nit == newton_maxit || !isfinite(en)) break;
         or_coarse_operator(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac);
         if (or_lu_factor(Nc, Ac, piv) != 0) { rc = -3; break; }
-        void *ilu = smoother == 1 ? or_ilu0_block_create(g, W, W + N, W + 2 * N, diag, bx, by, bz)
+        void *ilu = smoother >= 1 ? or_ilu0_block_create(g, W, W + N, W + 2 * N, diag, bx, by, bz)
                                   : or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
-        int its = or_cams_solve(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac, piv, ilu,
+        void *alt = smoother == 2 ? or_ilu0_block_create_shifted(g, W, W + N, W + 2 * N, diag, bx, by, bz,
+                                                                 bx / 2, by / 2, bz / 2)
+                                  : NULL;
+        int its = or_cams_solve(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac, piv, ilu, alt,
                                 n_pre, n_post, lin_rtol, lin_maxit, r, d, NULL);
         or_ilu0_free(ilu);
+        or_ilu0_free(alt);
         if (its < 0) { rc = -2; lit += lin_maxit; break; }
         lit += its;
         for (long n = 0; n < N; n++) p[n] += d[n];

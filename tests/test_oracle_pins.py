@@ -365,11 +365,12 @@ def test_msfe_stage_is_galerkin_orthogonal():
     assert np.max(np.abs(Ph.T @ r1)) <= 1e-12 * np.abs(r).sum()
 
 
-@pytest.mark.parametrize("restriction,n_pre", [(FV, 0), (FE, 0), (FV, 5)])
-def test_cams_converges_to_sparse_lu_solution(restriction, n_pre):
+@pytest.mark.parametrize("restriction,n_pre,smoother", [(FV, 0, "rb"), (FE, 0, "rb"), (FV, 5, "rb"),
+                                                        (FE, 0, "alt"), (FV, 5, "alt")])
+def test_cams_converges_to_sparse_lu_solution(restriction, n_pre, smoother):
     pb = small_problem(16, 16, 8, (4, 4, 4), sigma=2.0)
     T, P, W, diag, r, LU, piv = _setup(pb, restriction)
-    ilu = oracle.ILU0(pb, W, diag)
+    ilu = oracle.ILU0(pb, W, diag) if smoother == "rb" else oracle.smoother_for(pb, W, diag, oracle.SMOOTH_BLOCK_ALT)
     d, its, hist = oracle.cams_solve(pb, W, diag, P, restriction, LU, piv, ilu, r,
                                      n_pre=n_pre, n_post=5, rtol=1e-14, maxit=300)
     assert its > 0
@@ -432,3 +433,94 @@ def test_block_ilu0_is_ilu0_of_the_block_diagonal_part():
     z = np.random.default_rng(9).normal(size=N)
     x = np.linalg.solve(U, np.linalg.solve(L, z))
     assert np.allclose(ilu.apply(z), x, rtol=1e-11, atol=1e-13)
+
+
+def _factor_dense(ilu, N):
+    rp, col, val = ilu.export()
+    return sp.csr_matrix((val, col, rp), shape=(N, N)).toarray()
+
+
+def test_shifted_block_grid_cuts():
+    """The shifted block grid cuts the axes where the cyclic positions
+    (cell + offset) mod n cross a multiple of the block size.  Worked by hand
+    for blocks of 4 cells: x (10 cells, offset 2) is cut after cells 1, 5
+    and 7 (blocks {8, 9, 0, 1}, {2..5}, {6, 7}); y (6 cells, offset 1) after
+    cells 2 and 4 (blocks {5, 0, 1, 2}, {3, 4})."""
+    pb = small_problem(10, 6, 1, (2, 2, 1), sigma=1.0, wells="none")
+    T = oracle.transmissibility(pb)
+    p = np.random.default_rng(11).uniform(0, 1, pb.n)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
+    F = _factor_dense(oracle.ILU0(pb, W, diag, block=(4, 4, 1), shift=(2, 1, 0)), pb.n)
+    nx, ny = pb.nx, pb.ny
+    for j in range(ny):
+        for i in range(nx - 1):
+            a, b = i + nx * j, i + 1 + nx * j
+            assert (F[b, a] != 0) == (i not in (1, 5, 7)), (i, j)
+            assert (F[a, b] != 0) == (i not in (1, 5, 7)), (i, j)
+    for j in range(ny - 1):
+        for i in range(nx):
+            a, b = i + nx * j, i + nx * (j + 1)
+            assert (F[b, a] != 0) == (j not in (2, 4)), (i, j)
+
+
+def test_shifted_block_ilu0_is_ilu0_of_the_block_diagonal_part():
+    """The shifted block-Jacobi ILU(0) on a ragged grid: block labels made
+    here by rolling the unshifted labels of each axis; the factor reproduces
+    the block-diagonal part of A on its pattern, couples no two blocks, and
+    one application equals the triangular solves."""
+    pb = small_problem(19, 17, 11, 4, sigma=2.0)
+    T = oracle.transmissibility(pb)
+    p = np.random.default_rng(12).uniform(0, 1, pb.n)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
+    ilu = oracle.ILU0(pb, W, diag, block=(8, 8, 8), shift=(4, 4, 4))
+    N = pb.n
+    F = _factor_dense(ilu, N)
+    L = np.tril(F, -1) + np.eye(N)
+    U = np.triu(F)
+    A = helpers.stencil_matrix(pb, W, diag).toarray()
+    lab = [np.roll(np.arange(n) // 8, -4) for n in (pb.nx, pb.ny, pb.nz)]
+    idx = np.arange(N)
+    i, j, k = idx % pb.nx, (idx // pb.nx) % pb.ny, idx // (pb.nx * pb.ny)
+    blk = lab[0][i] + 100 * lab[1][j] + 10000 * lab[2][k]
+    same = blk[:, None] == blk[None, :]
+    Ab = np.where(same, A, 0.0)
+    pattern = Ab != 0
+    assert np.max(np.abs((L @ U - Ab)[pattern])) <= 1e-13 * np.abs(A).max()
+    assert np.all(F[~same] == 0)
+    assert len(np.unique(blk)) == 3 * 3 * 2   # 19, 17, 11 cells: 3, 3, 2 blocks of 8 positions
+    z = np.random.default_rng(13).normal(size=N)
+    x = np.linalg.solve(U, np.linalg.solve(L, z))
+    assert np.allclose(ilu.apply(z), x, rtol=1e-11, atol=1e-13)
+
+
+def test_alternating_smoother_step_order():
+    """One C-AMS iteration with two post-smoothing steps of the alternating
+    smoother: the first step takes the blocks at the origin, the second the
+    shifted blocks (composed here step by step)."""
+    pb = small_problem(16, 12, 10, (4, 4, 5), sigma=2.0)
+    T, P, W, diag, r, LU, piv = _setup(pb, FE)
+    A0, A1 = oracle.smoother_for(pb, W, diag, oracle.SMOOTH_BLOCK_ALT)
+    d, its, _ = oracle.cams_solve(pb, W, diag, P, FE, LU, piv, (A0, A1), r, n_pre=0, n_post=2,
+                                  rtol=1e-30, maxit=1)
+    assert its == -1
+    d1 = oracle.prolong(pb, P, oracle.lu_solve(LU, piv, oracle.restrict(pb, P, FE, r)))
+    r1 = r - oracle.matvec(pb, W, diag, d1)
+    e = A0.apply(r1)
+    e = e + A1.apply(r1 - oracle.matvec(pb, W, diag, e))
+    assert np.allclose(d, d1 + e, rtol=1e-12, atol=1e-14 * np.abs(d).max())
+    swapped = d1 + A1.apply(r1)
+    swapped = swapped + A0.apply(r1 - oracle.matvec(pb, W, diag, swapped - d1))
+    assert not np.allclose(d, swapped, rtol=1e-6)
+
+
+def test_config1_newton_alternating_smoother_matches_direct_newton():
+    """As above with the alternating block smoother (pre- and post-smoothing)."""
+    pb = config1()
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, rc, st = oracle.newton_step(pb, T, P, p0, p0, lin_rtol=1e-13, newton_tol=1e-12,
+                                   smoother=oracle.SMOOTH_BLOCK_ALT)
+    assert rc == 0
+    ref, _ = helpers.direct_newton(pb, T, p0, p0, tol=1e-12)
+    assert np.max(np.abs(p - ref)) <= 1e-10 * np.abs(ref).max()
