@@ -329,7 +329,8 @@ def main():
         "dtype": "f32+f64" if "mixed" in runs else "f64",
         "data": "synthetic",
         "config": {"workload": "64x64x32 lognormal (sigma 3, corr. 8x8x2), coarsening 8^3 (256 coarse nodes), "
-                               "MSFE, 5 block-ILU(0) post-smoothing steps, 10 backward-Euler steps dt=0.05, "
+                               "MSFE, 5 block-ILU(0) post-smoothing steps (block grid shifted by half a block on every other "
+                               "step), 10 backward-Euler steps dt=0.05, "
                                "Newton and linear solves to 1e-8; value = mixed precision (FP32 smoother, "
                                "basis and prolongation, FP64 residual/update/coarse solve)" if "mixed" in runs
                                else "64x64x32 workload, plain FP64",

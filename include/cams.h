@@ -67,8 +67,15 @@ enum { CAMS_FP64 = 0, CAMS_MIXED_FP32 = 1, CAMS_MIXED_BF16 = 2 };
  * natural order on 8x8x8 cell blocks aligned at the origin (8x8 in 2D; the
  * last block of an axis may be shorter), couplings across block faces left
  * out of the factor only.  RB: ILU(0) of the whole matrix in red-black
- * order (even i+j+k first). */
-enum { CAMS_SMOOTH_BLOCK_ILU0 = 0, CAMS_SMOOTH_RB_ILU0 = 1 };
+ * order (even i+j+k first).  BLOCK_ALT: the Richardson steps of each
+ * smoothing stage alternate between the BLOCK factor and block-Jacobi
+ * ILU(0) on the block grid shifted cyclically by half a block on every
+ * axis longer than one block (cell i at position (i + 4) mod nx along x,
+ * blocks of 8 consecutive positions; likewise y and z; an axis of at most 8
+ * cells is one block either way); the first step of a stage takes the grid
+ * at the origin.  A closer stand-in for the paper's global ILU(0):
+ * fewer iterations for the same work per step. */
+enum { CAMS_SMOOTH_BLOCK_ILU0 = 0, CAMS_SMOOTH_RB_ILU0 = 1, CAMS_SMOOTH_BLOCK_ALT_ILU0 = 2 };
 
 typedef struct {
     int32_t nx, ny, nz;       /* fine cells per axis, >= 2 on active axes (nz == 1 for 2D) */
@@ -87,7 +94,7 @@ typedef struct {
     int32_t n_pre;            /* ILU(0) Richardson steps before the multiscale stage (0..64) */
     int32_t n_post;           /* ILU(0) Richardson steps after it (Table "cams" step 6; 0..64) */
     int32_t precision;        /* CAMS_FP64 / CAMS_MIXED_FP32 / CAMS_MIXED_BF16 */
-    int32_t smoother;         /* CAMS_SMOOTH_BLOCK_ILU0 or CAMS_SMOOTH_RB_ILU0 */
+    int32_t smoother;         /* CAMS_SMOOTH_BLOCK_ILU0, CAMS_SMOOTH_RB_ILU0 or CAMS_SMOOTH_BLOCK_ALT_ILU0 */
     double lin_rtol;          /* stop when ||r||_2 <= lin_rtol ||r0||_2 */
     int32_t lin_maxit;        /* linear iteration limit */
     double newton_tol;        /* stop Newton when ||eps||_2 <= newton_tol (Eq. (16)) */
@@ -110,7 +117,7 @@ typedef struct {
 /* Create a context for one grid.  Validates grid/fluid/options: active axes
  * >= 2 cells, 2 <= r <= 8 and r <= n per axis, vertex spacing >= 2 cells,
  * at most 32768 coarse nodes, dx,dy,dz,dt,mu,rho0 > 0, c >= 0, tolerances
- * > 0; the mixed precisions need the block smoother.  `hip_stream` is a
+ * > 0; the mixed precisions need a block smoother (BLOCK or BLOCK_ALT).  `hip_stream` is a
  * hipStream_t (NULL = default
  * stream).  Makes no HIP call (works without a GPU); on success *out owns
  * no device memory.  Release with cams_destroy.  Errors: CAMS_E_ARG,
@@ -194,7 +201,9 @@ cams_status cams_iterate(cams_ctx *ctx, double *p_dev, cams_stats *stats);
 cams_status cams_newton_step(cams_ctx *ctx, const double *pn_dev, double *p_dev, cams_stats *stats);
 
 /* One application of the smoother, x = M^{-1} z, with M the ILU(0) factor of
- * the assembled matrix chosen by options.smoother (Table "cams" step 6).  z_dev and
+ * the assembled matrix chosen by options.smoother (Table "cams" step 6); for
+ * BLOCK_ALT the pair of Richardson steps from zero, x1 = M0^{-1} z and
+ * x = x1 + M1^{-1}(z - A x1) (M0: blocks at the origin, M1: shifted).  z_dev and
  * x_dev have N entries.  Errors: CAMS_E_STATE (no coarse_op for the current
  * system: the factor is computed there). */
 cams_status cams_smooth_apply(cams_ctx *ctx, const double *z_dev, double *x_dev);
@@ -209,7 +218,8 @@ typedef enum {
     CAMS_ARR_P = 4,        /* 8*N doubles: basis weights, slot-major */
     CAMS_ARR_AC = 5,       /* Nc*Nc doubles: coarse operator, row-major (before factorisation) */
     CAMS_ARR_AC_INV = 6,   /* Nc*Nc doubles: inverse of the coarse operator */
-    CAMS_ARR_INVD = 7      /* N doubles: inverse ILU(0) pivots of the smoother */
+    CAMS_ARR_INVD = 7      /* N doubles: inverse ILU(0) pivots of the smoother (2N for BLOCK_ALT:
+                              those of the shifted block grid follow) */
 } cams_array;
 
 size_t cams_array_bytes(const cams_ctx *ctx, cams_array which);
@@ -330,7 +340,8 @@ const char *cams_last_error(const cams_ctx *ctx);
  *
  * The contexts must have been created on the same stream (the one given
  * here), have their workspace and rock set, share precision and n_pre /
- * n_post, use the block ILU(0) smoother and the local basis (no learned
+ * n_post, use a block ILU(0) smoother (BLOCK or BLOCK_ALT, may differ per
+ * instance) and the local basis (no learned
  * basis).  The batch keeps pointers to the contexts: destroy it before them.
  * Each instance computes exactly what cams_newton_step with newton_maxit = 1
  * computes for its first linear solve (same kernels, same order of

@@ -731,7 +731,8 @@ void or_ilu0_apply(void *h, const double *z, double *x)
  * block may consist of a piece at the far end of the axis and a piece at
  * its start (the two pieces share no coupling, so their ILU(0) factors are
  * independent).  Two cells of a row are coupled in the factor iff their
- * positions fall in the same block. */
+ * positions fall in the same block; an axis of at most b cells is then one
+ * block for any offset. */
 static int same_block(int i, int n, int b, int o)
 {
     return ((i + o) % n) / b == ((i + 1 + o) % n) / b;

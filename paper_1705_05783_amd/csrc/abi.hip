@@ -263,8 +263,10 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     if (O.n_pre < 0 || O.n_pre > 64 || O.n_post < 0 || O.n_post > 64) return CAMS_E_ARG;
     if (O.precision != CAMS_FP64 && O.precision != CAMS_MIXED_FP32 && O.precision != CAMS_MIXED_BF16)
         return CAMS_E_ARG;
-    if (O.smoother != CAMS_SMOOTH_BLOCK_ILU0 && O.smoother != CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
-    if (O.precision != CAMS_FP64 && O.smoother != CAMS_SMOOTH_BLOCK_ILU0) return CAMS_E_ARG;
+    if (O.smoother != CAMS_SMOOTH_BLOCK_ILU0 && O.smoother != CAMS_SMOOTH_RB_ILU0 &&
+        O.smoother != CAMS_SMOOTH_BLOCK_ALT_ILU0)
+        return CAMS_E_ARG;
+    if (O.precision != CAMS_FP64 && O.smoother == CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
     if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
     const int nb[3] = {num_blocks(n[0], r[0]), num_blocks(n[1], r[1]), num_blocks(n[2], r[2])};
     const double Nc = (double)nb[0] * nb[1] * nb[2];
@@ -351,7 +353,18 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
         c->nreg[f] = (int)by[f].size();
         c->regoff[f] = off;
         off += c->nreg[f];
-        for (const Region &R : by[f]) t.regions.push_back(R);
+        c->maxm[f] = 1;
+        c->maxbw[f] = 1;
+        for (const Region &R : by[f]) {
+            t.regions.push_back(R);
+            // local system size and bandwidth (stride of the last open axis)
+            const int st[3] = {1, R.len[0], R.len[0] * R.len[1]};
+            int bw = 1;
+            for (int a = 0; a < 3; ++a)
+                if (R.freemask & (1 << a)) bw = st[a];
+            c->maxm[f] = std::max(c->maxm[f], R.len[0] * R.len[1] * R.len[2]);
+            c->maxbw[f] = std::max(c->maxbw[f], bw);
+        }
     }
     c->region_total = off;
 
@@ -381,7 +394,8 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     put(L.add(n8));            // 11 d2
     put(L.add(n8));            // 12 z
     put(L.add(n8));            // 13 x
-    put(L.add(n8));            // 14 invd
+    const size_t npiv = O.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0 ? 2 : 1;   // pivot sets
+    put(L.add(npiv * n8));     // 14 invd
     put(L.add(8 * n8));        // 15 P
     put(L.add(nc * nc * 8));   // 16 Ac
     put(L.add(nc * nc * 8));   // 17 Ainv
@@ -405,7 +419,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     const size_t n4 = mixed ? (size_t)g.N * 4 : 0;
     put(L.add(3 * n4));        // 33 W32
     put(L.add(n4));            // 34 diag32
-    put(L.add(n4));            // 35 invd32
+    put(L.add(npiv * n4));     // 35 invd32
     put(L.add(O.precision == CAMS_MIXED_FP32 ? 8 * n4 : 0));   // 36 P32
     put(L.add(O.precision == CAMS_MIXED_BF16 ? 4 * n4 : 0));   // 37 Pbf (8 x 2 bytes per cell)
     put(L.add(n4));            // 38 r1f
@@ -413,7 +427,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     put(L.add(n4));            // 40 d1f
     put(L.add(n4));            // 41 d2f
     put(L.add(n4));            // 42 zf
-    put(L.add((size_t)2 * ((nc + 63) / 64) * 64 * 64 * 8));   // 43 coarse LU block inverses
+    put(L.add(0));             // 43 (unused)
     {   // 44 Gauss-Jordan GEMM descriptors (MSFE): 8 per 64-column panel of each inverted matrix
         const size_t mats = c->blocktri ? (size_t)nb[2] : 1, dim = c->blocktri ? (size_t)nb[0] * nb[1] : nc;
         put(L.add(O.restriction == CAMS_R_FE ? mats * ((dim + 63) / 64) * 12 * sizeof(GemmDesc) : 0));
@@ -487,7 +501,6 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.d1f = (float *)(w + off[40]);
     a.d2f = (float *)(w + off[41]);
     a.zf = (float *)(w + off[42]);
-    a.tri = (double *)(w + off[43]);
     a.gjd = (void *)(w + off[44]);
     a.gjcb = (double *)(w + off[45]);
     if (!c->host) {
@@ -702,7 +715,7 @@ cams_status cams_smooth_apply(cams_ctx *c, const double *z, double *x)
     if (!c || !z || !x) return CAMS_E_ARG;
     if (!c->has_coarse) return fail(c, CAMS_E_STATE, "smoother factor is built by coarse_op");
     try {
-        launch_smooth(c, z, x, 1, nullptr);
+        launch_smooth(c, z, x, c->opt.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0 ? 2 : 1, nullptr);
         CAMS_HIP(hipGetLastError());
     } catch (const HipError &e) {
         return fail(c, CAMS_E_DEVICE, std::string("smooth_apply: ") + hipGetErrorString(e.code));
@@ -754,7 +767,7 @@ static void enqueue_iteration(cams_ctx *c, int it)
         if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done, a.d1f);
         return;
     }
-    const bool block = O.smoother == CAMS_SMOOTH_BLOCK_ILU0;
+    const bool block = O.smoother != CAMS_SMOOTH_RB_ILU0;
     const double *pend0 = O.n_pre > 0 ? a.d0 : nullptr;
     const double *pend1 = O.n_post > 0 && block ? a.d2 : a.d1;
     const double *pend2 = O.n_post > 0 && !block ? a.d2 : nullptr;
@@ -907,7 +920,8 @@ size_t cams_array_bytes(const cams_ctx *c, cams_array which)
     const size_t N = c->g.N, Nc = c->g.Nc;
     switch (which) {
     case CAMS_ARR_T: case CAMS_ARR_W: return 3 * N * 8;
-    case CAMS_ARR_DIAG: case CAMS_ARR_R0: case CAMS_ARR_INVD: return N * 8;
+    case CAMS_ARR_DIAG: case CAMS_ARR_R0: return N * 8;
+    case CAMS_ARR_INVD: return N * 8 * (c->opt.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0 ? 2 : 1);
     case CAMS_ARR_P: return 8 * N * 8;
     case CAMS_ARR_AC: case CAMS_ARR_AC_INV: return Nc * Nc * 8;
     }

@@ -97,8 +97,8 @@ struct cams_batch {
     // batched factorisation of the MSFE instances (plan built with the workspace)
     std::vector<cams_ctx *> fe;
     size_t lu_steps_cap = 0, lu_gemms_cap = 0;
-    BatchLuPlan lu;
-    LuStep *d_steps = nullptr;
+    BatchGjPlan lu;
+    GjPivotDesc *d_steps = nullptr;
     GemmDesc *d_gemms = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -287,7 +287,7 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         const cams_ctx *c = ctxs[i];
         if (!c) return CAMS_E_ARG;
         if (c->stream != st) return CAMS_E_ARG;                 // one stream for the whole batch
-        if (c->opt.smoother != CAMS_SMOOTH_BLOCK_ILU0) return CAMS_E_ARG;
+        if (c->opt.smoother == CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
         if (c->opt.precision != O.precision || c->opt.n_pre != O.n_pre || c->opt.n_post != O.n_post)
             return CAMS_E_ARG;
         if (c->g.dim != 3 && c->g.dim != 2) return CAMS_E_ARG;
@@ -340,11 +340,11 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         if (ctxs[i]->opt.restriction == CAMS_R_FE) {
             const size_t T = (ctxs[i]->g.Nc + 63) / 64;
             b->fe.push_back(ctxs[i]);
-            b->lu_steps_cap += T;
-            b->lu_gemms_cap += 7 * T;   // per panel at most: L21, U12, trailing, two forward, two backward
+            b->lu_steps_cap += T;        // one pivot step per panel
+            b->lu_gemms_cap += 10 * T;   // per panel at most: 4 panel products, 2 + 4 update blocks
         }
     b->off_lu_steps = o;
-    o = align_up(o + b->lu_steps_cap * sizeof(LuStep));
+    o = align_up(o + b->lu_steps_cap * sizeof(GjPivotDesc));
     b->off_lu_gemms = o;
     o = align_up(o + b->lu_gemms_cap * sizeof(GemmDesc));
     b->need = o;
@@ -388,7 +388,7 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
         for (int l = 0; l <= L_NUM; ++l) b->work[l] = (WorkItem *)(w + b->off_list[l]);
         b->nwork = (int32_t *)(w + b->off_nwork);
         b->res = (BatchResult *)(w + b->off_res);
-        b->d_steps = (LuStep *)(w + b->off_lu_steps);
+        b->d_steps = (GjPivotDesc *)(w + b->off_lu_steps);
         b->d_gemms = (GemmDesc *)(w + b->off_lu_gemms);
         b->pptr = (double **)(w + b->off_pptr);
         b->h_inst.resize(count);
@@ -402,6 +402,7 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
             d.bf16 = b->bf16;
             d.n_pre = c->opt.n_pre;
             d.n_post = c->opt.n_post;
+            d.alt = c->opt.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0;
             d.nparts = (c->g.N + kBlock - 1) / kBlock;
             d.maxit = c->opt.lin_maxit;
             d.rtol2 = c->opt.lin_rtol * c->opt.lin_rtol;
@@ -417,11 +418,11 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
                                     hipMemcpyHostToDevice, b->stream));
             CAMS_HIP(hipStreamSynchronize(b->stream));   // `full` must outlive the copy
         }
-        plan_batch_lu(b->fe, b->lu);
-        if (b->lu.steps.size() > b->lu_steps_cap || b->lu.gemms.size() > b->lu_gemms_cap)
+        plan_batch_gj(b->fe, b->lu);
+        if (b->lu.piv.size() > b->lu_steps_cap || b->lu.gemms.size() > b->lu_gemms_cap)
             return bfail(b, CAMS_E_STATE, "factorisation plan exceeds its capacity");
-        if (!b->lu.steps.empty())
-            CAMS_HIP(hipMemcpyAsync(b->d_steps, b->lu.steps.data(), b->lu.steps.size() * sizeof(LuStep),
+        if (!b->lu.piv.empty())
+            CAMS_HIP(hipMemcpyAsync(b->d_steps, b->lu.piv.data(), b->lu.piv.size() * sizeof(GjPivotDesc),
                                     hipMemcpyHostToDevice, b->stream));
         if (!b->lu.gemms.empty())
             CAMS_HIP(hipMemcpyAsync(b->d_gemms, b->lu.gemms.data(), b->lu.gemms.size() * sizeof(GemmDesc),
@@ -488,7 +489,7 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
             CAMS_HIP(hipEventRecord(b->join[s], b->side[s]));
             CAMS_HIP(hipStreamWaitEvent(b->stream, b->join[s], 0));
         }
-        launch_batch_lu(b->lu, b->d_steps, b->d_gemms, b->stream);
+        launch_batch_gj(b->lu, b->d_steps, b->d_gemms, b->stream);
         CAMS_HIP(hipGetLastError());
         CAMS_HIP(hipEventRecord(b->ev[1], b->stream));
 

@@ -54,7 +54,6 @@ struct Arrays {
     double *d0, *d1, *d2, *z, *x, *invd;
     double *P;        // 8N slot-major
     double *Ac, *Ainv, *work; // Nc*Nc each
-    double *tri;      // inverses of the 64x64 diagonal blocks of the coarse LU (2 per panel)
     double *rc, *xc;  // Nc
     double *partial;  // reduction partials
     double *slots;    // Nc*8 restriction partials: slot s of owner box k
@@ -85,6 +84,7 @@ struct InstDev {
     int fe;           // MSFE restriction
     int bf16;         // mixed precision with a bfloat16 basis
     int n_pre, n_post;
+    int alt;          // alternating block smoother (odd steps on the shifted block grid)
     int nparts;       // residual partials: Nc (fused residual-restriction) or ceil(N / kBlock)
     int maxit;
     double rtol2;
@@ -299,13 +299,14 @@ void cnn_scatter(cams_ctx *c, const Region *regs, int nblk, const float *phi);
 void cnn_block_residual(cams_ctx *c, const Region *regs, int nblk, double *ratio);
 
 // ---- batched coarse factorisation (k_coarse.hip)
-// Diagonal-block step of one instance: factor F (n x n) at (j0, j0), nb
-// columns, and the inverses of its two triangles (Linv, Uinv: 64 x 64).
-struct LuStep {
-    double *F;
-    int n, j0, nb;
+// One Gauss-Jordan pivot step of one instance: the inverse of the nb x nb
+// pivot block of A (n x n) at (j0, j0) and the copy of its old column block
+// into Cb; its workgroups are wg0 .. wg0 + 1 + ceil((n - nb) nb / 256) - 1
+// of the launch.
+struct GjPivotDesc {
+    double *A, *Cb;
     int32_t *status;
-    double *Linv, *Uinv;
+    int n, j0, nb, wg0;
 };
 // C = alpha A B + beta C for one instance; its tiles are tile0 .. tile0 +
 // tiles_n * ceil(M / 64) - 1 of the launch.
@@ -316,21 +317,22 @@ struct GemmDesc {
     double alpha, beta;
     int tiles_n, tile0;
 };
-struct BatchLuPlan {
-    enum Kind { DIAG = 0, GEMM = 2 };
+struct BatchGjPlan {
+    enum Kind { PIVOT = 0, GEMM = 1, UPDATE_PIVOT = 2 };
     struct Launch {
         int kind;
-        size_t off;     // into steps (DIAG) or gemms (GEMM)
-        int count;      // descriptors
-        int tiles;      // GEMM: workgroups
+        size_t poff;    // into piv
+        int pcount, pw; // pivot descriptors and their workgroups
+        size_t goff;    // into gemms
+        int gcount, tiles;
     };
-    std::vector<LuStep> steps;
+    std::vector<GjPivotDesc> piv;
     std::vector<GemmDesc> gemms;
     std::vector<Launch> launches;
 };
 void launch_coarse_factor_prepare(cams_ctx *c);
-void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan);
-void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDesc *gemms, hipStream_t st);
+void plan_batch_gj(const std::vector<cams_ctx *> &fe, BatchGjPlan &plan);
+void launch_batch_gj(const BatchGjPlan &plan, const GjPivotDesc *piv, const GemmDesc *gemms, hipStream_t st);
 
 // ---- coarse level (k_coarse.hip)
 void launch_coarse_operator(cams_ctx *c);

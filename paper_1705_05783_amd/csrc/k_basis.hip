@@ -26,14 +26,30 @@ __global__ __launch_bounds__(kBlock) void k_basis_vertices(GridDev g, double *__
     for (int s = 0; s < 8; ++s) P[(size_t)s * g.N + n] = (s == 0 && lev == g.dim) ? 1.0 : 0.0;
 }
 
-// MAXM / MAXBW bound the local system of this stage; the LDS holds the band
-// of L by columns (L[c*(bw+1)+d] = entry (c+d, c)) followed by 8 rhs per cell.
-template <int NT, int MAXM, int MAXBW>
+// Blocked banded Cholesky: columns are taken KB at a time.  The first wave
+// factors the panel (the KB columns with the <= bw rows below them) with one
+// row per lane in registers, pivots and multipliers broadcast by readlane;
+// then all threads subtract the panel's rank-KB product from the trailing
+// band.  Two barriers per KB columns instead of three per column.
+constexpr int KB = 8;
+
+__device__ __forceinline__ double lane_bcast(double v, int lane)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The local system of one region: band of L by columns (L[c*ld + d] = entry
+// (c+d, c), ld = bw + 1) followed by 8 right-hand sides per cell, in dynamic
+// LDS of `cap` doubles (sized by the host for the largest region of the stage).
+template <int NT>
 __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__restrict__ T,
                                                       const Region *__restrict__ regs, double *__restrict__ P,
-                                                      int32_t *status)
+                                                      int32_t *status, int cap)
 {
-    __shared__ double lds[MAXM * (MAXBW + 1) + 8 * MAXM];
+    extern __shared__ double lds[];
     const Region R = regs[blockIdx.x];
     const int e0 = R.len[0], e1 = R.len[1], e2 = R.len[2];
     const int m = e0 * e1 * e2;
@@ -42,11 +58,11 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
     int bw = 1;
     for (int a = 0; a < 3; ++a)
         if (R.freemask & (1 << a)) bw = lstride[a];
-    if (m > MAXM || bw > MAXBW) {  // region larger than this stage's buffers: host bug
+    const int ld = bw + 1;
+    if (m * (ld + 8) > cap || bw + KB > 64) {  // region larger than the launch's buffer: host bug
         if (threadIdx.x == 0) atomicOr(status, F_BAD_INPUT);
         return;
     }
-    const int ld = bw + 1;
     double *L = lds;
     double *B = lds + m * ld;
     const int rlo[3] = {g.lo[0][R.s[0]], g.lo[1][R.s[1]], g.lo[2][R.s[2]]};
@@ -96,49 +112,101 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
     }
     __syncthreads();
 
-    // banded Cholesky, right looking, one column per step
-    for (int c = 0; c < m; ++c) {
-        double piv = L[c * ld];
-        if (!(piv > 0.0)) {
-            if (threadIdx.x == 0) atomicOr(status, F_BAD_PIVOT);
-            piv = 1.0;
+    const int lane = threadIdx.x;   // meaningful in the first wave
+    for (int c0 = 0; c0 < m; c0 += KB) {
+        const int kc = min(KB, m - c0), nr = min(bw, m - c0 - kc), rows = kc + nr;
+        if (threadIdx.x < 64) {
+            // panel: lane = row c0 + lane, v[q] = entry (row, c0 + q) inside the band
+            double v[KB];
+            const int i = c0 + lane;
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int d = i - (c0 + q);
+                v[q] = (q < kc && lane < rows && d >= 0 && d <= bw) ? L[(c0 + q) * ld + d] : 0.0;
+            }
+            bool bad = false;
+#pragma unroll
+            for (int q0 = 0; q0 < KB; ++q0) {
+                if (q0 >= kc) break;
+                double piv = lane_bcast(v[q0], q0);
+                if (!(piv > 0.0)) {
+                    bad = true;
+                    piv = 1.0;
+                }
+                const double sq = sqrt(piv);
+                v[q0] = lane == q0 ? sq : (lane > q0 ? v[q0] / sq : v[q0]);
+#pragma unroll
+                for (int q2 = q0 + 1; q2 < KB; ++q2) {
+                    if (q2 >= kc) break;
+                    const double l = lane_bcast(v[q0], q2);
+                    if (lane >= q2) v[q2] -= v[q0] * l;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int d = i - (c0 + q);
+                if (q < kc && lane < rows && d >= 0 && d <= bw) L[(c0 + q) * ld + d] = v[q];
+            }
+            if (bad && lane == 0) atomicOr(status, F_BAD_PIVOT);
         }
-        const double s = sqrt(piv);
         __syncthreads();
-        for (int d = threadIdx.x; d <= bw; d += NT)
-            if (c + d < m) L[c * ld + d] = (d == 0) ? s : L[c * ld + d] / s;
-        __syncthreads();
-        const int nd = min(bw, m - 1 - c);
-        for (int t = threadIdx.x; t < nd * nd; t += NT) {
-            const int d1 = t % nd + 1, d2 = t / nd + 1;
-            if (d1 > d2) continue;
-            const double l2 = L[c * ld + d2];
-            if (l2 == 0.0) continue;
-            const double l1 = L[c * ld + d1];
-            if (l1 == 0.0) continue;
-            L[(c + d1) * ld + (d2 - d1)] -= l1 * l2;
+        // trailing band: entry (i, j), c0 + kc <= j <= i < c0 + kc + nr, minus the panel's products
+        for (int t = threadIdx.x; t < nr * nr; t += NT) {
+            const int ii = t / nr, jj = t % nr;
+            if (jj > ii || ii - jj > bw) continue;
+            const int i = c0 + kc + ii, j = c0 + kc + jj;
+            double acc = 0.0;
+            for (int q = 0; q < kc; ++q) {
+                const int c = c0 + q;
+                if (i - c <= bw) acc += L[c * ld + (i - c)] * L[c * ld + (j - c)];
+            }
+            L[j * ld + (i - j)] -= acc;
         }
         __syncthreads();
     }
-    // forward substitution L y = b
-    for (int c = 0; c < m; ++c) {
-        if (threadIdx.x < 8) B[c * 8 + threadIdx.x] /= L[c * ld];
+    // forward substitution L y = b, KB rows at a time: the first 8 lanes solve
+    // the diagonal block (one right-hand side each), then all threads update
+    // the <= bw rows below
+    for (int c0 = 0; c0 < m; c0 += KB) {
+        const int kc = min(KB, m - c0), nr = min(bw, m - c0 - kc);
+        if (threadIdx.x < 8) {
+            const int q = threadIdx.x;
+            for (int r = 0; r < kc; ++r) {
+                const int i = c0 + r;
+                double s = B[i * 8 + q];
+                for (int c = max(c0, i - bw); c < i; ++c) s -= L[c * ld + (i - c)] * B[c * 8 + q];
+                B[i * 8 + q] = s / L[i * ld];
+            }
+        }
         __syncthreads();
-        const int nd = min(bw, m - 1 - c);
-        for (int t = threadIdx.x; t < nd * 8; t += NT) {
-            const int d = t / 8 + 1, q = t % 8;
-            B[(c + d) * 8 + q] -= L[c * ld + d] * B[c * 8 + q];
+        for (int t = threadIdx.x; t < nr * 8; t += NT) {
+            const int i = c0 + kc + t / 8, q = t % 8;
+            double acc = 0.0;
+            for (int c = max(c0, i - bw); c < c0 + kc; ++c) acc += L[c * ld + (i - c)] * B[c * 8 + q];
+            B[i * 8 + q] -= acc;
         }
         __syncthreads();
     }
-    // backward substitution L^T x = y
-    for (int c = m - 1; c >= 0; --c) {
-        if (threadIdx.x < 8) B[c * 8 + threadIdx.x] /= L[c * ld];
+    // backward substitution L^T x = y, blocks in reverse: the diagonal block,
+    // then the <= bw rows above it
+    for (int c0 = ((m - 1) / KB) * KB; c0 >= 0; c0 -= KB) {
+        const int kc = min(KB, m - c0);
+        if (threadIdx.x < 8) {
+            const int q = threadIdx.x;
+            for (int r = kc - 1; r >= 0; --r) {
+                const int c = c0 + r;
+                double s = B[c * 8 + q];
+                for (int i = c + 1; i < min(c0 + kc, c + bw + 1); ++i) s -= L[c * ld + (i - c)] * B[i * 8 + q];
+                B[c * 8 + q] = s / L[c * ld];
+            }
+        }
         __syncthreads();
-        const int nd = min(bw, c);
-        for (int t = threadIdx.x; t < nd * 8; t += NT) {
-            const int d = t / 8 + 1, q = t % 8;
-            B[(c - d) * 8 + q] -= L[(c - d) * ld + d] * B[c * 8 + q];
+        const int lo = max(0, c0 - bw), na = c0 - lo;
+        for (int t = threadIdx.x; t < na * 8; t += NT) {
+            const int c = lo + t / 8, q = t % 8;
+            double acc = 0.0;
+            for (int i = c0; i < min(c0 + kc, c + bw + 1); ++i) acc += L[c * ld + (i - c)] * B[i * 8 + q];
+            B[c * 8 + q] -= acc;
         }
         __syncthreads();
     }
@@ -158,19 +226,18 @@ void launch_basis_vertices(cams_ctx *c)
     k_basis_vertices<<<(g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(g, c->a.P);
 }
 
-// Exact local solves of `count` regions with `nfree` open axes.
+// Exact local solves of `count` regions with `nfree` open axes (a subset of
+// that stage's regions: the LDS is sized for the stage's largest system).
 void launch_basis_regions(cams_ctx *c, int nfree, const Region *regs, int count)
 {
     if (count <= 0) return;
     const GridDev &g = c->g;
-    constexpr int E = kMaxRatio - 1;
+    const int cap = c->maxm[nfree] * (c->maxbw[nfree] + 1 + 8);
+    const size_t bytes = (size_t)cap * sizeof(double);
     if (nfree == 1)
-        k_basis_region<64, E, 1><<<count, 64, 0, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status);
-    else if (nfree == 2)
-        k_basis_region<kBlock, E * E, E><<<count, kBlock, 0, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status);
+        k_basis_region<64><<<count, 64, bytes, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status, cap);
     else
-        k_basis_region<kBlock, E * E * E, E * E><<<count, kBlock, 0, c->stream>>>(g, c->a.T, regs, c->a.P,
-                                                                            c->a.status);
+        k_basis_region<kBlock><<<count, kBlock, bytes, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status, cap);
 }
 
 void launch_basis(cams_ctx *c)

@@ -409,82 +409,6 @@ __global__ __launch_bounds__(kBlock) void k_lu_panel_lds(double *__restrict__ A,
     }
 }
 
-// Unpivoted LU of the diagonal block at (j0, j0) together with the inverses
-// of its two triangles (unit lower L, upper U; both padded with identity
-// beyond nb), in one workgroup.  Wave 0 factorises with one row per lane in
-// registers: at step c, lane c's row is final and is broadcast with
-// readlane, and every lower lane eliminates with it (no workgroup barrier
-// inside the 64 steps).  Then wave 0 inverts L and wave 1 inverts U, one
-// column per lane, reading the factor from LDS (all lanes read the same
-// element: broadcast).  Linv and Uinv are 64 x 64, leading dimension 64.
-__device__ __forceinline__ double bcast(double v, int lane)
-{
-    const unsigned long long u = __double_as_longlong(v);
-    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
-    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
-    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
-}
-
-__device__ __forceinline__ void lu_diag_inv_body(double *__restrict__ A, int n, int j0, int nb, int32_t *status,
-                                                 double *__restrict__ Linv, double *__restrict__ Uinv)
-{
-    __shared__ double D[kNB][kNB + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (wave == 0) {
-        double r[kNB];
-#pragma unroll
-        for (int j = 0; j < kNB; ++j)
-            r[j] = (lane < nb && j < nb) ? A[(size_t)(j0 + lane) * n + j0 + j] : (lane == j ? 1.0 : 0.0);
-        bool bad = false;
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) {
-            double pv = bcast(r[c], c);
-            if (!(pv > 0.0)) {
-                bad = true;
-                pv = 1.0;
-            }
-            const double rp = 1.0 / pv;
-            const double l = r[c] * rp;
-            if (lane > c) r[c] = l;
-#pragma unroll
-            for (int j = c + 1; j < kNB; ++j) {
-                const double u = bcast(r[j], c);
-                if (lane > c) r[j] -= l * u;
-            }
-        }
-        if (bad && lane == 0) atomicOr(status, F_SINGULAR_COARSE);
-#pragma unroll
-        for (int j = 0; j < kNB; ++j) D[lane][j] = r[j];
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nb * nb; t += kBlock) A[(size_t)(j0 + t / nb) * n + j0 + t % nb] = D[t / nb][t % nb];
-    if (wave == 0) {
-        // column `lane` of L^-1: x_r = -sum_{k<r} L[r][k] x_k, x_lane = 1
-        double x[kNB];
-#pragma unroll
-        for (int r = 0; r < kNB; ++r) {
-            double v = r == lane ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < r; ++k) v -= D[r][k] * x[k];
-            x[r] = r < lane ? 0.0 : v;
-        }
-#pragma unroll
-        for (int r = 0; r < kNB; ++r) Linv[r * kNB + lane] = x[r];
-    } else if (wave == 1) {
-        // column `lane` of U^-1: x_r = (e_r - sum_{k>r} U[r][k] x_k) / U[r][r]
-        double x[kNB];
-#pragma unroll
-        for (int r = kNB - 1; r >= 0; --r) {
-            double v = r == lane ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = r + 1; k < kNB; ++k) v -= D[r][k] * x[k];
-            x[r] = r > lane ? 0.0 : v / D[r][r];
-        }
-#pragma unroll
-        for (int r = 0; r < kNB; ++r) Uinv[r * kNB + lane] = x[r];
-    }
-}
-
 // Apply the panel's interchanges to the columns outside [j0, j0+nb).
 __global__ __launch_bounds__(kBlock) void k_lu_swap(double *__restrict__ A, int n, int j0, int nb,
                                                      const int32_t *__restrict__ piv)
@@ -738,14 +662,27 @@ __global__ __launch_bounds__(kBlock) void k_gemm(double *C, int ldc, const doubl
     gemm_tile(C, ldc, A, lda, B, ldb, M, Nn, K, alpha, beta, blockIdx.y * 64, blockIdx.x * 64);
 }
 
-// ---- batched unpivoted factorisation and inverse (MSFE instances of a
-// batch): every launch carries one descriptor per participating instance;
-// a GEMM launch covers all tiles of all its descriptors.
+// ---- batched Gauss-Jordan inverses (MSFE instances of a batch): every
+// launch carries one descriptor per participating instance; a GEMM launch
+// covers all tiles of all its descriptors, a pivot launch all workgroups of
+// all its pivot steps.
 
-__global__ __launch_bounds__(kBlock) void kb_lu_diag(const LuStep *__restrict__ st)
+// The pivot step whose workgroup range holds workgroup `wg` (binary search on wg0).
+__device__ __forceinline__ const GjPivotDesc &pivot_desc_of(const GjPivotDesc *__restrict__ p, int np, int wg)
 {
-    const LuStep s = st[blockIdx.x];
-    lu_diag_inv_body(s.F, s.n, s.j0, s.nb, s.status, s.Linv, s.Uinv);
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (p[mid].wg0 <= wg) lo = mid;
+        else hi = mid - 1;
+    }
+    return p[lo];
+}
+
+__global__ __launch_bounds__(kBlock) void kb_gj_pivot(const GjPivotDesc *__restrict__ p, int np)
+{
+    const GjPivotDesc &q = pivot_desc_of(p, np, blockIdx.x);
+    gj_pivot_wg(q.A, q.n, q.j0, q.nb, q.Cb, q.status, blockIdx.x - q.wg0);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_gemm(const GemmDesc *__restrict__ d, int nd)
@@ -790,10 +727,27 @@ __global__ __launch_bounds__(kBlock) void k_gj_update_pivot(const GemmDesc *__re
               (t % g.tiles_n) * 64);
 }
 
-__global__ __launch_bounds__(kBlock) void k_identity_piv(int32_t *__restrict__ piv, int n)
+// The batched form: the first `pw` workgroups are the pivot steps of the
+// next panel of every instance that has one, the others GEMM tiles.
+__global__ __launch_bounds__(kBlock) void kb_gj_update_pivot(const GjPivotDesc *__restrict__ p, int np, int pw,
+                                                              const GemmDesc *__restrict__ d, int nd)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t < n) piv[t] = t;
+    if ((int)blockIdx.x < pw) {
+        const GjPivotDesc &q = pivot_desc_of(p, np, blockIdx.x);
+        gj_pivot_wg(q.A, q.n, q.j0, q.nb, q.Cb, q.status, blockIdx.x - q.wg0);
+        return;
+    }
+    const int tile = blockIdx.x - pw;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc g = d[lo];
+    const int t = tile - g.tile0;
+    gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
+              (t % g.tiles_n) * 64);
 }
 
 // B = P I for the row interchanges of the factorisation (one thread builds
@@ -1033,13 +987,6 @@ void gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, const d
     gemm(c, C, ldc, A, lda, B, ldb, M, Nn, K, -1.0, 1.0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_identity64(double *__restrict__ X, int blocks)
-{
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= blocks * kNB * kNB) return;
-    const int e = t % (kNB * kNB);
-    X[t] = (e / kNB == e % kNB) ? 1.0 : 0.0;
-}
 
 }  // namespace
 
@@ -1056,132 +1003,6 @@ void launch_coarse_operator(cams_ctx *c)
     }
     k_coarse_box<<<n, kOpThreads, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.dmask, c->a.P, c->a.boxp);
     k_coarse_nodes<<<cdiv((size_t)27 * n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.boxp, c->a.Ac);
-}
-
-// The per-instance part of the batched MSFE factorisation: working copy of
-// A_c, identity triangle blocks and X = I.
-void launch_coarse_factor_prepare(cams_ctx *c)
-{
-    const int n = c->g.Nc;
-    const size_t nn = (size_t)n * n;
-    const int npan = (n + kNB - 1) / kNB;
-    k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, c->a.work, nn);
-    k_identity64<<<cdiv((size_t)2 * npan * kNB * kNB, kBlock), kBlock, 0, c->stream>>>(c->a.tri, 2 * npan);
-    k_identity_piv<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n);
-    k_perm_fill<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.piv + n, n, c->a.Ainv);
-}
-
-// The launches of the batched MSFE factorisation and inverse: unpivoted
-// blocked LU by 64-column panels (diagonal block factorised and its two
-// triangles inverted by one workgroup; L21 = A21 U11^-1, U12 = L11^-1 A12
-// and A22 -= L21 U12 as MFMA products), then X = U^-1 L^-1 by block
-// substitutions; every launch covers the same step of all instances.  (The
-// single-instance path inverts by Gauss-Jordan sweeps instead; the two agree
-// to rounding.)
-void plan_batch_lu(const std::vector<cams_ctx *> &fe, BatchLuPlan &plan)
-{
-    plan = BatchLuPlan();
-    int maxT = 0;
-    for (const cams_ctx *c : fe) maxT = std::max(maxT, (c->g.Nc + kNB - 1) / kNB);
-    auto add_gemm = [&](std::vector<GemmDesc> &v, double *C, int ldc, const double *A, int lda, const double *B,
-                        int ldb, int M, int Nn, int K, double alpha, double beta) {
-        if (M <= 0 || Nn <= 0 || K <= 0) return;
-        GemmDesc g{C, A, B, ldc, lda, ldb, M, Nn, K, alpha, beta, (int)cdiv(Nn, 64), 0};
-        v.push_back(g);
-    };
-    auto flush_gemms = [&](std::vector<GemmDesc> &v) {
-        if (v.empty()) return;
-        int tiles = 0;
-        for (GemmDesc &g : v) {
-            g.tile0 = tiles;
-            tiles += g.tiles_n * (int)cdiv(g.M, 64);
-        }
-        plan.launches.push_back({BatchLuPlan::GEMM, plan.gemms.size(), (int)v.size(), tiles});
-        plan.gemms.insert(plan.gemms.end(), v.begin(), v.end());
-        v.clear();
-    };
-    std::vector<GemmDesc> v;
-    for (int b = 0; b < maxT; ++b) {
-        std::vector<LuStep> steps;
-        for (const cams_ctx *c : fe) {
-            const int n = c->g.Nc, j0 = b * kNB;
-            if (j0 >= n) continue;
-            const int nb = std::min(kNB, n - j0);
-            double *Linv = c->a.tri + (size_t)(2 * b) * kNB * kNB;
-            steps.push_back({c->a.work, n, j0, nb, c->a.status, Linv, Linv + kNB * kNB});
-        }
-        plan.launches.push_back({BatchLuPlan::DIAG, plan.steps.size(), (int)steps.size(), 0});
-        plan.steps.insert(plan.steps.end(), steps.begin(), steps.end());
-        for (const cams_ctx *c : fe) {   // L21 = A21 U^-1 and U12 = L^-1 A12 (independent)
-            const int n = c->g.Nc, j0 = b * kNB;
-            if (j0 >= n) continue;
-            const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
-            if (rest <= 0) continue;
-            double *F = c->a.work, *Linv = c->a.tri + (size_t)(2 * b) * kNB * kNB, *Uinv = Linv + kNB * kNB;
-            double *A21 = F + (size_t)(j0 + nb) * n + j0, *A12 = F + (size_t)j0 * n + j0 + nb;
-            add_gemm(v, A21, n, A21, n, Uinv, kNB, rest, nb, nb, 1.0, 0.0);
-            add_gemm(v, A12, n, Linv, kNB, A12, n, nb, rest, nb, 1.0, 0.0);
-        }
-        flush_gemms(v);
-        for (const cams_ctx *c : fe) {   // A22 -= L21 U12
-            const int n = c->g.Nc, j0 = b * kNB;
-            if (j0 >= n) continue;
-            const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
-            if (rest <= 0) continue;
-            double *F = c->a.work;
-            add_gemm(v, F + (size_t)(j0 + nb) * n + j0 + nb, n, F + (size_t)(j0 + nb) * n + j0, n,
-                     F + (size_t)j0 * n + j0 + nb, n, rest, rest, nb, -1.0, 1.0);
-        }
-        flush_gemms(v);
-    }
-    for (int b = 0; b < maxT; ++b) {   // X = L^-1 X
-        for (const cams_ctx *c : fe) {
-            const int n = c->g.Nc, j0 = b * kNB;
-            if (j0 >= n) continue;
-            const int nb = std::min(kNB, n - j0);
-            double *Xb = c->a.Ainv + (size_t)j0 * n;
-            add_gemm(v, Xb, n, c->a.tri + (size_t)(2 * b) * kNB * kNB, kNB, Xb, n, nb, j0 + nb, nb, 1.0, 0.0);
-        }
-        flush_gemms(v);
-        for (const cams_ctx *c : fe) {
-            const int n = c->g.Nc, j0 = b * kNB;
-            if (j0 >= n) continue;
-            const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
-            double *X = c->a.Ainv, *F = c->a.work;
-            add_gemm(v, X + (size_t)(j0 + nb) * n, n, F + (size_t)(j0 + nb) * n + j0, n, X + (size_t)j0 * n, n,
-                     rest, j0 + nb, nb, -1.0, 1.0);
-        }
-        flush_gemms(v);
-    }
-    for (int b = maxT - 1; b >= 0; --b) {   // X = U^-1 X
-        for (const cams_ctx *c : fe) {
-            const int n = c->g.Nc, j0 = b * kNB;
-            if (j0 >= n) continue;
-            const int nb = std::min(kNB, n - j0);
-            double *Xb = c->a.Ainv + (size_t)j0 * n;
-            add_gemm(v, Xb, n, c->a.tri + (size_t)(2 * b + 1) * kNB * kNB, kNB, Xb, n, nb, n, nb, 1.0, 0.0);
-        }
-        flush_gemms(v);
-        for (const cams_ctx *c : fe) {
-            const int n = c->g.Nc, j0 = b * kNB;
-            if (j0 >= n || j0 == 0) continue;
-            const int nb = std::min(kNB, n - j0);
-            double *X = c->a.Ainv, *F = c->a.work;
-            add_gemm(v, X, n, F + j0, n, X + (size_t)j0 * n, n, j0, n, nb, -1.0, 1.0);
-        }
-        flush_gemms(v);
-    }
-}
-
-void launch_batch_lu(const BatchLuPlan &plan, const LuStep *steps, const GemmDesc *gemms, hipStream_t st)
-{
-    for (const BatchLuPlan::Launch &L : plan.launches) {
-        if (L.count <= 0) continue;
-        if (L.kind == BatchLuPlan::DIAG)
-            kb_lu_diag<<<L.count, kBlock, 0, st>>>(steps + L.off);
-        else
-            kb_gemm<<<L.tiles, kBlock, 0, st>>>(gemms + L.off, L.count);
-    }
 }
 
 // Descriptors of the three GEMM launches of every panel of the Gauss-Jordan
@@ -1276,6 +1097,109 @@ static void inverse_gj(cams_ctx *c, double *A, int m, int mat)
                                                                    Cb[(p + 1) & 1], c->a.status);
         } else if (e[1] > 0) {
             kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+        }
+    }
+}
+
+// ---- batched MSFE factorisation: the Gauss-Jordan sweeps of every FE
+// instance of a batch, one launch per step for all instances (the same
+// steps as inverse_gj, in place in each instance's Ainv).
+
+// Saved column blocks of an instance's dense sweep: its own buffer, or for
+// an instance that factorises by planes when alone (its buffer is sized for
+// one plane) the working matrix, which the dense sweep does not use.
+static void batch_gj_cb(const cams_ctx *c, double *Cb[2])
+{
+    const size_t n = (size_t)c->g.Nc;
+    double *base = c->blocktri ? c->a.work : c->a.gjcb;
+    Cb[0] = base;
+    Cb[1] = base + n * kNB;
+}
+
+// Per instance: A_c copied into Ainv, which the sweeps invert in place.
+void launch_coarse_factor_prepare(cams_ctx *c)
+{
+    const size_t nn = (size_t)c->g.Nc * c->g.Nc;
+    k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, c->a.Ainv, nn);
+}
+
+void plan_batch_gj(const std::vector<cams_ctx *> &fe, BatchGjPlan &plan)
+{
+    plan = BatchGjPlan();
+    const int m = (int)fe.size();
+    std::vector<std::vector<GemmDesc>> d(m);
+    std::vector<std::vector<int>> L(m);
+    int maxP = 0;
+    for (int i = 0; i < m; ++i) {
+        const cams_ctx *c = fe[i];
+        double *Cb[2];
+        batch_gj_cb(c, Cb);
+        gj_plan(c->a.Ainv, c->g.Nc, Cb, d[i], L[i]);
+        maxP = std::max(maxP, (c->g.Nc + kNB - 1) / kNB);
+    }
+    // pivot steps of panel p of every instance that has it
+    auto pivots = [&](int p, int &count, int &wgs) -> size_t {
+        const size_t off = plan.piv.size();
+        wgs = 0;
+        for (int i = 0; i < m; ++i) {
+            const cams_ctx *c = fe[i];
+            const int n = c->g.Nc, j0 = p * kNB;
+            if (j0 >= n) continue;
+            const int nb = std::min(kNB, n - j0);
+            double *Cb[2];
+            batch_gj_cb(c, Cb);
+            plan.piv.push_back(GjPivotDesc{c->a.Ainv, Cb[p & 1], c->a.status, n, j0, nb, wgs});
+            wgs += (int)gj_pivot_wgs(n, nb);
+        }
+        count = (int)(plan.piv.size() - off);
+        return off;
+    };
+    // launch h (0..2) of panel p of every instance, tiles renumbered
+    auto gemms = [&](int p, int h, int &count, int &tiles) -> size_t {
+        const size_t off = plan.gemms.size();
+        tiles = 0;
+        for (int i = 0; i < m; ++i) {
+            const int panels = (fe[i]->g.Nc + kNB - 1) / kNB;
+            if (p >= panels) continue;
+            const int *e = &L[i][3 * (3 * p + h)];
+            for (int k = 0; k < e[1]; ++k) {
+                GemmDesc g = d[i][e[0] + k];
+                g.tile0 += tiles;
+                plan.gemms.push_back(g);
+            }
+            tiles += e[2];
+        }
+        count = (int)(plan.gemms.size() - off);
+        return off;
+    };
+    BatchGjPlan::Launch first{BatchGjPlan::PIVOT, 0, 0, 0, 0, 0, 0};
+    first.poff = pivots(0, first.pcount, first.pw);
+    plan.launches.push_back(first);
+    for (int p = 0; p < maxP; ++p) {
+        for (int h = 0; h < 2; ++h) {
+            BatchGjPlan::Launch g{BatchGjPlan::GEMM, 0, 0, 0, 0, 0, 0};
+            g.goff = gemms(p, h, g.gcount, g.tiles);
+            if (g.gcount > 0) plan.launches.push_back(g);
+        }
+        BatchGjPlan::Launch u{BatchGjPlan::UPDATE_PIVOT, 0, 0, 0, 0, 0, 0};
+        u.poff = pivots(p + 1, u.pcount, u.pw);
+        u.goff = gemms(p, 2, u.gcount, u.tiles);
+        if (u.pcount + u.gcount > 0) plan.launches.push_back(u);
+    }
+}
+
+void launch_batch_gj(const BatchGjPlan &plan, const GjPivotDesc *piv, const GemmDesc *gemms, hipStream_t st)
+{
+    for (const BatchGjPlan::Launch &L : plan.launches) {
+        if (L.kind == BatchGjPlan::PIVOT) {
+            if (L.pcount > 0) kb_gj_pivot<<<L.pw, kBlock, 0, st>>>(piv + L.poff, L.pcount);
+        } else if (L.kind == BatchGjPlan::GEMM) {
+            kb_gemm<<<L.tiles, kBlock, 0, st>>>(gemms + L.goff, L.gcount);
+        } else if (L.pcount > 0) {
+            kb_gj_update_pivot<<<L.pw + L.tiles, kBlock, 0, st>>>(piv + L.poff, L.pcount, L.pw, gemms + L.goff,
+                                                                  L.gcount);
+        } else if (L.gcount > 0) {
+            kb_gemm<<<L.tiles, kBlock, 0, st>>>(gemms + L.goff, L.gcount);
         }
     }
 }

@@ -142,7 +142,8 @@ void launch_convert_matrix32(cams_ctx *c)
     const size_t n = (size_t)c->g.N;
     k_to_f32<<<blocks_of(3 * n), kBlock, 0, c->stream>>>(c->a.W, c->a.W32, 3 * n);
     k_to_f32<<<blocks_of(n), kBlock, 0, c->stream>>>(c->a.diag, c->a.diag32, n);
-    k_to_f32<<<blocks_of(n), kBlock, 0, c->stream>>>(c->a.invd, c->a.invd32, n);
+    const size_t npiv = c->opt.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0 ? 2 * n : n;   // both pivot sets
+    k_to_f32<<<blocks_of(npiv), kBlock, 0, c->stream>>>(c->a.invd, c->a.invd32, npiv);
 }
 
 void launch_round_basis(cams_ctx *c)

@@ -6,6 +6,15 @@
 // const, 22 levels for a full block); the Richardson residual of each step
 // still uses the full matrix.
 //
+// The alternating form takes every other step on a second block grid,
+// shifted cyclically by half a block on every axis longer than one block
+// (a shorter axis is one block either way): along x the block
+// holds 8 consecutive positions p, cell i = (p - ox) mod nx.  The block that
+// wraps round the end of an axis is two pieces with no coupling between
+// them (the coupling of cell nx-1 to its +x side is the zero boundary
+// face), so it is still one block of the same shape for the kernels; the
+// faces the first grid leaves out are inside the blocks of the second.
+//
 // For the 7-point matrix in natural order ILU(0) keeps the off-diagonals of
 // A and only modifies the diagonal: d_i = a_ii - sum_{j<i} W_ij^2 / d_j.
 // One application of M^{-1} z is then
@@ -37,8 +46,29 @@ struct BlockCell {
     bool active;
 };
 
+// Offsets of the shifted block grid: half a block on every axis longer than
+// one block.  An axis of at most one block stays unshifted: its single block
+// holds the whole axis either way, and the cyclic positions would put the
+// grid neighbours at positions n-1 and 0 at the two ends of that block.
+struct Shift {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Shift block_shift(const GridDev &g, int shifted)
+{
+    if (!shifted) return Shift{0, 0, 0};
+    return Shift{g.nx > SB ? SB / 2 : 0, g.ny > SB ? SB / 2 : 0, g.nz > SB ? SB / 2 : 0};
+}
+
+// Cell coordinate of position p on an axis of n cells shifted by o < n.
+__device__ __forceinline__ int wrap_cell(int p, int o, int n)
+{
+    const int i = p - o;
+    return i < 0 ? i + n : i;
+}
+
 // Cell of this thread in logical block `id` (x fastest, then y, then z).
-__device__ __forceinline__ BlockCell block_cell(const GridDev &g, int id)
+__device__ __forceinline__ BlockCell block_cell(const GridDev &g, int id, Shift o)
 {
     BlockCell b;
     const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
@@ -52,27 +82,30 @@ __device__ __forceinline__ BlockCell block_cell(const GridDev &g, int id)
     b.lj = (b.t >> 3) & (SB - 1);
     b.lk = b.t >> 6;
     b.active = b.li < b.ex && b.lj < b.ey && b.lk < b.ez;
-    b.i = i0 + b.li;
-    b.j = j0 + b.lj;
-    b.k = k0 + b.lk;
+    b.i = wrap_cell(i0 + b.li, o.x, g.nx);
+    b.j = wrap_cell(j0 + b.lj, o.y, g.ny);
+    b.k = wrap_cell(k0 + b.lk, o.z, g.nz);
     b.n = b.active ? b.i + g.nx * (b.j + g.ny * b.k) : 0;
     return b;
 }
 
-// Pivots of the block ILU(0), once per assembled matrix.
+// Pivots of the block ILU(0), once per assembled matrix (`shifted`: on the
+// shifted block grid).  A cell's lower neighbour in the block is its lower
+// neighbour in the grid, except at the seam of a wrapped block (cell 0 after
+// cell n-1), where the two are not coupled.
 __global__ __launch_bounds__(ST) void k_bilu_setup(GridDev g, const double *__restrict__ W,
                                                     const double *__restrict__ diag, double *__restrict__ invd,
-                                                    int32_t *status)
+                                                    int32_t *status, int shifted)
 {
     __shared__ double d[ST];
-    const BlockCell b = block_cell(g, xcd_swizzle(blockIdx.x, gridDim.x));
+    const BlockCell b = block_cell(g, xcd_swizzle(blockIdx.x, gridDim.x), block_shift(g, shifted));
     const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
     double dg = 1.0, wxm = 0.0, wym = 0.0, wzm = 0.0;
     if (b.active) {
         dg = diag[b.n];
-        if (b.li > 0) wxm = Wx[b.n - 1];
-        if (b.lj > 0) wym = Wy[b.n - g.nx];
-        if (b.lk > 0) wzm = Wz[b.n - g.sxy];
+        if (b.li > 0 && b.i > 0) wxm = Wx[b.n - 1];
+        if (b.lj > 0 && b.j > 0) wym = Wy[b.n - g.nx];
+        if (b.lk > 0 && b.k > 0) wzm = Wz[b.n - g.sxy];
     }
     d[b.t] = 1.0;
     __syncthreads();
@@ -309,11 +342,13 @@ __device__ __forceinline__ void cube_fill(const GridDev &g, const FromCoarse<T, 
     }
 }
 
+// `o`: offsets of the block grid (the prolongating first step takes the
+// grid at the origin only).  i0, j0, k0 are positions on the shifted axes.
 template <class T, class TR, int NT, int SW = 0, class TP = void>
 __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
                                                const T *__restrict__ invd, const TR *__restrict__ rhs,
                                                const T *__restrict__ eold, T *__restrict__ enew, int blk,
-                                               SmoothLds<T> &L, FromCoarse<T, TP> fc = {})
+                                               SmoothLds<T> &L, Shift o, FromCoarse<T, TP> fc = {})
 {
     constexpr int CPT = ST / NT;   // cells per thread
     const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
@@ -410,7 +445,8 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         const int t = threadIdx.x + NT * c;
         const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
         const bool act = li < ex && lj < ey && lk < ez;
-        const int i = i0 + (act ? li : 0), j = j0 + (act ? lj : 0), k = k0 + (act ? lk : 0);
+        const int i = wrap_cell(i0 + (act ? li : 0), o.x, g.nx), j = wrap_cell(j0 + (act ? lj : 0), o.y, g.ny);
+        const int k = wrap_cell(k0 + (act ? lk : 0), o.z, g.nz);
         const int n = i + g.nx * (j + g.ny * k);
         const bool xm = i > 0, xp = i + 1 < g.nx, ym = j > 0, yp = j + 1 < g.ny, zm = k > 0, zp = k + 1 < g.nz;
         const int nxm = xm ? n - 1 : n, nxp = xp ? n + 1 : n, nym = ym ? n - g.nx : n, nyp = yp ? n + g.nx : n;
@@ -479,7 +515,9 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         const int t = threadIdx.x + NT * c;
         const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
         if (li < ex && lj < ey && lk < ez)
-            enew[(i0 + li) + g.nx * ((j0 + lj) + g.ny * (k0 + lk))] = e0[c] + L.y[PAD + t];
+            enew[wrap_cell(i0 + li, o.x, g.nx) +
+                 g.nx * (wrap_cell(j0 + lj, o.y, g.ny) + g.ny * wrap_cell(k0 + lk, o.z, g.nz))] =
+                e0[c] + L.y[PAD + t];
     }
 }
 
@@ -493,11 +531,12 @@ template <class T, class TR, int NT, int SW>
 __global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
                                                    const T *__restrict__ invd, const TR *__restrict__ rhs,
                                                    const T *__restrict__ eold, T *__restrict__ enew,
-                                                   const int32_t *done)
+                                                   const int32_t *done, int shifted)
 {
     __shared__ SmoothLds<T> lds;
     if (done && *done) return;
-    bilu_step_body<T, TR, NT, SW>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds);
+    bilu_step_body<T, TR, NT, SW>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds,
+                                  block_shift(g, shifted));
 }
 
 // The first post-smoothing step, whose e_old is the prolongated coarse
@@ -517,7 +556,7 @@ __global__ __launch_bounds__(NT) void k_bilu_first(GridDev g, const T *__restric
     __shared__ double xs[kXcLds];
     if (done && *done) return;
     bilu_step_body<T, TR, NT, SW, TP>(g, W, diag, invd, rhs, nullptr, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds,
-                                      FromCoarse<T, TP>{P, dm, xc, cube, xs});
+                                      Shift{0, 0, 0}, FromCoarse<T, TP>{P, dm, xc, cube, xs});
 }
 
 // Batched step `s` of `steps` for every instance.  `post` selects the
@@ -537,6 +576,7 @@ __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ i
         const InstDev &d = inst[w.inst];
         if (d.a.ictl[C_DONE]) continue;
         const Arrays &a = d.a;
+        const int shifted = d.alt && (s & 1);   // alternating smoother: odd steps on the shifted grid
         const T *W, *diag, *invd;
         T *e, *scratch;
         if constexpr (sizeof(T) == 4) {
@@ -557,7 +597,8 @@ __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ i
         T *buf[2] = {e, scratch};
         T *out = buf[(steps - 1 - s) & 1];
         const T *prev = s > 0 ? buf[(steps - s) & 1] : init;
-        bilu_step_body<T, TR, NT>(d.g, W, diag, invd, rhs, prev, out, w.blk, lds);
+        bilu_step_body<T, TR, NT>(d.g, W, diag, shifted ? invd + d.g.N : invd, rhs, prev, out, w.blk, lds,
+                                  block_shift(d.g, shifted));
     }
 }
 
@@ -568,9 +609,20 @@ inline int num_sblocks(const GridDev &g)
 
 }  // namespace
 
+// Pivots of the block grid at the origin into invd[0, N); for the
+// alternating smoother also those of the shifted grid into invd[N, 2N).
 void launch_bilu_setup(cams_ctx *c)
 {
-    k_bilu_setup<<<num_sblocks(c->g), ST, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd, c->a.status);
+    k_bilu_setup<<<num_sblocks(c->g), ST, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd, c->a.status, 0);
+    if (c->opt.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0)
+        k_bilu_setup<<<num_sblocks(c->g), ST, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.invd + c->g.N,
+                                                             c->a.status, 1);
+}
+
+// Whether step s of a smoothing stage takes the shifted block grid.
+static inline int step_shifted(const cams_ctx *c, int s)
+{
+    return c->opt.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0 && (s & 1);
 }
 
 template <class T, class TR>
@@ -592,12 +644,14 @@ void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR
     const bool in_regs = nb <= resident_workgroups((const void *)k_bilu_step<T, TR, kSmoothThreads, 1>, kSmoothThreads);
     for (int s = 0; s < steps; ++s) {
         T *out = buf[(steps - 1 - s) & 1];
+        const int sh = step_shifted(c, s);
+        const T *iv = sh ? invd + c->g.N : invd;
         if (in_regs)
-            k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, invd, rhs,
-                                                                                        prev, out, done);
+            k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, iv, rhs,
+                                                                                        prev, out, done, sh);
         else
             k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(
-                c->g, W, diag, invd, rhs, prev, out, done);
+                c->g, W, diag, iv, rhs, prev, out, done, sh);
         prev = out;
     }
     if (timed) prof_end(c);
@@ -632,12 +686,14 @@ void bilu_smooth_from_coarse(cams_ctx *c, const T *W, const T *diag, const T *in
                                                      kSmoothThreads);
     for (int s = 1; s < steps; ++s) {
         out = buf[(steps - 1 - s) & 1];
+        const int sh = step_shifted(c, s);
+        const T *iv = sh ? invd + c->g.N : invd;
         if (regs_step)
-            k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, invd, rhs,
-                                                                                        prev, out, done);
+            k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, iv, rhs,
+                                                                                        prev, out, done, sh);
         else
             k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(
-                c->g, W, diag, invd, rhs, prev, out, done);
+                c->g, W, diag, iv, rhs, prev, out, done, sh);
         prev = out;
     }
     if (timed) prof_end(c);

@@ -16,7 +16,7 @@ import pytest
 import oracle
 from tests.gpu_util import log, rel_err, require_gpu, to_np
 from workloads import small_problem
-from workloads.configs import FE, FP64, FV, MIXED_BF16, MIXED_FP32, batch_problems
+from workloads.configs import FE, FP64, FV, MIXED_BF16, MIXED_FP32, SMOOTH_BLOCK, SMOOTH_BLOCK_ALT, batch_problems
 
 pytestmark = pytest.mark.gpu
 
@@ -26,8 +26,9 @@ def torch():
     return require_gpu()
 
 
-def _instances(precision, n_pre=0, rtol=1e-12):
-    """Uneven shapes, ratios and restrictions, one instance at rest."""
+def _instances(precision, n_pre=0, rtol=1e-12, alt=False):
+    """Uneven shapes, ratios and restrictions, one instance at rest; with
+    `alt` every other instance takes the alternating block smoother."""
     specs = [
         ((16, 12, 8), 4, FE, dict(sigma=2.0, seed=3, c=0.1)),
         ((19, 17, 11), (4, 3, 5), FE, dict(sigma=2.5, seed=4, c=0.05)),
@@ -39,9 +40,11 @@ def _instances(precision, n_pre=0, rtol=1e-12):
         ((16, 12, 8), 4, FE, dict(sigma=2.0, seed=10, c=0.1, wells="none")),   # at rest: r0 = 0
     ]
     out = []
-    for shape, r, restr, kw in specs:
+    for q, (shape, r, restr, kw) in enumerate(specs):
         pb = small_problem(*shape, r, restriction=restr, n_pre=n_pre, **kw)
-        out.append(pb.with_options(precision=precision, lin_rtol=rtol, newton_maxit=1))
+        pb = pb.with_options(precision=precision, lin_rtol=rtol, newton_maxit=1,
+                             smoother=SMOOTH_BLOCK_ALT if alt and q % 2 == 0 else SMOOTH_BLOCK)
+        out.append(pb)
     return out
 
 
@@ -69,9 +72,10 @@ def _oracle_update(pb, lin_rtol):
     return p - p0, st
 
 
-@pytest.mark.parametrize("precision", [FP64, MIXED_FP32, MIXED_BF16])
-def test_batch_matches_oracle(torch, precision):
-    pbs = _instances(precision)
+@pytest.mark.parametrize("precision,alt", [(FP64, False), (MIXED_FP32, False), (MIXED_BF16, False),
+                                           (FP64, True), (MIXED_FP32, True)])
+def test_batch_matches_oracle(torch, precision, alt):
+    pbs = _instances(precision, alt=alt)
     b, status, stats, p = _run_batch(torch, pbs)
     log("batch", precision, status, [s["lin_iters_last"] for s in stats], b.tuning())
     for pb, s, st, pg in zip(pbs, status, stats, p):
@@ -88,10 +92,11 @@ def test_batch_matches_oracle(torch, precision):
     b.close()
 
 
-@pytest.mark.parametrize("precision,n_pre", [(FP64, 0), (FP64, 2), (MIXED_FP32, 1), (MIXED_BF16, 0)])
-def test_batch_matches_single_path(torch, precision, n_pre):
+@pytest.mark.parametrize("precision,n_pre,alt", [(FP64, 0, False), (FP64, 2, False), (MIXED_FP32, 1, False),
+                                                 (MIXED_BF16, 0, False), (FP64, 3, True), (MIXED_FP32, 0, True)])
+def test_batch_matches_single_path(torch, precision, n_pre, alt):
     from paper_1705_05783_amd.solver import Solver
-    pbs = _instances(precision, n_pre=n_pre, rtol=1e-8)
+    pbs = _instances(precision, n_pre=n_pre, rtol=1e-8, alt=alt)
     b, status, stats, p = _run_batch(torch, pbs)
     for pb, s, st, pg in zip(pbs, status, stats, p):
         assert s == 0, (pb.name, s)

@@ -15,7 +15,7 @@ import pytest
 import oracle
 from tests.gpu_util import log, rel_err, require_gpu, solver_for, to_np
 from workloads import config1, config2, small_problem
-from workloads.configs import FE, FV, SMOOTH_BLOCK, SMOOTH_REDBLACK
+from workloads.configs import FE, FV, SMOOTH_BLOCK, SMOOTH_BLOCK_ALT, SMOOTH_REDBLACK
 
 pytestmark = pytest.mark.gpu
 
@@ -126,12 +126,24 @@ def test_matrix_core_gemm(_gpu, M, N, K):
     assert np.max(np.abs(to_np(Ct) - ref)) <= 1e-13 * max(1.0, np.abs(ref).max()) * K
 
 
-@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK])
-@pytest.mark.parametrize("shape,r", SHAPES[:5] + [((37, 29, 19), 4), ((75, 70, 45), 8)])
+def _oracle_smooth(pb, W, diag, z):
+    """The oracle's smoother application; for the alternating smoother the
+    two Richardson steps from zero (origin blocks, then shifted blocks)."""
+    ilu = oracle.smoother_for(pb, W, diag)
+    if not isinstance(ilu, tuple):
+        return ilu.apply(z)
+    x = ilu[0].apply(z)
+    return x + ilu[1].apply(z - oracle.matvec(pb, W, diag, x))
+
+
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK, SMOOTH_BLOCK_ALT])
+@pytest.mark.parametrize("shape,r", SHAPES + [((37, 29, 19), 4), ((75, 70, 45), 8)])
 def test_smoother_apply(_gpu, shape, r, smoother):
     """One smoother application against the oracle's.  The small grids have
     fewer 8^3 blocks than the device has compute units (register sweeps); the
-    75x70x45 grid (540 blocks, ragged on every axis) takes the LDS sweeps."""
+    75x70x45 grid (540 blocks, ragged on every axis) takes the LDS sweeps.
+    The shifted block grid wraps round every axis (axes shorter than a block
+    included)."""
     torch = _gpu
     pb = _pb(shape, r, sigma=2.0, seed=6)
     pb.smoother = smoother
@@ -147,14 +159,20 @@ def test_smoother_apply(_gpu, shape, r, smoother):
     s.coarse_op()
     T = oracle.transmissibility(pb)
     W, diag, _, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
-    ilu = oracle.smoother_for(pb, W, diag)
     z = rng.normal(size=pb.n)
     z[~free] = 0.0
     x = to_np(s.smooth_apply(torch.as_tensor(z, device="cuda")))
-    assert rel_err(x, ilu.apply(z)) <= 1e-12
+    assert rel_err(x, _oracle_smooth(pb, W, diag, z)) <= 1e-12
+    if smoother == SMOOTH_BLOCK_ALT:
+        # inverse pivots of both block grids: 1 / diag(U) of the oracle's factors
+        iv = to_np(s.export(C.CAMS_ARR_INVD)).reshape(2, -1)
+        for h, f in enumerate(oracle.smoother_for(pb, W, diag)):
+            rp, col, val = f.export()
+            dpos = [rp[t] + int(np.nonzero(col[rp[t]:rp[t + 1]] == t)[0][0]) for t in range(pb.n)]
+            assert rel_err(iv[h], 1.0 / val[dpos]) <= 1e-13
 
 
-@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK])
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK, SMOOTH_BLOCK_ALT])
 @pytest.mark.parametrize("restriction,n_pre", [(FE, 0), (FV, 0), (FV, 5)])
 @pytest.mark.parametrize("shape,r", [((16, 12, 8), 4), ((24, 24, 16), 8), ((20, 20, 1), 4)])
 def test_linear_solve(_gpu, shape, r, restriction, n_pre, smoother):
@@ -213,7 +231,10 @@ def test_newton_config1_2d_msfv(_gpu):
                                                            ((24, 24, 16), 8, FE, SMOOTH_BLOCK),
                                                            ((24, 24, 16), 8, FV, SMOOTH_BLOCK),
                                                            ((24, 24, 16), 8, FE, SMOOTH_REDBLACK),
-                                                           ((13, 11, 1), (3, 4, 1), FE, SMOOTH_BLOCK)])
+                                                           ((13, 11, 1), (3, 4, 1), FE, SMOOTH_BLOCK),
+                                                           ((19, 17, 11), (4, 3, 5), FE, SMOOTH_BLOCK_ALT),
+                                                           ((24, 24, 16), 8, FV, SMOOTH_BLOCK_ALT),
+                                                           ((13, 11, 1), (3, 4, 1), FE, SMOOTH_BLOCK_ALT)])
 def test_newton_3d(_gpu, shape, r, restriction, smoother):
     pb = _pb(shape, r, sigma=2.5, seed=8, restriction=restriction, c=0.08, dt=0.05)
     pb.smoother = smoother
@@ -295,16 +316,18 @@ def test_determinism_bitwise(_gpu):
 
 # ---------------------------------------------------------------- mixed precision ----
 
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_BLOCK_ALT])
 @pytest.mark.parametrize("precision", [1, 2])
 @pytest.mark.parametrize("shape,r,restriction", [((24, 24, 16), 8, FE), ((19, 17, 11), (4, 3, 5), FV),
                                                   ((20, 20, 1), 4, FE)])
-def test_mixed_linear_solve_meets_fp64_residual(_gpu, shape, r, restriction, precision):
+def test_mixed_linear_solve_meets_fp64_residual(_gpu, shape, r, restriction, precision, smoother):
     """Mixed FP32/BF16 smoother + prolongation with FP64 refinement: the
     update satisfies the FP64 linear system to the requested 1e-8 relative
     residual, recomputed independently by the oracle."""
     torch = _gpu
     pb = _pb(shape, r, sigma=2.5, seed=9, restriction=restriction)
     pb.precision = precision
+    pb.smoother = smoother
     s = solver_for(pb)
     s.build_basis()
     p = pb.initial_pressure()

@@ -524,3 +524,16 @@ def test_config1_newton_alternating_smoother_matches_direct_newton():
     assert rc == 0
     ref, _ = helpers.direct_newton(pb, T, p0, p0, tol=1e-12)
     assert np.max(np.abs(p - ref)) <= 1e-10 * np.abs(ref).max()
+
+
+def test_shift_on_a_single_block_axis_changes_nothing():
+    """An axis no longer than a block is one block for any offset: the
+    shifted factor equals the unshifted one there (8 x 8 x 8 grid)."""
+    pb = small_problem(8, 8, 8, 4, sigma=2.0)
+    T = oracle.transmissibility(pb)
+    p = np.random.default_rng(14).uniform(0, 1, pb.n)
+    W, diag, r, _ = oracle.linear_system(pb, T, p, pb.initial_pressure())
+    a = oracle.ILU0(pb, W, diag, block=(8, 8, 8))
+    b = oracle.ILU0(pb, W, diag, block=(8, 8, 8), shift=(4, 4, 4))
+    for u, v in zip(a.export(), b.export()):
+        assert np.array_equal(u, v)

@@ -33,6 +33,7 @@ MIXED_BF16 = 2
 
 SMOOTH_BLOCK = 0      # block-Jacobi ILU(0) on 8x8x8 blocks
 SMOOTH_REDBLACK = 1   # ILU(0) in red-black order
+SMOOTH_BLOCK_ALT = 2  # block ILU(0), every other step on the half-block-shifted block grid
 
 
 @dataclasses.dataclass
@@ -65,7 +66,7 @@ class Problem:
     newton_tol: float = 1e-8
     newton_maxit: int = 30
     precision: int = FP64
-    smoother: int = SMOOTH_BLOCK
+    smoother: int = SMOOTH_BLOCK_ALT
 
     @property
     def n(self) -> int:
