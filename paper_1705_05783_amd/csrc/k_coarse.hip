@@ -11,8 +11,8 @@
 //    the next update; MSFV: LU with partial pivoting by panels, then the
 //    inverse from the factors with the same kernels.  Large MSFE coarse grids
 //    are eliminated plane by plane (block tridiagonal).
-//  - the batched MSFE factorisation of many instances (blocked LU, every
-//    instance's step in one launch).
+//  - the batched MSFE factorisation of many instances (the same Gauss-Jordan
+//    sweeps, every instance's step in one launch).
 #include "cams_internal.h"
 #include "dev_util.h"
 
@@ -87,43 +87,62 @@ __global__ __launch_bounds__(kOpThreads) void k_coarse_box(GridDev g, const doub
         const int tt = act ? t : 0;
         const int ci[3] = {x0 + tt % ex, y0 + (tt / ex) % ey, z0 + tt / (ex * ey)};
         const int n = ci[0] + g.nx * (ci[1] + g.ny * ci[2]);
+        // every load of the cell first (basis of the cell and of its six
+        // neighbours, couplings, masks, node tables), so that they are all in
+        // flight together; a neighbour outside the grid reads the cell itself
+        int nm[6], cm[6];
+        bool inside[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int a = f >> 1, dir = (f & 1) ? 1 : -1;
+            const int ext = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+            const int stride = a == 0 ? 1 : (a == 1 ? g.nx : g.sxy);
+            inside[f] = dir < 0 ? ci[a] > 0 : ci[a] + 1 < ext;
+            nm[f] = inside[f] ? n + dir * stride : n;
+            cm[f] = inside[f] ? ci[a] + dir : ci[a];
+        }
+        double pc[8], pn[6][8], cf[6];
+        uint8_t dmn[6];
+        int lon[6];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) pc[s] = P[(size_t)s * g.N + n];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int a = f >> 1;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) pn[f][s] = P[(size_t)s * g.N + nm[f]];
+            cf[f] = (f & 1) ? Wa[a][n] : Wa[a][nm[f]];
+            dmn[f] = dm[nm[f]];
+            lon[f] = g.lo[a][cm[f]];
+        }
+        const double dg = diag[n];
         const bool keep = act && !dm[n];
+        __builtin_amdgcn_sched_barrier(0);
         double w[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             const bool in = la + (s & 1) < g.nb[0] && lb + ((s >> 1) & 1) < g.nb[1] && lc + (s >> 2) < g.nb[2];
-            const double pv = P[(size_t)s * g.N + n];
-            w[s] = keep && in ? pv : 0.0;
+            w[s] = keep && in ? pc[s] : 0.0;
         }
         double v[64];
 #pragma unroll
         for (int q = 0; q < 64; ++q) v[q] = 0.0;
-        {
-            const double dg = diag[n];
 #pragma unroll
-            for (int s = 0; s < 8; ++s) v[u_index(s & 1, (s >> 1) & 1, s >> 2)] += dg * P[(size_t)s * g.N + n];
-        }
+        for (int s = 0; s < 8; ++s) v[u_index(s & 1, (s >> 1) & 1, s >> 2)] += dg * pc[s];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int ext = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
-            const int stride = a == 0 ? 1 : (a == 1 ? g.nx : g.sxy);
+        for (int f = 0; f < 6; ++f) {
+            const int a = f >> 1, dir = (f & 1) ? 1 : -1;
+            const double coef = -cf[f];
+            const bool ok = inside[f] && !dmn[f];
+            const bool moved = lon[f] != Lv[a];   // the neighbour's lower node is L + dir e_a
 #pragma unroll
-            for (int dir = -1; dir <= 1; dir += 2) {
-                const bool inside = dir < 0 ? ci[a] > 0 : ci[a] + 1 < ext;
-                const int nm = inside ? n + dir * stride : n;
-                const int cm = inside ? ci[a] + dir : ci[a];
-                const double coef = -(dir > 0 ? Wa[a][n] : Wa[a][nm]);
-                const bool ok = inside && !dm[nm];
-                const bool moved = g.lo[a][cm] != Lv[a];   // the neighbour's lower node is L + dir e_a
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int t3[3] = {s & 1, (s >> 1) & 1, s >> 2};
-                    const double val = ok ? coef * P[(size_t)s * g.N + nm] : 0.0;
-                    int us[3] = {t3[0], t3[1], t3[2]};
-                    v[u_index(us[0], us[1], us[2])] += moved ? 0.0 : val;
-                    us[a] += dir;
-                    v[u_index(us[0], us[1], us[2])] += moved ? val : 0.0;
-                }
+            for (int s = 0; s < 8; ++s) {
+                const int t3[3] = {s & 1, (s >> 1) & 1, s >> 2};
+                const double val = ok ? coef * pn[f][s] : 0.0;
+                int us[3] = {t3[0], t3[1], t3[2]};
+                v[u_index(us[0], us[1], us[2])] += moved ? 0.0 : val;
+                us[a] += dir;
+                v[u_index(us[0], us[1], us[2])] += moved ? val : 0.0;
             }
         }
 #pragma unroll
