@@ -570,9 +570,14 @@ __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ i
                                                     const int32_t *nwork, int post, int s, int steps)
 {
     __shared__ SmoothLds<T> lds;
-    CAMS_FOR_ITEMS(t, nwork)
-    {
-        const WorkItem w = work[t];
+    // each workgroup takes items blockIdx.x, + gridDim.x, ...; the next
+    // item's descriptor is loaded while the current one runs
+    const int nw = *nwork;
+    int t = blockIdx.x;
+    WorkItem wnext = t < nw ? work[t] : WorkItem{0, 0};
+    for (; t < nw; t += gridDim.x) {
+        const WorkItem w = wnext;
+        if (t + (int)gridDim.x < nw) wnext = work[t + gridDim.x];
         const InstDev &d = inst[w.inst];
         if (d.a.ictl[C_DONE]) continue;
         const Arrays &a = d.a;
