@@ -503,9 +503,9 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
 // so that the sequential pivot inverse overlaps the matrix-core update.
 
 // Workgroup 0: D^-1 of the nb x nb pivot block (padded to 64 x 64 with the
-// identity) by the same sweep on single entries, 4 x 4 entries per thread,
-// pivot row and column through LDS (two buffers, one barrier per pivot);
-// writes it into A[J,J].  Workgroups 1..: Cb[i][c] = A[i][j0 + c] for the
+// identity) by the same sweep on entries two at a time, 4 x 4 entries per
+// thread, the two pivot rows and columns through LDS (two buffers, one
+// barrier per pair of pivots); writes it into A[J,J].  Workgroups 1..: Cb[i][c] = A[i][j0 + c] for the
 // rows i outside J.
 __device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j0, int nb, double *__restrict__ Cb,
                                             int32_t *status, int blk)
@@ -518,7 +518,7 @@ __device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j
         Cb[(size_t)i * nb + cc] = A[(size_t)i * n + j0 + cc];
         return;
     }
-    __shared__ double colk[2][kNB], rowk[2][kNB];
+    __shared__ double colk[2][2][kNB], rowk[2][2][kNB];
     const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
     double a[4][4];
 #pragma unroll
@@ -529,39 +529,75 @@ __device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j
             a[r][c] = (i < nb && j < nb) ? A[(size_t)(j0 + i) * n + j0 + j] : (i == j ? 1.0 : 0.0);
         }
     bool bad = false;
+    // two pivots per step: with J = {k, k+1}, P = D[J,J] and Q = P^-1,
+    //   D[J,J] <- Q,  D[J,~J] <- Q D[J,~J],  D[~J,J] <- -D[~J,J] Q,
+    //   D[~J,~J] <- D[~J,~J] - D[~J,J] Q D[J,~J]
+    // (the same sweep, two columns at a time: half the barriers, one
+    // reciprocal per step)
 #pragma unroll
-    for (int k = 0; k < kNB; ++k) {
-        const int kg = k >> 2, kr = k & 3, b = k & 1;
+    for (int k = 0; k < kNB; k += 2) {
+        const int kg = k >> 2, kr = k & 3, b = (k >> 1) & 1;
         if (tj == kg)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) colk[b][4 * ti + r] = a[r][kr];
+            for (int r = 0; r < 4; ++r) {
+                colk[b][0][4 * ti + r] = a[r][kr];
+                colk[b][1][4 * ti + r] = a[r][kr + 1];
+            }
         if (ti == kg)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) rowk[b][4 * tj + c] = a[kr][c];
+            for (int c = 0; c < 4; ++c) {
+                rowk[b][0][4 * tj + c] = a[kr][c];
+                rowk[b][1][4 * tj + c] = a[kr + 1][c];
+            }
         __syncthreads();
-        double p = rowk[b][k];
-        if (!(p > 0.0 && p < 1e300)) {   // not positive definite (or not finite)
+        const double p00 = rowk[b][0][k], p01 = rowk[b][0][k + 1], p10 = rowk[b][1][k], p11 = rowk[b][1][k + 1];
+        double det = p00 * p11 - p01 * p10;
+        if (!(p00 > 0.0 && p00 < 1e300 && det > 0.0 && det < 1e300)) {   // not positive definite (or not finite)
             bad = true;
-            p = 1.0;
+            det = 1.0;
         }
-        // 1/p by the hardware estimate and two Newton steps (relative error
-        // near 1 ulp) instead of the correctly rounded division sequence, which
-        // sits on this loop's critical path 64 times
-        double ip = __builtin_amdgcn_rcp(p);
-        ip = ip * (2.0 - p * ip);
-        ip = ip * (2.0 - p * ip);
-        double ck[4], rk[4];
+        // 1/det by the hardware estimate and two Newton steps (relative error
+        // near 1 ulp) instead of the correctly rounded division sequence
+        double id = __builtin_amdgcn_rcp(det);
+        id = id * (2.0 - det * id);
+        id = id * (2.0 - det * id);
+        const double q00 = p11 * id, q01 = -p01 * id, q10 = -p10 * id, q11 = p00 * id;
+        double u0[4], u1[4], c0[4], c1[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) ck[r] = colk[b][4 * ti + r] * ip;
+        for (int c = 0; c < 4; ++c) {
+            const double r0 = rowk[b][0][4 * tj + c], r1 = rowk[b][1][4 * tj + c];
+            u0[c] = q00 * r0 + q01 * r1;
+            u1[c] = q10 * r0 + q11 * r1;
+        }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) rk[c] = rowk[b][4 * tj + c];
+        for (int r = 0; r < 4; ++r) {
+            c0[r] = colk[b][0][4 * ti + r];
+            c1[r] = colk[b][1][4 * ti + r];
+        }
+        // every entry as if off the pivot rows and columns (two FMAs), then
+        // the owners of the pivot rows, columns and block overwrite theirs
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
+            for (int c = 0; c < 4; ++c) a[r][c] -= c0[r] * u0[c] + c1[r] * u1[c];
+        if (ti == kg)
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const bool onrow = ti == kg && r == kr, oncol = tj == kg && c == kr;
-                a[r][c] = onrow ? (oncol ? ip : a[r][c] * ip) : (oncol ? -a[r][c] * ip : a[r][c] - ck[r] * rk[c]);
+                a[kr][c] = u0[c];
+                a[kr + 1][c] = u1[c];
             }
+        if (tj == kg)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a[r][kr] = -(c0[r] * q00 + c1[r] * q10);
+                a[r][kr + 1] = -(c0[r] * q01 + c1[r] * q11);
+            }
+        if (ti == kg && tj == kg) {
+            a[kr][kr] = q00;
+            a[kr][kr + 1] = q01;
+            a[kr + 1][kr] = q10;
+            a[kr + 1][kr + 1] = q11;
+        }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
