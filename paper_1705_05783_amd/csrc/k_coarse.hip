@@ -534,9 +534,14 @@ __device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j
     //   D[~J,~J] <- D[~J,~J] - D[~J,J] Q D[J,~J]
     // (the same sweep, two columns at a time: half the barriers, one
     // reciprocal per step)
+    // the loop over the 16 tile columns stays rolled: its body (two pivot
+    // pairs) is reused from the instruction cache, where the fully unrolled
+    // sweep would stream every instruction once
+#pragma nounroll
+    for (int kg = 0; kg < kNB / 4; ++kg)
 #pragma unroll
-    for (int k = 0; k < kNB; k += 2) {
-        const int kg = k >> 2, kr = k & 3, b = (k >> 1) & 1;
+    for (int h = 0; h < 2; ++h) {
+        const int kr = 2 * h, k = 4 * kg + kr, b = h;
         if (tj == kg)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
