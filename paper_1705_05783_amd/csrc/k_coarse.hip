@@ -888,18 +888,30 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
         stop_test(partial, nparts, ictl, scal, rtol2, maxit, xs);
         return;
     }
-    const double *xv = x;
-    if (slots) {
-        for (int k = threadIdx.x; k < n; k += kBlock) xs[k] = node_sum(g, slots, fe, k);
-        __syncthreads();
-        xv = xs;
-    }
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const double *mr = M + (size_t)(row < n ? row : 0) * n;
+    if (slots) {
+        // R r formed in LDS: the row's entries are loaded first, so that
+        // their latency overlaps the node sums (n <= kGemvLds)
+        constexpr int Q = kGemvLds / 64;
+        double mv[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) mv[q] = lane + 64 * q < n ? mr[lane + 64 * q] : 0.0;
+        for (int k = threadIdx.x; k < n; k += kBlock) xs[k] = node_sum(g, slots, fe, k);
+        __syncthreads();
+        if (row >= n) return;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (lane + 64 * q < n) s += mv[q] * xs[lane + 64 * q];
+        s = wave_sum(s);
+        if (lane == 0) y[row] = s;
+        return;
+    }
     if (row >= n) return;
-    const double *mr = M + (size_t)row * n;
     double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += mr[c] * xv[c];
+    for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
     s = wave_sum(s);
     if (lane == 0) y[row] = s;
 }
