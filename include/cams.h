@@ -177,8 +177,11 @@ cams_status cams_assemble(cams_ctx *ctx, const double *p_dev, const double *pn_d
 cams_status cams_build_basis(cams_ctx *ctx);
 
 /* Coarse operator A_c = R A P_hat (Eq. (13); P_hat = basis with Dirichlet rows
- * zeroed, R = R^FV of Eq. (7) or P_hat^T) and its factorisation (LU with
- * partial pivoting, then the explicit inverse used by every coarse solve).
+ * zeroed, R = R^FV of Eq. (7) or P_hat^T) and the explicit inverse used by
+ * every coarse solve: MSFV by LU with partial pivoting; MSFE (symmetric
+ * positive definite) by Gauss-Jordan sweeps without pivoting, or, above 4096
+ * coarse nodes with at least 3 coarse z-planes, by block elimination over
+ * the z-planes (one dense inverse per plane).
  * Errors: CAMS_E_STATE (no basis or no assembled system), CAMS_E_BREAKDOWN
  * (singular coarse matrix). */
 cams_status cams_coarse_op(cams_ctx *ctx);
