@@ -228,7 +228,7 @@ void tune_smoother(cams_batch *b)
 {
     const int steps = std::max(1, b->n_post > 0 ? b->n_post : b->n_pre);
     const int kind = b->n_post > 0 ? 1 : 0;
-    int best = kNumSmooth - 1;
+    int best = 0;
     for (int k = 0; k < kNumSmooth; ++k) {
         launch_batch_smooth(L(b, L_SBLOCK), steps, kind, b->mixed, kSmoothNT[k]);   // warm
         CAMS_HIP(hipEventRecord(b->ev[2], b->stream));
@@ -238,7 +238,7 @@ void tune_smoother(cams_batch *b)
         float ms = 0.f;
         CAMS_HIP(hipEventElapsedTime(&ms, b->ev[2], b->ev[3]));
         b->smooth_ms[k] = ms / steps;
-        if (b->smooth_ms[k] < b->smooth_ms[best]) best = k;
+        if (b->smooth_ms[k] < b->smooth_ms[best]) best = k;   // compared with measured sizes only
     }
     b->smooth_nt = kSmoothNT[best];
 }

@@ -129,6 +129,9 @@ def test_batch_second_call_replays_the_tuned_graph(torch):
     t = b.tuning()
     log("tuning", t)
     assert t["iters_per_graph"] in (2, 4, 8) and t["smoother_threads"] in (128, 256, 512)
+    # the tuner keeps the fastest smoother workgroup size it measured
+    ms = t["ms_per_smooth_step"]
+    assert ms[(128, 256, 512).index(t["smoother_threads"])] == min(ms)
     assert runs[0][1] == runs[1][1]
     for a, c in zip(runs[0][0], runs[1][0]):
         assert np.array_equal(a, c)
