@@ -12,7 +12,7 @@ headline value is the mixed-precision solve (FP32 smoother, basis storage
 and prolongation; FP64 residual, update and coarse solve); the plain FP64
 solve of the same workload is timed beside it.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the solve runs on one GPU.
 """
 
 from __future__ import annotations
@@ -278,7 +278,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the large and learned-basis workloads")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the solve runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
