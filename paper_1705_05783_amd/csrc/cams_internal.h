@@ -316,6 +316,12 @@ struct GemmDesc {
     int ldc, lda, ldb, M, N, K;
     double alpha, beta;
     int tiles_n, tile0;
+    // Optional (null when unused).  pre, S: B is not read from memory but
+    // formed per tile as pre (K x K, row pitch ldc) times S (K x N, row pitch
+    // 64).  copy: the descriptor's first tile also writes its result there
+    // (row pitch 64).
+    const double *pre, *S;
+    double *copy;
 };
 struct BatchGjPlan {
     enum Kind { PIVOT = 0, GEMM = 1, UPDATE_PIVOT = 2 };

@@ -500,7 +500,9 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
 // Three launches per panel: the panel products (one launch), the update of
 // the next panel's columns, and the rest of the update together with the
 // next panel's pivot-block inverse (and the copy of its old column block),
-// so that the sequential pivot inverse overlaps the matrix-core update.
+// so that the sequential pivot inverse overlaps the matrix-core update.  In
+// the single-matrix sweep the first two share one launch from the second
+// panel on (k_gj_panel).
 
 // Workgroup 0: D^-1 of the nb x nb pivot block (padded to 64 x 64 with the
 // identity) by the same sweep on entries two at a time, 4 x 4 entries per
@@ -641,7 +643,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int KS = 32;
 
 __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, int lda, const double *B, int ldb,
-                                          int M, int Nn, int K, double alpha, double beta, int tm, int tn)
+                                          int M, int Nn, int K, double alpha, double beta, int tm, int tn,
+                                          double *copy = nullptr)
 {
     __shared__ double As[64][KS + 1];
     __shared__ double Bs[KS][64 + 1];
@@ -711,7 +714,9 @@ __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, i
                 const int c = tn + wn + b * 16 + (lane & 15);
                 if (r < M && c < Nn) {
                     const double prod = alpha * acc[a][b][v];
-                    C[(size_t)r * ldc + c] = beta == 0.0 ? prod : beta * cv[a][b][v] + prod;
+                    const double out = beta == 0.0 ? prod : beta * cv[a][b][v] + prod;
+                    C[(size_t)r * ldc + c] = out;
+                    if (copy) copy[(size_t)(r - tm) * 64 + (c - tn)] = out;
                 }
             }
 }
@@ -784,6 +789,36 @@ __global__ __launch_bounds__(kBlock) void k_gj_update_pivot(const GemmDesc *__re
     const GemmDesc g = d[lo];
     const int t = tile - g.tile0;
     gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
+              (t % g.tiles_n) * 64, t == 0 ? g.copy : nullptr);
+}
+
+// The panel products of a Gauss-Jordan panel and the update of the next
+// panel's columns in one launch.  The column update needs the scaled pivot
+// rows D^-1 A[J,J2], which the row-scaling tiles of the same launch are
+// overwriting; each column-update tile therefore forms them itself, in LDS,
+// from the copy of A[J,J2] that the previous update launch saved (S) and
+// D^-1 (pre), by the same tile product as the row-scaling tile (so the
+// values are bitwise the ones that tile writes).
+__global__ __launch_bounds__(kBlock) void k_gj_panel(const GemmDesc *__restrict__ d, int nd)
+{
+    __shared__ double Ts[64 * 65];
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc g = d[lo];
+    const int t = blockIdx.x - g.tile0;
+    const double *B = g.B;
+    int ldb = g.ldb;
+    if (g.pre) {   // uniform over the workgroup
+        gemm_tile(Ts, 65, g.pre, g.ldc, g.S, 64, g.K, g.N, g.K, 1.0, 0.0, 0, 0);
+        __syncthreads();
+        B = Ts;
+        ldb = 65;
+    }
+    gemm_tile(g.C, g.ldc, g.A, g.lda, B, ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
               (t % g.tiles_n) * 64);
 }
 
@@ -1083,8 +1118,11 @@ void launch_coarse_operator(cams_ctx *c)
 // the next pivot step).  Panel p saves its old column block in Cb[p & 1]
 // (row stride nb), so the next pivot step can fill the other buffer while
 // the update still reads this one.  Each launch entry of L is (offset,
-// count, tiles).
-static void gj_plan(double *A, int n, double *const Cb[2], std::vector<GemmDesc> &d, std::vector<int> &L)
+// count, tiles).  With a 64 x 64 buffer S, the rest update of panel p also
+// saves A[J_{p+1}, J_{p+2}] there, and panel p+1 runs its panel products and
+// the next panel's columns in one launch (k_gj_panel; the second entry of
+// that panel is then empty).
+static void gj_plan(double *A, int n, double *const Cb[2], double *S, std::vector<GemmDesc> &d, std::vector<int> &L)
 {
     std::vector<GemmDesc> v;
     auto add = [&](double *C, const double *Aop, int lda, const double *B, int M, int N, int K, double al,
@@ -1116,18 +1154,31 @@ static void gj_plan(double *A, int n, double *const Cb[2], std::vector<GemmDesc>
         add(rowJ + j0 + nb, Dq, n, rowJ + j0 + nb, nb, rest, nb, 1.0, 0.0);
         add(A + j0, A + j0, n, Dq, j0, nb, nb, -1.0, 0.0);
         add(A + (size_t)(j0 + nb) * n + j0, A + (size_t)(j0 + nb) * n + j0, n, Dq, rest, nb, nb, -1.0, 0.0);
-        flush();
         // A[~J,~J] -= Cb[~J] A[J,~J]: first the next panel's columns, then the rest
+        const bool merged = S != nullptr && p > 0;   // A[J,J2] saved by the previous panel's update
+        if (!merged) flush();
         const int r0[2] = {0, j0 + nb}, rn[2] = {j0, rest};
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 2; ++u) {
+            const size_t before = v.size();
             add(A + (size_t)r0[u] * n + j0 + nb, Cbp + (size_t)r0[u] * nb, nb, rowJ + j0 + nb, rn[u], nb2, nb, -1.0,
                 1.0);
+            if (merged && v.size() > before) {
+                v.back().B = nullptr;
+                v.back().pre = Dq;
+                v.back().S = S;
+            }
+        }
         flush();
+        if (merged) flush();   // the second entry stays empty
         const int c0[2] = {0, j0 + nb + nb2}, cn[2] = {j0, rest - nb2};
         for (int u = 0; u < 2; ++u)
-            for (int w = 0; w < 2; ++w)
+            for (int w = 0; w < 2; ++w) {
+                const size_t before = v.size();
                 add(A + (size_t)r0[u] * n + c0[w], Cbp + (size_t)r0[u] * nb, nb, rowJ + c0[w], rn[u], cn[w], nb, -1.0,
                     1.0);
+                // its first tile is A[J_{p+1}, J_{p+2}]: rows from j0 + nb, columns from j0 + nb + nb2
+                if (S != nullptr && u == 1 && w == 1 && v.size() > before) v.back().copy = S;
+            }
         flush();
     }
 }
@@ -1140,7 +1191,8 @@ static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m)
     std::vector<GemmDesc> d;
     c->gj_launch.clear();
     double *const Cb[2] = {c->a.gjcb, c->a.gjcb + (size_t)m * kNB};
-    for (double *A : mats) gj_plan(A, m, Cb, d, c->gj_launch);
+    double *const S = c->a.gjcb + (size_t)2 * m * kNB;
+    for (double *A : mats) gj_plan(A, m, Cb, S, d, c->gj_launch);
     if (!d.empty())
         CAMS_HIP(hipMemcpyAsync(c->a.gjd, d.data(), d.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, c->stream));
     CAMS_HIP(hipStreamSynchronize(c->stream));   // d is a local buffer
@@ -1148,8 +1200,9 @@ static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m)
 }
 
 // In-place inverse of matrix `mat` (the mat-th of gj_prepare's list), m x m.
-// Per panel: the panel products, the update of the next panel's columns,
-// then the rest of the update together with the next pivot step.
+// Per panel: the panel products and the update of the next panel's columns
+// (one launch from the second panel on), then the rest of the update
+// together with the next pivot step.
 static void inverse_gj(cams_ctx *c, double *A, int m, int mat)
 {
     const int panels = (m + kNB - 1) / kNB;
@@ -1159,8 +1212,13 @@ static void inverse_gj(cams_ctx *c, double *A, int m, int mat)
                                                                            c->a.status);
     for (int p = 0; p < panels; ++p) {
         const int *e = &c->gj_launch[3 * 3 * (mat * panels + p)];
-        for (int h = 0; h < 2; ++h, e += 3)
-            if (e[1] > 0) kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+        if (e[1] > 0) {
+            if (p > 0) k_gj_panel<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+            else kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+        }
+        e += 3;
+        if (e[1] > 0) kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+        e += 3;
         const int j1 = (p + 1) * kNB;
         if (j1 < m) {
             const int nb1 = std::min(kNB, m - j1);
@@ -1206,7 +1264,7 @@ void plan_batch_gj(const std::vector<cams_ctx *> &fe, BatchGjPlan &plan)
         const cams_ctx *c = fe[i];
         double *Cb[2];
         batch_gj_cb(c, Cb);
-        gj_plan(c->a.Ainv, c->g.Nc, Cb, d[i], L[i]);
+        gj_plan(c->a.Ainv, c->g.Nc, Cb, nullptr, d[i], L[i]);
         maxP = std::max(maxP, (c->g.Nc + kNB - 1) / kNB);
     }
     // pivot steps of panel p of every instance that has it
