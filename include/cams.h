@@ -19,7 +19,11 @@
  *    memory, copied before the call returns.
  *  - All device work is enqueued on the HIP stream given to cams_create.
  *    Calls that return a host-visible number (eps_norm_out, cams_stats)
- *    synchronise that stream; the others return after enqueueing.
+ *    synchronise that stream; the others return after enqueueing.  The one
+ *    exception is the block elimination of cams_coarse_op (below): half of
+ *    it runs on a second stream that the context creates (default priority)
+ *    and joins back to the given stream with an event before the call
+ *    returns, so later work on the given stream sees the complete result.
  *  - The library allocates no device memory of its own beyond one small
  *    pinned host buffer: all device state lives in a caller-provided
  *    workspace (cams_workspace_bytes / cams_set_workspace), typically a
@@ -181,7 +185,8 @@ cams_status cams_build_basis(cams_ctx *ctx);
  * every coarse solve: MSFV by LU with partial pivoting; MSFE (symmetric
  * positive definite) by Gauss-Jordan sweeps without pivoting, or, above 4096
  * coarse nodes with at least 3 coarse z-planes, by block elimination over
- * the z-planes (one dense inverse per plane).
+ * the z-planes (one dense inverse per plane) from both ends towards the
+ * middle plane, the two chains at the same time on two streams.
  * Errors: CAMS_E_STATE (no basis or no assembled system), CAMS_E_BREAKDOWN
  * (singular coarse matrix). */
 cams_status cams_coarse_op(cams_ctx *ctx);

@@ -431,7 +431,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     {   // 44 Gauss-Jordan GEMM descriptors (MSFE): 8 per 64-column panel of each inverted matrix
         const size_t mats = c->blocktri ? (size_t)nb[2] : 1, dim = c->blocktri ? (size_t)nb[0] * nb[1] : nc;
         put(L.add(O.restriction == CAMS_R_FE ? mats * ((dim + 63) / 64) * 12 * sizeof(GemmDesc) : 0));
-        put(L.add(O.restriction == CAMS_R_FE ? (2 * dim * 64 + 64 * 64) * 8 : 0));   // 45 saved column blocks, saved pivot rows
+        put(L.add(O.restriction == CAMS_R_FE ? (c->blocktri ? 2 : 1) * (2 * dim * 64 + 64 * 64) * 8 : 0));   // 45 saved column blocks, saved pivot rows (per chain)
     }
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
@@ -511,6 +511,18 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
         }
         for (int e = 0; e < 8; ++e)
             if (hipEventCreate(&c->ev[e]) != hipSuccess) c->ev[e] = nullptr;
+        // the second elimination chain of the block-tridiagonal factorisation
+        // (default priority); without it both chains run on the caller's stream
+        if (c->blocktri) {
+            if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
+            if (c->side && (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+                            hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess)) {
+                if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+                (void)hipStreamDestroy(c->side);
+                c->side = nullptr;
+                c->fork_ev = nullptr;
+            }
+        }
     }
     const cams_ctx &t = *c;
     for (int ax = 0; ax < 3; ++ax) {
@@ -1096,6 +1108,12 @@ cams_status cams_destroy(cams_ctx *c)
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     for (int e = 0; e < 8; ++e)
         if (c->ev[e]) (void)hipEventDestroy(c->ev[e]);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipEventDestroy(c->fork_ev);
+        (void)hipEventDestroy(c->join_ev);
+        (void)hipStreamDestroy(c->side);
+    }
     delete c;
     return CAMS_OK;
 }

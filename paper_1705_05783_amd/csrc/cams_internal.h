@@ -174,6 +174,9 @@ struct cams_ctx {
     int cur_dp;
     double *host;           // pinned host scalars
     hipEvent_t ev[8];
+    // second stream and its fork / join events (block-tridiagonal factorisation only)
+    hipStream_t side;
+    hipEvent_t fork_ev, join_ev;
     cams_stats last;
     std::string err;
     // host copies of the per-axis tables and dual regions (uploaded by

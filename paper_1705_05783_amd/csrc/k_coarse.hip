@@ -951,22 +951,44 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
     if (lane == 0) y[row] = s;
 }
 
-// y = alpha M x + beta y for an m-row block M (leading dimension ldm, ncol
-// columns), one workgroup per row (the blocks have ~1000 rows, so a whole
-// workgroup per row keeps enough loads in flight); used by the
-// block-tridiagonal coarse solve.
-__global__ __launch_bounds__(kBlock) void k_gemv_ab(const double *__restrict__ M, int ldm, int m, int ncol,
-                                                     const double *__restrict__ x, double *y, double alpha,
-                                                     double beta, const int32_t *done)
+// Two independent products y = alpha M x + beta y with m x m matrices (row
+// pitch m) in one launch, for the two chains of the block-tridiagonal
+// substitutions: workgroups [0, m) are the rows of the first, [m, 2m) those
+// of the second (a launch of m workgroups runs the first alone).
+struct GemvJob {
+    const double *M, *x;
+    double *y;
+    double alpha, beta;
+};
+__global__ __launch_bounds__(kBlock) void k_gemv_pair(GemvJob j0, GemvJob j1, int m, const int32_t *done)
 {
     __shared__ double sh[kBlock / 64];
     if (done && *done) return;
-    const int row = blockIdx.x;
-    const double *mr = M + (size_t)row * ldm;
+    const bool second = (int)blockIdx.x >= m;
+    const GemvJob j = second ? j1 : j0;
+    const int row = (int)blockIdx.x - (second ? m : 0);
+    const double *mr = j.M + (size_t)row * m;
     double s = 0.0;
-    for (int c = threadIdx.x; c < ncol; c += kBlock) s += mr[c] * x[c];
+    for (int c = threadIdx.x; c < m; c += kBlock) s += mr[c] * j.x[c];
     s = block_sum<kBlock>(s, sh);
-    if (threadIdx.x == 0) y[row] = beta == 0.0 ? alpha * s : beta * y[row] + alpha * s;
+    if (threadIdx.x == 0) j.y[row] = j.beta == 0.0 ? j.alpha * s : j.beta * j.y[row] + j.alpha * s;
+}
+
+// y_k = E_k x_k for every plane k at once (E: the planes' m x m blocks one
+// after another, so row R of the launch is row R of E; x, y: m per plane).
+__global__ __launch_bounds__(kBlock) void k_gemv_planes(const double *__restrict__ E, int m,
+                                                         const double *__restrict__ x, double *__restrict__ y,
+                                                         const int32_t *done)
+{
+    __shared__ double sh[kBlock / 64];
+    if (done && *done) return;
+    const size_t R = blockIdx.x;
+    const double *mr = E + R * m;
+    const double *xk = x + (R / m) * m;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < m; c += kBlock) s += mr[c] * xk[c];
+    s = block_sum<kBlock>(s, sh);
+    if (threadIdx.x == 0) y[R] = s;
 }
 
 // dst (rows x cols, ldd) = src (lds)
@@ -1183,16 +1205,28 @@ static void gj_plan(double *A, int n, double *const Cb[2], double *S, std::vecto
     }
 }
 
+// Buffers of the Gauss-Jordan sweeps of chain `ch` (the block-tridiagonal
+// form runs two elimination chains at once; everything else uses chain 0):
+// the two saved column blocks (m x kNB each), then the saved pivot-row tile
+// (64 x 64).
+static double *gj_buf(const cams_ctx *c, int m, int ch)
+{
+    return c->a.gjcb + (size_t)ch * ((size_t)2 * m * kNB + 64 * 64);
+}
+
 // The descriptors of every matrix the factorisation inverts, uploaded once
-// per workspace (the matrices live at fixed places in it).
-static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m)
+// per workspace (the matrices live at fixed places in it); matrix i uses the
+// buffers of chain chains[i].
+static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, const std::vector<int> &chains, int m)
 {
     if (c->gj_ready) return;
     std::vector<GemmDesc> d;
     c->gj_launch.clear();
-    double *const Cb[2] = {c->a.gjcb, c->a.gjcb + (size_t)m * kNB};
-    double *const S = c->a.gjcb + (size_t)2 * m * kNB;
-    for (double *A : mats) gj_plan(A, m, Cb, S, d, c->gj_launch);
+    for (size_t i = 0; i < mats.size(); ++i) {
+        double *const base = gj_buf(c, m, chains[i]);
+        double *const Cb[2] = {base, base + (size_t)m * kNB};
+        gj_plan(mats[i], m, Cb, base + (size_t)2 * m * kNB, d, c->gj_launch);
+    }
     if (!d.empty())
         CAMS_HIP(hipMemcpyAsync(c->a.gjd, d.data(), d.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, c->stream));
     CAMS_HIP(hipStreamSynchronize(c->stream));   // d is a local buffer
@@ -1202,31 +1236,33 @@ static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, int m)
 // In-place inverse of matrix `mat` (the mat-th of gj_prepare's list), m x m.
 // Per panel: the panel products and the update of the next panel's columns
 // (one launch from the second panel on), then the rest of the update
-// together with the next pivot step.
-static void inverse_gj(cams_ctx *c, double *A, int m, int mat)
+// together with the next pivot step.  Enqueued on stream st with the
+// buffers of chain ch (as given to gj_prepare for this matrix).
+static void inverse_gj(cams_ctx *c, double *A, int m, int mat, int ch, hipStream_t st)
 {
     const int panels = (m + kNB - 1) / kNB;
     const GemmDesc *dd = (const GemmDesc *)c->a.gjd;
-    double *const Cb[2] = {c->a.gjcb, c->a.gjcb + (size_t)m * kNB};
-    k_gj_pivot<<<gj_pivot_wgs(m, std::min(kNB, m)), kBlock, 0, c->stream>>>(A, m, 0, std::min(kNB, m), Cb[0],
-                                                                           c->a.status);
+    double *const base = gj_buf(c, m, ch);
+    double *const Cb[2] = {base, base + (size_t)m * kNB};
+    k_gj_pivot<<<gj_pivot_wgs(m, std::min(kNB, m)), kBlock, 0, st>>>(A, m, 0, std::min(kNB, m), Cb[0],
+                                                                    c->a.status);
     for (int p = 0; p < panels; ++p) {
         const int *e = &c->gj_launch[3 * 3 * (mat * panels + p)];
         if (e[1] > 0) {
-            if (p > 0) k_gj_panel<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
-            else kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+            if (p > 0) k_gj_panel<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
+            else kb_gemm<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
         }
         e += 3;
-        if (e[1] > 0) kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+        if (e[1] > 0) kb_gemm<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
         e += 3;
         const int j1 = (p + 1) * kNB;
         if (j1 < m) {
             const int nb1 = std::min(kNB, m - j1);
             const unsigned pw = gj_pivot_wgs(m, nb1);
-            k_gj_update_pivot<<<pw + e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1], (int)pw, A, m, j1, nb1,
+            k_gj_update_pivot<<<pw + e[2], kBlock, 0, st>>>(dd + e[0], e[1], (int)pw, A, m, j1, nb1,
                                                                    Cb[(p + 1) & 1], c->a.status);
         } else if (e[1] > 0) {
-            kb_gemm<<<e[2], kBlock, 0, c->stream>>>(dd + e[0], e[1]);
+            kb_gemm<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
         }
     }
 }
@@ -1335,9 +1371,18 @@ void launch_batch_gj(const BatchGjPlan &plan, const GjPivotDesc *piv, const Gemm
 }
 
 // Blocks of the block-tridiagonal form (coarse nodes ordered plane by plane
-// in z, m = nb_x nb_y nodes per plane, Z planes): E_k = S_k^-1 with the
-// Schur complements S_0 = D_0, S_k = D_k - L_k E_{k-1} U_{k-1}; F_k = L_k
-// E_{k-1} and G_k = E_k U_k.  Stored in Ainv as E (Z m^2), F, G.
+// in z, m = nb_x nb_y nodes per plane, Z planes, L_k / U_k the blocks that
+// couple plane k with planes k - 1 / k + 1), eliminated from both ends
+// towards the twist plane t = (Z - 1) / 2, so the two chains of dense
+// inversions run at the same time:
+//   top, k < t:     S_0 = D_0, S_k = D_k - F_k U_{k-1},  F_k = L_k E_{k-1},
+//                   G_k = E_k U_k;
+//   bottom, k > t:  S_{Z-1} = D_{Z-1}, S_k = D_k - H_k L_{k+1},
+//                   H_k = U_k E_{k+1},  K_k = E_k L_k;
+//   twist:          S_t = D_t - F_t U_{t-1} - H_t L_{t+1};
+// E_k = S_k^-1 for every plane.  Stored in Ainv as E (Z m^2), then F_k at
+// slot k (k = 1..t) and H_k at slot k + 1 (k = t..Z-2), then G_k at slot k
+// (k < t) and K_k at slot k (k > t).
 static void blocktri_parts(const cams_ctx *c, double *&E, double *&Fk, double *&G, int &m, int &Z)
 {
     m = c->g.nb[0] * c->g.nb[1];
@@ -1348,63 +1393,120 @@ static void blocktri_parts(const cams_ctx *c, double *&E, double *&Fk, double *&
     G = Fk + Z * mm;
 }
 
+inline int twist_plane(int Z) { return (Z - 1) / 2; }
+
 // A_c of an MSFE problem couples only nodes of adjacent z-planes (a basis
 // function vanishes on the vertex planes next to its own), so the coarse
 // operator is block tridiagonal by planes.  Factorisation by block
-// elimination: Z dense m x m inversions on matrix cores instead of one
-// Nc x Nc inversion (Nc = Z m); the products with the off-diagonal plane
-// blocks L_k, U_k use their 9-point sparsity.
+// elimination from both ends: Z dense m x m inversions on matrix cores
+// instead of one Nc x Nc inversion (Nc = Z m), at most Z - t of them in
+// sequence (the bottom chain runs on the context's second stream); the
+// products with the off-diagonal plane blocks use their 9-point sparsity.
 static void factor_blocktri(cams_ctx *c)
 {
     double *E, *Fk, *G;
     int m, Z;
     blocktri_parts(c, E, Fk, G, m, Z);
-    const int n = c->g.Nc;
+    const int n = c->g.Nc, t = twist_plane(Z);
     const size_t mm = (size_t)m * m;
     const double *Ac = c->a.Ac;
     auto D = [&](int k) { return Ac + (size_t)k * m * n + (size_t)k * m; };
     auto Lo = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k - 1) * m; };
     auto Up = [&](int k) { return Ac + (size_t)k * m * n + (size_t)(k + 1) * m; };
-    double *Uc = c->a.work;   // column nonzeros of U_{k-1}, m x 9
+    // column nonzeros (m x 9) of a coupling block, one buffer per chain
+    double *const Uc[2] = {c->a.work, c->a.work + (size_t)9 * m};
     const int nbx = c->g.nb[0], nby = c->g.nb[1];
     const dim3 rows(cdiv(m, kBlock), m);
+    const unsigned cols9 = cdiv((size_t)9 * m, kBlock), cells = cdiv(mm, kBlock);
     std::vector<double *> mats;
-    for (int k = 0; k < Z; ++k) mats.push_back(E + k * mm);
-    gj_prepare(c, mats, m);
+    std::vector<int> chains;
     for (int k = 0; k < Z; ++k) {
-        double *S = E + k * mm;   // S_k, inverted in place into E_k
-        k_copy2d<<<cdiv(mm, kBlock), kBlock, 0, c->stream>>>(D(k), n, S, m, m, m);
-        if (k > 0) {
-            // F_k = L_k E_{k-1}; S_k -= F_k U_{k-1}
-            k_plane_left<<<rows, kBlock, 0, c->stream>>>(Fk + k * mm, Lo(k), n, E + (k - 1) * mm, m, nbx, nby);
-            k_plane_cols<<<cdiv((size_t)9 * m, kBlock), kBlock, 0, c->stream>>>(Uc, Up(k - 1), n, m, nbx, nby);
-            k_plane_right<<<rows, kBlock, 0, c->stream>>>(S, Fk + k * mm, Uc, m, nbx, nby, 1);
-        }
-        inverse_gj(c, S, m, k);
-        if (k > 0)   // G_{k-1} = E_{k-1} U_{k-1} (E_{k-1} is final once S_k is formed)
-            k_plane_right<<<rows, kBlock, 0, c->stream>>>(G + (k - 1) * mm, E + (k - 1) * mm, Uc, m, nbx, nby, 0);
+        mats.push_back(E + k * mm);
+        chains.push_back(k > t ? 1 : 0);
     }
+    gj_prepare(c, mats, chains, m);
+    hipStream_t s0 = c->stream, s1 = c->side ? c->side : c->stream;
+    if (s1 != s0) {
+        CAMS_HIP(hipEventRecord(c->fork_ev, s0));
+        CAMS_HIP(hipStreamWaitEvent(s1, c->fork_ev, 0));
+    }
+    // top chain, planes 0 .. t-1
+    for (int k = 0; k < t; ++k) {
+        double *S = E + k * mm;
+        k_copy2d<<<cells, kBlock, 0, s0>>>(D(k), n, S, m, m, m);
+        if (k > 0) {
+            k_plane_left<<<rows, kBlock, 0, s0>>>(Fk + k * mm, Lo(k), n, E + (k - 1) * mm, m, nbx, nby);
+            k_plane_cols<<<cols9, kBlock, 0, s0>>>(Uc[0], Up(k - 1), n, m, nbx, nby);
+            k_plane_right<<<rows, kBlock, 0, s0>>>(S, Fk + k * mm, Uc[0], m, nbx, nby, 1);
+        }
+        inverse_gj(c, S, m, k, 0, s0);
+        if (k > 0)   // G_{k-1} = E_{k-1} U_{k-1}
+            k_plane_right<<<rows, kBlock, 0, s0>>>(G + (k - 1) * mm, E + (k - 1) * mm, Uc[0], m, nbx, nby, 0);
+    }
+    k_plane_cols<<<cols9, kBlock, 0, s0>>>(Uc[0], Up(t - 1), n, m, nbx, nby);
+    k_plane_right<<<rows, kBlock, 0, s0>>>(G + (t - 1) * mm, E + (t - 1) * mm, Uc[0], m, nbx, nby, 0);
+    k_plane_left<<<rows, kBlock, 0, s0>>>(Fk + t * mm, Lo(t), n, E + (t - 1) * mm, m, nbx, nby);
+    // bottom chain, planes Z-1 .. t+1
+    for (int k = Z - 1; k > t; --k) {
+        double *S = E + k * mm;
+        k_copy2d<<<cells, kBlock, 0, s1>>>(D(k), n, S, m, m, m);
+        if (k < Z - 1) {
+            k_plane_left<<<rows, kBlock, 0, s1>>>(Fk + (k + 1) * mm, Up(k), n, E + (k + 1) * mm, m, nbx, nby);
+            k_plane_cols<<<cols9, kBlock, 0, s1>>>(Uc[1], Lo(k + 1), n, m, nbx, nby);
+            k_plane_right<<<rows, kBlock, 0, s1>>>(S, Fk + (k + 1) * mm, Uc[1], m, nbx, nby, 1);
+        }
+        inverse_gj(c, S, m, k, 1, s1);
+        if (k < Z - 1)   // K_{k+1} = E_{k+1} L_{k+1}
+            k_plane_right<<<rows, kBlock, 0, s1>>>(G + (k + 1) * mm, E + (k + 1) * mm, Uc[1], m, nbx, nby, 0);
+    }
+    k_plane_cols<<<cols9, kBlock, 0, s1>>>(Uc[1], Lo(t + 1), n, m, nbx, nby);
+    k_plane_right<<<rows, kBlock, 0, s1>>>(G + (t + 1) * mm, E + (t + 1) * mm, Uc[1], m, nbx, nby, 0);
+    k_plane_left<<<rows, kBlock, 0, s1>>>(Fk + (t + 1) * mm, Up(t), n, E + (t + 1) * mm, m, nbx, nby);
+    if (s1 != s0) {
+        CAMS_HIP(hipEventRecord(c->join_ev, s1));
+        CAMS_HIP(hipStreamWaitEvent(s0, c->join_ev, 0));
+    }
+    // twist plane
+    double *S = E + t * mm;
+    k_copy2d<<<cells, kBlock, 0, s0>>>(D(t), n, S, m, m, m);
+    k_plane_cols<<<cols9, kBlock, 0, s0>>>(Uc[0], Up(t - 1), n, m, nbx, nby);
+    k_plane_right<<<rows, kBlock, 0, s0>>>(S, Fk + t * mm, Uc[0], m, nbx, nby, 1);
+    k_plane_cols<<<cols9, kBlock, 0, s0>>>(Uc[0], Lo(t + 1), n, m, nbx, nby);
+    k_plane_right<<<rows, kBlock, 0, s0>>>(S, Fk + (t + 1) * mm, Uc[0], m, nbx, nby, 1);
+    inverse_gj(c, S, m, t, 0, s0);
 }
 
-// xc = A_c^-1 rc by block forward and backward substitution:
-// g_0 = rc_0, g_k = rc_k - F_k g_{k-1};  x_{Z-1} = E_{Z-1} g_{Z-1},
-// x_k = E_k g_k - G_k x_{k+1}.  rc is overwritten by g.
+// xc = A_c^-1 rc by block substitution from both ends:
+//   g_k = rc_k - F_k g_{k-1} (k = 1..t),  g_k = rc_k - H_k g_{k+1} (k = Z-2..t+1),
+//   then g_t -= H_t g_{t+1};  x_k = E_k g_k for every plane;
+//   x_k -= G_k x_{k+1} (k = t-1..0),  x_k -= K_k x_{k-1} (k = t+1..Z-1).
+// The two chains go in pairs, one launch per step.  rc is overwritten by g.
 static void solve_blocktri(cams_ctx *c, double *rc, double *xc, const int32_t *done)
 {
     double *E, *Fk, *G;
     int m, Z;
     blocktri_parts(c, E, Fk, G, m, Z);
+    const int t = twist_plane(Z);
     const size_t mm = (size_t)m * m;
-    const unsigned grid = m;
-    for (int k = 1; k < Z; ++k)
-        k_gemv_ab<<<grid, kBlock, 0, c->stream>>>(Fk + k * mm, m, m, m, rc + (size_t)(k - 1) * m,
-                                                  rc + (size_t)k * m, -1.0, 1.0, done);
-    for (int k = Z - 1; k >= 0; --k) {
-        k_gemv_ab<<<grid, kBlock, 0, c->stream>>>(E + k * mm, m, m, m, rc + (size_t)k * m, xc + (size_t)k * m, 1.0,
-                                                  0.0, done);
-        if (k < Z - 1)
-            k_gemv_ab<<<grid, kBlock, 0, c->stream>>>(G + k * mm, m, m, m, xc + (size_t)(k + 1) * m,
-                                                      xc + (size_t)k * m, -1.0, 1.0, done);
+    auto pair = [&](bool has0, GemvJob a, bool has1, GemvJob b) {
+        if (!has0 && !has1) return;
+        if (!has0) a = b;
+        k_gemv_pair<<<(has0 && has1 ? 2 : 1) * m, kBlock, 0, c->stream>>>(a, b, m, done);
+    };
+    const int nt = t, nbm = Z - 2 - t;   // forward steps of each chain
+    for (int i = 0; i < std::max(nt, nbm); ++i) {
+        const int kt = 1 + i, kb = Z - 2 - i;
+        pair(i < nt, GemvJob{Fk + kt * mm, rc + (size_t)(kt - 1) * m, rc + (size_t)kt * m, -1.0, 1.0},
+             i < nbm, GemvJob{Fk + (kb + 1) * mm, rc + (size_t)(kb + 1) * m, rc + (size_t)kb * m, -1.0, 1.0});
+    }
+    pair(true, GemvJob{Fk + (t + 1) * mm, rc + (size_t)(t + 1) * m, rc + (size_t)t * m, -1.0, 1.0}, false,
+         GemvJob{});
+    k_gemv_planes<<<(unsigned)(Z * m), kBlock, 0, c->stream>>>(E, m, rc, xc, done);
+    const int ut = t, ub = Z - 1 - t;    // backward steps of each chain
+    for (int i = 0; i < std::max(ut, ub); ++i) {
+        const int kt = t - 1 - i, kb = t + 1 + i;
+        pair(i < ut, GemvJob{G + kt * mm, xc + (size_t)(kt + 1) * m, xc + (size_t)kt * m, -1.0, 1.0},
+             i < ub, GemvJob{G + kb * mm, xc + (size_t)(kb - 1) * m, xc + (size_t)kb * m, -1.0, 1.0});
     }
 }
 
@@ -1420,9 +1522,9 @@ void launch_coarse_factor(cams_ctx *c)
         return;
     }
     if (!pivoting) {   // Gauss-Jordan in place in X
-        gj_prepare(c, {X}, n);
+        gj_prepare(c, {X}, {0}, n);
         k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, X, nn);
-        inverse_gj(c, X, n, 0);
+        inverse_gj(c, X, n, 0, 0, c->stream);
         return;
     }
     k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
