@@ -27,11 +27,16 @@ def torch():
     return require_gpu()
 
 
-def test_blocktri_coarse_operator_and_solve(torch):
+# (grid, seed): 10 coarse z-planes (elimination chains of 4 and 5 planes
+# around the twist plane), 3 (one plane each side) and 4 (one above, two below)
+@pytest.mark.parametrize("shape,seed", [((96, 96, 40), 31), ((160, 160, 12), 33), ((144, 144, 16), 34)])
+def test_blocktri_coarse_operator_and_solve(torch, shape, seed):
     from paper_1705_05783_amd import _cams as C
-    pb = small_problem(96, 96, 40, 4, sigma=2.0, seed=31, c=0.1)
+    pb = small_problem(*shape, 4, sigma=2.0, seed=seed, c=0.1)
     s = solver_for(pb)
-    assert C.cams_coarse_planes(s.ctx) == 10 and s.Nc == 5760
+    nbx, Z = shape[0] // 4, shape[2] // 4
+    m = nbx * (shape[1] // 4)
+    assert C.cams_coarse_planes(s.ctx) == Z and s.Nc == Z * m
     p0 = torch.as_tensor(pb.initial_pressure(), device="cuda")
     s.assemble(p0, p0.clone())
     s.build_basis()
@@ -40,18 +45,17 @@ def test_blocktri_coarse_operator_and_solve(torch):
     P = oracle.basis_b4(pb, T)
     W, diag, r0, _ = oracle.linear_system(pb, T, pb.initial_pressure(), pb.initial_pressure())
     Ac = oracle.coarse_operator(pb, W, diag, P, pb.restriction)
-    m = 24 * 24
     plane = np.arange(s.Nc) // m
     far = np.abs(plane[:, None] - plane[None, :]) > 1
     assert np.count_nonzero(Ac[far]) == 0   # block tridiagonal over coarse z-planes
     # and within the coupling of adjacent planes, 9-point: the plane products use it
     node = np.arange(s.Nc) % m
-    ax, by = node % 24, node // 24
+    ax, by = node % nbx, node // nbx
     spread = (np.abs(ax[:, None] - ax[None, :]) > 1) | (np.abs(by[:, None] - by[None, :]) > 1)
     assert np.count_nonzero(Ac[~far & spread]) == 0
     Ac_gpu = to_np(s.export(C.CAMS_ARR_AC)).reshape(s.Nc, s.Nc)
     assert rel_err(Ac_gpu, Ac) <= 1e-12
-    rng = np.random.default_rng(5)
+    rng = np.random.default_rng(seed)
     rc = rng.normal(size=s.Nc)
     xc = to_np(s.coarse_solve(torch.as_tensor(rc, device="cuda")))
     ref = np.linalg.solve(Ac, rc)
