@@ -66,6 +66,31 @@ def test_blocktri_coarse_operator_and_solve(torch, shape, seed):
     s.close()
 
 
+def test_blocktri_on_a_caller_stream(torch):
+    """The second elimination chain forks from and joins back to the stream
+    the context was created on; here a stream of the caller's own (not the
+    default one), with the solve right after the factorisation on it."""
+    pb = small_problem(144, 144, 16, 4, sigma=2.0, seed=35, c=0.1)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = solver_for(pb, stream=st)
+        p0 = torch.as_tensor(pb.initial_pressure(), device="cuda")
+        s.assemble(p0, p0.clone())
+        s.build_basis()
+        s.coarse_op()
+        rng = np.random.default_rng(35)
+        rc = rng.normal(size=s.Nc)
+        xc = to_np(s.coarse_solve(torch.as_tensor(rc, device="cuda")))
+        s.close()
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    W, diag, r0, _ = oracle.linear_system(pb, T, pb.initial_pressure(), pb.initial_pressure())
+    Ac = oracle.coarse_operator(pb, W, diag, P, pb.restriction)
+    err = rel_err(xc, np.linalg.solve(Ac, rc))
+    log("blocktri on a caller stream: rel err", err)
+    assert err <= 1e-8
+
+
 def test_blocktri_linear_solve_meets_tolerance(torch):
     pb = small_problem(96, 96, 40, 4, sigma=2.0, seed=32, c=0.1).with_options(lin_rtol=1e-10, newton_maxit=1)
     s = solver_for(pb)
