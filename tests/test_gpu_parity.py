@@ -348,6 +348,38 @@ def test_mixed_linear_solve_meets_fp64_residual(_gpu, shape, r, restriction, pre
     assert np.max(np.abs(P - P_ref)) <= tol
 
 
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_BLOCK_ALT])
+@pytest.mark.parametrize("shape,r", [((96, 96, 40), 8), ((100, 92, 36), 4)])
+def test_mixed_solve_on_grids_of_the_lds_smoother(_gpu, shape, r, smoother):
+    """Grids with more smoother blocks than are resident at once take the
+    LDS form of the FP32 smoother (the second grid's last x-block is 4 cells
+    wide, and its shifted grid wraps inside a block): the FP64 residual the
+    oracle recomputes meets the tolerance, and the iteration count stays
+    within 3 of the FP64 solve's (a wrong coupling would change it)."""
+    torch = _gpu
+    its = {}
+    for precision in (0, 1):
+        pb = _pb(shape, r, sigma=2.0, seed=13)
+        pb.precision = precision
+        pb.smoother = smoother
+        s = solver_for(pb)
+        s.build_basis()
+        p = pb.initial_pressure()
+        pt = torch.as_tensor(p, device="cuda")
+        s.assemble(pt, pt)
+        s.coarse_op()
+        st = s.iterate(pt)
+        its[precision] = st["lin_iters_last"]
+        s.close()
+        T = oracle.transmissibility(pb)
+        W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
+        res = r0 - oracle.matvec(pb, W, diag, to_np(pt) - p)
+        rel = np.linalg.norm(res) / np.linalg.norm(r0)
+        log(pb.name, "precision", precision, "iters", its[precision], "relres", rel)
+        assert rel <= 1.05e-8
+    assert abs(its[1] - its[0]) <= 3, its
+
+
 @pytest.mark.parametrize("precision", [1, 2])
 def test_mixed_newton_matches_fp64_oracle(_gpu, precision):
     """One time step of the 64x64x32 workload in mixed precision: the
