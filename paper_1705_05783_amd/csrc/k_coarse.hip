@@ -986,7 +986,25 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
     }
     if (row >= n) return;
     double s = 0.0;
-    for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    if (n % 512 == 0) {
+        // 16-byte loads, four in flight per lane, four independent sums
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 *m2 = (const d2 *)mr, *x2 = (const d2 *)x;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = lane; c < n / 2; c += 256) {
+            d2 mv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                mv[u] = m2[c + 64 * u];
+                xv[u] = x2[c + 64 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += mv[u].x * xv[u].x + mv[u].y * xv[u].y;
+        }
+        s = (a[0] + a[1]) + (a[2] + a[3]);
+    } else {
+        for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    }
     s = wave_sum(s);
     if (lane == 0) y[row] = s;
 }

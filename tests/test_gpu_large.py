@@ -66,6 +66,33 @@ def test_blocktri_coarse_operator_and_solve(torch, shape, seed):
     s.close()
 
 
+def test_dense_coarse_solve_at_4096_nodes(torch):
+    """4096 coarse nodes, the largest dense MSFE inverse (Gauss-Jordan sweeps
+    whose update launches take the lean GEMM tile) and the dense coarse GEMV
+    with 16-byte row loads: the GPU coarse solve against a LAPACK solve of
+    the oracle's operator."""
+    from paper_1705_05783_amd import _cams as C
+    pb = small_problem(64, 64, 64, 4, sigma=2.0, seed=36, c=0.1)
+    s = solver_for(pb)
+    assert C.cams_coarse_planes(s.ctx) == 0 and s.Nc == 4096
+    p0 = torch.as_tensor(pb.initial_pressure(), device="cuda")
+    s.assemble(p0, p0.clone())
+    s.build_basis()
+    s.coarse_op()
+    rng = np.random.default_rng(36)
+    rc = rng.normal(size=s.Nc)
+    xc = to_np(s.coarse_solve(torch.as_tensor(rc, device="cuda")))
+    s.close()
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    W, diag, r0, _ = oracle.linear_system(pb, T, pb.initial_pressure(), pb.initial_pressure())
+    Ac = oracle.coarse_operator(pb, W, diag, P, pb.restriction)
+    err = rel_err(xc, np.linalg.solve(Ac, rc))
+    res = np.linalg.norm(Ac @ xc - rc) / np.linalg.norm(rc)
+    log("dense 4096 coarse solve: rel err", err, "residual", res)
+    assert err <= 1e-8 and res <= 1e-10
+
+
 def test_blocktri_on_a_caller_stream(torch):
     """The second elimination chain forks from and joins back to the stream
     the context was created on; here a stream of the caller's own (not the
