@@ -942,6 +942,34 @@ __global__ __launch_bounds__(kBlock) void k_node_sum(GridDev g, const double *__
 
 constexpr int kGemvLds = 1024;   // coarse sizes for which every GEMV workgroup forms R r itself
 
+// Dot product of the row mr (n entries) with x by one wave: 16-byte loads,
+// four in flight per lane, four independent sums when n is a multiple of 512
+// (mr and x then 16-byte aligned), else one entry per lane and step.
+__device__ __forceinline__ double row_dot(const double *__restrict__ mr, const double *__restrict__ x, int n,
+                                          int lane)
+{
+    double s = 0.0;
+    if (n % 512 == 0) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 *m2 = (const d2 *)mr, *x2 = (const d2 *)x;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = lane; c < n / 2; c += 256) {
+            d2 mv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                mv[u] = m2[c + 64 * u];
+                xv[u] = x2[c + 64 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += mv[u].x * xv[u].x + mv[u].y * xv[u].y;
+        }
+        s = (a[0] + a[1]) + (a[2] + a[3]);
+    } else {
+        for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
+    }
+    return wave_sum(s);
+}
+
 // y = M x, one wave per row (fixed lane partition and shuffle tree).  With
 // `slots` set (n <= kGemvLds), x = R r is first assembled in LDS from the
 // restriction's slot partials.
@@ -985,68 +1013,43 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
         return;
     }
     if (row >= n) return;
-    double s = 0.0;
-    if (n % 512 == 0) {
-        // 16-byte loads, four in flight per lane, four independent sums
-        typedef double d2 __attribute__((ext_vector_type(2)));
-        const d2 *m2 = (const d2 *)mr, *x2 = (const d2 *)x;
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int c = lane; c < n / 2; c += 256) {
-            d2 mv[4], xv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                mv[u] = m2[c + 64 * u];
-                xv[u] = x2[c + 64 * u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] += mv[u].x * xv[u].x + mv[u].y * xv[u].y;
-        }
-        s = (a[0] + a[1]) + (a[2] + a[3]);
-    } else {
-        for (int c = lane; c < n; c += 64) s += mr[c] * x[c];
-    }
-    s = wave_sum(s);
+    const double s = row_dot(mr, x, n, lane);
     if (lane == 0) y[row] = s;
 }
 
 // Two independent products y = alpha M x + beta y with m x m matrices (row
 // pitch m) in one launch, for the two chains of the block-tridiagonal
-// substitutions: workgroups [0, m) are the rows of the first, [m, 2m) those
-// of the second (a launch of m workgroups runs the first alone).
+// substitutions, one wave per row: rows [0, m) of the launch are the first
+// product's, [m, 2m) the second's (rows = m runs the first alone).
 struct GemvJob {
     const double *M, *x;
     double *y;
     double alpha, beta;
 };
-__global__ __launch_bounds__(kBlock) void k_gemv_pair(GemvJob j0, GemvJob j1, int m, const int32_t *done)
+__global__ __launch_bounds__(kBlock) void k_gemv_pair(GemvJob j0, GemvJob j1, int m, int rows, const int32_t *done)
 {
-    __shared__ double sh[kBlock / 64];
     if (done && *done) return;
-    const bool second = (int)blockIdx.x >= m;
+    const int R = (int)blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (R >= rows) return;
+    const bool second = R >= m;
     const GemvJob j = second ? j1 : j0;
-    const int row = (int)blockIdx.x - (second ? m : 0);
-    const double *mr = j.M + (size_t)row * m;
-    double s = 0.0;
-    for (int c = threadIdx.x; c < m; c += kBlock) s += mr[c] * j.x[c];
-    s = block_sum<kBlock>(s, sh);
-    if (threadIdx.x == 0) j.y[row] = j.beta == 0.0 ? j.alpha * s : j.beta * j.y[row] + j.alpha * s;
+    const int row = R - (second ? m : 0);
+    const double s = row_dot(j.M + (size_t)row * m, j.x, m, lane);
+    if (lane == 0) j.y[row] = j.beta == 0.0 ? j.alpha * s : j.beta * j.y[row] + j.alpha * s;
 }
 
 // y_k = E_k x_k for every plane k at once (E: the planes' m x m blocks one
-// after another, so row R of the launch is row R of E; x, y: m per plane).
-__global__ __launch_bounds__(kBlock) void k_gemv_planes(const double *__restrict__ E, int m,
+// after another, so row R of the launch is row R of E; x, y: m per plane),
+// one wave per row.
+__global__ __launch_bounds__(kBlock) void k_gemv_planes(const double *__restrict__ E, int m, size_t rows,
                                                          const double *__restrict__ x, double *__restrict__ y,
                                                          const int32_t *done)
 {
-    __shared__ double sh[kBlock / 64];
     if (done && *done) return;
-    const size_t R = blockIdx.x;
-    const double *mr = E + R * m;
-    const double *xk = x + (R / m) * m;
-    double s = 0.0;
-    for (int c = threadIdx.x; c < m; c += kBlock) s += mr[c] * xk[c];
-    s = block_sum<kBlock>(s, sh);
-    if (threadIdx.x == 0) y[R] = s;
+    const size_t R = (size_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (R >= rows) return;
+    const double s = row_dot(E + R * m, x + (R / m) * m, m, threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0) y[R] = s;
 }
 
 // dst (rows x cols, ldd) = src (lds)
@@ -1557,7 +1560,8 @@ static void solve_blocktri(cams_ctx *c, double *rc, double *xc, const int32_t *d
     auto pair = [&](bool has0, GemvJob a, bool has1, GemvJob b) {
         if (!has0 && !has1) return;
         if (!has0) a = b;
-        k_gemv_pair<<<(has0 && has1 ? 2 : 1) * m, kBlock, 0, c->stream>>>(a, b, m, done);
+        const int rows = (has0 && has1 ? 2 : 1) * m;
+        k_gemv_pair<<<cdiv(rows, kBlock / 64), kBlock, 0, c->stream>>>(a, b, m, rows, done);
     };
     const int nt = t, nbm = Z - 2 - t;   // forward steps of each chain
     for (int i = 0; i < std::max(nt, nbm); ++i) {
@@ -1567,7 +1571,7 @@ static void solve_blocktri(cams_ctx *c, double *rc, double *xc, const int32_t *d
     }
     pair(true, GemvJob{Fk + (t + 1) * mm, rc + (size_t)(t + 1) * m, rc + (size_t)t * m, -1.0, 1.0}, false,
          GemvJob{});
-    k_gemv_planes<<<(unsigned)(Z * m), kBlock, 0, c->stream>>>(E, m, rc, xc, done);
+    k_gemv_planes<<<cdiv((size_t)Z * m, kBlock / 64), kBlock, 0, c->stream>>>(E, m, (size_t)Z * m, rc, xc, done);
     const int ut = t, ub = Z - 1 - t;    // backward steps of each chain
     for (int i = 0; i < std::max(ut, ub); ++i) {
         const int kt = t - 1 - i, kb = t + 1 + i;

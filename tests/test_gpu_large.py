@@ -28,8 +28,10 @@ def torch():
 
 
 # (grid, seed): 10 coarse z-planes (elimination chains of 4 and 5 planes
-# around the twist plane), 3 (one plane each side) and 4 (one above, two below)
-@pytest.mark.parametrize("shape,seed", [((96, 96, 40), 31), ((160, 160, 12), 33), ((144, 144, 16), 34)])
+# around the twist plane), 3 (one plane each side), 4 (one above, two below)
+# and 5 planes of 1024 nodes (the block GEMVs' 16-byte row loads)
+@pytest.mark.parametrize("shape,seed", [((96, 96, 40), 31), ((160, 160, 12), 33), ((144, 144, 16), 34),
+                                        ((128, 128, 20), 37)])
 def test_blocktri_coarse_operator_and_solve(torch, shape, seed):
     from paper_1705_05783_amd import _cams as C
     pb = small_problem(*shape, 4, sigma=2.0, seed=seed, c=0.1)
