@@ -188,9 +188,14 @@ constexpr int kStopThreads = 256;
 __device__ __forceinline__ void stop_test(const double *__restrict__ partial, int nparts, int32_t *ictl,
                                           double *scal, double rtol2, int maxit, double *sh)
 {
-    double u = 0.0;
-    for (int t = threadIdx.x; t < nparts; t += kStopThreads) u += partial[t];
-    const double s = block_sum<kStopThreads>(u, sh);
+    // four independent sums per thread, so that four loads are in flight
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int t = threadIdx.x;
+    for (; t + 3 * kStopThreads < nparts; t += 4 * kStopThreads)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] += partial[t + u * kStopThreads];
+    for (; t < nparts; t += kStopThreads) a[0] += partial[t];
+    const double s = block_sum<kStopThreads>((a[0] + a[1]) + (a[2] + a[3]), sh);
     if (threadIdx.x != 0) return;
     const int it = ictl[C_IT];
     if (it == 0) scal[S_R0N2] = s;
