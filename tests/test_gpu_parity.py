@@ -349,13 +349,14 @@ def test_mixed_linear_solve_meets_fp64_residual(_gpu, shape, r, restriction, pre
 
 
 @pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_BLOCK_ALT])
-@pytest.mark.parametrize("shape,r", [((96, 96, 40), 8), ((100, 92, 36), 4)])
+@pytest.mark.parametrize("shape,r", [((96, 96, 40), 8), ((100, 92, 36), 4), ((128, 128, 72), 8)])
 def test_mixed_solve_on_grids_of_the_lds_smoother(_gpu, shape, r, smoother):
     """Grids with more smoother blocks than are resident at once take the
     LDS form of the FP32 smoother (the second grid's last x-block is 4 cells
     wide, and its shifted grid wraps inside a block): the FP64 residual the
     oracle recomputes meets the tolerance, and the iteration count stays
-    within 3 of the FP64 solve's (a wrong coupling would change it)."""
+    within 3 of the FP64 solve's (a wrong coupling would change it); the
+    third grid has over 2^20 cells."""
     torch = _gpu
     its = {}
     for precision in (0, 1):
