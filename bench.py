@@ -1,16 +1,30 @@
 """Benchmark of the C-AMS pressure solve on one MI355X.
 
-Workload (one "step"): the 3D 64x64x32 problem with coarsening 8^3, log-
-normal permeability (sigma 3), porosity U[0.1,0.3], c = 0.05, corner column
-wells: transmissibilities, B4 basis, then 10 backward-Euler time steps of
-dt = 0.05, each Newton iteration solving its linear system by C-AMS to a
-1e-8 relative residual (Newton to ||eps||_2 <= 1e-8).
+Headline workload: the 128^3 learned-basis evaluation field (ln k lognormal,
+sigma 3, correlation length 8 cells, seed 5; coarsening 8^3 = 4096 coarse
+nodes; porosity 0.2, c = 0.1, dt = 0.1, corner column wells; MSFE; 5
+alternating block-ILU(0) post-smoothing steps; Newton and linear solves to
+1e-8).  One "step" = one pass of the whole hot path over it: new rock
+(transmissibilities), basis, then one backward-Euler time step whose Newton
+iterations each assemble, build the coarse operator and its inverse, and
+solve the linear system by C-AMS.  Three variants run the same pass:
 
-Metric: seconds per Newton linear solve = (timed wall time of K steps) /
-(number of Newton linear solves in them), inputs resident in HBM.  The
-headline value is the mixed-precision solve (FP32 smoother, basis storage
-and prolongation; FP64 residual, update and coarse solve); the plain FP64
-solve of the same workload is timed beside it.
+  plain_fp64      FP64 throughout, basis by exact local solves;
+  mixed           FP32 smoother, basis storage and prolongation, FP64
+                  residual, update and coarse solve (iterative refinement);
+  learned_mixed   mixed, with the trained network for the interiors of the
+                  full dual blocks (exact re-solve of blocks whose local
+                  equation ratio exceeds the calibrated fallback tolerance).
+
+Metric: seconds per Newton linear solve to a 1e-8 relative residual =
+median pass wall time / Newton linear solves per pass (time to solution per
+solve: the basis is rebuilt in every pass and counted), inputs resident in
+HBM.  value = learned_mixed; plain_fp64 and mixed beside it, with the
+iterations-only time per solve (hipEvent around the C-AMS iterations).
+The roofline object is the smoother step, the kernel with the largest total
+time in the learned_mixed pass, timed live with HIP events on the library's
+stream.  The other workloads (64x64x32, the 256x256x128 channelised field,
+the 256-instance batch) follow as extra keys with the same --steps/--warmup.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the solve runs on one GPU.
 """
@@ -18,17 +32,20 @@ Prints one JSON line.  --gpus N with N > 1 exits: the solve runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-
-import numpy as np
 import os
 import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E
 
 
 def _cpu_model():
@@ -41,66 +58,178 @@ def _cpu_model():
     return platform.processor()
 
 
-def run_workload(solver, pb, torch):
-    """One pass of the whole hot path over the workload; returns stats."""
-    # new rock => transmissibilities and basis are rebuilt inside the step
+def run_pass(solver, pb):
+    """One pass of the hot path: rock (and so basis) reset, then every time
+    step of the workload.  Returns per-pass totals from the library's stats."""
     solver.reset_rock()
     pn = solver.new_pressure()
     p = pn.clone()
-    solves = 0
-    iters = 0
+    out = {"solves": 0, "iters": 0, "t_iterate_ms": 0.0, "t_basis_ms": 0.0, "t_coarse_ms": 0.0,
+           "t_assemble_ms": 0.0, "fallback_blocks": 0}
     for _ in range(pb.n_steps):
         st = solver.newton_step(pn, p)
-        solves += st["newton_iters"]
-        iters += st["lin_iters_total"]
+        out["solves"] += st["newton_iters"]
+        out["iters"] += st["lin_iters_total"]
+        for k in ("t_iterate_ms", "t_basis_ms", "t_coarse_ms", "t_assemble_ms"):
+            out[k] += st[k]
+        out["fallback_blocks"] = max(out["fallback_blocks"], st["fallback_blocks"])
         pn.copy_(p)
-    return solves, iters, p
+    return out
 
 
-def cpu_baseline(pb):
-    """The oracle (single-threaded C) on a bounded sample of the workload:
-    one Newton linear solve of the first time step (assembly, coarse
-    operator and LU, ILU(0), C-AMS to 1e-8)."""
-    import numpy as np
-    import oracle
-    T = oracle.transmissibility(pb)
-    P = oracle.basis_b4(pb, T)
-    pn = pb.initial_pressure()
-    t0 = time.perf_counter()
-    W, diag, r0, _ = oracle.linear_system(pb, T, pn, pn)
-    LU, piv = oracle.lu_factor(oracle.coarse_operator(pb, W, diag, P, pb.restriction))
-    ilu = oracle.smoother_for(pb, W, diag)
-    d, its, _ = oracle.cams_solve(pb, W, diag, P, pb.restriction, LU, piv, ilu, r0)
-    dt = time.perf_counter() - t0
-    return {"value": dt, "unit": "s per Newton linear solve", "cores": 1, "kind": "oracle",
-            "sample": f"one Newton linear solve (first iteration of time step 1) of the 64x64x32 workload, "
-                      f"{its} C-AMS iterations to 1e-8; basis excluded; CPU {_cpu_model()}, "
-                      f"{len(os.sched_getaffinity(0))} host cores available, oracle is single-threaded"}
-
-
-PEAK_HBM_GBS = 8000.0   # MI355X HBM3E
-LEARNED_FALLBACK_TOL = 10.0   # a network block is re-solved when its basis residual exceeds 10x its boundary flux
-
-
-def timed_run(pb, steps, warmup, torch):
-    """Warm up, then time `steps` whole-workload passes; the smoothing-step
-    kernel is timed by the library with HIP events on its stream."""
-    from paper_1705_05783_amd.solver import Solver
-    solver = Solver(pb, device=torch.device("cuda:0"))
+def timed_passes(solver, pb, steps, warmup, torch):
+    """`warmup` untimed passes, then `steps` passes each timed on the wall
+    clock (synchronised on both sides); the smoother step is timed by the
+    library with HIP events on its stream during the timed passes."""
     for _ in range(warmup):
-        run_workload(solver, pb, torch)
+        run_pass(solver, pb)
     torch.cuda.synchronize()
     solver.profile()
-    t0 = time.perf_counter()
-    solves = iters = 0
+    walls, stats = [], []
+    t_all = time.perf_counter()
     for _ in range(steps):
-        s, i, _ = run_workload(solver, pb, torch)
-        solves += s
-        iters += i
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = run_pass(solver, pb)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        stats.append(st)
+    total = time.perf_counter() - t_all
     prof = solver.profile_read()
-    return {"elapsed": elapsed, "solves": solves, "iters": iters, "prof": prof, "Nc": solver.Nc}
+    solves = stats[0]["solves"]
+    assert all(s["solves"] == solves for s in stats), "passes differ in their Newton iterations"
+    med = float(np.median(walls))
+    return {"s_per_solve": med / max(solves, 1),
+            "ms_per_pass_median": med * 1e3, "ms_per_pass_min": min(walls) * 1e3,
+            "ms_per_pass_max": max(walls) * 1e3, "passes": steps, "total_s": total,
+            "newton_solves_per_pass": solves,
+            "cams_iterations_per_solve": stats[0]["iters"] / max(solves, 1),
+            "iterate_ms_per_solve_median": float(np.median([s["t_iterate_ms"] / max(s["solves"], 1)
+                                                            for s in stats])),
+            "basis_ms_median": float(np.median([s["t_basis_ms"] for s in stats])),
+            "coarse_ms_per_solve_median": float(np.median([s["t_coarse_ms"] / max(s["solves"], 1)
+                                                          for s in stats])),
+            "fallback_blocks": stats[0]["fallback_blocks"], "prof": prof}
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the smoother step from the committed memory
+    counter record (FETCH_SIZE + WRITE_SIZE, scaled by a device copy), or
+    None when the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_bilu_step.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    w = rec["workloads"].get(workload)
+    return None if w is None else w["traffic_bytes_per_launch"]
+
+
+def roofline(prof, workload=None):
+    if prof["launches"] == 0 or prof["total_ms"] <= 0:
+        return None
+    per_launch_bytes = prof["bytes"] / prof["launches"]
+    avg_s = prof["total_ms"] * 1e-3 / prof["launches"]
+    achieved = per_launch_bytes / avg_s / 1e9
+    return {"kernel": "k_bilu_step (block-ILU(0) Richardson step)", "bound": "hbm",
+            "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": measured_traffic(workload) if workload else None, "avg_launch_us": avg_s * 1e6,
+            "bytes_per_launch": per_launch_bytes, "launches": prof["launches"]}
+
+
+def headline(steps, warmup, torch):
+    """The 128^3 workload: plain FP64, mixed and learned+mixed."""
+    from paper_1705_05783_amd.solver import Solver
+    from paper_1705_05783_amd.train_basis import load_fallback_tol, load_weights
+    from workloads.configs import FP64, MIXED_FP32, config5_eval
+    params = load_weights()
+    tol = load_fallback_tol()
+    out = {}
+    for label, prec, learned in (("plain_fp64", FP64, False), ("mixed", MIXED_FP32, False),
+                                 ("learned_mixed", MIXED_FP32, True)):
+        pb = config5_eval(precision=prec)
+        solver = Solver(pb)
+        if learned:
+            solver.set_learned(params, fallback_tol=tol)
+        r = timed_passes(solver, pb, steps, warmup, torch)
+        r["roofline_smoother"] = roofline(r.pop("prof"), f"128^3 {label}")
+        if learned:
+            r["fallback_tol"] = tol
+            r["full_dual_blocks"] = solver.num_full_blocks()
+        r["coarse_nodes"] = solver.Nc
+        out[label] = r
+        solver.close()
+    pl, mx, lm = out["plain_fp64"], out["mixed"], out["learned_mixed"]
+    out["speedup_learned_mixed_vs_plain"] = pl["s_per_solve"] / lm["s_per_solve"]
+    out["speedup_mixed_vs_plain"] = pl["s_per_solve"] / mx["s_per_solve"]
+    out["speedup_learned_mixed_vs_mixed"] = mx["s_per_solve"] / lm["s_per_solve"]
+    out["speedup_learned_mixed_vs_plain_iterations_only"] = (pl["iterate_ms_per_solve_median"] /
+                                                             lm["iterate_ms_per_solve_median"])
+    return out
+
+
+def adaptive_run(steps, warmup, torch):
+    """The paper's linear/nonlinear stopping strategies (Sec. 4.1.1) on the
+    headline workload in its learned+mixed form, both to ||eps||_2 < 1e-6:
+    each Newton linear system solved to 1e-8 relative residual, against the
+    adaptive strategy that updates the system once the residual has dropped
+    by one order (linear 1e-1).  Time to solution per pass (one time step)."""
+    from paper_1705_05783_amd.solver import Solver
+    from paper_1705_05783_amd.train_basis import load_fallback_tol, load_weights
+    from workloads.configs import MIXED_FP32, config5_eval
+    params = load_weights()
+    out = {"workload": "128^3 learned+mixed, one time step per pass, Newton to ||eps||_2 < 1e-6"}
+    for label, lin in (("linear_1e-8", 1e-8), ("adaptive_1e-1", 1e-1)):
+        pb = config5_eval(precision=MIXED_FP32).with_options(lin_rtol=lin, newton_tol=1e-6)
+        solver = Solver(pb)
+        solver.set_learned(params, fallback_tol=load_fallback_tol())
+        r = timed_passes(solver, pb, steps, warmup, torch)
+        r.pop("prof")
+        r["s_per_time_step"] = r["ms_per_pass_median"] * 1e-3
+        out[label] = r
+        solver.close()
+    out["speedup_adaptive"] = out["linear_1e-8"]["s_per_time_step"] / out["adaptive_1e-1"]["s_per_time_step"]
+    return out
+
+
+def small_run(steps, warmup, torch):
+    """The 64x64x32 workload (10 time steps of dt 0.05 per pass), mixed and
+    plain FP64."""
+    from paper_1705_05783_amd.solver import Solver
+    from workloads import config2
+    from workloads.configs import FP64, MIXED_FP32
+    out = {"workload": "64x64x32 lognormal (sigma 3, corr. 8x8x2), coarsening 8^3 (256 coarse nodes), MSFE, "
+                       "10 backward-Euler steps dt=0.05 per pass, Newton and linear solves to 1e-8"}
+    for label, prec in (("mixed", MIXED_FP32), ("plain_fp64", FP64)):
+        pb = config2(precision=prec)
+        solver = Solver(pb)
+        r = timed_passes(solver, pb, steps, warmup, torch)
+        r["roofline_smoother"] = roofline(r.pop("prof"), "64x64x32 mixed" if label == "mixed" else None)
+        out[label] = r
+        solver.close()
+    out["speedup_mixed_vs_plain"] = out["plain_fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
+    return out
+
+
+def large_run(steps, warmup, torch):
+    """The 256x256x128 channelised workload (8.4M cells, 16384 coarse nodes,
+    block-tridiagonal coarse factorisation), BF16 basis and prolongation,
+    FP32 smoother, FP64 residual and coarse solve; one pass = its 5 time
+    steps."""
+    from paper_1705_05783_amd.solver import Solver
+    from workloads.configs import config4
+    pb = config4()
+    solver = Solver(pb)
+    r = timed_passes(solver, pb, steps, warmup, torch)
+    r["roofline_smoother"] = roofline(r.pop("prof"), "256x256x128 channelised BF16")
+    r.update({"workload": "256x256x128 channelised (k 1 / 1e-4, 30% channels), coarsening 8^3, 16384 coarse "
+                          "nodes, BF16 basis, 5 time steps dt=0.05 per pass, to 1e-8",
+              "cells": pb.n, "coarse_nodes": solver.Nc})
+    solver.close()
+    return r
 
 
 def batch_run(steps, warmup, torch, sequential=True):
@@ -132,20 +261,21 @@ def batch_run(steps, warmup, torch, sequential=True):
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    walls = []
     for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         stats = step()
-    torch.cuda.synchronize()
-    elapsed = (time.perf_counter() - t0) / steps
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    med = float(np.median(walls))
     its = np.array([st["lin_iters_last"] for st in stats])
     out = {"workload": "256 uneven 3D instances (16k-411k cells), mixed precision, one Newton iteration each",
-           "instances": len(pbs), "cells": int(sum(sizes)), "s_per_batch_step": elapsed,
-           "instances_per_s": len(pbs) / elapsed, "cells_per_s": sum(sizes) / elapsed,
+           "instances": len(pbs), "cells": int(sum(sizes)), "s_per_batch_step_median": med,
+           "instances_per_s": len(pbs) / med, "cells_per_s": sum(sizes) / med, "passes": steps,
            "cams_iterations": {"min": int(its.min()), "mean": float(its.mean()), "max": int(its.max())},
            "setup_ms": stats[0]["t_coarse_ms"], "iterate_ms": stats[0]["t_iterate_ms"], "tuning": b.tuning()}
     if sequential:
-        # the same instances, one at a time through the single-problem path
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, sv in enumerate(b.solvers):
@@ -155,136 +285,92 @@ def batch_run(steps, warmup, torch, sequential=True):
         torch.cuda.synchronize()
         seq = time.perf_counter() - t0
         out["sequential_single_path_s"] = seq
-        out["speedup_vs_sequential"] = seq / elapsed
+        out["speedup_vs_sequential"] = seq / med
     b.close()
     return out
 
 
-def large_run(torch):
-    """The 256x256x128 channelised workload (8.4M cells, 16384 coarse nodes,
-    block-tridiagonal coarse factorisation), BF16 basis and prolongation,
-    FP32 smoother, FP64 residual and coarse solve: one pass of its 5 time
-    steps, smoother kernel timed live."""
-    from paper_1705_05783_amd.solver import Solver
-    from workloads.configs import config4
-    pb = config4()
-    solver = Solver(pb, device=torch.device("cuda:0"))
-    solver.profile()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solves, iters, _ = run_workload(solver, pb, torch)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    out = {"workload": "256x256x128 channelised (k 1 / 1e-4, 30% channels), coarsening 8^3, 16384 coarse nodes, "
-                       "BF16 basis, 5 time steps dt=0.05 to 1e-8",
-           "cells": pb.n, "coarse_nodes": solver.Nc, "s_per_solve": elapsed / max(solves, 1),
-           "ms_per_pass": elapsed * 1e3, "newton_solves": solves,
-           "cams_iterations_per_solve": iters / max(solves, 1),
-           "roofline_smoother": roofline(solver.profile_read(), "256x256x128 channelised BF16")}
-    solver.close()
-    return out
-
-
-def learned_run(torch):
-    """The 128^3 evaluation workload (sigma 3, correlation 8, c = 0.1, one
-    time step): time to solution per Newton linear solve for plain FP64
-    C-AMS, mixed precision, and mixed precision with the trained network for
-    the full dual-block interiors (local-solve fallback for blocks whose
-    basis residual exceeds LEARNED_FALLBACK_TOL times their boundary flux).
-    The basis is rebuilt in every pass, so its cost is in the per-solve
-    time."""
-    import torch as _t
-    from paper_1705_05783_amd import _cams as C
-    from paper_1705_05783_amd.solver import Solver
-    from paper_1705_05783_amd.train_basis import load_weights
-    from workloads.configs import FP64, MIXED_FP32, config5_eval
-    params = load_weights()
-    out = {"workload": "128^3 lognormal (sigma 3, corr. 8), coarsening 8^3, c=0.1, one time step, Newton and "
-                       "linear solves to 1e-8"}
-    for label, prec, learned in (("plain_fp64", FP64, False), ("mixed", MIXED_FP32, False),
-                                 ("learned_mixed", MIXED_FP32, True)):
-        pb = config5_eval(precision=prec)
-        solver = Solver(pb, device=_t.device("cuda:0"))
-        if learned:
-            solver.set_learned(params, fallback_tol=LEARNED_FALLBACK_TOL)
-        run_workload(solver, pb, torch)   # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        solves, iters, _ = run_workload(solver, pb, torch)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        r = {"s_per_solve": elapsed / max(solves, 1), "newton_solves": solves,
-             "cams_iterations_per_solve": iters / max(solves, 1)}
-        if learned:
-            r.update(solver.basis_stats())
-        out[label] = r
-        solver.close()
-    out["speedup_learned_mixed_vs_plain"] = out["plain_fp64"]["s_per_solve"] / out["learned_mixed"]["s_per_solve"]
-    out["speedup_mixed_vs_plain"] = out["plain_fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
-    # basis error of the network against the exact local solves (FP64 storage)
+def cpu_baseline(gpu_plain):
+    """The oracle (plain FP64 C-AMS, the same algorithm as plain_fp64) on the
+    128^3 workload, in its timing build (-O3 -march=native -fopenmp, built
+    here for this host), on a bounded sample of one pass: transmissibilities,
+    the whole B4 basis, then the first Newton iteration's assembly, coarse
+    operator R A P, coarse LU, ILU(0) factors and 3 C-AMS iterations.  Per
+    Newton linear solve = basis / solves per pass + assembly + coarse
+    operator + LU + ILU(0) setup + (C-AMS iterations per solve of the GPU
+    plain_fp64 pass, which the oracle's count matches within one) x time per
+    iteration.  Two legs: all host cores, and one thread (there the LU is
+    timed on the leading 2048 x 2048 block of the coarse operator and scaled
+    by 8 = (4096/2048)^3)."""
+    import oracle
+    from workloads.configs import FP64, config5_eval
     pb = config5_eval(precision=FP64)
-    solver = Solver(pb, device=_t.device("cuda:0"))
-    solver.build_basis()
-    P_exact = solver.export(C.CAMS_ARR_P)
-    solver.set_learned(params, fallback_tol=1e30)
-    solver.build_basis()
-    P_net = solver.export(C.CAMS_ARR_P)
-    out["basis_rel_l2_error_no_fallback"] = float((P_net - P_exact).norm() / P_exact.norm())
-    solver.close()
-    return out
-
-
-def measured_traffic(workload):
-    """HBM bytes per launch of the smoother kernel from the committed memory
-    counter record (FETCH_SIZE + WRITE_SIZE, scaled by a device copy), or
-    None when the kernel source has changed since the counters were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_bilu_step.json")
-    try:
-        rec = json.load(open(path))
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    except (OSError, ValueError, KeyError):
-        return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
-        return None
-    w = rec["workloads"].get(workload)
-    return None if w is None else w["traffic_bytes_per_launch"]
-
-
-def roofline(prof, workload=None):
-    if prof["launches"] == 0 or prof["total_ms"] <= 0:
-        return None
-    per_launch_bytes = prof["bytes"] / prof["launches"]
-    avg_s = prof["total_ms"] * 1e-3 / prof["launches"]
-    achieved = per_launch_bytes / avg_s / 1e9
-    return {"kernel": "k_bilu_step (block-ILU(0) Richardson step)", "bound": "hbm",
-            "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_traffic(workload) if workload else None, "avg_launch_us": avg_s * 1e6,
-            "bytes_per_launch": per_launch_bytes, "launches": prof["launches"]}
+    oracle.build_timing()
+    cores = min(16, len(os.sched_getaffinity(0)))   # the host share of one GPU
+    solves = gpu_plain["newton_solves_per_pass"]
+    its = gpu_plain["cams_iterations_per_solve"]
+    legs = {}
+    for threads in (cores, 1) if cores > 1 else (1,):
+        with oracle.timing_build(threads):
+            t = {}
+            t0 = time.perf_counter()
+            T = oracle.transmissibility(pb)
+            P = oracle.basis_b4(pb, T)
+            t["basis"] = time.perf_counter() - t0
+            pn = pb.initial_pressure()
+            t0 = time.perf_counter()
+            W, diag, r0, _ = oracle.linear_system(pb, T, pn, pn)
+            t["assemble"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            Ac = oracle.coarse_operator(pb, W, diag, P, pb.restriction)
+            t["coarse_operator"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            if threads == 1 and cores > 1:
+                oracle.lu_factor(Ac[:2048, :2048])
+                t["coarse_lu"] = 8.0 * (time.perf_counter() - t0)
+                LU, piv = legs[cores]["_lu"]
+            else:
+                LU, piv = oracle.lu_factor(Ac)
+                t["coarse_lu"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            ilu = oracle.smoother_for(pb, W, diag)
+            t["ilu_setup"] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.cams_solve(pb, W, diag, P, pb.restriction, LU, piv, ilu, r0, maxit=3)
+            t["per_iteration"] = (time.perf_counter() - t0) / 3
+            per_solve = (t["basis"] / max(solves, 1) + t["assemble"] + t["coarse_operator"] + t["coarse_lu"] +
+                         t["ilu_setup"] + its * t["per_iteration"])
+            legs[threads] = {"s_per_solve": per_solve, "threads": threads, "parts_s": t, "_lu": (LU, piv)}
+    for leg in legs.values():
+        leg.pop("_lu")
+    best = legs[cores]
+    return {"value": best["s_per_solve"], "unit": "s per Newton linear solve", "cores": cores, "kind": "oracle",
+            "sample": f"128^3 plain FP64 (the headline workload): B4 basis + first Newton iteration's assembly, "
+                      f"R A P, coarse LU (4096 nodes), ILU(0) setup and 3 C-AMS iterations, scaled to "
+                      f"{its:.1f} iterations per solve and {solves} solves per pass; oracle timing build "
+                      f"-O3 -march=native -fopenmp on {cores} threads; CPU {_cpu_model()}",
+            "single_thread": {"value": legs[1]["s_per_solve"], "parts_s": legs[1]["parts_s"],
+                              "note": "coarse LU timed on the leading 2048 x 2048 block, x8" if cores > 1
+                              else "coarse LU timed in full"},
+            "all_cores": {"value": best["s_per_solve"], "threads": cores, "parts_s": best["parts_s"]}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=7, help="timed passes per workload (median reported)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed passes per workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["mixed", "plain", "both", "batch", "large", "learned", "copy"],
-                    default="both",
-                    help="mixed/plain/both: the headline workload; batch/large/learned: that workload alone "
-                         "(one JSON object, for profiling); copy: a 256 MiB device copy, the reference kernel "
-                         "for scaling memory counters")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batched solve")
-    ap.add_argument("--no-extra", action="store_true", help="skip the large and learned-basis workloads")
+    ap.add_argument("--only", choices=["headline", "adaptive", "small", "large", "batch", "copy", "all"],
+                    default="all",
+                    help="headline/small/large/batch: that workload alone (one JSON object, for profiling); "
+                         "copy: a 256 MiB device copy, the reference kernel for scaling memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the solve runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}), flush=True)
+        print(json.dumps({"error": "the solve runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}),
+              flush=True)
         sys.exit(2)
-
     import torch
-    from workloads import config2
-    from workloads.configs import FP64, MIXED_FP32
 
     if args.only == "copy":
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -294,63 +380,54 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copies": 3}), flush=True)
         return
-    if args.only in ("batch", "large", "learned"):
-        fn = {"batch": lambda: batch_run(args.steps, args.warmup, torch, sequential=False),
-              "large": lambda: large_run(torch), "learned": lambda: learned_run(torch)}[args.only]
-        print(json.dumps({args.only: fn()}), flush=True)
+    steps, warmup = max(1, args.steps), max(0, args.warmup)
+    if args.only in ("adaptive", "small", "large", "batch"):
+        fn = {"adaptive": adaptive_run, "small": small_run, "large": large_run,
+              "batch": lambda s, w, t: batch_run(s, w, t, False)}
+        print(json.dumps({args.only: fn[args.only](steps, warmup, torch)}), flush=True)
         return
 
-    runs = {}
-    if args.only in ("mixed", "both"):
-        runs["mixed"] = timed_run(config2(precision=MIXED_FP32), args.steps, args.warmup, torch)
-    if args.only in ("plain", "both"):
-        runs["plain"] = timed_run(config2(precision=FP64), args.steps, args.warmup, torch)
-    head = runs.get("mixed") or runs["plain"]
-    pb = config2()
-
-    def summary(r):
-        return {"s_per_solve": r["elapsed"] / max(r["solves"], 1),
-                "ms_per_step": r["elapsed"] * 1e3 / args.steps,
-                "newton_solves_per_step": r["solves"] / args.steps,
-                "cams_iterations_per_solve": r["iters"] / max(r["solves"], 1),
-                "roofline_smoother": roofline(r["prof"])}
-
+    head = headline(steps, warmup, torch)
+    lm = head["learned_mixed"]
+    from workloads.configs import config5_eval
+    pb = config5_eval()
     out = {
-        "metric": "s per Newton linear solve to 1e-8 rel. residual",
-        "value": head["elapsed"] / max(head["solves"], 1),
+        "metric": "s per Newton linear solve to 1e-8 rel. residual, learned+mixed vs plain; HBM GB/s",
+        "value": lm["s_per_solve"],
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": head["elapsed"] * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": lm["ms_per_pass_median"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if "mixed" in runs else "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "64x64x32 lognormal (sigma 3, corr. 8x8x2), coarsening 8^3 (256 coarse nodes), "
-                               "MSFE, 5 block-ILU(0) post-smoothing steps (block grid shifted by half a block on every other "
-                               "step), 10 backward-Euler steps dt=0.05, "
-                               "Newton and linear solves to 1e-8; value = mixed precision (FP32 smoother, "
-                               "basis and prolongation, FP64 residual/update/coarse solve)" if "mixed" in runs
-                               else "64x64x32 workload, plain FP64",
-                   "cells": pb.n, "coarse_nodes": head["Nc"],
-                   "newton_solves_per_step": head["solves"] / args.steps,
-                   "cams_iterations_per_solve": head["iters"] / max(head["solves"], 1)},
-        "roofline": roofline(head["prof"], "64x64x32 mixed" if "mixed" in runs else None),
+        "config": {"workload": "128^3 lognormal (sigma 3, corr. 8, seed 5), coarsening 8^3 (4096 coarse nodes), "
+                               "c=0.1, dt=0.1, one time step per pass, MSFE, 5 alternating block-ILU(0) "
+                               "post-smoothing steps, Newton and linear solves to 1e-8; value = learned+mixed "
+                               "(trained network for the full dual-block interiors with local-solve fallback, "
+                               "FP32 smoother/basis/prolongation, FP64 residual/update/coarse solve), time to "
+                               "solution per Newton linear solve incl. the basis",
+                   "cells": pb.n, "coarse_nodes": lm["coarse_nodes"],
+                   "newton_solves_per_step": lm["newton_solves_per_pass"],
+                   "cams_iterations_per_solve": lm["cams_iterations_per_solve"]},
+        "roofline": lm["roofline_smoother"],
+        "learned_mixed": lm,
+        "mixed": head["mixed"],
+        "plain_fp64": head["plain_fp64"],
     }
-    for k, r in runs.items():
-        out[k] = summary(r)
-    if "mixed" in runs and "plain" in runs:
-        out["speedup_mixed_vs_plain_per_solve"] = (runs["plain"]["elapsed"] / runs["plain"]["solves"]) / \
-            (runs["mixed"]["elapsed"] / runs["mixed"]["solves"])
-    if not args.no_batch:
-        out["batch"] = batch_run(args.steps, args.warmup, torch)
-    if not args.no_extra:
-        out["large"] = large_run(torch)
-        out["learned"] = learned_run(torch)
+    for k in ("speedup_learned_mixed_vs_plain", "speedup_mixed_vs_plain", "speedup_learned_mixed_vs_mixed",
+              "speedup_learned_mixed_vs_plain_iterations_only"):
+        out[k] = head[k]
+    if args.only == "all":
+        out["adaptive_newton"] = adaptive_run(steps, warmup, torch)
+        out["small"] = small_run(steps, warmup, torch)
+        out["large"] = large_run(steps, warmup, torch)
+        out["batch"] = batch_run(steps, warmup, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pb)
+        out["cpu_baseline"] = cpu_baseline(head["plain_fp64"])
     print(json.dumps(out), flush=True)
 
 

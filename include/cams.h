@@ -103,13 +103,14 @@ typedef struct {
     int32_t lin_maxit;        /* linear iteration limit */
     double newton_tol;        /* stop Newton when ||eps||_2 <= newton_tol (Eq. (16)) */
     int32_t newton_maxit;     /* Newton iteration limit per time step */
+    double lin_atol;          /* also stop when ||r||_2 <= lin_atol (absolute; 0 = relative test only) */
 } cams_options;
 
 typedef struct {
     int32_t newton_iters;     /* linear solves performed in the last cams_newton_step */
     int32_t lin_iters_total;  /* C-AMS iterations summed over those solves */
     int32_t lin_iters_last;   /* C-AMS iterations of the last cams_iterate */
-    int32_t reserved;
+    int32_t fallback_blocks;  /* learned basis: blocks re-solved exactly in the basis build (0 otherwise) */
     double relres_last;       /* ||r||/||r0|| at the end of the last cams_iterate */
     double eps_norm_last;     /* last ||eps||_2 from cams_assemble */
     double t_assemble_ms;     /* device time of the last newton step's phases (hipEvent) */
@@ -145,8 +146,9 @@ cams_status cams_set_workspace(cams_ctx *ctx, void *dev_ptr, size_t bytes);
  * none).  Copies them into the workspace and computes the two-point
  * transmissibilities (harmonic average of the two half-cell conductances,
  * Eq. (6)).  Invalidates any basis already built.
- * Errors: CAMS_E_STATE (no workspace), CAMS_E_ARG (null pointers),
- * CAMS_E_BREAKDOWN (a permeability or porosity value is out of range). */
+ * Errors: CAMS_E_STATE (no workspace), CAMS_E_ARG (null pointers, or a
+ * permeability or porosity value out of range: checked on the device, so
+ * this call synchronises the stream). */
 cams_status cams_set_rock(cams_ctx *ctx, const double *perm_dev, const double *phi_dev,
                           const double *q_dev);
 
@@ -194,10 +196,13 @@ cams_status cams_coarse_op(cams_ctx *ctx);
 /* Solve the assembled system for the Newton update by C-AMS iterations
  * (Table "cams"; Eq. (15) multiscale stage, ILU(0) smoothing) and add it to
  * p_dev in place:  p <- p + d,  A d = r.  Stops when
- * ||r||_2 <= lin_rtol ||r0||_2 or after lin_maxit iterations.  `stats` may be
- * NULL.  Errors: CAMS_E_STATE (no coarse operator for the current system),
- * CAMS_E_NOT_CONVERGED (limit reached; p holds the last iterate),
- * CAMS_E_BREAKDOWN (non-finite residual norm). */
+ * ||r||_2 <= max(lin_rtol ||r0||_2, lin_atol) or after lin_maxit iterations.  Stagnation
+ * also stops it: when ||r||_2 has not fallen below 0.9 times its smallest
+ * value so far for 100 iterations (e.g. a tolerance below the rounding level
+ * of the FP64 residual).  `stats` may be NULL.  Errors: CAMS_E_STATE (no
+ * coarse operator for the current system), CAMS_E_NOT_CONVERGED (limit
+ * reached or stagnation; p holds the last iterate whose residual was
+ * evaluated), CAMS_E_BREAKDOWN (non-finite residual norm). */
 cams_status cams_iterate(cams_ctx *ctx, double *p_dev, cams_stats *stats);
 
 /* One backward-Euler time step: Dirichlet values are imposed on p_dev, the
@@ -207,6 +212,44 @@ cams_status cams_iterate(cams_ctx *ctx, double *p_dev, cams_stats *stats);
  * Errors: as the calls above; CAMS_E_NOT_CONVERGED if Newton does not reach
  * newton_tol. */
 cams_status cams_newton_step(cams_ctx *ctx, const double *pn_dev, double *p_dev, cams_stats *stats);
+
+/* Mass-conservative finish of a time step (Sec. 4.2: converge with MSFE,
+ * then apply a single MSFV sweep; an MSFV stage yields fluxes that are
+ * conservative on the coarse grid, Sec. 4).  At pressure p_dev (normally
+ * the converged result of cams_newton_step with MSFE) and old-time pressure
+ * pn_dev: assemble the Newton system (Eqs. (3)-(6)), form the MSFV coarse
+ * operator R^FV A P_hat (Eqs. (7), (13)), invert it (LU with partial
+ * pivoting), and apply one multiscale stage d = P_hat (R^FV A P_hat)^-1 R^FV r
+ * (Eqs. (12), (15)); p_dev += d.  flux_dev (3N doubles, device) receives
+ * the two-point mass fluxes of that linear system at the updated pressure,
+ * T (rho(p_n) + rho(p_m))/2 (p'_n - p'_m) with the face densities of the
+ * assembly point p and the updated p', on the +x, +y, +z face of every cell
+ * (positive out of the cell, 0 on the domain boundary): on every primal
+ * coarse block, accumulation (linearised at p) + net outflow - sources sums
+ * to zero.  Builds the basis if needed; the coarse factorisation is
+ * replaced, so the next cams_iterate needs cams_coarse_op again.
+ * Errors: CAMS_E_STATE (no rock), CAMS_E_ARG (null arrays; more than 4096
+ * coarse nodes, which use the block-tridiagonal MSFE factorisation),
+ * CAMS_E_BREAKDOWN (singular coarse matrix), CAMS_E_DEVICE. */
+cams_status cams_conservative_sweep(cams_ctx *ctx, const double *pn_dev, double *p_dev, double *flux_dev);
+
+/* One time step as cams_newton_step, recording after every C-AMS iteration
+ * (each evaluation of the linear residual, the first one being r0) the
+ * Newton iteration index nu, the linear residual norm ||r||_2 of the
+ * current Newton system and the nonlinear error ||eps||_2 (Eq. (16)) at the
+ * current iterate p^nu + d.  These are the error and residual norm histories
+ * of the paper's study of linear and nonlinear stopping (Sec. 4.1.1: with
+ * the linear solve converged at every Newton step, and with the adaptive
+ * strategy of lin_rtol = 1e-1 and newton_tol = 1e-6, which updates the
+ * linear system only after the residual has dropped by an order of
+ * magnitude).  Host arrays of `cap` entries receive the first `cap` entries;
+ * *count is set to the number of entries produced (may exceed cap).  Each
+ * entry costs one extra nonlinear-error evaluation and a synchronisation:
+ * for studies, not for timing.  Errors: as cams_newton_step; CAMS_E_ARG
+ * (null buffers with cap > 0, null count). */
+cams_status cams_newton_history(cams_ctx *ctx, const double *pn_dev, double *p_dev, double *res_host,
+                                double *err_host, int32_t *newton_host, int32_t cap, int32_t *count,
+                                cams_stats *stats);
 
 /* One application of the smoother, x = M^{-1} z, with M the ILU(0) factor of
  * the assembled matrix chosen by options.smoother (Table "cams" step 6); for
@@ -313,6 +356,12 @@ cams_status cams_set_learned(cams_ctx *ctx, const float *params_dev, void *scrat
                              double fallback_tol);
 /* Blocks taken from the network and blocks re-solved by the fallback in the
  * last cams_build_basis.  Errors: CAMS_E_ARG. */
+/* The local-equation ratio ||(T Phi)_I|| / ||T_IF Phi_F|| of the network's
+ * prediction for each full dual block of the last learned cams_build_basis
+ * (before any fallback), in block order (x fastest); n <= the number of full
+ * blocks, written to host memory.  Used to calibrate fallback_tol.
+ * Errors: CAMS_E_ARG, CAMS_E_STATE (no learned build, or n too large). */
+cams_status cams_basis_block_ratios(const cams_ctx *ctx, double *ratio_host, int32_t n);
 cams_status cams_basis_stats(const cams_ctx *ctx, int32_t *learned_blocks, int32_t *fallback_blocks);
 
 /* Number of coarse nodes (product of ceil(n/r) per axis). */

@@ -28,6 +28,14 @@
  *   - vertex of a primal block of length L starting at s is s + floor(L/2).
  *
  * Parity status per function is listed in the header comment of each.
+ *
+ * The tests build this file without OpenMP, so every "omp" pragma below is
+ * ignored there and the oracle runs serially and deterministically.  The
+ * CPU-baseline timing build (-O3 -march=native -fopenmp) runs the loops the
+ * pragmas mark on all host cores: cells, dual regions of one level, rows of
+ * the coarse LU update, blocks of a block-ILU(0) factor.  Only reductions
+ * and the scatter-adds of the coarse operator and the restriction change
+ * their order of summation there.
  */
 #include <math.h>
 #include <stdint.h>
@@ -86,6 +94,7 @@ void or_transmissibility(const og_grid *g, double mu, const double *perm,
                          double *Tx, double *Ty, double *Tz)
 {
     double ax = g->dy * g->dz, ay = g->dx * g->dz, az = g->dx * g->dy;
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < g->nz; k++)
         for (int j = 0; j < g->ny; j++)
             for (int i = 0; i < g->nx; i++) {
@@ -127,6 +136,7 @@ double or_nonlinear_residual(const og_grid *g, const og_fluid *f,
 {
     long N = ncells(g);
     double dV = g->dx * g->dy * g->dz, e2 = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : e2)
     for (long n = 0; n < N; n++) {
         if (dmask[n]) { F[n] = 0.0; continue; }
         double rho = density(f, p[n]), rhon = density(f, pn[n]);
@@ -169,6 +179,7 @@ double or_linear_system(const og_grid *g, const og_fluid *f,
     double dV = g->dx * g->dy * g->dz;
     double en = or_nonlinear_residual(g, f, Tx, Ty, Tz, phi, q, dmask, p, pn, r);
     for (long n = 0; n < N; n++) r[n] = -r[n];
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < g->nz; k++)
         for (int j = 0; j < g->ny; j++)
             for (int i = 0; i < g->nx; i++) {
@@ -194,11 +205,39 @@ double or_linear_system(const og_grid *g, const og_fluid *f,
     return en;
 }
 
+/* ------------------------------------------------------------------------
+ * Two-point mass fluxes (Sec. 2, the flux term of Eqs. (2)-(3)): on the face
+ * between cell n and its +x / +y / +z neighbour m,
+ *   flux = T_nm (rho(q_n) + rho(q_m)) / 2 (p_n - p_m),
+ * positive from n to m, stored on n (0 on the domain boundary).  With q = p
+ * these are the fluxes of the nonlinear residual F; with q the iterate at
+ * which a Newton system was assembled and p its updated solution they are
+ * the fluxes of that linear system (face densities frozen at q).
+ * Pinned: F rebuilt from the fluxes equals or_nonlinear_residual; after an
+ * MSFV stage the coarse-block sums of the linearised balance vanish.
+ * ---------------------------------------------------------------------- */
+void or_face_flux(const og_grid *g, const og_fluid *f, const double *Tx, const double *Ty, const double *Tz,
+                  const double *q, const double *p, double *Fx, double *Fy, double *Fz)
+{
+    long s = (long)g->nx * g->ny;
+    for (int k = 0; k < g->nz; k++)
+        for (int j = 0; j < g->ny; j++)
+            for (int i = 0; i < g->nx; i++) {
+                long n = cell_index(g, i, j, k);
+                double rho = density(f, q[n]);
+                Fx[n] = Fy[n] = Fz[n] = 0.0;
+                if (i + 1 < g->nx) Fx[n] = Tx[n] * 0.5 * (rho + density(f, q[n + 1])) * (p[n] - p[n + 1]);
+                if (j + 1 < g->ny) Fy[n] = Ty[n] * 0.5 * (rho + density(f, q[n + g->nx])) * (p[n] - p[n + g->nx]);
+                if (k + 1 < g->nz) Fz[n] = Tz[n] * 0.5 * (rho + density(f, q[n + s])) * (p[n] - p[n + s]);
+            }
+}
+
 /* y = A x for the 7-point operator stored as (W, diag). */
 void or_matvec(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
                const double *diag, const double *x, double *y)
 {
     long N = ncells(g);
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; n++) {
         double s = diag[n] * x[n];
         for (int fc = 0; fc < 6; fc++) {
@@ -357,8 +396,90 @@ static int dense_solve(int m, double *M, int nrhs, double *B)
  * Pinned: partition of unity, 0 <= Phi <= 1, unit value at own vertex,
  * bilinear/trilinear hat for homogeneous k, series-resistance edges.
  * ---------------------------------------------------------------------- */
+/* Local problem of one dual region (the connected set of cells of level L
+ * given in `rc_cells`): unknowns are its cells, Dirichlet data the basis
+ * values already set on higher-level neighbours, couplings to lower-level
+ * neighbours lumped (left out of the row).  Writes the region's basis
+ * values into P.  `pos` is scratch of N entries, -1 outside the call for
+ * the region's cells.  Returns 0, or -1 if the local matrix is singular or
+ * a value falls on a node that does not bracket its cell. */
+static int solve_region(const og_grid *g, const og_dual *dd, const double *Tx, const double *Ty,
+                        const double *Tz, const double *adiag, const int *level, long *pos,
+                        const long *rc_cells, long m, int L, long N, double *P)
+{
+    og_dual d = *dd;
+    int rc = 0;
+    for (long a = 0; a < m; a++) pos[rc_cells[a]] = a;
+    /* coarse nodes reached through higher-level neighbours */
+    long nodes[64]; int nn = 0;
+    for (long a = 0; a < m; a++) {
+        long n = rc_cells[a];
+        for (int fc = 0; fc < 6; fc++) {
+            long nb; double T;
+            if (!neighbour(g, Tx, Ty, Tz, n, fc, &nb, &T)) continue;
+            if (level[nb] <= L) continue;
+            for (int s = 0; s < 8; s++) {
+                if (P[(long)s * N + nb] == 0.0) continue;
+                int ia, ib, ic;
+                long node = node_of_slot(g, &d, nb, s, &ia, &ib, &ic);
+                int seen = 0;
+                for (int t = 0; t < nn; t++) if (nodes[t] == node) seen = 1;
+                if (!seen && nn < 64) nodes[nn++] = node;
+            }
+        }
+    }
+    double *M = (double *)calloc((size_t)m * m, sizeof(double));
+    double *B = (double *)calloc((size_t)m * (nn > 0 ? nn : 1), sizeof(double));
+    for (long a = 0; a < m; a++) {
+        long n = rc_cells[a];
+        if (adiag) M[a * m + a] += adiag[n];       /* accumulation term of B1 / B3 */
+        for (int fc = 0; fc < 6; fc++) {
+            long nb; double T;
+            if (!neighbour(g, Tx, Ty, Tz, n, fc, &nb, &T)) continue;
+            if (level[nb] < L) continue;             /* lumped */
+            M[a * m + a] += T;
+            if (level[nb] == L) { M[a * m + pos[nb]] -= T; continue; }
+            for (int s = 0; s < 8; s++) {
+                double w = P[(long)s * N + nb];
+                if (w == 0.0) continue;
+                int ia, ib, ic;
+                long node = node_of_slot(g, &d, nb, s, &ia, &ib, &ic);
+                for (int t = 0; t < nn; t++) if (nodes[t] == node) B[a * nn + t] += T * w;
+            }
+        }
+    }
+    if (nn > 0 && dense_solve((int)m, M, nn, B) != 0) rc = -1;
+    for (long a = 0; a < m && rc == 0; a++) {
+        long n = rc_cells[a];
+        for (int t = 0; t < nn; t++) {
+            long node = nodes[t];
+            int ia = (int)(node % d.nb[0]), ib = (int)((node / d.nb[0]) % d.nb[1]), ic = (int)(node / ((long)d.nb[0] * d.nb[1]));
+            int s = node_slot(g, &d, n, ia, ib, ic);
+            if (s < 0) { if (B[a * nn + t] != 0.0) rc = -1; continue; }
+            P[(long)s * N + n] = B[a * nn + t];
+        }
+    }
+    for (long a = 0; a < m; a++) pos[rc_cells[a]] = -1;
+    free(M); free(B);
+    return rc;
+}
+
+/* Basis of a general local operator (Sec. 3, Eqs. (8)-(11)): face
+ * couplings Cx/Cy/Cz (T for B3/B4, the density-weighted W = T rho_f of the
+ * current iterate for B1/B2) and an optional extra diagonal adiag (the
+ * accumulation term of B1/B3; NULL for B2/B4).  Same wirebasket order and
+ * reduced boundary conditions as B4. */
+int or_basis_general(const og_grid *g, const double *Tx, const double *Ty, const double *Tz,
+                     const double *adiag, double *P);
+
 int or_basis_b4(const og_grid *g, const double *Tx, const double *Ty, const double *Tz,
                 double *P)
+{
+    return or_basis_general(g, Tx, Ty, Tz, NULL, P);
+}
+
+int or_basis_general(const og_grid *g, const double *Tx, const double *Ty, const double *Tz,
+                     const double *adiag, double *P)
 {
     long N = ncells(g);
     og_dual d; dual_init(g, &d);
@@ -373,11 +494,15 @@ int or_basis_b4(const og_grid *g, const double *Tx, const double *Ty, const doub
     for (long n = 0; n < N; n++)
         if (level[n] == d.dim) P[0 * N + n] = 1.0;   /* own node sits in slot 0 */
 
+    long *rstart = (long *)malloc(sizeof(long) * (N + 1));
     for (int L = d.dim - 1; L >= 0 && rc == 0; L--) {
-        for (long seed = 0; seed < N && rc == 0; seed++) {
+        /* the connected sets (regions) of level-L cells, by flood fill; the
+         * cells of region q are cells[rstart[q] .. rstart[q+1]) */
+        long nreg = 0, m = 0;
+        for (long seed = 0; seed < N; seed++) {
             if (level[seed] != L || region[seed] >= 0) continue;
-            /* flood fill the connected set of level-L cells */
-            long m = 0, top = 0;
+            long top = 0;
+            rstart[nreg++] = m;
             stack[top++] = seed; region[seed] = seed;
             while (top > 0) {
                 long n = stack[--top];
@@ -388,59 +513,19 @@ int or_basis_b4(const og_grid *g, const double *Tx, const double *Ty, const doub
                     if (level[nb] == L && region[nb] < 0) { region[nb] = seed; stack[top++] = nb; }
                 }
             }
-            for (long a = 0; a < m; a++) pos[cells[a]] = a;
-            /* coarse nodes reached through higher-level neighbours */
-            long nodes[64]; int nn = 0;
-            for (long a = 0; a < m; a++) {
-                long n = cells[a];
-                for (int fc = 0; fc < 6; fc++) {
-                    long nb; double T;
-                    if (!neighbour(g, Tx, Ty, Tz, n, fc, &nb, &T)) continue;
-                    if (level[nb] <= L) continue;
-                    for (int s = 0; s < 8; s++) {
-                        if (P[(long)s * N + nb] == 0.0) continue;
-                        int ia, ib, ic;
-                        long node = node_of_slot(g, &d, nb, s, &ia, &ib, &ic);
-                        int seen = 0;
-                        for (int t = 0; t < nn; t++) if (nodes[t] == node) seen = 1;
-                        if (!seen && nn < 64) nodes[nn++] = node;
-                    }
-                }
-            }
-            double *M = (double *)calloc((size_t)m * m, sizeof(double));
-            double *B = (double *)calloc((size_t)m * (nn > 0 ? nn : 1), sizeof(double));
-            for (long a = 0; a < m; a++) {
-                long n = cells[a];
-                for (int fc = 0; fc < 6; fc++) {
-                    long nb; double T;
-                    if (!neighbour(g, Tx, Ty, Tz, n, fc, &nb, &T)) continue;
-                    if (level[nb] < L) continue;             /* lumped */
-                    M[a * m + a] += T;
-                    if (level[nb] == L) { M[a * m + pos[nb]] -= T; continue; }
-                    for (int s = 0; s < 8; s++) {
-                        double w = P[(long)s * N + nb];
-                        if (w == 0.0) continue;
-                        int ia, ib, ic;
-                        long node = node_of_slot(g, &d, nb, s, &ia, &ib, &ic);
-                        for (int t = 0; t < nn; t++) if (nodes[t] == node) B[a * nn + t] += T * w;
-                    }
-                }
-            }
-            if (nn > 0 && dense_solve((int)m, M, nn, B) != 0) rc = -1;
-            for (long a = 0; a < m && rc == 0; a++) {
-                long n = cells[a];
-                for (int t = 0; t < nn; t++) {
-                    long node = nodes[t];
-                    int ia = (int)(node % d.nb[0]), ib = (int)((node / d.nb[0]) % d.nb[1]), ic = (int)(node / ((long)d.nb[0] * d.nb[1]));
-                    int s = node_slot(g, &d, n, ia, ib, ic);
-                    if (s < 0) { if (B[a * nn + t] != 0.0) rc = -1; continue; }
-                    P[(long)s * N + n] = B[a * nn + t];
-                }
-            }
-            for (long a = 0; a < m; a++) pos[cells[a]] = -1;
-            free(M); free(B);
+        }
+        rstart[nreg] = m;
+        /* one local problem per region; regions of a level only read basis
+         * values of higher levels, so they are independent */
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : rc)
+        for (long q = 0; q < nreg; q++) {
+            const long *rc_cells = cells + rstart[q];
+            long mq = rstart[q + 1] - rstart[q];
+            if (solve_region(g, &d, Tx, Ty, Tz, adiag, level, pos, rc_cells, mq, L, N, P) != 0) rc |= 1;
         }
     }
+    if (rc) rc = -1;
+    free(rstart);
     free(level); free(region); free(stack); free(cells); free(pos);
     dual_free(&d);
     return rc;
@@ -485,8 +570,9 @@ void or_coarse_operator(const og_grid *g, const double *Wx, const double *Wy, co
     int32_t *blk = (int32_t *)malloc(sizeof(int32_t) * N);
     or_primal_block(g, blk);
     memset(Ac, 0, sizeof(double) * (size_t)Nc * Nc);
-    long ids[64]; double vals[64];
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; n++) {
+        long ids[64]; double vals[64];
         int cnt = 0;
         /* row n of A P_hat as a short list of (coarse node, value) */
         for (int fc = -1; fc < 6; fc++) {
@@ -509,7 +595,10 @@ void or_coarse_operator(const og_grid *g, const double *Wx, const double *Wy, co
             }
         }
         if (restriction == OR_FV) {
-            for (int t = 0; t < cnt; t++) Ac[(long)blk[n] * Nc + ids[t]] += vals[t];
+            for (int t = 0; t < cnt; t++) {
+#pragma omp atomic
+                Ac[(long)blk[n] * Nc + ids[t]] += vals[t];
+            }
         } else {
             if (dmask[n]) continue;
             for (int s = 0; s < 8; s++) {
@@ -517,7 +606,10 @@ void or_coarse_operator(const og_grid *g, const double *Wx, const double *Wy, co
                 if (w == 0.0) continue;
                 int a, b, c;
                 long k = node_of_slot(g, &d, n, s, &a, &b, &c);
-                for (int t = 0; t < cnt; t++) Ac[k * Nc + ids[t]] += w * vals[t];
+                for (int t = 0; t < cnt; t++) {
+#pragma omp atomic
+                    Ac[k * Nc + ids[t]] += w * vals[t];
+                }
             }
         }
     }
@@ -539,6 +631,7 @@ void or_restrict(const og_grid *g, const uint8_t *dmask, const double *P, int re
         for (long n = 0; n < N; n++) xc[blk[n]] += x[n];
         free(blk);
     } else {
+#pragma omp parallel for schedule(static)
         for (long n = 0; n < N; n++) {
             if (dmask[n]) continue;
             for (int s = 0; s < 8; s++) {
@@ -546,6 +639,7 @@ void or_restrict(const og_grid *g, const uint8_t *dmask, const double *P, int re
                 if (w == 0.0) continue;
                 int a, b, c;
                 long k = node_of_slot(g, &d, n, s, &a, &b, &c);
+#pragma omp atomic
                 xc[k] += w * x[n];
             }
         }
@@ -558,6 +652,7 @@ void or_prolong(const og_grid *g, const uint8_t *dmask, const double *P, const d
 {
     og_dual d; dual_init(g, &d);
     long N = ncells(g);
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; n++) {
         double s = 0.0;
         if (!dmask[n])
@@ -588,6 +683,7 @@ int or_lu_factor(int n, double *A, int32_t *piv)
         if (A[(long)p * n + k] == 0.0) return -1;
         if (p != k)
             for (int j = 0; j < n; j++) { double t = A[(long)k * n + j]; A[(long)k * n + j] = A[(long)p * n + j]; A[(long)p * n + j] = t; }
+#pragma omp parallel for schedule(static) if (n - k > 64)
         for (int i = k + 1; i < n; i++) {
             A[(long)i * n + k] /= A[(long)k * n + k];
             double l = A[(long)i * n + k];
@@ -627,6 +723,9 @@ typedef struct {
     long *diagpos;
     long *order;    /* position -> cell */
     long *where;    /* cell -> position */
+    long nblk;      /* block-Jacobi factors: independent blocks (0 otherwise) */
+    long *blkptr;   /* positions of block b: blkpos[blkptr[b] .. blkptr[b+1]), ascending */
+    long *blkpos;
 } og_ilu;
 
 void *or_ilu0_create(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
@@ -688,6 +787,7 @@ void or_ilu0_free(void *h)
     og_ilu *M = (og_ilu *)h;
     if (!M) return;
     free(M->rowptr); free(M->col); free(M->val); free(M->diagpos); free(M->order); free(M->where);
+    free(M->blkptr); free(M->blkpos);
     free(M);
 }
 
@@ -701,12 +801,34 @@ void or_ilu0_export(void *h, int64_t *rowptr, int64_t *col, double *val)
     for (long q = 0; q < M->rowptr[M->n]; q++) { col[q] = M->col[q]; val[q] = M->val[q]; }
 }
 
-/* x = (L U)^{-1} z, in cell order. */
+/* x = (L U)^{-1} z, in cell order.  A block-Jacobi factor has no coupling
+ * between its blocks, so each block's triangular solves run on their own
+ * (same operations per row as the whole-matrix sweep). */
 void or_ilu0_apply(void *h, const double *z, double *x)
 {
     og_ilu *M = (og_ilu *)h;
     long N = M->n;
     double *y = (double *)malloc(sizeof(double) * N);
+    if (M->nblk > 0) {
+#pragma omp parallel for schedule(static)
+        for (long b = 0; b < M->nblk; b++) {
+            for (long u = M->blkptr[b]; u < M->blkptr[b + 1]; u++) {
+                long t = M->blkpos[u];
+                double s = z[M->order[t]];
+                for (long q = M->rowptr[t]; q < M->diagpos[t]; q++) s -= M->val[q] * y[M->col[q]];
+                y[t] = s;
+            }
+            for (long u = M->blkptr[b + 1] - 1; u >= M->blkptr[b]; u--) {
+                long t = M->blkpos[u];
+                double s = y[t];
+                for (long q = M->diagpos[t] + 1; q < M->rowptr[t + 1]; q++) s -= M->val[q] * y[M->col[q]];
+                y[t] = s / M->val[M->diagpos[t]];
+            }
+        }
+        for (long t = 0; t < N; t++) x[M->order[t]] = y[t];
+        free(y);
+        return;
+    }
     for (long t = 0; t < N; t++) {
         double s = z[M->order[t]];
         for (long q = M->rowptr[t]; q < M->diagpos[t]; q++) s -= M->val[q] * y[M->col[q]];
@@ -753,10 +875,29 @@ void *or_ilu0_block_create_shifted(const og_grid *g, const double *Wx, const dou
                 W[2 * N + n] = same_block(k, g->nz, bz, oz) ? Wz[n] : 0.0;
                 order[n] = n;
             }
-    void *h = or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
+    og_ilu *M = (og_ilu *)or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
     free(W);
     free(order);
-    return h;
+    /* block lists (natural order = positions) */
+    int nb[3] = {(g->nx + bx - 1) / bx, (g->ny + by - 1) / by, (g->nz + bz - 1) / bz};
+    M->nblk = (long)nb[0] * nb[1] * nb[2];
+    M->blkptr = (long *)calloc(M->nblk + 1, sizeof(long));
+    M->blkpos = (long *)malloc(sizeof(long) * N);
+    long *id = (long *)malloc(sizeof(long) * N);
+    for (int k = 0; k < g->nz; k++)
+        for (int j = 0; j < g->ny; j++)
+            for (int i = 0; i < g->nx; i++) {
+                long n = cell_index(g, i, j, k);
+                id[n] = ((i + ox) % g->nx) / bx + (long)nb[0] * (((j + oy) % g->ny) / by + (long)nb[1] * (((k + oz) % g->nz) / bz));
+                M->blkptr[id[n] + 1]++;
+            }
+    for (long b = 0; b < M->nblk; b++) M->blkptr[b + 1] += M->blkptr[b];
+    long *fill = (long *)malloc(sizeof(long) * M->nblk);
+    for (long b = 0; b < M->nblk; b++) fill[b] = M->blkptr[b];
+    for (long n = 0; n < N; n++) M->blkpos[fill[id[n]]++] = n;
+    free(fill);
+    free(id);
+    return M;
 }
 
 void *or_ilu0_block_create(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
@@ -786,6 +927,7 @@ void or_redblack_order(const og_grid *g, int64_t *order)
  * With a second smoother `ilu_alt` (nullable) the Richardson steps of each
  * smoothing stage take M = ilu, ilu_alt, ilu, ... (the first step of the
  * stage takes ilu).
+ * Stops when ||r|| <= rtol ||r0|| or ||r|| <= atol (atol = 0: relative only).
  * Returns the number of iterations (>= 0), or -1 if maxit was reached;
  * hist (length maxit+1, nullable) receives ||r||/||r0|| per iteration.
  * Pinned: MSFV zero block residual / MSFE Galerkin orthogonality after the
@@ -794,7 +936,7 @@ void or_redblack_order(const og_grid *g, int64_t *order)
 int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const double *Wz,
                   const double *diag, const uint8_t *dmask, const double *P, int restriction,
                   const double *LU, const int32_t *piv, void *ilu, void *ilu_alt,
-                  int n_pre, int n_post, double rtol, int maxit,
+                  int n_pre, int n_post, double rtol, double atol, int maxit,
                   const double *r0, double *dsol, double *hist)
 {
     long N = ncells(g);
@@ -811,22 +953,27 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
     for (;; it++) {
         or_matvec(g, Wx, Wy, Wz, diag, dsol, t);
         double nr = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : nr)
         for (long n = 0; n < N; n++) { r[n] = r0[n] - t[n]; nr += r[n] * r[n]; }
         nr = sqrt(nr);
         double rel = nr0 > 0 ? nr / nr0 : 0.0;
         if (hist && it <= maxit) hist[it] = rel;
-        if (rel <= rtol || nr0 == 0.0) { result = it; break; }
+        if (rel <= rtol || nr <= atol || nr0 == 0.0) { result = it; break; }
         if (it >= maxit || !isfinite(rel)) break;
         /* optional pre-smoothing */
         if (n_pre > 0) {
+            #pragma omp parallel for schedule(static)
             for (long n = 0; n < N; n++) e[n] = 0.0;
             for (int s = 0; s < n_pre; s++) {
                 or_matvec(g, Wx, Wy, Wz, diag, e, t);
+                #pragma omp parallel for schedule(static)
                 for (long n = 0; n < N; n++) t[n] = r[n] - t[n];
                 or_ilu0_apply((s & 1) && ilu_alt ? ilu_alt : ilu, t, x);
+                #pragma omp parallel for schedule(static)
                 for (long n = 0; n < N; n++) e[n] += x[n];
             }
             or_matvec(g, Wx, Wy, Wz, diag, e, t);
+            #pragma omp parallel for schedule(static)
             for (long n = 0; n < N; n++) { dsol[n] += e[n]; r[n] -= t[n]; }
         }
         /* multiscale stage, Eq. (15) */
@@ -834,15 +981,20 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
         or_lu_solve(Nc, LU, piv, rc);
         or_prolong(g, dmask, P, rc, e);
         or_matvec(g, Wx, Wy, Wz, diag, e, t);
+        #pragma omp parallel for schedule(static)
         for (long n = 0; n < N; n++) { dsol[n] += e[n]; r[n] -= t[n]; }
         /* post-smoothing on r1 = r - A d1 */
+        #pragma omp parallel for schedule(static)
         for (long n = 0; n < N; n++) e[n] = 0.0;
         for (int s = 0; s < n_post; s++) {
             or_matvec(g, Wx, Wy, Wz, diag, e, t);
+            #pragma omp parallel for schedule(static)
             for (long n = 0; n < N; n++) t[n] = r[n] - t[n];
             or_ilu0_apply((s & 1) && ilu_alt ? ilu_alt : ilu, t, x);
+            #pragma omp parallel for schedule(static)
             for (long n = 0; n < N; n++) e[n] += x[n];
         }
+        #pragma omp parallel for schedule(static)
         for (long n = 0; n < N; n++) dsol[n] += e[n];
     }
     free(r); free(t); free(e); free(x); free(rc);
@@ -866,7 +1018,7 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
 int or_newton_step(const og_grid *g, const og_fluid *f,
                    const double *Tx, const double *Ty, const double *Tz,
                    const double *phi, const double *q, const uint8_t *dmask, const double *P,
-                   int restriction, int n_pre, int n_post, double lin_rtol, int lin_maxit,
+                   int restriction, int n_pre, int n_post, double lin_rtol, double lin_atol, int lin_maxit,
                    double newton_tol, int newton_maxit, int smoother, int bx, int by, int bz,
                    const double *pn, double *p, double *stats)
 {
@@ -894,7 +1046,7 @@ int or_newton_step(const og_grid *g, const og_fluid *f,
                                                                  bx / 2, by / 2, bz / 2)
                                   : NULL;
         int its = or_cams_solve(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac, piv, ilu, alt,
-                                n_pre, n_post, lin_rtol, lin_maxit, r, d, NULL);
+                                n_pre, n_post, lin_rtol, lin_atol, lin_maxit, r, d, NULL);
         or_ilu0_free(ilu);
         or_ilu0_free(alt);
         if (its < 0) { rc = -2; lit += lin_maxit; break; }

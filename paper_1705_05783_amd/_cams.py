@@ -57,18 +57,19 @@ class cams_options(ctypes.Structure):
     _fields_ = [("restriction", ctypes.c_int32), ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("smoother", ctypes.c_int32),
                 ("lin_rtol", ctypes.c_double), ("lin_maxit", ctypes.c_int32),
-                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32)]
+                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
+                ("lin_atol", ctypes.c_double)]
 
 
 class cams_stats(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("lin_iters_total", ctypes.c_int32),
-                ("lin_iters_last", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lin_iters_last", ctypes.c_int32), ("fallback_blocks", ctypes.c_int32),
                 ("relres_last", ctypes.c_double), ("eps_norm_last", ctypes.c_double),
                 ("t_assemble_ms", ctypes.c_double), ("t_basis_ms", ctypes.c_double),
                 ("t_coarse_ms", ctypes.c_double), ("t_iterate_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 # (name, restype, argtypes) for every entry point declared in include/cams.h
@@ -86,6 +87,9 @@ _SIGS = [
     ("cams_coarse_op", _I, [_VP]),
     ("cams_iterate", _I, [_VP, _VP, ctypes.POINTER(cams_stats)]),
     ("cams_newton_step", _I, [_VP, _VP, _VP, ctypes.POINTER(cams_stats)]),
+    ("cams_conservative_sweep", _I, [_VP, _VP, _VP, _VP]),
+    ("cams_newton_history", _I, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(cams_stats)]),
     ("cams_smooth_apply", _I, [_VP, _VP, _VP]),
     ("cams_array_bytes", ctypes.c_size_t, [_VP, _I]),
     ("cams_export", _I, [_VP, _I, _VP, ctypes.c_size_t]),
@@ -104,6 +108,7 @@ _SIGS = [
     ("cams_learned_scratch_bytes", ctypes.c_size_t, [_VP]),
     ("cams_set_learned", _I, [_VP, _VP, _VP, ctypes.c_size_t, ctypes.c_double]),
     ("cams_basis_stats", _I, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    ("cams_basis_block_ratios", _I, [_VP, _VP, ctypes.c_int32]),
     ("cams_profile", _I, [_VP, _I]),
     ("cams_profile_read", _I, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_double)]),
@@ -166,45 +171,7 @@ def _fwd(name):
     return f
 
 
-cams_create = _fwd("cams_create")
-cams_workspace_bytes = _fwd("cams_workspace_bytes")
-cams_set_workspace = _fwd("cams_set_workspace")
-cams_set_rock = _fwd("cams_set_rock")
-cams_set_wells = _fwd("cams_set_wells")
-cams_assemble = _fwd("cams_assemble")
-cams_build_basis = _fwd("cams_build_basis")
-cams_coarse_op = _fwd("cams_coarse_op")
-cams_iterate = _fwd("cams_iterate")
-cams_newton_step = _fwd("cams_newton_step")
-cams_smooth_apply = _fwd("cams_smooth_apply")
-cams_array_bytes = _fwd("cams_array_bytes")
-cams_export = _fwd("cams_export")
-cams_num_coarse = _fwd("cams_num_coarse")
-cams_debug_gemm_sub = _fwd("cams_debug_gemm_sub")
-cams_cnn_num_params = _fwd("cams_cnn_num_params")
-cams_cnn_workspace_bytes = _fwd("cams_cnn_workspace_bytes")
-cams_cnn_forward = _fwd("cams_cnn_forward")
-cams_cnn_loss_grad = _fwd("cams_cnn_loss_grad")
-cams_cnn_adam = _fwd("cams_cnn_adam")
-cams_cnn_num_blocks = _fwd("cams_cnn_num_blocks")
-cams_cnn_patches = _fwd("cams_cnn_patches")
-cams_learned_scratch_bytes = _fwd("cams_learned_scratch_bytes")
-cams_set_learned = _fwd("cams_set_learned")
-cams_basis_stats = _fwd("cams_basis_stats")
-cams_profile = _fwd("cams_profile")
-cams_profile_read = _fwd("cams_profile_read")
-cams_destroy = _fwd("cams_destroy")
-cams_status_string = _fwd("cams_status_string")
-cams_last_error = _fwd("cams_last_error")
-cams_batch_create = _fwd("cams_batch_create")
-cams_batch_workspace_bytes = _fwd("cams_batch_workspace_bytes")
-cams_batch_set_workspace = _fwd("cams_batch_set_workspace")
-cams_batch_newton_iteration = _fwd("cams_batch_newton_iteration")
-cams_batch_tuning = _fwd("cams_batch_tuning")
-cams_batch_last_error = _fwd("cams_batch_last_error")
-cams_batch_destroy = _fwd("cams_batch_destroy")
-cams_invalidate_basis = _fwd("cams_invalidate_basis")
-cams_coarse_planes = _fwd("cams_coarse_planes")
-cams_debug_coarse_solve = _fwd("cams_debug_coarse_solve")
-cams_cnn_bf16_workspace_bytes = _fwd("cams_cnn_bf16_workspace_bytes")
-cams_cnn_forward_bf16 = _fwd("cams_cnn_forward_bf16")
+# one forwarder per entry point of include/cams.h, e.g. cams_iterate(...)
+for _name in EXPORTED:
+    globals()[_name] = _fwd(_name)
+del _name

@@ -194,7 +194,8 @@ static void build_basis_learned(cams_ctx *c)
     cnn_forward_bf16(c->stream, c->learned_params, feat, c->nfull, ws, phi);
     cnn_scatter(c, full, c->nfull, phi);
     cnn_block_residual(c, full, c->nfull, ratio);
-    std::vector<double> r(nf);
+    std::vector<double> &r = c->block_ratio;
+    r.assign(nf, 0.0);
     CAMS_HIP(hipMemcpyAsync(r.data(), ratio, nf * 8, hipMemcpyDeviceToHost, c->stream));
     CAMS_HIP(hipStreamSynchronize(c->stream));
     std::vector<Region> host_full(c->regions.begin() + c->regoff[3], c->regions.begin() + c->regoff[3] + c->nfull);
@@ -268,6 +269,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
         return CAMS_E_ARG;
     if (O.precision != CAMS_FP64 && O.smoother == CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
     if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
+    if (!(O.lin_atol >= 0) || !isfinite(O.lin_atol)) return CAMS_E_ARG;
     const int nb[3] = {num_blocks(n[0], r[0]), num_blocks(n[1], r[1]), num_blocks(n[2], r[2])};
     const double Nc = (double)nb[0] * nb[1] * nb[2];
     if (Nc > 32768) return CAMS_E_ARG;  // dense coarse operator limit
@@ -540,6 +542,10 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
         CAMS_HIP(hipMemcpyAsync(a.dmask, zero.data(), (size_t)N, hipMemcpyHostToDevice, c->stream));
         std::vector<int32_t> zctl((size_t)c->g.Nc + 64, 0);
         CAMS_HIP(hipMemcpyAsync(a.ictl, zctl.data(), zctl.size() * 4, hipMemcpyHostToDevice, c->stream));
+        // absolute linear tolerance, squared, for the device stopping test
+        std::vector<double> zscal(64, 0.0);
+        zscal[S_ATOL2] = c->opt.lin_atol * c->opt.lin_atol;
+        CAMS_HIP(hipMemcpyAsync(a.scal, zscal.data(), zscal.size() * 8, hipMemcpyHostToDevice, c->stream));
         clear_status(c);
         CAMS_HIP(hipStreamSynchronize(c->stream));
     } catch (const HipError &e) {
@@ -570,7 +576,7 @@ cams_status cams_set_rock(cams_ctx *c, const double *perm_dev, const double *phi
         CAMS_HIP(hipGetLastError());
         int32_t flags = 0;
         sync_status(c, &flags);
-        if (flags & F_BAD_INPUT) return fail(c, CAMS_E_BREAKDOWN, "permeability must be > 0, porosity in (0,1]");
+        if (flags & F_BAD_INPUT) return fail(c, CAMS_E_ARG, "permeability must be > 0, porosity in (0,1]");
     } catch (const HipError &e) {
         return fail(c, CAMS_E_DEVICE, std::string("set_rock: ") + hipGetErrorString(e.code));
     }
@@ -684,6 +690,7 @@ cams_status cams_build_basis(cams_ctx *c)
     try {
         clear_status(c);
         c->learned_blocks = c->fallback_blocks = 0;
+        c->block_ratio.clear();
         if (c->learned_params && c->nfull > 0) {
             build_basis_learned(c);
             if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
@@ -823,8 +830,13 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
         launch_iter_reset(c);
         int launched = 0, ahead = 4;
         double prev_nr = -1.0;
-        // the red-black smoother kernels have no stop flag: check every iteration
-        const bool sync_each = O.smoother == CAMS_SMOOTH_RB_ILU0;
+        // stagnation: the residual norm has not fallen below kStagDrop times
+        // its best value for kStagWindow iterations
+        double best_nr = -1.0;
+        int it_best = 0;
+        // the red-black smoother kernels have no stop flag: check every
+        // iteration; so does a norm history (one entry per iteration)
+        const bool sync_each = O.smoother == CAMS_SMOOTH_RB_ILU0 || c->hist;
         for (;;) {
             const int batch = sync_each ? 1 : ahead;
             for (int q = 0; q < batch && launched <= O.lin_maxit; ++q) enqueue_iteration(c, launched++);
@@ -837,6 +849,23 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
             nr0 = sqrt(c->host[20]);
             nr = sqrt(c->host[21]);
             it = ctl[0];
+            if (c->hist) {
+                // the last residual kernel wrote the accumulated update to
+                // dp[it & 1] (or dp[(it + 1) & 1] when it stopped there):
+                // nonlinear error at p + that update
+                cams_history &h = *c->hist;
+                const double *dpl = a.dp[ctl[1] ? ((it + 1) & 1) : (it & 1)];
+                launch_eps_at(c, h.p, dpl, h.pn, a.scal + S_EPSH);
+                CAMS_HIP(hipMemcpyAsync(c->host + 24, a.scal + S_EPSH, sizeof(double), hipMemcpyDeviceToHost,
+                                        c->stream));
+                CAMS_HIP(hipStreamSynchronize(c->stream));
+                if (h.count < h.cap) {
+                    h.res[h.count] = nr;
+                    h.err[h.count] = sqrt(c->host[24]);
+                    h.newton[h.count] = h.nu;
+                }
+                ++h.count;
+            }
             if (ctl[1]) {
                 outcome = ctl[2];
                 break;
@@ -845,10 +874,21 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
                 outcome = 1;
                 break;
             }
+            if (best_nr < 0.0 || nr < kStagDrop * best_nr) {
+                best_nr = nr;
+                it_best = it;
+            } else if (it - it_best >= kStagWindow) {
+                // Nothing is in flight (the stream was synchronised): the
+                // last residual kernel, of iteration it - 1, wrote dp[it & 1];
+                // report that iterate, as at the iteration limit.
+                it -= 1;
+                outcome = 3;
+                break;
+            }
             // enqueue about as many iterations as the observed rate needs
             if (prev_nr > 0.0 && nr < prev_nr && nr0 > 0.0) {
                 const double rate = pow(nr / prev_nr, 1.0 / std::max(1, batch));
-                const double need = log(O.lin_rtol * nr0 / nr) / log(rate);
+                const double need = log(std::max(O.lin_rtol * nr0, O.lin_atol) / nr) / log(rate);
                 ahead = (int)std::min(32.0, std::max(2.0, ceil(need)));
             }
             prev_nr = nr;
@@ -867,6 +907,7 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
         stats->relres_last = c->last.relres_last;
     }
     if (outcome == 1) return fail(c, CAMS_E_NOT_CONVERGED, "linear iteration limit reached");
+    if (outcome == 3) return fail(c, CAMS_E_NOT_CONVERGED, "linear iterations stagnated");
     if (outcome == 2) return fail(c, CAMS_E_BREAKDOWN, "non-finite residual norm");
     return CAMS_OK;
 }
@@ -890,6 +931,7 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
             CAMS_HIP(hipEventSynchronize(c->ev[1]));
             st.t_basis_ms = elapsed_ms(c, 0, 1);
         }
+        st.fallback_blocks = c->fallback_blocks;
         for (int nit = 0;; ++nit) {
             double en = 0.0;
             CAMS_HIP(hipEventRecord(c->ev[2], c->stream));
@@ -904,6 +946,7 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
             if (nit >= c->opt.newton_maxit) { s = fail(c, CAMS_E_NOT_CONVERGED, "Newton iteration limit"); break; }
             s = cams_coarse_op(c);
             if (s != CAMS_OK) break;
+            if (c->hist) c->hist->nu = nit;
             CAMS_HIP(hipEventRecord(c->ev[4], c->stream));
             cams_stats ls;
             memset(&ls, 0, sizeof(ls));
@@ -923,6 +966,73 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
     }
     c->last = st;
     if (stats) *stats = st;
+    return s;
+}
+
+cams_status cams_conservative_sweep(cams_ctx *c, const double *pn_dev, double *p_dev, double *flux_dev)
+{
+    if (!c) return CAMS_E_ARG;
+    if (!pn_dev || !p_dev || !flux_dev) return fail(c, CAMS_E_ARG, "null pressure or flux array");
+    if (!c->has_rock) return fail(c, CAMS_E_STATE, "conservative_sweep before set_rock");
+    if (c->blocktri)
+        return fail(c, CAMS_E_ARG, "conservative_sweep needs the dense coarse inverse (at most 4096 coarse nodes)");
+    if (!c->has_basis) {
+        const cams_status s = cams_build_basis(c);
+        if (s != CAMS_OK) return s;
+    }
+    const int32_t restriction = c->opt.restriction;
+    try {
+        clear_status(c);
+        launch_iter_reset(c);                 // clears the stop flag the restriction tests
+        enqueue_assemble(c, p_dev, pn_dev);
+        // the MSFV coarse operator R^FV A P_hat and its inverse (LU with partial pivoting)
+        c->opt.restriction = CAMS_R_FV;
+        launch_coarse_operator(c);
+        launch_coarse_factor(c);
+        // one multiscale stage on r0: d = P_hat (R^FV A P_hat)^-1 R^FV r0
+        launch_restrict(c, c->a.r0);
+        launch_gemv(c, c->a.rc, c->a.xc, nullptr, 0);
+        c->opt.restriction = restriction;
+        launch_prolong(c, c->a.xc, c->a.d1, nullptr);
+        launch_face_flux(c, p_dev, c->a.d1, flux_dev);
+        launch_axpy(c, p_dev, c->a.d1, c->g.N);
+        CAMS_HIP(hipGetLastError());
+        int32_t flags = 0;
+        sync_status(c, &flags);
+        if (flags & F_SINGULAR_COARSE) {
+            c->has_coarse = c->has_system = false;
+            return fail(c, CAMS_E_BREAKDOWN, "singular MSFV coarse operator");
+        }
+    } catch (const HipError &e) {
+        c->opt.restriction = restriction;
+        c->has_coarse = c->has_system = false;
+        return fail(c, CAMS_E_DEVICE, std::string("conservative_sweep: ") + hipGetErrorString(e.code));
+    }
+    // the coarse factor now holds the MSFV inverse, and p has moved
+    c->has_coarse = c->has_system = false;
+    return CAMS_OK;
+}
+
+cams_status cams_newton_history(cams_ctx *c, const double *pn_dev, double *p_dev, double *res_host,
+                                double *err_host, int32_t *newton_host, int32_t cap, int32_t *count,
+                                cams_stats *stats)
+{
+    if (!c) return CAMS_E_ARG;
+    if (cap < 0 || !count || (cap > 0 && (!res_host || !err_host || !newton_host)))
+        return fail(c, CAMS_E_ARG, "history buffers");
+    cams_history h;
+    h.res = res_host;
+    h.err = err_host;
+    h.newton = newton_host;
+    h.cap = cap;
+    h.count = 0;
+    h.nu = 0;
+    h.p = p_dev;
+    h.pn = pn_dev;
+    c->hist = &h;
+    const cams_status s = cams_newton_step(c, pn_dev, p_dev, stats);
+    c->hist = nullptr;
+    *count = h.count;
     return s;
 }
 
@@ -1071,6 +1181,14 @@ cams_status cams_set_learned(cams_ctx *c, const float *params, void *scratch, si
     c->learned_scratch_bytes = bytes;
     c->fallback_tol = fallback_tol;
     c->has_basis = c->has_coarse = false;
+    return CAMS_OK;
+}
+
+cams_status cams_basis_block_ratios(const cams_ctx *c, double *ratio_host, int32_t n)
+{
+    if (!c || !ratio_host || n < 0) return CAMS_E_ARG;
+    if ((size_t)n > c->block_ratio.size()) return CAMS_E_STATE;
+    memcpy(ratio_host, c->block_ratio.data(), (size_t)n * sizeof(double));
     return CAMS_OK;
 }
 

@@ -14,6 +14,8 @@ namespace cams {
 constexpr int kMaxRatio = 8;      // largest coarsening ratio the LDS local solves support
 constexpr int kBlock = 256;       // threads per workgroup of the fine-grid kernels
 constexpr int kBlockTriMin = 4096; // MSFE coarse grids above this many nodes use block-tridiagonal elimination
+constexpr int kStagWindow = 100;   // C-AMS iterations without a kStagDrop reduction of ||r|| = stagnation
+constexpr double kStagDrop = 0.9;
 
 // Grid descriptor passed by value to kernels.  Per-axis tables live in the
 // workspace: vertex coordinates (nb entries), "is vertex coordinate" flags
@@ -134,12 +136,21 @@ struct BatchResult {
 enum { C_IT = 0, C_DONE = 1, C_OUTCOME = 2, C_ARRIVE = 3, C_NODE = 4 };
 
 // Scalar slots in Arrays::scal.
-enum { S_EPS2 = 0, S_R0N2 = 1, S_RN2 = 2 };
+enum { S_EPS2 = 0, S_R0N2 = 1, S_RN2 = 2, S_ATOL2 = 3, S_EPSH = 4 };
 
 // Device status flags (bitwise OR).
 enum { F_BAD_PIVOT = 1, F_BAD_INPUT = 2, F_SINGULAR_COARSE = 4 };
 
 }  // namespace cams
+
+// Norm histories of cams_newton_history: one entry per evaluated C-AMS
+// residual (Newton index, ||r||_2, ||eps||_2 at the current iterate).
+struct cams_history {
+    double *res, *err;
+    int32_t *newton;
+    int cap, count, nu;
+    const double *p, *pn;   // Newton iterate and old-time pressure of the running solve
+};
 
 struct cams_ctx {
     cams_grid grid;
@@ -161,6 +172,7 @@ struct cams_ctx {
     double fallback_tol;
     int learned_blocks, fallback_blocks;
     std::vector<cams::Region> fallback_list;
+    std::vector<double> block_ratio;   // local-equation ratio of each full block in the last learned build
     size_t need;
     char *ws;
     size_t ws_bytes;
@@ -178,6 +190,7 @@ struct cams_ctx {
     hipStream_t side;
     hipEvent_t fork_ev, join_ev;
     cams_stats last;
+    cams_history *hist;     // non-null while cams_newton_history runs
     std::string err;
     // host copies of the per-axis tables and dual regions (uploaded by
     // cams_set_workspace) and the workspace offsets
@@ -205,6 +218,15 @@ void launch_transmissibility(cams_ctx *c, const double *perm);
 void launch_check_rock(cams_ctx *c, const double *perm, const double *phi);
 void launch_assemble(cams_ctx *c, const double *p, const double *pn);
 void launch_reduce(cams_ctx *c, const double *partial, int n, double *out);
+// ||eps||^2 (Eq. (16)) at x = p + dp (dp nullable) into *out, without
+// touching the assembled system; partials in Arrays::partial.
+void launch_eps_at(cams_ctx *c, const double *p, const double *dp, const double *pn, double *out);
+// Two-point mass fluxes (3N, on the lower cell of each face) of the system
+// assembled at p, at the pressure p + d.
+void launch_face_flux(cams_ctx *c, const double *p, const double *d, double *flux);
+// Zero the coarse operator once per workspace (entries outside the 27-point
+// pattern stay zero afterwards).
+void launch_zero_coarse(cams_ctx *c);
 void launch_impose_wells(cams_ctx *c, double *p);
 void launch_stencil_sub(cams_ctx *c, const double *b, const double *x, double *out, const int32_t *done);
 void launch_prolong(cams_ctx *c, const double *xc, double *out, const int32_t *done);

@@ -204,7 +204,7 @@ __device__ __forceinline__ void stop_test(const double *__restrict__ partial, in
     int outcome = -1;
     if (!(s < 1e300))                          // NaN or Inf
         outcome = 2;
-    else if (s <= rtol2 * r0n2 || r0n2 == 0.0)
+    else if (s <= rtol2 * r0n2 || s <= scal[S_ATOL2] || r0n2 == 0.0)
         outcome = 0;
     else if (it >= maxit)
         outcome = 1;

@@ -312,6 +312,11 @@ __global__ __launch_bounds__(CT) void k_cnn_scatter(GridDev g, const float *__re
 
 // Local-equation check of a predicted interior: ||(T Phi)_I|| / ||T_IF Phi_F||
 // over the 8 basis functions (T the incompressible two-point operator).
+// The basis is stored per cell relative to the cell's lower bracketing
+// vertex: interior cells and the lower vertex planes share the block's lower
+// vertex, but on an upper vertex plane the lower vertex is the block's upper
+// one, so there the block's node s is slot s - bit if s has that axis' bit
+// and otherwise a node whose function vanishes on the plane.
 __global__ __launch_bounds__(CT) void k_block_residual(GridDev g, const double *__restrict__ T,
                                                         const double *__restrict__ P,
                                                         const Region *__restrict__ regs, double *__restrict__ ratio)
@@ -334,7 +339,13 @@ __global__ __launch_bounds__(CT) void k_block_residual(GridDev g, const double *
         const bool onb[6] = {x == 0, x == 6, y == 0, y == 6, z == 0, z == 6};
 #pragma unroll
         for (int f = 0; f < 6; ++f) {
-            const double pj = Ps[nbr[f]];
+            // f odd: the +x/+y/+z neighbour; on the block boundary it lies on an upper vertex plane
+            const int bit = 1 << (f >> 1);
+            const bool upper = (f & 1) && onb[f];
+            const bool vanish = upper && !(s & bit);
+            const int sj = upper && (s & bit) ? s - bit : s;
+            const double pv = P[(size_t)sj * g.N + nbr[f]];
+            const double pj = vanish ? 0.0 : pv;
             res += tf[f] * (pn - pj);
             if (onb[f]) bnd += tf[f] * pj;
         }

@@ -1180,6 +1180,15 @@ void gemm_sub(cams_ctx *c, double *C, int ldc, const double *A, int lda, const d
 
 }  // namespace
 
+void launch_zero_coarse(cams_ctx *c)
+{
+    const int n = c->g.Nc;
+    if (!c->ac_zeroed) {   // entries outside the 27-point pattern stay zero from now on
+        k_zero<<<cdiv((size_t)n * n, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, (size_t)n * n);
+        c->ac_zeroed = true;
+    }
+}
+
 void launch_coarse_operator(cams_ctx *c)
 {
     const int n = c->g.Nc;
@@ -1187,10 +1196,7 @@ void launch_coarse_operator(cams_ctx *c)
         k_coarse_row<<<n, kBlock, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.dmask, c->a.P, 0, c->a.Ac);
         return;
     }
-    if (!c->ac_zeroed) {   // entries outside the 27-point pattern stay zero from now on
-        k_zero<<<cdiv((size_t)n * n, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, (size_t)n * n);
-        c->ac_zeroed = true;
-    }
+    launch_zero_coarse(c);
     k_coarse_box<<<n, kOpThreads, 0, c->stream>>>(c->g, c->a.W, c->a.diag, c->a.dmask, c->a.P, c->a.boxp);
     k_coarse_nodes<<<cdiv((size_t)27 * n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.boxp, c->a.Ac);
 }

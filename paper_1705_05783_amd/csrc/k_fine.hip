@@ -109,6 +109,62 @@ __global__ __launch_bounds__(kBlock) void k_assemble(GridDev g, Fluid f, const d
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// Partial sums of eps^2 (Eq. (16)) at x = p + dp (dp nullable): the
+// residual F of k_assemble at another pressure, with nothing else written.
+__global__ __launch_bounds__(kBlock) void k_eps_at(GridDev g, Fluid f, const double *__restrict__ T,
+                                                    const double *__restrict__ phi, const double *__restrict__ q,
+                                                    const uint8_t *__restrict__ dm, const double *__restrict__ p,
+                                                    const double *__restrict__ dp, const double *__restrict__ pn,
+                                                    double *__restrict__ partial)
+{
+    __shared__ double sh[kBlock / 64];
+    int n = blockIdx.x * kBlock + threadIdx.x;
+    double e2 = 0.0;
+    if (n < g.N && !dm[n]) {
+        Cell c = cell_of(g, n);
+        const double *Tx = T, *Ty = T + g.N, *Tz = T + 2 * g.N;
+        auto x = [&](int m) { return dp ? p[m] + dp[m] : p[m]; };
+        const double xi = x(n);
+        const double rho = density(f, xi);
+        double flux = 0.0;
+        auto face = [&](int m, double t) {
+            const double xm = x(m);
+            flux += t * 0.5 * (rho + density(f, xm)) * (xi - xm);
+        };
+        if (c.i > 0) face(n - 1, Tx[n - 1]);
+        if (c.i + 1 < g.nx) face(n + 1, Tx[n]);
+        if (c.j > 0) face(n - g.nx, Ty[n - g.nx]);
+        if (c.j + 1 < g.ny) face(n + g.nx, Ty[n]);
+        if (c.k > 0) face(n - g.sxy, Tz[n - g.sxy]);
+        if (c.k + 1 < g.nz) face(n + g.sxy, Tz[n]);
+        const double rhon = density(f, pn[n]);
+        double F = phi[n] * g.dV * (rho - rhon) / f.dt + flux;
+        if (q) F -= rho * q[n] * g.dV;
+        const double e = F / (rho * g.dV);
+        e2 = e * e;
+    }
+    double s = block_sum<kBlock>(e2, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Two-point mass fluxes of the Newton system assembled at p, at the updated
+// pressure x = p + d: on the face between n and its +x/+y/+z neighbour m,
+// T (rho(p_n) + rho(p_m)) / 2 (x_n - x_m), positive from n to m, stored on n.
+__global__ __launch_bounds__(kBlock) void k_face_flux(GridDev g, Fluid f, const double *__restrict__ T,
+                                                       const double *__restrict__ p, const double *__restrict__ d,
+                                                       double *__restrict__ flux)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    Cell c = cell_of(g, n);
+    const double rho = density(f, p[n]);
+    const double xn = p[n] + d[n];
+    auto fl = [&](int m, double t) { return t * 0.5 * (rho + density(f, p[m])) * (xn - (p[m] + d[m])); };
+    flux[n] = c.i + 1 < g.nx ? fl(n + 1, T[n]) : 0.0;
+    flux[g.N + n] = c.j + 1 < g.ny ? fl(n + g.nx, T[g.N + n]) : 0.0;
+    flux[2 * (size_t)g.N + n] = c.k + 1 < g.nz ? fl(n + g.sxy, T[2 * (size_t)g.N + n]) : 0.0;
+}
+
 // Deterministic final sum of `n` partials by one workgroup.
 __global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ partial, int n, double *__restrict__ out)
 {
@@ -345,6 +401,19 @@ void launch_assemble(cams_ctx *c, const double *p, const double *pn)
 void launch_reduce(cams_ctx *c, const double *partial, int n, double *out)
 {
     k_reduce<<<1, kBlock, 0, c->stream>>>(partial, n, out);
+}
+
+void launch_face_flux(cams_ctx *c, const double *p, const double *d, double *flux)
+{
+    k_face_flux<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->fl, c->a.T, p, d, flux);
+}
+
+void launch_eps_at(cams_ctx *c, const double *p, const double *dp, const double *pn, double *out)
+{
+    k_eps_at<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->fl, c->a.T, c->a.phi,
+                                                            c->has_q ? c->a.q : nullptr, c->a.dmask, p, dp, pn,
+                                                            c->a.partial);
+    launch_reduce(c, c->a.partial, grid_blocks(c->g.N), out);
 }
 
 void launch_impose_wells(cams_ctx *c, double *p)

@@ -164,8 +164,13 @@ __device__ __forceinline__ void restrict_box(const GridDev &g, const uint8_t *__
                                              double *__restrict__ slots, int k, double *sh)
 {
     const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
-    const int x0 = g.ob[0][ka], y0 = g.ob[1][kb], z0 = g.ob[2][kc];
-    const int ex = g.ob[0][ka + 1] - x0, ey = g.ob[1][kb + 1] - y0, ez = g.ob[2][kc + 1] - z0;
+    // MSFE: the owner box from the tables; MSFV: the primal block [a r, min((a+1) r, n)) of
+    // node k, also when the context was set up for MSFE (the conservative sweep)
+    const int x0 = fe ? g.ob[0][ka] : ka * g.r[0], y0 = fe ? g.ob[1][kb] : kb * g.r[1];
+    const int z0 = fe ? g.ob[2][kc] : kc * g.r[2];
+    const int ex = (fe ? g.ob[0][ka + 1] : min(x0 + g.r[0], g.nx)) - x0;
+    const int ey = (fe ? g.ob[1][kb + 1] : min(y0 + g.r[1], g.ny)) - y0;
+    const int ez = (fe ? g.ob[2][kc + 1] : min(z0 + g.r[2], g.nz)) - z0;
     const int m = ex * ey * ez;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = threadIdx.x; t < m; t += kBlock) {
@@ -223,8 +228,13 @@ __device__ __forceinline__ void residual_restrict_box(const GridDev &g, const do
                                                       int fe, double *__restrict__ slots, int k, double *sh)
 {
     const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
-    const int x0 = g.ob[0][ka], y0 = g.ob[1][kb], z0 = g.ob[2][kc];
-    const int ex = g.ob[0][ka + 1] - x0, ey = g.ob[1][kb + 1] - y0, ez = g.ob[2][kc + 1] - z0;
+    // MSFE: the owner box from the tables; MSFV: the primal block [a r, min((a+1) r, n)) of
+    // node k, also when the context was set up for MSFE (the conservative sweep)
+    const int x0 = fe ? g.ob[0][ka] : ka * g.r[0], y0 = fe ? g.ob[1][kb] : kb * g.r[1];
+    const int z0 = fe ? g.ob[2][kc] : kc * g.r[2];
+    const int ex = (fe ? g.ob[0][ka + 1] : min(x0 + g.r[0], g.nx)) - x0;
+    const int ey = (fe ? g.ob[1][kb + 1] : min(y0 + g.r[1], g.ny)) - y0;
+    const int ez = (fe ? g.ob[2][kc + 1] : min(z0 + g.r[2], g.nz)) - z0;
     const int m = ex * ey * ez;
     double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double e2 = 0.0;

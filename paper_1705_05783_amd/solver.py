@@ -37,7 +37,8 @@ class Solver:
                            overrides.get("lin_rtol", problem.lin_rtol),
                            overrides.get("lin_maxit", problem.lin_maxit),
                            overrides.get("newton_tol", problem.newton_tol),
-                           overrides.get("newton_maxit", problem.newton_maxit))
+                           overrides.get("newton_maxit", problem.newton_maxit),
+                           overrides.get("lin_atol", getattr(problem, "lin_atol", 0.0)))
         self.options = o
         h = ctypes.c_void_p()
         C.check(C.cams_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(o),
@@ -109,6 +110,33 @@ class Solver:
         d["status"] = status
         return d
 
+    def conservative_sweep(self, pn: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+        """One MSFV stage at p (updated in place); returns the (3, N) two-point
+        mass fluxes of that linear system at the new pressure."""
+        flux = torch.empty((3, self.N), dtype=torch.float64, device=self.device)
+        C.check(C.cams_conservative_sweep(self.ctx, _ptr(pn), _ptr(p), _ptr(flux)), self.ctx,
+                "cams_conservative_sweep")
+        return flux
+
+    def newton_history(self, pn: torch.Tensor, p: torch.Tensor, cap=20000, check=True):
+        """One time step with the norm history of every C-AMS iteration:
+        (stats dict, Newton index (n,), ||r||_2 (n,), ||eps||_2 (n,))."""
+        res = np.zeros(cap)
+        err = np.zeros(cap)
+        nwt = np.zeros(cap, dtype=np.int32)
+        cnt = ctypes.c_int32()
+        st = C.cams_stats()
+        status = C.cams_newton_history(self.ctx, _ptr(pn), _ptr(p), res.ctypes.data_as(ctypes.c_void_p),
+                                       err.ctypes.data_as(ctypes.c_void_p), nwt.ctypes.data_as(ctypes.c_void_p),
+                                       cap, ctypes.byref(cnt), ctypes.byref(st))
+        if check:
+            C.check(status, self.ctx, "cams_newton_history")
+        n = min(cnt.value, cap)
+        d = st.as_dict()
+        d["status"] = status
+        d["entries"] = cnt.value
+        return d, nwt[:n], res[:n], err[:n]
+
     def smooth_apply(self, z: torch.Tensor) -> torch.Tensor:
         x = torch.empty_like(z)
         C.check(C.cams_smooth_apply(self.ctx, _ptr(z), _ptr(x)), self.ctx, "cams_smooth_apply")
@@ -146,6 +174,15 @@ class Solver:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         C.check(C.cams_basis_stats(self.ctx, ctypes.byref(a), ctypes.byref(b)), self.ctx, "cams_basis_stats")
         return {"learned_blocks": a.value, "fallback_blocks": b.value}
+
+    def block_ratios(self) -> np.ndarray:
+        """Local-equation ratio of the network's prediction per full dual
+        block, from the last learned basis build (before fallback)."""
+        n = self.num_full_blocks()
+        out = np.zeros(n, dtype=np.float64)
+        C.check(C.cams_basis_block_ratios(self.ctx, out.ctypes.data_as(ctypes.c_void_p), n), self.ctx,
+                "cams_basis_block_ratios")
+        return out
 
     # ---- measurement
     def profile(self, kernel=C.CAMS_PROF_SMOOTH_STEP):

@@ -21,6 +21,7 @@ import numpy as np
 import torch
 
 from . import learned
+from .solver import Solver
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "weights", "cnn_basis_f32.npy")
@@ -35,6 +36,37 @@ def load_weights(path=WEIGHTS, device="cuda:0") -> torch.Tensor:
     return torch.tensor(arr, device=device)
 
 
+def load_fallback_tol(path=RECORD) -> float:
+    """The calibrated per-block fallback tolerance of the trained network
+    (see `calibrate`)."""
+    with open(path) as f:
+        rec = json.load(f)
+    return float(rec["fallback_tol"]["value"])
+
+
+def calibrate(params, count, seed0, quantile=0.99, log=None):
+    """Per-block local-equation ratios ||(T Phi)_I|| / ||T_IF Phi_F|| of the
+    network's interiors on `count` held-out realisations drawn like the
+    training set (seeds seed0 .. seed0 + count - 1, past the training and
+    validation seeds), with no fallback.  The fallback tolerance is their
+    `quantile` quantile: a block whose prediction is worse than the network
+    achieves on that share of in-distribution blocks is taken as outside
+    what it learned and re-solved exactly.  Returns (tolerance, summary)."""
+    ratios = []
+    for i in range(count):
+        s = Solver(learned.training_problem(i, seed0))
+        s.set_learned(params, fallback_tol=1e30)
+        s.build_basis()
+        ratios.append(s.block_ratios())
+        s.close()
+        if log:
+            log(f"calibration realisation {i + 1}/{count}: median ratio {np.median(ratios[-1]):.3e}")
+    r = np.concatenate(ratios)
+    q = np.quantile(r, [0.5, 0.9, quantile, 1.0])
+    return float(q[2]), {"blocks": int(r.size), "median": float(q[0]), "p90": float(q[1]),
+                         "quantile": quantile, "max": float(q[3])}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--count", type=int, default=200, help="training realisations (343 patches each)")
@@ -46,10 +78,26 @@ def main(argv=None):
     ap.add_argument("--time-limit", type=float, default=None, help="seconds of training")
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--record", default=RECORD)
+    ap.add_argument("--calibrate", type=int, default=0, metavar="COUNT",
+                    help="only calibrate the fallback tolerance of the stored network on COUNT held-out "
+                         "realisations and add it to the record")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
+
+    if a.calibrate:
+        with open(a.record) as f:
+            rec = json.load(f)
+        seed_cal = rec["seed0"] + rec["realisations"] + rec["holdout_realisations"]
+        tol, summary = calibrate(load_weights(a.out), a.calibrate, seed_cal, log=log)
+        rec["fallback_tol"] = {"value": tol, "seed0": seed_cal, "realisations": a.calibrate, **summary,
+                               "command": " ".join(["python -m paper_1705_05783_amd.train_basis"] +
+                                                   (argv or sys.argv[1:]))}
+        with open(a.record, "w") as f:
+            json.dump(rec, f, indent=1)
+        log(json.dumps(rec["fallback_tol"]))
+        return
 
     t0 = time.time()
     feat, tgt = learned.generate(a.count, seed0=a.seed0, log=log)

@@ -33,3 +33,108 @@ def solver_for(pb, **kw):
 
 def log(*args):
     print(*args, flush=True)
+
+
+def linear_residual_check(pb, T, p_before, pn, p_after, r0=None, d=None):
+    """(relres, bound): the relative linear residual ||r0 - A d|| / ||r0|| of
+    the update d = p_after - p_before with the oracle's own FP64 matrix A at
+    p_before, and the acceptance bound for a solve stopped at pb.lin_rtol.
+
+    r0 is the right-hand side the solver had (the GPU's exported Newton
+    residual; default: the oracle's); d, when given, is the update itself
+    (exact, where p_after - p_before is rounded to the pressure's ulps).  The GPU stops on ||r|| <= rtol ||r0||
+    computed in FP64 from its own matrix; the oracle recomputes r0 - A d in
+    another order with a matrix that agrees to a few ulps, so the two
+    residuals differ by at most about 16 u || |r0| + |A| |d| || (u = 2^-53),
+    and the bound is rtol (1 + 1e-6) + 16 u || |r0| + |A| |d| || / ||r0||."""
+    import oracle
+    W, diag, r0_or, _ = oracle.linear_system(pb, T, p_before, pn)
+    r0 = r0_or if r0 is None else np.asarray(r0, dtype=np.float64)
+    if d is None:
+        d = np.asarray(p_after, dtype=np.float64) - np.asarray(p_before, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    res = r0 - oracle.matvec(pb, W, diag, d)
+    n0 = np.linalg.norm(r0)
+    ad = np.abs(d)
+    absAd = 2.0 * diag * ad - oracle.matvec(pb, W, diag, ad)   # |A| |d| (off-diagonals are -W)
+    u = 2.0 ** -53
+    bound = pb.lin_rtol * (1.0 + 1e-6) + 16.0 * u * np.linalg.norm(np.abs(r0) + absAd) / n0
+    return float(np.linalg.norm(res) / n0), float(bound)
+
+
+def newton_residual_terms(pb, T, p, pn):
+    """Per cell, the sum of the magnitudes of the terms that make up the
+    Newton residual r = -F(p) of the mass-form Eq. (2): accumulation
+    phi dV (rho + rho^n) / dt, the six face fluxes T rho_f |p_i - p_j| and the
+    source |rho q| dV.  An FP64 evaluation of F (eight summed terms, each a
+    product of a few rounded factors and exp values within a few ulps) is
+    within about 16 u times this sum of the exact value, whatever the size
+    of F itself, so two evaluations differ by at most 32 u times it."""
+    nx, ny, nz = pb.nx, pb.ny, pb.nz
+    rho = pb.rho0 * np.exp(pb.c * (np.asarray(p) - pb.p0))
+    rhon = pb.rho0 * np.exp(pb.c * (np.asarray(pn) - pb.p0))
+    dV = pb.dx * pb.dy * pb.dz
+    terms = pb.phi * dV * (rho + rhon) / pb.dt
+    if pb.q is not None:
+        terms = terms + np.abs(rho * pb.q) * dV
+    P3, R3 = np.asarray(p).reshape(nz, ny, nx), rho.reshape(nz, ny, nx)
+    t3 = terms.reshape(nz, ny, nx).copy()
+    for axis, Ta in ((2, T[0]), (1, T[1]), (0, T[2])):
+        Ta = np.asarray(Ta).reshape(nz, ny, nx)
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, -1)
+        hi[axis] = slice(1, None)
+        lo, hi = tuple(lo), tuple(hi)
+        f = Ta[lo] * 0.5 * (R3[lo] + R3[hi]) * np.abs(P3[lo] - P3[hi])
+        t3[lo] += f
+        t3[hi] += f
+    out = t3.reshape(-1)
+    out[pb.dirichlet_mask().astype(bool)] = 0.0
+    return out
+
+
+def checked_newton_step(s, pb, T, pn_t, p_t, torch, check_linear=True):
+    """One time step through the C ABI's hot-path calls (the sequence
+    cams_newton_step runs: basis once, then assemble -> stop test ->
+    coarse operator -> C-AMS iterations), with the oracle checking every
+    Newton iteration: the GPU's Newton residual against the oracle's
+    (elementwise, within 32 u times the magnitude of the terms summed in F),
+    and the update against the oracle's FP64 matrix with the GPU's residual
+    as right-hand side (linear_residual_check).  Returns (Newton
+    iterations, C-AMS iterations, worst relres / bound ratio)."""
+    import oracle
+    from paper_1705_05783_amd import _cams as C
+    pn = to_np(pn_t)
+    if not getattr(s, "_basis_built", False):
+        s.build_basis()
+        s._basis_built = True
+    nit = lits = 0
+    worst = 0.0
+    u = 2.0 ** -53
+    while True:
+        e = s.assemble(p_t, pn_t)
+        if e <= pb.newton_tol:
+            break
+        assert nit < pb.newton_maxit, "Newton iteration limit"
+        s.coarse_op()
+        p_before = to_np(p_t)
+        r0_gpu = to_np(s.export(C.CAMS_ARR_R0)) if check_linear else None
+        # cams_iterate adds the update to the vector it is given: from zero it
+        # returns the update itself, which p_after - p_before would round away
+        # once the update is far below the pressure (late Newton iterations)
+        d_t = torch.zeros_like(p_t)
+        st = s.iterate(d_t)
+        p_t += d_t
+        nit += 1
+        lits += st["lin_iters_last"]
+        if check_linear:
+            _, _, r0_or, _ = oracle.linear_system(pb, T, p_before, pn)
+            gap = np.abs(r0_gpu - r0_or)
+            assert np.all(gap <= 32.0 * u * newton_residual_terms(pb, T, p_before, pn) + 1e-300), \
+                (pb.name, nit, float(gap.max()))
+            rel, bound = linear_residual_check(pb, T, p_before, pn, p_before + to_np(d_t), r0=r0_gpu,
+                                               d=to_np(d_t))
+            worst = max(worst, rel / bound)
+            assert rel <= bound, (pb.name, nit, rel, bound)
+    return nit, lits, worst

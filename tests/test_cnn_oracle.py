@@ -87,3 +87,38 @@ def test_adam_matches_torch():
         opt.step()
         p, m, v = cnn.adam_step(p, g, m, v, t, lr=1e-2)
     assert np.allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_loss_window_hand_worked():
+    """The loss compares the network output on the 7x7x7 interior cells of the
+    9x9x9 patch (patch positions 1..7 on each axis) with the targets, in the
+    same (z, y, x) order.  Hand-worked case: a network that passes input
+    channel 0 through every layer at the centre tap to output channel 0
+    (all other weights and biases 0) gives logits z_0 = x_0, z_1..7 = 0, so
+    phi = (e^x0, 1, ..., 1) / (e^x0 + 7).  With x_0 = ln 7 at patch cell
+    (z, y, x) = (7, 1, 1) and at (8, 8, 8) (a vertex plane, outside the
+    interior), 0 elsewhere, phi is uniform 1/8 except phi = (1/2, 1/14, ...)
+    at those two cells.  Targets: uniform 1/8, except interior index
+    (6, 0, 0) (= patch cell (7, 1, 1)) set to (1/2, 1/14, ...) and interior
+    index (0, 0, 0) set to the same vector.  Only interior (0, 0, 0) then
+    differs: (1/2 - 1/8)^2 + 7 (1/14 - 1/8)^2 = 9/56, so the loss is
+    9 / (56 * 8 * 343).  A window shifted by one cell, a transposed window
+    or a loss over all 9^3 cells gives another value."""
+    params = np.zeros(cnn.num_params())
+    o = 0
+    for li, (ci, co) in enumerate(cnn.LAYERS):
+        W = np.zeros((27, ci, co))
+        W[13, 0, 0] = 1.0          # centre tap, channel 0 -> channel 0
+        params[o:o + W.size] = W.ravel()
+        o += W.size + co            # biases stay 0
+    x = np.zeros((1, 3, 9, 9, 9))
+    x[0, 0, 7, 1, 1] = np.log(7.0)
+    x[0, 0, 8, 8, 8] = np.log(7.0)
+    hot = np.array([0.5] + [1.0 / 14.0] * 7)
+    target = np.full((1, 8, 7, 7, 7), 1.0 / 8.0)
+    target[0, :, 6, 0, 0] = hot
+    target[0, :, 0, 0, 0] = hot
+    phi, _ = cnn.forward(params, x)
+    assert np.allclose(phi[0, :, 7, 1, 1], hot, rtol=1e-14) and np.allclose(phi[0, :, 8, 8, 8], hot, rtol=1e-14)
+    loss, _ = cnn.loss_and_grad(params, x, target)
+    assert abs(loss - 9.0 / (56.0 * 8 * 343)) <= 1e-15

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import log, rel_err, require_gpu, to_np
+from tests.gpu_util import linear_residual_check, log, rel_err, require_gpu, to_np
 from workloads import small_problem
 from workloads.configs import FE, FP64, FV, MIXED_BF16, MIXED_FP32, SMOOTH_BLOCK, SMOOTH_BLOCK_ALT, batch_problems
 
@@ -169,10 +169,8 @@ def test_batch_full_size_256_instances(torch):
     for i, pb in enumerate(pbs):
         T = oracle.transmissibility(pb)
         p0 = _start(pb)
-        W, diag, r0, _ = oracle.linear_system(pb, T, p0, p0)
-        r = r0 - oracle.matvec(pb, W, diag, p[i] - p0)
-        rel = np.linalg.norm(r) / np.linalg.norm(r0)
-        assert rel <= 1e-8 * 1.01 + 1e-12, (pb.name, rel)
+        rel, bound = linear_residual_check(pb, T, p0, p0, p[i])
+        assert rel <= bound, (pb.name, rel, bound)
     order = np.argsort([pb.n for pb in pbs])
     for i in (order[0], order[len(order) // 2], order[-1]):
         pb = pbs[i]

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from oracle import cnn as ocnn
-from tests.gpu_util import log, rel_err, require_gpu, solver_for, to_np
+from tests.gpu_util import checked_newton_step, log, rel_err, require_gpu, solver_for, to_np
 from workloads import small_problem
 
 pytestmark = pytest.mark.gpu
@@ -227,3 +227,83 @@ def test_trained_network_gain(torch):
     assert err["trained"] < 0.5 * err["untrained"]
     assert iters["trained"] <= 1.1 * iters["exact"]
     assert iters["untrained"] > iters["trained"]
+
+
+def test_fallback_at_an_intermediate_tolerance(torch):
+    """The per-block guard where it acts on some blocks and not others.  With
+    the trained network and no fallback, the GPU's ratio of every full dual
+    block matches the oracle's recomputation from the exported basis.  Then,
+    with fallback_tol between two ratios near the median, exactly the blocks
+    above it are re-solved: their interiors equal the oracle's exact basis
+    (1e-12), the others keep the network's values bit for bit, and every
+    other cell is exact."""
+    from paper_1705_05783_amd import _cams as C
+    from paper_1705_05783_amd.train_basis import load_weights
+    pb = small_problem(64, 64, 32, 8, sigma=2.5, seed=23)
+    params = load_weights()
+    T = oracle.transmissibility(pb)
+    P_ref = oracle.basis_b4(pb, T)
+    starts = oracle.full_dual_blocks(pb)
+    s = solver_for(pb)
+    nb = s.num_full_blocks()
+    assert nb == len(starts) == 147
+    s.set_learned(params, fallback_tol=1e30)
+    s.build_basis()
+    P_net = to_np(s.export(C.CAMS_ARR_P)).reshape(8, -1)
+    r_gpu = s.block_ratios()
+    r_ref = oracle.basis_block_ratios(pb, T, P_net, starts)
+    log("ratios: min", r_ref.min(), "median", np.median(r_ref), "max", r_ref.max(),
+        "gpu vs oracle", rel_err(r_gpu, r_ref))
+    assert rel_err(r_gpu, r_ref) <= 1e-12
+    order = np.sort(r_ref)
+    k = nb // 2
+    tol = 0.5 * (order[k - 1] + order[k])
+    assert order[k] - order[k - 1] > 1e-9 * tol      # no block sits at the threshold
+    above = r_ref > tol
+    s.set_learned(params, fallback_tol=tol)
+    s.build_basis()
+    st = s.basis_stats()
+    log("fallback_tol", tol, st)
+    assert st["fallback_blocks"] == int(above.sum()) and st["learned_blocks"] == nb - int(above.sum())
+    P_fb = to_np(s.export(C.CAMS_ARR_P)).reshape(8, pb.nz, pb.ny, pb.nx)
+    Pn = P_net.reshape(8, pb.nz, pb.ny, pb.nx)
+    Pr = P_ref.reshape(8, pb.nz, pb.ny, pb.nx)
+    interior = np.zeros((pb.nz, pb.ny, pb.nx), dtype=bool)
+    for b, (x0, y0, z0) in enumerate(starts):
+        sl = (slice(None), slice(z0, z0 + 7), slice(y0, y0 + 7), slice(x0, x0 + 7))
+        interior[sl[1:]] = True
+        if above[b]:
+            assert np.max(np.abs(P_fb[sl] - Pr[sl])) <= 1e-12, b
+        else:
+            assert np.array_equal(P_fb[sl], Pn[sl]), b
+    assert np.max(np.abs(P_fb[:, ~interior] - Pr[:, ~interior])) <= 1e-12
+    # the stats of a Newton step report the same count
+    pn = torch.as_tensor(pb.initial_pressure(), device="cuda")
+    s.invalidate_basis()
+    st2 = s.newton_step(pn.clone(), pn.clone())
+    assert st2["fallback_blocks"] == int(above.sum())
+    s.close()
+
+
+def test_config5_learned_mixed_full_size(torch):
+    """The metric's learned+mixed configuration at full size: 128^3 (seed 5,
+    outside the network's training seeds), trained network for the full
+    dual-block interiors with the calibrated fallback tolerance, FP32 basis
+    storage and smoother, FP64 refinement.  One time step through the ABI's
+    hot-path calls: every linear solve meets 1e-8 on the oracle's own FP64
+    matrix, and the oracle's nonlinear error of the GPU pressure meets the
+    Newton tolerance."""
+    from paper_1705_05783_amd.train_basis import load_fallback_tol, load_weights
+    from workloads.configs import config5_eval
+    pb = config5_eval()
+    s = solver_for(pb)
+    s.set_learned(load_weights(), fallback_tol=load_fallback_tol())
+    T = oracle.transmissibility(pb)
+    pn_t = torch.as_tensor(pb.initial_pressure(), device="cuda")
+    p_t = pn_t.clone()
+    nit, lits, worst = checked_newton_step(s, pb, T, pn_t, p_t, torch)
+    _, e = oracle.nonlinear_residual(pb, T, to_np(p_t), to_np(pn_t))
+    log("128^3 learned+mixed: newton", nit, "cams", lits, "worst relres/bound", worst, "eps", e,
+        s.basis_stats())
+    assert nit >= 1 and e <= pb.newton_tol
+    s.close()

@@ -6,16 +6,19 @@ z-planes (exact zeros elsewhere), the GPU coarse operator matches it to
 1e-12, and the GPU coarse solve matches a LAPACK solve of the oracle's
 operator (relative error <= 1e-8, residual <= 1e-10).  At the full
 256x256x128 size (8.4M cells, 16384 coarse nodes, BF16 basis) one Newton
-iteration is checked through a property that holds at any size: the
-oracle recomputes r0 - A delta on its own FP64 matrix and finds
-||r|| <= lin_rtol ||r0|| (1% slack for the different summation order).
+workload runs all 5 time steps, checked through properties that hold at
+any size: after every Newton iteration the oracle recomputes r0 - A delta on
+its own FP64 matrix and finds ||r|| <= lin_rtol ||r0|| (up to the rounding
+bound of the two evaluations), and after every step the oracle's nonlinear
+error of the GPU pressure is <= the Newton tolerance.  A 32x32x16 channelised
+field with the same settings is compared with the oracle's own Newton.
 """
 
 import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import log, rel_err, require_gpu, solver_for, to_np
+from tests.gpu_util import checked_newton_step, linear_residual_check, log, rel_err, require_gpu, solver_for, to_np
 from workloads import small_problem
 from workloads.configs import config4
 
@@ -128,30 +131,59 @@ def test_blocktri_linear_solve_meets_tolerance(torch):
     st = s.newton_step(p.clone(), p, check=False)
     log("blocktri newton iteration", st)
     T = oracle.transmissibility(pb)
-    W, diag, r0, _ = oracle.linear_system(pb, T, p0, p0)
-    r = r0 - oracle.matvec(pb, W, diag, to_np(p) - p0)
-    rel = np.linalg.norm(r) / np.linalg.norm(r0)
-    assert st["newton_iters"] == 1 and rel <= 1e-10 * 1.01, rel
+    rel, bound = linear_residual_check(pb, T, p0, p0, to_np(p))
+    assert st["newton_iters"] == 1 and rel <= bound, (rel, bound)
     s.close()
 
 
-def test_config4_full_size_one_newton_iteration(torch):
-    """256x256x128 channelised field, BF16 basis and prolongation, FP32
-    smoother, FP64 residual and block-tridiagonal coarse solve."""
+def test_config4_full_size_five_steps(torch):
+    """256x256x128 channelised field (8.4M cells, 16384 coarse nodes), BF16
+    basis and prolongation, FP32 smoother, FP64 residual and block-tridiagonal
+    coarse solve: the 5 time steps the benchmark runs, every linear solve and
+    every step's nonlinear error checked by the oracle."""
     from paper_1705_05783_amd import _cams as C
-    pb = config4().with_options(newton_maxit=1)
+    pb = config4()
     s = solver_for(pb)
     assert C.cams_coarse_planes(s.ctx) == 16
-    p0 = pb.initial_pressure()
-    p = torch.as_tensor(p0, device="cuda")
-    st = s.newton_step(p.clone(), p, check=False)
-    log("config4 one Newton iteration", st)
     T = oracle.transmissibility(pb)
-    W, diag, r0, e0 = oracle.linear_system(pb, T, p0, p0)
-    r = r0 - oracle.matvec(pb, W, diag, to_np(p) - p0)
-    rel = np.linalg.norm(r) / np.linalg.norm(r0)
-    assert st["newton_iters"] == 1 and rel <= pb.lin_rtol * 1.01, rel
-    _, e1 = oracle.nonlinear_residual(pb, T, to_np(p), p0)
-    log("eps before", e0, "after", e1)
-    assert e1 < 0.1 * e0
+    pn_t = torch.as_tensor(pb.initial_pressure(), device="cuda")
+    p_t = pn_t.clone()
+    e_first = None
+    for step in range(pb.n_steps):
+        nit, lits, worst = checked_newton_step(s, pb, T, pn_t, p_t, torch)
+        _, e = oracle.nonlinear_residual(pb, T, to_np(p_t), to_np(pn_t))
+        log("config4 step", step + 1, "newton", nit, "cams", lits, "worst relres/bound", worst, "eps", e)
+        assert nit >= 1 and e <= pb.newton_tol
+        pn_t.copy_(p_t)
+    s.close()
+
+
+def test_channelised_mid_size_against_oracle_newton(torch):
+    """A 32x32x16 binary channelised field (the large workload's generator,
+    k 1 / 1e-4, 30% channels) in the large workload's precision (BF16 basis,
+    FP32 smoother, FP64 refinement), one time step with the linear solves to
+    1e-12 and Newton to 1e-11: the pressure against the oracle's own FP64
+    Newton at the same tolerances.  Both are converged far below the
+    1e-8 relative difference allowed here; the oracle's nonlinear error of
+    the GPU pressure is <= 1e-11."""
+    import dataclasses
+    from workloads.configs import MIXED_BF16
+    from workloads.fields import channel_permeability
+    base = small_problem(32, 32, 16, 8, seed=41, c=0.1, dt=0.05)
+    perm = channel_permeability((16, 32, 32), seed=41).reshape(-1)
+    pb = dataclasses.replace(base, perm=perm, phi=np.full(base.n, 0.2), precision=MIXED_BF16,
+                             lin_rtol=1e-12, newton_tol=1e-11)
+    s = solver_for(pb)
+    T = oracle.transmissibility(pb)
+    pn = pb.initial_pressure()
+    pn_t = torch.as_tensor(pn, device="cuda")
+    p_t = pn_t.clone()
+    nit, lits, worst = checked_newton_step(s, pb, T, pn_t, p_t, torch)
+    _, e = oracle.nonlinear_residual(pb, T, to_np(p_t), pn)
+    p_ref, rc, ost = oracle.newton_step(pb, T, oracle.basis_b4(pb, T), pn, pn, lin_rtol=1e-12,
+                                        newton_tol=1e-11)
+    err = rel_err(to_np(p_t), p_ref)
+    log("channelised 32x32x16: gpu newton", nit, "cams", lits, "oracle", ost, "eps", e, "rel err", err)
+    assert rc == 0 and e <= pb.newton_tol
+    assert err <= 1e-8
     s.close()

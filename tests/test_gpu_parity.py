@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import log, rel_err, require_gpu, solver_for, to_np
+from tests.gpu_util import checked_newton_step, linear_residual_check, log, rel_err, require_gpu, solver_for, to_np
 from workloads import config1, config2, small_problem
 from workloads.configs import FE, FV, SMOOTH_BLOCK, SMOOTH_BLOCK_ALT, SMOOTH_REDBLACK
 
@@ -200,8 +200,8 @@ def test_linear_solve(_gpu, shape, r, restriction, n_pre, smoother):
     assert abs(st["lin_iters_last"] - its) <= 1
     assert rel_err(d_gpu, d_ref) <= 1e-10
     # residual recomputed independently by the oracle
-    res = r0 - oracle.matvec(pb, W, diag, d_gpu)
-    assert np.linalg.norm(res) <= 2e-12 * np.linalg.norm(r0)
+    rel, bound = linear_residual_check(pb, T, p, p, to_np(pt))
+    assert rel <= bound, (rel, bound)
 
 
 def _newton_parity(torch, pb, tol_p=1e-10):
@@ -258,27 +258,65 @@ def test_degenerate_no_wells_closed_domain(_gpu):
     assert float((p - 0.3).abs().max()) == 0.0
 
 
-def test_config2_full_size_one_step(_gpu):
-    """64x64x32, coarsening 8^3 (256 coarse nodes), MSFE, first time step at
-    the workload tolerances; the oracle recomputes the nonlinear error of the
-    GPU pressure and runs its own Newton to compare pressures."""
+def test_config2_full_size_workload_tolerances(_gpu):
+    """64x64x32, coarsening 8^3 (256 coarse nodes), MSFE, all 10 time steps
+    at the workload tolerances (linear 1e-8 relative, Newton 1e-8): every
+    Newton iteration's update meets the linear tolerance on the oracle's own
+    FP64 matrix, and after every step the oracle's nonlinear error of the GPU
+    pressure is <= 1e-8; step 1 is also compared with the oracle's own
+    Newton (both stop at 1e-8, so the pressures agree to that level)."""
     torch = _gpu
     pb = config2()
     s = solver_for(pb)
-    pn = pb.initial_pressure()
-    p_gpu = torch.as_tensor(pn, device="cuda")
-    st = s.newton_step(p_gpu.clone(), p_gpu)
-    log("config2 gpu", st)
     T = oracle.transmissibility(pb)
-    _, e = oracle.nonlinear_residual(pb, T, to_np(p_gpu), pn)
-    assert e <= pb.newton_tol
-    P = oracle.basis_b4(pb, T)
-    assert np.max(np.abs(to_np(s.export(C.CAMS_ARR_P)).reshape(8, -1) - P)) <= 1e-12
-    p_ref, rc, ost = oracle.newton_step(pb, T, P, pn, pn)
-    log("config2 oracle", ost)
-    assert rc == 0
-    # both stop at ||eps|| <= 1e-8; their pressures agree to that level
-    assert rel_err(to_np(p_gpu), p_ref) <= 1e-7
+    pn = pb.initial_pressure()
+    pn_t = torch.as_tensor(pn, device="cuda")
+    p_t = pn_t.clone()
+    for step in range(pb.n_steps):
+        nit, lits, worst = checked_newton_step(s, pb, T, pn_t, p_t, torch)
+        _, e = oracle.nonlinear_residual(pb, T, to_np(p_t), to_np(pn_t))
+        log("config2 step", step + 1, "newton", nit, "cams", lits, "worst relres/bound", worst, "eps", e)
+        assert e <= pb.newton_tol
+        if step == 0:
+            P = oracle.basis_b4(pb, T)
+            assert np.max(np.abs(to_np(s.export(C.CAMS_ARR_P)).reshape(8, -1) - P)) <= 1e-12
+            p_ref, rc, ost = oracle.newton_step(pb, T, P, pn, pn)
+            assert rc == 0
+            assert rel_err(to_np(p_t), p_ref) <= 1e-7
+        pn_t.copy_(p_t)
+
+
+def test_config2_plain_full_size_to_1e10(_gpu):
+    """The plain FP64 target at full size: 64x64x32 with the linear solves
+    to 1e-13 and Newton to ||eps||_2 <= 1e-12.  Steps 1 and 2 against the
+    oracle's pressures at the same tolerances (stored by
+    tests/golden/make_reference_pressures.py, which calls only the oracle):
+    1e-10 relative error; all 10 steps: every linear solve checked on the
+    oracle's FP64 matrix and the oracle's nonlinear error <= 1e-12."""
+    import json
+    import os
+    from tests.golden.make_reference_pressures import input_digest
+    torch = _gpu
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    meta = json.load(open(os.path.join(here, "config2_plain_steps.json")))
+    ref = np.load(os.path.join(here, "config2_plain_steps.npz"), allow_pickle=False)
+    pb = config2().with_options(lin_rtol=meta["lin_rtol"], newton_tol=meta["newton_tol"])
+    assert input_digest(pb) == meta["inputs_sha256"], "stored reference is stale: regenerate it"
+    s = solver_for(pb)
+    T = oracle.transmissibility(pb)
+    pn_t = torch.as_tensor(pb.initial_pressure(), device="cuda")
+    p_t = pn_t.clone()
+    for step in range(pb.n_steps):
+        nit, lits, worst = checked_newton_step(s, pb, T, pn_t, p_t, torch)
+        _, e = oracle.nonlinear_residual(pb, T, to_np(p_t), to_np(pn_t))
+        msg = ["plain step", step + 1, "newton", nit, "cams", lits, "worst relres/bound", worst, "eps", e]
+        if f"step{step + 1}" in ref:
+            err = rel_err(to_np(p_t), ref[f"step{step + 1}"])
+            msg += ["rel err vs oracle", err]
+            assert err <= 1e-10
+        log(*msg)
+        assert e <= pb.newton_tol
+        pn_t.copy_(p_t)
 
 
 def test_error_paths(_gpu):
@@ -294,12 +332,49 @@ def test_error_paths(_gpu):
     st = s2.newton_step(p.clone(), p, check=False)
     assert st["status"] == _cams.CAMS_E_NOT_CONVERGED
     assert bool(torch.isfinite(p).all())
-    # invalid permeability is caught on the device and reported
+    # invalid permeability is caught on the device and reported as an argument error
     bad = pb.with_options()
     bad.perm = pb.perm.copy()
     bad.perm[5] = -1.0
-    with pytest.raises(_cams.CamsError):
+    with pytest.raises(_cams.CamsError) as ei:
         solver_for(bad)
+    assert ei.value.status == _cams.CAMS_E_ARG
+    bad.perm = pb.perm.copy()
+    bad.phi = pb.phi.copy()
+    bad.phi[7] = 1.5
+    with pytest.raises(_cams.CamsError) as ei:
+        solver_for(bad)
+    assert ei.value.status == _cams.CAMS_E_ARG
+
+
+def test_stagnation_is_reported(_gpu):
+    """A tolerance below the rounding level of the FP64 residual cannot be
+    met: the residual norm stalls, and the solve stops on stagnation (no
+    0.9x reduction in 100 iterations) long before lin_maxit, with
+    NOT_CONVERGED and the last evaluated iterate, which still satisfies the
+    system to the rounding level."""
+    torch = _gpu
+    from paper_1705_05783_amd import _cams
+    pb = _pb((24, 24, 16), 8, sigma=2.0, seed=17).with_options(lin_rtol=1e-20, lin_maxit=100000)
+    s = solver_for(pb)
+    s.build_basis()
+    p = pb.initial_pressure()
+    pt = torch.as_tensor(p, device="cuda")
+    s.assemble(pt, pt)
+    s.coarse_op()
+    import ctypes
+    st = _cams.cams_stats()
+    rc = _cams.cams_iterate(s.ctx, ctypes.c_void_p(pt.data_ptr()), ctypes.byref(st))
+    log("stagnation: status", rc, "iterations", st.lin_iters_last, "relres", st.relres_last,
+        _cams.load().cams_last_error(s.ctx).decode())
+    assert rc == _cams.CAMS_E_NOT_CONVERGED
+    assert 100 <= st.lin_iters_last < 2000
+    assert "stagnat" in _cams.load().cams_last_error(s.ctx).decode()
+    T = oracle.transmissibility(pb)
+    W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
+    res = r0 - oracle.matvec(pb, W, diag, to_np(pt) - p)
+    rel = np.linalg.norm(res) / np.linalg.norm(r0)
+    assert rel <= 1e-12 and abs(rel - st.relres_last) <= 1e-13
 
 
 def test_determinism_bitwise(_gpu):
@@ -336,11 +411,9 @@ def test_mixed_linear_solve_meets_fp64_residual(_gpu, shape, r, restriction, pre
     s.coarse_op()
     st = s.iterate(pt)
     T = oracle.transmissibility(pb)
-    W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
-    res = r0 - oracle.matvec(pb, W, diag, to_np(pt) - p)
-    rel = np.linalg.norm(res) / np.linalg.norm(r0)
-    log(pb.name, "precision", precision, "iters", st["lin_iters_last"], "relres", rel)
-    assert rel <= 1.05e-8
+    rel, bound = linear_residual_check(pb, T, p, p, to_np(pt))
+    log(pb.name, "precision", precision, "iters", st["lin_iters_last"], "relres", rel, "bound", bound)
+    assert rel <= bound
     # the prolongation in use is the rounded basis (FP32 / BF16)
     P = to_np(s.export(C.CAMS_ARR_P)).reshape(8, -1)
     P_ref = oracle.basis_b4(pb, T)
@@ -373,11 +446,9 @@ def test_mixed_solve_on_grids_of_the_lds_smoother(_gpu, shape, r, smoother):
         its[precision] = st["lin_iters_last"]
         s.close()
         T = oracle.transmissibility(pb)
-        W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
-        res = r0 - oracle.matvec(pb, W, diag, to_np(pt) - p)
-        rel = np.linalg.norm(res) / np.linalg.norm(r0)
-        log(pb.name, "precision", precision, "iters", its[precision], "relres", rel)
-        assert rel <= 1.05e-8
+        rel, bound = linear_residual_check(pb, T, p, p, to_np(pt))
+        log(pb.name, "precision", precision, "iters", its[precision], "relres", rel, "bound", bound)
+        assert rel <= bound
     assert abs(its[1] - its[0]) <= 3, its
 
 
@@ -403,8 +474,12 @@ def test_mixed_newton_matches_fp64_oracle(_gpu, precision):
 
 @pytest.mark.parametrize("shape,r,restriction", [((48, 48, 40), 4, FE), ((40, 32, 16), 4, FV)])
 def test_coarse_inverse_multi_panel(_gpu, shape, r, restriction):
-    """Coarse sizes beyond one LDS panel: MSFE 1440 nodes (unpivoted blocked
-    LU, 23 panels), MSFV 320 nodes (pivoted panels in global memory)."""
+    """Coarse sizes beyond one LDS panel: MSFE 1440 nodes (Gauss-Jordan
+    sweeps over 23 panels of 64 columns), MSFV 320 nodes (LU with partial
+    pivoting, panels in global memory).  The GPU's coarse operator against
+    the oracle's R A P_hat (1e-12), its inverse against the oracle's operator
+    (A_c^-1 A_c = I to the conditioning bound) and a coarse solve against
+    LAPACK on the oracle's operator."""
     torch = _gpu
     pb = _pb(shape, r, sigma=1.5, seed=12, restriction=restriction)
     s = solver_for(pb)
@@ -416,5 +491,14 @@ def test_coarse_inverse_multi_panel(_gpu, shape, r, restriction):
     Nc = s.Nc
     Ac = to_np(s.export(C.CAMS_ARR_AC)).reshape(Nc, Nc)
     Ainv = to_np(s.export(C.CAMS_ARR_AC_INV)).reshape(Nc, Nc)
-    log(pb.name, "Nc", Nc, "cond", np.linalg.cond(Ac))
-    assert np.max(np.abs(Ainv @ Ac - np.eye(Nc))) <= 1e-15 * np.linalg.cond(Ac) * 100
+    T = oracle.transmissibility(pb)
+    W, diag, _, _ = oracle.linear_system(pb, T, p, p)
+    Ac_ref = oracle.coarse_operator(pb, W, diag, oracle.basis_b4(pb, T), restriction)
+    kappa = np.linalg.cond(Ac_ref)
+    log(pb.name, "Nc", Nc, "cond", kappa)
+    assert rel_err(Ac, Ac_ref) <= 1e-12
+    assert np.max(np.abs(Ainv @ Ac_ref - np.eye(Nc))) <= 1e-15 * kappa * 100
+    rng = np.random.default_rng(5)
+    rc = rng.normal(size=Nc)
+    xc = to_np(s.coarse_solve(torch.as_tensor(rc, device="cuda")))
+    assert rel_err(xc, np.linalg.solve(Ac_ref, rc)) <= 1e-15 * kappa * 100

@@ -537,3 +537,206 @@ def test_shift_on_a_single_block_axis_changes_nothing():
     b = oracle.ILU0(pb, W, diag, block=(8, 8, 8), shift=(4, 4, 4))
     for u, v in zip(a.export(), b.export()):
         assert np.array_equal(u, v)
+
+
+def test_full_dual_blocks_by_brute_force():
+    """Full dual blocks = 7x7x7 cells strictly between vertex planes 8 apart
+    on every axis; counted by enumerating every cell triple of vertex
+    coordinates on a grid with ragged last blocks."""
+    pb = small_problem(37, 30, 26, 8, seed=2)
+    starts = oracle.full_dual_blocks(pb)
+    axes = []
+    for n in (pb.nx, pb.ny, pb.nz):
+        v = [a * 8 + min(8, n - a * 8) // 2 for a in range((n + 7) // 8)]
+        axes.append([v[a] + 1 for a in range(len(v) - 1) if v[a + 1] - v[a] == 8])
+    expect = [(x, y, z) for z in axes[2] for y in axes[1] for x in axes[0]]
+    assert [tuple(s) for s in starts] == expect and len(expect) > 1
+
+
+def test_basis_block_ratio_pins():
+    """The learned-basis check ||(T Phi)_I|| / ||T_IF Phi_F|| over full dual
+    blocks: ~0 for the exact B4 basis (the interior equations hold), exactly
+    1 with the interiors zeroed ((T Phi)_I = -T_IF Phi_F), linear in a
+    perturbation of the exact basis, and for a perturbation d at one cell c
+    with six interior neighbours the squared ratio is proportional to
+    (sum_f T_f)^2 + sum_f T_f^2 (the perturbed row and its six neighbours),
+    so two cells' ratios compare by their transmissibilities alone."""
+    pb = small_problem(24, 24, 16, 8, seed=6, sigma=2.0)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    starts = oracle.full_dual_blocks(pb)
+    assert len(starts) == 4
+    r_exact = oracle.basis_block_ratios(pb, T, P, starts)
+    assert np.all(r_exact <= 1e-12)
+    Pz = P.copy().reshape(8, pb.nz, pb.ny, pb.nx)
+    for (x0, y0, z0) in starts:
+        Pz[:, z0:z0 + 7, y0:y0 + 7, x0:x0 + 7] = 0.0
+    r_zero = oracle.basis_block_ratios(pb, T, Pz.reshape(8, -1), starts)
+    assert np.allclose(r_zero, 1.0, rtol=1e-13)
+
+    x0, y0, z0 = starts[0]
+
+    def bumped(cells, d):
+        Q = P.copy().reshape(8, pb.nz, pb.ny, pb.nx)
+        for (i, j, k) in cells:
+            Q[3, k, j, i] += d
+        return oracle.basis_block_ratios(pb, T, Q.reshape(8, -1), starts[:1])[0]
+
+    def K(i, j, k):
+        Tx, Ty, Tz = (T[a].reshape(pb.nz, pb.ny, pb.nx) for a in range(3))
+        tf = [Tx[k, j, i - 1], Tx[k, j, i], Ty[k, j - 1, i], Ty[k, j, i], Tz[k - 1, j, i], Tz[k, j, i]]
+        return sum(tf) ** 2 + sum(t * t for t in tf)
+
+    a = (x0 + 2, y0 + 3, z0 + 3)
+    b = (x0 + 4, y0 + 2, z0 + 4)
+    ra, rb = bumped([a], 1e-3), bumped([b], 1e-3)
+    assert abs(bumped([a], 2e-3) / ra - 2.0) <= 1e-8
+    assert abs((ra / rb) ** 2 - K(*a) / K(*b)) <= 1e-8 * K(*a) / K(*b)
+
+
+def test_norm_history_incompressible_error_equals_residual():
+    """c = 0 (constant density rho0 = 1, dV = 1): F is affine in p and its
+    linearisation is exact, so F(p + d) = F(p) + A d = -(r0 - A d) and the
+    nonlinear error of every iterate equals the linear residual:
+    ||eps(p + d_i)|| = ||r_i|| along the whole history, and one Newton
+    iteration suffices."""
+    pb = small_problem(16, 12, 8, 4, seed=5, sigma=2.0, c=0.0)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, nu, res, err = oracle.newton_history(pb, T, P, p0, p0, lin_rtol=1e-10, newton_tol=1e-8)
+    assert set(nu.tolist()) == {0} and len(res) >= 3
+    assert np.allclose(err, res, rtol=1e-9, atol=1e-14 * res[0])
+    assert np.all(np.diff(res[:3]) < 0)
+
+
+def test_norm_history_entries():
+    """c > 0: the first entry of each Newton iteration is the Newton error
+    ||eps(p^nu)|| and the residual ||r0|| of its system; each linear solve
+    stops at its tolerance (relative 1e-1, the paper's adaptive strategy) and
+    only there; the step ends with ||eps|| <= 1e-6."""
+    pb = small_problem(16, 12, 8, 4, seed=5, sigma=2.0, c=0.1)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, nu, res, err = oracle.newton_history(pb, T, P, p0, p0, lin_rtol=1e-1, newton_tol=1e-6)
+    assert oracle.nonlinear_residual(pb, T, p, p0)[1] <= 1e-6
+    q = p0.copy()
+    for v in range(nu.max() + 1):
+        idx = np.nonzero(nu == v)[0]
+        W, diag, r0, e = oracle.linear_system(pb, T, q, p0)
+        assert abs(err[idx[0]] - e) <= 1e-13 * e and abs(res[idx[0]] - np.linalg.norm(r0)) <= 1e-13 * res[idx[0]]
+        assert res[idx[-1]] <= 0.1 * res[idx[0]] and np.all(res[idx[:-1]] > 0.1 * res[idx[0]])
+        LU, piv = oracle.lu_factor(oracle.coarse_operator(pb, W, diag, P, pb.restriction))
+        d, its, _ = oracle.cams_solve(pb, W, diag, P, pb.restriction, LU, piv, oracle.smoother_for(pb, W, diag),
+                                      r0, rtol=1e-1)
+        assert its == len(idx) - 1
+        q = q + d
+
+
+def test_absolute_linear_tolerance():
+    """lin_atol stops the C-AMS iteration at ||r|| <= atol whatever ||r0||."""
+    pb = small_problem(16, 12, 8, 4, seed=5, sigma=2.0, c=0.1)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    W, diag, r0, _ = oracle.linear_system(pb, T, p0, p0)
+    LU, piv = oracle.lu_factor(oracle.coarse_operator(pb, W, diag, P, pb.restriction))
+    ilu = oracle.smoother_for(pb, W, diag)
+    atol = 1e-6 * np.linalg.norm(r0)
+    d, its, hist = oracle.cams_solve(pb, W, diag, P, pb.restriction, LU, piv, ilu, r0, rtol=1e-300, atol=atol)
+    assert its > 0
+    assert np.linalg.norm(r0 - oracle.matvec(pb, W, diag, d)) <= atol
+    assert hist[its - 1] * np.linalg.norm(r0) > atol
+
+
+def _acc_src(pb, p, pn):
+    rho = pb.rho0 * np.exp(pb.c * (p - pb.p0))
+    rhon = pb.rho0 * np.exp(pb.c * (pn - pb.p0))
+    dV = pb.dx * pb.dy * pb.dz
+    src = rho * pb.q * dV if pb.q is not None else 0.0
+    return pb.phi * dV * (rho - rhon) / pb.dt, src, pb.phi * pb.c * rhon * dV / pb.dt
+
+
+def test_face_fluxes_rebuild_the_residual():
+    """F_n = accumulation + net outflow of the two-point fluxes - source on
+    every non-Dirichlet cell (Eq. (2) cell by cell), with the fluxes
+    antisymmetric by construction (one value per face)."""
+    pb = small_problem(13, 11, 7, (3, 4, 2), seed=4, sigma=2.0, c=0.1)
+    T = oracle.transmissibility(pb)
+    rng = np.random.default_rng(3)
+    p = rng.uniform(0, 1, pb.n)
+    pn = rng.uniform(0, 1, pb.n)
+    F_ref, _ = oracle.nonlinear_residual(pb, T, p, pn)
+    acc, src, _ = _acc_src(pb, p, pn)
+    F = acc + oracle.cell_outflow(pb, oracle.face_flux(pb, T, p)) - src
+    free = pb.dirichlet_mask() == 0
+    assert np.allclose(F[free], F_ref[free], rtol=1e-12, atol=1e-13 * np.abs(F_ref).max())
+
+
+@pytest.mark.parametrize("c", [0.0, 0.1])
+def test_msfv_sweep_balances_every_coarse_block(c):
+    """After MSFE Newton to a loose tolerance, one MSFV stage makes the fluxes
+    of the linear system conservative on every primal coarse block: the
+    block sums of (accumulation linearised at p + net outflow - source)
+    vanish to rounding, where before the sweep they were of the size of the
+    Newton error (Sec. 4.2 strategy; MSFV conservation, Sec. 4).  For c = 0
+    the linearisation is exact, so the nonlinear block balance also
+    vanishes."""
+    pb = small_problem(24, 24, 16, 8, seed=9, sigma=2.0, c=c)
+    T = oracle.transmissibility(pb)
+    P = oracle.basis_b4(pb, T)
+    p0 = pb.initial_pressure()
+    p, rc, st = oracle.newton_step(pb, T, P, p0, p0, lin_rtol=1e-3, newton_tol=1e-5)
+    assert rc == 0
+    before = np.abs(oracle.block_balance(pb, T, p, p0)).max()
+    p_new, d, flux = oracle.conservative_sweep(pb, T, P, p, p0)
+    acc, src, acc_lin = _acc_src(pb, p, p0)
+    lin = acc + acc_lin * d + oracle.cell_outflow(pb, flux) - src
+    free = pb.dirichlet_mask() == 0
+    blk = np.bincount(oracle.primal_block(pb)[free], weights=lin[free], minlength=oracle.num_coarse(pb))
+    scale = np.abs(acc).max() + np.abs(flux).max()
+    assert before > 1e3 * 1e-14 * scale
+    assert np.abs(blk).max() <= 1e-14 * scale * 64
+    if c == 0.0:
+        assert np.abs(oracle.block_balance(pb, T, p_new, p0)).max() <= 1e-14 * scale * 64
+
+
+def test_b2_at_uniform_pressure_is_b4():
+    """B2 (Eq. (9)) weights the couplings by the face densities of the
+    iterate; at a uniform pressure they are T times one constant, and the
+    local problems (homogeneous equations with lumped couplings) are
+    invariant under that scaling: B2 = B4."""
+    pb = small_problem(19, 17, 11, (4, 3, 5), seed=3, sigma=2.0, c=0.2)
+    T = oracle.transmissibility(pb)
+    p = np.full(pb.n, 0.37)
+    C, a = oracle.basis_operator(pb, T, oracle.B2, p=p, pn=p)
+    assert a is None
+    assert np.abs(oracle.basis_general(pb, C) - oracle.basis_b4(pb, T)).max() <= 1e-14
+
+
+def test_b3_edge_closed_form_and_no_partition_of_unity():
+    """Homogeneous medium (unit transmissibility), B3 (Eq. (10)): along a dual
+    edge of 7 cells between vertices 8 apart, (a + 2) Phi_m - Phi_{m-1} -
+    Phi_{m+1} = 0 with Phi_0 = 1, Phi_8 = 0, so Phi_m = sinh(th (8 - m)) /
+    sinh(8 th) with cosh th = 1 + a / 2 (a = phi c dV / dt).  With the
+    accumulation the basis no longer sums to one away from the vertices
+    (it does for B2, whose rows sum to zero)."""
+    pb = small_problem(16, 16, 16, 8, seed=1, c=0.1, dt=0.1)
+    pb.perm = np.ones(pb.n)
+    pb.phi = np.full(pb.n, 0.2)
+    T = oracle.transmissibility(pb)
+    C, a = oracle.basis_operator(pb, T, oracle.B3)
+    P = oracle.basis_general(pb, C, a)
+    a0 = 0.2 * 0.1 / 0.1
+    th = np.arccosh(1.0 + a0 / 2.0)
+    m = np.arange(1, 8)
+    cells = [pb.cell(4 + k, 4, 4) for k in m]
+    assert np.allclose(P[0, cells], np.sinh(th * (8 - m)) / np.sinh(8 * th), rtol=1e-12, atol=1e-15)
+    lv = oracle.cell_levels(pb)
+    inner = lv < 3
+    assert np.all(P.sum(axis=0)[inner] < 1.0 - 1e-6)
+    rng = np.random.default_rng(2)
+    p = rng.uniform(0, 1, pb.n)
+    C2, _ = oracle.basis_operator(pb, T, oracle.B2, p=p, pn=p)
+    assert np.allclose(oracle.basis_general(pb, C2).sum(axis=0), 1.0, atol=1e-13)

@@ -62,6 +62,7 @@ class Problem:
     n_pre: int = 0
     n_post: int = 5
     lin_rtol: float = 1e-8
+    lin_atol: float = 0.0           # absolute linear tolerance (0: relative only)
     lin_maxit: int = 500
     newton_tol: float = 1e-8
     newton_maxit: int = 30
