@@ -81,6 +81,22 @@ enum { CAMS_FP64 = 0, CAMS_MIXED_FP32 = 1, CAMS_MIXED_BF16 = 2 };
  * fewer iterations for the same work per step. */
 enum { CAMS_SMOOTH_BLOCK_ILU0 = 0, CAMS_SMOOTH_RB_ILU0 = 1, CAMS_SMOOTH_BLOCK_ALT_ILU0 = 2 };
 
+/* Basis function type (Sec. 3, Eqs. (8)-(11)), each solved with the same
+ * reduced-problem boundary conditions, in the mass form of the Newton
+ * system (rows multiplied by rho dV):
+ *   B4 (default): -div(lambda grad Phi) = 0: couplings T; pressure
+ *       independent, built once per rock;
+ *   B3: c^n Phi - div(lambda grad Phi) = 0: couplings T plus the diagonal
+ *       phi c dV / dt (c^n at the old time level; pressure independent);
+ *   B2: -(1/rho) div(rho lambda grad Phi) = 0: couplings
+ *       T (rho_i + rho_j)/2 of the current Newton iterate;
+ *   B1: c Phi - (1/rho) div(rho lambda grad Phi) = 0: those couplings plus
+ *       the accumulation diagonal of the Newton matrix, phi c rho(p^n) dV/dt.
+ * B1 and B2 depend on pressure: cams_newton_step updates them adaptively at
+ * every Newton iteration (see basis_tol).  With an accumulation term (B1,
+ * B3) the basis is not a partition of unity. */
+enum { CAMS_BASIS_B4 = 0, CAMS_BASIS_B1 = 1, CAMS_BASIS_B2 = 2, CAMS_BASIS_B3 = 3 };
+
 typedef struct {
     int32_t nx, ny, nz;       /* fine cells per axis, >= 2 on active axes (nz == 1 for 2D) */
     double dx, dy, dz;        /* cell sizes (> 0) */
@@ -104,6 +120,11 @@ typedef struct {
     double newton_tol;        /* stop Newton when ||eps||_2 <= newton_tol (Eq. (16)) */
     int32_t newton_maxit;     /* Newton iteration limit per time step */
     double lin_atol;          /* also stop when ||r||_2 <= lin_atol (absolute; 0 = relative test only) */
+    int32_t basis_type;       /* CAMS_BASIS_B4 (0, default), B1, B2 or B3 */
+    double basis_tol;         /* B1/B2 adaptive update: a dual region is re-solved when a coefficient of
+                                 its local problem changed by more than this (relative) since it was
+                                 last solved, and so is every region that takes it as boundary data;
+                                 0 = every region at every Newton iteration */
 } cams_options;
 
 typedef struct {
@@ -117,6 +138,8 @@ typedef struct {
     double t_basis_ms;
     double t_coarse_ms;
     double t_iterate_ms;
+    int32_t basis_updates;          /* B1/B2: adaptive basis updates in the last cams_newton_step */
+    int32_t basis_regions_rebuilt;  /* dual regions solved by the basis builds and updates of that step */
 } cams_stats;
 
 /* Create a context for one grid.  Validates grid/fluid/options: active axes
@@ -163,6 +186,18 @@ cams_status cams_invalidate_basis(cams_ctx *ctx);
  * for a non-singular system).  Errors: CAMS_E_ARG (index out of range,
  * duplicate, non-finite pressure), CAMS_E_STATE (no workspace). */
 cams_status cams_set_wells(cams_ctx *ctx, const int64_t *cells_host, const double *p_host, int32_t n);
+
+/* Dirichlet boundary face (Sec. 4: the default test cases fix the pressure
+ * on the west and east faces, no flow elsewhere): face 0 = west (x = 0),
+ * 1 = east (x = nx - 1), at `pressure`; NaN removes it.  Every cell on that
+ * face gets the two-point flux T_b (rho_i + rho(p_b))/2 (p_i - p_b) through
+ * it, with T_b = 2 (k_i / mu) dy dz / dx the half-cell transmissibility
+ * between the cell centre and the face, in the residual and (with the face
+ * density frozen, as for interior faces) on the diagonal of the Newton
+ * matrix.  The basis (Eq. (11)) is unaffected.  Host only; call before
+ * cams_set_wells when the faces are the only Dirichlet data with c = 0.
+ * Errors: CAMS_E_ARG (face, infinite pressure). */
+cams_status cams_set_face_dirichlet(cams_ctx *ctx, int32_t face, double pressure);
 
 /* Assemble the Newton linear system at pressure p_dev, old-time pressure
  * pn_dev (Sec. 2, Eqs. (2)-(6), multiplied by rho_i dV_i):

@@ -152,6 +152,32 @@ def transmissibility(pb):
     return T
 
 
+def face_bc_arrays(pb):
+    """(bt, bp) of the Dirichlet boundary faces of pb.face_bc ({"W": p, "E": p}
+    for the west face x = 0 / east face x = nx - 1), or (None, None):
+    bt = half-cell transmissibility 2 (k / mu) dy dz / dx of a cell whose
+    face lies on such a boundary, bp = the face pressure."""
+    bc = getattr(pb, "face_bc", None)
+    if not bc:
+        return None, None
+    bt = np.zeros(pb.n)
+    bp = np.zeros(pb.n)
+    i = np.arange(pb.n) % pb.nx
+    for side, col in (("W", 0), ("E", pb.nx - 1)):
+        if side in bc:
+            m = i == col
+            bt[m] = 2.0 * np.asarray(pb.perm)[m] / pb.mu * pb.dy * pb.dz / pb.dx
+            bp[m] = float(bc[side])
+    return bt, bp
+
+
+def _bc_ptrs(pb):
+    bt, bp = face_bc_arrays(pb)
+    if bt is None:
+        return None, None, ()
+    return _ptr(bt), _ptr(bp), (bt, bp)
+
+
 def nonlinear_residual(pb, T, p, pn):
     """(F, ||eps||_2): mass-form residual of Eq. (2) and the error norm."""
     g, f = grid_of(pb), fluid_of(pb)
@@ -159,9 +185,10 @@ def nonlinear_residual(pb, T, p, pn):
     q = None if pb.q is None else _f64(pb.q)
     dm = pb.dirichlet_mask()
     T = _f64(T)
+    btp, bpp, keep = _bc_ptrs(pb)
     e = lib().or_nonlinear_residual(ctypes.byref(g), ctypes.byref(f), _ptr(T[0]), _ptr(T[1]),
                                     _ptr(T[2]), _ptr(_f64(pb.phi)),
-                                    None if q is None else _ptr(q), _ptr(dm),
+                                    None if q is None else _ptr(q), _ptr(dm), btp, bpp,
                                     _ptr(_f64(p)), _ptr(_f64(pn)), _ptr(F))
     return F, e
 
@@ -176,8 +203,9 @@ def linear_system(pb, T, p, pn):
     q = None if pb.q is None else _f64(pb.q)
     dm = pb.dirichlet_mask()
     T = _f64(T)
+    btp, bpp, keep = _bc_ptrs(pb)
     e = lib().or_linear_system(ctypes.byref(g), ctypes.byref(f), _ptr(T[0]), _ptr(T[1]), _ptr(T[2]),
-                               _ptr(_f64(pb.phi)), None if q is None else _ptr(q), _ptr(dm),
+                               _ptr(_f64(pb.phi)), None if q is None else _ptr(q), _ptr(dm), btp, bpp,
                                _ptr(_f64(p)), _ptr(_f64(pn)),
                                _ptr(W[0]), _ptr(W[1]), _ptr(W[2]), _ptr(diag), _ptr(r))
     return W, diag, r, e
@@ -424,9 +452,10 @@ def newton_step(pb, T, P, pn, p, restriction=None, n_pre=None, n_post=None, lin_
     q = None if pb.q is None else _f64(pb.q)
     st = np.zeros(3)
     kind = getattr(pb, "smoother", SMOOTH_BLOCK) if smoother is None else smoother
+    btp, bpp, keep = _bc_ptrs(pb)
     rc = lib().or_newton_step(
         ctypes.byref(g), ctypes.byref(f), _ptr(T[0]), _ptr(T[1]), _ptr(T[2]), _ptr(_f64(pb.phi)),
-        None if q is None else _ptr(q), _ptr(pb.dirichlet_mask()), _ptr(_f64(P)),
+        None if q is None else _ptr(q), _ptr(pb.dirichlet_mask()), btp, bpp, _ptr(_f64(P)),
         int(pb.restriction if restriction is None else restriction),
         int(pb.n_pre if n_pre is None else n_pre), int(pb.n_post if n_post is None else n_post),
         ctypes.c_double(pb.lin_rtol if lin_rtol is None else lin_rtol),
@@ -600,3 +629,27 @@ def block_balance(pb, T, p, pn):
     (Eq. (2) integrated over the block; interior faces cancel)."""
     F, _ = nonlinear_residual(pb, T, p, pn)
     return np.bincount(primal_block(pb), weights=F, minlength=num_coarse(pb))
+
+
+def newton_step_basis(pb, T, pn, p, kind, lin_rtol, newton_tol, newton_maxit=30, lin_maxit=2000):
+    """One time step with basis type `kind` (Sec. 3): B3/B4 built once at
+    the start, B1/B2 rebuilt from the current iterate at every Newton
+    iteration (Table "cams" step 3; every region, i.e. a zero update
+    threshold).  Returns (p, Newton iterations, C-AMS iterations)."""
+    p = np.array(p, dtype=np.float64, copy=True)
+    P = None
+    lits = 0
+    for nu in range(newton_maxit + 1):
+        W, diag, r0, e = linear_system(pb, T, p, pn)
+        if e <= newton_tol:
+            return p, nu, lits
+        if P is None or kind in (B1, B2):
+            P = basis_general(pb, *basis_operator(pb, T, kind, p=p, pn=pn))
+        LU, piv = lu_factor(coarse_operator(pb, W, diag, P, pb.restriction))
+        d, its, _ = cams_solve(pb, W, diag, P, pb.restriction, LU, piv, smoother_for(pb, W, diag), r0,
+                               rtol=lin_rtol, maxit=lin_maxit)
+        if its < 0:
+            raise RuntimeError("oracle linear solve did not converge")
+        lits += its
+        p = p + d
+    raise RuntimeError("oracle Newton did not converge")

@@ -125,6 +125,11 @@ static double density(const og_fluid *f, double p) { return f->rho0 * exp(f->c *
  * Eq. (2)), multiplied by rho_i dV_i:
  *   F_i = phi_i dV (rho_i - rho_i^n)/dt + sum_j T_ij rho_ij (p_i - p_j) - rho_i q_i dV
  * with rho_ij the mean of the two cell densities.  F_i = 0 on Dirichlet cells.
+ * A Dirichlet boundary face (fixed pressure pb on the west or east face,
+ * Sec. 4: the default test cases) adds T_b (rho_i + rho(pb))/2 (p_i - pb),
+ * with T_b = 2 lambda_i A / dx the half-cell transmissibility between the
+ * cell centre and the face: bt[i] = T_b, bp[i] = pb (both NULL: no face
+ * condition; bt[i] = 0 on cells without one).
  * The nonlinear error (Sec. 4.1.1, Eq. (16)) is eps_i = F_i / (rho_i dV);
  * the function returns ||eps||_2 over the non-Dirichlet cells.
  * Pinned: global mass balance, c = 0 linearity, direct-solve Newton.
@@ -132,6 +137,7 @@ static double density(const og_fluid *f, double p) { return f->rho0 * exp(f->c *
 double or_nonlinear_residual(const og_grid *g, const og_fluid *f,
                              const double *Tx, const double *Ty, const double *Tz,
                              const double *phi, const double *q, const uint8_t *dmask,
+                             const double *bt, const double *bp,
                              const double *p, const double *pn, double *F)
 {
     long N = ncells(g);
@@ -148,6 +154,7 @@ double or_nonlinear_residual(const og_grid *g, const og_fluid *f,
             double rhof = 0.5 * (rho + density(f, p[m]));
             flux += T * rhof * (p[n] - p[m]);
         }
+        if (bt && bt[n] > 0.0) flux += bt[n] * 0.5 * (rho + density(f, bp[n])) * (p[n] - bp[n]);
         double src = q ? rho * q[n] * dV : 0.0;
         F[n] = acc + flux - src;
         double e = F[n] / (rho * dV);
@@ -172,12 +179,13 @@ double or_nonlinear_residual(const og_grid *g, const og_fluid *f,
 double or_linear_system(const og_grid *g, const og_fluid *f,
                         const double *Tx, const double *Ty, const double *Tz,
                         const double *phi, const double *q, const uint8_t *dmask,
+                        const double *bt, const double *bp,
                         const double *p, const double *pn,
                         double *Wx, double *Wy, double *Wz, double *diag, double *r)
 {
     long N = ncells(g);
     double dV = g->dx * g->dy * g->dz;
-    double en = or_nonlinear_residual(g, f, Tx, Ty, Tz, phi, q, dmask, p, pn, r);
+    double en = or_nonlinear_residual(g, f, Tx, Ty, Tz, phi, q, dmask, bt, bp, p, pn, r);
     for (long n = 0; n < N; n++) r[n] = -r[n];
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < g->nz; k++)
@@ -200,6 +208,7 @@ double or_linear_system(const og_grid *g, const og_fluid *f,
                     if (!neighbour(g, Tx, Ty, Tz, n, fc, &m, &T)) continue;
                     d += T * 0.5 * (rho + density(f, p[m]));
                 }
+                if (bt && bt[n] > 0.0) d += bt[n] * 0.5 * (rho + density(f, bp[n]));
                 diag[n] = d;
             }
     return en;
@@ -1017,7 +1026,8 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
  * ---------------------------------------------------------------------- */
 int or_newton_step(const og_grid *g, const og_fluid *f,
                    const double *Tx, const double *Ty, const double *Tz,
-                   const double *phi, const double *q, const uint8_t *dmask, const double *P,
+                   const double *phi, const double *q, const uint8_t *dmask, const double *bt,
+                   const double *bp, const double *P,
                    int restriction, int n_pre, int n_post, double lin_rtol, double lin_atol, int lin_maxit,
                    double newton_tol, int newton_maxit, int smoother, int bx, int by, int bz,
                    const double *pn, double *p, double *stats)
@@ -1035,7 +1045,7 @@ int or_newton_step(const og_grid *g, const og_fluid *f,
     int rc = -1, nit = 0, lit = 0;
     double en = 0.0;
     for (nit = 0; nit <= newton_maxit; nit++) {
-        en = or_linear_system(g, f, Tx, Ty, Tz, phi, q, dmask, p, pn, W, W + N, W + 2 * N, diag, r);
+        en = or_linear_system(g, f, Tx, Ty, Tz, phi, q, dmask, bt, bp, p, pn, W, W + N, W + 2 * N, diag, r);
         if (en <= newton_tol) { rc = 0; break; }
         if (nit == newton_maxit || !isfinite(en)) break;
         or_coarse_operator(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac);

@@ -38,6 +38,10 @@ CAMS_ARR_AC = 5
 CAMS_ARR_AC_INV = 6
 CAMS_ARR_INVD = 7
 
+CAMS_BASIS_B4 = 0
+CAMS_BASIS_B1 = 1
+CAMS_BASIS_B2 = 2
+CAMS_BASIS_B3 = 3
 CAMS_PROF_NONE = 0
 CAMS_PROF_SMOOTH_STEP = 1
 
@@ -58,7 +62,7 @@ class cams_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("smoother", ctypes.c_int32),
                 ("lin_rtol", ctypes.c_double), ("lin_maxit", ctypes.c_int32),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
-                ("lin_atol", ctypes.c_double)]
+                ("lin_atol", ctypes.c_double), ("basis_type", ctypes.c_int32), ("basis_tol", ctypes.c_double)]
 
 
 class cams_stats(ctypes.Structure):
@@ -66,7 +70,8 @@ class cams_stats(ctypes.Structure):
                 ("lin_iters_last", ctypes.c_int32), ("fallback_blocks", ctypes.c_int32),
                 ("relres_last", ctypes.c_double), ("eps_norm_last", ctypes.c_double),
                 ("t_assemble_ms", ctypes.c_double), ("t_basis_ms", ctypes.c_double),
-                ("t_coarse_ms", ctypes.c_double), ("t_iterate_ms", ctypes.c_double)]
+                ("t_coarse_ms", ctypes.c_double), ("t_iterate_ms", ctypes.c_double),
+                ("basis_updates", ctypes.c_int32), ("basis_regions_rebuilt", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -88,6 +93,7 @@ _SIGS = [
     ("cams_iterate", _I, [_VP, _VP, ctypes.POINTER(cams_stats)]),
     ("cams_newton_step", _I, [_VP, _VP, _VP, ctypes.POINTER(cams_stats)]),
     ("cams_conservative_sweep", _I, [_VP, _VP, _VP, _VP]),
+    ("cams_set_face_dirichlet", _I, [_VP, ctypes.c_int32, ctypes.c_double]),
     ("cams_newton_history", _I, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(cams_stats)]),
     ("cams_smooth_apply", _I, [_VP, _VP, _VP]),

@@ -270,6 +270,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     if (O.precision != CAMS_FP64 && O.smoother == CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
     if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
     if (!(O.lin_atol >= 0) || !isfinite(O.lin_atol)) return CAMS_E_ARG;
+    if (O.basis_type < CAMS_BASIS_B4 || O.basis_type > CAMS_BASIS_B3 || !(O.basis_tol >= 0)) return CAMS_E_ARG;
     const int nb[3] = {num_blocks(n[0], r[0]), num_blocks(n[1], r[1]), num_blocks(n[2], r[2])};
     const double Nc = (double)nb[0] * nb[1] * nb[2];
     if (Nc > 32768) return CAMS_E_ARG;  // dense coarse operator limit
@@ -369,6 +370,45 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
         }
     }
     c->region_total = off;
+    if (O.basis_type == CAMS_BASIS_B1 || O.basis_type == CAMS_BASIS_B2) {
+        // which regions take a region's values as Dirichlet data: a region's
+        // cells reach, across its open axes, cells of lower-dimensional
+        // regions (edges for faces, faces for interiors)
+        std::vector<int32_t> rid((size_t)g.N, -1);
+        const int nx = G.nx, ny = G.ny, nz = G.nz;
+        auto for_cells = [&](const Region &R, auto fn) {
+            for (int z = R.s[2]; z < R.s[2] + R.len[2]; ++z)
+                for (int y = R.s[1]; y < R.s[1] + R.len[1]; ++y)
+                    for (int x = R.s[0]; x < R.s[0] + R.len[0]; ++x) fn(x, y, z);
+        };
+        for (int q = 0; q < off; ++q)
+            for_cells(t.regions[q], [&](int x, int y, int z) { rid[x + (size_t)nx * (y + (size_t)ny * z)] = q; });
+        std::vector<std::vector<int32_t>> dep(off);
+        for (int q = 0; q < off; ++q) {
+            const Region &R = t.regions[q];
+            for_cells(R, [&](int x, int y, int z) {
+                const int xyz[3] = {x, y, z}, nn[3] = {nx, ny, nz};
+                for (int a = 0; a < 3; ++a) {
+                    if (!(R.freemask & (1 << a))) continue;
+                    for (int dir = -1; dir <= 1; dir += 2) {
+                        int v[3] = {xyz[0], xyz[1], xyz[2]};
+                        v[a] += dir;
+                        if (v[a] < 0 || v[a] >= nn[a] || (v[a] >= R.s[a] && v[a] < R.s[a] + R.len[a])) continue;
+                        const int r = rid[v[0] + (size_t)nx * (v[1] + (size_t)ny * v[2])];
+                        if (r >= 0 && r != q) dep[r].push_back(q);
+                    }
+                }
+            });
+        }
+        c->dep_ptr.assign(1, 0);
+        c->dep_idx.clear();
+        for (int q = 0; q < off; ++q) {
+            std::sort(dep[q].begin(), dep[q].end());
+            dep[q].erase(std::unique(dep[q].begin(), dep[q].end()), dep[q].end());
+            c->dep_idx.insert(c->dep_idx.end(), dep[q].begin(), dep[q].end());
+            c->dep_ptr.push_back((int32_t)c->dep_idx.size());
+        }
+    }
 
     // workspace layout
     Layout L;
@@ -435,6 +475,18 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
         put(L.add(O.restriction == CAMS_R_FE ? mats * ((dim + 63) / 64) * 12 * sizeof(GemmDesc) : 0));
         put(L.add(O.restriction == CAMS_R_FE ? (c->blocktri ? 2 : 1) * (2 * dim * 64 + 64 * 64) * 8 : 0));   // 45 saved column blocks, saved pivot rows (per chain)
     }
+    {   // 46-51 basis types B1-B3
+        const bool pdep = O.basis_type == CAMS_BASIS_B1 || O.basis_type == CAMS_BASIS_B2;
+        const bool diag = O.basis_type == CAMS_BASIS_B1 || O.basis_type == CAMS_BASIS_B3;
+        const size_t nreg = (size_t)c->region_total;
+        put(L.add(pdep ? 3 * n8 : 0));                  // 46 bcoef
+        put(L.add(diag ? n8 : 0));                      // 47 bdiag
+        put(L.add(pdep ? 3 * n8 : 0));                  // 48 bsnap
+        put(L.add(pdep && diag ? n8 : 0));              // 49 bdsnap
+        put(L.add(pdep ? nreg * 4 : 0));                // 50 rflag
+        put(L.add(pdep ? nreg * sizeof(Region) : 0));   // 51 rlist
+    }
+    put(L.add((size_t)2 * G.ny * G.nz * 8));   // 52 Tb: west and east boundary-face transmissibilities
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
         return CAMS_E_NOMEM;
@@ -505,6 +557,13 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.zf = (float *)(w + off[42]);
     a.gjd = (void *)(w + off[44]);
     a.gjcb = (double *)(w + off[45]);
+    a.bcoef = (double *)(w + off[46]);
+    a.bdiag = (double *)(w + off[47]);
+    a.bsnap = (double *)(w + off[48]);
+    a.bdsnap = (double *)(w + off[49]);
+    a.rflag = (int32_t *)(w + off[50]);
+    a.rlist = (Region *)(w + off[51]);
+    a.Tb = (double *)(w + off[52]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -554,7 +613,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     c->ws = w;
     c->ws_bytes = bytes;
     c->has_ws = true;
-    c->has_rock = c->has_basis = c->has_system = c->has_coarse = false;
+    c->has_rock = c->has_basis = c->has_system = c->has_coarse = c->has_bcoef = false;
     c->ac_zeroed = false;
     c->gj_ready = false;
     c->nwells = 0;
@@ -599,7 +658,8 @@ cams_status cams_set_wells(cams_ctx *c, const int64_t *cells, const double *p, i
     if (!c->has_ws) return fail(c, CAMS_E_STATE, "set_wells before set_workspace");
     const size_t wcap = (size_t)c->g.N / 8 + 64;
     if (n < 0 || (size_t)n > wcap || (n > 0 && (!cells || !p))) return fail(c, CAMS_E_ARG, "bad well list");
-    if (n == 0 && !(c->fl.c > 0)) return fail(c, CAMS_E_ARG, "no wells and c = 0: singular system");
+    if (n == 0 && !(c->fl.c > 0) && !c->bc.on[0] && !c->bc.on[1])
+        return fail(c, CAMS_E_ARG, "no wells, no Dirichlet face and c = 0: singular system");
     std::vector<uint8_t> mask((size_t)c->g.N, 0);
     std::vector<int32_t> ci(n);
     std::vector<double> pv(n);
@@ -660,6 +720,60 @@ void enqueue_clear_status(cams_ctx *c) { clear_status(c); }
 
 }  // namespace cams
 
+// B1/B2 adaptive update (Sec. 4.1.2, adaptive updating of the multiscale
+// operators): re-solve the dual regions whose local coefficients changed by
+// more than basis_tol since their last solve (every region when basis_tol
+// is 0), and every region that takes a re-solved region's values as
+// boundary data; the others keep their basis values.  Returns the number
+// of regions re-solved.
+static int update_basis_adaptive(cams_ctx *c)
+{
+    const int first = c->regoff[1], count = c->region_total - first;
+    const double tol = c->opt.basis_tol;
+    std::vector<int32_t> flag((size_t)count, 1);
+    if (tol > 0) {
+        launch_region_change(c, first, count, tol);
+        CAMS_HIP(hipMemcpyAsync(flag.data(), c->a.rflag + first, (size_t)count * 4, hipMemcpyDeviceToHost,
+                                c->stream));
+        CAMS_HIP(hipStreamSynchronize(c->stream));
+        // regions are listed by stage and depend only on earlier stages: one
+        // forward pass carries the marks through edges, faces and interiors
+        for (int q = 0; q < count; ++q)
+            if (flag[q])
+                for (int32_t e = c->dep_ptr[first + q]; e < c->dep_ptr[first + q + 1]; ++e)
+                    flag[c->dep_idx[e] - first] = 1;
+    }
+    std::vector<Region> list;
+    int per[4] = {0, 0, 0, 0};
+    for (int f = 1; f <= c->g.dim; ++f)
+        for (int q = c->regoff[f]; q < c->regoff[f] + c->nreg[f]; ++q)
+            if (flag[q - first]) {
+                list.push_back(c->regions[q]);
+                ++per[f];
+            }
+    if (list.empty()) return 0;
+    clear_status(c);
+    CAMS_HIP(hipMemcpyAsync(c->a.rlist, list.data(), list.size() * sizeof(Region), hipMemcpyHostToDevice, c->stream));
+    int at = 0;
+    for (int f = 1; f <= c->g.dim; ++f) {
+        launch_basis_regions(c, f, c->a.rlist + at, per[f]);
+        at += per[f];
+    }
+    launch_region_snapshot(c, c->a.rlist, (int)list.size());
+    if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
+    CAMS_HIP(hipGetLastError());
+    CAMS_HIP(hipStreamSynchronize(c->stream));   // the host list must outlive the copy
+    return (int)list.size();
+}
+
+static cams_status check_basis_status(cams_ctx *c)
+{
+    int32_t flags = 0;
+    sync_status(c, &flags);
+    if (flags) return fail(c, CAMS_E_BREAKDOWN, "basis: non-positive local pivot or inconsistent region");
+    return CAMS_OK;
+}
+
 extern "C" {
 
 cams_status cams_assemble(cams_ctx *c, const double *p_dev, const double *pn_dev, double *eps_norm_out)
@@ -669,6 +783,10 @@ cams_status cams_assemble(cams_ctx *c, const double *p_dev, const double *pn_dev
     if (!p_dev || !pn_dev) return fail(c, CAMS_E_ARG, "null pressure");
     try {
         enqueue_assemble(c, p_dev, pn_dev);
+        if (c->opt.basis_type == CAMS_BASIS_B1 || c->opt.basis_type == CAMS_BASIS_B2) {
+            launch_basis_coeffs(c, p_dev, pn_dev);   // local-problem coefficients at this iterate
+            c->has_bcoef = true;
+        }
         CAMS_HIP(hipGetLastError());
         if (eps_norm_out) {
             double e2 = read_scalar(c, c->a.scal + S_EPS2);
@@ -687,7 +805,11 @@ cams_status cams_build_basis(cams_ctx *c)
 {
     if (!c) return CAMS_E_ARG;
     if (!c->has_rock) return fail(c, CAMS_E_STATE, "build_basis before set_rock");
+    const int kind = c->opt.basis_type;
+    if ((kind == CAMS_BASIS_B1 || kind == CAMS_BASIS_B2) && !c->has_bcoef)
+        return fail(c, CAMS_E_STATE, "pressure-dependent basis (B1/B2): assemble at an iterate first");
     try {
+        if (kind == CAMS_BASIS_B3) launch_basis_coeffs(c, nullptr, nullptr);
         clear_status(c);
         c->learned_blocks = c->fallback_blocks = 0;
         c->block_ratio.clear();
@@ -923,13 +1045,17 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
     try {
         launch_impose_wells(c, p_dev);
         CAMS_HIP(hipGetLastError());
-        if (!c->has_basis) {
+        // B1/B2 depend on the iterate: built after the first assembly and
+        // updated adaptively at every Newton iteration (below)
+        const bool pdep = c->opt.basis_type == CAMS_BASIS_B1 || c->opt.basis_type == CAMS_BASIS_B2;
+        if (!c->has_basis && !pdep) {
             CAMS_HIP(hipEventRecord(c->ev[0], c->stream));
             s = cams_build_basis(c);
             if (s != CAMS_OK) return s;
             CAMS_HIP(hipEventRecord(c->ev[1], c->stream));
             CAMS_HIP(hipEventSynchronize(c->ev[1]));
             st.t_basis_ms = elapsed_ms(c, 0, 1);
+            st.basis_regions_rebuilt = c->region_total;
         }
         st.fallback_blocks = c->fallback_blocks;
         for (int nit = 0;; ++nit) {
@@ -944,6 +1070,23 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
             if (!isfinite(en)) { s = fail(c, CAMS_E_BREAKDOWN, "non-finite nonlinear error"); break; }
             if (en <= c->opt.newton_tol) break;
             if (nit >= c->opt.newton_maxit) { s = fail(c, CAMS_E_NOT_CONVERGED, "Newton iteration limit"); break; }
+            if (pdep) {
+                CAMS_HIP(hipEventRecord(c->ev[0], c->stream));
+                int rebuilt = c->region_total;
+                if (!c->has_basis) {
+                    s = cams_build_basis(c);
+                } else {
+                    rebuilt = update_basis_adaptive(c);
+                    st.basis_updates += 1;
+                    s = check_basis_status(c);
+                }
+                if (s != CAMS_OK) break;
+                CAMS_HIP(hipEventRecord(c->ev[1], c->stream));
+                CAMS_HIP(hipEventSynchronize(c->ev[1]));
+                st.t_basis_ms += elapsed_ms(c, 0, 1);
+                st.basis_regions_rebuilt += rebuilt;
+                c->has_coarse = false;
+            }
             s = cams_coarse_op(c);
             if (s != CAMS_OK) break;
             if (c->hist) c->hist->nu = nit;
@@ -967,6 +1110,21 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
     c->last = st;
     if (stats) *stats = st;
     return s;
+}
+
+cams_status cams_set_face_dirichlet(cams_ctx *c, int32_t face, double pressure)
+{
+    if (!c) return CAMS_E_ARG;
+    if (face != 0 && face != 1) return fail(c, CAMS_E_ARG, "face must be 0 (west, x = 0) or 1 (east)");
+    if (isnan(pressure)) {
+        c->bc.on[face] = 0;
+    } else {
+        if (!isfinite(pressure)) return fail(c, CAMS_E_ARG, "face pressure must be finite (NaN removes it)");
+        c->bc.on[face] = 1;
+        c->bc.p[face] = pressure;
+    }
+    c->has_system = c->has_coarse = false;
+    return CAMS_OK;
 }
 
 cams_status cams_conservative_sweep(cams_ctx *c, const double *pn_dev, double *p_dev, double *flux_dev)
@@ -1174,6 +1332,7 @@ cams_status cams_set_learned(cams_ctx *c, const float *params, void *scratch, si
     }
     if (c->g.dim != 3 || c->g.r[0] != 8 || c->g.r[1] != 8 || c->g.r[2] != 8)
         return fail(c, CAMS_E_ARG, "the learned basis needs coarsening ratio 8 on a 3D grid");
+    if (c->opt.basis_type != CAMS_BASIS_B4) return fail(c, CAMS_E_ARG, "the learned basis predicts B4 bases only");
     if (!scratch || ((uintptr_t)scratch) % kAlign || bytes < learned_scratch_need(c) || !(fallback_tol > 0))
         return fail(c, CAMS_E_ARG, "learned basis: scratch missing, misaligned or too small, or bad tolerance");
     c->learned_params = params;

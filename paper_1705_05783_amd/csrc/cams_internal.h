@@ -37,6 +37,13 @@ struct Fluid {
     double rho0, c, p0, mu, dt;
 };
 
+// Dirichlet boundary faces (fixed pressure on the west face x = 0 and / or
+// the east face x = nx - 1), passed by value to the residual kernels.
+struct FaceBC {
+    double p[2];
+    int on[2];
+};
+
 // One dual region (edge segment, face patch or interior box): per axis the
 // first cell and the number of cells; `nfree` axes are open intervals.
 struct Region {
@@ -72,6 +79,13 @@ struct Arrays {
     double *wp;
     int32_t *tab;     // per-axis tables
     Region *regions;  // dual regions of all stages
+    // basis types B1-B3: couplings and extra diagonal of the local problems,
+    // their snapshot at each region's last solve, per-region change flags and
+    // the list of regions to re-solve (B1/B2 adaptive updates)
+    double *bcoef, *bdiag, *bsnap, *bdsnap;
+    double *Tb;       // 2 ny nz: half-cell transmissibilities of the west and east boundary faces
+    int32_t *rflag;
+    Region *rlist;
     // mixed precision copies
     float *W32, *diag32, *invd32, *P32;
     uint16_t *Pbf;
@@ -207,7 +221,13 @@ struct cams_ctx {
     int prof_iter;                          // iteration index being enqueued
     double prof_ms, prof_bytes;
     long long prof_launches;
-    size_t off[48];         // workspace offsets (kMaxArrays entries)
+    size_t off[64];         // workspace offsets (kMaxArrays entries)
+    // pressure-dependent bases (B1/B2): coefficients assembled for the current
+    // iterate, and for each region the regions that take its values as
+    // boundary data (CSR over the region order of `regions`)
+    bool has_bcoef;
+    cams::FaceBC bc;        // Dirichlet boundary faces (cams_set_face_dirichlet)
+    std::vector<int32_t> dep_ptr, dep_idx;
 };
 
 namespace cams {
@@ -221,6 +241,12 @@ void launch_reduce(cams_ctx *c, const double *partial, int n, double *out);
 // ||eps||^2 (Eq. (16)) at x = p + dp (dp nullable) into *out, without
 // touching the assembled system; partials in Arrays::partial.
 void launch_eps_at(cams_ctx *c, const double *p, const double *dp, const double *pn, double *out);
+// Basis types B1-B3 (Sec. 3): local-problem coefficients at the iterate p
+// (B1/B2) or from the rock (B3); per-region coefficient change against the
+// snapshot (flags of regions [first, first + count)); snapshot of listed regions.
+void launch_basis_coeffs(cams_ctx *c, const double *p, const double *pn);
+void launch_region_change(cams_ctx *c, int first, int count, double tol);
+void launch_region_snapshot(cams_ctx *c, const Region *regs, int count);
 // Two-point mass fluxes (3N, on the lower cell of each face) of the system
 // assembled at p, at the pressure p + d.
 void launch_face_flux(cams_ctx *c, const double *p, const double *d, double *flux);

@@ -46,6 +46,7 @@ __device__ __forceinline__ double lane_bcast(double v, int lane)
 // LDS of `cap` doubles (sized by the host for the largest region of the stage).
 template <int NT>
 __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__restrict__ T,
+                                                      const double *__restrict__ adiag,
                                                       const Region *__restrict__ regs, double *__restrict__ P,
                                                       int32_t *status, int cap)
 {
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
                 }
             }
         }
-        L[c * ld] = dsum;
+        L[c * ld] = adiag ? dsum + adiag[n] : dsum;   // B1 / B3: accumulation term on the diagonal
     }
     __syncthreads();
 
@@ -218,7 +219,136 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
     }
 }
 
+// Couplings and extra diagonal of the local problems of the basis types
+// other than B4: B1/B2 couplings T (rho_i + rho_j)/2 at the iterate p (no
+// Dirichlet masking); B1 diagonal phi c rho(p^n) dV / dt, B3 phi c dV / dt.
+__global__ __launch_bounds__(kBlock) void k_basis_coeffs(GridDev g, Fluid f, const double *__restrict__ T,
+                                                          const double *__restrict__ phi,
+                                                          const double *__restrict__ p,
+                                                          const double *__restrict__ pn, int kind,
+                                                          double *__restrict__ C, double *__restrict__ A)
+{
+    const int n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= g.N) return;
+    if (kind == CAMS_BASIS_B1 || kind == CAMS_BASIS_B2) {
+        const Cell c = cell_of(g, n);
+        const double rho = f.rho0 * exp(f.c * (p[n] - f.p0));
+        auto w = [&](int m, double t) { return t * 0.5 * (rho + f.rho0 * exp(f.c * (p[m] - f.p0))); };
+        C[n] = c.i + 1 < g.nx ? w(n + 1, T[n]) : 0.0;
+        C[g.N + n] = c.j + 1 < g.ny ? w(n + g.nx, T[g.N + n]) : 0.0;
+        C[2 * (size_t)g.N + n] = c.k + 1 < g.nz ? w(n + g.sxy, T[2 * (size_t)g.N + n]) : 0.0;
+    }
+    if (kind == CAMS_BASIS_B1) A[n] = phi[n] * f.c * f.rho0 * exp(f.c * (pn[n] - f.p0)) * g.dV / f.dt;
+    if (kind == CAMS_BASIS_B3) A[n] = phi[n] * f.c * g.dV / f.dt;
+}
+
+// The coefficients a region's local problem uses: per cell, the faces along
+// its open axes (those to cells of the region and to the higher-level
+// neighbours whose values are its Dirichlet data) and, with an extra
+// diagonal, the cell's own entry.  Each face is used by one region only.
+template <class F>
+__device__ __forceinline__ void region_coeffs(const GridDev &g, const Region &R, int t, F &&fn)
+{
+    const int e0 = R.len[0], e1 = R.len[1];
+    const int x[3] = {R.s[0] + t % e0, R.s[1] + (t / e0) % e1, R.s[2] + t / (e0 * e1)};
+    const int n = x[0] + g.nx * (x[1] + g.ny * x[2]);
+    const int gstride[3] = {1, g.nx, g.sxy};
+    const int ncoord[3] = {g.nx, g.ny, g.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (!(R.freemask & (1 << a))) continue;
+        if (x[a] > 0) fn((size_t)a * g.N + (n - gstride[a]));
+        if (x[a] + 1 < ncoord[a]) fn((size_t)a * g.N + n);
+    }
+    fn((size_t)3 * g.N + n);   // the diagonal entry (index 3N + n)
+}
+
+// Largest relative change of a region's coefficients against the snapshot
+// taken when the region was last solved; flag[r] = 1 when above tol.
+__global__ __launch_bounds__(kBlock) void k_region_change(GridDev g, const double *__restrict__ C,
+                                                           const double *__restrict__ A,
+                                                           const double *__restrict__ Cs,
+                                                           const double *__restrict__ As,
+                                                           const Region *__restrict__ regs, double tol,
+                                                           int32_t *__restrict__ flag)
+{
+    __shared__ double sh[kBlock];
+    const Region R = regs[blockIdx.x];
+    const int m = R.len[0] * R.len[1] * R.len[2];
+    double mx = 0.0;
+    for (int t = threadIdx.x; t < m; t += kBlock)
+        region_coeffs(g, R, t, [&](size_t i) {
+            double v, o;
+            if (i < (size_t)3 * g.N) {
+                v = C[i];
+                o = Cs[i];
+            } else {
+                if (!A) return;
+                v = A[i - (size_t)3 * g.N];
+                o = As[i - (size_t)3 * g.N];
+            }
+            const double d = fabs(v - o);
+            mx = fmax(mx, o != 0.0 ? d / fabs(o) : (d > 0.0 ? 1e300 : 0.0));
+        });
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flag[blockIdx.x] = sh[0] > tol ? 1 : 0;
+}
+
+// Snapshot of the coefficients of the listed (just solved) regions.
+__global__ __launch_bounds__(kBlock) void k_region_snapshot(GridDev g, const double *__restrict__ C,
+                                                             const double *__restrict__ A,
+                                                             double *__restrict__ Cs, double *__restrict__ As,
+                                                             const Region *__restrict__ regs)
+{
+    const Region R = regs[blockIdx.x];
+    const int m = R.len[0] * R.len[1] * R.len[2];
+    for (int t = threadIdx.x; t < m; t += kBlock)
+        region_coeffs(g, R, t, [&](size_t i) {
+            if (i < (size_t)3 * g.N)
+                Cs[i] = C[i];
+            else if (A)
+                As[i - (size_t)3 * g.N] = A[i - (size_t)3 * g.N];
+        });
+}
+
 }  // namespace
+
+// Couplings and extra diagonal of the context's basis type.
+static void basis_operator(const cams_ctx *c, const double *&C, const double *&A)
+{
+    const int kind = c->opt.basis_type;
+    C = (kind == CAMS_BASIS_B1 || kind == CAMS_BASIS_B2) ? c->a.bcoef : c->a.T;
+    A = (kind == CAMS_BASIS_B1 || kind == CAMS_BASIS_B3) ? c->a.bdiag : nullptr;
+}
+
+void launch_basis_coeffs(cams_ctx *c, const double *p, const double *pn)
+{
+    const int kind = c->opt.basis_type;
+    if (kind == CAMS_BASIS_B4) return;
+    k_basis_coeffs<<<(c->g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(
+        c->g, c->fl, c->a.T, c->a.phi, p, pn, kind, c->a.bcoef, c->a.bdiag);
+}
+
+void launch_region_change(cams_ctx *c, int first, int count, double tol)
+{
+    if (count <= 0) return;
+    const double *C, *A;
+    basis_operator(c, C, A);
+    k_region_change<<<count, kBlock, 0, c->stream>>>(c->g, C, A, c->a.bsnap, c->a.bdsnap, c->a.regions + first, tol,
+                                                     c->a.rflag + first);
+}
+
+void launch_region_snapshot(cams_ctx *c, const Region *regs, int count)
+{
+    if (count <= 0) return;
+    const double *C, *A;
+    basis_operator(c, C, A);
+    k_region_snapshot<<<count, kBlock, 0, c->stream>>>(c->g, C, A, c->a.bsnap, c->a.bdsnap, regs);
+}
 
 void launch_basis_vertices(cams_ctx *c)
 {
@@ -234,10 +364,12 @@ void launch_basis_regions(cams_ctx *c, int nfree, const Region *regs, int count)
     const GridDev &g = c->g;
     const int cap = c->maxm[nfree] * (c->maxbw[nfree] + 1 + 8);
     const size_t bytes = (size_t)cap * sizeof(double);
+    const double *C, *A;
+    basis_operator(c, C, A);
     if (nfree == 1)
-        k_basis_region<64><<<count, 64, bytes, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status, cap);
+        k_basis_region<64><<<count, 64, bytes, c->stream>>>(g, C, A, regs, c->a.P, c->a.status, cap);
     else
-        k_basis_region<kBlock><<<count, kBlock, bytes, c->stream>>>(g, c->a.T, regs, c->a.P, c->a.status, cap);
+        k_basis_region<kBlock><<<count, kBlock, bytes, c->stream>>>(g, C, A, regs, c->a.P, c->a.status, cap);
 }
 
 void launch_basis(cams_ctx *c)
@@ -245,6 +377,8 @@ void launch_basis(cams_ctx *c)
     launch_basis_vertices(c);
     for (int nfree = 1; nfree <= c->g.dim; ++nfree)
         launch_basis_regions(c, nfree, c->a.regions + c->regoff[nfree], c->nreg[nfree]);
+    if (c->opt.basis_type == CAMS_BASIS_B1 || c->opt.basis_type == CAMS_BASIS_B2)
+        launch_region_snapshot(c, c->a.regions + c->regoff[1], c->region_total - c->regoff[1]);
 }
 
 }  // namespace cams

@@ -20,7 +20,8 @@ __global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ x, int n, 
 
 // Face conductance of two cells in series: (A/h) * 2 l1 l2 / (l1 + l2).
 __global__ __launch_bounds__(kBlock) void k_transmissibility(GridDev g, const double *__restrict__ perm,
-                                                              double mu, double *__restrict__ T)
+                                                              double mu, double *__restrict__ T,
+                                                              double *__restrict__ Tb)
 {
     int n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= g.N) return;
@@ -42,6 +43,29 @@ __global__ __launch_bounds__(kBlock) void k_transmissibility(GridDev g, const do
     T[n] = tx;
     T[g.N + n] = ty;
     T[2 * g.N + n] = tz;
+    // half-cell transmissibility between the centre and a west / east boundary face
+    const double tb = (g.dy * g.dz / g.dx) * 2.0 * l;
+    if (c.i == 0) Tb[c.j + g.ny * c.k] = tb;
+    if (c.i == g.nx - 1) Tb[(size_t)g.ny * g.nz + c.j + g.ny * c.k] = tb;
+}
+
+// Flux through a Dirichlet boundary face of cell (i, j, k), if it has one:
+// T_b (rho_i + rho(p_b)) / 2 (p_i - p_b); w receives T_b (rho_i + rho(p_b)) / 2.
+__device__ __forceinline__ double boundary_flux(const GridDev &g, const Fluid &f, const FaceBC &bc,
+                                                const double *__restrict__ Tb, const Cell &c, double pi,
+                                                double rho, double &w)
+{
+    w = 0.0;
+    double fl = 0.0;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        if (!bc.on[side] || c.i != (side ? g.nx - 1 : 0)) continue;
+        const double t = Tb[(size_t)side * g.ny * g.nz + c.j + g.ny * c.k];
+        const double ws = t * 0.5 * (rho + f.rho0 * exp(f.c * (bc.p[side] - f.p0)));
+        w += ws;
+        fl += ws * (pi - bc.p[side]);
+    }
+    return fl;
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_rock(int N, const double *__restrict__ perm,
@@ -63,7 +87,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(GridDev g, Fluid f, const d
                                                       const uint8_t *__restrict__ dm, const double *__restrict__ p,
                                                       const double *__restrict__ pn, double *__restrict__ W,
                                                       double *__restrict__ diag, double *__restrict__ r0,
-                                                      double *__restrict__ partial)
+                                                      double *__restrict__ partial, const double *__restrict__ Tb,
+                                                      FaceBC bc)
 {
     __shared__ double sh[kBlock / 64];
     int n = blockIdx.x * kBlock + threadIdx.x;
@@ -89,6 +114,9 @@ __global__ __launch_bounds__(kBlock) void k_assemble(GridDev g, Fluid f, const d
         if (c.j + 1 < g.ny) wy = face(n + g.nx, Ty[n]);
         if (c.k > 0) face(n - g.sxy, Tz[n - g.sxy]);
         if (c.k + 1 < g.nz) wz = face(n + g.sxy, Tz[n]);
+        double wb;
+        flux += boundary_flux(g, f, bc, Tb, c, pi, rho, wb);
+        sumW += wb;
         W[n] = wx;
         W[g.N + n] = wy;
         W[2 * g.N + n] = wz;
@@ -115,7 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_eps_at(GridDev g, Fluid f, const dou
                                                     const double *__restrict__ phi, const double *__restrict__ q,
                                                     const uint8_t *__restrict__ dm, const double *__restrict__ p,
                                                     const double *__restrict__ dp, const double *__restrict__ pn,
-                                                    double *__restrict__ partial)
+                                                    double *__restrict__ partial, const double *__restrict__ Tb,
+                                                    FaceBC bc)
 {
     __shared__ double sh[kBlock / 64];
     int n = blockIdx.x * kBlock + threadIdx.x;
@@ -137,6 +166,8 @@ __global__ __launch_bounds__(kBlock) void k_eps_at(GridDev g, Fluid f, const dou
         if (c.j + 1 < g.ny) face(n + g.nx, Ty[n]);
         if (c.k > 0) face(n - g.sxy, Tz[n - g.sxy]);
         if (c.k + 1 < g.nz) face(n + g.sxy, Tz[n]);
+        double wb;
+        flux += boundary_flux(g, f, bc, Tb, c, xi, rho, wb);
         const double rhon = density(f, pn[n]);
         double F = phi[n] * g.dV * (rho - rhon) / f.dt + flux;
         if (q) F -= rho * q[n] * g.dV;
@@ -383,7 +414,7 @@ void launch_fill(cams_ctx *c, double *x, int n, double v)
 
 void launch_transmissibility(cams_ctx *c, const double *perm)
 {
-    k_transmissibility<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, perm, c->fl.mu, c->a.T);
+    k_transmissibility<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, perm, c->fl.mu, c->a.T, c->a.Tb);
 }
 
 void launch_check_rock(cams_ctx *c, const double *perm, const double *phi)
@@ -395,7 +426,7 @@ void launch_assemble(cams_ctx *c, const double *p, const double *pn)
 {
     k_assemble<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(
         c->g, c->fl, c->a.T, c->a.phi, c->has_q ? c->a.q : nullptr, c->a.dmask, p, pn, c->a.W, c->a.diag,
-        c->a.r0, c->a.partial);
+        c->a.r0, c->a.partial, c->a.Tb, c->bc);
 }
 
 void launch_reduce(cams_ctx *c, const double *partial, int n, double *out)
@@ -412,7 +443,7 @@ void launch_eps_at(cams_ctx *c, const double *p, const double *dp, const double 
 {
     k_eps_at<<<grid_blocks(c->g.N), kBlock, 0, c->stream>>>(c->g, c->fl, c->a.T, c->a.phi,
                                                             c->has_q ? c->a.q : nullptr, c->a.dmask, p, dp, pn,
-                                                            c->a.partial);
+                                                            c->a.partial, c->a.Tb, c->bc);
     launch_reduce(c, c->a.partial, grid_blocks(c->g.N), out);
 }
 

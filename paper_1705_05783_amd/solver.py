@@ -38,7 +38,9 @@ class Solver:
                            overrides.get("lin_maxit", problem.lin_maxit),
                            overrides.get("newton_tol", problem.newton_tol),
                            overrides.get("newton_maxit", problem.newton_maxit),
-                           overrides.get("lin_atol", getattr(problem, "lin_atol", 0.0)))
+                           overrides.get("lin_atol", getattr(problem, "lin_atol", 0.0)),
+                           overrides.get("basis_type", getattr(problem, "basis_type", 0)),
+                           overrides.get("basis_tol", getattr(problem, "basis_tol", 0.0)))
         self.options = o
         h = ctypes.c_void_p()
         C.check(C.cams_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(o),
@@ -59,6 +61,11 @@ class Solver:
             q = torch.as_tensor(np.ascontiguousarray(problem.q, dtype=np.float64), device=self.device)
         self._rock = (perm, phi, q)
         self.reset_rock()
+        for side, face in (("W", 0), ("E", 1)):
+            bc = getattr(problem, "face_bc", None) or {}
+            if side in bc:
+                C.check(C.cams_set_face_dirichlet(self.ctx, face, float(bc[side])), self.ctx,
+                        "cams_set_face_dirichlet")
         cells = np.array([w[0] for w in problem.wells], dtype=np.int64)
         vals = np.array([w[1] for w in problem.wells], dtype=np.float64)
         C.check(C.cams_set_wells(self.ctx, cells.ctypes.data_as(ctypes.c_void_p),

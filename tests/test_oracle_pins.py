@@ -740,3 +740,36 @@ def test_b3_edge_closed_form_and_no_partition_of_unity():
     p = rng.uniform(0, 1, pb.n)
     C2, _ = oracle.basis_operator(pb, T, oracle.B2, p=p, pn=p)
     assert np.allclose(oracle.basis_general(pb, C2).sum(axis=0), 1.0, atol=1e-13)
+
+
+def test_newton_step_basis_b4_equals_c_newton():
+    """The Python Newton loop with a basis type (used for B1-B3) reduces to
+    the C Newton step for B4 (same iterates, same count)."""
+    pb = small_problem(16, 12, 8, 4, seed=8, sigma=2.0, c=0.1)
+    T = oracle.transmissibility(pb)
+    p0 = pb.initial_pressure()
+    p1, nit, lits = oracle.newton_step_basis(pb, T, p0, p0, oracle.B4, 1e-10, 1e-9)
+    p2, rc, st = oracle.newton_step(pb, T, oracle.basis_b4(pb, T), p0, p0, lin_rtol=1e-10, newton_tol=1e-9)
+    assert rc == 0 and nit == st["newton_iters"] and lits == st["lin_iters"]
+    assert np.array_equal(p1, p2)
+
+
+@pytest.mark.parametrize("layered", [False, True])
+def test_face_dirichlet_series_profile(layered):
+    """Pressure fixed on the west (1) and east (0) faces, no flow elsewhere,
+    incompressible (c = 0), no wells: steady 1D flow along x.  With the
+    half-cell transmissibility 2 k / dx between a cell centre and a boundary
+    face, the two-point scheme reproduces the series-resistance profile
+    exactly: flux q = 1 / sum_i dx / k_i, and p at cell i = 1 - q (sum_{j<i}
+    dx / k_j + dx / (2 k_i)) (homogeneous: 1 - (i + 1/2) / nx)."""
+    nx, ny, nz = 12, 3, 2
+    pb = small_problem(nx, ny, nz, (4, 3, 2), seed=1, c=0.0, wells="none")
+    kx = np.linspace(0.5, 3.0, nx) ** 2 if layered else np.ones(nx)
+    pb.perm = np.tile(kx, ny * nz)
+    pb.face_bc = {"W": 1.0, "E": 0.0}
+    T = oracle.transmissibility(pb)
+    p, _ = helpers.direct_newton(pb, T, np.zeros(pb.n), np.zeros(pb.n), tol=1e-13)
+    R = 1.0 / kx                        # dx = 1
+    q = 1.0 / R.sum()
+    ref = 1.0 - q * (np.concatenate([[0.0], np.cumsum(R)[:-1]]) + 0.5 * R)
+    assert np.allclose(p.reshape(nz, ny, nx), ref[None, None, :], rtol=0, atol=1e-12)

@@ -57,6 +57,7 @@ class Problem:
     mu: float = 1.0
     dt: float = 0.1
     q: Optional[np.ndarray] = None  # (N,) source per unit volume, or None
+    face_bc: Optional[dict] = None  # Dirichlet boundary faces {"W": p, "E": p} (x = 0 / x = nx-1 faces)
     n_steps: int = 1
     restriction: int = FE
     n_pre: int = 0
@@ -68,6 +69,8 @@ class Problem:
     newton_maxit: int = 30
     precision: int = FP64
     smoother: int = SMOOTH_BLOCK_ALT
+    basis_type: int = 0             # 0 = B4, 1 = B1, 2 = B2, 3 = B3 (Sec. 3)
+    basis_tol: float = 0.0          # B1/B2 adaptive update threshold (0: rebuild every Newton iteration)
 
     @property
     def n(self) -> int:
@@ -150,6 +153,38 @@ def config5_eval(precision: int = MIXED_FP32) -> Problem:
     return Problem("config5_eval_128^3", n, n, n, 8, 8, 8, perm, phi, wells,
                    c=0.1, dt=0.1, n_steps=1, restriction=FE, n_pre=0, n_post=5,
                    precision=precision)
+
+
+def stretched_problem(alpha: float, seed: int = 8, n: int = 64, precision: int = FP64) -> Problem:
+    """Test case 2 of Sec. 4.2 on a synthetic field: 64^3 cells of aspect
+    ratio dx / alpha = dy = dz = 1, ln k lognormal sigma 2 (variance 4, the
+    paper's permeability set 1) with correlation length 8 cells, Dirichlet
+    line sources along the vertical columns (0, 0, :) p = 1 and
+    (63, 63, :) p = 0; coarsening 8x8x8 for alpha = 1 and 2x8x8 for the
+    stretched grids (the paper's choice); c = 0.1, porosity 0.2, dt = 0.1,
+    one time step, MSFE."""
+    perm = lognormal_permeability((n, n, n), 0.0, 2.0, 8.0, seed=seed).reshape(-1)
+    r = (8, 8, 8) if alpha == 1 else (2, 8, 8)
+    wells = _column_wells(n, n, n, [((0, 0), 1.0), ((n - 1, n - 1), 0.0)])
+    return Problem(f"stretched_alpha{alpha:g}_{n}^3", n, n, n, *r, perm, np.full(n ** 3, 0.2), wells,
+                   dx=float(alpha), c=0.1, dt=0.1, n_steps=1, restriction=FE, n_pre=0, n_post=5,
+                   precision=precision)
+
+
+def variance_problem(sigma: float, seed: int, layered: bool = False, n: int = 64, restriction: int = FE,
+                     precision: int = FP64) -> Problem:
+    """Test case 3 of Sec. 4.2 on synthetic fields: 64^3, ln k lognormal with
+    standard deviation sigma (2, 4 or 8), patchy (correlation length 8
+    cells) or layered (16 x 16 cells in x-y, 1 cell in z); the default
+    boundary conditions of the paper's test cases: pressure 1 on the west
+    face, 0 on the east face, no flow elsewhere, no wells; coarsening 8^3,
+    c = 0.1, porosity 0.2, dt = 0.1, one time step."""
+    corr = (1.0, 16.0, 16.0) if layered else 8.0
+    perm = lognormal_permeability((n, n, n), 0.0, sigma, corr, seed=seed).reshape(-1)
+    kind = "layered" if layered else "patchy"
+    return Problem(f"variance_{kind}_sigma{sigma:g}_s{seed}", n, n, n, 8, 8, 8, perm, np.full(n ** 3, 0.2), [],
+                   c=0.1, dt=0.1, n_steps=1, restriction=restriction, n_pre=0, n_post=5, precision=precision,
+                   face_bc={"W": 1.0, "E": 0.0})
 
 
 def small_problem(nx, ny, nz, r, seed=7, sigma=1.5, corr=3.0, c=0.1, dt=0.1,
