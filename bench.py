@@ -65,7 +65,7 @@ def run_pass(solver, pb):
     pn = solver.new_pressure()
     p = pn.clone()
     out = {"solves": 0, "iters": 0, "t_iterate_ms": 0.0, "t_basis_ms": 0.0, "t_coarse_ms": 0.0,
-           "t_assemble_ms": 0.0, "fallback_blocks": 0}
+           "t_assemble_ms": 0.0, "fallback_blocks": 0, "coarse_factorizations": 0}
     for _ in range(pb.n_steps):
         st = solver.newton_step(pn, p)
         out["solves"] += st["newton_iters"]
@@ -73,6 +73,7 @@ def run_pass(solver, pb):
         for k in ("t_iterate_ms", "t_basis_ms", "t_coarse_ms", "t_assemble_ms"):
             out[k] += st[k]
         out["fallback_blocks"] = max(out["fallback_blocks"], st["fallback_blocks"])
+        out["coarse_factorizations"] += st["coarse_factorizations"]
         pn.copy_(p)
     return out
 
@@ -109,7 +110,8 @@ def timed_passes(solver, pb, steps, warmup, torch):
             "basis_ms_median": float(np.median([s["t_basis_ms"] for s in stats])),
             "coarse_ms_per_solve_median": float(np.median([s["t_coarse_ms"] / max(s["solves"], 1)
                                                           for s in stats])),
-            "fallback_blocks": stats[0]["fallback_blocks"], "prof": prof}
+            "fallback_blocks": stats[0]["fallback_blocks"],
+            "coarse_factorizations_per_pass": stats[0]["coarse_factorizations"], "prof": prof}
 
 
 def measured_traffic(workload):
@@ -192,6 +194,29 @@ def adaptive_run(steps, warmup, torch):
         out[label] = r
         solver.close()
     out["speedup_adaptive"] = out["linear_1e-8"]["s_per_time_step"] / out["adaptive_1e-1"]["s_per_time_step"]
+    return out
+
+
+def coarse_reuse_run(steps, warmup, torch):
+    """Adaptive coarse factorisation (coarse_tol 0.05: the inverse is kept
+    while R A P_hat stays within 5 % of the factorised operator) against
+    factorising at every Newton iteration, on the 128^3 learned+mixed
+    workload and on the 256x256x128 channelised one."""
+    from paper_1705_05783_amd.solver import Solver
+    from paper_1705_05783_amd.train_basis import load_fallback_tol, load_weights
+    from workloads.configs import MIXED_FP32, config4, config5_eval
+    out = {"coarse_tol": 0.05}
+    params = load_weights()
+    for name, make in (("128^3_learned_mixed", lambda: config5_eval(precision=MIXED_FP32)),
+                       ("256x256x128_channelised", config4)):
+        pb = make().with_options(coarse_tol=0.05)
+        solver = Solver(pb)
+        if name.startswith("128"):
+            solver.set_learned(params, fallback_tol=load_fallback_tol())
+        r = timed_passes(solver, pb, steps, warmup, torch)
+        r.pop("prof")
+        out[name] = r
+        solver.close()
     return out
 
 
@@ -361,7 +386,7 @@ def main():
     ap.add_argument("--steps", type=int, default=7, help="timed passes per workload (median reported)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed passes per workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["headline", "adaptive", "small", "large", "batch", "copy", "all"],
+    ap.add_argument("--only", choices=["headline", "adaptive", "coarse", "small", "large", "batch", "copy", "all"],
                     default="all",
                     help="headline/small/large/batch: that workload alone (one JSON object, for profiling); "
                          "copy: a 256 MiB device copy, the reference kernel for scaling memory counters")
@@ -381,8 +406,8 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copies": 3}), flush=True)
         return
     steps, warmup = max(1, args.steps), max(0, args.warmup)
-    if args.only in ("adaptive", "small", "large", "batch"):
-        fn = {"adaptive": adaptive_run, "small": small_run, "large": large_run,
+    if args.only in ("adaptive", "coarse", "small", "large", "batch"):
+        fn = {"adaptive": adaptive_run, "coarse": coarse_reuse_run, "small": small_run, "large": large_run,
               "batch": lambda s, w, t: batch_run(s, w, t, False)}
         print(json.dumps({args.only: fn[args.only](steps, warmup, torch)}), flush=True)
         return
@@ -423,6 +448,7 @@ def main():
         out[k] = head[k]
     if args.only == "all":
         out["adaptive_newton"] = adaptive_run(steps, warmup, torch)
+        out["adaptive_coarse"] = coarse_reuse_run(steps, warmup, torch)
         out["small"] = small_run(steps, warmup, torch)
         out["large"] = large_run(steps, warmup, torch)
         out["batch"] = batch_run(steps, warmup, torch)

@@ -125,6 +125,10 @@ typedef struct {
                                  its local problem changed by more than this (relative) since it was
                                  last solved, and so is every region that takes it as boundary data;
                                  0 = every region at every Newton iteration */
+    double coarse_tol;        /* adaptive coarse factorisation: cams_coarse_op keeps the last inverse
+                                 while no entry of R A P_hat changed by more than this (relative) since
+                                 it was factorised; 0 (default) = factorise at every call, as Table
+                                 "cams" updates the system at every Newton iteration */
 } cams_options;
 
 typedef struct {
@@ -140,6 +144,8 @@ typedef struct {
     double t_iterate_ms;
     int32_t basis_updates;          /* B1/B2: adaptive basis updates in the last cams_newton_step */
     int32_t basis_regions_rebuilt;  /* dual regions solved by the basis builds and updates of that step */
+    int32_t coarse_factorizations;  /* coarse inverses computed in that step (< newton_iters with coarse_tol) */
+    int32_t reserved;
 } cams_stats;
 
 /* Create a context for one grid.  Validates grid/fluid/options: active axes

@@ -62,7 +62,8 @@ class cams_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("smoother", ctypes.c_int32),
                 ("lin_rtol", ctypes.c_double), ("lin_maxit", ctypes.c_int32),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
-                ("lin_atol", ctypes.c_double), ("basis_type", ctypes.c_int32), ("basis_tol", ctypes.c_double)]
+                ("lin_atol", ctypes.c_double), ("basis_type", ctypes.c_int32), ("basis_tol", ctypes.c_double),
+                ("coarse_tol", ctypes.c_double)]
 
 
 class cams_stats(ctypes.Structure):
@@ -71,10 +72,11 @@ class cams_stats(ctypes.Structure):
                 ("relres_last", ctypes.c_double), ("eps_norm_last", ctypes.c_double),
                 ("t_assemble_ms", ctypes.c_double), ("t_basis_ms", ctypes.c_double),
                 ("t_coarse_ms", ctypes.c_double), ("t_iterate_ms", ctypes.c_double),
-                ("basis_updates", ctypes.c_int32), ("basis_regions_rebuilt", ctypes.c_int32)]
+                ("basis_updates", ctypes.c_int32), ("basis_regions_rebuilt", ctypes.c_int32),
+                ("coarse_factorizations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 # (name, restype, argtypes) for every entry point declared in include/cams.h

@@ -271,6 +271,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
     if (!(O.lin_atol >= 0) || !isfinite(O.lin_atol)) return CAMS_E_ARG;
     if (O.basis_type < CAMS_BASIS_B4 || O.basis_type > CAMS_BASIS_B3 || !(O.basis_tol >= 0)) return CAMS_E_ARG;
+    if (!(O.coarse_tol >= 0)) return CAMS_E_ARG;
     const int nb[3] = {num_blocks(n[0], r[0]), num_blocks(n[1], r[1]), num_blocks(n[2], r[2])};
     const double Nc = (double)nb[0] * nb[1] * nb[2];
     if (Nc > 32768) return CAMS_E_ARG;  // dense coarse operator limit
@@ -487,6 +488,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
         put(L.add(pdep ? nreg * sizeof(Region) : 0));   // 51 rlist
     }
     put(L.add((size_t)2 * G.ny * G.nz * 8));   // 52 Tb: west and east boundary-face transmissibilities
+    put(L.add(O.coarse_tol > 0 ? nc * 27 * 8 : 0));   // 53 Acs: coarse operator at its last factorisation
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
         return CAMS_E_NOMEM;
@@ -564,6 +566,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.rflag = (int32_t *)(w + off[50]);
     a.rlist = (Region *)(w + off[51]);
     a.Tb = (double *)(w + off[52]);
+    a.Acs = (double *)(w + off[53]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -613,7 +616,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     c->ws = w;
     c->ws_bytes = bytes;
     c->has_ws = true;
-    c->has_rock = c->has_basis = c->has_system = c->has_coarse = c->has_bcoef = false;
+    c->has_rock = c->has_basis = c->has_system = c->has_coarse = c->has_bcoef = c->has_cfac = false;
     c->ac_zeroed = false;
     c->gj_ready = false;
     c->nwells = 0;
@@ -827,7 +830,7 @@ cams_status cams_build_basis(cams_ctx *c)
         return fail(c, CAMS_E_DEVICE, std::string("build_basis: ") + hipGetErrorString(e.code));
     }
     c->has_basis = true;
-    c->has_coarse = false;
+    c->has_coarse = c->has_cfac = false;
     return CAMS_OK;
 }
 
@@ -838,11 +841,28 @@ cams_status cams_coarse_op(cams_ctx *c)
     if (!c->has_system) return fail(c, CAMS_E_STATE, "coarse_op before assemble");
     try {
         clear_status(c);
-        enqueue_coarse(c);
+        enqueue_coarse_operator(c);
+        // adaptive coarse factorisation: keep the last inverse while the
+        // operator's entries stay within coarse_tol of the factorised ones
+        bool factor = true;
+        if (c->opt.coarse_tol > 0 && c->has_cfac) {
+            launch_coarse_change(c, false);
+            const double chg = read_scalar(c, c->a.scal + S_CCHG);
+            factor = !(chg <= c->opt.coarse_tol);
+        }
+        if (factor) {
+            launch_coarse_factor(c);
+            if (c->opt.coarse_tol > 0) launch_coarse_change(c, true);
+            c->has_cfac = true;
+            ++c->n_factor;
+        }
         CAMS_HIP(hipGetLastError());
         int32_t flags = 0;
         sync_status(c, &flags);
-        if (flags & F_SINGULAR_COARSE) return fail(c, CAMS_E_BREAKDOWN, "singular coarse operator");
+        if (flags & F_SINGULAR_COARSE) {
+            c->has_cfac = false;
+            return fail(c, CAMS_E_BREAKDOWN, "singular coarse operator");
+        }
         if (flags & F_BAD_PIVOT) return fail(c, CAMS_E_BREAKDOWN, "non-positive ILU(0) pivot");
     } catch (const HipError &e) {
         return fail(c, CAMS_E_DEVICE, std::string("coarse_op: ") + hipGetErrorString(e.code));
@@ -1042,6 +1062,7 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
     cams_stats st;
     memset(&st, 0, sizeof(st));
     cams_status s = CAMS_OK;
+    c->n_factor = 0;
     try {
         launch_impose_wells(c, p_dev);
         CAMS_HIP(hipGetLastError());
@@ -1107,6 +1128,7 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
     } catch (const HipError &e) {
         s = fail(c, CAMS_E_DEVICE, std::string("newton_step: ") + hipGetErrorString(e.code));
     }
+    st.coarse_factorizations = c->n_factor;
     c->last = st;
     if (stats) *stats = st;
     return s;
@@ -1167,7 +1189,7 @@ cams_status cams_conservative_sweep(cams_ctx *c, const double *pn_dev, double *p
         return fail(c, CAMS_E_DEVICE, std::string("conservative_sweep: ") + hipGetErrorString(e.code));
     }
     // the coarse factor now holds the MSFV inverse, and p has moved
-    c->has_coarse = c->has_system = false;
+    c->has_coarse = c->has_system = c->has_cfac = false;
     return CAMS_OK;
 }
 

@@ -554,7 +554,12 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
         else if (r.status) s = CAMS_E_BREAKDOWN;
         else if (r.outcome == 1) s = CAMS_E_NOT_CONVERGED;
         else if (r.outcome == 2) s = CAMS_E_BREAKDOWN;
-        c->has_basis = c->has_system = c->has_coarse = true;
+        c->has_basis = c->has_system = true;
+        // the batch leaves a dense inverse in Ainv; a context whose own
+        // coarse solve is the block-tridiagonal form must factorise again
+        // before cams_iterate (it would read Ainv as plane blocks)
+        c->has_coarse = !c->blocktri;
+        c->has_cfac = false;   // Ainv was overwritten by the batch's own inverse
         cams_stats st;
         memset(&st, 0, sizeof(st));
         st.newton_iters = 1;

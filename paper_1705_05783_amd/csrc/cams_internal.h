@@ -84,6 +84,7 @@ struct Arrays {
     // the list of regions to re-solve (B1/B2 adaptive updates)
     double *bcoef, *bdiag, *bsnap, *bdsnap;
     double *Tb;       // 2 ny nz: half-cell transmissibilities of the west and east boundary faces
+    double *Acs;      // 27 Nc: the coarse operator's 27-point entries when it was last factorised
     int32_t *rflag;
     Region *rlist;
     // mixed precision copies
@@ -150,7 +151,7 @@ struct BatchResult {
 enum { C_IT = 0, C_DONE = 1, C_OUTCOME = 2, C_ARRIVE = 3, C_NODE = 4 };
 
 // Scalar slots in Arrays::scal.
-enum { S_EPS2 = 0, S_R0N2 = 1, S_RN2 = 2, S_ATOL2 = 3, S_EPSH = 4 };
+enum { S_EPS2 = 0, S_R0N2 = 1, S_RN2 = 2, S_ATOL2 = 3, S_EPSH = 4, S_CCHG = 5 };
 
 // Device status flags (bitwise OR).
 enum { F_BAD_PIVOT = 1, F_BAD_INPUT = 2, F_SINGULAR_COARSE = 4 };
@@ -227,6 +228,8 @@ struct cams_ctx {
     // boundary data (CSR over the region order of `regions`)
     bool has_bcoef;
     cams::FaceBC bc;        // Dirichlet boundary faces (cams_set_face_dirichlet)
+    bool has_cfac;          // Ainv holds a factorisation of the operator snapshotted in Acs
+    int n_factor;           // coarse factorisations since the last reset of the counter
     std::vector<int32_t> dep_ptr, dep_idx;
 };
 
@@ -253,6 +256,9 @@ void launch_face_flux(cams_ctx *c, const double *p, const double *d, double *flu
 // Zero the coarse operator once per workspace (entries outside the 27-point
 // pattern stay zero afterwards).
 void launch_zero_coarse(cams_ctx *c);
+// Largest relative change of the coarse operator's 27-point entries since
+// the snapshot (into scal[S_CCHG]), or (snap) take the snapshot.
+void launch_coarse_change(cams_ctx *c, bool snap);
 void launch_impose_wells(cams_ctx *c, double *p);
 void launch_stencil_sub(cams_ctx *c, const double *b, const double *x, double *out, const int32_t *done);
 void launch_prolong(cams_ctx *c, const double *xc, double *out, const int32_t *done);

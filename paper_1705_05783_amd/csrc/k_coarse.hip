@@ -203,6 +203,55 @@ __global__ __launch_bounds__(kBlock) void k_coarse_nodes(GridDev g, const double
     Ac[(size_t)I * g.Nc + (ja + g.nb[0] * (jb + g.nb[1] * jc))] = sum;
 }
 
+// Coarse-operator change since the last factorisation: entry t = 27 I + d of
+// the 27-point pattern (node I, neighbour offset d) against the snapshot;
+// per-workgroup maxima of the relative change, or (snap) the snapshot itself.
+__global__ __launch_bounds__(kBlock) void k_coarse_change(GridDev g, const double *__restrict__ Ac,
+                                                           double *__restrict__ Acs, int snap,
+                                                           double *__restrict__ partial)
+{
+    __shared__ double sh[kBlock];
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    double rel = 0.0;
+    if (t < 27 * g.Nc) {
+        const int I = t / 27, d = t % 27;
+        const int ia = I % g.nb[0], ib = (I / g.nb[0]) % g.nb[1], ic = I / (g.nb[0] * g.nb[1]);
+        const int ja = ia + d % 3 - 1, jb = ib + (d / 3) % 3 - 1, jc = ic + d / 9 - 1;
+        double v = 0.0;
+        if (ja >= 0 && ja < g.nb[0] && jb >= 0 && jb < g.nb[1] && jc >= 0 && jc < g.nb[2])
+            v = Ac[(size_t)I * g.Nc + (ja + g.nb[0] * (jb + g.nb[1] * jc))];
+        if (snap) {
+            Acs[t] = v;
+        } else {
+            const double o = Acs[t], dv = fabs(v - o);
+            rel = o != 0.0 ? dv / fabs(o) : (dv > 0.0 ? 1e300 : 0.0);
+        }
+    }
+    if (snap) return;
+    sh[threadIdx.x] = rel;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_reduce(const double *__restrict__ partial, int n,
+                                                        double *__restrict__ out)
+{
+    __shared__ double sh[kBlock];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < n; t += kBlock) m = fmax(m, partial[t]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
 // Cell range of coarse row k along one axis.
 __device__ __forceinline__ void row_range(const GridDev &g, int axis, int a, int fe, int &lo, int &hi)
 {
@@ -1187,6 +1236,13 @@ void launch_zero_coarse(cams_ctx *c)
         k_zero<<<cdiv((size_t)n * n, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, (size_t)n * n);
         c->ac_zeroed = true;
     }
+}
+
+void launch_coarse_change(cams_ctx *c, bool snap)
+{
+    const int n = 27 * c->g.Nc, nb = (int)cdiv(n, kBlock);
+    k_coarse_change<<<nb, kBlock, 0, c->stream>>>(c->g, c->a.Ac, c->a.Acs, snap ? 1 : 0, c->a.partial);
+    if (!snap) k_max_reduce<<<1, kBlock, 0, c->stream>>>(c->a.partial, nb, c->a.scal + S_CCHG);
 }
 
 void launch_coarse_operator(cams_ctx *c)

@@ -174,6 +174,17 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Synchronisation of the threads that share one block: the workgroup, or
+// one wave when every wave of the workgroup has a block of its own (NT = 64).
+template <int NT>
+__device__ __forceinline__ void team_sync()
+{
+    if constexpr (NT == 64)
+        wave_sync();
+    else
+        __syncthreads();
+}
+
 // Value of v in lane `src` of the wave.
 template <class T>
 __device__ __forceinline__ T lane_value(T v, int src)
@@ -194,12 +205,11 @@ __device__ __forceinline__ T lane_value(T v, int src)
 // Coefficients are loaded in batches of CH levels (all 22 in FP32, 11 in
 // FP64 to bound the register count); inactive lanes keep their running value
 // and store into the upper zero pad, which nothing reads here.
-template <class T>
-__device__ __forceinline__ void sweep_registers(SmoothLds<T> &L, int ex, int ey, int ez)
+template <class T, int CHF = 0>
+__device__ __forceinline__ void sweep_registers(SmoothLds<T> &L, int ex, int ey, int ez, int lane)
 {
     constexpr int NL = 3 * SB - 2;
-    constexpr int CH = sizeof(T) == 4 ? NL : NL / 2;
-    const int lane = threadIdx.x;
+    constexpr int CH = CHF > 0 ? CHF : (sizeof(T) == 4 ? NL : NL / 2);
     const int pj = lane & (SB - 1), pk = lane >> 3;
     const bool pencil = pj < ey && pk < ez;
     const int base = PAD + SB * pj + SB * SB * pk, s0 = pj + pk;
@@ -314,13 +324,13 @@ struct CubeLoads {
 
 template <class T, class TP, int NT>
 __device__ __forceinline__ void cube_load(const GridDev &g, const FromCoarse<T, TP> &fc, int i0, int j0, int k0,
-                                          int ex, int ey, int ez, CubeLoads<TP, NT> &cl)
+                                          int ex, int ey, int ez, CubeLoads<TP, NT> &cl, int tid)
 {
 #pragma unroll
     for (int h = 0; h < CubeLoads<TP, NT>::R; ++h) {
         int ci, cj, ck;
         bool need;
-        cube_slot<NT>(threadIdx.x + h * NT, ex, ey, ez, ci, cj, ck, need);
+        cube_slot<NT>(tid + h * NT, ex, ey, ez, ci, cj, ck, need);
         const int i = i0 + ci, j = j0 + cj, k = k0 + ck;
         const bool in = need && i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz;
         const int ii = in ? i : i0, jj = in ? j : j0, kk = in ? k : k0;
@@ -344,18 +354,18 @@ __device__ __forceinline__ void cube_fill(const GridDev &g, const FromCoarse<T, 
 
 // `o`: offsets of the block grid (the prolongating first step takes the
 // grid at the origin only).  i0, j0, k0 are positions on the shifted axes.
-template <class T, class TR, int NT, int SW = 0, class TP = void>
+template <class T, class TR, int NT, int SW = 0, class TP = void, int CHF = 0>
 __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
                                                const T *__restrict__ invd, const TR *__restrict__ rhs,
                                                const T *__restrict__ eold, T *__restrict__ enew, int blk,
-                                               SmoothLds<T> &L, Shift o, FromCoarse<T, TP> fc = {})
+                                               SmoothLds<T> &L, Shift o, FromCoarse<T, TP> fc, int tid)
 {
     constexpr int CPT = ST / NT;   // cells per thread
     const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
     const int i0 = (blk % nbx) * SB, j0 = ((blk / nbx) % nby) * SB, k0 = (blk / (nbx * nby)) * SB;
     const int ex = min(SB, g.nx - i0), ey = min(SB, g.ny - j0), ez = min(SB, g.nz - k0);
     const T *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
-    for (int q = threadIdx.x; q < 2 * PAD; q += NT) {
+    for (int q = tid; q < 2 * PAD; q += NT) {
         const int idx = q < PAD ? q : ST + q;
         L.y[idx] = 0;
         L.wx[idx] = 0;
@@ -375,7 +385,7 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         bool av[CPT];
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int t = threadIdx.x + NT * c;
+            const int t = tid + NT * c;
             const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
             const bool act = li < ex && lj < ey && lk < ez;
             const int ai = act ? li : 0, aj = act ? lj : 0, ak = act ? lk : 0;
@@ -399,28 +409,28 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         // every global load of the step goes out here: the prolongation's
         // tables and basis values, and the coarse vector (into LDS when it fits)
         CubeLoads<TP, NT> cl;
-        cube_load<T, TP, NT>(g, fc, i0, j0, k0, ex, ey, ez, cl);
+        cube_load<T, TP, NT>(g, fc, i0, j0, k0, ex, ey, ez, cl, tid);
         const bool xlds = g.Nc <= kXcLds;
         if (xlds) {
             constexpr int XR = (kXcLds + NT - 1) / NT;
             double xv[XR];
 #pragma unroll
             for (int h = 0; h < XR; ++h) {
-                const int q = threadIdx.x + h * NT;
+                const int q = tid + h * NT;
                 xv[h] = q < g.Nc ? fc.xc[q] : 0.0;
             }
 #pragma unroll
             for (int h = 0; h < XR; ++h) {
-                const int q = threadIdx.x + h * NT;
+                const int q = tid + h * NT;
                 if (q < g.Nc) fc.xs[q] = xv[h];
             }
-            __syncthreads();
+            team_sync<NT>();
         }
         cube_fill<T, TP, NT>(g, fc, cl, xlds ? fc.xs : fc.xc);
-        __syncthreads();
+        team_sync<NT>();
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int t = threadIdx.x + NT * c;
+            const int t = tid + NT * c;
             const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
             const T *cb = fc.cube + qc[c];
             const T ec = cb[0];
@@ -442,7 +452,7 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
     } else {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const int t = threadIdx.x + NT * c;
+        const int t = tid + NT * c;
         const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
         const bool act = li < ex && lj < ey && lk < ez;
         const int i = wrap_cell(i0 + (act ? li : 0), o.x, g.nx), j = wrap_cell(j0 + (act ? lj : 0), o.y, g.ny);
@@ -481,14 +491,14 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
         L.wz[PAD + t] = act && lk + 1 < ez ? fzp : T(0);
     }
     }
-    __syncthreads();
-    if (SW == 1 && threadIdx.x < 64) {
-        sweep_registers<T>(L, ex, ey, ez);
-    } else if (SW == 0 && threadIdx.x < 64) {
+    team_sync<NT>();
+    if (SW == 1 && tid < 64) {
+        sweep_registers<T, CHF>(L, ex, ey, ez, tid);
+    } else if (SW == 0 && tid < 64) {
         // lane owns the x-pencil (pj, pk) = (lane % 8, lane / 8); at time step
         // tau it handles the cell li = tau - pj - pk of hyperplane tau
         T *y = L.y, *wx = L.wx, *wy = L.wy, *wz = L.wz, *dinv = L.dinv;
-        const int pj = threadIdx.x & (SB - 1), pk = threadIdx.x >> 3;
+        const int pj = tid & (SB - 1), pk = tid >> 3;
         const bool pencil = pj < ey && pk < ez;
         const int nlev = ex + ey + ez - 2;
         const int base = PAD + SB * pj + SB * SB * pk;
@@ -509,10 +519,10 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
             wave_sync();
         }
     }
-    __syncthreads();
+    team_sync<NT>();
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const int t = threadIdx.x + NT * c;
+        const int t = tid + NT * c;
         const int li = t & (SB - 1), lj = (t >> 3) & (SB - 1), lk = t >> 6;
         if (li < ex && lj < ey && lk < ez)
             enew[wrap_cell(i0 + li, o.x, g.nx) +
@@ -536,7 +546,7 @@ __global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict
     __shared__ SmoothLds<T> lds;
     if (done && *done) return;
     bilu_step_body<T, TR, NT, SW>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds,
-                                  block_shift(g, shifted));
+                                  block_shift(g, shifted), FromCoarse<T, void>{}, (int)threadIdx.x);
 }
 
 // The first post-smoothing step, whose e_old is the prolongated coarse
@@ -556,7 +566,7 @@ __global__ __launch_bounds__(NT) void k_bilu_first(GridDev g, const T *__restric
     __shared__ double xs[kXcLds];
     if (done && *done) return;
     bilu_step_body<T, TR, NT, SW, TP>(g, W, diag, invd, rhs, nullptr, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds,
-                                      Shift{0, 0, 0}, FromCoarse<T, TP>{P, dm, xc, cube, xs});
+                                      Shift{0, 0, 0}, FromCoarse<T, TP>{P, dm, xc, cube, xs}, (int)threadIdx.x);
 }
 
 // Batched step `s` of `steps` for every instance.  `post` selects the
@@ -603,7 +613,7 @@ __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ i
         T *out = buf[(steps - 1 - s) & 1];
         const T *prev = s > 0 ? buf[(steps - s) & 1] : init;
         bilu_step_body<T, TR, NT>(d.g, W, diag, shifted ? invd + d.g.N : invd, rhs, prev, out, w.blk, lds,
-                                  block_shift(d.g, shifted));
+                                  block_shift(d.g, shifted), FromCoarse<T, void>{}, (int)threadIdx.x);
     }
 }
 

@@ -40,7 +40,8 @@ class Solver:
                            overrides.get("newton_maxit", problem.newton_maxit),
                            overrides.get("lin_atol", getattr(problem, "lin_atol", 0.0)),
                            overrides.get("basis_type", getattr(problem, "basis_type", 0)),
-                           overrides.get("basis_tol", getattr(problem, "basis_tol", 0.0)))
+                           overrides.get("basis_tol", getattr(problem, "basis_tol", 0.0)),
+                           overrides.get("coarse_tol", getattr(problem, "coarse_tol", 0.0)))
         self.options = o
         h = ctypes.c_void_p()
         C.check(C.cams_create(ctypes.byref(g), ctypes.byref(f), ctypes.byref(o),

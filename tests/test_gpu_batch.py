@@ -183,3 +183,31 @@ def test_batch_full_size_256_instances(torch):
         assert diff <= 1e-12 and single["lin_iters_total"] == its[i]
         sv.close()
     b.close()
+
+
+def test_block_tridiagonal_instance_needs_its_own_factorisation_after_a_batch(torch):
+    """The batch inverts every MSFE instance densely; an instance whose own
+    coarse solve is block tridiagonal (over 4096 nodes, here 5760) must not
+    reuse that inverse: cams_iterate after the batch reports CAMS_E_STATE,
+    and after cams_coarse_op the solve meets the tolerance on the oracle's
+    matrix."""
+    import ctypes
+    from paper_1705_05783_amd import _cams as C
+    from tests.gpu_util import linear_residual_check
+    big = small_problem(96, 96, 40, 4, sigma=2.0, seed=31, c=0.1).with_options(precision=MIXED_FP32, newton_maxit=1)
+    small = small_problem(16, 12, 8, 4, sigma=2.0, seed=3, c=0.1).with_options(precision=MIXED_FP32, newton_maxit=1)
+    b, status, stats, p = _run_batch(torch, [big, small])
+    assert all(s_ == 0 for s_ in status)
+    s = b.solvers[0]
+    assert C.cams_coarse_planes(s.ctx) > 0
+    p0 = _start(big)
+    pt = torch.as_tensor(p0, device="cuda")
+    s.assemble(pt, pt.clone())
+    rc = C.cams_iterate(s.ctx, ctypes.c_void_p(pt.data_ptr()), None)
+    assert rc == C.CAMS_E_STATE
+    s.coarse_op()
+    d = torch.zeros_like(pt)
+    s.iterate(d)
+    rel, bound = linear_residual_check(big, oracle.transmissibility(big), p0, p0, p0 + to_np(d), d=to_np(d))
+    assert rel <= bound, (rel, bound)
+    b.close()

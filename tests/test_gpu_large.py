@@ -187,3 +187,48 @@ def test_channelised_mid_size_against_oracle_newton(torch):
     assert rc == 0 and e <= pb.newton_tol
     assert err <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("shape,seed", [((64, 64, 64), 36), ((96, 96, 40), 31)])
+def test_adaptive_coarse_factorisation(torch, shape, seed):
+    """coarse_tol = 0.05: the coarse inverse (dense 4096-node Gauss-Jordan;
+    block-tridiagonal over 10 planes) is kept while no entry of R A P_hat has
+    changed by more than 5 % since it was factorised.  Two time steps: every
+    linear solve still meets the tolerance on the oracle's FP64 matrix, every
+    step's nonlinear error meets the Newton tolerance, and fewer inverses are
+    computed than Newton iterations taken."""
+    pb = small_problem(*shape, 4, sigma=2.0, seed=seed, c=0.1, dt=0.05).with_options(coarse_tol=0.05)
+    pb.n_steps = 2
+    T = oracle.transmissibility(pb)
+    s = solver_for(pb)
+    pn_t = s.new_pressure()
+    p_t = pn_t.clone()
+    for step in range(pb.n_steps):
+        nit, lits, worst = checked_newton_step(s, pb, T, pn_t, p_t, torch)
+        _, e = oracle.nonlinear_residual(pb, T, to_np(p_t), to_np(pn_t))
+        log(pb.name, "step", step + 1, "newton", nit, "cams", lits, "eps", e)
+        assert e <= pb.newton_tol
+        pn_t.copy_(p_t)
+    s.close()
+    s = solver_for(pb)
+    pn_t = s.new_pressure()
+    p_t = pn_t.clone()
+    total_newton = total_fact = 0
+    for step in range(pb.n_steps):
+        st = s.newton_step(pn_t, p_t)
+        total_newton += st["newton_iters"]
+        total_fact += st["coarse_factorizations"]
+        pn_t.copy_(p_t)
+    s.close()
+    ref = solver_for(pb.with_options(coarse_tol=0.0))
+    qn = ref.new_pressure()
+    q = qn.clone()
+    ref_its = 0
+    for step in range(pb.n_steps):
+        st = ref.newton_step(qn, q)
+        ref_its += st["lin_iters_total"]
+        assert st["coarse_factorizations"] == st["newton_iters"]
+        qn.copy_(q)
+    ref.close()
+    log(pb.name, "Newton iterations", total_newton, "coarse inverses", total_fact, "C-AMS (refactorised)", ref_its)
+    assert 1 <= total_fact < total_newton

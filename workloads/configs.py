@@ -71,6 +71,7 @@ class Problem:
     smoother: int = SMOOTH_BLOCK_ALT
     basis_type: int = 0             # 0 = B4, 1 = B1, 2 = B2, 3 = B3 (Sec. 3)
     basis_tol: float = 0.0          # B1/B2 adaptive update threshold (0: rebuild every Newton iteration)
+    coarse_tol: float = 0.0         # adaptive coarse factorisation threshold (0: every Newton iteration)
 
     @property
     def n(self) -> int:
