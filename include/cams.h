@@ -368,6 +368,21 @@ cams_status cams_cnn_forward(void *stream, const float *params_dev, const float 
 size_t cams_cnn_bf16_workspace_bytes(void);
 cams_status cams_cnn_forward_bf16(void *stream, const float *params_dev, const float *feat_dev, int32_t batch,
                                   void *ws_dev, float *phi_dev);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation): cams_cnn_forward_bf16
+ * without the caller's workspace.  The bfloat16 weights and FP32 biases are
+ * staged in a fixed device array of cams_cnn_noalloc_scratch_bytes() bytes
+ * (512 KB) that each GPU the library runs on holds until the process ends;
+ * its address on the current device is looked up once (the stream must
+ * belong to the current device).  Calls allocate nothing.  Every call on a
+ * GPU shares that GPU's array and rewrites it from `params_dev`, so calls
+ * that overlap on one GPU (different streams, or threads) race.  Same
+ * arguments and result as cams_cnn_forward_bf16.
+ * Errors: CAMS_E_ARG (null pointer, batch <= 0), CAMS_E_NOMEM (the network
+ * needs more than the fixed array), CAMS_E_DEVICE. */
+size_t cams_cnn_noalloc_scratch_bytes(void);
+cams_status cams_cnn_forward_bf16_noalloc(void *stream, const float *params_dev, const float *feat_dev,
+                                          int32_t batch, float *phi_dev);
 /* Mean-squared error of phi against tgt over the interior cells and 8 channels
  * (written to *loss_dev, a device double) and its gradient wrt the
  * parameters (grad_dev, cams_cnn_num_params floats); the project's own

@@ -108,6 +108,8 @@ _SIGS = [
     ("cams_cnn_forward", _I, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
     ("cams_cnn_bf16_workspace_bytes", ctypes.c_size_t, []),
     ("cams_cnn_forward_bf16", _I, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
+    ("cams_cnn_noalloc_scratch_bytes", ctypes.c_size_t, []),
+    ("cams_cnn_forward_bf16_noalloc", _I, [_VP, _VP, _VP, ctypes.c_int32, _VP]),
     ("cams_cnn_loss_grad", _I, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP]),
     ("cams_cnn_adam", _I, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                            ctypes.c_float, ctypes.c_float, ctypes.c_float]),
