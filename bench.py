@@ -130,13 +130,25 @@ def measured_traffic(workload):
     return None if w is None else w["traffic_bytes_per_launch"]
 
 
-def roofline(prof, workload=None):
+# The smoothing-step kernel each precision and grid size launches: one
+# workgroup per 8^3 block with register sweeps while all blocks are resident
+# at once (64x64x32), else the LDS sweeps (FP32: four blocks along x per
+# workgroup; FP64: one block per workgroup).
+SMOOTHER_KERNEL = {
+    ("resident", "f32"): "k_bilu_step<float, float, 512, 1>",
+    ("resident", "f64"): "k_bilu_step<double, double, 512, 1>",
+    ("many", "f32"): "k_bilu_step_row<float, float, 4, 512>",
+    ("many", "f64"): "k_bilu_step<double, double, 256, 0>",
+}
+
+
+def roofline(prof, workload=None, kernel=None):
     if prof["launches"] == 0 or prof["total_ms"] <= 0:
         return None
     per_launch_bytes = prof["bytes"] / prof["launches"]
     avg_s = prof["total_ms"] * 1e-3 / prof["launches"]
     achieved = per_launch_bytes / avg_s / 1e9
-    return {"kernel": "k_bilu_step (block-ILU(0) Richardson step)", "bound": "hbm",
+    return {"kernel": f"{kernel} (block-ILU(0) Richardson step)", "bound": "hbm",
             "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
             "traffic": measured_traffic(workload) if workload else None, "avg_launch_us": avg_s * 1e6,
             "bytes_per_launch": per_launch_bytes, "launches": prof["launches"]}
@@ -157,7 +169,8 @@ def headline(steps, warmup, torch):
         if learned:
             solver.set_learned(params, fallback_tol=tol)
         r = timed_passes(solver, pb, steps, warmup, torch)
-        r["roofline_smoother"] = roofline(r.pop("prof"), f"128^3 {label}")
+        r["roofline_smoother"] = roofline(r.pop("prof"), f"128^3 {label}",
+                                          SMOOTHER_KERNEL["many", "f64" if prec == FP64 else "f32"])
         if learned:
             r["fallback_tol"] = tol
             r["full_dual_blocks"] = solver.num_full_blocks()
@@ -232,7 +245,8 @@ def small_run(steps, warmup, torch):
         pb = config2(precision=prec)
         solver = Solver(pb)
         r = timed_passes(solver, pb, steps, warmup, torch)
-        r["roofline_smoother"] = roofline(r.pop("prof"), "64x64x32 mixed" if label == "mixed" else None)
+        r["roofline_smoother"] = roofline(r.pop("prof"), "64x64x32 mixed" if label == "mixed" else None,
+                                          SMOOTHER_KERNEL["resident", "f32" if label == "mixed" else "f64"])
         out[label] = r
         solver.close()
     out["speedup_mixed_vs_plain"] = out["plain_fp64"]["s_per_solve"] / out["mixed"]["s_per_solve"]
@@ -249,7 +263,7 @@ def large_run(steps, warmup, torch):
     pb = config4()
     solver = Solver(pb)
     r = timed_passes(solver, pb, steps, warmup, torch)
-    r["roofline_smoother"] = roofline(r.pop("prof"), "256x256x128 channelised BF16")
+    r["roofline_smoother"] = roofline(r.pop("prof"), "256x256x128 channelised BF16", SMOOTHER_KERNEL["many", "f32"])
     r.update({"workload": "256x256x128 channelised (k 1 / 1e-4, 30% channels), coarsening 8^3, 16384 coarse "
                           "nodes, BF16 basis, 5 time steps dt=0.05 per pass, to 1e-8",
               "cells": pb.n, "coarse_nodes": solver.Nc})

@@ -267,6 +267,36 @@ __device__ __forceinline__ void sweep_registers(SmoothLds<T> &L, int ex, int ey,
     }
 }
 
+// Forward and backward sweeps of the staged block by one wave with the
+// running values in LDS (SW = 0): lane owns the x-pencil (pj, pk) =
+// (lane % 8, lane / 8); at time step tau it handles the cell
+// li = tau - pj - pk of hyperplane tau.
+template <class T>
+__device__ __forceinline__ void sweep_lds(SmoothLds<T> &L, int ex, int ey, int ez, int lane)
+{
+    T *y = L.y, *wx = L.wx, *wy = L.wy, *wz = L.wz, *dinv = L.dinv;
+    const int pj = lane & (SB - 1), pk = lane >> 3;
+    const bool pencil = pj < ey && pk < ez;
+    const int nlev = ex + ey + ez - 2;
+    const int base = PAD + SB * pj + SB * SB * pk;
+    for (int tau = 0; tau < nlev; ++tau) {
+        const int a = tau - pj - pk;
+        const bool act = pencil && a >= 0 && a < ex;
+        const int t = base + min(max(a, 0), SB - 1);
+        const T s = y[t] + wx[t - 1] * y[t - 1] + wy[t - SB] * y[t - SB] + wz[t - SB * SB] * y[t - SB * SB];
+        if (act) y[t] = s * dinv[t - PAD];
+        wave_sync();
+    }
+    for (int tau = nlev - 1; tau >= 0; --tau) {
+        const int a = tau - pj - pk;
+        const bool act = pencil && a >= 0 && a < ex;
+        const int t = base + min(max(a, 0), SB - 1);
+        const T s = wx[t] * y[t + 1] + wy[t] * y[t + SB] + wz[t] * y[t + SB * SB];
+        if (act) y[t] += s * dinv[t - PAD];
+        wave_sync();
+    }
+}
+
 // Prolongated coarse correction as e_old (the first post-smoothing step):
 // basis P (TP = double, float or bfloat16 bits), Dirichlet mask, coarse
 // solution, and an LDS cube of (SB + 2)^3 values for the block and its face
@@ -495,29 +525,7 @@ __device__ __forceinline__ void bilu_step_body(const GridDev &g, const T *__rest
     if (SW == 1 && tid < 64) {
         sweep_registers<T, CHF>(L, ex, ey, ez, tid);
     } else if (SW == 0 && tid < 64) {
-        // lane owns the x-pencil (pj, pk) = (lane % 8, lane / 8); at time step
-        // tau it handles the cell li = tau - pj - pk of hyperplane tau
-        T *y = L.y, *wx = L.wx, *wy = L.wy, *wz = L.wz, *dinv = L.dinv;
-        const int pj = tid & (SB - 1), pk = tid >> 3;
-        const bool pencil = pj < ey && pk < ez;
-        const int nlev = ex + ey + ez - 2;
-        const int base = PAD + SB * pj + SB * SB * pk;
-        for (int tau = 0; tau < nlev; ++tau) {
-            const int a = tau - pj - pk;
-            const bool act = pencil && a >= 0 && a < ex;
-            const int t = base + min(max(a, 0), SB - 1);
-            const T s = y[t] + wx[t - 1] * y[t - 1] + wy[t - SB] * y[t - SB] + wz[t - SB * SB] * y[t - SB * SB];
-            if (act) y[t] = s * dinv[t - PAD];
-            wave_sync();
-        }
-        for (int tau = nlev - 1; tau >= 0; --tau) {
-            const int a = tau - pj - pk;
-            const bool act = pencil && a >= 0 && a < ex;
-            const int t = base + min(max(a, 0), SB - 1);
-            const T s = wx[t] * y[t + 1] + wy[t] * y[t + SB] + wz[t] * y[t + SB * SB];
-            if (act) y[t] += s * dinv[t - PAD];
-            wave_sync();
-        }
+        sweep_lds<T>(L, ex, ey, ez, tid);
     }
     team_sync<NT>();
 #pragma unroll
@@ -547,6 +555,104 @@ __global__ __launch_bounds__(NT) void k_bilu_step(GridDev g, const T *__restrict
     if (done && *done) return;
     bilu_step_body<T, TR, NT, SW>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), lds,
                                   block_shift(g, shifted), FromCoarse<T, void>{}, (int)threadIdx.x);
+}
+
+constexpr int kRowBlocks = 4;     // FP32 blocks per workgroup of the row form
+constexpr int kRowThreads = 512;
+
+// The same step for BPX neighbouring blocks along x per workgroup of NT
+// threads: all threads stage the BPX blocks together, x fastest over the
+// BPX * 8 cells of a row, so that a wave's loads cover rows of 8 BPX
+// consecutive cells (128 bytes: BPX = 4 in FP32, 2 in FP64) instead of the
+// 8-cell rows of one block; then wave w < BPX sweeps block w (those waves
+// at once) and all threads write the blocks back.  The operations per cell
+// are those of bilu_step_body.
+template <class T, class TR, int BPX, int NT>
+__global__ __launch_bounds__(NT) void k_bilu_step_row(GridDev g, const T *__restrict__ W,
+                                                       const T *__restrict__ diag, const T *__restrict__ invd,
+                                                       const TR *__restrict__ rhs, const T *__restrict__ eold,
+                                                       T *__restrict__ enew, const int32_t *done, int shifted)
+{
+    static_assert(NT % 64 == 0 && NT >= 64 * BPX && (ST * BPX) % NT == 0, "one wave per block at least");
+    constexpr int RX = SB * BPX, CPT = ST * BPX / NT;
+    __shared__ SmoothLds<T> Ls[BPX];
+    if (done && *done) return;
+    const Shift o = block_shift(g, shifted);
+    const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
+    const int nsx = (nbx + BPX - 1) / BPX;
+    const int sb = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int bx0 = (sb % nsx) * BPX, j0 = ((sb / nsx) % nby) * SB, k0 = (sb / (nsx * nby)) * SB;
+    const int ey = min(SB, g.ny - j0), ez = min(SB, g.nz - k0);
+    const T *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < BPX * 2 * PAD; q += NT) {
+        const int b = q / (2 * PAD), r = q % (2 * PAD);
+        const int idx = r < PAD ? r : ST + r;
+        Ls[b].y[idx] = 0;
+        Ls[b].wx[idx] = 0;
+        Ls[b].wy[idx] = 0;
+        Ls[b].wz[idx] = 0;
+    }
+    T e0[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int q = tid + NT * c;
+        const int lx = q % RX, lj = (q / RX) % SB, lk = q / (RX * SB);
+        const int b = lx / SB, li = lx % SB;
+        const int i0 = (bx0 + b) * SB;
+        const int ex = bx0 + b < nbx ? min(SB, g.nx - i0) : 0;
+        const bool act = li < ex && lj < ey && lk < ez;
+        const int i = act ? wrap_cell(i0 + li, o.x, g.nx) : 0;
+        const int j = wrap_cell(j0 + (act ? lj : 0), o.y, g.ny), k = wrap_cell(k0 + (act ? lk : 0), o.z, g.nz);
+        const int n = i + g.nx * (j + g.ny * k);
+        const bool xm = i > 0, xp = i + 1 < g.nx, ym = j > 0, yp = j + 1 < g.ny, zm = k > 0, zp = k + 1 < g.nz;
+        const int nxm = xm ? n - 1 : n, nxp = xp ? n + 1 : n, nym = ym ? n - g.nx : n, nyp = yp ? n + g.nx : n;
+        const int nzm = zm ? n - g.sxy : n, nzp = zp ? n + g.sxy : n;
+        const T wxm = Wx[nxm], wxp = Wx[n], wym = Wy[nym], wyp = Wy[n], wzm = Wz[nzm], wzp = Wz[n];
+        const T fxm = xm ? wxm : T(0), fxp = xp ? wxp : T(0);
+        const T fym = ym ? wym : T(0), fyp = yp ? wyp : T(0);
+        const T fzm = zm ? wzm : T(0), fzp = zp ? wzp : T(0);
+        const T *eo = eold ? eold : W;
+        const T ec = eo[n], exm = eo[nxm], exp = eo[nxp], eym = eo[nym], eyp = eo[nyp];
+        const T ezm = eo[nzm], ezp = eo[nzp];
+        T ae = diag[n] * ec;
+        ae -= fxm * exm;
+        ae -= fxp * exp;
+        ae -= fym * eym;
+        ae -= fyp * eyp;
+        ae -= fzm * ezm;
+        ae -= fzp * ezp;
+        const T on = eold ? T(1) : T(0);
+        const T z = (T)rhs[n] - on * ae;
+        const T ev = on * ec;
+        const T id = invd[n];
+        const int t = li + SB * lj + SB * SB * lk;
+        SmoothLds<T> &L = Ls[b];
+        e0[c] = act ? ev : T(0);
+        L.y[PAD + t] = act ? z : T(0);
+        L.dinv[t] = act ? id : T(0);
+        L.wx[PAD + t] = act && li + 1 < ex ? fxp : T(0);
+        L.wy[PAD + t] = act && lj + 1 < ey ? fyp : T(0);
+        L.wz[PAD + t] = act && lk + 1 < ez ? fzp : T(0);
+    }
+    __syncthreads();
+    {
+        const int w = tid >> 6;
+        if (w < BPX && bx0 + w < nbx) sweep_lds<T>(Ls[w], min(SB, g.nx - (bx0 + w) * SB), ey, ez, tid & 63);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int q = tid + NT * c;
+        const int lx = q % RX, lj = (q / RX) % SB, lk = q / (RX * SB);
+        const int b = lx / SB, li = lx % SB;
+        const int i0 = (bx0 + b) * SB;
+        const int ex = bx0 + b < nbx ? min(SB, g.nx - i0) : 0;
+        if (li < ex && lj < ey && lk < ez)
+            enew[wrap_cell(i0 + li, o.x, g.nx) +
+                 g.nx * (wrap_cell(j0 + lj, o.y, g.ny) + g.ny * wrap_cell(k0 + lk, o.z, g.nz))] =
+                e0[c] + Ls[b].y[PAD + li + SB * lj + SB * SB * lk];
+    }
 }
 
 // The first post-smoothing step, whose e_old is the prolongated coarse
@@ -617,6 +723,26 @@ __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ i
     }
 }
 
+// Smoothing step on a grid with more blocks than are resident at once.
+// FP32: four blocks along x per 512-thread workgroup (k_bilu_step_row: a
+// wave's loads cover 128-byte rows); FP64: one 256-thread workgroup per
+// block (the multi-block shapes measured slower there, see the design notes).
+template <class T, class TR>
+void launch_step_many(cams_ctx *c, const T *W, const T *diag, const T *iv, const TR *rhs, const T *prev, T *out,
+                      const int32_t *done, int sh, int nb)
+{
+    if constexpr (sizeof(T) == 4) {
+        constexpr int BPX = kRowBlocks, NT = kRowThreads;
+        const GridDev &g = c->g;
+        const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB, nbz = (g.nz + SB - 1) / SB;
+        const int wgs = ((nbx + BPX - 1) / BPX) * nby * nbz;
+        k_bilu_step_row<T, TR, BPX, NT><<<wgs, NT, 0, c->stream>>>(g, W, diag, iv, rhs, prev, out, done, sh);
+    } else {
+        k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(c->g, W, diag, iv, rhs,
+                                                                                            prev, out, done, sh);
+    }
+}
+
 inline int num_sblocks(const GridDev &g)
 {
     return ((g.nx + SB - 1) / SB) * ((g.ny + SB - 1) / SB) * ((g.nz + SB - 1) / SB);
@@ -665,8 +791,7 @@ void bilu_smooth(cams_ctx *c, const T *W, const T *diag, const T *invd, const TR
             k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, iv, rhs,
                                                                                         prev, out, done, sh);
         else
-            k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(
-                c->g, W, diag, iv, rhs, prev, out, done, sh);
+            launch_step_many<T, TR>(c, W, diag, iv, rhs, prev, out, done, sh, nb);
         prev = out;
     }
     if (timed) prof_end(c);
@@ -707,8 +832,7 @@ void bilu_smooth_from_coarse(cams_ctx *c, const T *W, const T *diag, const T *in
             k_bilu_step<T, TR, kSmoothThreads, 1><<<nb, kSmoothThreads, 0, c->stream>>>(c->g, W, diag, iv, rhs,
                                                                                         prev, out, done, sh);
         else
-            k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(
-                c->g, W, diag, iv, rhs, prev, out, done, sh);
+            launch_step_many<T, TR>(c, W, diag, iv, rhs, prev, out, done, sh, nb);
         prev = out;
     }
     if (timed) prof_end(c);
