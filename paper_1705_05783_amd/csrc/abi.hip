@@ -474,7 +474,7 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     {   // 44 Gauss-Jordan GEMM descriptors (MSFE): 8 per 64-column panel of each inverted matrix
         const size_t mats = c->blocktri ? (size_t)nb[2] : 1, dim = c->blocktri ? (size_t)nb[0] * nb[1] : nc;
         put(L.add(O.restriction == CAMS_R_FE ? mats * ((dim + 63) / 64) * 12 * sizeof(GemmDesc) : 0));
-        put(L.add(O.restriction == CAMS_R_FE ? (c->blocktri ? 2 : 1) * (2 * dim * 64 + 64 * 64) * 8 : 0));   // 45 saved column blocks, saved pivot rows (per chain)
+        put(L.add(O.restriction == CAMS_R_FE ? (c->blocktri ? 2 : 1) * (5 * dim * 64 + 64 * 64) * 8 : 0));   // 45 old column blocks, their transposes, G (per chain)
     }
     {   // 46-51 basis types B1-B3
         const bool pdep = O.basis_type == CAMS_BASIS_B1 || O.basis_type == CAMS_BASIS_B2;

@@ -68,7 +68,7 @@ struct Arrays {
     double *slots;    // Nc*8 restriction partials: slot s of owner box k
     double *boxp;     // Nc*216 coarse-operator partials of the owner boxes (MSFE)
     void *gjd;        // GEMM descriptors of the Gauss-Jordan inverse (MSFE)
-    double *gjcb;     // two saved column blocks of the Gauss-Jordan sweep (2 x 64 x matrix order)
+    double *gjcb;     // Gauss-Jordan sweep buffers: old column blocks, their transposes, G (5 x 64 x matrix order per chain)
     double *scal;     // device scalars
     int32_t *piv;     // Nc
     int32_t *status;  // device error flags
@@ -373,12 +373,13 @@ struct GemmDesc {
     int ldc, lda, ldb, M, N, K;
     double alpha, beta;
     int tiles_n, tile0;
-    // Optional (null when unused).  pre, S: B is not read from memory but
-    // formed per tile as pre (K x K, row pitch ldc) times S (K x N, row pitch
-    // 64).  copy: the descriptor's first tile also writes its result there
-    // (row pitch 64).
+    // Optional (null when unused; k_gj_panel_sym only): the A operand is not
+    // read from memory but formed per tile as the tile's rows of S (row
+    // pitch lda) times pre (K x K, row pitch ldc).
     const double *pre, *S;
-    double *copy;
+    // tri: the tiles are those of the lower triangle (diagonal tiles whole)
+    // of the square M x N region, counted row by row.
+    int tri;
 };
 struct BatchGjPlan {
     enum Kind { PIVOT = 0, GEMM = 1, UPDATE_PIVOT = 2 };

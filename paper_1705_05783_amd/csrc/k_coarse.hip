@@ -6,9 +6,10 @@
 //  - the explicit inverse, so that every coarse solve of the iteration is one
 //    fully parallel GEMV instead of two latency-bound triangular sweeps:
 //    MSFE (symmetric positive definite): Gauss-Jordan sweeps over 64-column
-//    panels, the products on FP64 matrix cores (v_mfma_f64_16x16x4f64,
-//    64x64 tiles per workgroup), the 64x64 pivot-block inverse overlapping
-//    the next update; MSFV: LU with partial pivoting by panels, then the
+//    panels that update the lower triangle only, the products on FP64
+//    matrix cores (v_mfma_f64_16x16x4f64, 64x64 tiles per workgroup), the
+//    64x64 pivot-block inverse overlapping the next update; MSFV: LU with
+//    partial pivoting by panels, then the
 //    inverse from the factors with the same kernels.  Large MSFE coarse grids
 //    are eliminated plane by plane (block tridiagonal).
 //  - the batched MSFE factorisation of many instances (the same Gauss-Jordan
@@ -546,12 +547,11 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
 //   A[J,J] <- D^-1,  A[J,~J] <- D^-1 A[J,~J],  A[~J,J] <- -A[~J,J] D^-1,
 //   A[~J,~J] <- A[~J,~J] - A[~J,J]_old D^-1 A[J,~J]_old;
 // after the last panel A holds its inverse (2 n^3 flop, as LU plus inverse).
-// Three launches per panel: the panel products (one launch), the update of
-// the next panel's columns, and the rest of the update together with the
-// next panel's pivot-block inverse (and the copy of its old column block),
-// so that the sequential pivot inverse overlaps the matrix-core update.  In
-// the single-matrix sweep the first two share one launch from the second
-// panel on (k_gj_panel).
+// The batched sweeps take three launches per panel: the panel products, the
+// update of the next panel's columns, and the rest of the update together
+// with the next panel's pivot-block inverse (and the copy of its old column
+// block), so that the sequential pivot inverse overlaps the matrix-core
+// update.  Single matrices take the symmetric form of the sweep below.
 
 // Workgroup 0: D^-1 of the nb x nb pivot block (padded to 64 x 64 with the
 // identity) by the same sweep on entries two at a time, 4 x 4 entries per
@@ -665,12 +665,6 @@ __device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j
     if (bad && threadIdx.x == 0) atomicOr(status, F_SINGULAR_COARSE);
 }
 
-__global__ __launch_bounds__(kBlock) void k_gj_pivot(double *__restrict__ A, int n, int j0, int nb,
-                                                      double *__restrict__ Cb, int32_t *status)
-{
-    gj_pivot_wg(A, n, j0, nb, Cb, status, blockIdx.x);
-}
-
 // Number of workgroups of a pivot step: the inverse and the column copy.
 inline unsigned gj_pivot_wgs(int n, int nb) { return 1 + (unsigned)(((size_t)(n - nb) * nb + kBlock - 1) / kBlock); }
 
@@ -690,9 +684,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // latency hides behind the products (C is only written at the end, so an
 // aliased A or B is still read before it is overwritten).
 constexpr int KS = 32;
-// Update launches with at least this many GEMM tiles (four rounds of two
-// workgroups per compute unit) take the lean tile at three per unit.
+// Batched update launches with at least this many GEMM tiles (four rounds
+// of two workgroups per compute unit) take the lean tile at three per unit;
+// the symmetric sweep's update launches from kWideTilesSym tiles on take it
+// at four per unit (a 4096^2 sweep: about 1950 tiles per launch, 49.6 ->
+// 41 us per launch).
 constexpr int kWideTiles = 2048;
+constexpr int kWideTilesSym = 1024;
 
 //
 // LEAN: no register prefetch of the next stage and C loaded only after the
@@ -702,8 +700,7 @@ constexpr int kWideTiles = 2048;
 // the prefetching form stays where one round of tiles bounds the launch.
 template <bool LEAN = false>
 __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, int lda, const double *B, int ldb,
-                                          int M, int Nn, int K, double alpha, double beta, int tm, int tn,
-                                          double *copy = nullptr)
+                                          int M, int Nn, int K, double alpha, double beta, int tm, int tn)
 {
     __shared__ double As[64][KS + 1];
     __shared__ double Bs[KS][64 + 1];
@@ -782,9 +779,23 @@ __device__ __forceinline__ void gemm_tile(double *C, int ldc, const double *A, i
                     const double prod = alpha * acc[a][b][v];
                     const double out = beta == 0.0 ? prod : beta * cv[a][b][v] + prod;
                     C[(size_t)r * ldc + c] = out;
-                    if (copy) copy[(size_t)(r - tm) * 64 + (c - tn)] = out;
                 }
             }
+}
+
+// Row and column offsets of tile t of descriptor g.
+__device__ __forceinline__ void tile_origin(const GemmDesc &g, int t, int &tm, int &tn)
+{
+    if (g.tri) {   // t = r (r + 1) / 2 + c, c <= r
+        int r = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while (r * (r + 1) / 2 > t) --r;
+        while ((r + 1) * (r + 2) / 2 <= t) ++r;
+        tm = 64 * r;
+        tn = 64 * (t - r * (r + 1) / 2);
+    } else {
+        tm = (t / g.tiles_n) * 64;
+        tn = (t % g.tiles_n) * 64;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_gemm(double *C, int ldc, const double *A, int lda, const double *B,
@@ -826,82 +837,17 @@ __global__ __launch_bounds__(kBlock) void kb_gemm(const GemmDesc *__restrict__ d
         else hi = mid - 1;
     }
     const GemmDesc g = d[lo];
-    const int t = blockIdx.x - g.tile0;
-    gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
-              (t % g.tiles_n) * 64);
+    int tm, tn;
+    tile_origin(g, blockIdx.x - g.tile0, tm, tn);
+    gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, tm, tn);
 }
 
-// The update of one Gauss-Jordan panel (outside the next panel's columns)
-// and the next panel's pivot step in one launch: workgroup 0 inverts the
-// next pivot block, the next `pw - 1` copy its old column block, the others
-// are GEMM tiles of the update.  The next pivot block and its column block
-// are final before the launch (their part of the update ran just before), so
-// the sequential pivot inverse runs while the matrix cores update the rest.
-template <bool LEAN>
-__device__ __forceinline__ void gj_update_pivot_body(const GemmDesc *__restrict__ d, int nd, int pw, double *A, int n,
-                                                     int j0, int nb, double *Cb, int32_t *status)
-{
-    if ((int)blockIdx.x < pw) {
-        gj_pivot_wg(A, n, j0, nb, Cb, status, blockIdx.x);
-        return;
-    }
-    const int tile = blockIdx.x - pw;
-    int lo = 0, hi = nd - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (d[mid].tile0 <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmDesc g = d[lo];
-    const int t = tile - g.tile0;
-    gemm_tile<LEAN>(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
-                    (t % g.tiles_n) * 64, t == 0 ? g.copy : nullptr);
-}
-__global__ __launch_bounds__(kBlock) void k_gj_update_pivot(const GemmDesc *__restrict__ d, int nd, int pw,
-                                                             double *A, int n, int j0, int nb, double *Cb,
-                                                             int32_t *status)
-{
-    gj_update_pivot_body<false>(d, nd, pw, A, n, j0, nb, Cb, status);
-}
-// The same with the lean GEMM tile, three workgroups per compute unit.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_gj_update_pivot_wide(
-    const GemmDesc *__restrict__ d, int nd, int pw, double *A, int n, int j0, int nb, double *Cb, int32_t *status)
-{
-    gj_update_pivot_body<true>(d, nd, pw, A, n, j0, nb, Cb, status);
-}
-
-// The panel products of a Gauss-Jordan panel and the update of the next
-// panel's columns in one launch.  The column update needs the scaled pivot
-// rows D^-1 A[J,J2], which the row-scaling tiles of the same launch are
-// overwriting; each column-update tile therefore forms them itself, in LDS,
-// from the copy of A[J,J2] that the previous update launch saved (S) and
-// D^-1 (pre), by the same tile product as the row-scaling tile (so the
-// values are bitwise the ones that tile writes).
-__global__ __launch_bounds__(kBlock) void k_gj_panel(const GemmDesc *__restrict__ d, int nd)
-{
-    __shared__ double Ts[64 * 65];
-    int lo = 0, hi = nd - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (d[mid].tile0 <= (int)blockIdx.x) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmDesc g = d[lo];
-    const int t = blockIdx.x - g.tile0;
-    const double *B = g.B;
-    int ldb = g.ldb;
-    if (g.pre) {   // uniform over the workgroup
-        gemm_tile(Ts, 65, g.pre, g.ldc, g.S, 64, g.K, g.N, g.K, 1.0, 0.0, 0, 0);
-        __syncthreads();
-        B = Ts;
-        ldb = 65;
-    }
-    gemm_tile(g.C, g.ldc, g.A, g.lda, B, ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
-              (t % g.tiles_n) * 64);
-}
-
-// The batched form: the first `pw` workgroups are the pivot steps of the
-// next panel of every instance that has one, the others GEMM tiles.
+// The update of one Gauss-Jordan panel of every instance of a batch
+// (outside the next panel's columns) and the next panel's pivot steps in one
+// launch: the first `pw` workgroups are the pivot steps of the next panel of
+// every instance that has one (the next pivot block and its column block are
+// final before the launch, so the sequential pivot inverse runs while the
+// matrix cores update the rest), the others GEMM tiles.
 template <bool LEAN>
 __device__ __forceinline__ void gjb_update_pivot_body(const GjPivotDesc *__restrict__ p, int np, int pw,
                                                       const GemmDesc *__restrict__ d, int nd)
@@ -932,6 +878,144 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     const GjPivotDesc *__restrict__ p, int np, int pw, const GemmDesc *__restrict__ d, int nd)
 {
     gjb_update_pivot_body<true>(p, np, pw, d, nd);
+}
+
+// ---- symmetric Gauss-Jordan sweeps (single MSFE matrices and the planes of
+// the block-tridiagonal form).  The sweep keeps A[U,U] and A[S,S] symmetric
+// and A[U,S] = -A[S,U]^T (S: swept columns, U: the others), so the lower
+// triangle (diagonal tiles whole) determines the whole matrix and only its
+// tiles are updated: half the flop and half the bytes of the full sweep.
+// Per panel J (D = A[J,J], old column block Cb = A[~J,J]):
+//   G = Cb D^-1;  A[J,J] <- D^-1;  A[I,J] <- -G_I (I > J);
+//   A[J,K] <- -D^-1 Cb_K^T (K < J);
+//   A[I,K] <- A[I,K] - s_K G_I Cb_K^T for the lower tiles I >= K outside J,
+//   with s_K = +1 for K > J and -1 for K < J (A[J,K] = s_K Cb_K^T);
+// where Cb_I = A[I,J] for I > J and -A[J,I]^T for I < J, both from the
+// lower triangle.  After the last panel the lower triangle holds the
+// inverse; k_mirror_lower copies it to the upper one.
+
+// Workgroup 0: D^-1 (gj_pivot_wg); workgroups 1..: Cb (row stride nb) and
+// its transpose CbT (nb x n, row stride n) for the rows outside J, from the
+// lower triangle: rows below J from column J (nb consecutive values per
+// row), rows above J from row J (consecutive along the row).
+__device__ __forceinline__ void gj_pivot_sym_wg(double *__restrict__ A, int n, int j0, int nb,
+                                                double *__restrict__ Cb, double *__restrict__ CbT, int32_t *status,
+                                                int blk)
+{
+    if (blk == 0) {
+        gj_pivot_wg(A, n, j0, nb, nullptr, status, 0);
+        return;
+    }
+    const size_t t = (size_t)(blk - 1) * kBlock + threadIdx.x;
+    const size_t below = (size_t)(n - j0 - nb) * nb;
+    if (t < below) {
+        const int i = j0 + nb + (int)(t / nb), cc = (int)(t % nb);
+        const double v = A[(size_t)i * n + j0 + cc];
+        Cb[(size_t)i * nb + cc] = v;
+        CbT[(size_t)cc * n + i] = v;
+    } else if (t < below + (size_t)j0 * nb) {
+        const size_t u = t - below;
+        const int cc = (int)(u / j0), i = (int)(u % j0);
+        const double v = -A[(size_t)(j0 + cc) * n + i];
+        Cb[(size_t)i * nb + cc] = v;
+        CbT[(size_t)cc * n + i] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gj_pivot_sym(double *__restrict__ A, int n, int j0, int nb,
+                                                          double *__restrict__ Cb, double *__restrict__ CbT,
+                                                          int32_t *status)
+{
+    gj_pivot_sym_wg(A, n, j0, nb, Cb, CbT, status, blockIdx.x);
+}
+
+// Entry 1 of a panel of the symmetric sweep: GEMM tiles, where a descriptor
+// with `pre` forms its A operand per tile in LDS as S (rows of Cb, row
+// pitch lda) times pre (D^-1, row pitch ldc): the rows of G that the
+// next panel's row and column need, computed by the same tile product as
+// the G tiles of the same launch.
+__global__ __launch_bounds__(kBlock) void k_gj_panel_sym(const GemmDesc *__restrict__ d, int nd)
+{
+    __shared__ double Ts[64 * 65];
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc g = d[lo];
+    int tm, tn;
+    tile_origin(g, blockIdx.x - g.tile0, tm, tn);
+    if (g.pre) {   // uniform over the workgroup
+        const int rows = min(64, g.M - tm);
+        gemm_tile(Ts, 65, g.S + (size_t)tm * g.lda, g.lda, g.pre, g.ldc, rows, g.K, g.K, 1.0, 0.0, 0, 0);
+        __syncthreads();
+        gemm_tile(g.C + (size_t)tm * g.ldc, g.ldc, Ts, 65, g.B, g.ldb, rows, g.N, g.K, g.alpha, g.beta, 0, tn);
+    } else {
+        gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, tm, tn);
+    }
+}
+
+// The lower-tile update of a panel outside the next panel's row and column,
+// and the next panel's pivot step (first `pw` workgroups), in one launch.
+template <bool LEAN>
+__device__ __forceinline__ void gj_update_pivot_sym_body(const GemmDesc *__restrict__ d, int nd, int pw, double *A,
+                                                         int n, int j0, int nb, double *Cb, double *CbT,
+                                                         int32_t *status)
+{
+    if ((int)blockIdx.x < pw) {
+        gj_pivot_sym_wg(A, n, j0, nb, Cb, CbT, status, blockIdx.x);
+        return;
+    }
+    const int tile = blockIdx.x - pw;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc g = d[lo];
+    int tm, tn;
+    tile_origin(g, tile - g.tile0, tm, tn);
+    gemm_tile<LEAN>(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, tm, tn);
+}
+__global__ __launch_bounds__(kBlock) void k_gj_update_pivot_sym(const GemmDesc *__restrict__ d, int nd, int pw,
+                                                                 double *A, int n, int j0, int nb, double *Cb,
+                                                                 double *CbT, int32_t *status)
+{
+    gj_update_pivot_sym_body<false>(d, nd, pw, A, n, j0, nb, Cb, CbT, status);
+}
+// The same with the lean GEMM tile at four workgroups per compute unit.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_gj_update_pivot_sym_wide(
+    const GemmDesc *__restrict__ d, int nd, int pw, double *A, int n, int j0, int nb, double *Cb, double *CbT,
+    int32_t *status)
+{
+    gj_update_pivot_sym_body<true>(d, nd, pw, A, n, j0, nb, Cb, CbT, status);
+}
+
+// A[i][j] = A[j][i] for i < j: one workgroup per 64 x 64 tile of the
+// upper triangle (tile row r < tile column c), through LDS so that reads
+// and writes both run along rows.
+__global__ __launch_bounds__(kBlock) void k_mirror_lower(double *__restrict__ A, int n)
+{
+    __shared__ double T[64][65];
+    const int t = blockIdx.x;
+    int c = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);   // t = c (c - 1) / 2 + r, r < c
+    c += 1;
+    while (c * (c - 1) / 2 > t) --c;
+    while ((c + 1) * c / 2 <= t) ++c;
+    const int r = t - c * (c - 1) / 2;
+    const int i0 = 64 * r, j0 = 64 * c;
+    // read the lower tile (rows j0.., columns i0..)
+    for (int q = threadIdx.x; q < 64 * 64; q += kBlock) {
+        const int a = q / 64, b = q % 64;
+        if (j0 + a < n && i0 + b < n) T[a][b] = A[(size_t)(j0 + a) * n + i0 + b];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 64 * 64; q += kBlock) {
+        const int a = q / 64, b = q % 64;   // upper element (i0 + a, j0 + b) = lower (j0 + b, i0 + a)
+        if (i0 + a < n && j0 + b < n) A[(size_t)(i0 + a) * n + j0 + b] = T[b][a];
+    }
 }
 
 // B = P I for the row interchanges of the factorisation (one thread builds
@@ -1257,17 +1341,14 @@ void launch_coarse_operator(cams_ctx *c)
     k_coarse_nodes<<<cdiv((size_t)27 * n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.boxp, c->a.Ac);
 }
 
-// Descriptors of the three GEMM launches of every panel of the Gauss-Jordan
-// sweep of A (n x n, leading dimension n): the panel products; the update of
-// the next panel's columns; the rest of the update (which runs together with
-// the next pivot step).  Panel p saves its old column block in Cb[p & 1]
-// (row stride nb), so the next pivot step can fill the other buffer while
-// the update still reads this one.  Each launch entry of L is (offset,
-// count, tiles).  With a 64 x 64 buffer S, the rest update of panel p also
-// saves A[J_{p+1}, J_{p+2}] there, and panel p+1 runs its panel products and
-// the next panel's columns in one launch (k_gj_panel; the second entry of
-// that panel is then empty).
-static void gj_plan(double *A, int n, double *const Cb[2], double *S, std::vector<GemmDesc> &d, std::vector<int> &L)
+// Descriptors of the three GEMM launches of every panel of the (batched)
+// Gauss-Jordan sweep of A (n x n, leading dimension n): the panel products;
+// the update of the next panel's columns; the rest of the update (which runs
+// together with the next pivot step).  Panel p saves its old column block in
+// Cb[p & 1] (row stride nb), so the next pivot step can fill the other
+// buffer while the update still reads this one.  Each launch entry of L is
+// (offset, count, tiles).
+static void gj_plan(double *A, int n, double *const Cb[2], std::vector<GemmDesc> &d, std::vector<int> &L)
 {
     std::vector<GemmDesc> v;
     auto add = [&](double *C, const double *Aop, int lda, const double *B, int M, int N, int K, double al,
@@ -1300,41 +1381,107 @@ static void gj_plan(double *A, int n, double *const Cb[2], double *S, std::vecto
         add(A + j0, A + j0, n, Dq, j0, nb, nb, -1.0, 0.0);
         add(A + (size_t)(j0 + nb) * n + j0, A + (size_t)(j0 + nb) * n + j0, n, Dq, rest, nb, nb, -1.0, 0.0);
         // A[~J,~J] -= Cb[~J] A[J,~J]: first the next panel's columns, then the rest
-        const bool merged = S != nullptr && p > 0;   // A[J,J2] saved by the previous panel's update
-        if (!merged) flush();
+        flush();
         const int r0[2] = {0, j0 + nb}, rn[2] = {j0, rest};
-        for (int u = 0; u < 2; ++u) {
-            const size_t before = v.size();
+        for (int u = 0; u < 2; ++u)
             add(A + (size_t)r0[u] * n + j0 + nb, Cbp + (size_t)r0[u] * nb, nb, rowJ + j0 + nb, rn[u], nb2, nb, -1.0,
                 1.0);
-            if (merged && v.size() > before) {
-                v.back().B = nullptr;
-                v.back().pre = Dq;
-                v.back().S = S;
-            }
-        }
         flush();
-        if (merged) flush();   // the second entry stays empty
         const int c0[2] = {0, j0 + nb + nb2}, cn[2] = {j0, rest - nb2};
         for (int u = 0; u < 2; ++u)
-            for (int w = 0; w < 2; ++w) {
-                const size_t before = v.size();
+            for (int w = 0; w < 2; ++w)
                 add(A + (size_t)r0[u] * n + c0[w], Cbp + (size_t)r0[u] * nb, nb, rowJ + c0[w], rn[u], cn[w], nb, -1.0,
                     1.0);
-                // its first tile is A[J_{p+1}, J_{p+2}]: rows from j0 + nb, columns from j0 + nb + nb2
-                if (S != nullptr && u == 1 && w == 1 && v.size() > before) v.back().copy = S;
-            }
         flush();
     }
 }
 
-// Buffers of the Gauss-Jordan sweeps of chain `ch` (the block-tridiagonal
-// form runs two elimination chains at once; everything else uses chain 0):
-// the two saved column blocks (m x kNB each), then the saved pivot-row tile
-// (64 x 64).
-static double *gj_buf(const cams_ctx *c, int m, int ch)
+// Descriptors of the symmetric sweep of A (n x n): three launch entries per
+// panel p, each (offset, count, tiles) in L:
+//   1. G = Cb D^-1 and the panel: A[I,J] = -Cb_I D^-1 (I > J),
+//      A[J,K] = -D^-1 CbT_K (K < J); in the same launch the lower tiles of
+//      the next panel's row (K < J) and column (I >= J2), whose tiles form
+//      their rows of G themselves (pre = D^-1, S = Cb: k_gj_panel_sym);
+//   2. empty;
+//   3. the other lower tiles outside J (launched with the next pivot step).
+// Cb[p & 1] / CbT[p & 1] hold panel p's old column block (row stride nb) and
+// its transpose (row stride n); G (row stride nb) is rewritten per panel.
+static void gj_plan_sym(double *A, int n, double *const Cb[2], double *const CbT[2], double *G,
+                        std::vector<GemmDesc> &d, std::vector<int> &L)
 {
-    return c->a.gjcb + (size_t)ch * ((size_t)2 * m * kNB + 64 * 64);
+    std::vector<GemmDesc> v;
+    auto add = [&](double *C, int ldc, const double *Aop, int lda, const double *B, int ldb, int M, int N, int K,
+                   double al, double be, int tri) {
+        if (M <= 0 || N <= 0 || K <= 0) return;
+        GemmDesc g{};
+        g.C = C;
+        g.A = Aop;
+        g.B = B;
+        g.ldc = ldc;
+        g.lda = lda;
+        g.ldb = ldb;
+        g.M = M;
+        g.N = N;
+        g.K = K;
+        g.alpha = al;
+        g.beta = be;
+        g.tiles_n = (int)cdiv(N, 64);
+        g.tri = tri;
+        v.push_back(g);
+    };
+    auto flush = [&]() {
+        int tiles = 0;
+        for (GemmDesc &g : v) {
+            g.tile0 = tiles;
+            tiles += g.tri ? g.tiles_n * (g.tiles_n + 1) / 2 : g.tiles_n * (int)cdiv(g.M, 64);
+        }
+        L.push_back((int)d.size());
+        L.push_back((int)v.size());
+        L.push_back(tiles);
+        d.insert(d.end(), v.begin(), v.end());
+        v.clear();
+    };
+    for (int p = 0, j0 = 0; j0 < n; ++p, j0 += kNB) {
+        const int nb = std::min(kNB, n - j0), j1 = j0 + nb, rest = n - j1;
+        const int nb1 = std::min(kNB, rest), j2 = j1 + nb1;   // next panel (width 0 after the last)
+        double *const cb = Cb[p & 1], *const cbt = CbT[p & 1];
+        const double *Dq = A + (size_t)j0 * n + j0;
+        // 1. G rows outside J, then the two parts of the panel
+        add(G, nb, cb, nb, Dq, n, j0, nb, nb, 1.0, 0.0, 0);
+        add(G + (size_t)j1 * nb, nb, cb + (size_t)j1 * nb, nb, Dq, n, rest, nb, nb, 1.0, 0.0, 0);
+        add(A + (size_t)j1 * n + j0, n, cb + (size_t)j1 * nb, nb, Dq, n, rest, nb, nb, -1.0, 0.0, 0);
+        add(A + (size_t)j0 * n, n, Dq, n, cbt, n, nb, j0, nb, -1.0, 0.0, 0);
+        // next panel's row (K < J: s_K = -1) and column (rows from J2 on: s_K = +1),
+        // the A operand G_I formed per tile as Cb_I D^-1
+        const size_t before = v.size();
+        add(A + (size_t)j1 * n, n, nullptr, nb, cbt, n, nb1, j0, nb, 1.0, 1.0, 0);
+        add(A + (size_t)j1 * n + j1, n, nullptr, nb, cbt + j1, n, rest, nb1, nb, -1.0, 1.0, 0);
+        for (size_t i = before; i < v.size(); ++i) {
+            v[i].pre = Dq;
+            v[i].S = cb + (size_t)j1 * nb;
+        }
+        flush();
+        flush();   // the second entry stays empty
+        // 3. the rest: K < J (triangle above J, rectangle below the next row), K > J2 (triangle)
+        add(A, n, G, nb, cbt, n, j0, j0, nb, 1.0, 1.0, 1);
+        add(A + (size_t)j2 * n, n, G + (size_t)j2 * nb, nb, cbt, n, n - j2, j0, nb, 1.0, 1.0, 0);
+        add(A + (size_t)j2 * n + j2, n, G + (size_t)j2 * nb, nb, cbt + j2, n, n - j2, n - j2, nb, -1.0, 1.0, 1);
+        flush();
+    }
+}
+
+// Buffers of the symmetric sweeps of chain `ch` (the block-tridiagonal form
+// runs two elimination chains at once; everything else uses chain 0): the
+// two old column blocks (m x kNB each), their transposes (kNB x m each) and
+// G (m x kNB).
+struct GjBufs {
+    double *Cb[2], *CbT[2], *G;
+};
+static GjBufs gj_bufs(const cams_ctx *c, int m, int ch)
+{
+    const size_t blk = (size_t)m * kNB;
+    double *const base = c->a.gjcb + (size_t)ch * (5 * blk + 64 * 64);
+    return GjBufs{{base, base + blk}, {base + 2 * blk, base + 3 * blk}, base + 4 * blk};
 }
 
 // The descriptors of every matrix the factorisation inverts, uploaded once
@@ -1346,9 +1493,8 @@ static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, const std
     std::vector<GemmDesc> d;
     c->gj_launch.clear();
     for (size_t i = 0; i < mats.size(); ++i) {
-        double *const base = gj_buf(c, m, chains[i]);
-        double *const Cb[2] = {base, base + (size_t)m * kNB};
-        gj_plan(mats[i], m, Cb, base + (size_t)2 * m * kNB, d, c->gj_launch);
+        const GjBufs b = gj_bufs(c, m, chains[i]);
+        gj_plan_sym(mats[i], m, b.Cb, b.CbT, b.G, d, c->gj_launch);
     }
     if (!d.empty())
         CAMS_HIP(hipMemcpyAsync(c->a.gjd, d.data(), d.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, c->stream));
@@ -1356,42 +1502,38 @@ static void gj_prepare(cams_ctx *c, const std::vector<double *> &mats, const std
     c->gj_ready = true;
 }
 
-// In-place inverse of matrix `mat` (the mat-th of gj_prepare's list), m x m.
-// Per panel: the panel products and the update of the next panel's columns
-// (one launch from the second panel on), then the rest of the update
-// together with the next pivot step.  Enqueued on stream st with the
-// buffers of chain ch (as given to gj_prepare for this matrix).
+// In-place inverse of matrix `mat` (the mat-th of gj_prepare's list), m x m,
+// by the symmetric sweep: the first pivot step, then per panel the panel
+// products with the next panel's row and column (one launch), and the rest
+// of the update together with the next pivot step; finally the lower
+// triangle is copied to the upper one.  Enqueued on stream st with the buffers of chain ch (as
+// given to gj_prepare for this matrix).
 static void inverse_gj(cams_ctx *c, double *A, int m, int mat, int ch, hipStream_t st)
 {
     const int panels = (m + kNB - 1) / kNB;
     const GemmDesc *dd = (const GemmDesc *)c->a.gjd;
-    double *const base = gj_buf(c, m, ch);
-    double *const Cb[2] = {base, base + (size_t)m * kNB};
-    k_gj_pivot<<<gj_pivot_wgs(m, std::min(kNB, m)), kBlock, 0, st>>>(A, m, 0, std::min(kNB, m), Cb[0],
-                                                                    c->a.status);
+    const GjBufs b = gj_bufs(c, m, ch);
+    const int nb0 = std::min(kNB, m);
+    k_gj_pivot_sym<<<gj_pivot_wgs(m, nb0), kBlock, 0, st>>>(A, m, 0, nb0, b.Cb[0], b.CbT[0], c->a.status);
     for (int p = 0; p < panels; ++p) {
         const int *e = &c->gj_launch[3 * 3 * (mat * panels + p)];
-        if (e[1] > 0) {
-            if (p > 0) k_gj_panel<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
-            else kb_gemm<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
-        }
-        e += 3;
-        if (e[1] > 0) kb_gemm<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
-        e += 3;
+        if (e[1] > 0) k_gj_panel_sym<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
+        e += 6;   // the second entry is empty
         const int j1 = (p + 1) * kNB;
         if (j1 < m) {
-            const int nb1 = std::min(kNB, m - j1);
+            const int nb1 = std::min(kNB, m - j1), q = (p + 1) & 1;
             const unsigned pw = gj_pivot_wgs(m, nb1);
-            if (e[2] >= kWideTiles)
-                k_gj_update_pivot_wide<<<pw + e[2], kBlock, 0, st>>>(dd + e[0], e[1], (int)pw, A, m, j1, nb1,
-                                                                     Cb[(p + 1) & 1], c->a.status);
+            if (e[2] >= kWideTilesSym)
+                k_gj_update_pivot_sym_wide<<<pw + e[2], kBlock, 0, st>>>(dd + e[0], e[1], (int)pw, A, m, j1, nb1,
+                                                                         b.Cb[q], b.CbT[q], c->a.status);
             else
-                k_gj_update_pivot<<<pw + e[2], kBlock, 0, st>>>(dd + e[0], e[1], (int)pw, A, m, j1, nb1,
-                                                                Cb[(p + 1) & 1], c->a.status);
+                k_gj_update_pivot_sym<<<pw + e[2], kBlock, 0, st>>>(dd + e[0], e[1], (int)pw, A, m, j1, nb1,
+                                                                    b.Cb[q], b.CbT[q], c->a.status);
         } else if (e[1] > 0) {
             kb_gemm<<<e[2], kBlock, 0, st>>>(dd + e[0], e[1]);
         }
     }
+    if (panels > 1) k_mirror_lower<<<panels * (panels - 1) / 2, kBlock, 0, st>>>(A, m);
 }
 
 // ---- batched MSFE factorisation: the Gauss-Jordan sweeps of every FE
@@ -1427,7 +1569,7 @@ void plan_batch_gj(const std::vector<cams_ctx *> &fe, BatchGjPlan &plan)
         const cams_ctx *c = fe[i];
         double *Cb[2];
         batch_gj_cb(c, Cb);
-        gj_plan(c->a.Ainv, c->g.Nc, Cb, nullptr, d[i], L[i]);
+        gj_plan(c->a.Ainv, c->g.Nc, Cb, d[i], L[i]);
         maxP = std::max(maxP, (c->g.Nc + kNB - 1) / kNB);
     }
     // pivot steps of panel p of every instance that has it
