@@ -330,6 +330,26 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
             t.tab.push_back(x);
         }
     }
+    // x-groups of boxes for the row form of the residual-restriction: greedy,
+    // at most kRowBoxes boxes and kRowCells cells per group
+    {
+        const int nbx = nb[0];
+        std::vector<int32_t> obx(t.tab.begin() + t.tab_off[0][3], t.tab.begin() + t.tab_off[0][3] + nbx + 1);
+        for (int v = 0; v < 2; ++v) {
+            auto xs = [&](int b) { return v == 1 ? obx[b] : std::min(b * r[0], n[0]); };
+            std::vector<int32_t> starts{0};
+            bool ok = true;
+            for (int b = 0; b < nbx && ok; ++b) {
+                if (xs(b + 1) - xs(b) > kRowCells) ok = false;
+                const int g0 = starts.back();
+                if (b > g0 && (b + 1 - g0 > kRowBoxes || xs(b + 1) - xs(g0) > kRowCells)) starts.push_back(b);
+            }
+            starts.push_back(nbx);
+            t.tab_gx[v] = t.tab.size();
+            c->g.ngx[v] = ok ? (int)starts.size() - 1 : 0;
+            for (int32_t x : starts) t.tab.push_back(x);
+        }
+    }
     // dual regions by number of open axes
     std::vector<Region> by[4];
     for (const Segment &sz : seg[2])
@@ -595,6 +615,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
         c->g.isv[ax] = (const uint8_t *)(a.tab + t.tab_off[ax][2]);
         c->g.ob[ax] = a.tab + t.tab_off[ax][3];
     }
+    for (int v = 0; v < 2; ++v) c->g.gx[v] = a.tab + t.tab_gx[v];
     try {
         CAMS_HIP(hipMemcpyAsync(a.tab, t.tab.data(), t.tab.size() * 4, hipMemcpyHostToDevice, c->stream));
         if (!t.regions.empty())

@@ -20,6 +20,11 @@ constexpr double kStagDrop = 0.9;
 // Grid descriptor passed by value to kernels.  Per-axis tables live in the
 // workspace: vertex coordinates (nb entries), "is vertex coordinate" flags
 // and the lower bracketing vertex of every coordinate (n entries).
+// Row form of the residual-restriction: a workgroup takes up to kRowBoxes
+// consecutive boxes along x whose cells fit rows of kRowCells.
+constexpr int kRowCells = 32;
+constexpr int kRowBoxes = 8;
+
 struct GridDev {
     int nx, ny, nz, N, sxy;
     double dx, dy, dz, dV;
@@ -31,6 +36,12 @@ struct GridDev {
     const int32_t *lo[3];
     const uint8_t *isv[3];
     const int32_t *ob[3];   // restriction-owner box starts per axis (nb + 1 entries)
+    // Groups of consecutive boxes along x whose cells fit a 32-cell row, for
+    // the row form of the residual-restriction: gx[v] holds the first box of
+    // each group (ngx[v] + 1 entries) over the primal blocks (v = 0) or the
+    // owner boxes of the table ob (v = 1); ngx[v] = 0 when a box is wider.
+    const int32_t *gx[2];
+    int ngx[2];
 };
 
 struct Fluid {
@@ -212,6 +223,7 @@ struct cams_ctx {
     std::vector<int32_t> tab;
     std::vector<cams::Region> regions;
     size_t tab_off[3][4];
+    size_t tab_gx[2];
     // timing of one kernel class for measurement (cams_profile)
     int prof_kernel;
     std::vector<hipEvent_t> prof_ev;        // pool: pairs (start, stop)

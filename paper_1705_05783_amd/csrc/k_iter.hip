@@ -301,6 +301,75 @@ __global__ __launch_bounds__(kBoxThreads) void k_residual_restrict(GridDev g, co
                                                xcd_swizzle(blockIdx.x, gridDim.x), sh);
 }
 
+// The same for a group of consecutive boxes along x (the table gx), so that
+// the loads and stores of a wave run along rows of up to 32 cells instead of
+// one box's rows of about 8: thread t takes column t % 32 of the group's
+// rows and every 16th row (y fastest, then z), so all its cells lie in one
+// box.  The per-box sums go through LDS: each wave then reduces some of the
+// (box, slot) pairs over that box's threads in a fixed order.
+constexpr int kRowThreads = 512;
+
+template <class TA, int NV, class TP>
+__global__ __launch_bounds__(kRowThreads) void k_residual_restrict_row(
+    GridDev g, const double *__restrict__ W, const double *__restrict__ diag, const double *__restrict__ r0,
+    Pending<TA, NV> v, double *__restrict__ dp_out, double *__restrict__ r, float *__restrict__ rf,
+    double *__restrict__ partial, const uint8_t *__restrict__ dm, const TP *__restrict__ P, int fe,
+    double *__restrict__ slots, const int32_t *ictl)
+{
+    constexpr int NT = kRowThreads, RW = NT / kRowCells;   // rows per pass (16)
+    __shared__ double red[9][NT];
+    if (ictl[C_DONE]) return;
+    v.fold = ictl[C_IT] > 0;
+    const int vi = fe ? 1 : 0, ngx = g.ngx[vi];
+    const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int gi = wg % ngx, kb = (wg / ngx) % g.nb[1], kc = wg / (ngx * g.nb[1]);
+    const int ka0 = g.gx[vi][gi], nbox = g.gx[vi][gi + 1] - ka0;
+    auto xs = [&](int b) { return fe ? g.ob[0][b] : min(b * g.r[0], g.nx); };
+    const int x0 = xs(ka0), ex = xs(ka0 + nbox) - x0;
+    const int y0 = fe ? g.ob[1][kb] : kb * g.r[1], z0 = fe ? g.ob[2][kc] : kc * g.r[2];
+    const int ey = (fe ? g.ob[1][kb + 1] : min(y0 + g.r[1], g.ny)) - y0;
+    const int ez = (fe ? g.ob[2][kc + 1] : min(z0 + g.r[2], g.nz)) - z0;
+    const int tid = threadIdx.x, lx = tid % kRowCells, row0 = tid / kRowCells;
+    const bool colx = lx < ex;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double e2 = 0.0;
+    const int rows = ey * ez;
+    for (int R = row0; colx && R < rows; R += RW) {
+        const int x = x0 + lx, y = y0 + R % ey, z = z0 + R / ey;
+        const int n = x + g.nx * (y + g.ny * z);
+        TP pv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[q] = P[(size_t)q * g.N + n];
+        const bool keep = !dm[n];
+        const double rn = residual_cell(g, W, diag, r0, v, dp_out, r, rf, n, x, y, z);
+        e2 += rn * rn;
+        if (fe) {
+            const double wn = keep ? rn : 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += basis_value(pv + q, 0) * wn;
+        } else {
+            acc[0] += rn;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][tid] = acc[q];
+    red[8][tid] = e2;
+    __syncthreads();
+    const int lane = tid & 63, w = tid >> 6;
+    for (int pr = w; pr < 9 * nbox; pr += NT / 64) {
+        const int b = pr / 9, q = pr % 9;
+        const int c0 = xs(ka0 + b) - x0, wdt = xs(ka0 + b + 1) - x0 - c0;
+        double sum = 0.0;
+        for (int u = lane; u < wdt * RW; u += 64) sum += red[q][(u / wdt) * kRowCells + c0 + u % wdt];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+            const int k = (ka0 + b) + g.nb[0] * (kb + g.nb[1] * kc);
+            if (q < 8) slots[(size_t)k * 8 + q] = sum;
+            else partial[k] = sum;
+        }
+    }
+}
+
 // ---- batched forms: one launch covers every instance of a batch; the work
 // item of a workgroup names the instance and the block within it, and
 // workgroups of instances that have converged return at once.
@@ -454,6 +523,22 @@ void residual_restrict(cams_ctx *c, const Pending<TA, NV> &v, double *dp_out, fl
     const GridDev &g = c->g;
     const Arrays &a = c->a;
     const int fe = c->opt.restriction == CAMS_R_FE;
+    const int ngx = g.ngx[fe];
+    // the row form where every box fits a 32-cell row (FP32 / BF16 at 128^3:
+    // 90 -> 77 us; 256x256x128: 358 -> 268 us), else one workgroup per box
+    if (ngx > 0) {
+        const unsigned wgs = (unsigned)ngx * g.nb[1] * g.nb[2];
+        if (c->opt.precision == CAMS_MIXED_BF16)
+            k_residual_restrict_row<TA, NV, uint16_t><<<wgs, kRowThreads, 0, c->stream>>>(
+                g, a.W, a.diag, a.r0, v, dp_out, a.r, rf, a.partial, a.dmask, a.Pbf, fe, a.slots, a.ictl);
+        else if (c->opt.precision == CAMS_MIXED_FP32)
+            k_residual_restrict_row<TA, NV, float><<<wgs, kRowThreads, 0, c->stream>>>(
+                g, a.W, a.diag, a.r0, v, dp_out, a.r, rf, a.partial, a.dmask, a.P32, fe, a.slots, a.ictl);
+        else
+            k_residual_restrict_row<TA, NV, double><<<wgs, kRowThreads, 0, c->stream>>>(
+                g, a.W, a.diag, a.r0, v, dp_out, a.r, rf, a.partial, a.dmask, a.P, fe, a.slots, a.ictl);
+        return;
+    }
     if (c->opt.precision == CAMS_MIXED_BF16)
         k_residual_restrict<TA, NV, uint16_t><<<g.Nc, kBoxThreads, 0, c->stream>>>(g, a.W, a.diag, a.r0, v, dp_out, a.r, rf,
                                                                            a.partial, a.dmask, a.Pbf, fe, a.slots,
