@@ -485,13 +485,23 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes);
 cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_dev, double *const *p_dev,
                                         int32_t *status_out, cams_stats *stats);
 /* Tuning outcome (0 / unset before the first call): iterations per graph
- * replay and the smoother's threads per 8x8x8 block, with the measured ms
- * per batched iteration of the graph candidates (2, 4, 8 iterations per
- * graph) and ms per smoothing step of the workgroup candidates (128, 256,
- * 512 threads); `ncand` entries of each array are written (arrays nullable). */
+ * replay, and the smoother's workgroup: threads per workgroup and 8x8x8
+ * blocks per workgroup (1, or 4 neighbouring blocks along x); with the
+ * measured ms per batched iteration of the graph candidates (2, 4, 8
+ * iterations per graph, up to 3 entries) and ms per smoothing step of the
+ * smoother candidates (128, 256, 512 threads per block, then 4 blocks per
+ * 512 threads, FP32 only and 0 when not measured; up to 4 entries); at most
+ * `ncand` entries of each array are written (pointers nullable). */
 cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, int32_t *smoother_threads,
-                              double *ms_per_iter_candidates, double *ms_per_smooth_step_candidates,
-                              int32_t ncand);
+                              int32_t *smoother_blocks, double *ms_per_iter_candidates,
+                              double *ms_per_smooth_step_candidates, int32_t ncand);
+/* Fix the smoother form instead of the tuner's choice: `threads` per
+ * workgroup and `blocks` 8x8x8 blocks per workgroup, one of (128, 1),
+ * (256, 1), (512, 1) and, in mixed precision, (512, 4); (0, 0) returns to
+ * the tuned choice.  The iterations are captured (and the graph length
+ * tuned) again on the next call.  For reproducible timings and for tests
+ * of each form.  Errors: CAMS_E_ARG (another pair). */
+cams_status cams_batch_set_smoother(cams_batch *b, int32_t threads, int32_t blocks);
 const char *cams_batch_last_error(const cams_batch *b);
 void cams_batch_destroy(cams_batch *b);
 

@@ -134,7 +134,9 @@ _SIGS = [
     ("cams_batch_newton_iteration", _I, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(cams_stats)]),
     ("cams_batch_tuning", _I, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+    ("cams_batch_set_smoother", _I, [_VP, ctypes.c_int32, ctypes.c_int32]),
     ("cams_batch_last_error", ctypes.c_char_p, [_VP]),
     ("cams_batch_destroy", None, [_VP]),
 ]

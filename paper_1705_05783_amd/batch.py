@@ -61,13 +61,19 @@ class Batch:
             _check(status, self.handle, "cams_batch_newton_iteration")
         return list(st), [s.as_dict() for s in stats]
 
+    def set_smoother(self, threads, blocks):
+        """Fix the smoother form ((128|256|512, 1), or (512, 4) in mixed
+        precision); (0, 0) returns to the tuner's choice."""
+        _check(C.cams_batch_set_smoother(self.handle, int(threads), int(blocks)), self.handle,
+               "cams_batch_set_smoother")
+
     def tuning(self):
-        k, nt = ctypes.c_int32(), ctypes.c_int32()
-        ms, sm = (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
-        _check(C.cams_batch_tuning(self.handle, ctypes.byref(k), ctypes.byref(nt), ms, sm, 3), self.handle,
-               "cams_batch_tuning")
-        return {"iters_per_graph": k.value, "smoother_threads": nt.value, "ms_per_iter": list(ms),
-                "ms_per_smooth_step": list(sm)}
+        k, nt, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms, sm = (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
+        _check(C.cams_batch_tuning(self.handle, ctypes.byref(k), ctypes.byref(nt), ctypes.byref(nb), ms, sm, 4),
+               self.handle, "cams_batch_tuning")
+        return {"iters_per_graph": k.value, "smoother_threads": nt.value, "smoother_blocks": nb.value,
+                "ms_per_iter": list(ms)[:3], "ms_per_smooth_step": list(sm)}
 
     def close(self):
         if self.handle:

@@ -345,8 +345,12 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
                 if (b > g0 && (b + 1 - g0 > kRowBoxes || xs(b + 1) - xs(g0) > kRowCells)) starts.push_back(b);
             }
             starts.push_back(nbx);
+            if (!ok) {   // cannot happen with ratios up to kMaxRatio (boxes of at most 12 cells)
+                delete c;
+                return CAMS_E_ARG;
+            }
             t.tab_gx[v] = t.tab.size();
-            c->g.ngx[v] = ok ? (int)starts.size() - 1 : 0;
+            c->g.ngx[v] = (int)starts.size() - 1;
             for (int32_t x : starts) t.tab.push_back(x);
         }
     }
@@ -509,6 +513,10 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     }
     put(L.add((size_t)2 * G.ny * G.nz * 8));   // 52 Tb: west and east boundary-face transmissibilities
     put(L.add(O.coarse_tol > 0 ? nc * 27 * 8 : 0));   // 53 Acs: coarse operator at its last factorisation
+    {   // 54 tile partials of the symmetric coarse GEMV (dense MSFE inverses above kGemvLds nodes)
+        const size_t T = (nc + 63) / 64;
+        put(L.add(O.restriction == CAMS_R_FE && !c->blocktri && nc > (size_t)kGemvLds ? T * T * 64 * 8 : 0));
+    }
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
         return CAMS_E_NOMEM;
@@ -587,6 +595,7 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.rlist = (Region *)(w + off[51]);
     a.Tb = (double *)(w + off[52]);
     a.Acs = (double *)(w + off[53]);
+    a.gpart = (double *)(w + off[54]);
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {

@@ -37,8 +37,10 @@ namespace {
 constexpr int kSide = 4;                     // setup streams (the device has 4 hardware queues per process)
 constexpr int kGraphIters[] = {2, 4, 8};     // candidates of the tuner (even: the ping-pong parity repeats)
 constexpr int kNumCand = 3;
-constexpr int kSmoothNT[] = {128, 256, 512};   // smoother workgroup sizes the tuner compares
-constexpr int kNumSmooth = 3;
+// smoother forms the tuner compares: 128, 256 or 512 threads per block, and
+// (FP32 only) four blocks along x per 512-thread workgroup (0)
+constexpr int kSmoothNT[] = {128, 256, 512, 0};
+constexpr int kNumSmooth = 4;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -52,7 +54,7 @@ int xcd_swizzle_host(int wg, int n)
     return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
-enum { L_FLAT = 0, L_SBLOCK, L_RESTRICT, L_NODES, L_ROWS, L_NUM };
+enum { L_FLAT = 0, L_SBLOCK, L_RESTRICT, L_NODES, L_ROWS, L_SROW, L_NUM };
 
 }  // namespace
 
@@ -116,6 +118,7 @@ struct cams_batch {
     int chosen = -1;                 // index into kGraphIters once tuned
     double tune_ms[kNumCand] = {};   // ms per iteration of each candidate (first call)
     int smooth_nt = 512;             // threads per smoother block (tuned on the first call)
+    int forced_nt = -1;              // smoother form set by the caller (-1: tuned)
     double smooth_ms[kNumSmooth] = {};
     std::string err;
     float t_setup_ms = 0.f, t_iter_ms = 0.f;
@@ -143,15 +146,16 @@ void enqueue_batch_iteration(cams_batch *b, int par, bool prime = false)
     const int count = (int)b->ctx.size();
     launch_batch_residual(L(b, L_FLAT, prime), par, b->mixed, b->n_pre > 0);
     if (!prime) launch_batch_finalize(b->inst, count, b->stream);
+    const int sl = b->smooth_nt == 0 ? L_SROW : L_SBLOCK;
     if (b->n_pre > 0) {
-        launch_batch_smooth(L(b, L_SBLOCK, prime), b->n_pre, 0, b->mixed, b->smooth_nt);
+        launch_batch_smooth(L(b, sl, prime), b->n_pre, 0, b->mixed, b->smooth_nt);
         launch_batch_sub_pre(L(b, L_FLAT, prime), b->mixed);
     }
     launch_batch_restrict(L(b, L_RESTRICT, prime), b->precision);
     launch_batch_node_sum(L(b, L_NODES, prime));
     launch_batch_gemv(L(b, L_ROWS, prime));
     launch_batch_prolong(L(b, L_FLAT, prime), b->mixed, b->bf16);
-    if (b->n_post > 0) launch_batch_smooth(L(b, L_SBLOCK, prime), b->n_post, 1, b->mixed, b->smooth_nt);
+    if (b->n_post > 0) launch_batch_smooth(L(b, sl, prime), b->n_post, 1, b->mixed, b->smooth_nt);
 }
 
 WorkItem *host_list(cams_batch *b, int l);
@@ -230,9 +234,11 @@ void tune_smoother(cams_batch *b)
     const int kind = b->n_post > 0 ? 1 : 0;
     int best = 0;
     for (int k = 0; k < kNumSmooth; ++k) {
-        launch_batch_smooth(L(b, L_SBLOCK), steps, kind, b->mixed, kSmoothNT[k]);   // warm
+        if (kSmoothNT[k] == 0 && !b->mixed) continue;   // the row form is FP32 only
+        const int sl = kSmoothNT[k] == 0 ? L_SROW : L_SBLOCK;
+        launch_batch_smooth(L(b, sl), steps, kind, b->mixed, kSmoothNT[k]);   // warm
         CAMS_HIP(hipEventRecord(b->ev[2], b->stream));
-        launch_batch_smooth(L(b, L_SBLOCK), steps, kind, b->mixed, kSmoothNT[k]);
+        launch_batch_smooth(L(b, sl), steps, kind, b->mixed, kSmoothNT[k]);
         CAMS_HIP(hipEventRecord(b->ev[3], b->stream));
         CAMS_HIP(hipEventSynchronize(b->ev[3]));
         float ms = 0.f;
@@ -314,6 +320,8 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         for (int k = 0; k < nflat; ++k) b->lists[L_FLAT].push_back({i, k});
         const int nsb = ((g.nx + 7) / 8) * ((g.ny + 7) / 8) * ((g.nz + 7) / 8);
         for (int k = 0; k < nsb; ++k) b->lists[L_SBLOCK].push_back({i, k});
+        const int nsrow = ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * ((g.nz + 7) / 8);   // groups of 4 x-blocks
+        for (int k = 0; k < nsrow; ++k) b->lists[L_SROW].push_back({i, k});
         for (int k = 0; k < g.Nc; ++k) b->lists[L_RESTRICT].push_back({i, k});
         for (int k = 0; k < (g.Nc + kBlock - 1) / kBlock; ++k) b->lists[L_NODES].push_back({i, k});
         for (int k = 0; k < (g.Nc + kBlock / 64 - 1) / (kBlock / 64); ++k) b->lists[L_ROWS].push_back({i, k});
@@ -342,7 +350,7 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
             const size_t T = (ctxs[i]->g.Nc + 63) / 64;
             b->fe.push_back(ctxs[i]);
             b->lu_steps_cap += T;        // one pivot step per panel
-            b->lu_gemms_cap += 10 * T;   // per panel at most: 4 panel products, 2 + 4 update blocks
+            b->lu_gemms_cap += 10 * T + 1;   // per panel at most 9 descriptors, and the mirror
         }
     b->off_lu_steps = o;
     o = align_up(o + b->lu_steps_cap * sizeof(GjPivotDesc));
@@ -499,7 +507,8 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
         for (char k : b->listed) all_listed = all_listed && k;
         if (!all_listed) upload_lists(b, std::vector<char>(count, 1));
         if (!b->exec[0]) {
-            tune_smoother(b);
+            if (b->forced_nt >= 0) b->smooth_nt = b->forced_nt;
+            else tune_smoother(b);
             for (int k = 0; k < kNumCand; ++k) b->exec[k] = capture(b, kGraphIters[k]);
         }
         if (b->chosen < 0) tune(b);
@@ -580,15 +589,38 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
 }
 
 cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, int32_t *smoother_threads,
-                              double *ms_per_iter_candidates, double *ms_per_smooth_step_candidates, int32_t ncand)
+                              int32_t *smoother_blocks, double *ms_per_iter_candidates,
+                              double *ms_per_smooth_step_candidates, int32_t ncand)
 {
     if (!b) return CAMS_E_ARG;
     if (iters_per_graph) *iters_per_graph = b->chosen >= 0 ? kGraphIters[b->chosen] : 0;
-    if (smoother_threads) *smoother_threads = b->exec[0] ? b->smooth_nt : 0;
-    for (int k = 0; k < std::min<int>(ncand, kNumCand); ++k) {
+    const bool row = b->smooth_nt == 0;
+    if (smoother_threads) *smoother_threads = b->exec[0] ? (row ? 512 : b->smooth_nt) : 0;
+    if (smoother_blocks) *smoother_blocks = b->exec[0] ? (row ? 4 : 1) : 0;
+    for (int k = 0; k < std::min<int>(ncand, kNumCand); ++k)
         if (ms_per_iter_candidates) ms_per_iter_candidates[k] = b->tune_ms[k];
+    for (int k = 0; k < std::min<int>(ncand, kNumSmooth); ++k)
         if (ms_per_smooth_step_candidates) ms_per_smooth_step_candidates[k] = b->smooth_ms[k];
-    }
+    return CAMS_OK;
+}
+
+cams_status cams_batch_set_smoother(cams_batch *b, int32_t threads, int32_t blocks)
+{
+    if (!b) return CAMS_E_ARG;
+    int nt;
+    if (threads == 0 && blocks == 0) nt = -1;
+    else if (blocks == 1 && (threads == 128 || threads == 256 || threads == 512)) nt = threads;
+    else if (blocks == 4 && threads == 512 && b->mixed) nt = 0;
+    else return bfail(b, CAMS_E_ARG, "smoother form: (128|256|512, 1), (512, 4) in mixed precision, or (0, 0)");
+    if (nt == b->forced_nt) return CAMS_OK;
+    b->forced_nt = nt;
+    // the captured iterations hold the smoother launches: capture (and tune) again
+    for (int k = 0; k < kNumCand; ++k)
+        if (b->exec[k]) {
+            (void)hipGraphExecDestroy(b->exec[k]);
+            b->exec[k] = nullptr;
+        }
+    b->chosen = -1;
     return CAMS_OK;
 }
 

@@ -23,6 +23,9 @@ constexpr double kStagDrop = 0.9;
 // Row form of the residual-restriction: a workgroup takes up to kRowBoxes
 // consecutive boxes along x whose cells fit rows of kRowCells.
 constexpr int kRowCells = 32;
+// Coarse sizes up to which every coarse-GEMV workgroup forms R r itself;
+// larger dense MSFE inverses take the symmetric tile GEMV.
+constexpr int kGemvLds = 1024;
 constexpr int kRowBoxes = 8;
 
 struct GridDev {
@@ -37,9 +40,9 @@ struct GridDev {
     const uint8_t *isv[3];
     const int32_t *ob[3];   // restriction-owner box starts per axis (nb + 1 entries)
     // Groups of consecutive boxes along x whose cells fit a 32-cell row, for
-    // the row form of the residual-restriction: gx[v] holds the first box of
-    // each group (ngx[v] + 1 entries) over the primal blocks (v = 0) or the
-    // owner boxes of the table ob (v = 1); ngx[v] = 0 when a box is wider.
+    // the residual-restriction: gx[v] holds the first box of each group
+    // (ngx[v] + 1 entries) over the primal blocks (v = 0) or the owner boxes
+    // of the table ob (v = 1).
     const int32_t *gx[2];
     int ngx[2];
 };
@@ -96,6 +99,7 @@ struct Arrays {
     double *bcoef, *bdiag, *bsnap, *bdsnap;
     double *Tb;       // 2 ny nz: half-cell transmissibilities of the west and east boundary faces
     double *Acs;      // 27 Nc: the coarse operator's 27-point entries when it was last factorised
+    double *gpart;    // T^2 x 64 (T = ceil(Nc / 64)): tile partials of the symmetric coarse GEMV
     int32_t *rflag;
     Region *rlist;
     // mixed precision copies
@@ -373,7 +377,7 @@ void cnn_block_residual(cams_ctx *c, const Region *regs, int nblk, double *ratio
 // into Cb; its workgroups are wg0 .. wg0 + 1 + ceil((n - nb) nb / 256) - 1
 // of the launch.
 struct GjPivotDesc {
-    double *A, *Cb;
+    double *A, *Cb, *CbT;
     int32_t *status;
     int n, j0, nb, wg0;
 };
@@ -394,7 +398,7 @@ struct GemmDesc {
     int tri;
 };
 struct BatchGjPlan {
-    enum Kind { PIVOT = 0, GEMM = 1, UPDATE_PIVOT = 2 };
+    enum Kind { PIVOT = 0, PANEL = 1, UPDATE_PIVOT = 2, MIRROR = 3 };
     struct Launch {
         int kind;
         size_t poff;    // into piv

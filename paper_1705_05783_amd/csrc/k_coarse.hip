@@ -546,29 +546,15 @@ __global__ __launch_bounds__(kBlock) void k_trsm(const double *__restrict__ F, i
 // sweeps over 64-column panels J with D = A[J,J]:
 //   A[J,J] <- D^-1,  A[J,~J] <- D^-1 A[J,~J],  A[~J,J] <- -A[~J,J] D^-1,
 //   A[~J,~J] <- A[~J,~J] - A[~J,J]_old D^-1 A[J,~J]_old;
-// after the last panel A holds its inverse (2 n^3 flop, as LU plus inverse).
-// The batched sweeps take three launches per panel: the panel products, the
-// update of the next panel's columns, and the rest of the update together
-// with the next panel's pivot-block inverse (and the copy of its old column
-// block), so that the sequential pivot inverse overlaps the matrix-core
-// update.  Single matrices take the symmetric form of the sweep below.
+// after the last panel A holds its inverse.  The sweeps below keep only the
+// lower triangle (the symmetric form further down).
 
-// Workgroup 0: D^-1 of the nb x nb pivot block (padded to 64 x 64 with the
-// identity) by the same sweep on entries two at a time, 4 x 4 entries per
-// thread, the two pivot rows and columns through LDS (two buffers, one
-// barrier per pair of pivots); writes it into A[J,J].  Workgroups 1..: Cb[i][c] = A[i][j0 + c] for the
-// rows i outside J.
-__device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j0, int nb, double *__restrict__ Cb,
-                                            int32_t *status, int blk)
+// D^-1 of the nb x nb pivot block at (j0, j0) (padded to 64 x 64 with the
+// identity), by one workgroup: the same sweep on entries two at a time,
+// 4 x 4 entries per thread, the two pivot rows and columns through LDS (two
+// buffers, one barrier per pair of pivots); written into A[J,J].
+__device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j0, int nb, int32_t *status)
 {
-    if (blk > 0) {
-        const size_t t = (size_t)(blk - 1) * kBlock + threadIdx.x;
-        if (t >= (size_t)(n - nb) * nb) return;
-        const int rr = (int)(t / nb), cc = (int)(t % nb);
-        const int i = rr < j0 ? rr : rr + nb;
-        Cb[(size_t)i * nb + cc] = A[(size_t)i * n + j0 + cc];
-        return;
-    }
     __shared__ double colk[2][2][kNB], rowk[2][2][kNB];
     const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
     double a[4][4];
@@ -665,7 +651,8 @@ __device__ __forceinline__ void gj_pivot_wg(double *__restrict__ A, int n, int j
     if (bad && threadIdx.x == 0) atomicOr(status, F_SINGULAR_COARSE);
 }
 
-// Number of workgroups of a pivot step: the inverse and the column copy.
+// Number of workgroups of a pivot step: the inverse and the copies of the
+// old column block.
 inline unsigned gj_pivot_wgs(int n, int nb) { return 1 + (unsigned)(((size_t)(n - nb) * nb + kBlock - 1) / kBlock); }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -684,12 +671,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // latency hides behind the products (C is only written at the end, so an
 // aliased A or B is still read before it is overwritten).
 constexpr int KS = 32;
-// Batched update launches with at least this many GEMM tiles (four rounds
-// of two workgroups per compute unit) take the lean tile at three per unit;
-// the symmetric sweep's update launches from kWideTilesSym tiles on take it
-// at four per unit (a 4096^2 sweep: about 1950 tiles per launch, 49.6 ->
-// 41 us per launch).
-constexpr int kWideTiles = 2048;
+// Update launches of the symmetric sweep from kWideTilesSym tiles on take
+// the lean tile at four workgroups per compute unit (a 4096^2 sweep: about
+// 1950 tiles per launch, 49.6 -> 41 us per launch).
 constexpr int kWideTilesSym = 1024;
 
 //
@@ -821,12 +805,6 @@ __device__ __forceinline__ const GjPivotDesc &pivot_desc_of(const GjPivotDesc *_
     return p[lo];
 }
 
-__global__ __launch_bounds__(kBlock) void kb_gj_pivot(const GjPivotDesc *__restrict__ p, int np)
-{
-    const GjPivotDesc &q = pivot_desc_of(p, np, blockIdx.x);
-    gj_pivot_wg(q.A, q.n, q.j0, q.nb, q.Cb, q.status, blockIdx.x - q.wg0);
-}
-
 __global__ __launch_bounds__(kBlock) void kb_gemm(const GemmDesc *__restrict__ d, int nd)
 {
     // the descriptor whose tile range holds this workgroup (binary search on tile0)
@@ -840,44 +818,6 @@ __global__ __launch_bounds__(kBlock) void kb_gemm(const GemmDesc *__restrict__ d
     int tm, tn;
     tile_origin(g, blockIdx.x - g.tile0, tm, tn);
     gemm_tile(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, tm, tn);
-}
-
-// The update of one Gauss-Jordan panel of every instance of a batch
-// (outside the next panel's columns) and the next panel's pivot steps in one
-// launch: the first `pw` workgroups are the pivot steps of the next panel of
-// every instance that has one (the next pivot block and its column block are
-// final before the launch, so the sequential pivot inverse runs while the
-// matrix cores update the rest), the others GEMM tiles.
-template <bool LEAN>
-__device__ __forceinline__ void gjb_update_pivot_body(const GjPivotDesc *__restrict__ p, int np, int pw,
-                                                      const GemmDesc *__restrict__ d, int nd)
-{
-    if ((int)blockIdx.x < pw) {
-        const GjPivotDesc &q = pivot_desc_of(p, np, blockIdx.x);
-        gj_pivot_wg(q.A, q.n, q.j0, q.nb, q.Cb, q.status, blockIdx.x - q.wg0);
-        return;
-    }
-    const int tile = blockIdx.x - pw;
-    int lo = 0, hi = nd - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (d[mid].tile0 <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    const GemmDesc g = d[lo];
-    const int t = tile - g.tile0;
-    gemm_tile<LEAN>(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, (t / g.tiles_n) * 64,
-                    (t % g.tiles_n) * 64);
-}
-__global__ __launch_bounds__(kBlock) void kb_gj_update_pivot(const GjPivotDesc *__restrict__ p, int np, int pw,
-                                                              const GemmDesc *__restrict__ d, int nd)
-{
-    gjb_update_pivot_body<false>(p, np, pw, d, nd);
-}
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void kb_gj_update_pivot_wide(
-    const GjPivotDesc *__restrict__ p, int np, int pw, const GemmDesc *__restrict__ d, int nd)
-{
-    gjb_update_pivot_body<true>(p, np, pw, d, nd);
 }
 
 // ---- symmetric Gauss-Jordan sweeps (single MSFE matrices and the planes of
@@ -903,7 +843,7 @@ __device__ __forceinline__ void gj_pivot_sym_wg(double *__restrict__ A, int n, i
                                                 int blk)
 {
     if (blk == 0) {
-        gj_pivot_wg(A, n, j0, nb, nullptr, status, 0);
+        gj_pivot_wg(A, n, j0, nb, status);
         return;
     }
     const size_t t = (size_t)(blk - 1) * kBlock + threadIdx.x;
@@ -996,10 +936,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // A[i][j] = A[j][i] for i < j: one workgroup per 64 x 64 tile of the
 // upper triangle (tile row r < tile column c), through LDS so that reads
 // and writes both run along rows.
-__global__ __launch_bounds__(kBlock) void k_mirror_lower(double *__restrict__ A, int n)
+__device__ __forceinline__ void mirror_tile(double *__restrict__ A, int n, int t)
 {
     __shared__ double T[64][65];
-    const int t = blockIdx.x;
     int c = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);   // t = c (c - 1) / 2 + r, r < c
     c += 1;
     while (c * (c - 1) / 2 > t) --c;
@@ -1016,6 +955,70 @@ __global__ __launch_bounds__(kBlock) void k_mirror_lower(double *__restrict__ A,
         const int a = q / 64, b = q % 64;   // upper element (i0 + a, j0 + b) = lower (j0 + b, i0 + a)
         if (i0 + a < n && j0 + b < n) A[(size_t)(i0 + a) * n + j0 + b] = T[b][a];
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mirror_lower(double *__restrict__ A, int n)
+{
+    mirror_tile(A, n, blockIdx.x);
+}
+
+// ---- the symmetric sweeps of every MSFE instance of a batch, one launch
+// per step for all instances that have it.
+
+__global__ __launch_bounds__(kBlock) void kb_gj_pivot_sym(const GjPivotDesc *__restrict__ p, int np)
+{
+    const GjPivotDesc &q = pivot_desc_of(p, np, blockIdx.x);
+    gj_pivot_sym_wg(q.A, q.n, q.j0, q.nb, q.Cb, q.CbT, q.status, blockIdx.x - q.wg0);
+}
+
+// The lower-tile update of one panel of every instance (outside the next
+// panel's row and column) and the next panel's pivot steps in one launch:
+// the first `pw` workgroups are the pivot steps of the next panel of every
+// instance that has one, the others GEMM tiles.
+template <bool LEAN>
+__device__ __forceinline__ void gjb_update_pivot_body(const GjPivotDesc *__restrict__ p, int np, int pw,
+                                                      const GemmDesc *__restrict__ d, int nd)
+{
+    if ((int)blockIdx.x < pw) {
+        const GjPivotDesc &q = pivot_desc_of(p, np, blockIdx.x);
+        gj_pivot_sym_wg(q.A, q.n, q.j0, q.nb, q.Cb, q.CbT, q.status, blockIdx.x - q.wg0);
+        return;
+    }
+    const int tile = blockIdx.x - pw;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmDesc g = d[lo];
+    int tm, tn;
+    tile_origin(g, tile - g.tile0, tm, tn);
+    gemm_tile<LEAN>(g.C, g.ldc, g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, g.alpha, g.beta, tm, tn);
+}
+__global__ __launch_bounds__(kBlock) void kb_gj_update_pivot_sym(const GjPivotDesc *__restrict__ p, int np, int pw,
+                                                                  const GemmDesc *__restrict__ d, int nd)
+{
+    gjb_update_pivot_body<false>(p, np, pw, d, nd);
+}
+// The same with the lean GEMM tile at four workgroups per compute unit.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kb_gj_update_pivot_sym_wide(
+    const GjPivotDesc *__restrict__ p, int np, int pw, const GemmDesc *__restrict__ d, int nd)
+{
+    gjb_update_pivot_body<true>(p, np, pw, d, nd);
+}
+
+// Descriptor i mirrors the matrix C (order ldc) with the tiles tile0 ..
+// tile0 + T (T - 1) / 2 - 1 of the launch (T = tiles_n).
+__global__ __launch_bounds__(kBlock) void kb_mirror_lower(const GemmDesc *__restrict__ d, int nd)
+{
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    mirror_tile(d[lo].C, d[lo].ldc, blockIdx.x - d[lo].tile0);
 }
 
 // B = P I for the row interchanges of the factorisation (one thread builds
@@ -1073,7 +1076,6 @@ __global__ __launch_bounds__(kBlock) void k_node_sum(GridDev g, const double *__
     rc[k] = node_sum(g, slots, fe, k);
 }
 
-constexpr int kGemvLds = 1024;   // coarse sizes for which every GEMV workgroup forms R r itself
 
 // Dot product of the row mr (n entries) with x by one wave: 16-byte loads,
 // four in flight per lane, four independent sums when n is a multiple of 512
@@ -1148,6 +1150,106 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
     if (row >= n) return;
     const double s = row_dot(mr, x, n, lane);
     if (lane == 0) y[row] = s;
+}
+
+// y = M x for a symmetric M (the dense MSFE inverse) reading only its lower
+// triangle: one workgroup per 64 x 64 tile (I, J), J <= I, forms x_J and x_I
+// = (R r) from the restriction's slot partials, reads the tile once and
+// writes (M_IJ x_J) to part[I][J] and, below the diagonal, (M_IJ^T x_I) to
+// part[J][I] (64 values each); k_gemv_sym_reduce sums part[I][0..T) in a
+// fixed order.  The diagonal tiles also store x_I in rc.  Half the bytes of
+// the row-wise product.  With `partial` set one extra workgroup (the last)
+// runs the iteration's stopping test.
+__global__ __launch_bounds__(kBlock) void k_gemv_sym(const double *__restrict__ M, int n, GridDev g,
+                                                      const double *__restrict__ slots, int fe,
+                                                      double *__restrict__ rc, double *__restrict__ part,
+                                                      const int32_t *done, const double *__restrict__ partial,
+                                                      int nparts, int32_t *ictl, double *scal, double rtol2,
+                                                      int maxit)
+{
+    static_assert(kBlock == 256 && kBlock == kStopThreads, "four threads per tile row; one workgroup shape");
+    __shared__ double Ts[64][65];
+    __shared__ double xs[2][64];
+    __shared__ double red[4][64];
+    if (done && *done) return;
+    if (partial && blockIdx.x == gridDim.x - 1) {
+        stop_test(partial, nparts, ictl, scal, rtol2, maxit, &Ts[0][0]);
+        return;
+    }
+    const int t = blockIdx.x;   // t = I (I + 1) / 2 + J
+    int I = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2, T = (n + 63) / 64;
+    const int i0 = 64 * I, j0 = 64 * J;
+    // the tile's loads first: thread tid takes row r, 16 columns from cq
+    const int tid = threadIdx.x, r = tid >> 2, cq = (tid & 3) * 16;
+    const bool rin = i0 + r < n;
+    double a[16];
+    if (i0 + 64 <= n && j0 + 64 <= n && (n & 1) == 0) {   // whole tile, 16-byte aligned rows
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 *row = (const d2 *)(M + (size_t)(i0 + r) * n + j0 + cq);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const d2 v = row[u];
+            a[2 * u] = v.x;
+            a[2 * u + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int c = j0 + cq + u;
+            a[u] = rin && c < n ? M[(size_t)(i0 + r) * n + c] : 0.0;
+        }
+    }
+    if (tid < 128) {
+        const int h = tid >> 6, k = (h ? i0 : j0) + (tid & 63);
+        xs[h][tid & 63] = k < n ? node_sum(g, slots, fe, k) : 0.0;
+    }
+    __syncthreads();
+    double ur = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) ur += a[u] * xs[0][cq + u];
+    ur += __shfl_xor(ur, 1);
+    ur += __shfl_xor(ur, 2);
+    if ((tid & 3) == 0 && rin) part[((size_t)I * T + J) * 64 + r] = ur;
+    if (I == J) {
+        if (tid < 64 && i0 + tid < n) rc[i0 + tid] = xs[1][tid];
+        return;   // uniform over the workgroup
+    }
+    const double xr = xs[1][r];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) Ts[r][cq + u] = a[u] * xr;
+    __syncthreads();
+    {
+        const int c = tid & 63, q = tid >> 6;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += Ts[16 * q + k][c];
+        red[q][c] = s;
+    }
+    __syncthreads();
+    if (tid < 64 && j0 + tid < n)
+        part[((size_t)J * T + I) * 64 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+}
+
+// y[i] = sum over J of part[I][J][i mod 64] (I = i / 64), J ascending.
+__global__ __launch_bounds__(kBlock) void k_gemv_sym_reduce(const double *__restrict__ part, int n,
+                                                             double *__restrict__ y, const int32_t *done)
+{
+    if (done && *done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int T = (n + 63) / 64, I = i / 64;
+    const double *p = part + (size_t)I * T * 64 + (i % 64);
+    // eight independent sums (J mod 8), combined in a fixed order
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int J = 0;
+    for (; J + 8 <= T; J += 8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += p[(size_t)(J + k) * 64];
+    for (int k = 0; J + k < T; ++k) acc[k] += p[(size_t)(J + k) * 64];
+    y[i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 // Two independent products y = alpha M x + beta y with m x m matrices (row
@@ -1341,61 +1443,6 @@ void launch_coarse_operator(cams_ctx *c)
     k_coarse_nodes<<<cdiv((size_t)27 * n, kBlock), kBlock, 0, c->stream>>>(c->g, c->a.boxp, c->a.Ac);
 }
 
-// Descriptors of the three GEMM launches of every panel of the (batched)
-// Gauss-Jordan sweep of A (n x n, leading dimension n): the panel products;
-// the update of the next panel's columns; the rest of the update (which runs
-// together with the next pivot step).  Panel p saves its old column block in
-// Cb[p & 1] (row stride nb), so the next pivot step can fill the other
-// buffer while the update still reads this one.  Each launch entry of L is
-// (offset, count, tiles).
-static void gj_plan(double *A, int n, double *const Cb[2], std::vector<GemmDesc> &d, std::vector<int> &L)
-{
-    std::vector<GemmDesc> v;
-    auto add = [&](double *C, const double *Aop, int lda, const double *B, int M, int N, int K, double al,
-                   double be) {
-        if (M <= 0 || N <= 0 || K <= 0) return;
-        v.push_back(GemmDesc{C, Aop, B, n, lda, n, M, N, K, al, be, (int)cdiv(N, 64), 0});
-    };
-    auto flush = [&]() {
-        int tiles = 0;
-        for (GemmDesc &g : v) {
-            g.tile0 = tiles;
-            tiles += g.tiles_n * (int)cdiv(g.M, 64);
-        }
-        L.push_back((int)d.size());
-        L.push_back((int)v.size());
-        L.push_back(tiles);
-        d.insert(d.end(), v.begin(), v.end());
-        v.clear();
-    };
-    for (int p = 0, j0 = 0; j0 < n; ++p, j0 += kNB) {
-        const int nb = std::min(kNB, n - j0), rest = n - j0 - nb;
-        const int nb2 = std::min(kNB, rest);   // next panel's width (0 after the last)
-        const double *Dq = A + (size_t)j0 * n + j0;
-        double *rowJ = A + (size_t)j0 * n;
-        const double *Cbp = Cb[p & 1];
-        // A[J,~J] <- D^-1 A[J,~J] (in place: a workgroup owns whole columns);
-        // A[~J,J] <- -A[~J,J] D^-1 (in place: a workgroup owns whole rows)
-        add(rowJ, Dq, n, rowJ, nb, j0, nb, 1.0, 0.0);
-        add(rowJ + j0 + nb, Dq, n, rowJ + j0 + nb, nb, rest, nb, 1.0, 0.0);
-        add(A + j0, A + j0, n, Dq, j0, nb, nb, -1.0, 0.0);
-        add(A + (size_t)(j0 + nb) * n + j0, A + (size_t)(j0 + nb) * n + j0, n, Dq, rest, nb, nb, -1.0, 0.0);
-        // A[~J,~J] -= Cb[~J] A[J,~J]: first the next panel's columns, then the rest
-        flush();
-        const int r0[2] = {0, j0 + nb}, rn[2] = {j0, rest};
-        for (int u = 0; u < 2; ++u)
-            add(A + (size_t)r0[u] * n + j0 + nb, Cbp + (size_t)r0[u] * nb, nb, rowJ + j0 + nb, rn[u], nb2, nb, -1.0,
-                1.0);
-        flush();
-        const int c0[2] = {0, j0 + nb + nb2}, cn[2] = {j0, rest - nb2};
-        for (int u = 0; u < 2; ++u)
-            for (int w = 0; w < 2; ++w)
-                add(A + (size_t)r0[u] * n + c0[w], Cbp + (size_t)r0[u] * nb, nb, rowJ + c0[w], rn[u], cn[w], nb, -1.0,
-                    1.0);
-        flush();
-    }
-}
-
 // Descriptors of the symmetric sweep of A (n x n): three launch entries per
 // panel p, each (offset, count, tiles) in L:
 //   1. G = Cb D^-1 and the panel: A[I,J] = -Cb_I D^-1 (I > J),
@@ -1543,12 +1590,11 @@ static void inverse_gj(cams_ctx *c, double *A, int m, int mat, int ch, hipStream
 // Saved column blocks of an instance's dense sweep: its own buffer, or for
 // an instance that factorises by planes when alone (its buffer is sized for
 // one plane) the working matrix, which the dense sweep does not use.
-static void batch_gj_cb(const cams_ctx *c, double *Cb[2])
+static GjBufs batch_gj_bufs(const cams_ctx *c)
 {
-    const size_t n = (size_t)c->g.Nc;
+    const size_t blk = (size_t)c->g.Nc * kNB;
     double *base = c->blocktri ? c->a.work : c->a.gjcb;
-    Cb[0] = base;
-    Cb[1] = base + n * kNB;
+    return GjBufs{{base, base + blk}, {base + 2 * blk, base + 3 * blk}, base + 4 * blk};
 }
 
 // Per instance: A_c copied into Ainv, which the sweeps invert in place.
@@ -1567,9 +1613,8 @@ void plan_batch_gj(const std::vector<cams_ctx *> &fe, BatchGjPlan &plan)
     int maxP = 0;
     for (int i = 0; i < m; ++i) {
         const cams_ctx *c = fe[i];
-        double *Cb[2];
-        batch_gj_cb(c, Cb);
-        gj_plan(c->a.Ainv, c->g.Nc, Cb, d[i], L[i]);
+        const GjBufs bf = batch_gj_bufs(c);
+        gj_plan_sym(c->a.Ainv, c->g.Nc, bf.Cb, bf.CbT, bf.G, d[i], L[i]);
         maxP = std::max(maxP, (c->g.Nc + kNB - 1) / kNB);
     }
     // pivot steps of panel p of every instance that has it
@@ -1581,15 +1626,14 @@ void plan_batch_gj(const std::vector<cams_ctx *> &fe, BatchGjPlan &plan)
             const int n = c->g.Nc, j0 = p * kNB;
             if (j0 >= n) continue;
             const int nb = std::min(kNB, n - j0);
-            double *Cb[2];
-            batch_gj_cb(c, Cb);
-            plan.piv.push_back(GjPivotDesc{c->a.Ainv, Cb[p & 1], c->a.status, n, j0, nb, wgs});
+            const GjBufs bf = batch_gj_bufs(c);
+            plan.piv.push_back(GjPivotDesc{c->a.Ainv, bf.Cb[p & 1], bf.CbT[p & 1], c->a.status, n, j0, nb, wgs});
             wgs += (int)gj_pivot_wgs(n, nb);
         }
         count = (int)(plan.piv.size() - off);
         return off;
     };
-    // launch h (0..2) of panel p of every instance, tiles renumbered
+    // launch entry h (0: panel, 2: update) of panel p of every instance, tiles renumbered
     auto gemms = [&](int p, int h, int &count, int &tiles) -> size_t {
         const size_t off = plan.gemms.size();
         tiles = 0;
@@ -1611,32 +1655,48 @@ void plan_batch_gj(const std::vector<cams_ctx *> &fe, BatchGjPlan &plan)
     first.poff = pivots(0, first.pcount, first.pw);
     plan.launches.push_back(first);
     for (int p = 0; p < maxP; ++p) {
-        for (int h = 0; h < 2; ++h) {
-            BatchGjPlan::Launch g{BatchGjPlan::GEMM, 0, 0, 0, 0, 0, 0};
-            g.goff = gemms(p, h, g.gcount, g.tiles);
-            if (g.gcount > 0) plan.launches.push_back(g);
-        }
+        BatchGjPlan::Launch g{BatchGjPlan::PANEL, 0, 0, 0, 0, 0, 0};
+        g.goff = gemms(p, 0, g.gcount, g.tiles);
+        if (g.gcount > 0) plan.launches.push_back(g);
         BatchGjPlan::Launch u{BatchGjPlan::UPDATE_PIVOT, 0, 0, 0, 0, 0, 0};
         u.poff = pivots(p + 1, u.pcount, u.pw);
         u.goff = gemms(p, 2, u.gcount, u.tiles);
         if (u.pcount + u.gcount > 0) plan.launches.push_back(u);
     }
+    // the lower triangles to the upper ones, every instance in one launch
+    BatchGjPlan::Launch mr{BatchGjPlan::MIRROR, 0, 0, 0, 0, 0, 0};
+    mr.goff = plan.gemms.size();
+    for (int i = 0; i < m; ++i) {
+        const int n = fe[i]->g.Nc, T = (n + 63) / 64;
+        if (T < 2) continue;
+        GemmDesc g{};
+        g.C = fe[i]->a.Ainv;
+        g.ldc = n;
+        g.tiles_n = T;
+        g.tile0 = mr.tiles;
+        plan.gemms.push_back(g);
+        mr.tiles += T * (T - 1) / 2;
+    }
+    mr.gcount = (int)(plan.gemms.size() - mr.goff);
+    if (mr.gcount > 0) plan.launches.push_back(mr);
 }
 
 void launch_batch_gj(const BatchGjPlan &plan, const GjPivotDesc *piv, const GemmDesc *gemms, hipStream_t st)
 {
     for (const BatchGjPlan::Launch &L : plan.launches) {
         if (L.kind == BatchGjPlan::PIVOT) {
-            if (L.pcount > 0) kb_gj_pivot<<<L.pw, kBlock, 0, st>>>(piv + L.poff, L.pcount);
-        } else if (L.kind == BatchGjPlan::GEMM) {
-            kb_gemm<<<L.tiles, kBlock, 0, st>>>(gemms + L.goff, L.gcount);
+            if (L.pcount > 0) kb_gj_pivot_sym<<<L.pw, kBlock, 0, st>>>(piv + L.poff, L.pcount);
+        } else if (L.kind == BatchGjPlan::PANEL) {
+            k_gj_panel_sym<<<L.tiles, kBlock, 0, st>>>(gemms + L.goff, L.gcount);
+        } else if (L.kind == BatchGjPlan::MIRROR) {
+            kb_mirror_lower<<<L.tiles, kBlock, 0, st>>>(gemms + L.goff, L.gcount);
         } else if (L.pcount > 0) {
-            if (L.tiles >= kWideTiles)
-                kb_gj_update_pivot_wide<<<L.pw + L.tiles, kBlock, 0, st>>>(piv + L.poff, L.pcount, L.pw,
-                                                                           gemms + L.goff, L.gcount);
+            if (L.tiles >= kWideTilesSym)
+                kb_gj_update_pivot_sym_wide<<<L.pw + L.tiles, kBlock, 0, st>>>(piv + L.poff, L.pcount, L.pw,
+                                                                               gemms + L.goff, L.gcount);
             else
-                kb_gj_update_pivot<<<L.pw + L.tiles, kBlock, 0, st>>>(piv + L.poff, L.pcount, L.pw, gemms + L.goff,
-                                                                      L.gcount);
+                kb_gj_update_pivot_sym<<<L.pw + L.tiles, kBlock, 0, st>>>(piv + L.poff, L.pcount, L.pw,
+                                                                          gemms + L.goff, L.gcount);
         } else if (L.gcount > 0) {
             kb_gemm<<<L.tiles, kBlock, 0, st>>>(gemms + L.goff, L.gcount);
         }
@@ -1851,6 +1911,15 @@ void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done,
         k_gemv<<<cdiv(n, kBlock / 64) + (stop ? 1 : 0), kBlock, 0, c->stream>>>(
             c->a.Ainv, n, nullptr, c->g, c->a.slots, fe, xc, done, stop ? c->a.partial : nullptr, stop_parts,
             c->a.ictl, c->a.scal, rt * rt, c->opt.lin_maxit);
+        return;
+    }
+    if (!c->blocktri && fe) {   // symmetric inverse: its lower triangle, once
+        const int T = (n + 63) / 64;
+        const bool stop = stop_parts > 0;
+        k_gemv_sym<<<T * (T + 1) / 2 + (stop ? 1 : 0), kBlock, 0, c->stream>>>(
+            c->a.Ainv, n, c->g, c->a.slots, fe, c->a.rc, c->a.gpart, done, stop ? c->a.partial : nullptr,
+            stop_parts, c->a.ictl, c->a.scal, rt * rt, c->opt.lin_maxit);
+        k_gemv_sym_reduce<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.gpart, n, xc, done);
         return;
     }
     if (stop_parts > 0) launch_finalize_ctl(c, stop_parts);

@@ -567,24 +567,23 @@ constexpr int kRowThreads = 512;
 // 8-cell rows of one block; then wave w < BPX sweeps block w (those waves
 // at once) and all threads write the blocks back.  The operations per cell
 // are those of bilu_step_body.
+// Group sb of BPX blocks along x (groups x fastest, then y, then z), as
+// k_bilu_step_row and its batched form take it.  Each thread stages and
+// writes back only its own LDS slots, so consecutive groups need no
+// barrier between them.
 template <class T, class TR, int BPX, int NT>
-__global__ __launch_bounds__(NT) void k_bilu_step_row(GridDev g, const T *__restrict__ W,
-                                                       const T *__restrict__ diag, const T *__restrict__ invd,
-                                                       const TR *__restrict__ rhs, const T *__restrict__ eold,
-                                                       T *__restrict__ enew, const int32_t *done, int shifted)
+__device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
+                                              const T *__restrict__ invd, const TR *__restrict__ rhs,
+                                              const T *__restrict__ eold, T *__restrict__ enew, int sb,
+                                              SmoothLds<T> *Ls, Shift o, int tid)
 {
     static_assert(NT % 64 == 0 && NT >= 64 * BPX && (ST * BPX) % NT == 0, "one wave per block at least");
     constexpr int RX = SB * BPX, CPT = ST * BPX / NT;
-    __shared__ SmoothLds<T> Ls[BPX];
-    if (done && *done) return;
-    const Shift o = block_shift(g, shifted);
     const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
     const int nsx = (nbx + BPX - 1) / BPX;
-    const int sb = xcd_swizzle(blockIdx.x, gridDim.x);
     const int bx0 = (sb % nsx) * BPX, j0 = ((sb / nsx) % nby) * SB, k0 = (sb / (nsx * nby)) * SB;
     const int ey = min(SB, g.ny - j0), ez = min(SB, g.nz - k0);
     const T *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
-    const int tid = threadIdx.x;
     for (int q = tid; q < BPX * 2 * PAD; q += NT) {
         const int b = q / (2 * PAD), r = q % (2 * PAD);
         const int idx = r < PAD ? r : ST + r;
@@ -655,6 +654,18 @@ __global__ __launch_bounds__(NT) void k_bilu_step_row(GridDev g, const T *__rest
     }
 }
 
+template <class T, class TR, int BPX, int NT>
+__global__ __launch_bounds__(NT) void k_bilu_step_row(GridDev g, const T *__restrict__ W,
+                                                       const T *__restrict__ diag, const T *__restrict__ invd,
+                                                       const TR *__restrict__ rhs, const T *__restrict__ eold,
+                                                       T *__restrict__ enew, const int32_t *done, int shifted)
+{
+    __shared__ SmoothLds<T> Ls[BPX];
+    if (done && *done) return;
+    row_step_body<T, TR, BPX, NT>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), Ls,
+                                  block_shift(g, shifted), (int)threadIdx.x);
+}
+
 // The first post-smoothing step, whose e_old is the prolongated coarse
 // correction P xc (Eq. (12)): the prolongation runs inside the step (on the
 // block and its face neighbours), so it needs no launch of its own and the
@@ -720,6 +731,38 @@ __global__ __launch_bounds__(NT) void kb_bilu_step(const InstDev *__restrict__ i
         const T *prev = s > 0 ? buf[(steps - s) & 1] : init;
         bilu_step_body<T, TR, NT>(d.g, W, diag, shifted ? invd + d.g.N : invd, rhs, prev, out, w.blk, lds,
                                   block_shift(d.g, shifted), FromCoarse<T, void>{}, (int)threadIdx.x);
+    }
+}
+
+// The batched FP32 step in the row form: work item = (instance, group of
+// kRowBlocks blocks along x), kRowThreads threads per workgroup.
+template <class T, class TR>
+__global__ __launch_bounds__(kRowThreads) void kb_bilu_step_row(const InstDev *__restrict__ inst,
+                                                                 const WorkItem *__restrict__ work,
+                                                                 const int32_t *nwork, int post, int s, int steps)
+{
+    __shared__ SmoothLds<T> Ls[kRowBlocks];
+    const int nw = *nwork;
+    int t = blockIdx.x;
+    WorkItem wnext = t < nw ? work[t] : WorkItem{0, 0};
+    for (; t < nw; t += gridDim.x) {
+        const WorkItem w = wnext;
+        if (t + (int)gridDim.x < nw) wnext = work[t + gridDim.x];
+        const InstDev &d = inst[w.inst];
+        if (d.a.ictl[C_DONE]) continue;
+        const Arrays &a = d.a;
+        const int shifted = d.alt && (s & 1);
+        T *buf[2] = {post ? a.d2f : a.d0f, a.zf};
+        T *out = buf[(steps - 1 - s) & 1];
+        const T *prev = s > 0 ? buf[(steps - s) & 1] : (post ? a.d1f : nullptr);
+        const TR *rhs;
+        if constexpr (sizeof(TR) == 4)
+            rhs = a.r1f;
+        else
+            rhs = a.r;
+        row_step_body<T, TR, kRowBlocks, kRowThreads>(d.g, a.W32, a.diag32, shifted ? a.invd32 + d.g.N : a.invd32,
+                                                      rhs, prev, out, w.blk, Ls, block_shift(d.g, shifted),
+                                                      (int)threadIdx.x);
     }
 }
 
@@ -897,6 +940,12 @@ template <class T, class TR>
 void batch_smooth_nt(const BatchLaunch &L, int steps, int rhs_kind, int nt)
 {
     for (int s = 0; s < steps; ++s) {
+        if constexpr (sizeof(T) == 4)
+            if (nt == 0) {   // row form (list of block groups)
+                launch_persistent(kb_bilu_step_row<T, TR>, kRowThreads, L, L.inst, L.work, L.nwork, rhs_kind, s,
+                                  steps);
+                continue;
+            }
         switch (nt) {
         case 128: launch_persistent(kb_bilu_step<T, TR, 128>, 128, L, L.inst, L.work, L.nwork, rhs_kind, s, steps); break;
         case 256: launch_persistent(kb_bilu_step<T, TR, 256>, 256, L, L.inst, L.work, L.nwork, rhs_kind, s, steps); break;
@@ -906,7 +955,8 @@ void batch_smooth_nt(const BatchLaunch &L, int steps, int rhs_kind, int nt)
 }
 
 // Batched smoothing for every instance, `steps` Richardson steps with `nt`
-// threads per block (128, 256 or 512).  rhs_kind 0: pre-smoothing on r from
+// threads per block (128, 256 or 512), or with nt = 0 (FP32 only) in the
+// row form over the list of block groups.  rhs_kind 0: pre-smoothing on r from
 // zero; 1: post-smoothing on r (its FP32 copy when mixed) from d1.
 void launch_batch_smooth(const BatchLaunch &L, int steps, int rhs_kind, bool mixed, int nt)
 {

@@ -113,6 +113,50 @@ def test_batch_matches_single_path(torch, precision, n_pre, alt):
     b.close()
 
 
+@pytest.mark.parametrize("form", [(128, 1), (256, 1), (512, 1), (512, 4)])
+def test_batch_smoother_forms_match_single_path(torch, form):
+    """Every smoother form the tuner can pick (threads, blocks per
+    workgroup), fixed by cams_batch_set_smoother, gives the single path's
+    iteration counts and pressures (1e-12) on the mixed-precision batch with
+    the alternating smoother (the four-block form stages the shifted grid's
+    wrapped blocks too)."""
+    from paper_1705_05783_amd.batch import Batch
+    from paper_1705_05783_amd.solver import Solver
+    pbs = _instances(MIXED_FP32, rtol=1e-8, alt=True)
+    b = Batch.from_problems(pbs)
+    b.set_smoother(*form)
+    pn = [torch.as_tensor(_start(pb), device="cuda") for pb in pbs]
+    p = [t.clone() for t in pn]
+    status, stats = b.newton_iteration(pn, p)
+    t = b.tuning()
+    assert (t["smoother_threads"], t["smoother_blocks"]) == form
+    for pb, s, st, pg in zip(pbs, status, stats, p):
+        assert s == 0, (pb.name, s)
+        sv = Solver(pb)
+        q0 = torch.as_tensor(_start(pb), device="cuda")
+        q = q0.clone()
+        single = sv.newton_step(q0, q, check=False)
+        first = single["lin_iters_total"] if single["newton_iters"] else 0
+        diff = rel_err(to_np(pg), to_np(q))
+        log(pb.name, form, "batch iters", st["lin_iters_last"], "single", first, "diff", diff)
+        assert st["lin_iters_last"] == first, pb.name
+        assert diff <= 1e-12, pb.name
+        sv.close()
+    b.close()
+
+
+def test_batch_smoother_form_rejects_invalid_pairs(torch):
+    from paper_1705_05783_amd import _cams as C
+    from paper_1705_05783_amd.batch import Batch
+    b = Batch.from_problems(_instances(FP64, rtol=1e-8))
+    for bad in ((512, 4), (64, 1), (512, 2)):   # (512, 4) is FP32 only
+        with pytest.raises(C.CamsError) as e:
+            b.set_smoother(*bad)
+        assert e.value.status == C.CAMS_E_ARG
+    b.set_smoother(0, 0)
+    b.close()
+
+
 def test_batch_second_call_replays_the_tuned_graph(torch):
     """The second call runs the chosen graph only; it must reproduce the first
     call's result bit for bit from the same starting state."""
@@ -128,10 +172,14 @@ def test_batch_second_call_replays_the_tuned_graph(torch):
         runs.append(([to_np(t) for t in p], [s["lin_iters_last"] for s in stats]))
     t = b.tuning()
     log("tuning", t)
-    assert t["iters_per_graph"] in (2, 4, 8) and t["smoother_threads"] in (128, 256, 512)
-    # the tuner keeps the fastest smoother workgroup size it measured
+    assert t["iters_per_graph"] in (2, 4, 8)
+    forms = [(128, 1), (256, 1), (512, 1), (512, 4)]   # (threads, blocks) per workgroup
+    assert (t["smoother_threads"], t["smoother_blocks"]) in forms
+    # the tuner keeps the fastest smoother form it measured (the four-block
+    # form only in FP32: this batch is mixed, so all four are measured)
     ms = t["ms_per_smooth_step"]
-    assert ms[(128, 256, 512).index(t["smoother_threads"])] == min(ms)
+    assert all(m > 0 for m in ms)
+    assert ms[forms.index((t["smoother_threads"], t["smoother_blocks"]))] == min(ms)
     assert runs[0][1] == runs[1][1]
     for a, c in zip(runs[0][0], runs[1][0]):
         assert np.array_equal(a, c)
