@@ -81,7 +81,7 @@ __device__ __forceinline__ double residual_cell(const GridDev &g, const double *
     s -= (zm ? wzm : 0.0) * v(nzm);
     s -= (zp ? wzp : 0.0) * v(nzp);
     const double rr = r0[n] - s;
-    r[n] = rr;
+    if (r) r[n] = rr;   // null when only the FP32 copy is read afterwards
     if (rf) rf[n] = (float)rr;
     dp_out[n] = vn;
     return rr;
@@ -212,16 +212,101 @@ __global__ __launch_bounds__(kBlock) void k_restrict(GridDev g, const uint8_t *_
 }
 
 // Residual and restriction in one pass, for iterations without
-// pre-smoothing (the restriction then acts on the new residual itself): r =
-// r0 - A v as residual_body does, and per owner box k the partial of ||r||^2
-// (partial[k]) and its 8 restriction slots from the values just computed,
-// so r is not read back and the restriction needs no launch of its own.
-// One workgroup takes a group of consecutive boxes along x (the table gx),
-// so that the loads and stores of a wave run along rows of up to 32 cells
-// instead of one box's rows of about 8: thread t takes column t % 32 of the
-// group's rows and every 16th row (y fastest, then z), so all its cells lie
-// in one box.  The per-box sums go through LDS: each wave then reduces some
-// of the (box, slot) pairs over that box's threads in a fixed order.  (With
+// pre-smoothing (the restriction then acts on the new residual itself): one
+// workgroup per owner box k computes, over the box's cells in the order of
+// restrict_box, r = r0 - A v as residual_body does, the box's partial of
+// ||r||^2 (partial[k]) and its 8 restriction slots from the values just
+// computed, so r is not read back and the restriction needs no launch of its
+// own.  The slots equal restrict_box's (a masked cell adds P * 0 = +-0).
+template <class TA, int NV, class TP, int NT>
+__device__ __forceinline__ void residual_restrict_box(const GridDev &g, const double *__restrict__ W,
+                                                      const double *__restrict__ diag,
+                                                      const double *__restrict__ r0, const Pending<TA, NV> &v,
+                                                      double *__restrict__ dp_out, double *__restrict__ r,
+                                                      float *__restrict__ rf, double *__restrict__ partial,
+                                                      const uint8_t *__restrict__ dm, const TP *__restrict__ P,
+                                                      int fe, double *__restrict__ slots, int k, double *sh)
+{
+    const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
+    // MSFE: the owner box from the tables; MSFV: the primal block [a r, min((a+1) r, n)) of
+    // node k, also when the context was set up for MSFE (the conservative sweep)
+    const int x0 = fe ? g.ob[0][ka] : ka * g.r[0], y0 = fe ? g.ob[1][kb] : kb * g.r[1];
+    const int z0 = fe ? g.ob[2][kc] : kc * g.r[2];
+    const int ex = (fe ? g.ob[0][ka + 1] : min(x0 + g.r[0], g.nx)) - x0;
+    const int ey = (fe ? g.ob[1][kb + 1] : min(y0 + g.r[1], g.ny)) - y0;
+    const int ez = (fe ? g.ob[2][kc + 1] : min(z0 + g.r[2], g.nz)) - z0;
+    const int m = ex * ey * ez;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double e2 = 0.0;
+    for (int t = threadIdx.x; t < m; t += NT) {
+        const int x = x0 + t % ex, y = y0 + (t / ex) % ey, z = z0 + t / (ex * ey);
+        const int n = x + g.nx * (y + g.ny * z);
+        // issued with the residual's loads, outside any branch, so that no
+        // load waits for another (MSFV reads the basis without using it)
+        TP pv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[q] = P[(size_t)q * g.N + n];
+        const bool keep = !dm[n];
+        const double rn = residual_cell(g, W, diag, r0, v, dp_out, r, rf, n, x, y, z);
+        e2 += rn * rn;
+        if (fe) {
+            const double wn = keep ? rn : 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += basis_value(pv + q, 0) * wn;
+        } else {
+            acc[0] += rn;
+        }
+    }
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double u = wave_sum(acc[q]);
+        if (lane == 0) sh[q * NW + w] = u;
+    }
+    {
+        const double u = wave_sum(e2);
+        if (lane == 0) sh[8 * NW + w] = u;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double s = 0.0;
+        for (int u = 0; u < NW; ++u) s += sh[threadIdx.x * NW + u];
+        if (threadIdx.x < 8)
+            slots[(size_t)k * 8 + threadIdx.x] = s;
+        else
+            partial[k] = s;
+    }
+    __syncthreads();   // sh is reused by the caller's next box
+}
+
+// Threads per box of the single-problem form: one cell per thread in full
+// 8x8x8 boxes.
+constexpr int kBoxThreads = 512;
+
+template <class TA, int NV, class TP>
+__global__ __launch_bounds__(kBoxThreads) void k_residual_restrict(GridDev g, const double *__restrict__ W,
+                                                               const double *__restrict__ diag,
+                                                               const double *__restrict__ r0, Pending<TA, NV> v,
+                                                               double *__restrict__ dp_out, double *__restrict__ r,
+                                                               float *__restrict__ rf, double *__restrict__ partial,
+                                                               const uint8_t *__restrict__ dm,
+                                                               const TP *__restrict__ P, int fe,
+                                                               double *__restrict__ slots, const int32_t *ictl)
+{
+    __shared__ double sh[9 * (kBoxThreads / 64)];
+    if (ictl[C_DONE]) return;
+    v.fold = ictl[C_IT] > 0;
+    residual_restrict_box<TA, NV, TP, kBoxThreads>(g, W, diag, r0, v, dp_out, r, rf, partial, dm, P, fe, slots,
+                                               xcd_swizzle(blockIdx.x, gridDim.x), sh);
+}
+
+// The same for a group of consecutive boxes along x (the table gx), so that
+// the loads and stores of a wave run along rows of up to 32 cells instead of
+// one box's rows of about 8: thread t takes column t % 32 of the group's
+// rows and every 16th row (y fastest, then z), so all its cells lie in one
+// box.  The per-box sums go through LDS: each wave then reduces some of the
+// (box, slot) pairs over that box's threads in a fixed order.  (With
 // coarsening ratios up to 8 a box is at most 12 cells wide, so every grid
 // has such groups; cams_create checks it.)
 constexpr int kRowThreads = 512;
@@ -441,20 +526,35 @@ void residual_restrict(cams_ctx *c, const Pending<TA, NV> &v, double *dp_out, fl
     const Arrays &a = c->a;
     const int fe = c->opt.restriction == CAMS_R_FE;
     const int ngx = g.ngx[fe];
-    // groups of boxes per workgroup (FP32 / BF16 at 128^3: 90 -> 77 us per
-    // launch against one workgroup per box; 256x256x128: 358 -> 268 us)
-    {
-        const unsigned wgs = (unsigned)ngx * g.nb[1] * g.nb[2];
+    // in mixed precision the smoother reads the FP32 copy rf and the
+    // restriction uses r in registers, so the FP64 r is not stored
+    double *const rout = rf ? nullptr : a.r;
+    // groups of boxes per workgroup where they fill at least one round of
+    // resident workgroups (FP32 / BF16 at 128^3: 90 -> 77 us per launch;
+    // 256x256x128: 358 -> 268 us), else one workgroup per box (64x64x32:
+    // 96 groups, 18.8 against 9.5 us)
+    const unsigned wgs = (unsigned)ngx * g.nb[1] * g.nb[2];
+    if ((int)wgs >= resident_workgroups((const void *)k_residual_restrict_row<TA, NV, float>, kRowThreads)) {
         if (c->opt.precision == CAMS_MIXED_BF16)
             k_residual_restrict_row<TA, NV, uint16_t><<<wgs, kRowThreads, 0, c->stream>>>(
-                g, a.W, a.diag, a.r0, v, dp_out, a.r, rf, a.partial, a.dmask, a.Pbf, fe, a.slots, a.ictl);
+                g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.Pbf, fe, a.slots, a.ictl);
         else if (c->opt.precision == CAMS_MIXED_FP32)
             k_residual_restrict_row<TA, NV, float><<<wgs, kRowThreads, 0, c->stream>>>(
-                g, a.W, a.diag, a.r0, v, dp_out, a.r, rf, a.partial, a.dmask, a.P32, fe, a.slots, a.ictl);
+                g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.P32, fe, a.slots, a.ictl);
         else
             k_residual_restrict_row<TA, NV, double><<<wgs, kRowThreads, 0, c->stream>>>(
-                g, a.W, a.diag, a.r0, v, dp_out, a.r, rf, a.partial, a.dmask, a.P, fe, a.slots, a.ictl);
+                g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.P, fe, a.slots, a.ictl);
+        return;
     }
+    if (c->opt.precision == CAMS_MIXED_BF16)
+        k_residual_restrict<TA, NV, uint16_t><<<g.Nc, kBoxThreads, 0, c->stream>>>(
+            g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.Pbf, fe, a.slots, a.ictl);
+    else if (c->opt.precision == CAMS_MIXED_FP32)
+        k_residual_restrict<TA, NV, float><<<g.Nc, kBoxThreads, 0, c->stream>>>(
+            g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.P32, fe, a.slots, a.ictl);
+    else
+        k_residual_restrict<TA, NV, double><<<g.Nc, kBoxThreads, 0, c->stream>>>(
+            g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.P, fe, a.slots, a.ictl);
 }
 
 // Without pre-smoothing at most two corrections are pending (d1 and d2 of
