@@ -508,3 +508,14 @@ def test_coarse_inverse_multi_panel(_gpu, shape, r, restriction):
     rc = rng.normal(size=Nc)
     xc = to_np(s.coarse_solve(torch.as_tensor(rc, device="cuda")))
     assert rel_err(xc, np.linalg.solve(Ac_ref, rc)) <= 1e-15 * kappa * 100
+    if restriction == FE:
+        # a C-AMS solve on this operator: its coarse solves take the GEMV over
+        # the lower triangle of the inverse (23 tile rows, the last ragged)
+        st = s.iterate(pt)
+        LU, piv = oracle.lu_factor(Ac_ref)
+        _, its, _ = oracle.cams_solve(pb, W, diag, oracle.basis_b4(pb, T), restriction, LU, piv,
+                                      oracle.smoother_for(pb, W, diag), oracle.linear_system(pb, T, p, p)[2])
+        rel, bound = linear_residual_check(pb, T, p, p, to_np(pt))
+        log("C-AMS iterations gpu", st["lin_iters_last"], "oracle", its, "relres", rel, "bound", bound)
+        assert its >= 0 and abs(st["lin_iters_last"] - its) <= 1
+        assert rel <= bound
