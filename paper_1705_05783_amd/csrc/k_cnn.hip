@@ -10,7 +10,8 @@
 // weights W[tap][ci][co], tap = 9(dz+1) + 3(dy+1) + (dx+1); the convolution is
 // out[b][co][p] = bias[co] + sum_{tap,ci} W[tap][ci][co] x[b][ci][p + d(tap)]
 // with zero padding.  Network: conv 3->32, ReLU, 32->32, ReLU, 32->32, ReLU,
-// 32->8, softmax.  FP32 storage and accumulation.
+// 32->8, softmax.  FP32 storage and accumulation; training convolutions on
+// FP32 matrix cores, inference on BF16 matrix cores.
 #include "cams_internal.h"
 #include "dev_util.h"
 
@@ -21,7 +22,6 @@ namespace {
 constexpr int PD = 9;                 // patch extent
 constexpr int PP = PD * PD * PD;      // 729 positions
 constexpr int CT = 256;               // threads per workgroup
-constexpr int COG = 8;                // output channels per workgroup
 constexpr int MAXC = 32;
 __constant__ int kLayersDev[4][2] = {{3, 32}, {32, 32}, {32, 32}, {32, 8}};
 
@@ -34,61 +34,130 @@ __device__ __forceinline__ int nb_pos(int p, int tap)
     return X + PD * (Y + PD * Z);
 }
 
-// out[b][co][p] (8 channels co0..co0+7 per workgroup) = bias + conv(x), then
-// optional ReLU, optional multiplication by (mask[b][co][p] > 0).
-__global__ __launch_bounds__(CT) void k_conv_fwd(const float *__restrict__ x, int Ci, const float *__restrict__ W,
-                                                  const float *__restrict__ bias, int Co, float *__restrict__ out,
-                                                  int relu, const float *__restrict__ mask)
+// ---- training convolutions on FP32 matrix cores (v_mfma_f32_16x16x4f32,
+// FP32 inputs and accumulation).  Operand lanes: A row = lane % 16, k =
+// lane / 16; B column = lane % 16, k = lane / 16; result element v of a lane:
+// row 4 (lane / 16) + v, column lane % 16.
+typedef float f32x4m __attribute__((ext_vector_type(4)));
+constexpr int MT = 512;               // threads of the convolution workgroup (8 waves)
+constexpr int MPT = 46;               // 16-position tiles per patch (736 >= 729)
+constexpr int XP = 33;                // LDS row pitch of the staged activations (banks)
+
+// out[b][co][p] = bias[co] + conv(x) (then optional ReLU, optional
+// multiplication by (mask[b][co][p] > 0)) as an implicit GEMM: one workgroup
+// per (patch b, 16 output channels co0..co0+15); the patch's activations are
+// staged position-major in LDS (channels padded to a multiple of 4), the
+// layer's weights for the 16 channels likewise; wave w takes the position
+// tiles w, w + 8, ...; per tile and tap, one MFMA per 4 input channels.
+// CP: the input channels rounded up to the MFMA's k of 4 (4, 8 or 32), a
+// compile-time count so that a tap's operand reads go out together.
+template <int CP>
+__global__ __launch_bounds__(MT) void k_conv_mfma(const float *__restrict__ x, int Ci, const float *__restrict__ W,
+                                                   const float *__restrict__ bias, int Co, float *__restrict__ out,
+                                                   int relu, const float *__restrict__ mask)
 {
-    __shared__ float xs[MAXC * PP];
-    __shared__ float ws[27 * MAXC * COG];
-    const int b = blockIdx.x, co0 = blockIdx.y * COG;
-    const int nco = min(COG, Co - co0);
+    static_assert(CP % 4 == 0 && CP <= MAXC, "channel chunks of 4");
+    __shared__ float xs[MPT * 16 * XP];
+    __shared__ float ws[27 * CP * 16];
+    const int b = blockIdx.x, co0 = blockIdx.y * 16;
     const float *xb = x + (size_t)b * Ci * PP;
-    for (int t = threadIdx.x; t < Ci * PP; t += CT) xs[t] = xb[t];
-    for (int t = threadIdx.x; t < 27 * Ci * COG; t += CT) {
-        const int j = t % COG, ci = (t / COG) % Ci, tap = t / (COG * Ci);
-        ws[t] = j < nco ? W[((size_t)tap * Ci + ci) * Co + co0 + j] : 0.f;
+    for (int t = threadIdx.x; t < MPT * 16 * CP; t += MT) {
+        const int c = t / (MPT * 16), q = t % (MPT * 16);   // coalesced along positions
+        xs[q * XP + c] = (c < Ci && q < PP) ? xb[(size_t)c * PP + q] : 0.f;
+    }
+    for (int t = threadIdx.x; t < 27 * CP * 16; t += MT) {
+        const int j = t % 16, ci = (t / 16) % CP, tap = t / (16 * CP);
+        ws[t] = (ci < Ci && co0 + j < Co) ? W[((size_t)tap * Ci + ci) * Co + co0 + j] : 0.f;
     }
     __syncthreads();
-    float acc[3][COG];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int co = co0 + row;
+    const float bs = (bias && co < Co) ? bias[co] : 0.f;
+    for (int pt = wave; pt < MPT; pt += MT / 64) {
+        const int p = pt * 16 + row;
+        const int px = p % PD, py = (p / PD) % PD, pz = p / (PD * PD);
+        f32x4m acc = {0.f, 0.f, 0.f, 0.f};
+        // three taps' operand reads in flight at a time
+#pragma unroll 3
+        for (int tap = 0; tap < 27; ++tap) {
+            const int X = px + tap % 3 - 1, Y = py + (tap / 3) % 3 - 1, Z = pz + tap / 9 - 1;
+            const bool ok = p < PP && X >= 0 && X < PD && Y >= 0 && Y < PD && Z >= 0 && Z < PD;
+            const float *xa = xs + (ok ? X + PD * (Y + PD * Z) : 0) * XP + kq;
+            const float *wb = ws + (tap * CP + kq) * 16 + row;
+            float av[CP / 4], bv[CP / 4];
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int j = 0; j < COG; ++j) acc[q][j] = 0.f;
-    for (int tap = 0; tap < 27; ++tap) {
-        int nbq[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int p = threadIdx.x + q * CT;
-            nbq[q] = p < PP ? nb_pos(p, tap) : -1;
-        }
-        const float *wt = ws + tap * Ci * COG;
-        for (int ci = 0; ci < Ci; ++ci) {
-            float w[COG];
-#pragma unroll
-            for (int j = 0; j < COG; ++j) w[j] = wt[ci * COG + j];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const float a = nbq[q] >= 0 ? xs[ci * PP + nbq[q]] : 0.f;
-#pragma unroll
-                for (int j = 0; j < COG; ++j) acc[q][j] += a * w[j];
+            for (int c = 0; c < CP / 4; ++c) {
+                av[c] = ok ? xa[4 * c] : 0.f;
+                bv[c] = wb[4 * c * 16];
             }
+#pragma unroll
+            for (int c = 0; c < CP / 4; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c], acc, 0, 0, 0);
+        }
+        // element v: position pt * 16 + 4 kq + v, channel co
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int pr = pt * 16 + 4 * kq + v;
+            if (pr >= PP || co >= Co) continue;
+            float val = acc[v] + bs;
+            if (relu) val = fmaxf(val, 0.f);
+            const size_t o = ((size_t)b * Co + co) * PP + pr;
+            if (mask && !(mask[o] > 0.f)) val = 0.f;
+            out[o] = val;
         }
     }
+}
+
+// Partial weight gradient as per-tap GEMMs over the positions, on matrix
+// cores: part[grp][tap][ci][co] = sum_{b in grp} sum_p x[b][ci][p + d(tap)]
+// g[b][co][p].  Workgroup (tap, grp), 4 waves; wave w owns the 16 x 16 block
+// (ci tile w / 2, co tile w % 2) of the Ci x Co result; positions are staged
+// 64 at a time (x shifted by the tap, zero outside the patch), one MFMA per
+// 4 positions.
+__global__ __launch_bounds__(CT) void k_conv_wgrad_mfma(const float *__restrict__ x, int Ci,
+                                                         const float *__restrict__ g, int Co, int B, int per_group,
+                                                         float *__restrict__ part)
+{
+    constexpr int CH = 64;
+    __shared__ float xs[CH][MAXC + 1];
+    __shared__ float gs[CH][MAXC + 1];
+    const int tap = blockIdx.x, grp = blockIdx.y;
+    const int b0 = grp * per_group, b1 = min(B, b0 + per_group);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const int ci = (wave >> 1) * 16 + row, co = (wave & 1) * 16 + row;   // A row / B column of this lane
+    const bool active = (wave >> 1) * 16 < Ci && (wave & 1) * 16 < Co;
+    f32x4m acc = {0.f, 0.f, 0.f, 0.f};
+    for (int b = b0; b < b1; ++b) {
+        for (int p0 = 0; p0 < PP; p0 += CH) {
+            for (int t = threadIdx.x; t < MAXC * CH; t += CT) {
+                const int c = t / CH, pp = t % CH, p = p0 + pp;
+                float xv = 0.f, gv = 0.f;
+                if (p < PP) {
+                    if (c < Ci) {
+                        const int q = nb_pos(p, tap);
+                        if (q >= 0) xv = x[((size_t)b * Ci + c) * PP + q];
+                    }
+                    if (c < Co) gv = g[((size_t)b * Co + c) * PP + p];
+                }
+                xs[pp][c] = xv;
+                gs[pp][c] = gv;
+            }
+            __syncthreads();
+            if (active)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int p = threadIdx.x + q * CT;
-        if (p >= PP) continue;
+                for (int k4 = 0; k4 < CH; k4 += 4)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[k4 + kq][ci], gs[k4 + kq][co], acc, 0, 0, 0);
+            __syncthreads();
+        }
+    }
+    // element v: ci row 4 kq + v of the wave's ci tile, co = this lane's column
+    if (active) {
+        const int cot = (wave & 1) * 16 + row;
 #pragma unroll
-        for (int j = 0; j < COG; ++j) {
-            if (j >= nco) continue;
-            const int co = co0 + j;
-            float v = acc[q][j] + (bias ? bias[co] : 0.f);
-            if (relu) v = fmaxf(v, 0.f);
-            const size_t o = ((size_t)b * Co + co) * PP + p;
-            if (mask && !(mask[o] > 0.f)) v = 0.f;
-            out[o] = v;
+        for (int v = 0; v < 4; ++v) {
+            const int cr = (wave >> 1) * 16 + 4 * kq + v;
+            if (cr < Ci && cot < Co) part[((size_t)grp * 27 + tap) * Ci * Co + (size_t)cr * Co + cot] = acc[v];
         }
     }
 }
@@ -101,53 +170,6 @@ __global__ __launch_bounds__(CT) void k_flip_weights(const float *__restrict__ W
     if (t >= 27 * Ci * Co) return;
     const int co = t % Co, ci = (t / Co) % Ci, tap = t / (Co * Ci);
     Wt[((size_t)(26 - tap) * Co + co) * Ci + ci] = W[t];
-}
-
-// Partial weight gradient of one tap over a group of patches:
-// part[grp][tap][ci][co] = sum_{b in grp} sum_p x[b][ci][p + d(tap)] g[b][co][p].
-__global__ __launch_bounds__(CT) void k_conv_wgrad(const float *__restrict__ x, int Ci, const float *__restrict__ g,
-                                                    int Co, int B, int per_group, float *__restrict__ part)
-{
-    constexpr int CH = 64;
-    __shared__ float xs[MAXC][CH + 1];
-    __shared__ float gs[MAXC][CH + 1];
-    const int tap = blockIdx.x, grp = blockIdx.y;
-    const int b0 = grp * per_group, b1 = min(B, b0 + per_group);
-    const int ne = Ci * Co;
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int b = b0; b < b1; ++b) {
-        for (int p0 = 0; p0 < PP; p0 += CH) {
-            for (int t = threadIdx.x; t < Ci * CH; t += CT) {
-                const int ci = t / CH, pp = t % CH, p = p0 + pp;
-                float v = 0.f;
-                if (p < PP) {
-                    const int q = nb_pos(p, tap);
-                    if (q >= 0) v = x[((size_t)b * Ci + ci) * PP + q];
-                }
-                xs[ci][pp] = v;
-            }
-            for (int t = threadIdx.x; t < Co * CH; t += CT) {
-                const int co = t / CH, pp = t % CH, p = p0 + pp;
-                gs[co][pp] = p < PP ? g[((size_t)b * Co + co) * PP + p] : 0.f;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int e = threadIdx.x + j * CT;
-                if (e >= ne) continue;
-                const int ci = e / Co, co = e % Co;
-                float s = 0.f;
-                for (int pp = 0; pp < CH; ++pp) s += xs[ci][pp] * gs[co][pp];
-                acc[j] += s;
-            }
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int e = threadIdx.x + j * CT;
-        if (e < ne) part[((size_t)grp * 27 + tap) * ne + e] = acc[j];
-    }
 }
 
 // grad[i] = sum over groups of part[grp][i] (fixed order).
@@ -377,7 +399,9 @@ static size_t layer_offset(int l)
     return o;
 }
 
-static int wgrad_groups(int B) { return B < 8 ? B : 8; }
+// Weight-gradient partials: one group (workgroup per tap) per patch, so the
+// matrix-core launch has 27 B workgroups; k_sum_groups adds them up.
+static int wgrad_groups(int B) { return B; }
 
 // Workspace (floats) for a batch of B patches: three hidden activations,
 // logits, softmax output, two gradient buffers, flipped weights, partial
@@ -532,6 +556,18 @@ __global__ __launch_bounds__(IT) void k_cnn_infer(const float *__restrict__ feat
     }
 }
 
+static void conv_mfma(hipStream_t st, int B, const float *x, int Ci, const float *W, const float *bias, int Co,
+                      float *out, int relu, const float *mask)
+{
+    dim3 grid(B, cdiv_u(Co, 16));
+    if (Ci <= 4)
+        k_conv_mfma<4><<<grid, MT, 0, st>>>(x, Ci, W, bias, Co, out, relu, mask);
+    else if (Ci <= 8)
+        k_conv_mfma<8><<<grid, MT, 0, st>>>(x, Ci, W, bias, Co, out, relu, mask);
+    else
+        k_conv_mfma<MAXC><<<grid, MT, 0, st>>>(x, Ci, W, bias, Co, out, relu, mask);
+}
+
 void cnn_forward(hipStream_t st, const float *params, const float *feat, int B, float *ws_f, float *phi_out)
 {
     CnnWs w = carve(ws_f, B);
@@ -541,8 +577,7 @@ void cnn_forward(hipStream_t st, const float *params, const float *feat, int B, 
         const float *W = params + layer_offset(l);
         const float *bias = W + 27 * Ci * Co;
         float *out = l < 3 ? w.a[l] : w.logits;
-        dim3 grid(B, cdiv_u(Co, COG));
-        k_conv_fwd<<<grid, CT, 0, st>>>(in, Ci, W, bias, Co, out, l < 3, nullptr);
+        conv_mfma(st, B, in, Ci, W, bias, Co, out, l < 3, nullptr);
         in = out;
     }
     k_softmax_mse<<<cdiv_u((size_t)B * PP, CT), CT, 0, st>>>(w.logits, nullptr, B, 0.f, phi_out ? phi_out : w.phi,
@@ -569,14 +604,13 @@ void cnn_loss_grad(hipStream_t st, const float *params, const float *feat, const
         float *gW = grad + layer_offset(l);
         float *gb = gW + 27 * Ci * Co;
         dim3 gw(27, groups);
-        k_conv_wgrad<<<gw, CT, 0, st>>>(xin, Ci, gcur, Co, B, per, w.part);
+        k_conv_wgrad_mfma<<<gw, CT, 0, st>>>(xin, Ci, gcur, Co, B, per, w.part);
         k_sum_groups<<<cdiv_u(27 * Ci * Co, CT), CT, 0, st>>>(w.part, groups, 27 * Ci * Co, gW);
         k_bias_grad<<<Co, CT, 0, st>>>(gcur, Co, B, gb);
         if (l > 0) {
             // input gradient through the flipped kernel, masked by ReLU'(a)
             k_flip_weights<<<cdiv_u(27 * Ci * Co, CT), CT, 0, st>>>(W, Ci, Co, w.wflip);
-            dim3 grid(B, cdiv_u(Ci, COG));
-            k_conv_fwd<<<grid, CT, 0, st>>>(gcur, Co, w.wflip, nullptr, Ci, gnext, 0, w.a[l - 1]);
+            conv_mfma(st, B, gcur, Co, w.wflip, nullptr, Ci, gnext, 0, w.a[l - 1]);
             float *t = gcur;
             gcur = gnext;
             gnext = t;
