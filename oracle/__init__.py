@@ -352,6 +352,7 @@ def redblack_order(pb) -> np.ndarray:
 SMOOTH_BLOCK = 0       # block-Jacobi ILU(0), natural order inside 8x8x8 blocks
 SMOOTH_REDBLACK = 1    # ILU(0) in red-black order
 SMOOTH_BLOCK_ALT = 2   # block ILU(0), every other step on the half-block-shifted block grid
+SMOOTH_NATURAL = 3     # ILU(0) of the whole matrix in natural (lexicographic) order
 
 
 def smoother_block(pb):
@@ -433,13 +434,16 @@ def cams_solve(pb, W, diag, P, restriction, LU, piv, ilu, r0, n_pre=None, n_post
 def smoother_for(pb, W, diag, smoother=None):
     """The ILU(0) smoother the problem asks for (default: block-Jacobi): one
     ILU0, or for SMOOTH_BLOCK_ALT the pair (blocks at the origin, shifted
-    blocks)."""
+    blocks); for SMOOTH_NATURAL the global ILU(0) in cell order; otherwise
+    the red-black order."""
     kind = getattr(pb, "smoother", SMOOTH_BLOCK) if smoother is None else smoother
     if kind == SMOOTH_BLOCK:
         return ILU0(pb, W, diag, block=smoother_block(pb))
     if kind == SMOOTH_BLOCK_ALT:
         return (ILU0(pb, W, diag, block=smoother_block(pb)),
                 ILU0(pb, W, diag, block=smoother_block(pb), shift=smoother_shift(pb)))
+    if kind == SMOOTH_NATURAL:
+        return ILU0(pb, W, diag, order=np.arange(pb.n, dtype=np.int64))
     return ILU0(pb, W, diag)
 
 
@@ -463,7 +467,7 @@ def newton_step(pb, T, P, pn, p, restriction=None, n_pre=None, n_post=None, lin_
         int(pb.lin_maxit if lin_maxit is None else lin_maxit),
         ctypes.c_double(pb.newton_tol if newton_tol is None else newton_tol),
         int(pb.newton_maxit if newton_maxit is None else newton_maxit),
-        int({SMOOTH_BLOCK: 1, SMOOTH_BLOCK_ALT: 2}.get(kind, 0)), *smoother_block(pb),
+        int({SMOOTH_BLOCK: 1, SMOOTH_BLOCK_ALT: 2, SMOOTH_NATURAL: 3}.get(kind, 0)), *smoother_block(pb),
         _ptr(_f64(pn)), _ptr(p), _ptr(st))
     return p, rc, {"newton_iters": int(st[0]), "lin_iters": int(st[1]), "eps_norm": float(st[2])}
 

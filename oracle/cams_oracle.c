@@ -1017,7 +1017,8 @@ int or_cams_solve(const og_grid *g, const double *Wx, const double *Wy, const do
  *           coarse operator + LU; ILU(0) smoother (smoother 0: red-black
  *           order; 1: block-Jacobi ILU(0) on bx x by x bz blocks; 2: the
  *           same blocks alternating, step by step, with the block grid
- *           shifted cyclically by half a block, (bx/2, by/2, bz/2)); C-AMS
+ *           shifted cyclically by half a block, (bx/2, by/2, bz/2); 3: the
+ *           whole matrix in natural order, the paper's global ILU(0)); C-AMS
  *           solve; p += d.
  * The basis P (type B4) is pressure independent and passed in.
  * stats[0] = Newton iterations, stats[1] = total linear iterations,
@@ -1041,7 +1042,10 @@ int or_newton_step(const og_grid *g, const og_fluid *f,
     double *Ac = (double *)malloc(sizeof(double) * (size_t)Nc * Nc);
     int32_t *piv = (int32_t *)malloc(sizeof(int32_t) * Nc);
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * N);
-    or_redblack_order(g, order);
+    if (smoother == 3)
+        for (long n = 0; n < N; n++) order[n] = n;
+    else
+        or_redblack_order(g, order);
     int rc = -1, nit = 0, lit = 0;
     double en = 0.0;
     for (nit = 0; nit <= newton_maxit; nit++) {
@@ -1050,7 +1054,7 @@ int or_newton_step(const og_grid *g, const og_fluid *f,
         if (nit == newton_maxit || !isfinite(en)) break;
         or_coarse_operator(g, W, W + N, W + 2 * N, diag, dmask, P, restriction, Ac);
         if (or_lu_factor(Nc, Ac, piv) != 0) { rc = -3; break; }
-        void *ilu = smoother >= 1 ? or_ilu0_block_create(g, W, W + N, W + 2 * N, diag, bx, by, bz)
+        void *ilu = (smoother == 1 || smoother == 2) ? or_ilu0_block_create(g, W, W + N, W + 2 * N, diag, bx, by, bz)
                                   : or_ilu0_create(g, W, W + N, W + 2 * N, diag, order);
         void *alt = smoother == 2 ? or_ilu0_block_create_shifted(g, W, W + N, W + 2 * N, diag, bx, by, bz,
                                                                  bx / 2, by / 2, bz / 2)
