@@ -253,6 +253,31 @@ def small_run(steps, warmup, torch):
     return out
 
 
+def smoothers_run(steps, warmup, torch):
+    """The library's four ILU(0) smoothers (Table "cams" step 6) on the
+    64x64x32 workload in FP64 (10 time steps per pass): block-Jacobi on 8^3
+    blocks, the same alternating with the half-block-shifted grid,
+    red-black, and the paper's global ILU(0) in natural order (a wavefront
+    over 16x16x8 bricks, one launch per brick diagonal).  C-AMS iterations
+    and seconds per Newton solve."""
+    from paper_1705_05783_amd.solver import Solver
+    from workloads import config2
+    from workloads.configs import FP64, SMOOTH_BLOCK, SMOOTH_BLOCK_ALT, SMOOTH_NATURAL, SMOOTH_REDBLACK
+    out = {"workload": "64x64x32 lognormal (sigma 3, corr. 8x8x2), coarsening 8^3 (256 coarse nodes), MSFE, "
+                       "FP64, 10 backward-Euler steps dt=0.05 per pass, Newton and linear solves to 1e-8"}
+    for label, sm in (("block", SMOOTH_BLOCK), ("block_alt", SMOOTH_BLOCK_ALT), ("red_black", SMOOTH_REDBLACK),
+                      ("natural", SMOOTH_NATURAL)):
+        pb = config2(precision=FP64).with_options(smoother=sm)
+        solver = Solver(pb)
+        r = timed_passes(solver, pb, steps, warmup, torch)
+        r.pop("prof")
+        out[label] = {k: r[k] for k in ("s_per_solve", "cams_iterations_per_solve", "iterate_ms_per_solve_median",
+                                        "ms_per_pass_median", "newton_solves_per_pass")}
+        out[label]["ms_per_cams_iteration"] = r["iterate_ms_per_solve_median"] / r["cams_iterations_per_solve"]
+        solver.close()
+    return out
+
+
 def large_run(steps, warmup, torch):
     """The 256x256x128 channelised workload (8.4M cells, 16384 coarse nodes,
     block-tridiagonal coarse factorisation), BF16 basis and prolongation,
@@ -400,9 +425,11 @@ def main():
     ap.add_argument("--steps", type=int, default=7, help="timed passes per workload (median reported)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed passes per workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["headline", "adaptive", "coarse", "small", "large", "batch", "copy", "all"],
+    ap.add_argument("--only", choices=["headline", "adaptive", "coarse", "small", "large", "batch", "smoothers",
+                                       "copy", "all"],
                     default="all",
                     help="headline/small/large/batch: that workload alone (one JSON object, for profiling); "
+                         "smoothers: the four ILU(0) smoothers on the 64x64x32 workload (not part of 'all'); "
                          "copy: a 256 MiB device copy, the reference kernel for scaling memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -420,9 +447,9 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copies": 3}), flush=True)
         return
     steps, warmup = max(1, args.steps), max(0, args.warmup)
-    if args.only in ("adaptive", "coarse", "small", "large", "batch"):
+    if args.only in ("adaptive", "coarse", "small", "large", "batch", "smoothers"):
         fn = {"adaptive": adaptive_run, "coarse": coarse_reuse_run, "small": small_run, "large": large_run,
-              "batch": lambda s, w, t: batch_run(s, w, t, False)}
+              "batch": lambda s, w, t: batch_run(s, w, t, False), "smoothers": smoothers_run}
         print(json.dumps({args.only: fn[args.only](steps, warmup, torch)}), flush=True)
         return
 

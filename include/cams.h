@@ -78,8 +78,14 @@ enum { CAMS_FP64 = 0, CAMS_MIXED_FP32 = 1, CAMS_MIXED_BF16 = 2 };
  * blocks of 8 consecutive positions; likewise y and z; an axis of at most 8
  * cells is one block either way); the first step of a stage takes the grid
  * at the origin.  A closer stand-in for the paper's global ILU(0):
- * fewer iterations for the same work per step. */
-enum { CAMS_SMOOTH_BLOCK_ILU0 = 0, CAMS_SMOOTH_RB_ILU0 = 1, CAMS_SMOOTH_BLOCK_ALT_ILU0 = 2 };
+ * fewer iterations for the same work per step.  NAT: ILU(0) of the whole
+ * matrix in natural (cell) order, the paper's own smoother; its triangular
+ * solves are wavefronts over the grid's diagonals (one launch per diagonal
+ * of 16 x 16 x 8 cell bricks), so a step costs far more than a block step
+ * and the iteration count is the reference the block forms are judged by.
+ * RB and NAT are FP64 only and take no part in batches. */
+enum { CAMS_SMOOTH_BLOCK_ILU0 = 0, CAMS_SMOOTH_RB_ILU0 = 1, CAMS_SMOOTH_BLOCK_ALT_ILU0 = 2,
+       CAMS_SMOOTH_NAT_ILU0 = 3 };
 
 /* Basis function type (Sec. 3, Eqs. (8)-(11)), each solved with the same
  * reduced-problem boundary conditions, in the mass form of the Newton
@@ -114,7 +120,7 @@ typedef struct {
     int32_t n_pre;            /* ILU(0) Richardson steps before the multiscale stage (0..64) */
     int32_t n_post;           /* ILU(0) Richardson steps after it (Table "cams" step 6; 0..64) */
     int32_t precision;        /* CAMS_FP64 / CAMS_MIXED_FP32 / CAMS_MIXED_BF16 */
-    int32_t smoother;         /* CAMS_SMOOTH_BLOCK_ILU0, CAMS_SMOOTH_RB_ILU0 or CAMS_SMOOTH_BLOCK_ALT_ILU0 */
+    int32_t smoother;         /* CAMS_SMOOTH_BLOCK_ILU0, _RB_ILU0, _BLOCK_ALT_ILU0 or _NAT_ILU0 */
     double lin_rtol;          /* stop when ||r||_2 <= lin_rtol ||r0||_2 */
     int32_t lin_maxit;        /* linear iteration limit */
     double newton_tol;        /* stop Newton when ||eps||_2 <= newton_tol (Eq. (16)) */

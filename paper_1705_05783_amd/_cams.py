@@ -28,6 +28,7 @@ CAMS_MIXED_BF16 = 2
 CAMS_SMOOTH_BLOCK_ILU0 = 0
 CAMS_SMOOTH_RB_ILU0 = 1
 CAMS_SMOOTH_BLOCK_ALT_ILU0 = 2
+CAMS_SMOOTH_NAT_ILU0 = 3
 
 CAMS_ARR_T = 0
 CAMS_ARR_W = 1

@@ -265,9 +265,9 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     if (O.precision != CAMS_FP64 && O.precision != CAMS_MIXED_FP32 && O.precision != CAMS_MIXED_BF16)
         return CAMS_E_ARG;
     if (O.smoother != CAMS_SMOOTH_BLOCK_ILU0 && O.smoother != CAMS_SMOOTH_RB_ILU0 &&
-        O.smoother != CAMS_SMOOTH_BLOCK_ALT_ILU0)
+        O.smoother != CAMS_SMOOTH_BLOCK_ALT_ILU0 && O.smoother != CAMS_SMOOTH_NAT_ILU0)
         return CAMS_E_ARG;
-    if (O.precision != CAMS_FP64 && O.smoother == CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
+    if (O.precision != CAMS_FP64 && !block_smoother(O)) return CAMS_E_ARG;
     if (!(O.lin_rtol > 0) || O.lin_maxit < 1 || !(O.newton_tol > 0) || O.newton_maxit < 1) return CAMS_E_ARG;
     if (!(O.lin_atol >= 0) || !isfinite(O.lin_atol)) return CAMS_E_ARG;
     if (O.basis_type < CAMS_BASIS_B4 || O.basis_type > CAMS_BASIS_B3 || !(O.basis_tol >= 0)) return CAMS_E_ARG;
@@ -958,7 +958,7 @@ static void enqueue_iteration(cams_ctx *c, int it)
         if (O.n_post > 0) launch_bilu_smooth32(c, (const float *)a.r1f, a.d2f, O.n_post, done, a.d1f);
         return;
     }
-    const bool block = O.smoother != CAMS_SMOOTH_RB_ILU0;
+    const bool block = block_smoother(O);
     const double *pend0 = O.n_pre > 0 ? a.d0 : nullptr;
     const double *pend1 = O.n_post > 0 && block ? a.d2 : a.d1;
     const double *pend2 = O.n_post > 0 && !block ? a.d2 : nullptr;
@@ -1006,9 +1006,10 @@ cams_status cams_iterate(cams_ctx *c, double *p_dev, cams_stats *stats)
         // its best value for kStagWindow iterations
         double best_nr = -1.0;
         int it_best = 0;
-        // the red-black smoother kernels have no stop flag: check every
-        // iteration; so does a norm history (one entry per iteration)
-        const bool sync_each = O.smoother == CAMS_SMOOTH_RB_ILU0 || c->hist;
+        // the red-black and natural-order smoother kernels have no stop
+        // flag: check every iteration; so does a norm history (one entry
+        // per iteration)
+        const bool sync_each = !block_smoother(O) || c->hist;
         for (;;) {
             const int batch = sync_each ? 1 : ahead;
             for (int q = 0; q < batch && launched <= O.lin_maxit; ++q) enqueue_iteration(c, launched++);

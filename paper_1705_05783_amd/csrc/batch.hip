@@ -293,7 +293,7 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         const cams_ctx *c = ctxs[i];
         if (!c) return CAMS_E_ARG;
         if (c->stream != st) return CAMS_E_ARG;                 // one stream for the whole batch
-        if (c->opt.smoother == CAMS_SMOOTH_RB_ILU0) return CAMS_E_ARG;
+        if (!block_smoother(c->opt)) return CAMS_E_ARG;             // batches run block smoothers
         if (c->opt.basis_type != CAMS_BASIS_B4) return CAMS_E_ARG;   // the batch builds B4 bases
         if (c->opt.precision != O.precision || c->opt.n_pre != O.n_pre || c->opt.n_post != O.n_post)
             return CAMS_E_ARG;

@@ -281,6 +281,14 @@ void launch_prolong(cams_ctx *c, const double *xc, double *out, const int32_t *d
 void launch_ilu_setup(cams_ctx *c);  // dispatches on opt.smoother
 void launch_rb_setup(cams_ctx *c);
 void launch_rb_smooth(cams_ctx *c, const double *rhs, double *e, int steps);
+void launch_nat_setup(cams_ctx *c);
+void launch_nat_smooth(cams_ctx *c, const double *rhs, double *e, int steps);
+// Block ILU(0) smoothers (BLOCK, BLOCK_ALT): the forms with device stop
+// flags, mixed-precision variants and batched kernels.
+inline bool block_smoother(const cams_options &o)
+{
+    return o.smoother == CAMS_SMOOTH_BLOCK_ILU0 || o.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0;
+}
 // dispatches on opt.smoother; `done` (nullable) skips the work once the iteration has converged
 void launch_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const int32_t *done);
 void launch_axpy(cams_ctx *c, double *y, const double *x, int n);

@@ -472,6 +472,8 @@ void launch_ilu_setup(cams_ctx *c)
 {
     if (c->opt.smoother == CAMS_SMOOTH_RB_ILU0)
         launch_rb_setup(c);
+    else if (c->opt.smoother == CAMS_SMOOTH_NAT_ILU0)
+        launch_nat_setup(c);
     else
         launch_bilu_setup(c);
 }
@@ -480,6 +482,8 @@ void launch_smooth(cams_ctx *c, const double *rhs, double *e, int steps, const i
 {
     if (c->opt.smoother == CAMS_SMOOTH_RB_ILU0)
         launch_rb_smooth(c, rhs, e, steps);   // the red-black path is host-controlled only
+    else if (c->opt.smoother == CAMS_SMOOTH_NAT_ILU0)
+        launch_nat_smooth(c, rhs, e, steps);  // so is the natural-order one
     else
         launch_bilu_smooth(c, rhs, e, steps, done);
 }

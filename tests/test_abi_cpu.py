@@ -94,7 +94,7 @@ def test_create_rejects_bad_fluid(lib, field, value):
 
 @pytest.mark.parametrize("field,value", [("restriction", 3), ("n_post", -1), ("n_pre", 65),
                                          ("lin_rtol", 0.0), ("lin_maxit", 0), ("newton_maxit", 0),
-                                         ("precision", 7), ("smoother", 3), ("smoother", -1)])
+                                         ("precision", 7), ("smoother", 4), ("smoother", -1)])
 def test_create_rejects_bad_options(lib, field, value):
     from paper_1705_05783_amd import _cams as C
     o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 0, 1e-8, 100, 1e-8, 20)
@@ -127,7 +127,11 @@ def test_mixed_precision_needs_block_smoother(lib):
         assert s == C.CAMS_OK
         n_mixed = C.cams_workspace_bytes(h)
         C.cams_destroy(h)
-        o.smoother = C.CAMS_SMOOTH_RB_ILU0
+        for fp64_only in (C.CAMS_SMOOTH_RB_ILU0, C.CAMS_SMOOTH_NAT_ILU0):
+            o.smoother = fp64_only
+            s, h = _create(opt=o)
+            assert s == C.CAMS_E_ARG
+        o.smoother = 4                        # no such smoother
         s, h = _create(opt=o)
         assert s == C.CAMS_E_ARG
         o.smoother = C.CAMS_SMOOTH_BLOCK_ALT_ILU0
@@ -135,6 +139,10 @@ def test_mixed_precision_needs_block_smoother(lib):
         assert s == C.CAMS_OK
         assert C.cams_workspace_bytes(h) > n_mixed   # the shifted grid's pivots (FP64 and FP32)
         C.cams_destroy(h)
+    o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, C.CAMS_SMOOTH_NAT_ILU0, 1e-8, 100, 1e-8, 20)
+    s, h = _create(opt=o)
+    assert s == C.CAMS_OK
+    C.cams_destroy(h)
     o = C.cams_options(C.CAMS_R_FE, 0, 5, C.CAMS_FP64, 0, 1e-8, 100, 1e-8, 20)
     s, h = _create(opt=o)
     assert C.cams_workspace_bytes(h) < n_mixed

@@ -15,7 +15,7 @@ import pytest
 import oracle
 from tests.gpu_util import checked_newton_step, linear_residual_check, log, rel_err, require_gpu, solver_for, to_np
 from workloads import config1, config2, small_problem
-from workloads.configs import FE, FV, SMOOTH_BLOCK, SMOOTH_BLOCK_ALT, SMOOTH_REDBLACK
+from workloads.configs import FE, FV, SMOOTH_BLOCK, SMOOTH_BLOCK_ALT, SMOOTH_NATURAL, SMOOTH_REDBLACK
 
 pytestmark = pytest.mark.gpu
 
@@ -136,14 +136,16 @@ def _oracle_smooth(pb, W, diag, z):
     return x + ilu[1].apply(z - oracle.matvec(pb, W, diag, x))
 
 
-@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK, SMOOTH_BLOCK_ALT])
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK, SMOOTH_BLOCK_ALT, SMOOTH_NATURAL])
 @pytest.mark.parametrize("shape,r", SHAPES + [((37, 29, 19), 4), ((75, 70, 45), 8)])
 def test_smoother_apply(_gpu, shape, r, smoother):
     """One smoother application against the oracle's.  The small grids have
     fewer 8^3 blocks than the device has compute units (register sweeps); the
     75x70x45 grid (540 blocks, ragged on every axis) takes the LDS sweeps.
     The shifted block grid wraps round every axis (axes shorter than a block
-    included)."""
+    included).  The natural-order factor's wavefront runs over 16x16x8
+    bricks: one brick (13x11x1) up to 5x5x6 ragged bricks on 14 diagonals
+    (75x70x45)."""
     torch = _gpu
     pb = _pb(shape, r, sigma=2.0, seed=6)
     pb.smoother = smoother
@@ -163,16 +165,19 @@ def test_smoother_apply(_gpu, shape, r, smoother):
     z[~free] = 0.0
     x = to_np(s.smooth_apply(torch.as_tensor(z, device="cuda")))
     assert rel_err(x, _oracle_smooth(pb, W, diag, z)) <= 1e-12
-    if smoother == SMOOTH_BLOCK_ALT:
-        # inverse pivots of both block grids: 1 / diag(U) of the oracle's factors
-        iv = to_np(s.export(C.CAMS_ARR_INVD)).reshape(2, -1)
-        for h, f in enumerate(oracle.smoother_for(pb, W, diag)):
+    if smoother in (SMOOTH_BLOCK_ALT, SMOOTH_NATURAL):
+        # inverse pivots (both block grids for the alternating smoother):
+        # 1 / diag(U) of the oracle's factors
+        factors = oracle.smoother_for(pb, W, diag)
+        factors = factors if isinstance(factors, tuple) else (factors,)
+        iv = to_np(s.export(C.CAMS_ARR_INVD)).reshape(len(factors), -1)
+        for h, f in enumerate(factors):
             rp, col, val = f.export()
             dpos = [rp[t] + int(np.nonzero(col[rp[t]:rp[t + 1]] == t)[0][0]) for t in range(pb.n)]
             assert rel_err(iv[h], 1.0 / val[dpos]) <= 1e-13
 
 
-@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK, SMOOTH_BLOCK_ALT])
+@pytest.mark.parametrize("smoother", [SMOOTH_BLOCK, SMOOTH_REDBLACK, SMOOTH_BLOCK_ALT, SMOOTH_NATURAL])
 @pytest.mark.parametrize("restriction,n_pre", [(FE, 0), (FV, 0), (FV, 5)])
 @pytest.mark.parametrize("shape,r", [((16, 12, 8), 4), ((24, 24, 16), 8), ((20, 20, 1), 4)])
 def test_linear_solve(_gpu, shape, r, restriction, n_pre, smoother):
@@ -234,7 +239,10 @@ def test_newton_config1_2d_msfv(_gpu):
                                                            ((13, 11, 1), (3, 4, 1), FE, SMOOTH_BLOCK),
                                                            ((19, 17, 11), (4, 3, 5), FE, SMOOTH_BLOCK_ALT),
                                                            ((24, 24, 16), 8, FV, SMOOTH_BLOCK_ALT),
-                                                           ((13, 11, 1), (3, 4, 1), FE, SMOOTH_BLOCK_ALT)])
+                                                           ((13, 11, 1), (3, 4, 1), FE, SMOOTH_BLOCK_ALT),
+                                                           ((19, 17, 11), (4, 3, 5), FE, SMOOTH_NATURAL),
+                                                           ((24, 24, 16), 8, FV, SMOOTH_NATURAL),
+                                                           ((13, 11, 1), (3, 4, 1), FE, SMOOTH_NATURAL)])
 def test_newton_3d(_gpu, shape, r, restriction, smoother):
     pb = _pb(shape, r, sigma=2.5, seed=8, restriction=restriction, c=0.08, dt=0.05)
     pb.smoother = smoother
@@ -284,6 +292,39 @@ def test_config2_full_size_workload_tolerances(_gpu):
             assert rc == 0
             assert rel_err(to_np(p_t), p_ref) <= 1e-7
         pn_t.copy_(p_t)
+
+
+def test_natural_smoother_config2_matches_oracle(_gpu):
+    """The paper's global ILU(0) (natural order; a wavefront over 16x16x8
+    bricks on the GPU) on the 64x64x32 workload, first time step at the
+    workload tolerances: every Newton iteration's update meets the linear
+    tolerance on the oracle's FP64 matrix; the Newton and C-AMS iteration
+    counts match the oracle's own natural-order Newton (one per solve of
+    slack); the pressures agree to the stopping level.  It needs fewer
+    iterations than the block-Jacobi smoothers (the reference count for
+    them, Table "cams" step 6)."""
+    torch = _gpu
+    pb = config2().with_options(smoother=SMOOTH_NATURAL)
+    s = solver_for(pb)
+    T = oracle.transmissibility(pb)
+    pn = pb.initial_pressure()
+    pn_t = torch.as_tensor(pn, device="cuda")
+    p_t = pn_t.clone()
+    nit, lits, worst = checked_newton_step(s, pb, T, pn_t, p_t, torch)
+    P = oracle.basis_b4(pb, T)
+    p_ref, rc, ost = oracle.newton_step(pb, T, P, pn, pn)
+    assert rc == 0
+    log("natural ILU(0) 64x64x32: gpu newton", nit, "C-AMS", lits, "oracle", ost, "worst relres/bound", worst)
+    assert nit == ost["newton_iters"]
+    assert abs(lits - ost["lin_iters"]) <= nit
+    assert rel_err(to_np(p_t), p_ref) <= 1e-7
+    s.close()
+    blk = solver_for(config2().with_options(smoother=SMOOTH_BLOCK_ALT))
+    q_t = pn_t.clone()
+    st = blk.newton_step(pn_t.clone(), q_t, check=False)
+    log("alternating block smoother: C-AMS", st["lin_iters_total"])
+    assert st["lin_iters_total"] > lits
+    blk.close()
 
 
 def test_config2_plain_full_size_to_1e10(_gpu):

@@ -34,6 +34,7 @@ MIXED_BF16 = 2
 SMOOTH_BLOCK = 0      # block-Jacobi ILU(0) on 8x8x8 blocks
 SMOOTH_REDBLACK = 1   # ILU(0) in red-black order
 SMOOTH_BLOCK_ALT = 2  # block ILU(0), every other step on the half-block-shifted block grid
+SMOOTH_NATURAL = 3    # ILU(0) of the whole matrix in natural (cell) order
 
 
 @dataclasses.dataclass
