@@ -65,7 +65,7 @@ def run_pass(solver, pb):
     pn = solver.new_pressure()
     p = pn.clone()
     out = {"solves": 0, "iters": 0, "t_iterate_ms": 0.0, "t_basis_ms": 0.0, "t_coarse_ms": 0.0,
-           "t_assemble_ms": 0.0, "fallback_blocks": 0, "coarse_factorizations": 0}
+           "t_assemble_ms": 0.0, "fallback_blocks": 0, "coarse_factorizations": 0, "basis_rebuilds": 0}
     for _ in range(pb.n_steps):
         st = solver.newton_step(pn, p)
         out["solves"] += st["newton_iters"]
@@ -74,6 +74,7 @@ def run_pass(solver, pb):
             out[k] += st[k]
         out["fallback_blocks"] = max(out["fallback_blocks"], st["fallback_blocks"])
         out["coarse_factorizations"] += st["coarse_factorizations"]
+        out["basis_rebuilds"] += st["basis_rebuilds"]
         pn.copy_(p)
     return out
 
@@ -111,6 +112,7 @@ def timed_passes(solver, pb, steps, warmup, torch):
             "coarse_ms_per_solve_median": float(np.median([s["t_coarse_ms"] / max(s["solves"], 1)
                                                           for s in stats])),
             "fallback_blocks": stats[0]["fallback_blocks"],
+            "basis_rebuilds": sum(s["basis_rebuilds"] for s in stats),
             "coarse_factorizations_per_pass": stats[0]["coarse_factorizations"], "prof": prof}
 
 
@@ -166,13 +168,17 @@ def headline(steps, warmup, torch):
                                  ("learned_mixed", MIXED_FP32, True)):
         pb = config5_eval(precision=prec)
         solver = Solver(pb)
+        guard = 0
         if learned:
-            solver.set_learned(params, fallback_tol=tol)
+            # global check: twice the exact basis' iterations per solve (mixed run)
+            guard = int(np.ceil(out["mixed"]["cams_iterations_per_solve"]))
+            solver.set_learned(params, fallback_tol=tol, guard_iters=guard)
         r = timed_passes(solver, pb, steps, warmup, torch)
         r["roofline_smoother"] = roofline(r.pop("prof"), f"128^3 {label}",
                                           SMOOTHER_KERNEL["many", "f64" if prec == FP64 else "f32"])
         if learned:
             r["fallback_tol"] = tol
+            r["guard_iters"] = guard
             r["full_dual_blocks"] = solver.num_full_blocks()
         r["coarse_nodes"] = solver.Nc
         out[label] = r

@@ -151,7 +151,8 @@ typedef struct {
     int32_t basis_updates;          /* B1/B2: adaptive basis updates in the last cams_newton_step */
     int32_t basis_regions_rebuilt;  /* dual regions solved by the basis builds and updates of that step */
     int32_t coarse_factorizations;  /* coarse inverses computed in that step (< newton_iters with coarse_tol) */
-    int32_t reserved;
+    int32_t basis_rebuilds;         /* learned basis replaced by local solves in that step (the check of
+                                     * cams_set_learned_guard; 0 or 1) */
 } cams_stats;
 
 /* Create a context for one grid.  Validates grid/fluid/options: active axes
@@ -416,6 +417,18 @@ size_t cams_learned_scratch_bytes(const cams_ctx *ctx);
  * ratio 8, scratch too small, fallback_tol <= 0). */
 cams_status cams_set_learned(cams_ctx *ctx, const float *params_dev, void *scratch_dev, size_t scratch_bytes,
                              double fallback_tol);
+/* Global check of the learned basis, beside the per-block one: plain_iters
+ * is the number of C-AMS iterations per Newton linear solve that the exact
+ * (local-solve) basis needs on this problem, measured by the caller (0, the
+ * default, switches the check off).  When a linear solve of
+ * cams_newton_step with the learned basis takes more than 2 * plain_iters
+ * iterations, or stops without converging, the basis is rebuilt with local
+ * solves; the Newton iteration goes on from the iterate reached, and the
+ * rest of the time step and every later one use the exact basis
+ * (stats.basis_rebuilds counts the rebuild).  The learned basis comes back
+ * with the next cams_set_learned or cams_set_rock.
+ * Errors: CAMS_E_ARG (plain_iters < 0). */
+cams_status cams_set_learned_guard(cams_ctx *ctx, int32_t plain_iters);
 /* Blocks taken from the network and blocks re-solved by the fallback in the
  * last cams_build_basis.  Errors: CAMS_E_ARG. */
 /* The local-equation ratio ||(T Phi)_I|| / ||T_IF Phi_F|| of the network's

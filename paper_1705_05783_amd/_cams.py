@@ -74,10 +74,10 @@ class cams_stats(ctypes.Structure):
                 ("t_assemble_ms", ctypes.c_double), ("t_basis_ms", ctypes.c_double),
                 ("t_coarse_ms", ctypes.c_double), ("t_iterate_ms", ctypes.c_double),
                 ("basis_updates", ctypes.c_int32), ("basis_regions_rebuilt", ctypes.c_int32),
-                ("coarse_factorizations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("coarse_factorizations", ctypes.c_int32), ("basis_rebuilds", ctypes.c_int32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 # (name, restype, argtypes) for every entry point declared in include/cams.h
@@ -118,6 +118,7 @@ _SIGS = [
     ("cams_cnn_patches", _I, [_VP, _VP, _VP]),
     ("cams_learned_scratch_bytes", ctypes.c_size_t, [_VP]),
     ("cams_set_learned", _I, [_VP, _VP, _VP, ctypes.c_size_t, ctypes.c_double]),
+    ("cams_set_learned_guard", _I, [_VP, ctypes.c_int32]),
     ("cams_basis_stats", _I, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     ("cams_basis_block_ratios", _I, [_VP, _VP, ctypes.c_int32]),
     ("cams_profile", _I, [_VP, _I]),

@@ -675,6 +675,7 @@ cams_status cams_set_rock(cams_ctx *c, const double *perm_dev, const double *phi
     c->has_q = q_dev != nullptr;
     c->has_rock = true;
     c->has_basis = c->has_system = c->has_coarse = false;
+    c->learned_suspended = false;
     return CAMS_OK;
 }
 
@@ -846,7 +847,7 @@ cams_status cams_build_basis(cams_ctx *c)
         clear_status(c);
         c->learned_blocks = c->fallback_blocks = 0;
         c->block_ratio.clear();
-        if (c->learned_params && c->nfull > 0) {
+        if (c->learned_params && c->nfull > 0 && !c->learned_suspended) {
             build_basis_learned(c);
             if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
         } else {
@@ -1154,6 +1155,22 @@ cams_status cams_newton_step(cams_ctx *c, const double *pn_dev, double *p_dev, c
             st.lin_iters_total += ls.lin_iters_last;
             st.lin_iters_last = ls.lin_iters_last;
             st.relres_last = ls.relres_last;
+            // global check of the learned basis: a solve that needs more
+            // than twice the exact basis' iterations, or does not converge,
+            // replaces the network's basis by local solves from here on
+            if (c->learned_params && c->nfull > 0 && !c->learned_suspended && c->guard_iters > 0 &&
+                (s == CAMS_E_NOT_CONVERGED || ls.lin_iters_last > 2 * c->guard_iters)) {
+                c->learned_suspended = true;
+                CAMS_HIP(hipEventRecord(c->ev[0], c->stream));
+                s = cams_build_basis(c);
+                if (s != CAMS_OK) break;
+                CAMS_HIP(hipEventRecord(c->ev[1], c->stream));
+                CAMS_HIP(hipEventSynchronize(c->ev[1]));
+                st.t_basis_ms += elapsed_ms(c, 0, 1);
+                st.basis_regions_rebuilt += c->region_total;
+                st.basis_rebuilds += 1;
+                continue;   // the next Newton iteration assembles at the iterate reached
+            }
             if (s != CAMS_OK) break;
         }
     } catch (const HipError &e) {
@@ -1392,7 +1409,16 @@ cams_status cams_set_learned(cams_ctx *c, const float *params, void *scratch, si
     c->learned_scratch = (char *)scratch;
     c->learned_scratch_bytes = bytes;
     c->fallback_tol = fallback_tol;
+    c->learned_suspended = false;
     c->has_basis = c->has_coarse = false;
+    return CAMS_OK;
+}
+
+cams_status cams_set_learned_guard(cams_ctx *c, int32_t plain_iters)
+{
+    if (!c) return CAMS_E_ARG;
+    if (plain_iters < 0) return fail(c, CAMS_E_ARG, "plain_iters must be >= 0 (0: no global check)");
+    c->guard_iters = plain_iters;
     return CAMS_OK;
 }
 

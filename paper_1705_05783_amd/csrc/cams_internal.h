@@ -200,6 +200,8 @@ struct cams_ctx {
     char *learned_scratch;
     size_t learned_scratch_bytes;
     double fallback_tol;
+    int guard_iters;          // exact-basis iterations per solve for the global check (0: off)
+    bool learned_suspended;   // the global check switched the basis to local solves
     int learned_blocks, fallback_blocks;
     std::vector<cams::Region> fallback_list;
     std::vector<double> block_ratio;   // local-equation ratio of each full block in the last learned build

@@ -164,9 +164,12 @@ class Solver:
                 "cams_cnn_patches")
         return feat, tgt
 
-    def set_learned(self, params, fallback_tol=1e-2):
+    def set_learned(self, params, fallback_tol=1e-2, guard_iters=0):
         """Use the network for full-block interiors (params: float32 device
-        tensor), or exact local solves again (params None)."""
+        tensor), or exact local solves again (params None).  guard_iters > 0:
+        the exact basis' C-AMS iterations per solve, for the global check
+        (cams_set_learned_guard)."""
+        C.check(C.cams_set_learned_guard(self.ctx, int(guard_iters)), self.ctx, "cams_set_learned_guard")
         if params is None:
             C.check(C.cams_set_learned(self.ctx, None, None, 0, 0.0), self.ctx, "cams_set_learned")
             self._learned = None

@@ -119,6 +119,19 @@ def test_null_arguments(lib):
     assert C.cams_workspace_bytes(None) == 0
 
 
+def test_learned_guard_arguments(lib):
+    """The learned basis' global check takes a count >= 0 (0: off); no
+    device call, so it runs without a GPU."""
+    from paper_1705_05783_amd import _cams as C
+    s, h = _create()
+    assert s == C.CAMS_OK
+    assert C.cams_set_learned_guard(h, 0) == C.CAMS_OK
+    assert C.cams_set_learned_guard(h, 55) == C.CAMS_OK
+    assert C.cams_set_learned_guard(h, -1) == C.CAMS_E_ARG
+    assert C.cams_set_learned_guard(None, 5) == C.CAMS_E_ARG
+    C.cams_destroy(h)
+
+
 def test_mixed_precision_needs_block_smoother(lib):
     from paper_1705_05783_amd import _cams as C
     for prec in (C.CAMS_MIXED_FP32, C.CAMS_MIXED_BF16):

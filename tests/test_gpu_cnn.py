@@ -307,3 +307,47 @@ def test_config5_learned_mixed_full_size(torch):
         s.basis_stats())
     assert nit >= 1 and e <= pb.newton_tol
     s.close()
+
+
+def test_learned_global_guard(torch):
+    """The global check of the learned basis (cams_set_learned_guard).  On a
+    64x64x32 field the exact basis needs n_plain C-AMS iterations per solve.
+    With the trained network, the calibrated per-block fallback and the check
+    at n_plain, no rebuild happens (the network's solves stay well below
+    twice that).  With the check at one iteration, which every learned solve
+    exceeds, the first solve triggers it: afterwards the basis equals the
+    oracle's exact basis (local solves), the time step still converges (the
+    oracle's nonlinear error of the pressure meets the Newton tolerance), and
+    the next time step, already on the exact basis, rebuilds nothing.  A
+    negative count is refused."""
+    from paper_1705_05783_amd import _cams as C
+    from paper_1705_05783_amd.train_basis import load_fallback_tol, load_weights
+    pb = small_problem(64, 64, 32, 8, sigma=2.5, seed=23)
+    T = oracle.transmissibility(pb)
+    pn = torch.as_tensor(pb.initial_pressure(), device="cuda")
+    exact = solver_for(pb)
+    st0 = exact.newton_step(pn.clone(), pn.clone())
+    plain = -(-st0["lin_iters_total"] // st0["newton_iters"])
+    exact.close()
+    params = load_weights()
+    s = solver_for(pb)
+    s.set_learned(params, fallback_tol=load_fallback_tol(), guard_iters=plain)
+    st1 = s.newton_step(pn.clone(), pn.clone())
+    log("exact basis: C-AMS per solve", plain, "| learned with the check at that count:", st1["lin_iters_total"],
+        "over", st1["newton_iters"], "solves, rebuilds", st1["basis_rebuilds"])
+    assert st1["basis_rebuilds"] == 0
+    s.close()
+    s = solver_for(pb)
+    s.set_learned(params, fallback_tol=load_fallback_tol(), guard_iters=1)
+    p = pn.clone()
+    st2 = s.newton_step(pn.clone(), p)
+    log("check at one iteration:", st2)
+    assert st2["basis_rebuilds"] == 1
+    P = to_np(s.export(C.CAMS_ARR_P)).reshape(8, -1)
+    assert np.max(np.abs(P - oracle.basis_b4(pb, T))) <= 1e-12
+    _, e = oracle.nonlinear_residual(pb, T, to_np(p), to_np(pn))
+    assert e <= pb.newton_tol
+    st3 = s.newton_step(p.clone(), p.clone())
+    assert st3["basis_rebuilds"] == 0
+    assert C.cams_set_learned_guard(s.ctx, -1) == C.CAMS_E_ARG
+    s.close()
