@@ -323,6 +323,15 @@ typedef enum {
 
 size_t cams_array_bytes(const cams_ctx *ctx, cams_array which);
 cams_status cams_export(cams_ctx *ctx, cams_array which, void *dst_dev, size_t bytes);
+/* Replace the basis by a saved one: src_dev holds 8*N doubles on the device,
+ * slot-major as CAMS_ARR_P exports them, bytes = cams_array_bytes(ctx,
+ * CAMS_ARR_P).  For resuming a run from a checkpoint without rebuilding the
+ * basis: types B3 and B4 only, whose basis depends on the rock and not on
+ * the pressure (Sec. 3).  The mixed precisions round it as after a build;
+ * the next cams_coarse_op uses it.  The caller vouches that it belongs to
+ * the current rock.  Errors: CAMS_E_ARG (null, size, basis type B1/B2),
+ * CAMS_E_STATE (no rock), CAMS_E_DEVICE. */
+cams_status cams_import_basis(cams_ctx *ctx, const void *src_dev, size_t bytes);
 
 /* Test hook of the coarse factorisation's FP64 matrix-core GEMM: C -= A B for
  * dense row-major DEVICE matrices C (M x Nn), A (M x K), B (K x Nn), run on the

@@ -102,6 +102,7 @@ _SIGS = [
     ("cams_smooth_apply", _I, [_VP, _VP, _VP]),
     ("cams_array_bytes", ctypes.c_size_t, [_VP, _I]),
     ("cams_export", _I, [_VP, _I, _VP, ctypes.c_size_t]),
+    ("cams_import_basis", _I, [_VP, _VP, ctypes.c_size_t]),
     ("cams_num_coarse", ctypes.c_int64, [_VP]),
     ("cams_debug_gemm_sub", _I, [_VP, _VP, _VP, _VP, _I, _I, _I]),
     ("cams_cnn_num_params", ctypes.c_int64, []),

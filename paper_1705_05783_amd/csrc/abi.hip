@@ -1278,6 +1278,27 @@ size_t cams_array_bytes(const cams_ctx *c, cams_array which)
     return 0;
 }
 
+cams_status cams_import_basis(cams_ctx *c, const void *src, size_t bytes)
+{
+    if (!c || !src) return CAMS_E_ARG;
+    if (!c->has_rock) return fail(c, CAMS_E_STATE, "import_basis before set_rock");
+    if (c->opt.basis_type != CAMS_BASIS_B4 && c->opt.basis_type != CAMS_BASIS_B3)
+        return fail(c, CAMS_E_ARG, "only the pressure-independent bases (B3, B4) can be imported");
+    if (bytes != cams_array_bytes(c, CAMS_ARR_P)) return fail(c, CAMS_E_ARG, "basis must hold 8 N doubles");
+    try {
+        CAMS_HIP(hipMemcpyAsync(c->a.P, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+        if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
+        CAMS_HIP(hipGetLastError());
+    } catch (const HipError &e) {
+        return fail(c, CAMS_E_DEVICE, std::string("import_basis: ") + hipGetErrorString(e.code));
+    }
+    c->learned_blocks = c->fallback_blocks = 0;
+    c->block_ratio.clear();
+    c->has_basis = true;
+    c->has_coarse = c->has_cfac = false;
+    return CAMS_OK;
+}
+
 cams_status cams_export(cams_ctx *c, cams_array which, void *dst, size_t bytes)
 {
     if (!c || !dst) return CAMS_E_ARG;

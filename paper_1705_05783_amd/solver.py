@@ -212,6 +212,12 @@ class Solver:
         C.check(C.cams_export(self.ctx, which, _ptr(out), nbytes), self.ctx, "cams_export")
         return out
 
+    def import_basis(self, P: torch.Tensor):
+        """Use a saved basis (8*N float64 on this device, as export(CAMS_ARR_P)
+        returns it) instead of rebuilding it (types B3/B4)."""
+        P = P.to(device=self.device, dtype=torch.float64).contiguous()
+        C.check(C.cams_import_basis(self.ctx, _ptr(P), P.numel() * 8), self.ctx, "cams_import_basis")
+
     def new_pressure(self) -> torch.Tensor:
         return torch.as_tensor(self.pb.initial_pressure(), dtype=torch.float64, device=self.device)
 
