@@ -345,6 +345,17 @@ def batch_run(steps, warmup, torch, sequential=True):
            "instances_per_s": len(pbs) / med, "cells_per_s": sum(sizes) / med, "passes": steps,
            "cams_iterations": {"min": int(its.min()), "mean": float(its.mean()), "max": int(its.max())},
            "setup_ms": stats[0]["t_coarse_ms"], "iterate_ms": stats[0]["t_iterate_ms"], "tuning": b.tuning()}
+    # the batched FP32 smoothing step of the chosen form, as the tuner timed it
+    # (one launch over every block of every instance; 32 B per cell)
+    forms = [(128, 1), (256, 1), (512, 1), (512, 4)]
+    t = out["tuning"]
+    ms = t["ms_per_smooth_step"][forms.index((t["smoother_threads"], t["smoother_blocks"]))]
+    nbytes = 32.0 * sum(sizes)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out["roofline_batched_smoother"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                        "frac": gbs / PEAK_HBM_GBS, "ms_per_step": ms,
+                                        "bytes_per_step": nbytes,
+                                        "form": f"{t['smoother_threads']} threads, {t['smoother_blocks']} block(s)"}
     if sequential:
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -530,6 +530,17 @@ cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, int
  * tuned) again on the next call.  For reproducible timings and for tests
  * of each form.  Errors: CAMS_E_ARG (another pair). */
 cams_status cams_batch_set_smoother(cams_batch *b, int32_t threads, int32_t blocks);
+/* The tuning outcome is kept per process, keyed by precision, n_pre,
+ * n_post, whether an instance alternates block grids, and floor(log2) of
+ * the batch's total cells and of its instance count: a later batch with the
+ * same key takes the stored choice (and its timings, for cams_batch_tuning)
+ * instead of timing the candidates.  *from_cache: 1 when the batch's
+ * current choice came from there, 0 when it was measured (and stored), -1
+ * before the first call or with a smoother fixed by cams_batch_set_smoother.
+ * Errors: CAMS_E_ARG (null). */
+cams_status cams_batch_tuning_source(const cams_batch *b, int32_t *from_cache);
+/* Forget every stored tuning outcome (later batches measure again). */
+void cams_batch_clear_tuning_cache(void);
 const char *cams_batch_last_error(const cams_batch *b);
 void cams_batch_destroy(cams_batch *b);
 

@@ -140,6 +140,8 @@ _SIGS = [
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     ("cams_batch_set_smoother", _I, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    ("cams_batch_tuning_source", _I, [_VP, ctypes.POINTER(ctypes.c_int32)]),
+    ("cams_batch_clear_tuning_cache", None, []),
     ("cams_batch_last_error", ctypes.c_char_p, [_VP]),
     ("cams_batch_destroy", None, [_VP]),
 ]

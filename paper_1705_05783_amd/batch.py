@@ -72,8 +72,15 @@ class Batch:
         ms, sm = (ctypes.c_double * 4)(), (ctypes.c_double * 4)()
         _check(C.cams_batch_tuning(self.handle, ctypes.byref(k), ctypes.byref(nt), ctypes.byref(nb), ms, sm, 4),
                self.handle, "cams_batch_tuning")
+        src = ctypes.c_int32()
+        _check(C.cams_batch_tuning_source(self.handle, ctypes.byref(src)), self.handle, "cams_batch_tuning_source")
         return {"iters_per_graph": k.value, "smoother_threads": nt.value, "smoother_blocks": nb.value,
-                "ms_per_iter": list(ms)[:3], "ms_per_smooth_step": list(sm)}
+                "ms_per_iter": list(ms)[:3], "ms_per_smooth_step": list(sm), "from_cache": src.value}
+
+    @staticmethod
+    def clear_tuning_cache():
+        """Forget the tuning outcomes stored by earlier batches of this process."""
+        C.cams_batch_clear_tuning_cache()
 
     def close(self):
         if self.handle:

@@ -26,6 +26,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "cams_internal.h"
@@ -120,6 +121,7 @@ struct cams_batch {
     int smooth_nt = 512;             // threads per smoother block (tuned on the first call)
     int forced_nt = -1;              // smoother form set by the caller (-1: tuned)
     double smooth_ms[kNumSmooth] = {};
+    int from_cache = -1;             // last tuning: 1 from the process-wide cache, 0 measured, -1 none
     std::string err;
     float t_setup_ms = 0.f, t_iter_ms = 0.f;
     int iters_launched = 0;
@@ -222,6 +224,38 @@ void read_results(cams_batch *b)
 void reset_iteration(cams_batch *b)
 {
     launch_batch_reset(L(b, L_NUM));
+}
+
+// Tuning results shared by the batches of one process, keyed by what the
+// choice depends on: precision, smoothing counts, whether an instance
+// alternates block grids, and the powers of two of the batch's total cells
+// and instance count.  A batch whose key is cached takes the stored choice
+// (and timings) instead of timing the candidates again.
+struct TuneKey {
+    int precision, n_pre, n_post, alt, cells_log2, count_log2;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(precision, n_pre, n_post, alt, cells_log2, count_log2) <
+               std::tie(o.precision, o.n_pre, o.n_post, o.alt, o.cells_log2, o.count_log2);
+    }
+};
+struct TuneEntry {
+    int smooth_nt, chosen;
+    double tune_ms[kNumCand], smooth_ms[kNumSmooth];
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune_cache;
+
+TuneKey tune_key(const cams_batch *b)
+{
+    double cells = 0.0;
+    int alt = 0;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+        cells += b->cells[i];
+        alt |= b->ctx[i]->opt.smoother == CAMS_SMOOTH_BLOCK_ALT_ILU0;
+    }
+    return TuneKey{b->precision, b->n_pre, b->n_post, alt, (int)std::floor(std::log2(std::max(cells, 1.0))),
+                   (int)std::floor(std::log2((double)b->ctx.size()))};
 }
 
 // Choose the smoother's workgroup size: each candidate runs the same
@@ -506,12 +540,41 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
         bool all_listed = true;
         for (char k : b->listed) all_listed = all_listed && k;
         if (!all_listed) upload_lists(b, std::vector<char>(count, 1));
+        int cached_chosen = -1;
         if (!b->exec[0]) {
-            if (b->forced_nt >= 0) b->smooth_nt = b->forced_nt;
-            else tune_smoother(b);
+            b->from_cache = -1;
+            if (b->forced_nt >= 0) {
+                b->smooth_nt = b->forced_nt;
+            } else {
+                std::lock_guard<std::mutex> lock(g_tune_mu);
+                const auto it = g_tune_cache.find(tune_key(b));
+                if (it != g_tune_cache.end()) {
+                    const TuneEntry &e = it->second;
+                    b->smooth_nt = e.smooth_nt;
+                    cached_chosen = e.chosen;
+                    std::copy(e.tune_ms, e.tune_ms + kNumCand, b->tune_ms);
+                    std::copy(e.smooth_ms, e.smooth_ms + kNumSmooth, b->smooth_ms);
+                }
+            }
+            if (b->forced_nt < 0 && cached_chosen < 0) tune_smoother(b);
             for (int k = 0; k < kNumCand; ++k) b->exec[k] = capture(b, kGraphIters[k]);
         }
-        if (b->chosen < 0) tune(b);
+        if (b->chosen < 0) {
+            if (cached_chosen >= 0) {
+                b->chosen = cached_chosen;
+                b->from_cache = 1;
+            } else {
+                tune(b);
+                if (b->forced_nt < 0) {
+                    b->from_cache = 0;
+                    TuneEntry e{b->smooth_nt, b->chosen, {}, {}};
+                    std::copy(b->tune_ms, b->tune_ms + kNumCand, e.tune_ms);
+                    std::copy(b->smooth_ms, b->smooth_ms + kNumSmooth, e.smooth_ms);
+                    std::lock_guard<std::mutex> lock(g_tune_mu);
+                    g_tune_cache[tune_key(b)] = e;
+                }
+            }
+        }
         const int k = b->chosen;
         int launched = 0, done = 0;
         const int limit = b->maxit + 1;   // the device stops every instance by then
@@ -602,6 +665,19 @@ cams_status cams_batch_tuning(const cams_batch *b, int32_t *iters_per_graph, int
     for (int k = 0; k < std::min<int>(ncand, kNumSmooth); ++k)
         if (ms_per_smooth_step_candidates) ms_per_smooth_step_candidates[k] = b->smooth_ms[k];
     return CAMS_OK;
+}
+
+cams_status cams_batch_tuning_source(const cams_batch *b, int32_t *from_cache)
+{
+    if (!b || !from_cache) return CAMS_E_ARG;
+    *from_cache = b->from_cache;
+    return CAMS_OK;
+}
+
+void cams_batch_clear_tuning_cache(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache.clear();
 }
 
 cams_status cams_batch_set_smoother(cams_batch *b, int32_t threads, int32_t blocks)

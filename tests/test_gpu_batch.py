@@ -186,6 +186,40 @@ def test_batch_second_call_replays_the_tuned_graph(torch):
     b.close()
 
 
+def test_tuning_cache_reuses_the_choice(torch):
+    """The process-wide tuning cache.  After it is cleared, a batch times its
+    candidates (from_cache 0) and stores the outcome; a second batch with
+    the same key (new contexts; same precision, smoothing counts and size
+    buckets) takes the stored choice and timings without timing (from_cache
+    1) and computes the same pressures bit for bit; a batch of another size
+    bucket times its own; a fixed smoother form bypasses the cache (-1)."""
+    from paper_1705_05783_amd.batch import Batch
+    Batch.clear_tuning_cache()
+    pbs = _instances(MIXED_FP32, rtol=1e-8)
+    b1, s1, _, p1 = _run_batch(torch, pbs)
+    t1 = b1.tuning()
+    b1.close()
+    b2, s2, _, p2 = _run_batch(torch, pbs)
+    t2 = b2.tuning()
+    b2.close()
+    log("measured", t1, "cached", t2)
+    assert t1["from_cache"] == 0 and t2["from_cache"] == 1
+    assert {k: v for k, v in t2.items() if k != "from_cache"} == {k: v for k, v in t1.items() if k != "from_cache"}
+    assert s1 == s2 and all(s == 0 for s in s1)
+    for a, c in zip(p1, p2):
+        assert np.array_equal(a, c)
+    b3, s3, _, _ = _run_batch(torch, pbs[:2])
+    assert b3.tuning()["from_cache"] == 0
+    b3.close()
+    b4 = Batch.from_problems(pbs)
+    b4.set_smoother(256, 1)
+    pn = [torch.as_tensor(_start(pb), device="cuda") for pb in pbs]
+    p = [t.clone() for t in pn]
+    b4.newton_iteration(pn, p)
+    assert b4.tuning()["from_cache"] == -1
+    b4.close()
+
+
 def test_batch_of_one_and_iteration_limit(torch):
     """A batch of one instance; an instance that reaches lin_maxit reports
     CAMS_E_NOT_CONVERGED while the others finish."""
