@@ -79,6 +79,12 @@ int resident_workgroups(const void *kernel, int threads)
 
 }  // namespace cams
 
+// LDS classes of the batched local basis solves (bytes per workgroup):
+// small systems are launched apart from the 7^3 interiors so that many of
+// them share a compute unit.
+constexpr int kBasisClasses = 4;
+constexpr size_t kBasisClassBytes[kBasisClasses] = {16 << 10, 40 << 10, 80 << 10, 160 << 10};
+
 struct cams_batch {
     std::vector<cams_ctx *> ctx;
     hipStream_t user = nullptr;      // the contexts' stream: ordered before and after each call
@@ -121,6 +127,11 @@ struct cams_batch {
     int smooth_nt = 512;             // threads per smoother block (tuned on the first call)
     int forced_nt = -1;              // smoother form set by the caller (-1: tuned)
     double smooth_ms[kNumSmooth] = {};
+    // local basis solves of every instance, per stage (open axes 1..3) and
+    // LDS class: work items (instance, region) and the class's largest system
+    std::vector<WorkItem> blist[4][kBasisClasses];
+    int bcap[4][kBasisClasses] = {};
+    size_t off_blist[4][kBasisClasses] = {};
     int from_cache = -1;             // last tuning: 1 from the process-wide cache, 0 measured, -1 none
     std::string err;
     float t_setup_ms = 0.f, t_iter_ms = 0.f;
@@ -361,6 +372,23 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         for (int k = 0; k < (g.Nc + kBlock / 64 - 1) / (kBlock / 64); ++k) b->lists[L_ROWS].push_back({i, k});
     }
     for (int i = 0; i < count; ++i) b->cells.push_back((double)ctxs[i]->g.N);
+    // basis work lists: each instance's regions of a stage, by LDS class
+    for (int i = 0; i < count; ++i) {
+        const cams_ctx *c = ctxs[i];
+        for (int f = 1; f <= 3; ++f)
+            for (int q = c->regoff[f]; q < c->regoff[f] + c->nreg[f]; ++q) {
+                const Region &R = c->regions[q];
+                const int st[3] = {1, R.len[0], R.len[0] * R.len[1]};
+                int bw = 1;
+                for (int a = 0; a < 3; ++a)
+                    if (R.freemask & (1 << a)) bw = st[a];
+                const int need = R.len[0] * R.len[1] * R.len[2] * (bw + 1 + 8);
+                int k = 0;
+                while (k < kBasisClasses - 1 && (size_t)need * sizeof(double) > kBasisClassBytes[k]) ++k;
+                b->blist[f][k].push_back({i, q});
+                b->bcap[f][k] = std::max(b->bcap[f][k], need);
+            }
+    }
     for (int l = 0; l < L_NUM; ++l)
         if (b->lists[l].size() > 0x7fffffffu) {
             delete b;
@@ -373,6 +401,11 @@ cams_status cams_batch_create(cams_ctx *const *ctxs, int32_t count, void *hip_st
         b->off_list[l] = o;
         o = align_up(o + b->lists[l == L_NUM ? L_FLAT : l].size() * sizeof(WorkItem));
     }
+    for (int f = 1; f <= 3; ++f)
+        for (int k = 0; k < kBasisClasses; ++k) {
+            b->off_blist[f][k] = o;
+            o = align_up(o + b->blist[f][k].size() * sizeof(WorkItem));
+        }
     b->off_nwork = o;
     o = align_up(o + (L_NUM + 1) * sizeof(int32_t));
     b->off_res = o;
@@ -471,6 +504,12 @@ cams_status cams_batch_set_workspace(cams_batch *b, void *ws_dev, size_t bytes)
             CAMS_HIP(hipMemcpyAsync(b->d_gemms, b->lu.gemms.data(), b->lu.gemms.size() * sizeof(GemmDesc),
                                     hipMemcpyHostToDevice, b->stream));
         upload_lists(b, std::vector<char>(count, 1));
+        for (int f = 1; f <= 3; ++f)
+            for (int k = 0; k < kBasisClasses; ++k)
+                if (!b->blist[f][k].empty())
+                    CAMS_HIP(hipMemcpyAsync(w + b->off_blist[f][k], b->blist[f][k].data(),
+                                            b->blist[f][k].size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                            b->stream));
         // occupancy of every batched kernel, before any capture
         enqueue_batch_iteration(b, 0, true);
         launch_batch_reset(L(b, L_NUM, true));
@@ -504,33 +543,65 @@ cams_status cams_batch_newton_iteration(cams_batch *b, const double *const *pn_d
         CAMS_HIP(hipMemcpyAsync(b->pptr, host_pptr(b), count * sizeof(double *), hipMemcpyHostToDevice, b->stream));
         CAMS_HIP(hipEventRecord(b->ev[0], b->stream));
 
-        // setup of every instance, spread over the side streams
-        CAMS_HIP(hipEventRecord(b->fork, b->stream));
-        for (int s = 0; s < kSide; ++s) CAMS_HIP(hipStreamWaitEvent(b->side[s], b->fork, 0));
-        for (int i = 0; i < count; ++i) {
-            cams_ctx *c = b->ctx[i];
-            const hipStream_t own = c->stream;
-            c->stream = b->side[i % kSide];
-            try {
+        // setup of every instance, spread over the side streams.  When every
+        // instance needs its basis, the local solves of each stage run as
+        // batched launches over all instances' regions (by LDS class)
+        // between a first per-instance phase (vertices, assembly) and a
+        // second (rounding, coarse operator and its factorisation);
+        // otherwise each instance builds what it lacks in one phase.
+        bool all_basis = true;
+        for (const cams_ctx *c : b->ctx) all_basis = all_basis && !c->has_basis;
+        auto per_instance = [&](auto fn) {
+            CAMS_HIP(hipEventRecord(b->fork, b->stream));
+            for (int s = 0; s < kSide; ++s) CAMS_HIP(hipStreamWaitEvent(b->side[s], b->fork, 0));
+            for (int i = 0; i < count; ++i) {
+                cams_ctx *c = b->ctx[i];
+                const hipStream_t own = c->stream;
+                c->stream = b->side[i % kSide];
+                try {
+                    fn(c, i);
+                } catch (...) {
+                    c->stream = own;
+                    throw;
+                }
+                c->stream = own;
+            }
+            for (int s = 0; s < kSide; ++s) {
+                CAMS_HIP(hipEventRecord(b->join[s], b->side[s]));
+                CAMS_HIP(hipStreamWaitEvent(b->stream, b->join[s], 0));
+            }
+        };
+        auto coarse_setup = [&](cams_ctx *c) {
+            enqueue_coarse_operator(c);
+            if (c->opt.restriction == CAMS_R_FE)
+                launch_coarse_factor_prepare(c);   // factorised below, batched
+            else
+                launch_coarse_factor(c);
+            launch_iter_reset(c);
+        };
+        if (all_basis) {
+            per_instance([&](cams_ctx *c, int i) {
+                enqueue_clear_status(c);
+                launch_impose_wells(c, p_dev[i]);
+                launch_basis_vertices(c);
+                enqueue_assemble(c, p_dev[i], pn_dev[i]);
+            });
+            for (int f = 1; f <= 3; ++f)
+                for (int k = 0; k < kBasisClasses; ++k)
+                    launch_batch_basis_regions(b->inst, (const WorkItem *)(b->ws + b->off_blist[f][k]),
+                                               (int)b->blist[f][k].size(), f, b->bcap[f][k], b->stream);
+            per_instance([&](cams_ctx *c, int) {
+                if (c->opt.precision != CAMS_FP64) launch_round_basis(c);
+                coarse_setup(c);
+            });
+        } else {
+            per_instance([&](cams_ctx *c, int i) {
                 enqueue_clear_status(c);
                 launch_impose_wells(c, p_dev[i]);
                 if (!c->has_basis) enqueue_basis_local(c);
                 enqueue_assemble(c, p_dev[i], pn_dev[i]);
-                enqueue_coarse_operator(c);
-                if (c->opt.restriction == CAMS_R_FE)
-                    launch_coarse_factor_prepare(c);   // factorised below, batched
-                else
-                    launch_coarse_factor(c);
-                launch_iter_reset(c);
-            } catch (...) {
-                c->stream = own;
-                throw;
-            }
-            c->stream = own;
-        }
-        for (int s = 0; s < kSide; ++s) {
-            CAMS_HIP(hipEventRecord(b->join[s], b->side[s]));
-            CAMS_HIP(hipStreamWaitEvent(b->stream, b->join[s], 0));
+                coarse_setup(c);
+            });
         }
         launch_batch_gj(b->lu, b->d_steps, b->d_gemms, b->stream);
         CAMS_HIP(hipGetLastError());

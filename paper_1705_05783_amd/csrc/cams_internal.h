@@ -365,6 +365,8 @@ void launch_batch_sub_pre64(const BatchLaunch &L);
 void launch_basis(cams_ctx *c);
 void launch_basis_vertices(cams_ctx *c);
 void launch_basis_regions(cams_ctx *c, int nfree, const Region *regs, int count);
+void launch_batch_basis_regions(const InstDev *inst, const WorkItem *items, int count, int nfree, int cap,
+                                hipStream_t st);
 
 // ---- learned basis network (k_cnn.hip)
 size_t cnn_num_params();

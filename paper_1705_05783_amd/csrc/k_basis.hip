@@ -45,13 +45,11 @@ __device__ __forceinline__ double lane_bcast(double v, int lane)
 // (c+d, c), ld = bw + 1) followed by 8 right-hand sides per cell, in dynamic
 // LDS of `cap` doubles (sized by the host for the largest region of the stage).
 template <int NT>
-__global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__restrict__ T,
-                                                      const double *__restrict__ adiag,
-                                                      const Region *__restrict__ regs, double *__restrict__ P,
-                                                      int32_t *status, int cap)
+__device__ __forceinline__ void basis_region_body(const GridDev &g, const double *__restrict__ T,
+                                                  const double *__restrict__ adiag, const Region R,
+                                                  double *__restrict__ P, int32_t *status, int cap)
 {
     extern __shared__ double lds[];
-    const Region R = regs[blockIdx.x];
     const int e0 = R.len[0], e1 = R.len[1], e2 = R.len[2];
     const int m = e0 * e1 * e2;
     const int lstride[3] = {1, e0, e0 * e1};
@@ -166,18 +164,33 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
         __syncthreads();
     }
     // forward substitution L y = b, KB rows at a time: the first 8 lanes solve
-    // the diagonal block (one right-hand side each), then all threads update
-    // the <= bw rows below
+    // the diagonal block (one right-hand side each) with the block's factor
+    // entries and right-hand sides read into registers first, so the
+    // recurrence runs on registers rather than through a chain of LDS reads;
+    // then all threads update the <= bw rows below
     for (int c0 = 0; c0 < m; c0 += KB) {
         const int kc = min(KB, m - c0), nr = min(bw, m - c0 - kc);
         if (threadIdx.x < 8) {
             const int q = threadIdx.x;
-            for (int r = 0; r < kc; ++r) {
-                const int i = c0 + r;
-                double s = B[i * 8 + q];
-                for (int c = max(c0, i - bw); c < i; ++c) s -= L[c * ld + (i - c)] * B[c * 8 + q];
-                B[i * 8 + q] = s / L[i * ld];
+            double y[KB], Lb[KB][KB];
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                y[r] = r < kc ? B[(c0 + r) * 8 + q] : 0.0;
+#pragma unroll
+                for (int c = 0; c <= r; ++c)   // entry (c0 + r, c0 + c), zero outside the band
+                    Lb[r][c] = (r < kc && r - c <= bw) ? L[(c0 + c) * ld + (r - c)] : 0.0;
             }
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                if (r >= kc) break;
+                double s = y[r];
+#pragma unroll
+                for (int c = 0; c < r; ++c) s -= Lb[r][c] * y[c];
+                y[r] = s / Lb[r][r];
+            }
+#pragma unroll
+            for (int r = 0; r < KB; ++r)
+                if (r < kc) B[(c0 + r) * 8 + q] = y[r];
         }
         __syncthreads();
         for (int t = threadIdx.x; t < nr * 8; t += NT) {
@@ -194,12 +207,25 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
         const int kc = min(KB, m - c0);
         if (threadIdx.x < 8) {
             const int q = threadIdx.x;
-            for (int r = kc - 1; r >= 0; --r) {
-                const int c = c0 + r;
-                double s = B[c * 8 + q];
-                for (int i = c + 1; i < min(c0 + kc, c + bw + 1); ++i) s -= L[c * ld + (i - c)] * B[i * 8 + q];
-                B[c * 8 + q] = s / L[c * ld];
+            double x[KB], Lb[KB][KB];
+#pragma unroll
+            for (int r = 0; r < KB; ++r) {
+                x[r] = r < kc ? B[(c0 + r) * 8 + q] : 0.0;
+#pragma unroll
+                for (int i = r; i < KB; ++i)   // entry (c0 + i, c0 + r) of L, zero outside the band
+                    Lb[r][i] = (i < kc && i - r <= bw) ? L[(c0 + r) * ld + (i - r)] : 0.0;
             }
+#pragma unroll
+            for (int r = KB - 1; r >= 0; --r) {
+                if (r >= kc) continue;
+                double s = x[r];
+#pragma unroll
+                for (int i = r + 1; i < KB; ++i) s -= Lb[r][i] * x[i];
+                x[r] = s / Lb[r][r];
+            }
+#pragma unroll
+            for (int r = 0; r < KB; ++r)
+                if (r < kc) B[(c0 + r) * 8 + q] = x[r];
         }
         __syncthreads();
         const int lo = max(0, c0 - bw), na = c0 - lo;
@@ -217,6 +243,26 @@ __global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__
 #pragma unroll
         for (int s = 0; s < 8; ++s) P[(size_t)s * g.N + n] = B[c * 8 + s];
     }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_basis_region(GridDev g, const double *__restrict__ T,
+                                                      const double *__restrict__ adiag,
+                                                      const Region *__restrict__ regs, double *__restrict__ P,
+                                                      int32_t *status, int cap)
+{
+    basis_region_body<NT>(g, T, adiag, regs[blockIdx.x], P, status, cap);
+}
+
+// The same over the regions of many instances (B4: couplings T, no extra
+// diagonal): work item (instance, index into that instance's regions).
+template <int NT>
+__global__ __launch_bounds__(NT) void kb_basis_region(const InstDev *__restrict__ inst,
+                                                       const WorkItem *__restrict__ items, int cap)
+{
+    const WorkItem w = items[blockIdx.x];
+    const InstDev &d = inst[w.inst];
+    basis_region_body<NT>(d.g, d.a.T, nullptr, d.a.regions[w.blk], d.a.P, d.a.status, cap);
 }
 
 // Couplings and extra diagonal of the local problems of the basis types
@@ -356,6 +402,13 @@ void launch_basis_vertices(cams_ctx *c)
     k_basis_vertices<<<(g.N + kBlock - 1) / kBlock, kBlock, 0, c->stream>>>(g, c->a.P);
 }
 
+// Systems of at most kOneWaveLds doubles (every dual edge and face patch,
+// interiors up to ratio 5) are solved by one-wave workgroups: the panel
+// factorisation and the triangular solves use the first wave only, so the
+// other three waves of a 256-thread workgroup would mostly wait, and four
+// times as many small regions share a compute unit.
+constexpr int kOneWaveLds = 2048;   // 16 KB
+
 // Exact local solves of `count` regions with `nfree` open axes (a subset of
 // that stage's regions: the LDS is sized for the stage's largest system).
 void launch_basis_regions(cams_ctx *c, int nfree, const Region *regs, int count)
@@ -366,10 +419,21 @@ void launch_basis_regions(cams_ctx *c, int nfree, const Region *regs, int count)
     const size_t bytes = (size_t)cap * sizeof(double);
     const double *C, *A;
     basis_operator(c, C, A);
-    if (nfree == 1)
+    if (nfree == 1 || cap <= kOneWaveLds)
         k_basis_region<64><<<count, 64, bytes, c->stream>>>(g, C, A, regs, c->a.P, c->a.status, cap);
     else
         k_basis_region<kBlock><<<count, kBlock, bytes, c->stream>>>(g, C, A, regs, c->a.P, c->a.status, cap);
+}
+
+void launch_batch_basis_regions(const InstDev *inst, const WorkItem *items, int count, int nfree, int cap,
+                                 hipStream_t st)
+{
+    if (count <= 0) return;
+    const size_t bytes = (size_t)cap * sizeof(double);
+    if (nfree == 1 || cap <= kOneWaveLds)
+        kb_basis_region<64><<<count, 64, bytes, st>>>(inst, items, cap);
+    else
+        kb_basis_region<kBlock><<<count, kBlock, bytes, st>>>(inst, items, cap);
 }
 
 void launch_basis(cams_ctx *c)
