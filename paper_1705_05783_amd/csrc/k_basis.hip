@@ -42,8 +42,9 @@ __device__ __forceinline__ double lane_bcast(double v, int lane)
 }
 
 // The local system of one region: band of L by columns (L[c*ld + d] = entry
-// (c+d, c), ld = bw + 1) followed by 8 right-hand sides per cell, in dynamic
-// LDS of `cap` doubles (sized by the host for the largest region of the stage).
+// (c+d, c), ld = bw + 1; once factored, the diagonal entry holds its
+// reciprocal) followed by 8 right-hand sides per cell, in dynamic LDS of
+// `cap` doubles (sized by the host for the largest region of the stage).
 template <int NT>
 __device__ __forceinline__ void basis_region_body(const GridDev &g, const double *__restrict__ T,
                                                   const double *__restrict__ adiag, const Region R,
@@ -64,6 +65,17 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
     }
     double *L = lds;
     double *B = lds + m * ld;
+    // entry (c + d, c) of the band, or 0 when `ok` is false: read from a
+    // clamped in-band address and zeroed afterwards, so that the reads of an
+    // unrolled loop need no branches around them
+    auto band = [&](int c, int d, bool ok) -> double {
+        const double v = L[min(c, m - 1) * ld + min(max(d, 0), bw)];
+        return ok ? v : 0.0;
+    };
+    auto rhs = [&](int i, int q, bool ok) -> double {
+        const double v = B[min(max(i, 0), m - 1) * 8 + q];
+        return ok ? v : 0.0;
+    };
     const int rlo[3] = {g.lo[0][R.s[0]], g.lo[1][R.s[1]], g.lo[2][R.s[2]]};
     const double *Tax[3] = {T, T + g.N, T + 2 * g.N};
     const int ncoord[3] = {g.nx, g.ny, g.nz};
@@ -72,39 +84,57 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
     for (int t = threadIdx.x; t < m * 8; t += NT) B[t] = 0.0;
     __syncthreads();
 
-    // assemble the local matrix and the Dirichlet data of the boundary
+    // assemble the local matrix and the Dirichlet data of the boundary.  All
+    // loads of a cell go out before the first is used: the couplings of its
+    // six faces, the basis values of the neighbours across the faces that
+    // leave the region, and their lower vertex indices, from in-range
+    // addresses (the cell itself stands in where a face has none); the sums
+    // then run in the same order as face by face.
     for (int c = threadIdx.x; c < m; c += NT) {
         const int lc[3] = {c % e0, (c / e0) % e1, c / (e0 * e1)};
         const int x[3] = {R.s[0] + lc[0], R.s[1] + lc[1], R.s[2] + lc[2]};
         const int n = x[0] + g.nx * (x[1] + g.ny * x[2]);
+        double tf[6], wv[6][8];
+        int lo_nb[6];
+        bool face[6], ext[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {   // face f: axis f / 2, towards -1 (f even) or +1 (f odd)
+            const int a = f >> 1, dir = (f & 1) ? 1 : -1;
+            const int xa = x[a] + dir;
+            face[f] = (R.freemask & (1 << a)) && xa >= 0 && xa < ncoord[a];
+            ext[f] = face[f] && !(xa >= R.s[a] && xa < R.s[a] + R.len[a]);
+            tf[f] = Tax[a][face[f] && dir < 0 ? n - gstride[a] : n];
+            const int nb = ext[f] ? n + dir * gstride[a] : n;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) wv[f][s] = P[(size_t)s * g.N + nb];
+            lo_nb[f] = g.lo[a][ext[f] ? xa : x[a]];
+        }
         double dsum = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            if (!(R.freemask & (1 << a))) continue;
-            for (int dir = -1; dir <= 1; dir += 2) {
-                const int xa = x[a] + dir;
-                if (xa < 0 || xa >= ncoord[a]) continue;
-                const double t = dir > 0 ? Tax[a][n] : Tax[a][n - gstride[a]];
-                dsum += t;
-                if (xa >= R.s[a] && xa < R.s[a] + R.len[a]) {
-                    if (dir > 0) L[c * ld + lstride[a]] = -t;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (!face[f]) continue;
+            const int a = f >> 1;
+            const double t = tf[f];
+            dsum += t;
+            if (!ext[f]) {
+                if (f & 1) L[c * ld + lstride[a]] = -t;
+                continue;
+            }
+            // neighbour on a higher-level dual entity: known values
+            int nlo[3] = {rlo[0], rlo[1], rlo[2]};
+            nlo[a] = lo_nb[f];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const double w = wv[f][s];
+                if (w == 0.0) continue;
+                const int bx = nlo[0] + (s & 1) - rlo[0];
+                const int by = nlo[1] + ((s >> 1) & 1) - rlo[1];
+                const int bz = nlo[2] + ((s >> 2) & 1) - rlo[2];
+                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) {
+                    atomicOr(status, F_BAD_INPUT);
                     continue;
                 }
-                // neighbour on a higher-level dual entity: known values
-                const int nb = n + dir * gstride[a];
-                const int nlo[3] = {a == 0 ? g.lo[0][xa] : rlo[0], a == 1 ? g.lo[1][xa] : rlo[1],
-                                    a == 2 ? g.lo[2][xa] : rlo[2]};
-                for (int s = 0; s < 8; ++s) {
-                    const double w = P[(size_t)s * g.N + nb];
-                    if (w == 0.0) continue;
-                    const int bx = nlo[0] + (s & 1) - rlo[0];
-                    const int by = nlo[1] + ((s >> 1) & 1) - rlo[1];
-                    const int bz = nlo[2] + ((s >> 2) & 1) - rlo[2];
-                    if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) {
-                        atomicOr(status, F_BAD_INPUT);
-                        continue;
-                    }
-                    B[c * 8 + bx + 2 * by + 4 * bz] += t * w;
-                }
+                B[c * 8 + bx + 2 * by + 4 * bz] += t * w;
             }
         }
         L[c * ld] = adiag ? dsum + adiag[n] : dsum;   // B1 / B3: accumulation term on the diagonal
@@ -121,11 +151,13 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
 #pragma unroll
             for (int q = 0; q < KB; ++q) {
                 const int d = i - (c0 + q);
-                v[q] = (q < kc && lane < rows && d >= 0 && d <= bw) ? L[(c0 + q) * ld + d] : 0.0;
+                v[q] = band(c0 + q, d, q < kc && lane < rows && d >= 0 && d <= bw);
             }
             bool bad = false;
+            double rsv[KB];   // 1 / L(c0 + q, c0 + q), the diagonal as stored
 #pragma unroll
             for (int q0 = 0; q0 < KB; ++q0) {
+                rsv[q0] = 1.0;
                 if (q0 >= kc) break;
                 double piv = lane_bcast(v[q0], q0);
                 if (!(piv > 0.0)) {
@@ -133,7 +165,9 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
                     piv = 1.0;
                 }
                 const double sq = sqrt(piv);
-                v[q0] = lane == q0 ? sq : (lane > q0 ? v[q0] / sq : v[q0]);
+                const double rs = 1.0 / sq;   // one division per column; the multipliers scale by it
+                rsv[q0] = rs;
+                v[q0] = lane == q0 ? sq : (lane > q0 ? v[q0] * rs : v[q0]);
 #pragma unroll
                 for (int q2 = q0 + 1; q2 < KB; ++q2) {
                     if (q2 >= kc) break;
@@ -144,22 +178,54 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
 #pragma unroll
             for (int q = 0; q < KB; ++q) {
                 const int d = i - (c0 + q);
-                if (q < kc && lane < rows && d >= 0 && d <= bw) L[(c0 + q) * ld + d] = v[q];
+                if (q < kc && lane < rows && d >= 0 && d <= bw) L[(c0 + q) * ld + d] = d == 0 ? rsv[q] : v[q];
             }
             if (bad && lane == 0) atomicOr(status, F_BAD_PIVOT);
         }
         __syncthreads();
-        // trailing band: entry (i, j), c0 + kc <= j <= i < c0 + kc + nr, minus the panel's products
-        for (int t = threadIdx.x; t < nr * nr; t += NT) {
-            const int ii = t / nr, jj = t % nr;
-            if (jj > ii || ii - jj > bw) continue;
-            const int i = c0 + kc + ii, j = c0 + kc + jj;
-            double acc = 0.0;
-            for (int q = 0; q < kc; ++q) {
-                const int c = c0 + q;
-                if (i - c <= bw) acc += L[c * ld + (i - c)] * L[c * ld + (j - c)];
+        // trailing band: entry (i, j), c0 + kc <= j <= i < c0 + kc + nr, minus the
+        // panel's products.  Thread: column jj = t % 64 of the trailing block
+        // (nr <= bw < 64) with its KB panel values in registers, rows
+        // ii = jj + t / 64, + NT / 64, ... (each entry written by one thread);
+        // a row's KB panel values are read together, zero outside the band,
+        // and summed in column order.
+        {
+            constexpr int NG = NT / 64;
+            const int jj = threadIdx.x & 63;
+            if (jj < nr) {
+                const int j = c0 + kc + jj;
+                double pj[KB];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) {
+                    const int dj = j - (c0 + q);
+                    pj[q] = band(c0 + q, dj, q < kc && dj <= bw);
+                }
+                const int iimax = min(nr - 1, jj + bw);
+                // RC rows at a time: their reads go out before any of their
+                // writes (which the compiler cannot tell apart from the reads)
+                constexpr int RC = 4;
+                for (int ii0 = jj + (int)(threadIdx.x >> 6); ii0 <= iimax; ii0 += RC * NG) {
+                    double acc[RC];
+#pragma unroll
+                    for (int u = 0; u < RC; ++u) {
+                        const int i = c0 + kc + ii0 + u * NG;
+                        const bool row = ii0 + u * NG <= iimax;
+                        double a = 0.0;
+#pragma unroll
+                        for (int q = 0; q < KB; ++q) {
+                            const int di = i - (c0 + q);
+                            const bool ok = row && q < kc && di <= bw;
+                            a += band(c0 + q, di, ok) * pj[q];
+                        }
+                        acc[u] = a;
+                    }
+#pragma unroll
+                    for (int u = 0; u < RC; ++u) {
+                        const int i = c0 + kc + ii0 + u * NG;
+                        if (ii0 + u * NG <= iimax) L[j * ld + (i - j)] -= acc[u];
+                    }
+                }
             }
-            L[j * ld + (i - j)] -= acc;
         }
         __syncthreads();
     }
@@ -175,10 +241,10 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
             double y[KB], Lb[KB][KB];
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
-                y[r] = r < kc ? B[(c0 + r) * 8 + q] : 0.0;
+                y[r] = rhs(c0 + r, q, r < kc);
 #pragma unroll
                 for (int c = 0; c <= r; ++c)   // entry (c0 + r, c0 + c), zero outside the band
-                    Lb[r][c] = (r < kc && r - c <= bw) ? L[(c0 + c) * ld + (r - c)] : 0.0;
+                    Lb[r][c] = band(c0 + c, r - c, r < kc && r - c <= bw);
             }
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
@@ -186,18 +252,33 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
                 double s = y[r];
 #pragma unroll
                 for (int c = 0; c < r; ++c) s -= Lb[r][c] * y[c];
-                y[r] = s / Lb[r][r];
+                y[r] = s * Lb[r][r];   // the diagonal is stored inverted
             }
 #pragma unroll
             for (int r = 0; r < KB; ++r)
                 if (r < kc) B[(c0 + r) * 8 + q] = y[r];
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < nr * 8; t += NT) {
-            const int i = c0 + kc + t / 8, q = t % 8;
-            double acc = 0.0;
-            for (int c = max(c0, i - bw); c < c0 + kc; ++c) acc += L[c * ld + (i - c)] * B[c * 8 + q];
-            B[i * 8 + q] -= acc;
+        for (int t0 = threadIdx.x; t0 < nr * 8; t0 += 2 * NT) {   // two entries' reads before their writes
+            double acc[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = t0 + h * NT;
+                const int i = c0 + kc + t / 8, q = t % 8;
+                double a = 0.0;
+#pragma unroll
+                for (int u = 0; u < KB; ++u) {   // columns c0 + u of the block inside the band, in order
+                    const int c = c0 + u;
+                    const bool ok = t < nr * 8 && u < kc && i - c <= bw;
+                    a += band(c, i - c, ok) * rhs(c, q, ok);
+                }
+                acc[h] = a;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = t0 + h * NT;
+                if (t < nr * 8) B[(c0 + kc + t / 8) * 8 + t % 8] -= acc[h];
+            }
         }
         __syncthreads();
     }
@@ -210,10 +291,10 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
             double x[KB], Lb[KB][KB];
 #pragma unroll
             for (int r = 0; r < KB; ++r) {
-                x[r] = r < kc ? B[(c0 + r) * 8 + q] : 0.0;
+                x[r] = rhs(c0 + r, q, r < kc);
 #pragma unroll
                 for (int i = r; i < KB; ++i)   // entry (c0 + i, c0 + r) of L, zero outside the band
-                    Lb[r][i] = (i < kc && i - r <= bw) ? L[(c0 + r) * ld + (i - r)] : 0.0;
+                    Lb[r][i] = band(c0 + r, i - r, i < kc && i - r <= bw);
             }
 #pragma unroll
             for (int r = KB - 1; r >= 0; --r) {
@@ -221,7 +302,7 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
                 double s = x[r];
 #pragma unroll
                 for (int i = r + 1; i < KB; ++i) s -= Lb[r][i] * x[i];
-                x[r] = s / Lb[r][r];
+                x[r] = s * Lb[r][r];
             }
 #pragma unroll
             for (int r = 0; r < KB; ++r)
@@ -229,11 +310,26 @@ __device__ __forceinline__ void basis_region_body(const GridDev &g, const double
         }
         __syncthreads();
         const int lo = max(0, c0 - bw), na = c0 - lo;
-        for (int t = threadIdx.x; t < na * 8; t += NT) {
-            const int c = lo + t / 8, q = t % 8;
-            double acc = 0.0;
-            for (int i = c0; i < min(c0 + kc, c + bw + 1); ++i) acc += L[c * ld + (i - c)] * B[i * 8 + q];
-            B[c * 8 + q] -= acc;
+        for (int t0 = threadIdx.x; t0 < na * 8; t0 += 2 * NT) {
+            double acc[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = t0 + h * NT;
+                const int c = lo + t / 8, q = t % 8;
+                double a = 0.0;
+#pragma unroll
+                for (int u = 0; u < KB; ++u) {   // rows c0 + u of the block inside the band, in order
+                    const int i = c0 + u;
+                    const bool ok = t < na * 8 && u < kc && i - c <= bw;
+                    a += band(c, i - c, ok) * rhs(i, q, ok);
+                }
+                acc[h] = a;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = t0 + h * NT;
+                if (t < na * 8) B[(lo + t / 8) * 8 + t % 8] -= acc[h];
+            }
         }
         __syncthreads();
     }
