@@ -1153,7 +1153,9 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
 }
 
 // y = M x for a symmetric M (the dense MSFE inverse) reading only its lower
-// triangle: one workgroup per 64 x 64 tile (I, J), J <= I, forms x_J and x_I
+// triangle: one workgroup per 64 x 64 tile (I, J), J <= I (a lane reads a
+// 4 x 4 sub-block; row and column sums by lane exchanges, so the workgroup
+// needs 3 KB of LDS), forms x_J and x_I
 // = (R r) from the restriction's slot partials, reads the tile once and
 // writes (M_IJ x_J) to part[I][J] and, below the diagonal, (M_IJ^T x_I) to
 // part[J][I] (64 values each); k_gemv_sym_reduce sums part[I][0..T) in a
@@ -1167,13 +1169,12 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sym(const double *__restrict__ 
                                                       int nparts, int32_t *ictl, double *scal, double rtol2,
                                                       int maxit)
 {
-    static_assert(kBlock == 256 && kBlock == kStopThreads, "four threads per tile row; one workgroup shape");
-    __shared__ double Ts[64][65];
+    static_assert(kBlock == 256 && kBlock == kStopThreads, "four waves per tile; one workgroup shape");
     __shared__ double xs[2][64];
     __shared__ double red[4][64];
     if (done && *done) return;
     if (partial && blockIdx.x == gridDim.x - 1) {
-        stop_test(partial, nparts, ictl, scal, rtol2, maxit, &Ts[0][0]);
+        stop_test(partial, nparts, ictl, scal, rtol2, maxit, &red[0][0]);
         return;
     }
     const int t = blockIdx.x;   // t = I (I + 1) / 2 + J
@@ -1182,52 +1183,77 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sym(const double *__restrict__ 
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     const int J = t - I * (I + 1) / 2, T = (n + 63) / 64;
     const int i0 = 64 * I, j0 = 64 * J;
-    // the tile's loads first: thread tid takes row r, 16 columns from cq
-    const int tid = threadIdx.x, r = tid >> 2, cq = (tid & 3) * 16;
-    const bool rin = i0 + r < n;
-    double a[16];
+    // wave w takes tile rows 16 w .. 16 w + 15; lane: 4 x 4 sub-block at rows
+    // 16 w + 4 rq + k (k < 4), columns 4 cq + c (c < 4), rq = lane / 16,
+    // cq = lane % 16, so each row of the wave is read by 16 lanes, 512
+    // contiguous bytes.  The tile's loads first.
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, rq = lane >> 4, cq = lane & 15;
+    const int rbase = 16 * w + 4 * rq, cbase = 4 * cq;
+    double a[4][4];
     if (i0 + 64 <= n && j0 + 64 <= n && (n & 1) == 0) {   // whole tile, 16-byte aligned rows
         typedef double d2 __attribute__((ext_vector_type(2)));
-        const d2 *row = (const d2 *)(M + (size_t)(i0 + r) * n + j0 + cq);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const d2 v = row[u];
-            a[2 * u] = v.x;
-            a[2 * u + 1] = v.y;
+        for (int k = 0; k < 4; ++k) {
+            const d2 *row = (const d2 *)(M + (size_t)(i0 + rbase + k) * n + j0 + cbase);
+            const d2 v0 = row[0], v1 = row[1];
+            a[k][0] = v0.x;
+            a[k][1] = v0.y;
+            a[k][2] = v1.x;
+            a[k][3] = v1.y;
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int c = j0 + cq + u;
-            a[u] = rin && c < n ? M[(size_t)(i0 + r) * n + c] : 0.0;
-        }
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int r = i0 + rbase + k, cc = j0 + cbase + c;
+                a[k][c] = r < n && cc < n ? M[(size_t)r * n + cc] : 0.0;
+            }
     }
     if (tid < 128) {
         const int h = tid >> 6, k = (h ? i0 : j0) + (tid & 63);
         xs[h][tid & 63] = k < n ? node_sum(g, slots, fe, k) : 0.0;
     }
     __syncthreads();
-    double ur = 0.0;
+    // row products: the lane's 4 rows over its 4 columns, then summed over the
+    // 16 lanes of the row quad (xor over the lane's low four bits)
+    double ur[4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) ur += a[u] * xs[0][cq + u];
-    ur += __shfl_xor(ur, 1);
-    ur += __shfl_xor(ur, 2);
-    if ((tid & 3) == 0 && rin) part[((size_t)I * T + J) * 64 + r] = ur;
+    for (int k = 0; k < 4; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s += a[k][c] * xs[0][cbase + c];
+        ur[k] = s;
+    }
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ur[k] += __shfl_xor(ur[k], m);
+    if (cq == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + rbase + k < n) part[((size_t)I * T + J) * 64 + rbase + k] = ur[k];
     if (I == J) {
         if (tid < 64 && i0 + tid < n) rc[i0 + tid] = xs[1][tid];
         return;   // uniform over the workgroup
     }
-    const double xr = xs[1][r];
+    // transposed product: the lane's 4 columns over its 4 rows, summed over
+    // the wave's four row quads (xor 16, 32), then over the four waves in LDS
+    double uc[4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) Ts[r][cq + u] = a[u] * xr;
-    __syncthreads();
-    {
-        const int c = tid & 63, q = tid >> 6;
+    for (int c = 0; c < 4; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) s += Ts[16 * q + k][c];
-        red[q][c] = s;
+        for (int k = 0; k < 4; ++k) s += a[k][c] * xs[1][rbase + k];
+        uc[c] = s;
     }
+#pragma unroll
+    for (int m = 16; m < 64; m <<= 1)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) uc[c] += __shfl_xor(uc[c], m);
+    if (rq == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[w][cbase + c] = uc[c];
     __syncthreads();
     if (tid < 64 && j0 + tid < n)
         part[((size_t)J * T + I) * 64 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
