@@ -470,7 +470,13 @@ def main():
         print(json.dumps({args.only: fn[args.only](steps, warmup, torch)}), flush=True)
         return
 
+    t_start = time.perf_counter()
+
+    def progress(leg):   # one line on stderr per finished leg; stdout keeps the single JSON line
+        print(f"bench: {leg} done at {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
+
     head = headline(steps, warmup, torch)
+    progress("headline (128^3 plain, mixed, learned+mixed)")
     lm = head["learned_mixed"]
     from workloads.configs import config5_eval
     pb = config5_eval()
@@ -505,13 +511,13 @@ def main():
               "speedup_learned_mixed_vs_plain_iterations_only"):
         out[k] = head[k]
     if args.only == "all":
-        out["adaptive_newton"] = adaptive_run(steps, warmup, torch)
-        out["adaptive_coarse"] = coarse_reuse_run(steps, warmup, torch)
-        out["small"] = small_run(steps, warmup, torch)
-        out["large"] = large_run(steps, warmup, torch)
-        out["batch"] = batch_run(steps, warmup, torch)
+        for key, fn in (("adaptive_newton", adaptive_run), ("adaptive_coarse", coarse_reuse_run),
+                        ("small", small_run), ("large", large_run), ("batch", batch_run)):
+            out[key] = fn(steps, warmup, torch)
+            progress(key)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(head["plain_fp64"])
+        progress("cpu_baseline")
     print(json.dumps(out), flush=True)
 
 
