@@ -351,6 +351,9 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
             }
             t.tab_gx[v] = t.tab.size();
             c->g.ngx[v] = (int)starts.size() - 1;
+            bool even = n[0] % 2 == 0;
+            for (int b = 0; b <= nbx; ++b) even = even && xs(b) % 2 == 0;
+            t.row_pairs[v] = even;
             for (int32_t x : starts) t.tab.push_back(x);
         }
     }

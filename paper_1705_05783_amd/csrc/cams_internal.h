@@ -230,6 +230,9 @@ struct cams_ctx {
     std::vector<cams::Region> regions;
     size_t tab_off[3][4];
     size_t tab_gx[2];
+    // the pair form of the residual-restriction applies (nx and every box
+    // edge along x even), per restriction type as tab_gx
+    bool row_pairs[2];
     // timing of one kernel class for measurement (cams_profile)
     int prof_kernel;
     std::vector<hipEvent_t> prof_ev;        // pool: pairs (start, stop)

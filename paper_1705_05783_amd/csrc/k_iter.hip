@@ -372,6 +372,156 @@ __global__ __launch_bounds__(kRowThreads) void k_residual_restrict_row(
     }
 }
 
+// Pair form of the row kernel, for grids whose x-extent and box edges along x
+// are all even: thread t takes the two cells 2 (t % 16) and 2 (t % 16) + 1
+// of a 32-cell row segment, rows t / 16 + 16 i.  Each stencil point of both
+// cells is one 16-byte load (two FP64 values; 8 bytes for FP32, 4 for
+// BF16, 2 for the mask) instead of two, and only the x-neighbours outside
+// the pair take a load of their own, so a cell costs about half the vector
+// memory instructions of the row kernel, whose 64-lane loads keep the
+// texture address units busy for most of its time.  Both cells lie in one
+// box, so a thread keeps one set of box sums.  The residual of each cell is
+// formed in the same order as residual_cell, so r is the same bit for bit;
+// the box sums add the two cells of a thread first.
+constexpr int kPairThreads = 256;
+constexpr int kRowPairs = kRowCells / 2;
+
+template <class T>
+struct Two {
+    T a, b;
+};
+template <class T>
+__device__ __forceinline__ Two<T> load2(const T *__restrict__ p, int n)   // n even
+{
+    if constexpr (sizeof(T) == 8) {
+        const double2 v = *reinterpret_cast<const double2 *>(p + n);
+        return {v.x, v.y};
+    } else if constexpr (sizeof(T) == 4) {
+        const float2 v = *reinterpret_cast<const float2 *>(p + n);
+        return {v.x, v.y};
+    } else if constexpr (sizeof(T) == 2) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p + n);
+        return {(T)(v & 0xffffu), (T)(v >> 16)};
+    } else {
+        const uint16_t v = *reinterpret_cast<const uint16_t *>(p + n);
+        return {(T)(v & 0xffu), (T)(v >> 8)};
+    }
+}
+
+// Pending value at the even cell m and at m + 1, each summed as Pending does.
+template <class TA, int NV>
+__device__ __forceinline__ Two<double> pending2(const Pending<TA, NV> &v, int m)
+{
+    const Two<double> b = load2(v.v0, m);
+    Two<TA> a[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) a[q] = load2(v.v[q], m);
+    double s0 = b.a, s1 = b.b;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        s0 = v.fold ? s0 + (double)a[q].a : s0;
+        s1 = v.fold ? s1 + (double)a[q].b : s1;
+    }
+    return {s0, s1};
+}
+
+template <class TA, int NV, class TP>
+__global__ __launch_bounds__(kPairThreads) void k_residual_restrict_pair(
+    GridDev g, const double *__restrict__ W, const double *__restrict__ diag, const double *__restrict__ r0,
+    Pending<TA, NV> v, double *__restrict__ dp_out, double *__restrict__ r, float *__restrict__ rf,
+    double *__restrict__ partial, const uint8_t *__restrict__ dm, const TP *__restrict__ P, int fe,
+    double *__restrict__ slots, const int32_t *ictl)
+{
+    constexpr int NT = kPairThreads, RW = NT / kRowPairs;   // rows per pass (16)
+    __shared__ double red[9][NT];
+    if (ictl[C_DONE]) return;
+    v.fold = ictl[C_IT] > 0;
+    const int vi = fe ? 1 : 0, ngx = g.ngx[vi];
+    const int wg = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int gi = wg % ngx, kb = (wg / ngx) % g.nb[1], kc = wg / (ngx * g.nb[1]);
+    const int ka0 = g.gx[vi][gi], nbox = g.gx[vi][gi + 1] - ka0;
+    auto xs = [&](int b) { return fe ? g.ob[0][b] : min(b * g.r[0], g.nx); };
+    const int x0 = xs(ka0), ex = xs(ka0 + nbox) - x0;
+    const int y0 = fe ? g.ob[1][kb] : kb * g.r[1], z0 = fe ? g.ob[2][kc] : kc * g.r[2];
+    const int ey = (fe ? g.ob[1][kb + 1] : min(y0 + g.r[1], g.ny)) - y0;
+    const int ez = (fe ? g.ob[2][kc + 1] : min(z0 + g.r[2], g.nz)) - z0;
+    const int tid = threadIdx.x, px = tid % kRowPairs, row0 = tid / kRowPairs;
+    const bool colx = 2 * px < ex;
+    const double *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double e2 = 0.0;
+    const int rows = ey * ez;
+    for (int R = row0; colx && R < rows; R += RW) {
+        const int x = x0 + 2 * px, y = y0 + R % ey, z = z0 + R / ey;
+        const int n = x + g.nx * (y + g.ny * z);   // even
+        Two<TP> pv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[q] = load2(P + (size_t)q * g.N, n);
+        const Two<uint8_t> mk = load2(dm, n);
+        // the cells x and x + 1: x + 1 < nx always, x - 1 and x + 2 may be outside
+        const bool xm = x > 0, xp = x + 2 < g.nx, ym = y > 0, yp = y + 1 < g.ny, zm = z > 0, zp = z + 1 < g.nz;
+        const int nxm = xm ? n - 1 : n, nxp = xp ? n + 2 : n;
+        const int nym = ym ? n - g.nx : n, nyp = yp ? n + g.nx : n;
+        const int nzm = zm ? n - g.sxy : n, nzp = zp ? n + g.sxy : n;
+        const Two<double> wx = load2(Wx, n), wy = load2(Wy, n), wz = load2(Wz, n);
+        const Two<double> wym = load2(Wy, nym), wzm = load2(Wz, nzm);
+        const double wxm = Wx[nxm];
+        const Two<double> dg = load2(diag, n), rz = load2(r0, n);
+        const Two<double> vc = pending2(v, n), vym = pending2(v, nym), vyp = pending2(v, nyp);
+        const Two<double> vzm = pending2(v, nzm), vzp = pending2(v, nzp);
+        const double vxm = v(nxm), vxp = v(nxp);
+        // cell x: its +x neighbour is x + 1; cell x + 1: its -x neighbour is x
+        double s0 = dg.a * vc.a;
+        s0 -= (xm ? wxm : 0.0) * vxm;
+        s0 -= wx.a * vc.b;
+        s0 -= (ym ? wym.a : 0.0) * vym.a;
+        s0 -= (yp ? wy.a : 0.0) * vyp.a;
+        s0 -= (zm ? wzm.a : 0.0) * vzm.a;
+        s0 -= (zp ? wz.a : 0.0) * vzp.a;
+        double s1 = dg.b * vc.b;
+        s1 -= wx.a * vc.a;
+        s1 -= (xp ? wx.b : 0.0) * vxp;
+        s1 -= (ym ? wym.b : 0.0) * vym.b;
+        s1 -= (yp ? wy.b : 0.0) * vyp.b;
+        s1 -= (zm ? wzm.b : 0.0) * vzm.b;
+        s1 -= (zp ? wz.b : 0.0) * vzp.b;
+        const double ra = rz.a - s0, rb = rz.b - s1;
+        if (r) *reinterpret_cast<double2 *>(r + n) = double2{ra, rb};
+        if (rf) *reinterpret_cast<float2 *>(rf + n) = float2{(float)ra, (float)rb};
+        *reinterpret_cast<double2 *>(dp_out + n) = double2{vc.a, vc.b};
+        e2 += ra * ra;
+        e2 += rb * rb;
+        if (fe) {
+            const double wa = mk.a ? 0.0 : ra, wb = mk.b ? 0.0 : rb;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                acc[q] += basis_value(&pv[q].a, 0) * wa;
+                acc[q] += basis_value(&pv[q].b, 0) * wb;
+            }
+        } else {
+            acc[0] += ra;
+            acc[0] += rb;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) red[q][tid] = acc[q];
+    red[8][tid] = e2;
+    __syncthreads();
+    const int lane = tid & 63, w = tid >> 6;
+    for (int pr = w; pr < 9 * nbox; pr += NT / 64) {
+        const int b = pr / 9, q = pr % 9;
+        const int c0 = (xs(ka0 + b) - x0) / 2, wdt = (xs(ka0 + b + 1) - x0) / 2 - c0;
+        double sum = 0.0;
+        for (int u = lane; u < wdt * RW; u += 64) sum += red[q][(u / wdt) * kRowPairs + c0 + u % wdt];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+            const int k = (ka0 + b) + g.nb[0] * (kb + g.nb[1] * kc);
+            if (q < 8) slots[(size_t)k * 8 + q] = sum;
+            else partial[k] = sum;
+        }
+    }
+}
+
 // ---- batched forms: one launch covers every instance of a batch; the work
 // item of a workgroup names the instance and the block within it, and
 // workgroups of instances that have converged return at once.
@@ -534,6 +684,19 @@ void residual_restrict(cams_ctx *c, const Pending<TA, NV> &v, double *dp_out, fl
     // 256x256x128: 358 -> 268 us), else one workgroup per box (64x64x32:
     // 96 groups, 18.8 against 9.5 us)
     const unsigned wgs = (unsigned)ngx * g.nb[1] * g.nb[2];
+    if (c->row_pairs[fe] &&
+        (int)wgs >= resident_workgroups((const void *)k_residual_restrict_pair<TA, NV, float>, kPairThreads)) {
+        if (c->opt.precision == CAMS_MIXED_BF16)
+            k_residual_restrict_pair<TA, NV, uint16_t><<<wgs, kPairThreads, 0, c->stream>>>(
+                g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.Pbf, fe, a.slots, a.ictl);
+        else if (c->opt.precision == CAMS_MIXED_FP32)
+            k_residual_restrict_pair<TA, NV, float><<<wgs, kPairThreads, 0, c->stream>>>(
+                g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.P32, fe, a.slots, a.ictl);
+        else
+            k_residual_restrict_pair<TA, NV, double><<<wgs, kPairThreads, 0, c->stream>>>(
+                g, a.W, a.diag, a.r0, v, dp_out, rout, rf, a.partial, a.dmask, a.P, fe, a.slots, a.ictl);
+        return;
+    }
     if ((int)wgs >= resident_workgroups((const void *)k_residual_restrict_row<TA, NV, float>, kRowThreads)) {
         if (c->opt.precision == CAMS_MIXED_BF16)
             k_residual_restrict_row<TA, NV, uint16_t><<<wgs, kRowThreads, 0, c->stream>>>(

@@ -499,6 +499,43 @@ def test_mixed_solve_on_grids_of_the_lds_smoother(_gpu, shape, r, smoother):
     assert abs(its[1] - its[0]) <= 3, its
 
 
+@pytest.mark.parametrize("restriction,precision", [(FE, 0), (FE, 1), (FE, 2), (FV, 0)])
+def test_residual_pair_form_linear_solve(_gpu, restriction, precision):
+    """A grid whose x-extent and box edges along x are all even, with more
+    groups of boxes (2 x 32 x 32 = 2048 workgroups) than are resident at
+    once, takes the pair form of the residual-restriction (two cells per
+    thread, 16-byte loads): the FP64 solve matches the oracle's C-AMS solve
+    as on the smaller grids, and the mixed FP32 / BF16 solves meet the FP64
+    residual tolerance that the oracle recomputes."""
+    torch = _gpu
+    pb = _pb((32, 96, 96), (8, 3, 3), sigma=2.0, seed=17, restriction=restriction)
+    pb.precision = precision
+    if precision == 0:
+        pb.lin_rtol = 1e-12
+    s = solver_for(pb)
+    s.build_basis()
+    p = pb.initial_pressure()
+    pt = torch.as_tensor(p, device="cuda")
+    s.assemble(pt, pt)
+    s.coarse_op()
+    st = s.iterate(pt)
+    s.close()
+    T = oracle.transmissibility(pb)
+    rel, bound = linear_residual_check(pb, T, p, p, to_np(pt))
+    log(pb.name, restriction, "precision", precision, "iters", st["lin_iters_last"], "relres", rel, "bound", bound)
+    assert rel <= bound
+    if precision == 0:
+        W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
+        P = oracle.basis_b4(pb, T)
+        LU, piv = oracle.lu_factor(oracle.coarse_operator(pb, W, diag, P, restriction))
+        d_ref, its, _ = oracle.cams_solve(pb, W, diag, P, restriction, LU, piv, oracle.smoother_for(pb, W, diag),
+                                          r0, rtol=1e-12, maxit=500)
+        log("iters gpu", st["lin_iters_last"], "oracle", its)
+        assert its >= 0
+        assert abs(st["lin_iters_last"] - its) <= 1
+        assert rel_err(to_np(pt) - p, d_ref) <= 1e-10
+
+
 @pytest.mark.parametrize("precision", [1, 2])
 def test_mixed_newton_matches_fp64_oracle(_gpu, precision):
     """One time step of the 64x64x32 workload in mixed precision: the
