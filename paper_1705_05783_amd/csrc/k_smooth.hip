@@ -297,6 +297,48 @@ __device__ __forceinline__ void sweep_lds(SmoothLds<T> &L, int ex, int ey, int e
     }
 }
 
+// The LDS of one block for the row form, without the zero borders (10 KB
+// in FP32, so that four workgroups of four blocks, 160 KB, share one
+// compute unit and a 128^3 grid's 1024 workgroups run in one round instead
+// of 1.33).  The sweeps clamp neighbour indices into the block: a coupling
+// that leaves the block through a face inside it is zero in the arrays
+// (staged so), and only those that leave through the block's first cell,
+// first row or first layer (index below 0) are zeroed by a test; the
+// partner values read there are finite.  The arithmetic equals sweep_lds.
+template <class T>
+struct SmoothLdsTight {
+    T y[ST], wx[ST], wy[ST], wz[ST], dinv[ST];
+};
+
+template <class T>
+__device__ __forceinline__ void sweep_lds_tight(SmoothLdsTight<T> &L, int ex, int ey, int ez, int lane)
+{
+    T *y = L.y, *wx = L.wx, *wy = L.wy, *wz = L.wz, *dinv = L.dinv;
+    const int pj = lane & (SB - 1), pk = lane >> 3;
+    const bool pencil = pj < ey && pk < ez;
+    const int nlev = ex + ey + ez - 2;
+    const int base = SB * pj + SB * SB * pk;
+    for (int tau = 0; tau < nlev; ++tau) {
+        const int a = tau - pj - pk;
+        const bool act = pencil && a >= 0 && a < ex;
+        const int t = base + min(max(a, 0), SB - 1);
+        const int tx = max(t - 1, 0), ty = max(t - SB, 0), tz = max(t - SB * SB, 0);
+        const T cx = wx[tx], cy = wy[ty], cz = wz[tz];
+        const T s = y[t] + (t >= 1 ? cx : T(0)) * y[tx] + (t >= SB ? cy : T(0)) * y[ty] +
+                    (t >= SB * SB ? cz : T(0)) * y[tz];
+        if (act) y[t] = s * dinv[t];
+        wave_sync();
+    }
+    for (int tau = nlev - 1; tau >= 0; --tau) {
+        const int a = tau - pj - pk;
+        const bool act = pencil && a >= 0 && a < ex;
+        const int t = base + min(max(a, 0), SB - 1);
+        const T s = wx[t] * y[min(t + 1, ST - 1)] + wy[t] * y[min(t + SB, ST - 1)] + wz[t] * y[min(t + SB * SB, ST - 1)];
+        if (act) y[t] += s * dinv[t];
+        wave_sync();
+    }
+}
+
 // Prolongated coarse correction as e_old (the first post-smoothing step):
 // basis P (TP = double, float or bfloat16 bits), Dirichlet mask, coarse
 // solution, and an LDS cube of (SB + 2)^3 values for the block and its face
@@ -575,7 +617,7 @@ template <class T, class TR, int BPX, int NT>
 __device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
                                               const T *__restrict__ invd, const TR *__restrict__ rhs,
                                               const T *__restrict__ eold, T *__restrict__ enew, int sb,
-                                              SmoothLds<T> *Ls, Shift o, int tid)
+                                              SmoothLdsTight<T> *Ls, Shift o, int tid)
 {
     static_assert(NT % 64 == 0 && NT >= 64 * BPX && (ST * BPX) % NT == 0, "one wave per block at least");
     constexpr int RX = SB * BPX, CPT = ST * BPX / NT;
@@ -584,14 +626,6 @@ __device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restr
     const int bx0 = (sb % nsx) * BPX, j0 = ((sb / nsx) % nby) * SB, k0 = (sb / (nsx * nby)) * SB;
     const int ey = min(SB, g.ny - j0), ez = min(SB, g.nz - k0);
     const T *Wx = W, *Wy = W + g.N, *Wz = W + 2 * g.N;
-    for (int q = tid; q < BPX * 2 * PAD; q += NT) {
-        const int b = q / (2 * PAD), r = q % (2 * PAD);
-        const int idx = r < PAD ? r : ST + r;
-        Ls[b].y[idx] = 0;
-        Ls[b].wx[idx] = 0;
-        Ls[b].wy[idx] = 0;
-        Ls[b].wz[idx] = 0;
-    }
     T e0[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -626,18 +660,18 @@ __device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restr
         const T ev = on * ec;
         const T id = invd[n];
         const int t = li + SB * lj + SB * SB * lk;
-        SmoothLds<T> &L = Ls[b];
+        SmoothLdsTight<T> &L = Ls[b];
         e0[c] = act ? ev : T(0);
-        L.y[PAD + t] = act ? z : T(0);
+        L.y[t] = act ? z : T(0);
         L.dinv[t] = act ? id : T(0);
-        L.wx[PAD + t] = act && li + 1 < ex ? fxp : T(0);
-        L.wy[PAD + t] = act && lj + 1 < ey ? fyp : T(0);
-        L.wz[PAD + t] = act && lk + 1 < ez ? fzp : T(0);
+        L.wx[t] = act && li + 1 < ex ? fxp : T(0);
+        L.wy[t] = act && lj + 1 < ey ? fyp : T(0);
+        L.wz[t] = act && lk + 1 < ez ? fzp : T(0);
     }
     __syncthreads();
     {
         const int w = tid >> 6;
-        if (w < BPX && bx0 + w < nbx) sweep_lds<T>(Ls[w], min(SB, g.nx - (bx0 + w) * SB), ey, ez, tid & 63);
+        if (w < BPX && bx0 + w < nbx) sweep_lds_tight<T>(Ls[w], min(SB, g.nx - (bx0 + w) * SB), ey, ez, tid & 63);
     }
     __syncthreads();
 #pragma unroll
@@ -650,17 +684,16 @@ __device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restr
         if (li < ex && lj < ey && lk < ez)
             enew[wrap_cell(i0 + li, o.x, g.nx) +
                  g.nx * (wrap_cell(j0 + lj, o.y, g.ny) + g.ny * wrap_cell(k0 + lk, o.z, g.nz))] =
-                e0[c] + Ls[b].y[PAD + li + SB * lj + SB * SB * lk];
+                e0[c] + Ls[b].y[li + SB * lj + SB * SB * lk];
     }
 }
 
 template <class T, class TR, int BPX, int NT>
-__global__ __launch_bounds__(NT) void k_bilu_step_row(GridDev g, const T *__restrict__ W,
-                                                       const T *__restrict__ diag, const T *__restrict__ invd,
-                                                       const TR *__restrict__ rhs, const T *__restrict__ eold,
-                                                       T *__restrict__ enew, const int32_t *done, int shifted)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_bilu_step_row(
+    GridDev g, const T *__restrict__ W, const T *__restrict__ diag, const T *__restrict__ invd,
+    const TR *__restrict__ rhs, const T *__restrict__ eold, T *__restrict__ enew, const int32_t *done, int shifted)
 {
-    __shared__ SmoothLds<T> Ls[BPX];
+    __shared__ SmoothLdsTight<T> Ls[BPX];
     if (done && *done) return;
     row_step_body<T, TR, BPX, NT>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), Ls,
                                   block_shift(g, shifted), (int)threadIdx.x);
@@ -741,7 +774,7 @@ __global__ __launch_bounds__(kRowThreads) void kb_bilu_step_row(const InstDev *_
                                                                  const WorkItem *__restrict__ work,
                                                                  const int32_t *nwork, int post, int s, int steps)
 {
-    __shared__ SmoothLds<T> Ls[kRowBlocks];
+    __shared__ SmoothLdsTight<T> Ls[kRowBlocks];
     const int nw = *nwork;
     int t = blockIdx.x;
     WorkItem wnext = t < nw ? work[t] : WorkItem{0, 0};
