@@ -70,6 +70,14 @@ std::vector<Segment> segments(int n, const std::vector<int32_t> &v, bool active)
     return out;
 }
 
+// The mixed-precision solves read an FP32 copy of the dense MSFE inverse
+// where the symmetric coarse GEMV runs (above kGemvLds nodes, no plane
+// blocks): half the bytes per coarse solve, one rounding per factorisation.
+bool uses_inverse32(const cams_options &O, bool blocktri, int nc)
+{
+    return O.restriction == CAMS_R_FE && !blocktri && nc > kGemvLds && O.precision != CAMS_FP64;
+}
+
 struct Layout {
     size_t *off;
     size_t total = 0;
@@ -519,6 +527,8 @@ cams_status cams_create(const cams_grid *grid, const cams_fluid *fluid, const ca
     {   // 54 tile partials of the symmetric coarse GEMV (dense MSFE inverses above kGemvLds nodes)
         const size_t T = (nc + 63) / 64;
         put(L.add(O.restriction == CAMS_R_FE && !c->blocktri && nc > (size_t)kGemvLds ? T * T * 64 * 8 : 0));
+        // 55 its FP32 copy for the mixed-precision solves
+        put(L.add(uses_inverse32(O, c->blocktri, (int)nc) ? nc * nc * 4 : 0));
     }
     if (k > kMaxArrays) {  // more arrays than offset slots: a build error, never a silent overflow
         delete c;
@@ -599,6 +609,8 @@ cams_status cams_set_workspace(cams_ctx *c, void *dev_ptr, size_t bytes)
     a.Tb = (double *)(w + off[52]);
     a.Acs = (double *)(w + off[53]);
     a.gpart = (double *)(w + off[54]);
+    a.Ainv32 = uses_inverse32(c->opt, c->blocktri, c->g.Nc) ? (float *)(w + off[55]) : nullptr;
+    c->ainv32_ok = false;
     if (!c->host) {
         // first device interaction of the context: pinned scalars and timers
         if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {

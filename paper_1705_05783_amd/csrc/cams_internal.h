@@ -100,6 +100,7 @@ struct Arrays {
     double *Tb;       // 2 ny nz: half-cell transmissibilities of the west and east boundary faces
     double *Acs;      // 27 Nc: the coarse operator's 27-point entries when it was last factorised
     double *gpart;    // T^2 x 64 (T = ceil(Nc / 64)): tile partials of the symmetric coarse GEMV
+    float *Ainv32;    // Nc*Nc: the lower-triangle tiles of Ainv rounded to FP32 (mixed precision, symmetric GEMV)
     int32_t *rflag;
     Region *rlist;
     // mixed precision copies
@@ -250,6 +251,7 @@ struct cams_ctx {
     bool has_bcoef;
     cams::FaceBC bc;        // Dirichlet boundary faces (cams_set_face_dirichlet)
     bool has_cfac;          // Ainv holds a factorisation of the operator snapshotted in Acs
+    bool ainv32_ok;         // Ainv32 holds the current Ainv rounded (false after a batched factorisation)
     int n_factor;           // coarse factorisations since the last reset of the counter
     std::vector<int32_t> dep_ptr, dep_idx;
 };

@@ -1161,8 +1161,10 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double *__restrict__ M, i
 // part[J][I] (64 values each); k_gemv_sym_reduce sums part[I][0..T) in a
 // fixed order.  The diagonal tiles also store x_I in rc.  Half the bytes of
 // the row-wise product.  With `partial` set one extra workgroup (the last)
-// runs the iteration's stopping test.
-__global__ __launch_bounds__(kBlock) void k_gemv_sym(const double *__restrict__ M, int n, GridDev g,
+// runs the iteration's stopping test.  TM: the stored entries, FP64 or
+// (mixed-precision solves) the inverse rounded to FP32; sums in FP64.
+template <class TM>
+__global__ __launch_bounds__(kBlock) void k_gemv_sym(const TM *__restrict__ M, int n, GridDev g,
                                                       const double *__restrict__ slots, int fe,
                                                       double *__restrict__ rc, double *__restrict__ part,
                                                       const int32_t *done, const double *__restrict__ partial,
@@ -1190,16 +1192,27 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sym(const double *__restrict__ 
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, rq = lane >> 4, cq = lane & 15;
     const int rbase = 16 * w + 4 * rq, cbase = 4 * cq;
     double a[4][4];
-    if (i0 + 64 <= n && j0 + 64 <= n && (n & 1) == 0) {   // whole tile, 16-byte aligned rows
-        typedef double d2 __attribute__((ext_vector_type(2)));
+    if (i0 + 64 <= n && j0 + 64 <= n && n % (16 / (int)sizeof(TM)) == 0) {   // whole tile, 16-byte aligned rows
+        if constexpr (sizeof(TM) == 8) {
+            typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const d2 *row = (const d2 *)(M + (size_t)(i0 + rbase + k) * n + j0 + cbase);
-            const d2 v0 = row[0], v1 = row[1];
-            a[k][0] = v0.x;
-            a[k][1] = v0.y;
-            a[k][2] = v1.x;
-            a[k][3] = v1.y;
+            for (int k = 0; k < 4; ++k) {
+                const d2 *row = (const d2 *)(M + (size_t)(i0 + rbase + k) * n + j0 + cbase);
+                const d2 v0 = row[0], v1 = row[1];
+                a[k][0] = v0.x;
+                a[k][1] = v0.y;
+                a[k][2] = v1.x;
+                a[k][3] = v1.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float4 v = *(const float4 *)(M + (size_t)(i0 + rbase + k) * n + j0 + cbase);
+                a[k][0] = v.x;
+                a[k][1] = v.y;
+                a[k][2] = v.z;
+                a[k][3] = v.w;
+            }
         }
     } else {
 #pragma unroll
@@ -1207,7 +1220,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sym(const double *__restrict__ 
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int r = i0 + rbase + k, cc = j0 + cbase + c;
-                a[k][c] = r < n && cc < n ? M[(size_t)r * n + cc] : 0.0;
+                a[k][c] = r < n && cc < n ? (double)M[(size_t)r * n + cc] : 0.0;
             }
     }
     if (tid < 128) {
@@ -1257,6 +1270,21 @@ __global__ __launch_bounds__(kBlock) void k_gemv_sym(const double *__restrict__ 
     __syncthreads();
     if (tid < 64 && j0 + tid < n)
         part[((size_t)J * T + I) * 64 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+}
+
+// M32 = M rounded to FP32 on the 64 x 64 tiles (I, J), J <= I, that
+// k_gemv_sym reads (one workgroup per tile, t = I (I + 1) / 2 + J).
+__global__ __launch_bounds__(kBlock) void k_round_lower(const double *__restrict__ M, float *__restrict__ M32, int n)
+{
+    const int t = blockIdx.x;
+    int I = (int)((__builtin_sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    for (int q = threadIdx.x; q < 64 * 64; q += kBlock) {
+        const int r = 64 * I + q / 64, cc = 64 * J + q % 64;
+        if (r < n && cc < n) M32[(size_t)r * n + cc] = (float)M[(size_t)r * n + cc];
+    }
 }
 
 // y[i] = sum over J of part[I][J][i mod 64] (I = i / 64), J ascending.
@@ -1626,6 +1654,7 @@ static GjBufs batch_gj_bufs(const cams_ctx *c)
 // Per instance: A_c copied into Ainv, which the sweeps invert in place.
 void launch_coarse_factor_prepare(cams_ctx *c)
 {
+    c->ainv32_ok = false;   // the batched sweeps rewrite Ainv without rounding it
     const size_t nn = (size_t)c->g.Nc * c->g.Nc;
     k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, c->a.Ainv, nn);
 }
@@ -1885,6 +1914,11 @@ void launch_coarse_factor(cams_ctx *c)
         gj_prepare(c, {X}, {0}, n);
         k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, X, nn);
         inverse_gj(c, X, n, 0, 0, c->stream);
+        if (c->a.Ainv32) {
+            const int T = (n + 63) / 64;
+            k_round_lower<<<T * (T + 1) / 2, kBlock, 0, c->stream>>>(X, c->a.Ainv32, n);
+            c->ainv32_ok = true;
+        }
         return;
     }
     k_copy<<<cdiv(nn, kBlock), kBlock, 0, c->stream>>>(c->a.Ac, F, nn);
@@ -1942,9 +1976,16 @@ void launch_gemv(cams_ctx *c, const double *rc, double *xc, const int32_t *done,
     if (!c->blocktri && fe) {   // symmetric inverse: its lower triangle, once
         const int T = (n + 63) / 64;
         const bool stop = stop_parts > 0;
-        k_gemv_sym<<<T * (T + 1) / 2 + (stop ? 1 : 0), kBlock, 0, c->stream>>>(
-            c->a.Ainv, n, c->g, c->a.slots, fe, c->a.rc, c->a.gpart, done, stop ? c->a.partial : nullptr,
-            stop_parts, c->a.ictl, c->a.scal, rt * rt, c->opt.lin_maxit);
+        const unsigned wgs = T * (T + 1) / 2 + (stop ? 1 : 0);
+        if (c->a.Ainv32 && c->ainv32_ok)
+            k_gemv_sym<float><<<wgs, kBlock, 0, c->stream>>>(c->a.Ainv32, n, c->g, c->a.slots, fe, c->a.rc, c->a.gpart,
+                                                            done, stop ? c->a.partial : nullptr, stop_parts,
+                                                            c->a.ictl, c->a.scal, rt * rt, c->opt.lin_maxit);
+        else
+            k_gemv_sym<double><<<wgs, kBlock, 0, c->stream>>>(c->a.Ainv, n, c->g, c->a.slots, fe, c->a.rc,
+                                                             c->a.gpart, done, stop ? c->a.partial : nullptr,
+                                                             stop_parts, c->a.ictl, c->a.scal, rt * rt,
+                                                             c->opt.lin_maxit);
         k_gemv_sym_reduce<<<cdiv(n, kBlock), kBlock, 0, c->stream>>>(c->a.gpart, n, xc, done);
         return;
     }

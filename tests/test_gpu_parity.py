@@ -505,25 +505,36 @@ def test_residual_pair_form_linear_solve(_gpu, restriction, precision):
     groups of boxes (2 x 32 x 32 = 2048 workgroups) than are resident at
     once, takes the pair form of the residual-restriction (two cells per
     thread, 16-byte loads): the FP64 solve matches the oracle's C-AMS solve
-    as on the smaller grids, and the mixed FP32 / BF16 solves meet the FP64
-    residual tolerance that the oracle recomputes."""
+    as on the smaller grids, and the mixed FP32 / BF16 solves (whose coarse
+    GEMV reads the 4096^2 inverse rounded to FP32) meet the FP64 residual
+    tolerance that the oracle recomputes, within 3 iterations of the FP64
+    solve of the same system."""
     torch = _gpu
-    pb = _pb((32, 96, 96), (8, 3, 3), sigma=2.0, seed=17, restriction=restriction)
-    pb.precision = precision
-    if precision == 0:
-        pb.lin_rtol = 1e-12
-    s = solver_for(pb)
-    s.build_basis()
-    p = pb.initial_pressure()
-    pt = torch.as_tensor(p, device="cuda")
-    s.assemble(pt, pt)
-    s.coarse_op()
-    st = s.iterate(pt)
-    s.close()
+
+    def solve(prec, rtol=None):
+        pb = _pb((32, 96, 96), (8, 3, 3), sigma=2.0, seed=17, restriction=restriction)
+        pb.precision = prec
+        if rtol is not None:
+            pb.lin_rtol = rtol
+        s = solver_for(pb)
+        s.build_basis()
+        p = pb.initial_pressure()
+        pt = torch.as_tensor(p, device="cuda")
+        s.assemble(pt, pt)
+        s.coarse_op()
+        st = s.iterate(pt)
+        s.close()
+        return pb, p, pt, st
+
+    pb, p, pt, st = solve(precision, 1e-12 if precision == 0 else None)
     T = oracle.transmissibility(pb)
     rel, bound = linear_residual_check(pb, T, p, p, to_np(pt))
     log(pb.name, restriction, "precision", precision, "iters", st["lin_iters_last"], "relres", rel, "bound", bound)
     assert rel <= bound
+    if precision != 0:
+        its64 = solve(0)[3]["lin_iters_last"]
+        log("iters fp64", its64)
+        assert abs(st["lin_iters_last"] - its64) <= 3
     if precision == 0:
         W, diag, r0, _ = oracle.linear_system(pb, T, p, p)
         P = oracle.basis_b4(pb, T)
