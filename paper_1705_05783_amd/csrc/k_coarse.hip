@@ -1058,12 +1058,19 @@ __device__ __forceinline__ double node_sum(const GridDev &g, const double *__res
 {
     if (!fe) return slots[(size_t)k * 8];
     const int ka = k % g.nb[0], kb = (k / g.nb[0]) % g.nb[1], kc = k / (g.nb[0] * g.nb[1]);
-    double s = 0.0;
+    // the eight loads from clamped addresses, outside any branch, so that
+    // they are in flight together; slots outside the grid add zero
+    double v[8];
+    bool ok[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int a = ka - (q & 1), b = kb - ((q >> 1) & 1), c = kc - (q >> 2);
-        if (a >= 0 && b >= 0 && c >= 0) s += slots[(size_t)node_index(g, a, b, c) * 8 + q];
+        ok[q] = a >= 0 && b >= 0 && c >= 0;
+        v[q] = slots[(size_t)node_index(g, max(a, 0), max(b, 0), max(c, 0)) * 8 + q];
     }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += ok[q] ? v[q] : 0.0;
     return s;
 }
 
