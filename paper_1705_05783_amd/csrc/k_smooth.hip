@@ -612,15 +612,27 @@ constexpr int kRowThreads = 512;
 // Group sb of BPX blocks along x (groups x fastest, then y, then z), as
 // k_bilu_step_row and its batched form take it.  Each thread stages and
 // writes back only its own LDS slots, so consecutive groups need no
-// barrier between them.
-template <class T, class TR, int BPX, int NT>
+// barrier between them.  LS: the block LDS with zero borders (SmoothLds)
+// or without (SmoothLdsTight, swept by sweep_lds_tight).
+template <class T, class TR, int BPX, int NT, class LS>
 __device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restrict__ W, const T *__restrict__ diag,
                                               const T *__restrict__ invd, const TR *__restrict__ rhs,
-                                              const T *__restrict__ eold, T *__restrict__ enew, int sb,
-                                              SmoothLdsTight<T> *Ls, Shift o, int tid)
+                                              const T *__restrict__ eold, T *__restrict__ enew, int sb, LS *Ls,
+                                              Shift o, int tid)
 {
     static_assert(NT % 64 == 0 && NT >= 64 * BPX && (ST * BPX) % NT == 0, "one wave per block at least");
-    constexpr int RX = SB * BPX, CPT = ST * BPX / NT;
+    constexpr bool TIGHT = std::is_same<LS, SmoothLdsTight<T>>::value;
+    constexpr int RX = SB * BPX, CPT = ST * BPX / NT, OFF = TIGHT ? 0 : PAD;
+    if constexpr (!TIGHT) {
+        for (int q = tid; q < BPX * 2 * PAD; q += NT) {
+            const int b = q / (2 * PAD), r = q % (2 * PAD);
+            const int idx = r < PAD ? r : ST + r;
+            Ls[b].y[idx] = 0;
+            Ls[b].wx[idx] = 0;
+            Ls[b].wy[idx] = 0;
+            Ls[b].wz[idx] = 0;
+        }
+    }
     const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB;
     const int nsx = (nbx + BPX - 1) / BPX;
     const int bx0 = (sb % nsx) * BPX, j0 = ((sb / nsx) % nby) * SB, k0 = (sb / (nsx * nby)) * SB;
@@ -660,18 +672,23 @@ __device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restr
         const T ev = on * ec;
         const T id = invd[n];
         const int t = li + SB * lj + SB * SB * lk;
-        SmoothLdsTight<T> &L = Ls[b];
+        LS &L = Ls[b];
         e0[c] = act ? ev : T(0);
-        L.y[t] = act ? z : T(0);
+        L.y[OFF + t] = act ? z : T(0);
         L.dinv[t] = act ? id : T(0);
-        L.wx[t] = act && li + 1 < ex ? fxp : T(0);
-        L.wy[t] = act && lj + 1 < ey ? fyp : T(0);
-        L.wz[t] = act && lk + 1 < ez ? fzp : T(0);
+        L.wx[OFF + t] = act && li + 1 < ex ? fxp : T(0);
+        L.wy[OFF + t] = act && lj + 1 < ey ? fyp : T(0);
+        L.wz[OFF + t] = act && lk + 1 < ez ? fzp : T(0);
     }
     __syncthreads();
     {
         const int w = tid >> 6;
-        if (w < BPX && bx0 + w < nbx) sweep_lds_tight<T>(Ls[w], min(SB, g.nx - (bx0 + w) * SB), ey, ez, tid & 63);
+        if (w < BPX && bx0 + w < nbx) {
+            if constexpr (TIGHT)
+                sweep_lds_tight<T>(Ls[w], min(SB, g.nx - (bx0 + w) * SB), ey, ez, tid & 63);
+            else
+                sweep_lds<T>(Ls[w], min(SB, g.nx - (bx0 + w) * SB), ey, ez, tid & 63);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -684,16 +701,34 @@ __device__ __forceinline__ void row_step_body(const GridDev &g, const T *__restr
         if (li < ex && lj < ey && lk < ez)
             enew[wrap_cell(i0 + li, o.x, g.nx) +
                  g.nx * (wrap_cell(j0 + lj, o.y, g.ny) + g.ny * wrap_cell(k0 + lk, o.z, g.nz))] =
-                e0[c] + Ls[b].y[li + SB * lj + SB * SB * lk];
+                e0[c] + Ls[b].y[OFF + li + SB * lj + SB * SB * lk];
     }
 }
 
+// One round: the LDS without zero borders (40 KB) and at most 64 registers,
+// four workgroups per compute unit, for grids whose groups all fit at once
+// that way (128^3: 1024 groups, 22.6 -> 21.3 us per step).
 template <class T, class TR, int BPX, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_bilu_step_row(
     GridDev g, const T *__restrict__ W, const T *__restrict__ diag, const T *__restrict__ invd,
     const TR *__restrict__ rhs, const T *__restrict__ eold, T *__restrict__ enew, const int32_t *done, int shifted)
 {
     __shared__ SmoothLdsTight<T> Ls[BPX];
+    if (done && *done) return;
+    row_step_body<T, TR, BPX, NT>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), Ls,
+                                  block_shift(g, shifted), (int)threadIdx.x);
+}
+
+// Several rounds: the LDS with zero borders and no register limit, whose
+// staging keeps more loads in flight (256x256x128: 73 against 80 us for the
+// one-round form).
+template <class T, class TR, int BPX, int NT>
+__global__ __launch_bounds__(NT) void k_bilu_step_rows(GridDev g, const T *__restrict__ W, const T *__restrict__ diag,
+                                                        const T *__restrict__ invd, const TR *__restrict__ rhs,
+                                                        const T *__restrict__ eold, T *__restrict__ enew,
+                                                        const int32_t *done, int shifted)
+{
+    __shared__ SmoothLds<T> Ls[BPX];
     if (done && *done) return;
     row_step_body<T, TR, BPX, NT>(g, W, diag, invd, rhs, eold, enew, xcd_swizzle(blockIdx.x, gridDim.x), Ls,
                                   block_shift(g, shifted), (int)threadIdx.x);
@@ -774,7 +809,7 @@ __global__ __launch_bounds__(kRowThreads) void kb_bilu_step_row(const InstDev *_
                                                                  const WorkItem *__restrict__ work,
                                                                  const int32_t *nwork, int post, int s, int steps)
 {
-    __shared__ SmoothLdsTight<T> Ls[kRowBlocks];
+    __shared__ SmoothLds<T> Ls[kRowBlocks];
     const int nw = *nwork;
     int t = blockIdx.x;
     WorkItem wnext = t < nw ? work[t] : WorkItem{0, 0};
@@ -812,7 +847,10 @@ void launch_step_many(cams_ctx *c, const T *W, const T *diag, const T *iv, const
         const GridDev &g = c->g;
         const int nbx = (g.nx + SB - 1) / SB, nby = (g.ny + SB - 1) / SB, nbz = (g.nz + SB - 1) / SB;
         const int wgs = ((nbx + BPX - 1) / BPX) * nby * nbz;
-        k_bilu_step_row<T, TR, BPX, NT><<<wgs, NT, 0, c->stream>>>(g, W, diag, iv, rhs, prev, out, done, sh);
+        if (wgs <= resident_workgroups((const void *)k_bilu_step_row<T, TR, BPX, NT>, NT))
+            k_bilu_step_row<T, TR, BPX, NT><<<wgs, NT, 0, c->stream>>>(g, W, diag, iv, rhs, prev, out, done, sh);
+        else
+            k_bilu_step_rows<T, TR, BPX, NT><<<wgs, NT, 0, c->stream>>>(g, W, diag, iv, rhs, prev, out, done, sh);
     } else {
         k_bilu_step<T, TR, kSmoothThreadsMany, 0><<<nb, kSmoothThreadsMany, 0, c->stream>>>(c->g, W, diag, iv, rhs,
                                                                                             prev, out, done, sh);
