@@ -293,3 +293,33 @@ def test_block_tridiagonal_instance_needs_its_own_factorisation_after_a_batch(to
     rel, bound = linear_residual_check(big, oracle.transmissibility(big), p0, p0, p0 + to_np(d), d=to_np(d))
     assert rel <= bound, (rel, bound)
     b.close()
+
+
+def test_mixed_instance_iterates_on_the_batched_inverse_then_on_its_own_rounded_copy(torch):
+    """A mixed-precision MSFE instance with a dense inverse above 1024 coarse
+    nodes (here 2048) solves alone from an FP32 copy of its inverse; the
+    batch rewrites the inverse without rounding it, so cams_iterate on the
+    system the batch assembled (at the same start pressure) reads the FP64
+    inverse, and after a new assembly and cams_coarse_op the fresh FP32
+    copy.  Both solves meet the tolerance on the oracle's matrix."""
+    big = small_problem(64, 64, 32, 4, sigma=2.0, seed=33, c=0.1).with_options(precision=MIXED_FP32, newton_maxit=1)
+    small = small_problem(16, 12, 8, 4, sigma=2.0, seed=3, c=0.1).with_options(precision=MIXED_FP32, newton_maxit=1)
+    b, status, stats, p = _run_batch(torch, [big, small])
+    assert all(s_ == 0 for s_ in status)
+    s = b.solvers[0]
+    assert s.Nc == 2048
+    from paper_1705_05783_amd import _cams as C
+    assert C.cams_coarse_planes(s.ctx) == 0
+    p0 = _start(big)
+    T = oracle.transmissibility(big)
+    for refactor in (False, True):
+        pt = torch.as_tensor(p0, device="cuda")
+        if refactor:
+            s.assemble(pt, pt.clone())
+            s.coarse_op()
+        d = torch.zeros_like(pt)
+        st = s.iterate(d)
+        rel, bound = linear_residual_check(big, T, p0, p0, p0 + to_np(d), d=to_np(d))
+        log("refactor", refactor, "iters", st["lin_iters_last"], "relres", rel, "bound", bound)
+        assert rel <= bound, (refactor, rel, bound)
+    b.close()
